@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""CCMC step throughput on one MI355X: cluster spawn attempts per second.
+
+Workload (default): 3D uniform electron gas, 14 electrons in 114 spin orbitals (57 plane
+waves, |n|^2 <= 5, two 64-bit bitstring words), r_s = 1, CCSDT, full non-composite
+sampling, at least 4 spawning attempts per cluster (multi-spawn threshold 1), tau = 0.002,
+target population 1e6.  Synthetic and analytic: there is no dataset.
+
+Procedure: grow the population from the reference at a larger time step with the shift held
+at zero until it reaches the target, switch to tau = 0.002 with population control, run the
+warm-up steps, then time exactly `--steps` steps (each a full ccmc_step: selection,
+spawning, death and annihilation).  Inputs stay resident on the GPU throughout.  Kernel
+times come from HIP events recorded by the library on its own stream over the timed steps.
+
+Prints one JSON line.  --gpus N > 1 is not supported (one GPU only).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1807_03749_amd import ccmc, driver, inputs  # noqa: E402
+
+METRIC = "cluster spawn attempts/s on 1 MI355X; FP32 vs FP64 at equal E_proj error"
+HBM_PEAK_GBS = 8000.0
+# Plain 32-bit vector ALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+# Algorithmic 32-bit operations of one spawning attempt (Philox block, generator, element,
+# signs, amplitude) -- the per-unit figure of the generation kernel (see the design notes).
+OPS_PER_ATTEMPT = 300.0
+HBM_KERNELS = {"radix_scatter", "radix_hist", "gather", "seg_fold", "merge", "compact", "round", "weights",
+               "noncomposite"}
+
+
+def make_state(w: inputs.Workload, precision: str, init_pop: float):
+    kw = dict(precision=precision, full_noncomposite=int(w.full_noncomposite),
+              min_spawn_attempts=w.min_spawn_attempts, multispawn_threshold=w.multispawn_threshold,
+              noncomposite_threshold=w.noncomposite_threshold, init_pop=init_pop, seed=w.seed)
+    if w.system == "ueg":
+        return ccmc.State("ueg", w.n_electrons, w.truncation, n2_max=w.n2_max, rs=w.rs, **kw)
+    h, B = inputs.molecule_like(n_spatial=w.n_spatial, n_electrons=w.n_electrons, n_chol=w.n_chol)
+    return ccmc.State("mol", w.n_electrons, w.truncation, h=h, chol=B, **kw)
+
+
+def grow(state, w: inputs.Workload, log, max_steps: int = 20000, tau_grow_factor: float = 5.0):
+    """Shift held at zero (E_HF) until N_tot reaches the target."""
+    tau = w.tau * tau_grow_factor
+    nsel = driver.selections(state.options.init_pop)
+    st = None
+    for it in range(max_steps):
+        st = state.ccmc_step(tau, 0.0, nsel)
+        nsel = driver.selections(st["n_total"])
+        if it % 200 == 0:
+            log(f"grow step {it}: N_tot {st['n_total']:.3e} excitors {st['n_excitors']}")
+        if st["n_total"] >= w.target_population:
+            return st, it + 1
+    return st, max_steps
+
+
+def run_leg(w: inputs.Workload, precision: str, steps: int, warmup: int, log, profile: bool = True):
+    state = make_state(w, precision, init_pop=max(100.0, w.target_population / 50))
+    st, ngrow = grow(state, w, log)
+    ctl = driver.ShiftControl(target=w.target_population, tau=w.tau)
+    ctl.varying = True
+    ctl._anchor = 0
+    ctl.history = [st["n_total"]]
+    nsel = driver.selections(st["n_total"])
+    for _ in range(warmup):
+        st = state.ccmc_step(w.tau, ctl.shift, nsel)
+        ctl.update(st["n_total"])
+        nsel = driver.selections(st["n_total"])
+    if profile:
+        state.ccmc_profile(True)
+        state.ccmc_profile_read()
+    attempts = selections = spawns = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = state.ccmc_step(w.tau, ctl.shift, nsel)
+        ctl.update(st["n_total"])
+        nsel = driver.selections(st["n_total"])
+        attempts += st["n_spawn_attempts"]
+        selections += st["n_selections"]
+        spawns += st["n_spawns"]
+    elapsed = time.perf_counter() - t0
+    prof = state.ccmc_profile_read() if profile else {}
+    state.ccmc_profile(False)
+    keys, amps, n0, step = state.ccmc_export()
+    out = dict(attempts=attempts, selections=selections, spawns=spawns, seconds=elapsed, grow_steps=ngrow,
+               n_total=st["n_total"], n_ref=st["n_ref"], excitors=st["n_excitors"], shift=ctl.shift, profile=prof,
+               memory=state.ccmc_memory())
+    state.close()
+    return out
+
+
+def roofline(prof: dict):
+    """Roofline entry for the kernel with the most time in the timed region."""
+    if not prof:
+        return None
+    name, p = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    avg_s = p["ms"] / p["launches"] / 1e3
+    if name in HBM_KERNELS:
+        achieved = p["bytes"] / p["launches"] / avg_s / 1e9
+        peak = HBM_PEAK_GBS
+        r = dict(bound="hbm", achieved=achieved, peak=peak, unit="GB/s")
+    else:
+        achieved = p["items"] / p["launches"] * OPS_PER_ATTEMPT / avg_s / 1e9
+        r = dict(bound="alu", achieved=achieved, peak=ALU_PEAK_GOPS, unit="Gop/s")
+    r.update(frac=r["achieved"] / r["peak"], traffic=None, kernel=name, launches=p["launches"],
+             avg_ms=p["ms"] / p["launches"], bytes_per_launch=p["bytes"] / p["launches"])
+    return r
+
+
+def annihilation_roofline(prof: dict):
+    """Achieved HBM bandwidth of the sort / reduce / merge kernels taken together."""
+    names = [n for n in ("radix_hist", "radix_scatter", "gather", "seg_fold", "merge", "round", "compact")
+             if n in prof]
+    ms = sum(prof[n]["ms"] for n in names)
+    by = sum(prof[n]["bytes"] for n in names)
+    if ms <= 0:
+        return None
+    return dict(kernels=names, ms=ms, bytes=by, achieved=by / (ms / 1e3) / 1e9, peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS)
+
+
+def cpu_baseline(w: inputs.Workload, seconds: float, log):
+    """The CPU oracle, timed on this host on a bounded sample of the same workload: the
+    whole truncated space occupied with seeded amplitudes (N_tot = target), stepped until
+    `seconds` of CPU time have passed."""
+    from oracle import binding as orc  # CPU baseline leg only
+    import itertools
+
+    if w.system != "ueg":
+        return None
+    S = orc.System.ueg(w.n_electrons, w.n2_max, w.rs)
+    nv = S.nvec()
+    N, M = S.n_el, S.M
+    dets = []
+    for L in range(1, w.truncation + 1):
+        table = {}
+        for parts in itertools.combinations(range(N, M), L):
+            key = (tuple(int(x) for x in sum(nv[p >> 1] for p in parts)), sum(1 for p in parts if p % 2 == 0))
+            table.setdefault(key, []).append(parts)
+        for holes in itertools.combinations(range(N), L):
+            key = (tuple(int(x) for x in sum(nv[p >> 1] for p in holes)), sum(1 for p in holes if p % 2 == 0))
+            for parts in table.get(key, []):
+                v = (1 << N) - 1
+                for i in holes:
+                    v ^= 1 << i
+                for a in parts:
+                    v |= 1 << a
+                dets.append(v)
+    dets.sort()
+    levels = np.array([bin(d >> N).count("1") for d in dets])
+    n0 = 0.2 * w.target_population
+    amps = inputs.state_amplitudes(levels, target=0.8 * w.target_population, seed=1)
+    keys = np.array([[(d >> (64 * i)) & 0xFFFFFFFFFFFFFFFF for i in range(S.W)] for d in dets], dtype=np.uint64)
+    R = orc.Run(S, w.truncation, orc.RunOptions(full_noncomposite=w.full_noncomposite,
+                                                 min_spawn_attempts=w.min_spawn_attempts,
+                                                 multispawn_threshold=w.multispawn_threshold,
+                                                 noncomposite_threshold=w.noncomposite_threshold, seed=w.seed))
+    R.import_state(keys, amps, n0, 0)
+    nsel = driver.selections(np.abs(amps).sum() + n0)
+    attempts, steps = 0, 0
+    t0 = time.process_time()
+    while time.process_time() - t0 < seconds:
+        st = R.step(w.tau, 0.0, nsel)
+        attempts += st["n_spawn_attempts"]
+        nsel = driver.selections(st["n_total"])
+        steps += 1
+    el = time.process_time() - t0
+    log(f"cpu oracle: {steps} steps, {attempts} attempts in {el:.1f} s")
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    cpu = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(value=attempts / el, unit="attempts/s", cores=1, kind="oracle",
+                sample=f"{steps} serial FP64 oracle steps of {w.name} from a store holding the whole truncated "
+                       f"space ({len(keys)} excitors, N_tot {w.target_population:.0e}) on {cpu}")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="ueg14_114_ccsdt_fnc", choices=sorted(inputs.WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 leg")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU only "
+              f"(the multi-GPU design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+    log = (lambda m: None) if args.quiet else (lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+    w = inputs.WORKLOADS[args.workload]
+    log(f"workload {w.name} precision {args.precision}: growing to {w.target_population:.0e}")
+    main_leg = run_leg(w, args.precision, args.steps, args.warmup, log)
+    value = main_leg["attempts"] / main_leg["seconds"]
+    log(f"{args.precision}: {value:.4e} attempts/s, {1e3 * main_leg['seconds'] / args.steps:.3f} ms/step")
+    for k, p in sorted(main_leg["profile"].items(), key=lambda kv: -kv[1]["ms"]):
+        log(f"  {k:16s} {p['ms'] / max(p['launches'], 1):8.4f} ms avg  x{p['launches']}")
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * main_leg["seconds"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "synthetic (analytic UEG; population grown from the reference on the GPU)",
+        "config": {"workload": w.name, "system": w.system, "electrons": w.n_electrons,
+                   "spin_orbitals": w.n_spin_orbitals, "truncation": w.truncation, "tau": w.tau,
+                   "target_population": w.target_population, "full_noncomposite": w.full_noncomposite,
+                   "min_spawn_attempts": w.min_spawn_attempts, "excitors": main_leg["excitors"],
+                   "n_total": main_leg["n_total"], "selections_per_step": main_leg["selections"] / args.steps,
+                   "spawns_per_step": main_leg["spawns"] / args.steps, "parallelism": "1 GPU"},
+        "roofline": roofline(main_leg["profile"]),
+        "annihilation_roofline": annihilation_roofline(main_leg["profile"]),
+        "kernels": {k: dict(avg_ms=p["ms"] / max(p["launches"], 1), launches=p["launches"],
+                            share=p["ms"] / max(1e-9, sum(q["ms"] for q in main_leg["profile"].values())))
+                    for k, p in main_leg["profile"].items()},
+        "device_memory_bytes": main_leg["memory"],
+    }
+    if not args.no_fp32 and args.precision == "fp64":
+        log("fp32 leg")
+        f32 = run_leg(w, "fp32", args.steps, args.warmup, log, profile=False)
+        out["fp32"] = dict(value=f32["attempts"] / f32["seconds"], ms_per_step=1e3 * f32["seconds"] / args.steps,
+                           excitors=f32["excitors"], n_total=f32["n_total"])
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, log)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

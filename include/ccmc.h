@@ -1,0 +1,190 @@
+/*
+ * ccmc.h -- C ABI of the MI355X (gfx950) coupled cluster Monte Carlo step library.
+ *
+ * The library runs the data-parallel hot path of coupled cluster Monte Carlo (CCMC) as
+ * described by Spencer, Neufeld, Vigor, Franklin & Thom, "Large Scale Parallelization in
+ * Stochastic Coupled Cluster", arXiv:1807.03749: one call of ccmc_step performs one time
+ * step of eq. (CCMC) (Sec. II, eq. 3) -- cluster-size draw, excitor selection in
+ * proportion to |t_i|, collapse with its fermionic sign, spawning (with full
+ * non-composite and multi-spawn sampling, Sec. IV), death against the shift, and
+ * annihilation into the device-resident sorted excitor store -- entirely in HIP kernels
+ * on one GPU.
+ *
+ * Conventions shared by every entry point:
+ *   - Determinants are bitstrings of W = ceil(M/64) 64-bit words; spin orbital p is bit
+ *     (p & 63) of word (p >> 6); word 0 is least significant.  Keys order as W-word
+ *     unsigned integers, most significant word first.  Spin orbital p = 2*spatial + sigma
+ *     (sigma 0 = alpha, 1 = beta).  The Hartree-Fock reference occupies spin orbitals
+ *     0 .. N-1.  Host key arrays are entry-major: keys[i*W + w].
+ *   - Energies are relative to the Hartree-Fock energy E_HF; the shift S passed to
+ *     ccmc_step is relative to E_HF as well.
+ *   - Pointers in these signatures are HOST pointers, owned by the caller and only read
+ *     or written during the call.  The state owns all device memory until ccmc_free.
+ *   - Every call returns a ccmc_status; nothing throws across the ABI.  A failing call
+ *     leaves the state as it was before the call, and ccmc_last_error(state) explains it.
+ *   - One state is used by one host thread at a time.  Several states may share a HIP
+ *     stream.  ccmc_step is asynchronous to the host except for the statistics copy.
+ */
+#ifndef CCMC_H
+#define CCMC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ccmc_state ccmc_state;
+
+typedef enum {
+    CCMC_OK = 0,
+    CCMC_EINVAL = -1,    /* invalid argument (bad size, unsorted keys, NaN, ...) */
+    CCMC_ENOMEM = -2,    /* device memory or the HBM budget exhausted */
+    CCMC_EOVERFLOW = -3, /* a count exceeded a field width (e.g. > 2^30-2 attempts on one
+                            cluster, > 2^32-1 selections); the step was rolled back */
+    CCMC_EDEVICE = -4,   /* HIP runtime error */
+    CCMC_EBLOWUP = -5    /* population beyond the fixed-point range of the selection weights */
+} ccmc_status;
+
+enum { CCMC_UEG = 1, CCMC_MOLECULAR = 2 };
+enum { CCMC_FP64 = 0, CCMC_FP32 = 1 };
+
+/* The system (Sec. III.B uses the 3D uniform electron gas; Sec. III.B and IV use
+ * molecules).  UEG: closed-shell N electrons in the plane waves with |n|^2 <= n2_max of a
+ * cubic box of volume N (4 pi / 3) r_s^3; n_spin_orbitals is derived and ignored on input.
+ * Molecular: n_spin_orbitals = 2 * n_spatial of the integrals. */
+typedef struct {
+    int kind;            /* CCMC_UEG or CCMC_MOLECULAR */
+    int n_electrons;     /* even, closed shell */
+    int n_spin_orbitals; /* molecular: 2 * n_spatial; UEG: output only */
+    double rs;           /* UEG Wigner-Seitz radius (bohr) */
+    int n2_max;          /* UEG kinetic cut-off |n|^2 <= n2_max */
+} ccmc_system;
+
+/* Molecular integrals (host, copied at init): h[n][n] symmetric one-electron integrals and
+ * Cholesky vectors chol[n_chol][n][n] (each symmetric), so that the chemists' two-electron
+ * integrals are (pq|rs) = sum_L chol[L][p][q] chol[L][r][s]; the library builds that table on
+ * the device.  Pass NULL for the UEG. */
+typedef struct {
+    int n_spatial;
+    const double *h;
+    const double *chol;
+    int n_chol;
+} ccmc_integrals;
+
+/* Sampling options.  Defaults (ccmc_options_default): FP64, original selection, k_min 1,
+ * multi-spawn off, non-composite threshold 1, spawn cutoff 0.01, occupation threshold 1,
+ * init_pop 10, p_single 0.1, seed 1234, no budget, default stream, no spawn ids. */
+typedef struct {
+    int precision;                 /* CCMC_FP64 or CCMC_FP32 (amplitudes, spawns, integrals) */
+    int full_noncomposite;         /* 1: full non-composite sampling (Sec. IV.B) */
+    int min_spawn_attempts;        /* k_min >= 1: attempts per cluster are at least this */
+    double multispawn_threshold;   /* A_thresh of Sec. IV.C for sampled clusters; <= 0: off */
+    double noncomposite_threshold; /* A_thresh for the non-composite items; <= 0: off */
+    double spawn_cutoff;           /* |spawn| below it is rounded to +-cutoff or 0, unbiased */
+    double occupation_threshold;   /* |N_i| below it is rounded to +-threshold or 0, unbiased */
+    double init_pop;               /* initial reference amplitude N_0 */
+    double p_single;               /* molecular generator: probability of a single */
+    uint64_t seed;                 /* Philox4x32-10 key */
+    uint64_t hbm_budget_bytes;     /* 0: no limit; else device memory the state may hold */
+    void *hip_stream;              /* hipStream_t to run on; NULL: the library's own stream */
+    int keep_spawn_ids;            /* 1: keep the last step's spawn list for ccmc_export_spawns */
+} ccmc_options;
+
+typedef struct {
+    uint64_t step;                     /* step index after the step */
+    uint64_t n_selections;             /* sampled cluster selections (n_attempts argument) */
+    uint64_t n_discarded;              /* selections discarded (repeat, overlap, level) */
+    uint64_t n_spawn_attempts;         /* excitation-generator calls, null ones included */
+    uint64_t n_spawns;                 /* spawn records emitted (deaths excluded) */
+    uint64_t n_deaths;                 /* death records emitted */
+    uint64_t n_excitors;               /* excitors in the store after the step */
+    uint64_t max_attempts_per_cluster;
+    double n_total;                    /* |N_0| + sum |N_i| after the step (FP64) */
+    double n_ref;                      /* N_0 after the step (FP64) */
+    double eproj_num;                  /* sum over sampled clusters of <D_HF|H|D_c> s_D(c) A (FP64) */
+    double eproj_den;                  /* N_0 before the step (FP64) */
+} ccmc_stats;
+
+/* Per-kernel timing collected with HIP events on the state's stream (ccmc_profile). */
+typedef struct {
+    char name[40];
+    uint64_t launches;
+    double ms;        /* summed event time over the launches */
+    double bytes;     /* algorithmic bytes moved by those launches (model in the design notes) */
+    double items;     /* work units processed by those launches */
+} ccmc_kernel_time;
+
+/* Fill *opt with the defaults listed above. */
+ccmc_status ccmc_options_default(ccmc_options *opt);
+
+/* Create a state: builds the basis (UEG) or the two-electron table from the Cholesky
+ * vectors (molecular) on the device, and starts from N_0 = init_pop on the reference with an
+ * empty excitor store (Sec. II: the walk starts from unit-weight particles on the reference).
+ * truncation l: 1 <= l <= 6 (2 = CCSD, 3 = CCSDT, 4 = CCSDTQ), l <= n_electrons; M <= 512.
+ * On success *out owns device memory until ccmc_free.  Errors: EINVAL, ENOMEM, EDEVICE. */
+ccmc_status ccmc_init(const ccmc_system *sys, const ccmc_integrals *ints, int truncation,
+                      const ccmc_options *opt, ccmc_state **out);
+
+/* One time step of eq. (CCMC) (Sec. II, eq. 3) with time step tau > 0 and shift S:
+ *   - original selection: n_attempts cluster selections with p_size(s) = 2^-(s+1) over
+ *     s in [0, l+2] (Sec. II and its footnote);
+ *   - full non-composite (Sec. IV.B): the reference and every excitor are evolved
+ *     explicitly, plus n_attempts composite selections with s in [2, l+2];
+ *   - each cluster makes max(k_min, floor(|A| / A_thresh)) spawning attempts (Sec. IV.C);
+ *   - annihilation sums every contribution to a determinant in record-id order and adds
+ *     it to the store (or to N_0), then rounds small amplitudes and compacts.
+ * n_attempts <= 2^32 - 1.  *out (may be NULL) receives the step statistics.
+ * Errors: EINVAL, ENOMEM, EOVERFLOW, EBLOWUP, EDEVICE; on error the state is unchanged. */
+ccmc_status ccmc_step(ccmc_state *st, double tau, double shift, uint64_t n_attempts,
+                      ccmc_stats *out);
+
+/* Projected-energy estimator terms of the last step (Sec. II, eq. 7): E_proj is the ratio of
+ * the means of eproj_num and eproj_den over the equilibrated steps.  e_hf receives the
+ * Hartree-Fock energy.  Any output pointer may be NULL. */
+ccmc_status ccmc_energy(const ccmc_state *st, double *e_hf, double *eproj_num, double *eproj_den);
+
+/* Release the state and all its device memory.  NULL is ignored. */
+void ccmc_free(ccmc_state *st);
+
+/* Text of the last error on this state ("" if none); valid until the next call on it.
+ * With st == NULL: the last error of a failed ccmc_init on this thread. */
+const char *ccmc_last_error(const ccmc_state *st);
+
+/* Number of excitors in the store; then ccmc_export copies the store (keys[n][W] in key
+ * order and amplitudes as FP64), N_0 and the step index into host arrays of `capacity`
+ * entries.  EINVAL if capacity is too small. */
+ccmc_status ccmc_export_size(const ccmc_state *st, uint64_t *n);
+ccmc_status ccmc_export(const ccmc_state *st, uint64_t *keys, double *amps, uint64_t capacity,
+                        uint64_t *n, double *n_ref, uint64_t *step);
+
+/* Replace the store: keys strictly ascending, each with N electrons, excitation level in
+ * [1, l], no bits at or above M, amplitudes finite and non-zero; N_0 finite; the next step
+ * uses Philox counters of step index `step`.  EINVAL on any violation (state unchanged). */
+ccmc_status ccmc_import(ccmc_state *st, const uint64_t *keys, const double *amps, uint64_t n,
+                        double n_ref, uint64_t step);
+
+/* With keep_spawn_ids set: the last step's spawn and death records (key, amplitude as FP64,
+ * id) in id order, id = (class << 62) | (item << 30) | slot, class 0 for the non-composite
+ * items of full non-composite sampling (item 0 = reference, item i+1 = store entry i) and 1
+ * for sampled clusters (item = selection index); slot 0 is the death and slot m+1 attempt m.
+ * EINVAL if keep_spawn_ids is off or capacity is too small. */
+ccmc_status ccmc_spawns_size(const ccmc_state *st, uint64_t *n);
+ccmc_status ccmc_export_spawns(const ccmc_state *st, uint64_t *keys, double *amps, uint64_t *ids,
+                               uint64_t capacity, uint64_t *n);
+
+/* Kernel timing: enable (1) or disable (0) HIP-event timing of every launch on the state's
+ * stream; ccmc_profile_read copies up to `capacity` accumulated entries and resets them. */
+ccmc_status ccmc_profile(ccmc_state *st, int enable);
+ccmc_status ccmc_profile_read(ccmc_state *st, ccmc_kernel_time *out, int capacity, int *n);
+
+/* Sizes of the state's system: electrons N, spin orbitals M (for the UEG derived from
+ * n2_max at init) and bitstring words W = ceil(M/64).  Any output pointer may be NULL. */
+ccmc_status ccmc_dims(const ccmc_state *st, int *n_electrons, int *n_spin_orbitals, int *n_words);
+
+/* Device memory currently held by the state, in bytes. */
+ccmc_status ccmc_memory(const ccmc_state *st, uint64_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

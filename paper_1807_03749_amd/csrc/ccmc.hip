@@ -1,0 +1,1131 @@
+// ccmc.hip -- host side of the MI355X CCMC step library: system tables, device buffers,
+// the launch sequence of one time step, and the C ABI declared in include/ccmc.h.
+//
+// Paper: Spencer, Neufeld, Vigor, Franklin & Thom, arXiv:1807.03749 (Sec. II, Sec. IV).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "ccmc.h"
+#include "kernels.h"
+
+using namespace ccmc;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+// ------------------------------------------------------------------ device buffers
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Pending {
+    const char *name;
+    hipEvent_t a, b;
+    double bytes, items;
+};
+
+struct Accum {
+    uint64_t launches = 0;
+    double ms = 0, bytes = 0, items = 0;
+};
+
+// Host description of the system.
+struct HostSys {
+    int kind = 0, nel = 0, M = 0, W = 0, nsp = 0;
+    std::vector<int> nvec;   // [nsp][3]
+    double L = 0, omega = 0, kf = 0;
+    int n2max = 0, G = 0;
+    std::vector<int> grid;
+    std::vector<double> vq;
+    std::vector<double> h;   // molecular [nsp][nsp]
+    std::vector<double> fock, vpair;
+    double ehf = 0;
+};
+
+}  // namespace
+
+struct ccmc_state {
+    ccmc_system sys{};
+    ccmc_options opt{};
+    int l = 0;
+    int W = 0, WP = 0;
+    bool fp32 = false;
+    size_t es = 8;  // amplitude element size
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    HostSys hs;
+    SysDev sd{};
+    std::vector<DevBuf *> all;
+    DevBuf t_grid, t_nvec, t_vq, t_h, t_eri, t_fock, t_vpair;
+    // the store: current buffer cur, merge target 1 - cur
+    DevBuf skey[2], samp[2], sK[2];
+    uint64_t scap = 0;
+    int cur = 0;
+    uint64_t ne = 0;
+    double n0 = 0;
+    uint64_t step = 0;
+    double last_num = 0, last_den = 0;
+    // per-step buffers
+    DevBuf q, P, delta;
+    DevBuf ikey, iA, ideath, in, ilevel, icnt, ioff;
+    uint64_t icap = 0;
+    DevBuf num_part, abs_part;
+    DevBuf rkey, ramp, rid, rcount, boff;
+    uint64_t rcap = 0;  // region slots
+    DevBuf dkey, damp, did, sk[2], sidx[2], hist, hoff;
+    DevBuf flag, incl, start, is_new, new_pos, ins, seg_sum, nkey, nins, nsum, keep, pos;
+    uint64_t dcap = 0;  // dense record capacity
+    std::vector<DevBuf> scan_tmp;
+    DevBuf scratch;
+    Scratch *hscratch = nullptr;  // pinned
+    uint64_t *hpinned = nullptr;  // pinned small readbacks
+    // last step's spawn list (keep_spawn_ids)
+    uint64_t last_nrec = 0;
+    int last_rec_buf = -1;
+    size_t bytes_held = 0;
+    std::string err;
+    bool prof = false;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> ev_pool;
+    std::map<std::string, Accum> accum;
+};
+
+namespace {
+
+#define HIP_TRY(...)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (__VA_ARGS__);                                                        \
+        if (e_ != hipSuccess) {                                                               \
+            st->err = std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_);               \
+            return CCMC_EDEVICE;                                                              \
+        }                                                                                     \
+    } while (0)
+
+#define TRY(...)                                                                              \
+    do {                                                                                      \
+        ccmc_status s_ = (__VA_ARGS__);                                                       \
+        if (s_ != CCMC_OK) return s_;                                                         \
+    } while (0)
+
+ccmc_status ensure(ccmc_state *st, DevBuf &b, size_t bytes)
+{
+    if (bytes <= b.bytes) return CCMC_OK;
+    size_t nb = std::max<size_t>(bytes, 256);
+    nb = std::max(nb, b.bytes + b.bytes / 2);
+    if (st->opt.hbm_budget_bytes && st->bytes_held - b.bytes + nb > st->opt.hbm_budget_bytes) {
+        nb = bytes;
+        if (st->bytes_held - b.bytes + nb > st->opt.hbm_budget_bytes) {
+            st->err = "HBM budget of " + std::to_string(st->opt.hbm_budget_bytes) + " bytes exceeded";
+            return CCMC_ENOMEM;
+        }
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, nb) != hipSuccess) {
+        (void)hipGetLastError();
+        st->err = "hipMalloc of " + std::to_string(nb) + " bytes failed";
+        return CCMC_ENOMEM;
+    }
+    if (b.p) {
+        (void)hipStreamSynchronize(st->stream);
+        (void)hipFree(b.p);
+    }
+    st->bytes_held += nb - b.bytes;
+    b.p = p;
+    b.bytes = nb;
+    return CCMC_OK;
+}
+
+void release(ccmc_state *st, DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    st->bytes_held -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <class X>
+X *ptr(DevBuf &b)
+{
+    return static_cast<X *>(b.p);
+}
+
+unsigned grid_for(uint64_t n, uint64_t per_block = kThreads)
+{
+    return (unsigned)std::max<uint64_t>(1, (n + per_block - 1) / per_block);
+}
+
+// --------------------------------------------------------------------- profiling
+hipEvent_t take_event(ccmc_state *st)
+{
+    if (!st->ev_pool.empty()) {
+        hipEvent_t e = st->ev_pool.back();
+        st->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+template <class F>
+void launch(ccmc_state *st, const char *name, double bytes, double items, F &&f)
+{
+    if (!st->prof) {
+        f();
+        return;
+    }
+    Pending p{name, take_event(st), take_event(st), bytes, items};
+    (void)hipEventRecord(p.a, st->stream);
+    f();
+    (void)hipEventRecord(p.b, st->stream);
+    st->pending.push_back(p);
+}
+
+void resolve_profile(ccmc_state *st)
+{
+    for (auto &p : st->pending) {
+        float ms = 0;
+        (void)hipEventSynchronize(p.b);
+        (void)hipEventElapsedTime(&ms, p.a, p.b);
+        Accum &a = st->accum[p.name];
+        a.launches++;
+        a.ms += ms;
+        a.bytes += p.bytes;
+        a.items += p.items;
+        st->ev_pool.push_back(p.a);
+        st->ev_pool.push_back(p.b);
+    }
+    st->pending.clear();
+}
+
+// --------------------------------------------------------------------------- scan
+template <typename V>
+ccmc_status scan(ccmc_state *st, const V *in, V *out, uint64_t n, bool inclusive, int level = 0)
+{
+    if (n == 0) return CCMC_OK;
+    const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
+    if (tiles == 1) {
+        k_scan_tile<V><<<1, kThreads, 0, st->stream>>>(in, out, n, nullptr, inclusive ? 1 : 0);
+        return CCMC_OK;
+    }
+    if ((int)st->scan_tmp.size() < 2 * (level + 1)) st->scan_tmp.resize(2 * (level + 1));
+    TRY(ensure(st, st->scan_tmp[2 * level], tiles * sizeof(V)));
+    TRY(ensure(st, st->scan_tmp[2 * level + 1], tiles * sizeof(V)));
+    V *part = ptr<V>(st->scan_tmp[2 * level]);
+    V *poff = ptr<V>(st->scan_tmp[2 * level + 1]);
+    k_scan_reduce<V><<<(unsigned)tiles, kThreads, 0, st->stream>>>(in, n, part);
+    TRY(scan<V>(st, part, poff, tiles, false, level + 1));
+    k_scan_tile<V><<<(unsigned)tiles, kThreads, 0, st->stream>>>(in, out, n, poff, inclusive ? 1 : 0);
+    return CCMC_OK;
+}
+
+// ------------------------------------------------------------------------ systems
+int words_for(int M) { return (M + 63) / 64; }
+int padded_words(int W)
+{
+    static const int ws[] = {1, 2, 3, 4, 6, 8};
+    for (int w : ws)
+        if (w >= W) return w;
+    return -1;
+}
+
+bool build_ueg(HostSys &hs, int nel, int n2max, double rs, std::string &err)
+{
+    int nmax = 0;
+    while ((nmax + 1) * (nmax + 1) <= n2max) ++nmax;
+    std::vector<std::array<int, 4>> v;
+    for (int x = -nmax; x <= nmax; ++x)
+        for (int y = -nmax; y <= nmax; ++y)
+            for (int z = -nmax; z <= nmax; ++z) {
+                const int n2 = x * x + y * y + z * z;
+                if (n2 <= n2max) v.push_back({n2, x, y, z});
+            }
+    std::sort(v.begin(), v.end());  // by |n|^2, then n_x, n_y, n_z
+    const int nocc = nel / 2;
+    if (nel < 2 || (nel & 1) || nocc > (int)v.size() || 2 * (int)v.size() > 64 * kMaxWords) {
+        err = "UEG: need an even number of electrons that fits the basis (M <= 512)";
+        return false;
+    }
+    if (nocc < (int)v.size() && v[nocc - 1][0] == v[nocc][0]) {
+        err = "UEG: open shell (the last occupied and first virtual plane waves share |n|^2)";
+        return false;
+    }
+    hs.kind = CCMC_UEG;
+    hs.nel = nel;
+    hs.nsp = (int)v.size();
+    hs.M = 2 * hs.nsp;
+    hs.n2max = n2max;
+    hs.nvec.resize(3 * hs.nsp);
+    for (int i = 0; i < hs.nsp; ++i)
+        for (int c = 0; c < 3; ++c) hs.nvec[3 * i + c] = v[i][1 + c];
+    hs.L = rs * std::cbrt(4.0 * M_PI * nel / 3.0);
+    hs.omega = hs.L * hs.L * hs.L;
+    hs.kf = 2.0 * M_PI / hs.L;
+    // Coulomb kernel 4 pi / (Omega |k|^2), |k|^2 = kf^2 |dn|^2, |dn|^2 <= 4 n2max
+    hs.vq.assign(4 * n2max + 1, 0.0);
+    for (int d = 1; d <= 4 * n2max; ++d) hs.vq[d] = 4.0 * M_PI / (hs.omega * (hs.kf * hs.kf * (double)d));
+    hs.G = 3 * nmax;
+    const int D = 2 * hs.G + 1;
+    hs.grid.assign((size_t)D * D * D, -1);
+    for (int i = 0; i < hs.nsp; ++i) {
+        const int *n = &hs.nvec[3 * i];
+        hs.grid[((size_t)(n[0] + hs.G) * D + (n[1] + hs.G)) * D + (n[2] + hs.G)] = i;
+    }
+    const int M = hs.M;
+    auto u_exch = [&](int p, int q) -> double {  // <pq|qp>, p != q
+        if ((p ^ q) & 1) return 0.0;
+        const int *a = &hs.nvec[3 * (p >> 1)], *b = &hs.nvec[3 * (q >> 1)];
+        const int d = (a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]) + (a[2] - b[2]) * (a[2] - b[2]);
+        return d ? hs.vq[d] : 0.0;
+    };
+    hs.vpair.assign((size_t)M * M, 0.0);
+    for (int p = 0; p < M; ++p)
+        for (int q = 0; q < M; ++q)
+            if (p != q) hs.vpair[(size_t)p * M + q] = -u_exch(p, q);  // direct term is q = 0
+    hs.fock.assign(M, 0.0);
+    double e1 = 0, e2 = 0;
+    for (int p = 0; p < M; ++p) {
+        const int *n = &hs.nvec[3 * (p >> 1)];
+        const double t = 0.5 * hs.kf * hs.kf * (double)(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        double f = t;
+        for (int j = 0; j < nel; ++j) f += hs.vpair[(size_t)p * M + j];
+        hs.fock[p] = f;
+        if (p < nel) {
+            e1 += t;
+            for (int j = 0; j < nel; ++j) e2 += hs.vpair[(size_t)p * M + j];
+        }
+    }
+    hs.ehf = e1 + 0.5 * e2;
+    return true;
+}
+
+bool build_mol(HostSys &hs, int nel, const ccmc_integrals *ints, std::string &err)
+{
+    const int n = ints->n_spatial;
+    if (nel < 2 || (nel & 1) || n < 1 || nel > 2 * n || 2 * n > 64 * kMaxWords || !ints->h ||
+        ints->n_chol < 0 || (ints->n_chol > 0 && !ints->chol)) {
+        err = "molecular: invalid sizes or null integral arrays";
+        return false;
+    }
+    hs.kind = CCMC_MOLECULAR;
+    hs.nel = nel;
+    hs.nsp = n;
+    hs.M = 2 * n;
+    hs.h.assign(ints->h, ints->h + (size_t)n * n);
+    const int M = hs.M;
+    const size_t nn = (size_t)n * n;
+    auto eri = [&](int P, int Q, int R, int S) {  // (PQ|RS), summed over L in order
+        double v = 0.0;
+        for (int L = 0; L < ints->n_chol; ++L) v += ints->chol[L * nn + (size_t)P * n + Q] * ints->chol[L * nn + (size_t)R * n + S];
+        return v;
+    };
+    hs.vpair.assign((size_t)M * M, 0.0);
+    for (int p = 0; p < M; ++p)
+        for (int q = 0; q < M; ++q) {
+            if (p == q) continue;
+            const int P = p >> 1, Q = q >> 1;
+            double v = eri(P, P, Q, Q);  // <pq|pq> = (PP|QQ)
+            if (((p ^ q) & 1) == 0) v -= eri(P, Q, Q, P);  // <pq|qp> = (PQ|QP)
+            hs.vpair[(size_t)p * M + q] = v;
+        }
+    hs.fock.assign(M, 0.0);
+    double e1 = 0, e2 = 0;
+    for (int p = 0; p < M; ++p) {
+        const double hp = hs.h[(size_t)(p >> 1) * n + (p >> 1)];
+        double f = hp;
+        for (int j = 0; j < nel; ++j) f += hs.vpair[(size_t)p * M + j];
+        hs.fock[p] = f;
+        if (p < nel) {
+            e1 += hp;
+            for (int j = 0; j < nel; ++j) e2 += hs.vpair[(size_t)p * M + j];
+        }
+    }
+    hs.ehf = e1 + 0.5 * e2;
+    return true;
+}
+
+template <typename T>
+ccmc_status upload_table(ccmc_state *st, DevBuf &b, const std::vector<double> &v)
+{
+    std::vector<T> t(v.begin(), v.end());
+    TRY(ensure(st, b, std::max<size_t>(1, t.size()) * sizeof(T)));
+    if (!t.empty()) HIP_TRY(hipMemcpy(b.p, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice));
+    return CCMC_OK;
+}
+
+template <typename T>
+ccmc_status upload_system(ccmc_state *st, const ccmc_integrals *ints)
+{
+    HostSys &hs = st->hs;
+    SysDev &S = st->sd;
+    S.kind = hs.kind;
+    S.nel = hs.nel;
+    S.M = hs.M;
+    S.nsp = hs.nsp;
+    S.l = st->l;
+    S.npairs = (uint32_t)(hs.nel * (hs.nel - 1) / 2);
+    S.half = (uint32_t)(hs.M / 2);
+    for (int w = 0; w < kMaxWords; ++w) S.hf[w] = 0;
+    for (int p = 0; p < hs.nel; ++p) S.hf[p >> 6] |= 1ull << (p & 63);
+    S.p_single = st->opt.p_single;
+    TRY(upload_table<T>(st, st->t_fock, hs.fock));
+    TRY(upload_table<T>(st, st->t_vpair, hs.vpair));
+    S.fock = st->t_fock.p;
+    S.vpair = st->t_vpair.p;
+    if (hs.kind == CCMC_UEG) {
+        S.G = hs.G;
+        TRY(ensure(st, st->t_grid, hs.grid.size() * sizeof(int)));
+        HIP_TRY(hipMemcpy(st->t_grid.p, hs.grid.data(), hs.grid.size() * sizeof(int), hipMemcpyHostToDevice));
+        TRY(ensure(st, st->t_nvec, hs.nvec.size() * sizeof(int)));
+        HIP_TRY(hipMemcpy(st->t_nvec.p, hs.nvec.data(), hs.nvec.size() * sizeof(int), hipMemcpyHostToDevice));
+        TRY(upload_table<T>(st, st->t_vq, hs.vq));
+        S.grid = ptr<int>(st->t_grid);
+        S.nvec = ptr<int>(st->t_nvec);
+        S.vq = st->t_vq.p;
+    } else {
+        TRY(upload_table<T>(st, st->t_h, hs.h));
+        S.h = st->t_h.p;
+        const uint64_t n = hs.nsp, n4 = n * n * n * n;
+        DevBuf chol;
+        const size_t cb = std::max<size_t>(1, (size_t)ints->n_chol * n * n) * sizeof(double);
+        TRY(ensure(st, chol, cb));
+        if (ints->n_chol > 0)
+            HIP_TRY(hipMemcpy(chol.p, ints->chol, (size_t)ints->n_chol * n * n * sizeof(double), hipMemcpyHostToDevice));
+        TRY(ensure(st, st->t_eri, n4 * sizeof(T)));
+        k_build_eri<T><<<grid_for(n4), kThreads, 0, st->stream>>>(ptr<double>(chol), (int)n, ints->n_chol, ptr<T>(st->t_eri));
+        HIP_TRY(hipStreamSynchronize(st->stream));
+        release(st, chol);
+        S.eri = st->t_eri.p;
+    }
+    return CCMC_OK;
+}
+
+// ------------------------------------------------------------------------ the store
+// Grow the store (both buffers) to hold n entries, keeping the current contents.
+template <int W, typename T>
+ccmc_status ensure_store(ccmc_state *st, uint64_t n)
+{
+    if (n <= st->scap) return CCMC_OK;
+    uint64_t nc = std::max<uint64_t>(n, std::max<uint64_t>(1024, st->scap + st->scap / 2));
+    DevBuf k, a, K;
+    TRY(ensure(st, k, nc * W * sizeof(uint64_t)));
+    TRY(ensure(st, a, nc * sizeof(T)));
+    TRY(ensure(st, K, nc * sizeof(T)));
+    const int c = st->cur;
+    if (st->ne) {
+        HIP_TRY(hipMemcpy2DAsync(k.p, nc * sizeof(uint64_t), st->skey[c].p, st->scap * sizeof(uint64_t),
+                                 st->ne * sizeof(uint64_t), W, hipMemcpyDeviceToDevice, st->stream));
+        HIP_TRY(hipMemcpyAsync(a.p, st->samp[c].p, st->ne * sizeof(T), hipMemcpyDeviceToDevice, st->stream));
+        HIP_TRY(hipMemcpyAsync(K.p, st->sK[c].p, st->ne * sizeof(T), hipMemcpyDeviceToDevice, st->stream));
+        HIP_TRY(hipStreamSynchronize(st->stream));
+    }
+    for (int b = 0; b < 2; ++b) {
+        release(st, st->skey[b]);
+        release(st, st->samp[b]);
+        release(st, st->sK[b]);
+    }
+    st->skey[c] = k;
+    st->samp[c] = a;
+    st->sK[c] = K;
+    TRY(ensure(st, st->skey[1 - c], nc * W * sizeof(uint64_t)));
+    TRY(ensure(st, st->samp[1 - c], nc * sizeof(T)));
+    TRY(ensure(st, st->sK[1 - c], nc * sizeof(T)));
+    TRY(ensure(st, st->q, nc * sizeof(uint64_t)));
+    TRY(ensure(st, st->P, nc * sizeof(uint64_t)));
+    TRY(ensure(st, st->delta, nc * sizeof(double)));
+    st->scap = nc;
+    return CCMC_OK;
+}
+
+// ---------------------------------------------------------------------- the step
+template <int W, typename T>
+ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, ccmc_stats *out)
+{
+    hipStream_t s = st->stream;
+    const uint64_t ne = st->ne;
+    const bool fnc = st->opt.full_noncomposite != 0;
+    const uint64_t n_fnc = fnc ? ne + 1 : 0;
+    const uint64_t n_items = n_fnc + n_sel;
+    const int c = st->cur;
+    const uint64_t scap = st->scap;
+    const uint64_t *skey = ptr<uint64_t>(st->skey[c]);
+    const T *samp = ptr<T>(st->samp[c]);
+    const T *sK = ptr<T>(st->sK[c]);
+    const double ab = (double)(W * 8 + sizeof(T));  // bytes of one key + amplitude
+
+    StepArgs a;
+    a.tau = tau;
+    a.shift = shift;
+    a.cutoff = st->opt.spawn_cutoff;
+    a.theta = st->opt.occupation_threshold;
+    a.thr_cluster = st->opt.multispawn_threshold;
+    a.thr_nc = st->opt.noncomposite_threshold;
+    a.kmin = (uint32_t)st->opt.min_spawn_attempts;
+    a.step = (uint32_t)(st->step & 0x0FFFFFFFu);
+    a.key0 = (uint32_t)st->opt.seed;
+    a.key1 = (uint32_t)(st->opt.seed >> 32);
+    a.n_sel = n_sel;
+    a.fnc = fnc ? 1 : 0;
+
+    Scratch *sc = ptr<Scratch>(st->scratch);
+    HIP_TRY(hipMemsetAsync(sc, 0, sizeof(Scratch), s));
+
+    // (a1) selection weights and their inclusive prefix
+    if (ne) {
+        launch(st, "weights", ne * (sizeof(T) + 8.0), (double)ne, [&] {
+            k_weights<T><<<grid_for(ne), kThreads, 0, s>>>(samp, ne, ptr<uint64_t>(st->q), sc);
+        });
+        TRY(scan<uint64_t>(st, ptr<uint64_t>(st->q), ptr<uint64_t>(st->P), ne, true));
+    }
+    k_qtot<<<1, 1, 0, s>>>(ptr<uint64_t>(st->P), ne, sc);
+
+    // items: non-composite (FNC) then sampled clusters
+    if (n_items + 1 > st->icap) {
+        const uint64_t nc = std::max<uint64_t>(n_items + 1, st->icap + st->icap / 2);
+        TRY(ensure(st, st->ikey, nc * W * sizeof(uint64_t)));
+        TRY(ensure(st, st->iA, nc * sizeof(T)));
+        TRY(ensure(st, st->ideath, nc * sizeof(T)));
+        TRY(ensure(st, st->in, nc * sizeof(uint32_t)));
+        TRY(ensure(st, st->ilevel, nc));
+        TRY(ensure(st, st->icnt, nc * sizeof(uint64_t)));
+        TRY(ensure(st, st->ioff, nc * sizeof(uint64_t)));
+        st->icap = nc;
+    }
+    Items<T> it{ptr<uint64_t>(st->ikey), ptr<T>(st->iA), ptr<T>(st->ideath), ptr<uint32_t>(st->in),
+                ptr<uint8_t>(st->ilevel), ptr<uint64_t>(st->icnt), st->icap};
+    const unsigned nb_fnc = fnc ? grid_for(n_fnc) : 0, nb_sel = n_sel ? grid_for(n_sel) : 0;
+    TRY(ensure(st, st->num_part, (size_t)(nb_fnc + nb_sel + 1) * sizeof(double)));
+    double *num_part = ptr<double>(st->num_part);
+    if (fnc) {
+        launch(st, "noncomposite", n_fnc * (ab + sizeof(T)) + n_fnc * (W * 8 + 3 * sizeof(T) + 13.0), (double)n_fnc, [&] {
+            k_noncomposite<W, T><<<nb_fnc, kThreads, 0, s>>>(st->sd, skey, samp, sK, scap, ne, st->n0, a, it, num_part, sc);
+        });
+    }
+    if (n_sel) {
+        launch(st, "select", n_sel * (W * 8 + 2 * sizeof(T) + 13.0), (double)n_sel, [&] {
+            k_select<W, T><<<nb_sel, kThreads, 0, s>>>(st->sd, skey, samp, scap, ne, ptr<uint64_t>(st->P), st->n0, a, it,
+                                                        n_fnc, num_part + nb_fnc, sc);
+        });
+    }
+    k_fill<uint64_t><<<1, 1, 0, s>>>(it.cnt + n_items, 1, 0ull);
+    TRY(scan<uint64_t>(st, it.cnt, ptr<uint64_t>(st->ioff), n_items + 1, false));
+    k_reduce_partials<<<1, kThreads, 0, s>>>(num_part, nb_fnc + nb_sel, &sc->num);
+    HIP_TRY(hipMemcpyAsync(st->hpinned, ptr<uint64_t>(st->ioff) + n_items, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(st->hscratch, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (st->hscratch->err & 1ull) {
+        st->err = "population beyond the fixed-point range of the selection weights";
+        return CCMC_EBLOWUP;
+    }
+    if (st->hscratch->err & 2ull) {
+        st->err = "more than 2^30-2 spawning attempts on one cluster";
+        return CCMC_EOVERFLOW;
+    }
+    const uint64_t n_slots = st->hpinned[0];
+
+    // (a6-a8) records: death and spawning attempts, one lane per slot
+    const uint64_t nblk = (n_slots + kGenSlots - 1) / kGenSlots;
+    if (n_slots + ne + 1 >= (1ull << 32)) {
+        st->err = "more than 2^32 record slots in one step";
+        return CCMC_EOVERFLOW;
+    }
+    const bool ids = st->opt.keep_spawn_ids != 0;
+    if (nblk * kGenSlots > st->rcap) {
+        const uint64_t nc = std::max<uint64_t>(nblk * kGenSlots, st->rcap + st->rcap / 2);
+        TRY(ensure(st, st->rkey, nc * W * sizeof(uint64_t)));
+        TRY(ensure(st, st->ramp, nc * sizeof(T)));
+        if (ids) TRY(ensure(st, st->rid, nc * sizeof(uint64_t)));
+        TRY(ensure(st, st->rcount, (nc / kGenSlots + 1) * sizeof(uint32_t)));
+        TRY(ensure(st, st->boff, (nc / kGenSlots + 1) * sizeof(uint64_t)));
+        st->rcap = nc;
+    }
+    Records rec{ptr<uint64_t>(st->rkey), st->ramp.p, ptr<uint64_t>(st->rid), ptr<uint32_t>(st->rcount), st->rcap};
+    if (nblk) {
+        launch(st, "generate", (double)n_slots * 16.0, (double)n_slots, [&] {
+            k_generate<W, T><<<(unsigned)nblk, kThreads, 0, s>>>(st->sd, it, ptr<uint64_t>(st->ioff), n_items, n_fnc,
+                                                                 n_slots, a, rec, ids ? 1 : 0, sc);
+        });
+    }
+    // block counts -> offsets (u32 counts widened through a u64 scan buffer)
+    if (nblk) {
+        uint64_t *boff = ptr<uint64_t>(st->boff);
+        TRY(ensure(st, st->keep, (nblk + 1) * sizeof(uint64_t)));
+        uint64_t *cnt64 = ptr<uint64_t>(st->keep);
+        k_fill<uint64_t><<<grid_for(nblk + 1), kThreads, 0, s>>>(cnt64, nblk + 1, 0ull);
+        k_widen<<<grid_for(nblk), kThreads, 0, s>>>(ptr<uint32_t>(st->rcount), cnt64, nblk);
+        TRY(scan<uint64_t>(st, cnt64, boff, nblk + 1, false));
+        HIP_TRY(hipMemcpyAsync(st->hpinned, boff + nblk, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    } else {
+        st->hpinned[0] = 0;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint64_t nrec = st->hpinned[0];
+
+    // dense record arrays and sort buffers
+    if (nrec + 1 > st->dcap || ne + nrec + 1 > st->dcap) {
+        const uint64_t nc = std::max<uint64_t>(std::max(nrec, ne) + 1, st->dcap + st->dcap / 2);
+        for (DevBuf *b : {&st->dkey, &st->sk[0], &st->sk[1], &st->nkey}) TRY(ensure(st, *b, nc * W * sizeof(uint64_t)));
+        TRY(ensure(st, st->damp, nc * sizeof(T)));
+        if (ids) TRY(ensure(st, st->did, nc * sizeof(uint64_t)));
+        for (DevBuf *b : {&st->sidx[0], &st->sidx[1], &st->flag, &st->incl, &st->start, &st->is_new, &st->new_pos})
+            TRY(ensure(st, *b, nc * sizeof(uint32_t)));
+        for (DevBuf *b : {&st->ins, &st->nins}) TRY(ensure(st, *b, nc * sizeof(uint64_t)));
+        for (DevBuf *b : {&st->seg_sum, &st->nsum}) TRY(ensure(st, *b, nc * sizeof(double)));
+        st->dcap = nc;
+    }
+    TRY(ensure_store<W, T>(st, ne + nrec + 1));
+    // the store may have moved
+    skey = ptr<uint64_t>(st->skey[c]);
+    samp = ptr<T>(st->samp[c]);
+    sK = ptr<T>(st->sK[c]);
+    const uint64_t S2 = st->scap;
+    TRY(ensure(st, st->keep, (ne + nrec + 1) * sizeof(uint32_t)));
+    TRY(ensure(st, st->pos, (ne + nrec + 1) * sizeof(uint32_t)));
+    const uint64_t dc = st->dcap;
+    uint64_t *dkey = ptr<uint64_t>(st->dkey);
+    T *damp = ptr<T>(st->damp);
+    if (nblk) {
+        launch(st, "gather", 2.0 * nrec * (W * 8 + sizeof(T) + (ids ? 8 : 0)), (double)nrec, [&] {
+            k_gather<W, T><<<(unsigned)nblk, kThreads, 0, s>>>(st->sd, rec, ptr<uint64_t>(st->boff), dkey, damp,
+                                                               ptr<uint64_t>(st->did), dc, ids ? 1 : 0, sc);
+        });
+    }
+    HIP_TRY(hipMemcpyAsync(st->hscratch, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    Scratch scr = *st->hscratch;
+
+    // (a11) stable LSD radix sort by determinant over the digits that vary
+    std::vector<std::pair<int, int>> passes;
+    for (int w = 0; w < W; ++w)
+        for (int sh = 0; sh < 64; sh += 8)
+            if ((scr.diffmask[w] >> sh) & 0xFFull) passes.push_back({w, sh});
+    if (passes.empty()) passes.push_back({0, 0});
+    const uint32_t n32 = (uint32_t)nrec;
+    const uint32_t tiles = (uint32_t)std::max<uint64_t>(1, (nrec + kSortTile - 1) / kSortTile);
+    TRY(ensure(st, st->hist, (size_t)256 * tiles * sizeof(uint32_t)));
+    TRY(ensure(st, st->hoff, (size_t)256 * tiles * sizeof(uint32_t)));
+    const uint64_t *kin = dkey;
+    const uint32_t *iin = nullptr;
+    int ob = 0;
+    if (nrec) {
+        for (auto &pp : passes) {
+            uint64_t *kout = ptr<uint64_t>(st->sk[ob]);
+            uint32_t *iout = ptr<uint32_t>(st->sidx[ob]);
+            launch(st, "radix_hist", nrec * 8.0, (double)nrec, [&] {
+                k_radix_hist<W><<<tiles, kThreads, 0, s>>>(kin, dc, n32, pp.first, pp.second, ptr<uint32_t>(st->hist), tiles);
+            });
+            TRY(scan<uint32_t>(st, ptr<uint32_t>(st->hist), ptr<uint32_t>(st->hoff), (uint64_t)256 * tiles, false));
+            launch(st, "radix_scatter", 2.0 * nrec * (W * 8 + 4), (double)nrec, [&] {
+                k_radix_scatter<W><<<tiles, kThreads, 0, s>>>(kin, iin, kout, iout, dc, n32, pp.first, pp.second,
+                                                              ptr<uint32_t>(st->hoff), tiles);
+            });
+            kin = kout;
+            iin = iout;
+            ob ^= 1;
+        }
+    }
+    const uint64_t *sorted_key = kin;
+    const uint32_t *sorted_idx = iin;
+
+    // (a12) segments: heads, left fold in record order, store lookup
+    double *delta = ptr<double>(st->delta);
+    if (ne) k_fill<double><<<grid_for(ne), kThreads, 0, s>>>(delta, ne, 0.0);
+    if (nrec) {
+        uint32_t *flag = ptr<uint32_t>(st->flag), *incl = ptr<uint32_t>(st->incl), *start = ptr<uint32_t>(st->start);
+        k_seg_flags<W><<<grid_for(nrec), kThreads, 0, s>>>(sorted_key, dc, n32, flag);
+        TRY(scan<uint32_t>(st, flag, incl, nrec, true));
+        k_seg_starts<<<grid_for(nrec), kThreads, 0, s>>>(flag, incl, n32, start, sc);
+        k_fill<uint32_t><<<grid_for(nrec), kThreads, 0, s>>>(ptr<uint32_t>(st->is_new), nrec, 0u);
+        launch(st, "seg_fold", nrec * (W * 8 + 4.0 + sizeof(T)), (double)nrec, [&] {
+            k_seg_fold<W, T><<<grid_for(nrec), kThreads, 0, s>>>(st->sd, sorted_key, dc, sorted_idx, damp, n32, start, skey, S2,
+                                                                 ne, delta, ptr<uint32_t>(st->is_new), ptr<uint64_t>(st->ins),
+                                                                 ptr<double>(st->seg_sum), sc);
+        });
+        TRY(scan<uint32_t>(st, ptr<uint32_t>(st->is_new), ptr<uint32_t>(st->new_pos), nrec, false));
+        k_new_compact<W><<<grid_for(nrec), kThreads, 0, s>>>(sorted_key, dc, start, ptr<uint32_t>(st->is_new),
+                                                             ptr<uint32_t>(st->new_pos), ptr<uint64_t>(st->ins),
+                                                             ptr<double>(st->seg_sum), ptr<uint64_t>(st->nkey), dc,
+                                                             ptr<uint64_t>(st->nins), ptr<double>(st->nsum), sc);
+    }
+    // merge into the other store buffer, round, compact back into the current buffer
+    const int m = 1 - c;
+    uint64_t *mkey = ptr<uint64_t>(st->skey[m]);
+    T *mamp = ptr<T>(st->samp[m]);
+    T *mK = ptr<T>(st->sK[m]);
+    const uint64_t nmax = ne + nrec;
+    if (nmax) {
+        launch(st, "merge", (double)nmax * 2.0 * (W * 8 + 2 * sizeof(T)), (double)nmax, [&] {
+            k_merge<W, T><<<grid_for(nmax), kThreads, 0, s>>>(st->sd, skey, samp, sK, S2, ne, delta, ptr<uint64_t>(st->nkey),
+                                                              dc, ptr<uint64_t>(st->nins), ptr<double>(st->nsum), mkey, mamp,
+                                                              mK, S2, sc);
+        });
+        uint32_t *keep = ptr<uint32_t>(st->keep), *pos = ptr<uint32_t>(st->pos);
+        launch(st, "round", (double)nmax * (2 * sizeof(T) + 4.0), (double)nmax, [&] {
+            k_round<T><<<grid_for(nmax), kThreads, 0, s>>>(mamp, ne, a, keep, sc);
+        });
+        TRY(scan<uint32_t>(st, keep, pos, nmax, false));
+        TRY(ensure(st, st->abs_part, grid_for(nmax) * sizeof(double)));
+        launch(st, "compact", (double)nmax * 2.0 * (W * 8 + 2 * sizeof(T)), (double)nmax, [&] {
+            k_compact<W, T><<<grid_for(nmax), kThreads, 0, s>>>(mkey, mamp, mK, S2, ne, keep, pos, ptr<uint64_t>(st->skey[c]),
+                                                                ptr<T>(st->samp[c]), ptr<T>(st->sK[c]), S2,
+                                                                ptr<double>(st->abs_part), sc);
+        });
+        k_reduce_partials<<<1, kThreads, 0, s>>>(ptr<double>(st->abs_part), grid_for(nmax), &sc->n_total);
+    }
+    HIP_TRY(hipMemcpyAsync(st->hscratch, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    scr = *st->hscratch;
+    if (st->prof) resolve_profile(st);
+
+    const double n0_old = st->n0;
+    if (scr.hf_hit) st->n0 = st->n0 + scr.hf_sum;
+    st->ne = nmax ? scr.n_out : 0;
+    st->step += 1;
+    st->last_num = scr.num;
+    st->last_den = n0_old;
+    st->last_nrec = nrec;
+    st->last_rec_buf = ids ? 1 : -1;
+    if (out) {
+        out->step = st->step;
+        out->n_selections = n_sel;
+        out->n_discarded = scr.n_discarded;
+        out->n_spawn_attempts = scr.n_attempts;
+        out->n_spawns = scr.n_spawns;
+        out->n_deaths = scr.n_deaths;
+        out->n_excitors = st->ne;
+        out->max_attempts_per_cluster = scr.max_n;
+        out->n_total = scr.n_total + std::fabs(st->n0);
+        out->n_ref = st->n0;
+        out->eproj_num = scr.num;
+        out->eproj_den = n0_old;
+    }
+    return CCMC_OK;
+}
+
+template <int W, typename T>
+ccmc_status import_impl(ccmc_state *st, const uint64_t *keys, const double *amps, uint64_t n, double n_ref, uint64_t step)
+{
+    const int Wt = st->W, M = st->hs.M;
+    std::vector<uint64_t> hf(W, 0);
+    for (int p = 0; p < st->hs.nel; ++p) hf[p >> 6] |= 1ull << (p & 63);
+    auto cmp = [&](const uint64_t *x, const uint64_t *y) {
+        for (int w = Wt - 1; w >= 0; --w)
+            if (x[w] != y[w]) return x[w] < y[w] ? -1 : 1;
+        return 0;
+    };
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t *k = keys + i * Wt;
+        if (i && cmp(keys + (i - 1) * Wt, k) >= 0) {
+            st->err = "import: keys not strictly ascending at entry " + std::to_string(i);
+            return CCMC_EINVAL;
+        }
+        int cnt = 0, lev = 0;
+        for (int w = 0; w < Wt; ++w) {
+            uint64_t v = k[w];
+            if (64 * (w + 1) > M) {
+                const int keepb = M - 64 * w;
+                const uint64_t mask = keepb >= 64 ? ~0ull : ((1ull << keepb) - 1ull);
+                if (v & ~mask) {
+                    st->err = "import: bits at or above M in entry " + std::to_string(i);
+                    return CCMC_EINVAL;
+                }
+            }
+            cnt += __builtin_popcountll(v);
+            lev += __builtin_popcountll(v & ~hf[w]);
+        }
+        if (cnt != st->hs.nel || lev < 1 || lev > st->l) {
+            st->err = "import: entry " + std::to_string(i) + " has the wrong electron count or level";
+            return CCMC_EINVAL;
+        }
+        if (!(amps[i] != 0.0) || !std::isfinite(amps[i])) {
+            st->err = "import: amplitude " + std::to_string(i) + " is zero or not finite";
+            return CCMC_EINVAL;
+        }
+    }
+    if (!std::isfinite(n_ref)) {
+        st->err = "import: N_0 not finite";
+        return CCMC_EINVAL;
+    }
+    st->ne = 0;
+    TRY(ensure_store<W, T>(st, n + 1));
+    const int c = st->cur;
+    const uint64_t cap = st->scap;
+    std::vector<uint64_t> soa((size_t)W * std::max<uint64_t>(n, 1), 0);
+    for (uint64_t i = 0; i < n; ++i)
+        for (int w = 0; w < Wt; ++w) soa[(size_t)w * n + i] = keys[i * Wt + w];
+    std::vector<T> ta(amps, amps + n);
+    if (n) {
+        HIP_TRY(hipMemcpy2D(st->skey[c].p, cap * sizeof(uint64_t), soa.data(), n * sizeof(uint64_t), n * sizeof(uint64_t), W,
+                            hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(st->samp[c].p, ta.data(), n * sizeof(T), hipMemcpyHostToDevice));
+        k_store_diag<W, T><<<grid_for(n), kThreads, 0, st->stream>>>(st->sd, ptr<uint64_t>(st->skey[c]), cap, n,
+                                                                     ptr<T>(st->sK[c]));
+        HIP_TRY(hipStreamSynchronize(st->stream));
+    }
+    st->ne = n;
+    st->n0 = n_ref;
+    st->step = step;
+    st->last_rec_buf = -1;
+    st->last_nrec = 0;
+    return CCMC_OK;
+}
+
+template <int W, typename T>
+ccmc_status export_impl(const ccmc_state *cst, uint64_t *keys, double *amps)
+{
+    ccmc_state *st = const_cast<ccmc_state *>(cst);
+    const uint64_t n = st->ne;
+    if (!n) return CCMC_OK;
+    const int c = st->cur, Wt = st->W;
+    std::vector<uint64_t> soa((size_t)W * n);
+    std::vector<T> ta(n);
+    HIP_TRY(hipMemcpy2D(soa.data(), n * sizeof(uint64_t), st->skey[c].p, st->scap * sizeof(uint64_t), n * sizeof(uint64_t), W,
+                        hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ta.data(), st->samp[c].p, n * sizeof(T), hipMemcpyDeviceToHost));
+    for (uint64_t i = 0; i < n; ++i) {
+        if (keys)
+            for (int w = 0; w < Wt; ++w) keys[i * Wt + w] = soa[(size_t)w * n + i];
+        if (amps) amps[i] = (double)ta[i];
+    }
+    return CCMC_OK;
+}
+
+template <int W, typename T>
+ccmc_status export_spawns_impl(const ccmc_state *cst, uint64_t *keys, double *amps, uint64_t *ids)
+{
+    ccmc_state *st = const_cast<ccmc_state *>(cst);
+    const uint64_t n = st->last_nrec;
+    if (!n) return CCMC_OK;
+    const int Wt = st->W;
+    std::vector<uint64_t> soa((size_t)W * n), id(n);
+    std::vector<T> ta(n);
+    HIP_TRY(hipMemcpy2D(soa.data(), n * sizeof(uint64_t), st->dkey.p, st->dcap * sizeof(uint64_t), n * sizeof(uint64_t), W,
+                        hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ta.data(), st->damp.p, n * sizeof(T), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(id.data(), st->did.p, n * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    for (uint64_t i = 0; i < n; ++i) {
+        if (keys)
+            for (int w = 0; w < Wt; ++w) keys[i * Wt + w] = soa[(size_t)w * n + i];
+        if (amps) amps[i] = (double)ta[i];
+        if (ids) ids[i] = id[i];
+    }
+    return CCMC_OK;
+}
+
+// Dispatch on (padded words, precision).
+template <template <int, typename> class F, typename... Args>
+ccmc_status dispatch(const ccmc_state *st, Args... args)
+{
+#define CCMC_CASE(WW)                                                                   \
+    case WW:                                                                            \
+        return st->fp32 ? F<WW, float>::run(args...) : F<WW, double>::run(args...);
+    switch (st->WP) {
+        CCMC_CASE(1)
+        CCMC_CASE(2)
+        CCMC_CASE(3)
+        CCMC_CASE(4)
+        CCMC_CASE(6)
+        CCMC_CASE(8)
+    }
+#undef CCMC_CASE
+    return CCMC_EINVAL;
+}
+
+template <int W, typename T>
+struct StepF {
+    static ccmc_status run(ccmc_state *st, double tau, double shift, uint64_t n, ccmc_stats *out)
+    {
+        return step_impl<W, T>(st, tau, shift, n, out);
+    }
+};
+template <int W, typename T>
+struct ImportF {
+    static ccmc_status run(ccmc_state *st, const uint64_t *k, const double *a, uint64_t n, double r, uint64_t s)
+    {
+        return import_impl<W, T>(st, k, a, n, r, s);
+    }
+};
+template <int W, typename T>
+struct ExportF {
+    static ccmc_status run(const ccmc_state *st, uint64_t *k, double *a) { return export_impl<W, T>(st, k, a); }
+};
+template <int W, typename T>
+struct SpawnsF {
+    static ccmc_status run(const ccmc_state *st, uint64_t *k, double *a, uint64_t *i)
+    {
+        return export_spawns_impl<W, T>(st, k, a, i);
+    }
+};
+template <int W, typename T>
+struct StoreF {
+    static ccmc_status run(ccmc_state *st, uint64_t n) { return ensure_store<W, T>(st, n); }
+};
+template <int W, typename T>
+struct SystemF {
+    static ccmc_status run(ccmc_state *st, const ccmc_integrals *ints) { return upload_system<T>(st, ints); }
+};
+
+void destroy(ccmc_state *st)
+{
+    if (!st) return;
+    if (st->stream) (void)hipStreamSynchronize(st->stream);
+    DevBuf *bufs[] = {&st->t_grid, &st->t_nvec, &st->t_vq, &st->t_h, &st->t_eri, &st->t_fock, &st->t_vpair,
+                      &st->skey[0], &st->skey[1], &st->samp[0], &st->samp[1], &st->sK[0], &st->sK[1], &st->q, &st->P,
+                      &st->delta, &st->ikey, &st->iA, &st->ideath, &st->in, &st->ilevel, &st->icnt, &st->ioff,
+                      &st->num_part, &st->abs_part, &st->rkey, &st->ramp, &st->rid, &st->rcount, &st->boff, &st->dkey,
+                      &st->damp, &st->did, &st->sk[0], &st->sk[1], &st->sidx[0], &st->sidx[1], &st->hist, &st->hoff,
+                      &st->flag, &st->incl, &st->start, &st->is_new, &st->new_pos, &st->ins, &st->seg_sum, &st->nkey,
+                      &st->nins, &st->nsum, &st->keep, &st->pos, &st->scratch};
+    for (DevBuf *b : bufs) release(st, *b);
+    for (auto &b : st->scan_tmp) release(st, b);
+    for (auto &p : st->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : st->ev_pool) (void)hipEventDestroy(e);
+    if (st->hscratch) (void)hipHostFree(st->hscratch);
+    if (st->hpinned) (void)hipHostFree(st->hpinned);
+    if (st->own_stream && st->stream) (void)hipStreamDestroy(st->stream);
+    delete st;
+}
+
+}  // namespace
+
+// =========================================================================== C ABI
+extern "C" {
+
+ccmc_status ccmc_options_default(ccmc_options *opt)
+{
+    if (!opt) return CCMC_EINVAL;
+    std::memset(opt, 0, sizeof *opt);
+    opt->precision = CCMC_FP64;
+    opt->full_noncomposite = 0;
+    opt->min_spawn_attempts = 1;
+    opt->multispawn_threshold = 0.0;
+    opt->noncomposite_threshold = 1.0;
+    opt->spawn_cutoff = 0.01;
+    opt->occupation_threshold = 1.0;
+    opt->init_pop = 10.0;
+    opt->p_single = 0.1;
+    opt->seed = 1234;
+    return CCMC_OK;
+}
+
+ccmc_status ccmc_init(const ccmc_system *sys, const ccmc_integrals *ints, int truncation, const ccmc_options *opt,
+                      ccmc_state **out)
+{
+    g_init_error.clear();
+    if (!sys || !opt || !out) {
+        g_init_error = "ccmc_init: null argument";
+        return CCMC_EINVAL;
+    }
+    *out = nullptr;
+    if (opt->precision != CCMC_FP64 && opt->precision != CCMC_FP32) {
+        g_init_error = "ccmc_init: precision must be CCMC_FP64 or CCMC_FP32";
+        return CCMC_EINVAL;
+    }
+    if (opt->min_spawn_attempts < 1 || !(opt->spawn_cutoff >= 0) || !(opt->occupation_threshold >= 0) ||
+        !(opt->p_single >= 0 && opt->p_single <= 1) || !std::isfinite(opt->init_pop)) {
+        g_init_error = "ccmc_init: invalid sampling options";
+        return CCMC_EINVAL;
+    }
+    ccmc_state *st = new ccmc_state();
+    st->opt = *opt;
+    st->sys = *sys;
+    st->l = truncation;
+    st->fp32 = opt->precision == CCMC_FP32;
+    st->es = st->fp32 ? 4 : 8;
+    std::string err;
+    bool ok = false;
+    if (sys->kind == CCMC_UEG)
+        ok = build_ueg(st->hs, sys->n_electrons, sys->n2_max, sys->rs, err) && sys->rs > 0;
+    else if (sys->kind == CCMC_MOLECULAR && ints)
+        ok = build_mol(st->hs, sys->n_electrons, ints, err);
+    else
+        err = "ccmc_init: unknown system kind or missing integrals";
+    if (ok && (truncation < 1 || truncation > 6 || truncation > sys->n_electrons)) {
+        ok = false;
+        err = "ccmc_init: truncation must be in [1, min(6, N)]";
+    }
+    if (!ok) {
+        g_init_error = err.empty() ? "ccmc_init: invalid system" : err;
+        delete st;
+        return CCMC_EINVAL;
+    }
+    st->sys.n_spin_orbitals = st->hs.M;
+    st->W = words_for(st->hs.M);
+    st->WP = padded_words(st->W);
+    if (opt->hip_stream) {
+        st->stream = (hipStream_t)opt->hip_stream;
+    } else {
+        if (hipStreamCreate(&st->stream) != hipSuccess) {
+            g_init_error = "ccmc_init: hipStreamCreate failed (no GPU?)";
+            delete st;
+            return CCMC_EDEVICE;
+        }
+        st->own_stream = true;
+    }
+    ccmc_status rc = CCMC_OK;
+    if (hipHostMalloc((void **)&st->hscratch, sizeof(Scratch)) != hipSuccess ||
+        hipHostMalloc((void **)&st->hpinned, 64) != hipSuccess) {
+        st->err = "hipHostMalloc failed";
+        rc = CCMC_EDEVICE;
+    }
+    if (rc == CCMC_OK) rc = ensure(st, st->scratch, sizeof(Scratch));
+    if (rc == CCMC_OK) rc = dispatch<SystemF>(st, st, ints);
+    if (rc == CCMC_OK) rc = dispatch<StoreF>(st, st, (uint64_t)1024);
+    if (rc != CCMC_OK) {
+        g_init_error = st->err;
+        destroy(st);
+        return rc;
+    }
+    st->n0 = opt->init_pop;
+    *out = st;
+    return CCMC_OK;
+}
+
+ccmc_status ccmc_step(ccmc_state *st, double tau, double shift, uint64_t n_attempts, ccmc_stats *out)
+{
+    if (!st) return CCMC_EINVAL;
+    st->err.clear();
+    if (!(tau > 0) || !std::isfinite(tau) || !std::isfinite(shift) || n_attempts > 0xFFFFFFFFull) {
+        st->err = "ccmc_step: need tau > 0, finite shift and n_attempts < 2^32";
+        return CCMC_EINVAL;
+    }
+    if (st->ne + 1 > 0xFFFFFFFFull) {
+        st->err = "ccmc_step: store too large for 32-bit item indices";
+        return CCMC_EOVERFLOW;
+    }
+    return dispatch<StepF>(st, st, tau, shift, n_attempts, out);
+}
+
+ccmc_status ccmc_energy(const ccmc_state *st, double *e_hf, double *eproj_num, double *eproj_den)
+{
+    if (!st) return CCMC_EINVAL;
+    if (e_hf) *e_hf = st->hs.ehf;
+    if (eproj_num) *eproj_num = st->last_num;
+    if (eproj_den) *eproj_den = st->last_den;
+    return CCMC_OK;
+}
+
+void ccmc_free(ccmc_state *st) { destroy(st); }
+
+const char *ccmc_last_error(const ccmc_state *st) { return st ? st->err.c_str() : g_init_error.c_str(); }
+
+ccmc_status ccmc_export_size(const ccmc_state *st, uint64_t *n)
+{
+    if (!st || !n) return CCMC_EINVAL;
+    *n = st->ne;
+    return CCMC_OK;
+}
+
+ccmc_status ccmc_export(const ccmc_state *st, uint64_t *keys, double *amps, uint64_t capacity, uint64_t *n, double *n_ref,
+                        uint64_t *step)
+{
+    if (!st) return CCMC_EINVAL;
+    ccmc_state *m = const_cast<ccmc_state *>(st);
+    m->err.clear();
+    if (capacity < st->ne) {
+        m->err = "ccmc_export: capacity smaller than the store";
+        return CCMC_EINVAL;
+    }
+    ccmc_status rc = dispatch<ExportF>(st, st, keys, amps);
+    if (rc != CCMC_OK) return rc;
+    if (n) *n = st->ne;
+    if (n_ref) *n_ref = st->n0;
+    if (step) *step = st->step;
+    return CCMC_OK;
+}
+
+ccmc_status ccmc_import(ccmc_state *st, const uint64_t *keys, const double *amps, uint64_t n, double n_ref, uint64_t step)
+{
+    if (!st || (n && (!keys || !amps))) return CCMC_EINVAL;
+    st->err.clear();
+    return dispatch<ImportF>(st, st, keys, amps, n, n_ref, step);
+}
+
+ccmc_status ccmc_spawns_size(const ccmc_state *st, uint64_t *n)
+{
+    if (!st || !n) return CCMC_EINVAL;
+    *n = st->last_rec_buf >= 0 ? st->last_nrec : 0;
+    return CCMC_OK;
+}
+
+ccmc_status ccmc_export_spawns(const ccmc_state *st, uint64_t *keys, double *amps, uint64_t *ids, uint64_t capacity,
+                               uint64_t *n)
+{
+    if (!st) return CCMC_EINVAL;
+    ccmc_state *m = const_cast<ccmc_state *>(st);
+    m->err.clear();
+    if (!st->opt.keep_spawn_ids) {
+        m->err = "ccmc_export_spawns: keep_spawn_ids is off";
+        return CCMC_EINVAL;
+    }
+    const uint64_t nr = st->last_rec_buf >= 0 ? st->last_nrec : 0;
+    if (capacity < nr) {
+        m->err = "ccmc_export_spawns: capacity too small";
+        return CCMC_EINVAL;
+    }
+    if (nr) {
+        ccmc_status rc = dispatch<SpawnsF>(st, st, keys, amps, ids);
+        if (rc != CCMC_OK) return rc;
+    }
+    if (n) *n = nr;
+    return CCMC_OK;
+}
+
+ccmc_status ccmc_profile(ccmc_state *st, int enable)
+{
+    if (!st) return CCMC_EINVAL;
+    st->prof = enable != 0;
+    return CCMC_OK;
+}
+
+ccmc_status ccmc_profile_read(ccmc_state *st, ccmc_kernel_time *out, int capacity, int *n)
+{
+    if (!st || !n) return CCMC_EINVAL;
+    resolve_profile(st);
+    int k = 0;
+    for (auto &kv : st->accum) {
+        if (k < capacity && out) {
+            std::memset(&out[k], 0, sizeof(ccmc_kernel_time));
+            std::strncpy(out[k].name, kv.first.c_str(), sizeof(out[k].name) - 1);
+            out[k].launches = kv.second.launches;
+            out[k].ms = kv.second.ms;
+            out[k].bytes = kv.second.bytes;
+            out[k].items = kv.second.items;
+        }
+        ++k;
+    }
+    *n = std::min(k, capacity);
+    st->accum.clear();
+    return CCMC_OK;
+}
+
+ccmc_status ccmc_dims(const ccmc_state *st, int *n_electrons, int *n_spin_orbitals, int *n_words)
+{
+    if (!st) return CCMC_EINVAL;
+    if (n_electrons) *n_electrons = st->hs.nel;
+    if (n_spin_orbitals) *n_spin_orbitals = st->hs.M;
+    if (n_words) *n_words = st->W;
+    return CCMC_OK;
+}
+
+ccmc_status ccmc_memory(const ccmc_state *st, uint64_t *bytes)
+{
+    if (!st || !bytes) return CCMC_EINVAL;
+    *bytes = st->bytes_held;
+    return CCMC_OK;
+}
+
+}  // extern "C"

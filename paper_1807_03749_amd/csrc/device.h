@@ -1,0 +1,344 @@
+// device.h -- device-side building blocks of the CCMC step on gfx950: Philox4x32-10,
+// multi-word bitstring operations (popcount / select), fermionic signs by popcount,
+// Slater-Condon elements for the UEG and molecule-like Hamiltonians, and the diagonal
+// relative to E_HF.
+//
+// Paper: Spencer et al., arXiv:1807.03749, Sec. II (excitors, s_D, spawning sign).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccmc {
+
+constexpr int kMaxWords = 8;
+constexpr int kMaxClusterSize = 8;   // l + 2 with l <= 6
+constexpr uint32_t kMaxAttempts = (1u << 30) - 2;
+constexpr int kSystemUEG = 1;
+constexpr int kSystemMol = 2;
+
+enum Purpose : uint32_t { kSelect = 0, kSpawnSampled = 1, kSpawnNonComposite = 2, kRound = 3 };
+
+// Constant description of the system, passed by value to every kernel.
+struct SysDev {
+    int kind, nel, M, nsp, l;
+    uint32_t npairs, half;
+    uint64_t hf[kMaxWords];
+    // UEG
+    int G;                 // half-width of the momentum lookup grid
+    const int *grid;       // [(2G+1)^3] spatial index of a wavevector or -1
+    const int *nvec;       // [nsp][3] integer wavevectors
+    const void *vq;        // [dmax+1] Coulomb kernel 4 pi / (Omega |k|^2) by |dn|^2 (T)
+    // molecular
+    const void *h;         // [nsp][nsp] (T)
+    const void *eri;       // [nsp^4] chemists' (PQ|RS) (T)
+    // both
+    const void *fock;      // [M] f_p = h_pp + sum_{j in HF} <pj||pj> (T)
+    const void *vpair;     // [M][M] <pq||pq> (T)
+    double p_single;
+};
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror & Shaw (SC'11): ten rounds, two 32x32->64 products per round,
+// Weyl key schedule.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+// A stream of 64-bit draws for (purpose, item k, attempt m) at step t: Philox block j
+// uses counter (j, m, k, purpose << 28 | t); block words (x0..x3) give draws 2j and 2j+1 as
+// x0 | x1 << 32 and x2 | x3 << 32.
+struct Draws {
+    uint32_t k0, k1, m, k, w;
+    int have = -1;
+    uint4 blk;
+    __device__ Draws(uint32_t key0, uint32_t key1, uint32_t purpose, uint32_t item, uint32_t att, uint32_t step)
+        : k0(key0), k1(key1), m(att), k(item), w((purpose << 28) | (step & 0x0FFFFFFFu)) {}
+    __device__ __forceinline__ uint64_t get(int idx)
+    {
+        const int j = idx >> 1;
+        if (j != have) {
+            blk = philox4x32_10(make_uint4((uint32_t)j, m, k, w), k0, k1);
+            have = j;
+        }
+        return (idx & 1) ? ((uint64_t)blk.z | ((uint64_t)blk.w << 32)) : ((uint64_t)blk.x | ((uint64_t)blk.y << 32));
+    }
+};
+
+__device__ __forceinline__ double uniform53(uint64_t v) { return (double)(v >> 11) * 0x1.0p-53; }
+// integer uniform in [0, n): high word of v * n
+__device__ __forceinline__ uint64_t below(uint64_t v, uint64_t n) { return __umul64hi(v, n); }
+
+// --------------------------------------------------------------- bitstring helpers
+template <int W>
+__device__ __forceinline__ bool bit_test(const uint64_t *d, int p)
+{
+    return (d[p >> 6] >> (p & 63)) & 1ull;
+}
+template <int W>
+__device__ __forceinline__ void bit_flip(uint64_t *d, int p)
+{
+    d[p >> 6] ^= 1ull << (p & 63);
+}
+// number of set bits strictly below orbital p
+template <int W>
+__device__ __forceinline__ int count_below(const uint64_t *d, int p)
+{
+    int c = 0;
+    const int wp = p >> 6;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        if (w < wp) c += __popcll(d[w]);
+        if (w == wp) c += __popcll(d[w] & ((1ull << (p & 63)) - 1ull));
+    }
+    return c;
+}
+// position of the n-th set bit (0-based) of a 64-bit word
+__device__ __forceinline__ int select64(uint64_t x, int n)
+{
+    int pos = 0;
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) {
+        const int c = __popcll(x & ((1ull << s) - 1ull));
+        if (n >= c) {
+            n -= c;
+            x >>= s;
+            pos += s;
+        }
+    }
+    return pos;
+}
+// orbital of the n-th occupied spin orbital of d
+template <int W>
+__device__ __forceinline__ int select_bit(const uint64_t *d, int n)
+{
+    int base = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const int c = __popcll(d[w]);
+        if (n < c) return base + select64(d[w], n);
+        n -= c;
+        base += 64;
+    }
+    return -1;
+}
+template <int W>
+__device__ __forceinline__ int popcount(const uint64_t *d)
+{
+    int c = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) c += __popcll(d[w]);
+    return c;
+}
+// excitation level relative to the reference: number of occupied non-reference orbitals
+template <int W>
+__device__ __forceinline__ int level_of(const SysDev &S, const uint64_t *d)
+{
+    int c = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) c += __popcll(d[w] & ~S.hf[w]);
+    return c;
+}
+template <int W>
+__device__ __forceinline__ bool key_equal(const uint64_t *a, const uint64_t *b)
+{
+    bool e = true;
+#pragma unroll
+    for (int w = 0; w < W; ++w) e &= (a[w] == b[w]);
+    return e;
+}
+// -1, 0, 1 ordering as W-word unsigned integers, most significant word first
+template <int W>
+__device__ __forceinline__ int key_cmp(const uint64_t *a, const uint64_t *b)
+{
+#pragma unroll
+    for (int w = W - 1; w >= 0; --w) {
+        if (a[w] != b[w]) return a[w] < b[w] ? -1 : 1;
+    }
+    return 0;
+}
+
+// s_D(i) = <D_i| c_i |D_HF> (Sec. II, eq. 6).  With the reference on orbitals 0..N-1,
+// annihilating the holes i_1 < .. < i_L in turn gives (-1)^(sum_k i_k - L(L-1)/2), and each
+// creator passes the N-L remaining reference electrons: (-1)^(L(N-L)).  The parity of
+// sum_k i_k is the parity of the number of odd-numbered holes.
+template <int W>
+__device__ __forceinline__ int excitor_sign(const SysDev &S, const uint64_t *d)
+{
+    int L = 0, odd = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint64_t holes = S.hf[w] & ~d[w];
+        L += __popcll(holes);
+        odd += __popcll(holes & 0xAAAAAAAAAAAAAAAAull);
+    }
+    const int e = odd - (L * (L - 1)) / 2 + L * (S.nel - L);
+    return (e & 1) ? -1 : 1;
+}
+
+// ------------------------------------------------------------------- integrals
+// <pq|rs> with spin deltas; momentum conservation is guaranteed by the callers (UEG).
+template <typename T>
+__device__ __forceinline__ T u2(const SysDev &S, int p, int q, int r, int s)
+{
+    if (((p ^ r) & 1) | ((q ^ s) & 1)) return T(0);
+    const int P = p >> 1, Q = q >> 1, R = r >> 1, X = s >> 1;
+    if (S.kind == kSystemUEG) {
+        const int *np = S.nvec + 3 * P, *nr = S.nvec + 3 * R;
+        const int dx = np[0] - nr[0], dy = np[1] - nr[1], dz = np[2] - nr[2];
+        const int d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 == 0) return T(0);
+        return static_cast<const T *>(S.vq)[d2];
+    }
+    const size_t n = (size_t)S.nsp;
+    return static_cast<const T *>(S.eri)[((P * n + R) * n + Q) * n + X];
+}
+template <typename T>
+__device__ __forceinline__ T anti(const SysDev &S, int p, int q, int r, int s)
+{
+    return u2<T>(S, p, q, r, s) - u2<T>(S, p, q, s, r);
+}
+template <typename T>
+__device__ __forceinline__ T h1(const SysDev &S, int p, int q)
+{
+    if ((p ^ q) & 1) return T(0);
+    if (S.kind == kSystemUEG) return T(0);  // only used off-diagonal (singles)
+    return static_cast<const T *>(S.h)[(size_t)(p >> 1) * S.nsp + (q >> 1)];
+}
+
+// <D'| H |D> for D' = D with f1 < f2 replaced by t1 < t2 (a double excitation):
+// gamma <t1 t2 || f1 f2> with gamma = <D'| c+_t1 c+_t2 c_f2 c_f1 |D> from popcounts.
+template <int W, typename T>
+__device__ __forceinline__ T double_element(const SysDev &S, const uint64_t *d, int f1, int f2, int t1, int t2)
+{
+    uint64_t x[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = d[w];
+    int e = count_below<W>(x, f1);
+    bit_flip<W>(x, f1);
+    e += count_below<W>(x, f2);
+    bit_flip<W>(x, f2);
+    e += count_below<W>(x, t2);
+    bit_flip<W>(x, t2);
+    e += count_below<W>(x, t1);
+    const T v = anti<T>(S, t1, t2, f1, f2);
+    return (e & 1) ? -v : v;
+}
+
+// <D'| H |D> for D' = D with f replaced by t (a single excitation):
+// gamma (h_tf + sum_{k in D} <tk||fk>) with gamma = <D'| c+_t c_f |D>.
+template <int W, typename T>
+__device__ __forceinline__ T single_element(const SysDev &S, const uint64_t *d, int f, int t)
+{
+    uint64_t x[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = d[w];
+    int e = count_below<W>(x, f);
+    bit_flip<W>(x, f);
+    e += count_below<W>(x, t);
+    T v = h1<T>(S, t, f);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        uint64_t m = d[w];
+        while (m) {
+            const int k = 64 * w + __ffsll((long long)m) - 1;
+            m &= m - 1;
+            v += anti<T>(S, t, k, f, k);
+        }
+    }
+    return (e & 1) ? -v : v;
+}
+
+// <D_HF| H |D> for an excitor of level 1 or 2 (projected energy, Sec. II eq. 7).
+template <int W, typename T>
+__device__ __forceinline__ T reference_element(const SysDev &S, const uint64_t *d, int L)
+{
+    int parts[2], holes[2], np = 0, nh = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        uint64_t p = d[w] & ~S.hf[w], h = S.hf[w] & ~d[w];
+        while (p && np < 2) {
+            parts[np++] = 64 * w + __ffsll((long long)p) - 1;
+            p &= p - 1;
+        }
+        while (h && nh < 2) {
+            holes[nh++] = 64 * w + __ffsll((long long)h) - 1;
+            h &= h - 1;
+        }
+    }
+    if (L == 1) return single_element<W, T>(S, d, parts[0], holes[0]);
+    return double_element<W, T>(S, d, parts[0], parts[1], holes[0], holes[1]);
+}
+
+// K_D = H_DD - E_HF from the holes I and particles A of D:
+// sum_A f_a - sum_I f_i + sum_{a<b} <ab||ab> + sum_{i<j} <ij||ij> - sum_{a,i} <ai||ai>.
+template <int W, typename T>
+__device__ __forceinline__ T diagonal(const SysDev &S, const uint64_t *d)
+{
+    int hole[kMaxClusterSize], part[kMaxClusterSize], nh = 0, np = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        uint64_t p = d[w] & ~S.hf[w], h = S.hf[w] & ~d[w];
+        while (p && np < kMaxClusterSize) {
+            part[np++] = 64 * w + __ffsll((long long)p) - 1;
+            p &= p - 1;
+        }
+        while (h && nh < kMaxClusterSize) {
+            hole[nh++] = 64 * w + __ffsll((long long)h) - 1;
+            h &= h - 1;
+        }
+    }
+    const T *f = static_cast<const T *>(S.fock);
+    const T *V = static_cast<const T *>(S.vpair);
+    const size_t M = (size_t)S.M;
+    T k = T(0);
+    for (int a = 0; a < np; ++a) k += f[part[a]];
+    for (int i = 0; i < nh; ++i) k -= f[hole[i]];
+    for (int a = 0; a < np; ++a)
+        for (int b = a + 1; b < np; ++b) k += V[part[a] * M + part[b]];
+    for (int i = 0; i < nh; ++i)
+        for (int j = i + 1; j < nh; ++j) k += V[hole[i] * M + hole[j]];
+    for (int a = 0; a < np; ++a)
+        for (int i = 0; i < nh; ++i) k -= V[part[a] * M + hole[i]];
+    return k;
+}
+
+// Cluster-size distribution: p(s) = 2^-(s-lo+1) for lo <= s < hi, the remainder at hi.
+__device__ __forceinline__ int draw_size(double u, int lo, int hi)
+{
+    double c = 0.0;
+    for (int s = lo; s < hi; ++s) {
+        c += ldexp(1.0, -(s - lo + 1));
+        if (u < c) return s;
+    }
+    return hi;
+}
+__device__ __forceinline__ double size_prob(int s, int lo, int hi)
+{
+    return (s < hi) ? ldexp(1.0, -(s - lo + 1)) : ldexp(1.0, -(hi - lo));
+}
+
+// pair (x < y) of rank r in lexicographic order over n items
+__device__ __forceinline__ void unrank_pair(int n, uint32_t r, int &x, int &y)
+{
+    x = 0;
+    uint32_t row = (uint32_t)(n - 1);
+    while (r >= row) {
+        r -= row;
+        ++x;
+        --row;
+    }
+    y = x + 1 + (int)r;
+}
+
+}  // namespace ccmc

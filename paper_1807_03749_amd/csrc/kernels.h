@@ -1,0 +1,722 @@
+// kernels.h -- the CCMC time-step kernels (Spencer et al., arXiv:1807.03749, Sec. II & IV).
+//
+// One step, in launch order:
+//   k_weights        fixed-point selection weights q_i of the store          (a1)
+//   k_noncomposite   reference + every excitor as explicit items (FNC)        (a5, a9, a10)
+//   k_select         cluster size, excitor draws, collapse, amplitude         (a2, a3, a4, a9, a10)
+//   k_generate       one lane per record slot: death or spawning attempt      (a6, a7, a8)
+//   k_gather         concatenate per-block record regions                    (a8)
+//   radix sort       stable LSD sort of the records by determinant            (a11)
+//   k_seg_*          segment heads, left fold in record order, store lookup   (a12)
+//   k_merge          merge sums and new determinants into the sorted store    (a12)
+//   k_round          occupation rounding, then compaction                     (a13)
+//   k_stats_*        FP64 population and projected-energy reductions          (a14)
+#pragma once
+#include "device.h"
+#include "primitives.h"
+
+namespace ccmc {
+
+constexpr int kGenRounds = 4;                       // rounds of 256 slots per block
+constexpr int kGenSlots = kThreads * kGenRounds;    // slots (and record capacity) per block
+
+// Device-side scalars of one step.
+struct Scratch {
+    uint64_t qtot;
+    uint64_t err;             // bit 0: |N| too large; bit 1: too many attempts on a cluster
+    uint64_t n_discarded;
+    uint64_t n_attempts;
+    uint64_t n_spawns;
+    uint64_t n_deaths;
+    uint64_t max_n;
+    uint64_t diffmask[kMaxWords];
+    uint32_t n_seg;
+    uint32_t n_new;
+    uint32_t hf_hit;
+    uint32_t n_out;
+    double hf_sum;
+    double n_total;
+    double num;
+};
+
+struct StepArgs {
+    double tau, shift;
+    double cutoff, theta;
+    double thr_cluster, thr_nc;
+    uint32_t kmin;
+    uint32_t step;            // t & 0x0FFFFFFF
+    uint32_t key0, key1;
+    uint64_t n_sel;
+    int fnc;
+};
+
+// Items: one per cluster that may emit records.  SoA key layout with stride `stride`.
+template <typename T>
+struct Items {
+    uint64_t *key;
+    T *A;
+    T *death;      // death amount -tau (K - S) A, 0 when none
+    uint32_t *n;   // spawning attempts
+    uint8_t *level;
+    uint64_t *cnt; // record slots: n + 1 (slot 0 = death), 0 when discarded
+    uint64_t stride;
+};
+
+template <typename T>
+__device__ __forceinline__ uint32_t attempt_count(T A, double thr, uint32_t kmin, uint64_t *err)
+{
+    uint32_t k = kmin;
+    if (thr > 0) {
+        const double f = floor(fabs((double)A) / thr);
+        if (!(f <= (double)kMaxAttempts)) {
+            atomicOr((unsigned long long *)err, 2ull);
+            return kMaxAttempts;
+        }
+        if ((uint32_t)f > k) k = (uint32_t)f;
+    }
+    return k;
+}
+
+// ------------------------------------------------------------------------ weights
+// q_i = max(1, rint(|N_i| 2^24)): the prefix of q is exact, so the excitor drawn for a
+// given random number does not depend on the summation order (Sec. II: probability
+// |t_i| / (N_tot - t_HF)).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_weights(const T *__restrict__ amp, uint64_t n, uint64_t *__restrict__ q,
+                                                      Scratch *sc)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const double a = fabs((double)amp[i]);
+    if (!(a < 0x1.0p28)) atomicOr((unsigned long long *)&sc->err, 1ull);
+    double w = rint(a * 16777216.0);
+    if (w < 1.0) w = 1.0;
+    q[i] = (uint64_t)fmin(w, 0x1.0p60);
+}
+
+__global__ void k_qtot(const uint64_t *__restrict__ P, uint64_t n, Scratch *sc)
+{
+    sc->qtot = n ? P[n - 1] : 0;
+    if (sc->qtot > (1ull << 53)) atomicOr((unsigned long long *)&sc->err, 1ull);
+}
+
+// ------------------------------------------------------- non-composite items (FNC)
+// Item 0 is the reference (A = N_0, K = 0), item i+1 the store entry i (A = N_i);
+// p = 1 for all of them (Sec. IV.B).
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_noncomposite(SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
+                                                           const T *__restrict__ sK, uint64_t sstride, uint64_t ne, double n0,
+                                                           StepArgs a, Items<T> it, double *__restrict__ num_part,
+                                                           Scratch *sc)
+{
+    const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    double num = 0.0;
+    uint64_t att = 0, mx = 0;
+    if (k <= ne) {
+        uint64_t d[W];
+        T A, K;
+        int L;
+        if (k == 0) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) d[w] = S.hf[w];
+            A = (T)n0;
+            K = T(0);
+            L = 0;
+        } else {
+#pragma unroll
+            for (int w = 0; w < W; ++w) d[w] = skey[(uint64_t)w * sstride + (k - 1)];
+            A = samp[k - 1];
+            K = sK[k - 1];
+            L = level_of<W>(S, d);
+        }
+        const uint32_t n = attempt_count<T>(A, a.thr_nc, a.kmin, &sc->err);
+        T death = T(0);
+        if (L <= S.l) death = -(T)a.tau * (K - (T)a.shift) * A;
+        if (L == 1 || L == 2)
+            num = (double)(reference_element<W, T>(S, d, L) * (T)excitor_sign<W>(S, d) * A);
+#pragma unroll
+        for (int w = 0; w < W; ++w) it.key[(uint64_t)w * it.stride + k] = d[w];
+        it.A[k] = A;
+        it.death[k] = death;
+        it.n[k] = n;
+        it.level[k] = (uint8_t)L;
+        it.cnt[k] = (uint64_t)n + 1;
+        att = n;
+        mx = n;
+    }
+    const double bnum = block_reduce_sum(num);
+    const uint64_t batt = block_reduce_sum(att);
+    if (threadIdx.x == 0) {
+        num_part[blockIdx.x] = bnum;
+        atomicAdd((unsigned long long *)&sc->n_attempts, (unsigned long long)batt);
+    }
+    if (mx) atomicMax((unsigned long long *)&sc->max_n, (unsigned long long)mx);
+}
+
+// --------------------------------------------------------------- sampled clusters
+// Selection k draws s from p_size (s in [0, l+2], or [2, l+2] for the composite part of full
+// non-composite sampling), then s excitors with probability q_i / Q each; repeats are
+// discarded (Sec. II).  The product of the excitors is collapsed by applying them to the
+// reference one operator at a time; a repeated hole or particle makes it vanish.
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_select(SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
+                                                     uint64_t sstride, uint64_t ne, const uint64_t *__restrict__ P, double n0,
+                                                     StepArgs a, Items<T> it, uint64_t item_base,
+                                                     double *__restrict__ num_part, Scratch *sc)
+{
+    const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    double num = 0.0;
+    uint64_t att = 0, disc = 0, mx = 0;
+    if (k < a.n_sel) {
+        const uint64_t Q = sc->qtot;
+        Draws r(a.key0, a.key1, kSelect, (uint32_t)k, 0u, a.step);
+        const int lo = a.fnc ? 2 : 0, hi = S.l + 2;
+        const int s = draw_size(uniform53(r.get(0)), lo, hi);
+        uint64_t idx[kMaxClusterSize];
+        bool ok = !(s > 0 && Q == 0);
+        for (int c = 0; c < s && ok; ++c) {
+            const uint64_t x = below(r.get(1 + c), Q);
+            uint64_t l0 = 0, h0 = ne;  // first i with P[i] > x
+            while (l0 < h0) {
+                const uint64_t mid = (l0 + h0) >> 1;
+                if (P[mid] > x)
+                    h0 = mid;
+                else
+                    l0 = mid + 1;
+            }
+            idx[c] = l0;
+            for (int b = 0; b < c; ++b) ok &= (idx[b] != l0);
+        }
+        uint64_t d[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) d[w] = S.hf[w];
+        int e = 0;
+        // apply c_{X_s} first: annihilate holes ascending, then create particles descending
+        for (int c = s - 1; c >= 0 && ok; --c) {
+            uint64_t x[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) x[w] = skey[(uint64_t)w * sstride + idx[c]];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                uint64_t h = S.hf[w] & ~x[w];
+                while (h) {
+                    const int p = 64 * w + __ffsll((long long)h) - 1;
+                    h &= h - 1;
+                    if (!bit_test<W>(d, p)) ok = false;
+                    e += count_below<W>(d, p);
+                    bit_flip<W>(d, p);
+                }
+            }
+#pragma unroll
+            for (int w = W - 1; w >= 0; --w) {
+                uint64_t pm = x[w] & ~S.hf[w];
+                while (pm) {
+                    const int p = 64 * w + 63 - __clzll((long long)pm);
+                    pm &= ~(1ull << (p & 63));
+                    if (bit_test<W>(d, p)) ok = false;
+                    e += count_below<W>(d, p);
+                    bit_flip<W>(d, p);
+                }
+            }
+        }
+        const int L = level_of<W>(S, d);
+        if (L > S.l + 2) ok = false;
+        uint32_t n = 0;
+        uint64_t cnt = 0;
+        T A = T(0), death = T(0);
+        if (ok) {
+            // sign of c_X1..c_Xs |HF> = sigma s_D(X) |D_X>
+            const int sigma = ((e & 1) ? -1 : 1) * excitor_sign<W>(S, d);
+            double fact = 1.0;
+            for (int c = 2; c <= s; ++c) fact *= (double)c;
+            double p = (double)a.n_sel * size_prob(s, lo, hi) * fact;
+            for (int c = 0; c < s; ++c) {
+                const uint64_t qi = P[idx[c]] - (idx[c] ? P[idx[c] - 1] : 0);
+                p *= (double)qi / (double)Q;
+            }
+            T Ac;
+            if (s == 0) {
+                Ac = (T)n0;
+            } else {
+                Ac = (T)sigma * samp[idx[0]];
+                for (int c = 1; c < s; ++c) Ac *= samp[idx[c]] / (T)n0;
+            }
+            A = Ac / (T)p;
+            n = attempt_count<T>(A, a.thr_cluster, a.kmin, &sc->err);
+            cnt = (uint64_t)n + 1;
+            if (L <= S.l) death = -(T)a.tau * (diagonal<W, T>(S, d) - (T)a.shift) * A;
+            if (L == 1 || L == 2) num = (double)(reference_element<W, T>(S, d, L) * (T)excitor_sign<W>(S, d) * A);
+            att = n;
+            mx = n;
+        } else {
+            disc = 1;
+        }
+        const uint64_t j = item_base + k;
+#pragma unroll
+        for (int w = 0; w < W; ++w) it.key[(uint64_t)w * it.stride + j] = d[w];
+        it.A[j] = A;
+        it.death[j] = death;
+        it.n[j] = n;
+        it.level[j] = (uint8_t)L;
+        it.cnt[j] = cnt;
+    }
+    const double bnum = block_reduce_sum(num);
+    const uint64_t batt = block_reduce_sum(att);
+    const uint64_t bdisc = block_reduce_sum(disc);
+    if (threadIdx.x == 0) {
+        num_part[blockIdx.x] = bnum;
+        atomicAdd((unsigned long long *)&sc->n_attempts, (unsigned long long)batt);
+        atomicAdd((unsigned long long *)&sc->n_discarded, (unsigned long long)bdisc);
+    }
+    if (mx) atomicMax((unsigned long long *)&sc->max_n, (unsigned long long)mx);
+}
+
+// ----------------------------------------------------------------- generation
+// Records of one block of kGenSlots consecutive slots, compacted in slot order into the
+// block's own region.  Slot order is record-id order, so the stable sort that follows
+// keeps every determinant's contributions in id order.
+struct Records {
+    uint64_t *key;     // SoA, stride = region capacity
+    void *amp;         // T
+    uint64_t *id;      // optional
+    uint32_t *count;   // per block
+    uint64_t stride;
+};
+
+template <int W, typename T>
+__device__ __forceinline__ bool spawn_attempt(const SysDev &S, const uint64_t *d, T A, uint32_t n, uint32_t purpose,
+                                              uint32_t k, uint32_t m, const StepArgs &a, uint64_t *tgt, T &x)
+{
+    Draws r(a.key0, a.key1, purpose, k, m, a.step);
+    const int N = S.nel;
+    int i, j = -1, ta, tb = -1, ridx;
+    double pgen;
+    if (S.kind == kSystemUEG) {
+        const uint32_t pr = (uint32_t)below(r.get(0), S.npairs);
+        const int alpha = (int)below(r.get(1), S.half);
+        int xa, ya;
+        unrank_pair(N, pr, xa, ya);
+        i = select_bit<W>(d, xa);
+        j = select_bit<W>(d, ya);
+        ta = 2 * alpha + (i & 1);
+        if (bit_test<W>(d, ta)) return false;
+        const int *ni = S.nvec + 3 * (i >> 1), *nj = S.nvec + 3 * (j >> 1), *na = S.nvec + 3 * (ta >> 1);
+        const int bx = ni[0] + nj[0] - na[0], by = ni[1] + nj[1] - na[1], bz = ni[2] + nj[2] - na[2];
+        const int G = S.G, D = 2 * G + 1;
+        if (bx < -G || bx > G || by < -G || by > G || bz < -G || bz > G) return false;
+        const int beta = S.grid[((bx + G) * D + (by + G)) * D + (bz + G)];
+        if (beta < 0) return false;
+        tb = 2 * beta + (j & 1);
+        if (tb == ta || bit_test<W>(d, tb)) return false;
+        pgen = (((i & 1) == (j & 1)) ? 2.0 : 1.0) / ((double)S.npairs * (double)S.half);
+        ridx = 2;
+    } else {
+        const bool single = uniform53(r.get(0)) < S.p_single;
+        if (single) {
+            const int xa = (int)below(r.get(1), (uint64_t)N);
+            i = select_bit<W>(d, xa);
+            ta = 2 * (int)below(r.get(2), S.half) + (i & 1);
+            if (bit_test<W>(d, ta)) return false;
+            pgen = S.p_single / ((double)N * (double)S.half);
+        } else {
+            int xa, ya;
+            unrank_pair(N, (uint32_t)below(r.get(1), S.npairs), xa, ya);
+            i = select_bit<W>(d, xa);
+            j = select_bit<W>(d, ya);
+            ta = 2 * (int)below(r.get(2), S.half) + (i & 1);
+            tb = 2 * (int)below(r.get(3), S.half) + (j & 1);
+            if (ta == tb || bit_test<W>(d, ta) || bit_test<W>(d, tb)) return false;
+            pgen = (1.0 - S.p_single) * (((i & 1) == (j & 1)) ? 2.0 : 1.0) /
+                   ((double)S.npairs * (double)S.half * (double)S.half);
+        }
+        ridx = 4;
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) tgt[w] = d[w];
+    bit_flip<W>(tgt, i);
+    bit_flip<W>(tgt, ta);
+    if (j >= 0) {
+        bit_flip<W>(tgt, j);
+        bit_flip<W>(tgt, tb);
+    }
+    // spawns beyond the truncation level are discarded (Sec. II)
+    if (level_of<W>(S, tgt) > S.l) return false;
+    T H;
+    if (j < 0) {
+        H = single_element<W, T>(S, d, i, ta);
+    } else {
+        const int t1 = ta < tb ? ta : tb, t2 = ta < tb ? tb : ta;
+        H = double_element<W, T>(S, d, i, j, t1, t2);
+    }
+    const int sc = excitor_sign<W>(S, d), st = excitor_sign<W>(S, tgt);
+    // -dtau H_ij s_D(i) s_D(j) A / (n p_gen)  (Sec. II spawning sign, Sec. IV.C eq. 10)
+    x = -(T)a.tau * H * (T)sc * (T)st * A / ((T)n * (T)pgen);
+    if (x == T(0)) return false;
+    if (fabs((double)x) < a.cutoff) {
+        const double u = uniform53(r.get(ridx));
+        if (u < fabs((double)x) / a.cutoff)
+            x = (T)copysign(a.cutoff, (double)x);
+        else
+            return false;
+    }
+    return true;
+}
+
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, const uint64_t *__restrict__ off,
+                                                       uint64_t n_items, uint64_t n_fnc, uint64_t n_slots, StepArgs a,
+                                                       Records rec, int keep_ids, Scratch *sc)
+{
+    __shared__ uint64_t item_lo, item_hi;
+    __shared__ uint32_t wave_tot[kWaves];
+    const uint64_t g0 = (uint64_t)blockIdx.x * kGenSlots;
+    if (threadIdx.x == 0) {
+        // items covering this block's slots: last item with off <= g
+        auto find = [&](uint64_t g) {
+            uint64_t l0 = 0, h0 = n_items + 1;
+            while (l0 < h0) {
+                const uint64_t mid = (l0 + h0) >> 1;
+                if (off[mid] > g)
+                    h0 = mid;
+                else
+                    l0 = mid + 1;
+            }
+            return l0 - 1;
+        };
+        item_lo = find(g0);
+        const uint64_t gl = (g0 + kGenSlots - 1 < n_slots) ? g0 + kGenSlots - 1 : n_slots - 1;
+        item_hi = find(gl);
+    }
+    __syncthreads();
+    const uint64_t lo = item_lo, hi = item_hi;
+    uint32_t base = 0, spawns = 0, deaths = 0;
+    T *ramp = static_cast<T *>(rec.amp);
+    for (int rd = 0; rd < kGenRounds; ++rd) {
+        const uint64_t g = g0 + (uint64_t)rd * kThreads + threadIdx.x;
+        bool emit = false;
+        uint64_t tgt[W];
+        T x = T(0);
+        uint64_t id = 0;
+        if (g < n_slots) {
+            uint64_t l0 = lo, h0 = hi + 1;
+            while (l0 < h0) {
+                const uint64_t mid = (l0 + h0) >> 1;
+                if (off[mid] > g)
+                    h0 = mid;
+                else
+                    l0 = mid + 1;
+            }
+            const uint64_t item = l0 - 1;
+            const uint32_t slot = (uint32_t)(g - off[item]);
+            const bool nc = item < n_fnc;
+            const uint32_t k = (uint32_t)(nc ? item : item - n_fnc);
+            uint64_t d[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) d[w] = it.key[(uint64_t)w * it.stride + item];
+            if (slot == 0) {
+                x = it.death[item];
+                if (x != T(0)) {
+                    emit = true;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) tgt[w] = d[w];
+                    ++deaths;
+                }
+            } else {
+                emit = spawn_attempt<W, T>(S, d, it.A[item], it.n[item], nc ? kSpawnNonComposite : kSpawnSampled, k,
+                                           slot - 1, a, tgt, x);
+                spawns += emit ? 1u : 0u;
+            }
+            id = ((nc ? 0ull : 1ull) << 62) | ((uint64_t)k << 30) | (uint64_t)slot;
+        }
+        // compaction in slot order
+        const uint64_t m = __ballot(emit);
+        if (lane_id() == 0) wave_tot[wave_id()] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            if (w < wave_id()) before += wave_tot[w];
+            total += wave_tot[w];
+        }
+        if (emit) {
+            const uint64_t dst = g0 + base + before + (uint32_t)lanes_below(m);
+#pragma unroll
+            for (int w = 0; w < W; ++w) rec.key[(uint64_t)w * rec.stride + dst] = tgt[w];
+            ramp[dst] = x;
+            if (keep_ids) rec.id[dst] = id;
+        }
+        base += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rec.count[blockIdx.x] = base;
+    const uint64_t bs = block_reduce_sum((uint64_t)spawns);
+    const uint64_t bd = block_reduce_sum((uint64_t)deaths);
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long *)&sc->n_spawns, (unsigned long long)bs);
+        atomicAdd((unsigned long long *)&sc->n_deaths, (unsigned long long)bd);
+    }
+}
+
+// Concatenate the regions: block b's records go to off[b] ...  Also ORs the bits in which
+// any record differs from the reference, so that the sort skips constant digits.
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_gather(const SysDev S, Records rec, const uint64_t *__restrict__ boff,
+                                                     uint64_t *__restrict__ key, T *__restrict__ amp, uint64_t *__restrict__ ids,
+                                                     uint64_t stride, int keep_ids, Scratch *sc)
+{
+    const uint32_t cnt = rec.count[blockIdx.x];
+    const uint64_t src0 = (uint64_t)blockIdx.x * kGenSlots, dst0 = boff[blockIdx.x];
+    const T *ramp = static_cast<const T *>(rec.amp);
+    uint64_t diff[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) diff[w] = 0;
+    for (uint32_t i = threadIdx.x; i < cnt; i += kThreads) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint64_t v = rec.key[(uint64_t)w * rec.stride + src0 + i];
+            key[(uint64_t)w * stride + dst0 + i] = v;
+            diff[w] |= v ^ S.hf[w];
+        }
+        amp[dst0 + i] = ramp[src0 + i];
+        if (keep_ids) ids[dst0 + i] = rec.id[src0 + i];
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        uint64_t v = diff[w];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+        if (lane_id() == 0 && v) atomicOr((unsigned long long *)&sc->diffmask[w], (unsigned long long)v);
+    }
+}
+
+// ---------------------------------------------------------------- annihilation
+template <int W>
+__global__ void __launch_bounds__(kThreads) k_seg_flags(const uint64_t *__restrict__ key, uint64_t stride, uint32_t n,
+                                                        uint32_t *__restrict__ flag)
+{
+    const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n) return;
+    bool head = (r == 0);
+    if (!head) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) head |= key[(uint64_t)w * stride + r] != key[(uint64_t)w * stride + r - 1];
+    }
+    flag[r] = head ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(kThreads) k_seg_starts(const uint32_t *__restrict__ flag, const uint32_t *__restrict__ incl,
+                                                         uint32_t n, uint32_t *__restrict__ start, Scratch *sc)
+{
+    const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
+    if (r >= n) return;
+    if (flag[r]) start[incl[r] - 1] = r;
+    if (r == n - 1) sc->n_seg = incl[r];
+}
+
+// One lane per determinant: left fold of its records in id order (they are contiguous and
+// in id order after the stable sort), then look it up in the store.  A hit adds to that
+// entry, the reference adds to N_0, a miss becomes a new excitor at insertion point ins.
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_seg_fold(const SysDev S, const uint64_t *__restrict__ key, uint64_t stride,
+                                                       const uint32_t *__restrict__ idx, const T *__restrict__ ramp, uint32_t n,
+                                                       const uint32_t *__restrict__ start, const uint64_t *__restrict__ skey,
+                                                       uint64_t sstride, uint64_t ne, double *__restrict__ delta,
+                                                       uint32_t *__restrict__ is_new, uint64_t *__restrict__ ins,
+                                                       double *__restrict__ seg_sum, Scratch *sc)
+{
+    const uint32_t s = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t nseg = sc->n_seg;
+    if (s >= nseg) return;
+    const uint32_t r0 = start[s], r1 = (s + 1 < nseg) ? start[s + 1] : n;
+    double acc = (double)ramp[idx[r0]];
+    for (uint32_t r = r0 + 1; r < r1; ++r) acc += (double)ramp[idx[r]];
+    uint64_t d[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) d[w] = key[(uint64_t)w * stride + r0];
+    uint32_t fresh = 0;
+    uint64_t pos = 0;
+    if (key_equal<W>(d, S.hf)) {
+        sc->hf_sum = acc;
+        sc->hf_hit = 1;
+    } else {
+        uint64_t l0 = 0, h0 = ne;  // first store entry >= d
+        while (l0 < h0) {
+            const uint64_t mid = (l0 + h0) >> 1;
+            uint64_t e[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) e[w] = skey[(uint64_t)w * sstride + mid];
+            if (key_cmp<W>(e, d) < 0)
+                l0 = mid + 1;
+            else
+                h0 = mid;
+        }
+        bool found = false;
+        if (l0 < ne) {
+            uint64_t e[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) e[w] = skey[(uint64_t)w * sstride + l0];
+            found = key_equal<W>(e, d);
+        }
+        if (found)
+            delta[l0] = acc;
+        else
+            fresh = 1;
+        pos = l0;
+    }
+    is_new[s] = fresh;
+    ins[s] = pos;
+    seg_sum[s] = acc;
+}
+
+template <int W>
+__global__ void __launch_bounds__(kThreads) k_new_compact(const uint64_t *__restrict__ key, uint64_t stride,
+                                                          const uint32_t *__restrict__ start, const uint32_t *__restrict__ is_new,
+                                                          const uint32_t *__restrict__ new_pos, const uint64_t *__restrict__ ins,
+                                                          const double *__restrict__ seg_sum, uint64_t *__restrict__ nkey,
+                                                          uint64_t nstride, uint64_t *__restrict__ nins, double *__restrict__ nsum,
+                                                          Scratch *sc)
+{
+    const uint32_t s = blockIdx.x * kThreads + threadIdx.x;
+    const uint32_t nseg = sc->n_seg;
+    if (s >= nseg) return;
+    if (s == nseg - 1) sc->n_new = new_pos[s] + is_new[s];
+    if (!is_new[s]) return;
+    const uint32_t j = new_pos[s];
+#pragma unroll
+    for (int w = 0; w < W; ++w) nkey[(uint64_t)w * nstride + j] = key[(uint64_t)w * stride + start[s]];
+    nins[j] = ins[s];
+    nsum[j] = seg_sum[s];
+}
+
+// Merge the store (with its sums added) and the new determinants into key order.
+// Store entry i lands at i + #(new with ins <= i); new entry j at ins_j + j.
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_merge(const SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
+                                                    const T *__restrict__ sK, uint64_t sstride, uint64_t ne,
+                                                    const double *__restrict__ delta, const uint64_t *__restrict__ nkey,
+                                                    uint64_t nstride, const uint64_t *__restrict__ nins,
+                                                    const double *__restrict__ nsum, uint64_t *__restrict__ mkey,
+                                                    T *__restrict__ mamp, T *__restrict__ mK, uint64_t mstride, Scratch *sc)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint64_t nn = sc->n_new;
+    if (t >= ne + nn) return;
+    if (t < ne) {
+        uint64_t l0 = 0, h0 = nn;  // new entries with ins <= t
+        while (l0 < h0) {
+            const uint64_t mid = (l0 + h0) >> 1;
+            if (nins[mid] <= t)
+                l0 = mid + 1;
+            else
+                h0 = mid;
+        }
+        const uint64_t pos = t + l0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) mkey[(uint64_t)w * mstride + pos] = skey[(uint64_t)w * sstride + t];
+        mamp[pos] = (T)((double)samp[t] + delta[t]);
+        mK[pos] = sK[t];
+    } else {
+        const uint64_t j = t - ne;
+        const uint64_t pos = nins[j] + j;
+        uint64_t d[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            d[w] = nkey[(uint64_t)w * nstride + j];
+            mkey[(uint64_t)w * mstride + pos] = d[w];
+        }
+        mamp[pos] = (T)nsum[j];
+        mK[pos] = diagonal<W, T>(S, d);
+    }
+}
+
+// Real-weight occupation rounding: 0 < |N| < theta becomes +-theta with probability
+// |N| / theta, else 0, with a Philox draw keyed by the merged position (reference exempt).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_round(T *__restrict__ amp, uint64_t ne, StepArgs a, uint32_t *__restrict__ keep,
+                                                    Scratch *sc)
+{
+    const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint64_t n = ne + sc->n_new;
+    if (k >= n) return;
+    T v = amp[k];
+    if (v != T(0) && fabs((double)v) < a.theta) {
+        Draws r(a.key0, a.key1, kRound, (uint32_t)k, 0u, a.step);
+        const double u = uniform53(r.get(0));
+        v = (u < fabs((double)v) / a.theta) ? (T)copysign(a.theta, (double)v) : T(0);
+        amp[k] = v;
+    }
+    keep[k] = (v != T(0)) ? 1u : 0u;
+}
+
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_compact(const uint64_t *__restrict__ mkey, const T *__restrict__ mamp,
+                                                      const T *__restrict__ mK, uint64_t mstride, uint64_t ne,
+                                                      const uint32_t *__restrict__ keep, const uint32_t *__restrict__ pos,
+                                                      uint64_t *__restrict__ okey, T *__restrict__ oamp, T *__restrict__ oK,
+                                                      uint64_t ostride, double *__restrict__ abs_part, Scratch *sc)
+{
+    const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint64_t n = ne + sc->n_new;
+    double a = 0.0;
+    if (k < n && keep[k]) {
+        const uint32_t p = pos[k];
+#pragma unroll
+        for (int w = 0; w < W; ++w) okey[(uint64_t)w * ostride + p] = mkey[(uint64_t)w * mstride + k];
+        oamp[p] = mamp[k];
+        oK[p] = mK[k];
+        a = fabs((double)mamp[k]);
+    }
+    if (k == n - 1) sc->n_out = pos[k] + keep[k];
+    a = block_reduce_sum(a);
+    if (threadIdx.x == 0) abs_part[blockIdx.x] = a;
+}
+
+// Fixed-order FP64 reduction of per-block partials by one block.
+__global__ void __launch_bounds__(kThreads) k_reduce_partials(const double *__restrict__ part, uint64_t n, double *__restrict__ out)
+{
+    double s = 0.0;
+    for (uint64_t i = threadIdx.x; i < n; i += kThreads) s += part[i];
+    s = block_reduce_sum(s);
+    if (threadIdx.x == 0) *out = s;
+}
+
+__global__ void k_widen(const uint32_t *__restrict__ c32, uint64_t *__restrict__ c64, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) c64[i] = c32[i];
+}
+
+template <typename V>
+__global__ void k_fill(V *p, uint64_t n, V v)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Diagonal of imported / new store entries.
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_store_diag(const SysDev S, const uint64_t *__restrict__ key, uint64_t stride,
+                                                         uint64_t n, T *__restrict__ K)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    uint64_t d[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) d[w] = key[(uint64_t)w * stride + i];
+    K[i] = diagonal<W, T>(S, d);
+}
+
+// (PQ|RS) = sum_L B_LPQ B_LRS (the Cholesky-built two-electron table), summed over L in order.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_build_eri(const double *__restrict__ B, int n, int nchol, T *__restrict__ eri)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint64_t nn = (uint64_t)n * n;
+    if (t >= nn * nn) return;
+    const uint64_t pq = t / nn, rs = t % nn;
+    double v = 0.0;
+    for (int L = 0; L < nchol; ++L) v += B[(uint64_t)L * nn + pq] * B[(uint64_t)L * nn + rs];
+    eri[t] = (T)v;
+}
+
+}  // namespace ccmc

@@ -1,0 +1,133 @@
+"""Host-side driver of a CCMC calculation: shift update, number of selections, projected
+energy with Flyvbjerg-Petersen reblocking, and a run loop over ``ccmc_step``.
+
+Paper: Spencer et al., arXiv:1807.03749, Sec. II (the shift is held until the population
+reaches its target, then varied to keep it stable; projected energy, eq. 7) and the
+Computational Methods section (reblocking analysis of the stochastic error).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class ShiftControl:
+    """Log-growth population control (the standard form used by FCIQMC / DMC; the paper
+    cites it without giving the formula): every `period` steps once the population has
+    reached `target`, S <- S - damping / (period tau) * ln(N(t) / N(t - period))."""
+    target: float
+    tau: float
+    damping: float = 0.05
+    period: int = 10
+    shift: float = 0.0
+    varying: bool = False
+    history: list = field(default_factory=list)
+
+    def update(self, n_total: float) -> float:
+        self.history.append(n_total)
+        if not self.varying and n_total >= self.target:
+            self.varying = True
+            self._anchor = len(self.history) - 1
+        if self.varying and (len(self.history) - 1 - self._anchor) % self.period == 0 and \
+                len(self.history) - 1 > self._anchor:
+            prev = self.history[-1 - self.period]
+            self.shift -= self.damping / (self.period * self.tau) * math.log(n_total / prev)
+        return self.shift
+
+
+def selections(n_total: float) -> int:
+    """Cluster selections per step: the total amplitude, rounded half up (Sec. IV.B)."""
+    return int(math.floor(n_total + 0.5))
+
+
+# ------------------------------------------------------------------------ reblocking
+
+def _blocks(x: np.ndarray):
+    """Successive pairwise block averages of the rows of x (shape [n, k])."""
+    out = []
+    y = np.asarray(x, dtype=np.float64)
+    while len(y) >= 2:
+        out.append(y)
+        n = len(y) // 2 * 2
+        y = 0.5 * (y[0:n:2] + y[1:n:2])
+    return out
+
+
+def reblock_mean(x: np.ndarray):
+    """Flyvbjerg-Petersen blocking of a 1D series.  Returns (mean, standard error at the
+    optimal block, optimal level, per-level standard errors).  The optimal level is the
+    smallest with B^3 > 2 n (SE_B / SE_0)^4 (Lee, Kent, Foulkes & Needs 2011)."""
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x)
+    levels = _blocks(x)
+    se = np.array([y.std(ddof=1) / math.sqrt(len(y)) for y in levels])
+    opt = len(se) - 1
+    for i in range(len(se)):
+        if (2 ** i) ** 3 > 2 * n * (se[i] / se[0]) ** 4:
+            opt = i
+            break
+    return float(x.mean()), float(se[opt]), opt, se
+
+
+def reblock_ratio(num: np.ndarray, den: np.ndarray):
+    """Ratio of means E = <num>/<den> with its standard error from the blocked covariance of
+    (num, den) at the larger of the two optimal levels, by first-order propagation."""
+    num = np.asarray(num, dtype=np.float64)
+    den = np.asarray(den, dtype=np.float64)
+    _, _, on, _ = reblock_mean(num)
+    _, _, od, _ = reblock_mean(den)
+    lv = max(on, od)
+    xy = _blocks(np.stack([num, den], axis=1))[min(lv, len(_blocks(num)) - 1)]
+    mn, md = num.mean(), den.mean()
+    c = np.cov(xy.T, ddof=1) / len(xy)
+    e = mn / md
+    var = e * e * (c[0, 0] / mn ** 2 + c[1, 1] / md ** 2 - 2 * c[0, 1] / (mn * md))
+    return float(e), float(math.sqrt(max(var, 0.0))), lv
+
+
+# -------------------------------------------------------------------------- run loop
+
+@dataclass
+class RunResult:
+    steps: int
+    energy: float = float("nan")
+    error: float = float("nan")
+    shift: float = 0.0
+    n_total: list = field(default_factory=list)
+    n_ref: list = field(default_factory=list)
+    num: list = field(default_factory=list)
+    den: list = field(default_factory=list)
+    attempts: int = 0
+    seconds: float = 0.0
+
+
+def run(state, tau: float, steps: int, target: float, equilibrate: int = 0, shift: ShiftControl | None = None,
+        first_selections: int | None = None, callback=None) -> RunResult:
+    """Propagate `state` (a ccmc.State) for `steps` steps with population control; the
+    projected-energy terms after `equilibrate` steps enter the reblocked estimate."""
+    import time
+
+    ctl = shift or ShiftControl(target=target, tau=tau)
+    res = RunResult(steps=steps)
+    nsel = first_selections if first_selections is not None else selections(state.options.init_pop)
+    t0 = time.perf_counter()
+    for it in range(steps):
+        st = state.ccmc_step(tau, ctl.shift, nsel)
+        res.attempts += st["n_spawn_attempts"]
+        res.n_total.append(st["n_total"])
+        res.n_ref.append(st["n_ref"])
+        if it >= equilibrate:
+            res.num.append(st["eproj_num"])
+            res.den.append(st["eproj_den"])
+        ctl.update(st["n_total"])
+        nsel = selections(st["n_total"])
+        if callback:
+            callback(it, st, ctl)
+    res.seconds = time.perf_counter() - t0
+    res.shift = ctl.shift
+    if len(res.num) >= 16:
+        res.energy, res.error, _ = reblock_ratio(np.array(res.num), np.array(res.den))
+    return res

@@ -111,3 +111,16 @@ def serving_stream(n_requests: int = 64, rate: float = 2.0, seed: int = PHILOX_S
             tau=0.005 if trunc == 2 else 0.002,
             seed=int(rng.integers(1, 2**63 - 1))))
     return out
+
+
+def state_amplitudes(levels, target: float, seed: int = PHILOX_SEED, decay: float = 2.0):
+    """Seeded excitor amplitudes for a synthetic store: log-normal magnitudes whose median
+    falls by exp(decay) per excitation level above 2, random signs, scaled so that
+    sum |N_i| = target, and every |N_i| >= 1 (the default occupation threshold)."""
+    rng = np.random.default_rng(seed)
+    levels = np.asarray(levels)
+    mag = np.exp(rng.normal(0.0, 1.0, size=len(levels)) - decay * np.maximum(levels - 2, 0))
+    mag *= target / mag.sum()
+    mag = np.maximum(mag, 1.0)
+    sign = np.where(rng.random(len(levels)) < 0.5, -1.0, 1.0)
+    return sign * mag

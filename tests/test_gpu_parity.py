@@ -1,0 +1,193 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element by element.
+
+Each case imports one oracle-evolved state into both, runs one step with the same Philox
+key, and compares the spawn/death record lists (ids and keys bit-exact, amplitudes 1e-12
+relative), the annihilated store (keys bit-exact, amplitudes 1e-12 of the summed
+magnitude), N_0, every count and the FP64 estimator terms (see parity_util).
+"""
+from __future__ import annotations
+
+import itertools
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import binding as orc
+from paper_1807_03749_amd import ccmc, inputs
+from parity_util import compare_step, evolve_oracle, key_tuple, make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+CASES = [
+    # name, system kwargs, truncation, options, tau, init steps, init selections
+    ("ueg14_38_ccsd_original", dict(system="ueg", n_el=14, n2_max=2), 2,
+     dict(init_pop=400.0, seed=1234), 0.005, 40, 400),
+    ("ueg14_38_ccsdt_fnc_ms4", dict(system="ueg", n_el=14, n2_max=2), 3,
+     dict(full_noncomposite=True, min_spawn_attempts=4, multispawn_threshold=1.0, init_pop=300.0, seed=7), 0.004,
+     30, 300),
+    ("ueg14_114_ccsdt_fnc_ms4", dict(system="ueg", n_el=14, n2_max=5), 3,
+     dict(full_noncomposite=True, min_spawn_attempts=4, multispawn_threshold=1.0, init_pop=500.0, seed=1234),
+     0.002, 40, 500),
+    ("ueg54_246_ccsd_fnc_ms8", dict(system="ueg", n_el=54, n2_max=9), 2,
+     dict(full_noncomposite=True, min_spawn_attempts=8, multispawn_threshold=1.0, init_pop=300.0, seed=11),
+     0.001, 12, 300),
+    ("mol4_12_ccsd_original", dict(system="mol", n_el=4, n_spatial=6, n_chol=8, mol_seed=4), 2,
+     dict(init_pop=300.0, p_single=0.3, seed=5), 0.01, 40, 300),
+    ("mol16_92_ccsdtq_fnc_ms8", dict(system="mol", n_el=16, n_spatial=46, n_chol=138), 4,
+     dict(full_noncomposite=True, min_spawn_attempts=8, multispawn_threshold=1.0, init_pop=200.0, seed=1234),
+     5e-4 * 20, 10, 200),
+]
+
+
+@pytest.mark.parametrize("name,sysk,l,opts,tau,nsteps,nsel0", CASES, ids=[c[0] for c in CASES])
+def test_step_matches_oracle(name, sysk, l, opts, tau, nsteps, nsel0):
+    _say(f"[parity] {name}: building")
+    S, R, g = make_pair(l=l, opts=opts, **sysk)
+    st = evolve_oracle(R, nsteps, tau, nsel0)
+    _say(f"[parity] {name}: state with {st['n_excitors']} excitors, N_tot {st['n_total']:.1f}")
+    for rep in range(2):
+        shift = [0.0, -0.05][rep]
+        gs, os_ = compare_step(S, R, g, tau, shift, int(round(st["n_total"])))
+        st = os_
+        _say(f"[parity] {name}: step {rep} ok ({gs['n_spawn_attempts']} attempts, {gs['n_spawns']} spawns)")
+    g.close()
+
+
+def test_trajectory_matches_oracle():
+    """Twelve consecutive steps, each from the previous step's own result on each side
+    (the GPU state is never re-imported), stay equal."""
+    S, R, g = make_pair("ueg", 14, 2, dict(full_noncomposite=True, min_spawn_attempts=2, multispawn_threshold=1.0,
+                                           init_pop=200.0, seed=99), n2_max=2)
+    st = evolve_oracle(R, 10, 0.005, 200)
+    keys, amps, n0, step = R.export_state()
+    g.ccmc_import(keys, amps, n0, step)
+    shift = 0.0
+    for t in range(12):
+        nsel = int(round(st["n_total"]))
+        st = R.step(0.005, shift, nsel)
+        gs = g.ccmc_step(0.005, shift, nsel)
+        for f in ("n_spawns", "n_deaths", "n_excitors", "n_spawn_attempts", "n_discarded"):
+            assert gs[f] == st[f], (t, f)
+        k2, a2, r2, _ = R.export_state()
+        gk, ga, gr, _ = g.ccmc_export()
+        assert np.array_equal(gk, k2)
+        np.testing.assert_allclose(ga, a2, rtol=1e-11, atol=1e-12)
+        assert abs(gr - r2) <= 1e-11 * abs(r2)
+        shift -= 0.01
+    _say("[parity] trajectory ok")
+
+
+def test_first_step_from_empty_store_and_zero_selections():
+    for fnc in (False, True):
+        S, R, g = make_pair("ueg", 14, 2, dict(full_noncomposite=fnc, init_pop=50.0, seed=3), n2_max=2)
+        # the initial state: N_0 = init_pop, no excitors, step 0 -- identical on both sides
+        gs = g.ccmc_step(0.005, 0.0, 50)
+        os_ = R.step(0.005, 0.0, 50)
+        assert gs["n_excitors"] == os_["n_excitors"] and gs["n_spawns"] == os_["n_spawns"]
+        gk, ga, gr, _ = g.ccmc_export()
+        ok_, oa, orr, _ = R.export_state()
+        assert np.array_equal(gk, ok_)
+        np.testing.assert_allclose(ga, oa, rtol=1e-12)
+        compare_step(S, R, g, 0.005, 0.0, 0)      # no sampled clusters at all
+    _say("[parity] empty store / zero selections ok")
+
+
+def test_edge_options():
+    """No rounding at all (zero cutoff and threshold) and very large multi-spawn counts."""
+    S, R, g = make_pair("ueg", 14, 2, dict(full_noncomposite=True, spawn_cutoff=0.0, occupation_threshold=0.0,
+                                           min_spawn_attempts=1, multispawn_threshold=0.002, init_pop=100.0, seed=5),
+                        n2_max=2)
+    st = evolve_oracle(R, 6, 0.005, 100)
+    gs, os_ = compare_step(S, R, g, 0.005, 0.0, int(round(st["n_total"])))
+    assert gs["max_attempts_per_cluster"] > 1000
+    _say("[parity] edge options ok")
+
+
+def test_attempt_overflow_rolls_back():
+    """More than 2^30-2 attempts on one cluster: EOVERFLOW and the state is unchanged."""
+    S, R, g = make_pair("ueg", 14, 2, dict(full_noncomposite=True, multispawn_threshold=1e-9, init_pop=10.0), n2_max=2)
+    before = g.ccmc_export()
+    with pytest.raises(ccmc.CCMCError) as e:
+        g.ccmc_step(0.005, 0.0, 10)
+    assert e.value.status == -3
+    after = g.ccmc_export()
+    assert np.array_equal(before[0], after[0]) and before[2] == after[2] and before[3] == after[3]
+
+
+def test_import_validation():
+    g = ccmc.State("ueg", 14, 2, n2_max=2)
+    S = orc.System.ueg(14, 2, 1.0)
+    d1 = S.det(list(range(12)) + [14, 15])
+    d2 = S.det(list(range(12)) + [16, 17])
+    bad = [
+        (np.array([d2, d1]), [1.0, 1.0]),
+        (np.array([S.hf]), [1.0]),
+        (np.array([d1]), [0.0]),
+        (np.array([d1]), [float("nan")]),
+        (np.array([S.det(list(range(11)) + [14, 15, 16])]), [1.0]),
+        (np.array([S.det(list(range(13)) + [14, 15])]), [1.0]),
+        (np.array([S.det(list(range(12)) + [14, 40])]), [1.0]),
+    ]
+    for keys, amps in bad:
+        with pytest.raises(ccmc.CCMCError) as e:
+            g.ccmc_import(keys, amps, 5.0)
+        assert e.value.status == -1
+    g.ccmc_import(np.array([d1, d2]), [1.0, -2.0], 5.0, 3)
+    k, a, r, st = g.ccmc_export()
+    assert np.array_equal(k, np.array([d1, d2])) and list(a) == [1.0, -2.0] and r == 5.0 and st == 3
+
+
+def _full_cisdt_state(S: orc.System, l: int, seed: int, target: float):
+    """Every momentum-conserving S_z = 0 determinant of the UEG up to level l, with seeded
+    amplitudes (inputs.state_amplitudes) -- a synthetic store of the full truncated space."""
+    nv = S.nvec()
+    N, M = S.n_el, S.M
+    occ = list(range(N))
+    vir = list(range(N, M))
+    spin = lambda p: p & 1
+    dets = []
+    for L in range(1, l + 1):
+        # group particle sets by (momentum, alpha count) for the join with hole sets
+        table = {}
+        for parts in itertools.combinations(vir, L):
+            mom = tuple(int(x) for x in sum(nv[p >> 1] for p in parts))
+            key = (mom, sum(1 for p in parts if spin(p) == 0))
+            table.setdefault(key, []).append(parts)
+        for holes in itertools.combinations(occ, L):
+            mom = tuple(int(x) for x in sum(nv[p >> 1] for p in holes))
+            key = (mom, sum(1 for p in holes if spin(p) == 0))
+            for parts in table.get(key, []):
+                v = (1 << N) - 1
+                for i in holes:
+                    v ^= 1 << i
+                for a in parts:
+                    v |= 1 << a
+                dets.append(v)
+    dets.sort()
+    levels = np.array([bin(d >> N).count("1") for d in dets])
+    amps = inputs.state_amplitudes(levels, target=target, seed=seed)
+    W = S.W
+    keys = np.array([[(d >> (64 * w)) & 0xFFFFFFFFFFFFFFFF for w in range(W)] for d in dets], dtype=np.uint64)
+    return keys, amps
+
+
+def test_full_size_step_ueg14_114_ccsdt():
+    """One step at the benchmark's full size (14e/114so CCSDT, FNC, k_min 4, N_tot ~ 1e6,
+    the whole CISDT space of 108,753 determinants occupied), GPU against the oracle."""
+    S, R, g = make_pair("ueg", 14, 3, dict(full_noncomposite=True, min_spawn_attempts=4, multispawn_threshold=1.0,
+                                           seed=1234), n2_max=5)
+    keys, amps = _full_cisdt_state(S, 3, seed=1, target=8e5)
+    assert len(keys) == 108752
+    n0 = 2e5
+    R.import_state(keys, amps, n0, 500)
+    _say(f"[parity] full size: {len(keys)} excitors, N_tot {np.abs(amps).sum() + n0:.3e}")
+    gs, os_ = compare_step(S, R, g, 0.002, 0.0, int(round(np.abs(amps).sum() + n0)))
+    _say(f"[parity] full size ok: {gs['n_spawn_attempts']} attempts, {gs['n_spawns']} spawns")
