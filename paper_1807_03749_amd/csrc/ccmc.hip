@@ -66,9 +66,10 @@ struct ccmc_state {
     HostSys hs;
     SysDev sd{};
     std::vector<DevBuf *> all;
-    DevBuf t_grid, t_nvec, t_vq, t_h, t_eri, t_fock, t_vpair;
+    DevBuf t_grid, t_nvec, t_vq, t_h, t_eri, t_fock, t_vpair, t_binv, t_bino;
+    int rank_bits = 0;  // bits of the largest truncated-space rank
     // the store: current buffer cur, merge target 1 - cur
-    DevBuf skey[2], samp[2], sK[2];
+    DevBuf skey[2], samp[2], sK[2], srank[2];
     uint64_t scap = 0;
     int cur = 0;
     uint64_t ne = 0;
@@ -76,14 +77,15 @@ struct ccmc_state {
     uint64_t step = 0;
     double last_num = 0, last_den = 0;
     // per-step buffers
-    DevBuf q, P, delta;
+    DevBuf q, P, guide, delta;
     DevBuf ikey, iA, ideath, in, ilevel, icnt, ioff;
     uint64_t icap = 0;
     DevBuf num_part, abs_part;
-    DevBuf rkey, ramp, rid, rcount, boff;
-    uint64_t rcap = 0;  // region slots
-    DevBuf dkey, damp, did, sk[2], sidx[2], hist, hoff;
-    DevBuf flag, incl, start, is_new, new_pos, ins, seg_sum, nkey, nins, nsum, keep, pos;
+    DevBuf block_item, gcount, gspawn, gdeath, gor, boff;
+    DevBuf rrank, rkey, ramp, rid;  // per-block record regions
+    uint64_t rcap = 0;              // region slots
+    DevBuf drank, dkey, damp, did, sr[2], sidx[2], hist, hoff;
+    DevBuf flag, incl, start, is_new, new_pos, ins, seg_sum, nkey, nrank, nins, nsum, keep, pos;
     uint64_t dcap = 0;  // dense record capacity
     std::vector<DevBuf> scan_tmp;
     DevBuf scratch;
@@ -214,8 +216,8 @@ ccmc_status scan(ccmc_state *st, const V *in, V *out, uint64_t n, bool inclusive
 {
     if (n == 0) return CCMC_OK;
     const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
-    if (tiles == 1) {
-        k_scan_tile<V><<<1, kThreads, 0, st->stream>>>(in, out, n, nullptr, inclusive ? 1 : 0);
+    if (tiles <= 16) {
+        k_scan_small<V><<<1, kThreads, 0, st->stream>>>(in, out, n, inclusive ? 1 : 0);
         return CCMC_OK;
     }
     if ((int)st->scan_tmp.size() < 2 * (level + 1)) st->scan_tmp.resize(2 * (level + 1));
@@ -378,6 +380,41 @@ ccmc_status upload_system(ccmc_state *st, const ccmc_integrals *ints)
     for (int w = 0; w < kMaxWords; ++w) S.hf[w] = 0;
     for (int p = 0; p < hs.nel; ++p) S.hf[p >> 6] |= 1ull << (p & 63);
     S.p_single = st->opt.p_single;
+    {
+        // C(n, j) for the virtual part (j <= 8) and C(n, k) for the occupied part, both
+        // saturating at 2^63; the truncated space itself must stay below 2^62.
+        const int M = hs.M, N = hs.nel;
+        const uint64_t sat = 1ull << 63;
+        auto binom = [&](int n, int k) -> uint64_t {
+            if (k < 0 || k > n) return 0;
+            unsigned __int128 v = 1;
+            for (int i = 1; i <= k; ++i) {
+                v = v * (unsigned)(n - k + i) / (unsigned)i;
+                if (v > sat) return sat;
+            }
+            return (uint64_t)v;
+        };
+        std::vector<uint64_t> bv((size_t)(M + 1) * 9), bo((size_t)(N + 1) * (N + 1));
+        for (int n = 0; n <= M; ++n)
+            for (int j = 0; j <= 8; ++j) bv[(size_t)n * 9 + j] = binom(n, j);
+        for (int n = 0; n <= N; ++n)
+            for (int k = 0; k <= N; ++k) bo[(size_t)n * (N + 1) + k] = binom(n, k);
+        unsigned __int128 space = 0;
+        for (int j = 0; j <= st->l; ++j) space += (unsigned __int128)binom(N, j) * binom(M - N, j);
+        if (space >= ((unsigned __int128)1 << 62)) {
+            st->err = "truncated space too large for 64-bit determinant ranks";
+            return CCMC_EINVAL;
+        }
+        int bits = 0;
+        while (((unsigned __int128)1 << bits) < space) ++bits;
+        st->rank_bits = bits;
+        TRY(ensure(st, st->t_binv, bv.size() * 8));
+        TRY(ensure(st, st->t_bino, bo.size() * 8));
+        HIP_TRY(hipMemcpy(st->t_binv.p, bv.data(), bv.size() * 8, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(st->t_bino.p, bo.data(), bo.size() * 8, hipMemcpyHostToDevice));
+        S.binom_v = ptr<uint64_t>(st->t_binv);
+        S.binom_o = ptr<uint64_t>(st->t_bino);
+    }
     TRY(upload_table<T>(st, st->t_fock, hs.fock));
     TRY(upload_table<T>(st, st->t_vpair, hs.vpair));
     S.fock = st->t_fock.p;
@@ -417,31 +454,37 @@ ccmc_status ensure_store(ccmc_state *st, uint64_t n)
 {
     if (n <= st->scap) return CCMC_OK;
     uint64_t nc = std::max<uint64_t>(n, std::max<uint64_t>(1024, st->scap + st->scap / 2));
-    DevBuf k, a, K;
+    DevBuf k, a, K, r;
     TRY(ensure(st, k, nc * W * sizeof(uint64_t)));
     TRY(ensure(st, a, nc * sizeof(T)));
     TRY(ensure(st, K, nc * sizeof(T)));
+    TRY(ensure(st, r, nc * sizeof(uint64_t)));
     const int c = st->cur;
     if (st->ne) {
         HIP_TRY(hipMemcpy2DAsync(k.p, nc * sizeof(uint64_t), st->skey[c].p, st->scap * sizeof(uint64_t),
                                  st->ne * sizeof(uint64_t), W, hipMemcpyDeviceToDevice, st->stream));
         HIP_TRY(hipMemcpyAsync(a.p, st->samp[c].p, st->ne * sizeof(T), hipMemcpyDeviceToDevice, st->stream));
         HIP_TRY(hipMemcpyAsync(K.p, st->sK[c].p, st->ne * sizeof(T), hipMemcpyDeviceToDevice, st->stream));
+        HIP_TRY(hipMemcpyAsync(r.p, st->srank[c].p, st->ne * sizeof(uint64_t), hipMemcpyDeviceToDevice, st->stream));
         HIP_TRY(hipStreamSynchronize(st->stream));
     }
     for (int b = 0; b < 2; ++b) {
         release(st, st->skey[b]);
         release(st, st->samp[b]);
         release(st, st->sK[b]);
+        release(st, st->srank[b]);
     }
     st->skey[c] = k;
     st->samp[c] = a;
     st->sK[c] = K;
+    st->srank[c] = r;
     TRY(ensure(st, st->skey[1 - c], nc * W * sizeof(uint64_t)));
     TRY(ensure(st, st->samp[1 - c], nc * sizeof(T)));
     TRY(ensure(st, st->sK[1 - c], nc * sizeof(T)));
+    TRY(ensure(st, st->srank[1 - c], nc * sizeof(uint64_t)));
     TRY(ensure(st, st->q, nc * sizeof(uint64_t)));
     TRY(ensure(st, st->P, nc * sizeof(uint64_t)));
+    TRY(ensure(st, st->guide, (2 * nc + 4) * sizeof(uint32_t)));
     TRY(ensure(st, st->delta, nc * sizeof(double)));
     st->scap = nc;
     return CCMC_OK;
@@ -457,11 +500,8 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     const uint64_t n_fnc = fnc ? ne + 1 : 0;
     const uint64_t n_items = n_fnc + n_sel;
     const int c = st->cur;
-    const uint64_t scap = st->scap;
-    const uint64_t *skey = ptr<uint64_t>(st->skey[c]);
-    const T *samp = ptr<T>(st->samp[c]);
-    const T *sK = ptr<T>(st->sK[c]);
-    const double ab = (double)(W * 8 + sizeof(T));  // bytes of one key + amplitude
+    const double kb = (double)(W * 8);  // bytes of one bitstring
+    const double tb = (double)sizeof(T);
 
     StepArgs a;
     a.tau = tau;
@@ -479,15 +519,20 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
 
     Scratch *sc = ptr<Scratch>(st->scratch);
     HIP_TRY(hipMemsetAsync(sc, 0, sizeof(Scratch), s));
+    const uint64_t *skey = ptr<uint64_t>(st->skey[c]);
+    const T *samp = ptr<T>(st->samp[c]);
+    const T *sK = ptr<T>(st->sK[c]);
+    const uint64_t scap = st->scap;
 
-    // (a1) selection weights and their inclusive prefix
+    // (a1) selection weights, their inclusive prefix and the guide table of the draws
     if (ne) {
-        launch(st, "weights", ne * (sizeof(T) + 8.0), (double)ne, [&] {
+        launch(st, "weights", ne * (tb + 8.0), (double)ne, [&] {
             k_weights<T><<<grid_for(ne), kThreads, 0, s>>>(samp, ne, ptr<uint64_t>(st->q), sc);
         });
         TRY(scan<uint64_t>(st, ptr<uint64_t>(st->q), ptr<uint64_t>(st->P), ne, true));
     }
-    k_qtot<<<1, 1, 0, s>>>(ptr<uint64_t>(st->P), ne, sc);
+    k_guide_setup<<<1, 1, 0, s>>>(ptr<uint64_t>(st->P), ne, sc);
+    if (ne && n_sel) k_guide<<<grid_for(2 * ne + 2), kThreads, 0, s>>>(ptr<uint64_t>(st->P), ne, sc, ptr<uint32_t>(st->guide));
 
     // items: non-composite (FNC) then sampled clusters
     if (n_items + 1 > st->icap) {
@@ -506,15 +551,16 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     const unsigned nb_fnc = fnc ? grid_for(n_fnc) : 0, nb_sel = n_sel ? grid_for(n_sel) : 0;
     TRY(ensure(st, st->num_part, (size_t)(nb_fnc + nb_sel + 1) * sizeof(double)));
     double *num_part = ptr<double>(st->num_part);
+    const double item_bytes = kb + 2 * tb + 13.0;  // key, A, death, n, level, slot count
     if (fnc) {
-        launch(st, "noncomposite", n_fnc * (ab + sizeof(T)) + n_fnc * (W * 8 + 3 * sizeof(T) + 13.0), (double)n_fnc, [&] {
+        launch(st, "noncomposite", n_fnc * (kb + 2 * tb + item_bytes), (double)n_fnc, [&] {
             k_noncomposite<W, T><<<nb_fnc, kThreads, 0, s>>>(st->sd, skey, samp, sK, scap, ne, st->n0, a, it, num_part, sc);
         });
     }
     if (n_sel) {
-        launch(st, "select", n_sel * (W * 8 + 2 * sizeof(T) + 13.0), (double)n_sel, [&] {
-            k_select<W, T><<<nb_sel, kThreads, 0, s>>>(st->sd, skey, samp, scap, ne, ptr<uint64_t>(st->P), st->n0, a, it,
-                                                        n_fnc, num_part + nb_fnc, sc);
+        launch(st, "select", n_sel * item_bytes, (double)n_sel, [&] {
+            k_select<W, T><<<nb_sel, kThreads, 0, s>>>(st->sd, skey, samp, scap, ne, ptr<uint64_t>(st->P),
+                                                        ptr<uint32_t>(st->guide), st->n0, a, it, n_fnc, num_part + nb_fnc, sc);
         });
     }
     k_fill<uint64_t><<<1, 1, 0, s>>>(it.cnt + n_items, 1, 0ull);
@@ -532,129 +578,125 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
         return CCMC_EOVERFLOW;
     }
     const uint64_t n_slots = st->hpinned[0];
-
-    // (a6-a8) records: death and spawning attempts, one lane per slot
-    const uint64_t nblk = (n_slots + kGenSlots - 1) / kGenSlots;
     if (n_slots + ne + 1 >= (1ull << 32)) {
         st->err = "more than 2^32 record slots in one step";
         return CCMC_EOVERFLOW;
     }
+
+    // (a6-a8) records: death and spawning attempts, one lane per slot, compacted per block
     const bool ids = st->opt.keep_spawn_ids != 0;
+    const uint64_t nblk = (n_slots + kGenSlots - 1) / kGenSlots;
     if (nblk * kGenSlots > st->rcap) {
         const uint64_t nc = std::max<uint64_t>(nblk * kGenSlots, st->rcap + st->rcap / 2);
+        const uint64_t nb = nc / kGenSlots + 2;
         TRY(ensure(st, st->rkey, nc * W * sizeof(uint64_t)));
+        TRY(ensure(st, st->rrank, nc * sizeof(uint64_t)));
         TRY(ensure(st, st->ramp, nc * sizeof(T)));
-        if (ids) TRY(ensure(st, st->rid, nc * sizeof(uint64_t)));
-        TRY(ensure(st, st->rcount, (nc / kGenSlots + 1) * sizeof(uint32_t)));
-        TRY(ensure(st, st->boff, (nc / kGenSlots + 1) * sizeof(uint64_t)));
+        for (DevBuf *b : {&st->block_item, &st->gor}) TRY(ensure(st, *b, nb * sizeof(uint64_t)));
+        for (DevBuf *b : {&st->gcount, &st->gspawn, &st->gdeath, &st->boff}) TRY(ensure(st, *b, nb * sizeof(uint32_t)));
         st->rcap = nc;
     }
-    Records rec{ptr<uint64_t>(st->rkey), st->ramp.p, ptr<uint64_t>(st->rid), ptr<uint32_t>(st->rcount), st->rcap};
+    if (ids && st->rid.bytes < st->rcap * sizeof(uint64_t)) TRY(ensure(st, st->rid, st->rcap * sizeof(uint64_t)));
+    Records reg{ptr<uint64_t>(st->rrank), ptr<uint64_t>(st->rkey), st->ramp.p, ptr<uint64_t>(st->rid), st->rcap};
+    GenStats gst{ptr<uint32_t>(st->gcount), ptr<uint32_t>(st->gspawn), ptr<uint32_t>(st->gdeath), ptr<uint64_t>(st->gor)};
     if (nblk) {
+        k_block_items<<<grid_for(nblk + 1), kThreads, 0, s>>>(ptr<uint64_t>(st->ioff), n_items, nblk, n_slots,
+                                                             ptr<uint64_t>(st->block_item));
         launch(st, "generate", (double)n_slots * 16.0, (double)n_slots, [&] {
-            k_generate<W, T><<<(unsigned)nblk, kThreads, 0, s>>>(st->sd, it, ptr<uint64_t>(st->ioff), n_items, n_fnc,
-                                                                 n_slots, a, rec, ids ? 1 : 0, sc);
+            k_generate<W, T><<<(unsigned)nblk, kThreads, 0, s>>>(st->sd, it, ptr<uint64_t>(st->ioff),
+                                                                 ptr<uint64_t>(st->block_item), n_fnc, n_slots, a, reg,
+                                                                 ids ? 1 : 0, gst);
         });
-    }
-    // block counts -> offsets (u32 counts widened through a u64 scan buffer)
-    if (nblk) {
-        uint64_t *boff = ptr<uint64_t>(st->boff);
-        TRY(ensure(st, st->keep, (nblk + 1) * sizeof(uint64_t)));
-        uint64_t *cnt64 = ptr<uint64_t>(st->keep);
-        k_fill<uint64_t><<<grid_for(nblk + 1), kThreads, 0, s>>>(cnt64, nblk + 1, 0ull);
-        k_widen<<<grid_for(nblk), kThreads, 0, s>>>(ptr<uint32_t>(st->rcount), cnt64, nblk);
-        TRY(scan<uint64_t>(st, cnt64, boff, nblk + 1, false));
-        HIP_TRY(hipMemcpyAsync(st->hpinned, boff + nblk, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    } else {
-        st->hpinned[0] = 0;
-    }
-    HIP_TRY(hipStreamSynchronize(s));
-    const uint64_t nrec = st->hpinned[0];
-
-    // dense record arrays and sort buffers
-    if (nrec + 1 > st->dcap || ne + nrec + 1 > st->dcap) {
-        const uint64_t nc = std::max<uint64_t>(std::max(nrec, ne) + 1, st->dcap + st->dcap / 2);
-        for (DevBuf *b : {&st->dkey, &st->sk[0], &st->sk[1], &st->nkey}) TRY(ensure(st, *b, nc * W * sizeof(uint64_t)));
-        TRY(ensure(st, st->damp, nc * sizeof(T)));
-        if (ids) TRY(ensure(st, st->did, nc * sizeof(uint64_t)));
-        for (DevBuf *b : {&st->sidx[0], &st->sidx[1], &st->flag, &st->incl, &st->start, &st->is_new, &st->new_pos})
-            TRY(ensure(st, *b, nc * sizeof(uint32_t)));
-        for (DevBuf *b : {&st->ins, &st->nins}) TRY(ensure(st, *b, nc * sizeof(uint64_t)));
-        for (DevBuf *b : {&st->seg_sum, &st->nsum}) TRY(ensure(st, *b, nc * sizeof(double)));
-        st->dcap = nc;
-    }
-    TRY(ensure_store<W, T>(st, ne + nrec + 1));
-    // the store may have moved
-    skey = ptr<uint64_t>(st->skey[c]);
-    samp = ptr<T>(st->samp[c]);
-    sK = ptr<T>(st->sK[c]);
-    const uint64_t S2 = st->scap;
-    TRY(ensure(st, st->keep, (ne + nrec + 1) * sizeof(uint32_t)));
-    TRY(ensure(st, st->pos, (ne + nrec + 1) * sizeof(uint32_t)));
-    const uint64_t dc = st->dcap;
-    uint64_t *dkey = ptr<uint64_t>(st->dkey);
-    T *damp = ptr<T>(st->damp);
-    if (nblk) {
-        launch(st, "gather", 2.0 * nrec * (W * 8 + sizeof(T) + (ids ? 8 : 0)), (double)nrec, [&] {
-            k_gather<W, T><<<(unsigned)nblk, kThreads, 0, s>>>(st->sd, rec, ptr<uint64_t>(st->boff), dkey, damp,
-                                                               ptr<uint64_t>(st->did), dc, ids ? 1 : 0, sc);
-        });
+        k_fill<uint32_t><<<1, 1, 0, s>>>(gst.count + nblk, 1, 0u);
+        TRY(scan<uint32_t>(st, gst.count, ptr<uint32_t>(st->boff), nblk + 1, false));
+        k_gen_stats<<<1, kThreads, 0, s>>>(gst, ptr<uint32_t>(st->boff), nblk, sc);
     }
     HIP_TRY(hipMemcpyAsync(st->hscratch, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     Scratch scr = *st->hscratch;
+    const uint64_t nrec = nblk ? scr.n_rec : 0;
+    if (nrec + 1 > st->dcap || ne + nrec + 1 > st->dcap) {
+        const uint64_t nc = std::max<uint64_t>(std::max(nrec, ne) + 1, st->dcap + st->dcap / 2);
+        for (DevBuf *b : {&st->dkey, &st->nkey}) TRY(ensure(st, *b, nc * W * sizeof(uint64_t)));
+        TRY(ensure(st, st->damp, nc * sizeof(T)));
+        for (DevBuf *b : {&st->drank, &st->sr[0], &st->sr[1], &st->ins, &st->nins, &st->nrank})
+            TRY(ensure(st, *b, nc * sizeof(uint64_t)));
+        for (DevBuf *b : {&st->sidx[0], &st->sidx[1], &st->flag, &st->incl, &st->start, &st->is_new, &st->new_pos})
+            TRY(ensure(st, *b, nc * sizeof(uint32_t)));
+        for (DevBuf *b : {&st->seg_sum, &st->nsum}) TRY(ensure(st, *b, nc * sizeof(double)));
+        st->dcap = nc;
+    }
+    if (ids && st->did.bytes < st->dcap * sizeof(uint64_t)) TRY(ensure(st, st->did, st->dcap * sizeof(uint64_t)));
+    const uint64_t dc = st->dcap;
+    Records rec{ptr<uint64_t>(st->drank), ptr<uint64_t>(st->dkey), st->damp.p, ptr<uint64_t>(st->did), dc};
+    if (nrec) {
+        launch(st, "gather", 2.0 * nrec * (kb + 8.0 + tb + (ids ? 8.0 : 0.0)), (double)nrec, [&] {
+            k_gather<W, T><<<grid_for(nrec), kThreads, 0, s>>>(reg, ptr<uint32_t>(st->boff), nblk, rec, ids ? 1 : 0, sc);
+        });
+    }
 
-    // (a11) stable LSD radix sort by determinant over the digits that vary
-    std::vector<std::pair<int, int>> passes;
-    for (int w = 0; w < W; ++w)
-        for (int sh = 0; sh < 64; sh += 8)
-            if ((scr.diffmask[w] >> sh) & 0xFFull) passes.push_back({w, sh});
-    if (passes.empty()) passes.push_back({0, 0});
+    // the store must be able to take every new determinant
+    TRY(ensure_store<W, T>(st, ne + nrec + 1));
+    skey = ptr<uint64_t>(st->skey[c]);
+    samp = ptr<T>(st->samp[c]);
+    sK = ptr<T>(st->sK[c]);
+    const uint64_t *srank = ptr<uint64_t>(st->srank[c]);
+    const uint64_t S2 = st->scap;
+    TRY(ensure(st, st->keep, (ne + nrec + 1) * sizeof(uint32_t)));
+    TRY(ensure(st, st->pos, (ne + nrec + 1) * sizeof(uint32_t)));
+
+    // (a11) stable LSD radix sort of (rank, record index) over the rank digits that vary
+    int top = 0;
+    while (top < 64 && (scr.rank_or >> top)) ++top;
+    std::vector<int> passes;
+    for (int sh = 0; sh < top; sh += 8) passes.push_back(sh);
+    if (passes.empty()) passes.push_back(0);
     const uint32_t n32 = (uint32_t)nrec;
     const uint32_t tiles = (uint32_t)std::max<uint64_t>(1, (nrec + kSortTile - 1) / kSortTile);
     TRY(ensure(st, st->hist, (size_t)256 * tiles * sizeof(uint32_t)));
     TRY(ensure(st, st->hoff, (size_t)256 * tiles * sizeof(uint32_t)));
-    const uint64_t *kin = dkey;
+    const uint64_t *kin = ptr<uint64_t>(st->drank);
     const uint32_t *iin = nullptr;
     int ob = 0;
     if (nrec) {
-        for (auto &pp : passes) {
-            uint64_t *kout = ptr<uint64_t>(st->sk[ob]);
+        for (int sh : passes) {
+            uint64_t *kout = ptr<uint64_t>(st->sr[ob]);
             uint32_t *iout = ptr<uint32_t>(st->sidx[ob]);
             launch(st, "radix_hist", nrec * 8.0, (double)nrec, [&] {
-                k_radix_hist<W><<<tiles, kThreads, 0, s>>>(kin, dc, n32, pp.first, pp.second, ptr<uint32_t>(st->hist), tiles);
+                k_radix_hist<1><<<tiles, kThreads, 0, s>>>(kin, dc, n32, 0, sh, ptr<uint32_t>(st->hist), tiles);
             });
             TRY(scan<uint32_t>(st, ptr<uint32_t>(st->hist), ptr<uint32_t>(st->hoff), (uint64_t)256 * tiles, false));
-            launch(st, "radix_scatter", 2.0 * nrec * (W * 8 + 4), (double)nrec, [&] {
-                k_radix_scatter<W><<<tiles, kThreads, 0, s>>>(kin, iin, kout, iout, dc, n32, pp.first, pp.second,
-                                                              ptr<uint32_t>(st->hoff), tiles);
+            launch(st, "radix_scatter", nrec * (2 * 8.0 + (iin ? 8.0 : 4.0)), (double)nrec, [&] {
+                k_radix_scatter<1><<<tiles, kThreads, 0, s>>>(kin, iin, kout, iout, dc, n32, 0, sh, ptr<uint32_t>(st->hoff),
+                                                              tiles);
             });
             kin = kout;
             iin = iout;
             ob ^= 1;
         }
     }
-    const uint64_t *sorted_key = kin;
+    const uint64_t *sorted_rank = kin;
     const uint32_t *sorted_idx = iin;
 
-    // (a12) segments: heads, left fold in record order, store lookup
+    // (a12) segments: heads, left fold in record order, store lookup by rank
     double *delta = ptr<double>(st->delta);
     if (ne) k_fill<double><<<grid_for(ne), kThreads, 0, s>>>(delta, ne, 0.0);
     if (nrec) {
         uint32_t *flag = ptr<uint32_t>(st->flag), *incl = ptr<uint32_t>(st->incl), *start = ptr<uint32_t>(st->start);
-        k_seg_flags<W><<<grid_for(nrec), kThreads, 0, s>>>(sorted_key, dc, n32, flag);
+        k_seg_flags<<<grid_for(nrec), kThreads, 0, s>>>(sorted_rank, n32, flag);
         TRY(scan<uint32_t>(st, flag, incl, nrec, true));
         k_seg_starts<<<grid_for(nrec), kThreads, 0, s>>>(flag, incl, n32, start, sc);
         k_fill<uint32_t><<<grid_for(nrec), kThreads, 0, s>>>(ptr<uint32_t>(st->is_new), nrec, 0u);
-        launch(st, "seg_fold", nrec * (W * 8 + 4.0 + sizeof(T)), (double)nrec, [&] {
-            k_seg_fold<W, T><<<grid_for(nrec), kThreads, 0, s>>>(st->sd, sorted_key, dc, sorted_idx, damp, n32, start, skey, S2,
-                                                                 ne, delta, ptr<uint32_t>(st->is_new), ptr<uint64_t>(st->ins),
-                                                                 ptr<double>(st->seg_sum), sc);
+        launch(st, "seg_fold", nrec * (8.0 + 4.0 + tb), (double)nrec, [&] {
+            k_seg_fold<T><<<grid_for(nrec), kThreads, 0, s>>>(sorted_rank, sorted_idx, ptr<T>(st->damp), n32, start, srank, ne,
+                                                              delta, ptr<uint32_t>(st->is_new), ptr<uint64_t>(st->ins),
+                                                              ptr<double>(st->seg_sum), sc);
         });
         TRY(scan<uint32_t>(st, ptr<uint32_t>(st->is_new), ptr<uint32_t>(st->new_pos), nrec, false));
-        k_new_compact<W><<<grid_for(nrec), kThreads, 0, s>>>(sorted_key, dc, start, ptr<uint32_t>(st->is_new),
-                                                             ptr<uint32_t>(st->new_pos), ptr<uint64_t>(st->ins),
-                                                             ptr<double>(st->seg_sum), ptr<uint64_t>(st->nkey), dc,
+        k_new_compact<W><<<grid_for(nrec), kThreads, 0, s>>>(sorted_rank, sorted_idx, ptr<uint64_t>(st->dkey), dc, start,
+                                                             ptr<uint32_t>(st->is_new), ptr<uint32_t>(st->new_pos),
+                                                             ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum),
+                                                             ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), dc,
                                                              ptr<uint64_t>(st->nins), ptr<double>(st->nsum), sc);
     }
     // merge into the other store buffer, round, compact back into the current buffer
@@ -662,22 +704,26 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     uint64_t *mkey = ptr<uint64_t>(st->skey[m]);
     T *mamp = ptr<T>(st->samp[m]);
     T *mK = ptr<T>(st->sK[m]);
+    uint64_t *mrank = ptr<uint64_t>(st->srank[m]);
     const uint64_t nmax = ne + nrec;
+    const double eb = kb + 2 * tb + 8.0;  // one store entry: key, amplitude, diagonal, rank
     if (nmax) {
-        launch(st, "merge", (double)nmax * 2.0 * (W * 8 + 2 * sizeof(T)), (double)nmax, [&] {
-            k_merge<W, T><<<grid_for(nmax), kThreads, 0, s>>>(st->sd, skey, samp, sK, S2, ne, delta, ptr<uint64_t>(st->nkey),
-                                                              dc, ptr<uint64_t>(st->nins), ptr<double>(st->nsum), mkey, mamp,
-                                                              mK, S2, sc);
+        launch(st, "merge", (double)nmax * 2.0 * eb, (double)nmax, [&] {
+            k_merge<W, T><<<grid_for(nmax), kThreads, 0, s>>>(st->sd, skey, samp, sK, srank, S2, ne, delta,
+                                                              ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), dc,
+                                                              ptr<uint64_t>(st->nins), ptr<double>(st->nsum), mkey, mamp, mK,
+                                                              mrank, S2, sc);
         });
         uint32_t *keep = ptr<uint32_t>(st->keep), *pos = ptr<uint32_t>(st->pos);
-        launch(st, "round", (double)nmax * (2 * sizeof(T) + 4.0), (double)nmax, [&] {
+        launch(st, "round", (double)nmax * (2 * tb + 4.0), (double)nmax, [&] {
             k_round<T><<<grid_for(nmax), kThreads, 0, s>>>(mamp, ne, a, keep, sc);
         });
         TRY(scan<uint32_t>(st, keep, pos, nmax, false));
         TRY(ensure(st, st->abs_part, grid_for(nmax) * sizeof(double)));
-        launch(st, "compact", (double)nmax * 2.0 * (W * 8 + 2 * sizeof(T)), (double)nmax, [&] {
-            k_compact<W, T><<<grid_for(nmax), kThreads, 0, s>>>(mkey, mamp, mK, S2, ne, keep, pos, ptr<uint64_t>(st->skey[c]),
-                                                                ptr<T>(st->samp[c]), ptr<T>(st->sK[c]), S2,
+        launch(st, "compact", (double)nmax * 2.0 * eb, (double)nmax, [&] {
+            k_compact<W, T><<<grid_for(nmax), kThreads, 0, s>>>(mkey, mamp, mK, mrank, S2, ne, keep, pos,
+                                                                ptr<uint64_t>(st->skey[c]), ptr<T>(st->samp[c]),
+                                                                ptr<T>(st->sK[c]), ptr<uint64_t>(st->srank[c]), S2,
                                                                 ptr<double>(st->abs_part), sc);
         });
         k_reduce_partials<<<1, kThreads, 0, s>>>(ptr<double>(st->abs_part), grid_for(nmax), &sc->n_total);
@@ -768,8 +814,8 @@ ccmc_status import_impl(ccmc_state *st, const uint64_t *keys, const double *amps
         HIP_TRY(hipMemcpy2D(st->skey[c].p, cap * sizeof(uint64_t), soa.data(), n * sizeof(uint64_t), n * sizeof(uint64_t), W,
                             hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(st->samp[c].p, ta.data(), n * sizeof(T), hipMemcpyHostToDevice));
-        k_store_diag<W, T><<<grid_for(n), kThreads, 0, st->stream>>>(st->sd, ptr<uint64_t>(st->skey[c]), cap, n,
-                                                                     ptr<T>(st->sK[c]));
+        k_store_init<W, T><<<grid_for(n), kThreads, 0, st->stream>>>(st->sd, ptr<uint64_t>(st->skey[c]), cap, n,
+                                                                     ptr<T>(st->sK[c]), ptr<uint64_t>(st->srank[c]));
         HIP_TRY(hipStreamSynchronize(st->stream));
     }
     st->ne = n;
@@ -880,12 +926,14 @@ void destroy(ccmc_state *st)
     if (!st) return;
     if (st->stream) (void)hipStreamSynchronize(st->stream);
     DevBuf *bufs[] = {&st->t_grid, &st->t_nvec, &st->t_vq, &st->t_h, &st->t_eri, &st->t_fock, &st->t_vpair,
-                      &st->skey[0], &st->skey[1], &st->samp[0], &st->samp[1], &st->sK[0], &st->sK[1], &st->q, &st->P,
-                      &st->delta, &st->ikey, &st->iA, &st->ideath, &st->in, &st->ilevel, &st->icnt, &st->ioff,
-                      &st->num_part, &st->abs_part, &st->rkey, &st->ramp, &st->rid, &st->rcount, &st->boff, &st->dkey,
-                      &st->damp, &st->did, &st->sk[0], &st->sk[1], &st->sidx[0], &st->sidx[1], &st->hist, &st->hoff,
-                      &st->flag, &st->incl, &st->start, &st->is_new, &st->new_pos, &st->ins, &st->seg_sum, &st->nkey,
-                      &st->nins, &st->nsum, &st->keep, &st->pos, &st->scratch};
+                      &st->t_binv, &st->t_bino, &st->skey[0], &st->skey[1], &st->samp[0], &st->samp[1], &st->sK[0],
+                      &st->sK[1], &st->srank[0], &st->srank[1], &st->q, &st->P, &st->guide, &st->delta, &st->ikey,
+                      &st->iA, &st->ideath, &st->in, &st->ilevel, &st->icnt, &st->ioff, &st->num_part, &st->abs_part,
+                      &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->gor, &st->boff, &st->rrank,
+                      &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
+                      &st->sidx[0], &st->sidx[1], &st->hist, &st->hoff, &st->flag, &st->incl, &st->start, &st->is_new,
+                      &st->new_pos, &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->keep,
+                      &st->pos, &st->scratch};
     for (DevBuf *b : bufs) release(st, *b);
     for (auto &b : st->scan_tmp) release(st, b);
     for (auto &p : st->pending) {

@@ -35,6 +35,9 @@ struct SysDev {
     const void *fock;      // [M] f_p = h_pp + sum_{j in HF} <pj||pj> (T)
     const void *vpair;     // [M][M] <pq||pq> (T)
     double p_single;
+    // ranks in the truncated space (see space_rank)
+    const uint64_t *binom_v;  // [(M+1) * 9]: C(n, j), j <= 8
+    const uint64_t *binom_o;  // [(N+1) * (N+1)]: C(n, k), saturating
 };
 
 // ------------------------------------------------------------------ Philox4x32-10
@@ -311,6 +314,39 @@ __device__ __forceinline__ T diagonal(const SysDev &S, const uint64_t *d)
     for (int a = 0; a < np; ++a)
         for (int i = 0; i < nh; ++i) k -= V[part[a] * M + hole[i]];
     return k;
+}
+
+// Rank of a determinant among all determinants with N electrons and excitation level <= l,
+// in ascending bitstring order: the number of such D' < D.  Walking the set bits of D from
+// the top, D' agrees with D above bit p, has p empty, and places the remaining k electrons
+// below p: j of them in the virtual orbitals [N, p) and k - j in [0, min(p, N)), with at most
+// l - v virtual ones in total (v = virtual electrons of D above p).  The rank is monotone in
+// the key order, so sorting records by rank groups equal determinants and keeps the store's
+// key order, with ceil(log2(space)) bits instead of M.
+template <int W>
+__device__ __forceinline__ uint64_t space_rank(const SysDev &S, const uint64_t *d)
+{
+    const int N = S.nel, l = S.l;
+    uint64_t r = 0;
+    int a = 0, v = 0;
+#pragma unroll
+    for (int w = W - 1; w >= 0; --w) {
+        uint64_t m = d[w];
+        while (m) {
+            const int p = 64 * w + 63 - __clzll((long long)m);
+            m &= ~(1ull << (p & 63));
+            const int k = N - a;
+            const int nv = p > N ? p - N : 0, no = p < N ? p : N;
+            const int jmax = (l - v) < k ? (l - v) : k;
+            for (int j = 0; j <= jmax; ++j) {
+                if (k - j > no) continue;
+                r += S.binom_v[nv * 9 + j] * S.binom_o[no * (N + 1) + (k - j)];
+            }
+            ++a;
+            v += (p >= N) ? 1 : 0;
+        }
+    }
+    return r;
 }
 
 // Cluster-size distribution: p(s) = 2^-(s-lo+1) for lo <= s < hi, the remainder at hi.

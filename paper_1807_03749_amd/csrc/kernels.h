@@ -17,8 +17,8 @@
 
 namespace ccmc {
 
-constexpr int kGenRounds = 4;                       // rounds of 256 slots per block
-constexpr int kGenSlots = kThreads * kGenRounds;    // slots (and record capacity) per block
+constexpr int kGenRounds = 4;                       // rounds of 256 slots per generation block
+constexpr int kGenSlots = kThreads * kGenRounds;    // slots (and region capacity) per block
 
 // Device-side scalars of one step.
 struct Scratch {
@@ -29,11 +29,15 @@ struct Scratch {
     uint64_t n_spawns;
     uint64_t n_deaths;
     uint64_t max_n;
-    uint64_t diffmask[kMaxWords];
+    uint64_t n_rec;           // records emitted by the step
+    uint64_t rank_or;         // OR of all record ranks (digits that can vary)
+    uint64_t guide_n;         // entries of the selection guide table
+    uint32_t guide_shift;
     uint32_t n_seg;
     uint32_t n_new;
     uint32_t hf_hit;
     uint32_t n_out;
+    uint32_t pad;
     double hf_sum;
     double n_total;
     double num;
@@ -94,10 +98,36 @@ __global__ void __launch_bounds__(kThreads) k_weights(const T *__restrict__ amp,
     q[i] = (uint64_t)fmin(w, 0x1.0p60);
 }
 
-__global__ void k_qtot(const uint64_t *__restrict__ P, uint64_t n, Scratch *sc)
+// Q and the guide table of the excitor draws.  A draw r in [0, Q) falls in bucket r >> shift;
+// guide[b] is the first excitor whose prefix exceeds b << shift, so the drawn excitor lies
+// in [guide[b], guide[b+1]] -- a short search instead of one over the whole store.  With
+// about two buckets per excitor the range is usually a single entry.
+__global__ void k_guide_setup(const uint64_t *__restrict__ P, uint64_t n, Scratch *sc)
 {
-    sc->qtot = n ? P[n - 1] : 0;
-    if (sc->qtot > (1ull << 53)) atomicOr((unsigned long long *)&sc->err, 1ull);
+    const uint64_t Q = n ? P[n - 1] : 0;
+    sc->qtot = Q;
+    if (Q > (1ull << 53)) atomicOr((unsigned long long *)&sc->err, 1ull);
+    uint32_t sh = 0;
+    while (sh < 63 && (Q >> sh) + 2 > 2 * n + 2) ++sh;
+    sc->guide_shift = sh;
+    sc->guide_n = n ? (Q >> sh) + 2 : 0;
+}
+
+__global__ void __launch_bounds__(kThreads) k_guide(const uint64_t *__restrict__ P, uint64_t n, const Scratch *sc,
+                                                    uint32_t *__restrict__ guide)
+{
+    const uint64_t b = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (b >= sc->guide_n) return;
+    const uint64_t x = b << sc->guide_shift;
+    uint64_t l0 = 0, h0 = n;  // first i with P[i] > x
+    while (l0 < h0) {
+        const uint64_t mid = (l0 + h0) >> 1;
+        if (P[mid] > x)
+            h0 = mid;
+        else
+            l0 = mid + 1;
+    }
+    guide[b] = (uint32_t)(l0 < n ? l0 : n - 1);
 }
 
 // ------------------------------------------------------- non-composite items (FNC)
@@ -160,15 +190,17 @@ __global__ void __launch_bounds__(kThreads) k_noncomposite(SysDev S, const uint6
 // reference one operator at a time; a repeated hole or particle makes it vanish.
 template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_select(SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
-                                                     uint64_t sstride, uint64_t ne, const uint64_t *__restrict__ P, double n0,
-                                                     StepArgs a, Items<T> it, uint64_t item_base,
-                                                     double *__restrict__ num_part, Scratch *sc)
+                                                     uint64_t sstride, uint64_t ne, const uint64_t *__restrict__ P,
+                                                     const uint32_t *__restrict__ guide, double n0, StepArgs a,
+                                                     Items<T> it, uint64_t item_base, double *__restrict__ num_part,
+                                                     Scratch *sc)
 {
     const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     double num = 0.0;
     uint64_t att = 0, disc = 0, mx = 0;
     if (k < a.n_sel) {
         const uint64_t Q = sc->qtot;
+        const uint32_t gsh = sc->guide_shift;
         Draws r(a.key0, a.key1, kSelect, (uint32_t)k, 0u, a.step);
         const int lo = a.fnc ? 2 : 0, hi = S.l + 2;
         const int s = draw_size(uniform53(r.get(0)), lo, hi);
@@ -176,7 +208,8 @@ __global__ void __launch_bounds__(kThreads) k_select(SysDev S, const uint64_t *_
         bool ok = !(s > 0 && Q == 0);
         for (int c = 0; c < s && ok; ++c) {
             const uint64_t x = below(r.get(1 + c), Q);
-            uint64_t l0 = 0, h0 = ne;  // first i with P[i] > x
+            const uint64_t gb = x >> gsh;
+            uint64_t l0 = guide[gb], h0 = (uint64_t)guide[gb + 1] + 1;  // first i with P[i] > x
             while (l0 < h0) {
                 const uint64_t mid = (l0 + h0) >> 1;
                 if (P[mid] > x)
@@ -272,14 +305,15 @@ __global__ void __launch_bounds__(kThreads) k_select(SysDev S, const uint64_t *_
 }
 
 // ----------------------------------------------------------------- generation
-// Records of one block of kGenSlots consecutive slots, compacted in slot order into the
-// block's own region.  Slot order is record-id order, so the stable sort that follows
-// keeps every determinant's contributions in id order.
+// Records of one block of kGenSlots consecutive slots are compacted, in slot order, into
+// the block's own region; a scan of the block counts and a gather then lay them out densely.
+// Slot order is record-id order, so the stable sort that follows keeps every
+// determinant's contributions in id order.
 struct Records {
-    uint64_t *key;     // SoA, stride = region capacity
+    uint64_t *rank;    // rank of the target in the truncated space
+    uint64_t *key;     // SoA target bitstrings, stride `stride`
     void *amp;         // T
-    uint64_t *id;      // optional
-    uint32_t *count;   // per block
+    uint64_t *id;      // optional record ids
     uint64_t stride;
 };
 
@@ -362,51 +396,81 @@ __device__ __forceinline__ bool spawn_attempt(const SysDev &S, const uint64_t *d
     return true;
 }
 
+// First item of each generation block (last item whose offset is <= the block's first slot);
+// entry n_blocks holds the item of the last slot.
+__global__ void __launch_bounds__(kThreads) k_block_items(const uint64_t *__restrict__ off, uint64_t n_items, uint64_t n_blocks,
+                                                          uint64_t n_slots, uint64_t *__restrict__ block_item)
+{
+    const uint64_t u = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (u > n_blocks) return;
+    const uint64_t g = u < n_blocks ? u * kGenSlots : n_slots - 1;
+    uint64_t l0 = 0, h0 = n_items + 1;
+    while (l0 < h0) {
+        const uint64_t mid = (l0 + h0) >> 1;
+        if (off[mid] > g)
+            h0 = mid;
+        else
+            l0 = mid + 1;
+    }
+    block_item[u] = l0 - 1;
+}
+
+constexpr int kGenLdsItems = 2048;
+
+// Per-block statistics of the generation kernel (no single-address atomics).
+struct GenStats {
+    uint32_t *count;    // records of each block
+    uint32_t *spawns;
+    uint32_t *deaths;
+    uint64_t *rank_or;
+};
+
 template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, const uint64_t *__restrict__ off,
-                                                       uint64_t n_items, uint64_t n_fnc, uint64_t n_slots, StepArgs a,
-                                                       Records rec, int keep_ids, Scratch *sc)
+                                                       const uint64_t *__restrict__ block_item, uint64_t n_fnc,
+                                                       uint64_t n_slots, StepArgs a, Records rec, int keep_ids, GenStats gs)
 {
-    __shared__ uint64_t item_lo, item_hi;
+    __shared__ uint64_t s_off[kGenLdsItems + 1];
     __shared__ uint32_t wave_tot[kWaves];
-    const uint64_t g0 = (uint64_t)blockIdx.x * kGenSlots;
-    if (threadIdx.x == 0) {
-        // items covering this block's slots: last item with off <= g
-        auto find = [&](uint64_t g) {
-            uint64_t l0 = 0, h0 = n_items + 1;
-            while (l0 < h0) {
-                const uint64_t mid = (l0 + h0) >> 1;
-                if (off[mid] > g)
-                    h0 = mid;
-                else
-                    l0 = mid + 1;
-            }
-            return l0 - 1;
-        };
-        item_lo = find(g0);
-        const uint64_t gl = (g0 + kGenSlots - 1 < n_slots) ? g0 + kGenSlots - 1 : n_slots - 1;
-        item_hi = find(gl);
-    }
-    __syncthreads();
-    const uint64_t lo = item_lo, hi = item_hi;
-    uint32_t base = 0, spawns = 0, deaths = 0;
+    __shared__ uint64_t wave_or[kWaves];
     T *ramp = static_cast<T *>(rec.amp);
+    const uint64_t g0 = (uint64_t)blockIdx.x * kGenSlots;
+    const uint64_t lo = block_item[blockIdx.x], hi = block_item[blockIdx.x + 1];
+    const bool lds = hi - lo + 1 <= (uint64_t)kGenLdsItems;
+    if (lds)
+        for (uint64_t t = threadIdx.x; t <= hi - lo + 1; t += kThreads) s_off[t] = off[lo + t];
+    __syncthreads();
+    uint32_t base = 0, spawns = 0, deaths = 0;
+    uint64_t rank_or = 0;
     for (int rd = 0; rd < kGenRounds; ++rd) {
         const uint64_t g = g0 + (uint64_t)rd * kThreads + threadIdx.x;
         bool emit = false;
         uint64_t tgt[W];
         T x = T(0);
-        uint64_t id = 0;
+        uint64_t id = 0, rk = 0;
         if (g < n_slots) {
-            uint64_t l0 = lo, h0 = hi + 1;
-            while (l0 < h0) {
-                const uint64_t mid = (l0 + h0) >> 1;
-                if (off[mid] > g)
-                    h0 = mid;
-                else
-                    l0 = mid + 1;
+            uint64_t item;
+            if (lds) {  // last item in [lo, hi] whose offset is <= g, searched in LDS
+                uint32_t l0 = 0, h0 = (uint32_t)(hi - lo + 1);
+                while (l0 < h0) {
+                    const uint32_t mid = (l0 + h0) >> 1;
+                    if (s_off[mid] > g)
+                        h0 = mid;
+                    else
+                        l0 = mid + 1;
+                }
+                item = lo + l0 - 1;
+            } else {
+                uint64_t l0 = lo, h0 = hi + 1;
+                while (l0 < h0) {
+                    const uint64_t mid = (l0 + h0) >> 1;
+                    if (off[mid] > g)
+                        h0 = mid;
+                    else
+                        l0 = mid + 1;
+                }
+                item = l0 - 1;
             }
-            const uint64_t item = l0 - 1;
             const uint32_t slot = (uint32_t)(g - off[item]);
             const bool nc = item < n_fnc;
             const uint32_t k = (uint32_t)(nc ? item : item - n_fnc);
@@ -426,6 +490,10 @@ __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, co
                                            slot - 1, a, tgt, x);
                 spawns += emit ? 1u : 0u;
             }
+            if (emit) {
+                rk = space_rank<W>(S, tgt);
+                rank_or |= rk;
+            }
             id = ((nc ? 0ull : 1ull) << 62) | ((uint64_t)k << 30) | (uint64_t)slot;
         }
         // compaction in slot order
@@ -440,6 +508,7 @@ __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, co
         }
         if (emit) {
             const uint64_t dst = g0 + base + before + (uint32_t)lanes_below(m);
+            rec.rank[dst] = rk;
 #pragma unroll
             for (int w = 0; w < W; ++w) rec.key[(uint64_t)w * rec.stride + dst] = tgt[w];
             ramp[dst] = x;
@@ -448,60 +517,80 @@ __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, co
         base += total;
         __syncthreads();
     }
-    if (threadIdx.x == 0) rec.count[blockIdx.x] = base;
-    const uint64_t bs = block_reduce_sum((uint64_t)spawns);
-    const uint64_t bd = block_reduce_sum((uint64_t)deaths);
+    const uint32_t bs = block_reduce_sum(spawns);
+    const uint32_t bd = block_reduce_sum(deaths);
+    uint64_t ro = rank_or;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ro |= __shfl_xor(ro, o, 64);
+    if (lane_id() == 0) wave_or[wave_id()] = ro;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        atomicAdd((unsigned long long *)&sc->n_spawns, (unsigned long long)bs);
-        atomicAdd((unsigned long long *)&sc->n_deaths, (unsigned long long)bd);
+        gs.count[blockIdx.x] = base;
+        gs.spawns[blockIdx.x] = bs;
+        gs.deaths[blockIdx.x] = bd;
+        gs.rank_or[blockIdx.x] = wave_or[0] | wave_or[1] | wave_or[2] | wave_or[3];
     }
 }
 
-// Concatenate the regions: block b's records go to off[b] ...  Also ORs the bits in which
-// any record differs from the reference, so that the sort skips constant digits.
-template <int W, typename T>
-__global__ void __launch_bounds__(kThreads) k_gather(const SysDev S, Records rec, const uint64_t *__restrict__ boff,
-                                                     uint64_t *__restrict__ key, T *__restrict__ amp, uint64_t *__restrict__ ids,
-                                                     uint64_t stride, int keep_ids, Scratch *sc)
+// Sums of the per-block generation statistics (one block).
+__global__ void __launch_bounds__(kThreads) k_gen_stats(GenStats gs, const uint32_t *__restrict__ boff, uint64_t n_blocks,
+                                                        Scratch *sc)
 {
-    const uint32_t cnt = rec.count[blockIdx.x];
-    const uint64_t src0 = (uint64_t)blockIdx.x * kGenSlots, dst0 = boff[blockIdx.x];
-    const T *ramp = static_cast<const T *>(rec.amp);
-    uint64_t diff[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) diff[w] = 0;
-    for (uint32_t i = threadIdx.x; i < cnt; i += kThreads) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            const uint64_t v = rec.key[(uint64_t)w * rec.stride + src0 + i];
-            key[(uint64_t)w * stride + dst0 + i] = v;
-            diff[w] |= v ^ S.hf[w];
-        }
-        amp[dst0 + i] = ramp[src0 + i];
-        if (keep_ids) ids[dst0 + i] = rec.id[src0 + i];
+    uint64_t sp = 0, de = 0, ro = 0;
+    for (uint64_t b = threadIdx.x; b < n_blocks; b += kThreads) {
+        sp += gs.spawns[b];
+        de += gs.deaths[b];
+        ro |= gs.rank_or[b];
     }
+    sp = block_reduce_sum(sp);
+    de = block_reduce_sum(de);
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-        uint64_t v = diff[w];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
-        if (lane_id() == 0 && v) atomicOr((unsigned long long *)&sc->diffmask[w], (unsigned long long)v);
+    for (int o = 32; o > 0; o >>= 1) ro |= __shfl_xor(ro, o, 64);
+    __shared__ uint64_t wo[kWaves];
+    if (lane_id() == 0) wo[wave_id()] = ro;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sc->n_spawns = sp;
+        sc->n_deaths = de;
+        sc->rank_or = wo[0] | wo[1] | wo[2] | wo[3];
+        sc->n_rec = boff[n_blocks];
     }
+}
+
+// Dense layout of the records: output position r comes from the block b with
+// boff[b] <= r < boff[b+1], at slot position r - boff[b] of its region.
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_gather(Records reg, const uint32_t *__restrict__ boff, uint64_t n_blocks,
+                                                     Records out, int keep_ids, const Scratch *sc)
+{
+    const uint64_t r = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= sc->n_rec) return;
+    uint64_t l0 = 0, h0 = n_blocks + 1;  // last b with boff[b] <= r
+    while (l0 < h0) {
+        const uint64_t mid = (l0 + h0) >> 1;
+        if (boff[mid] > r)
+            h0 = mid;
+        else
+            l0 = mid + 1;
+    }
+    const uint64_t b = l0 - 1;
+    const uint64_t src = b * kGenSlots + (r - boff[b]);
+    out.rank[r] = reg.rank[src];
+#pragma unroll
+    for (int w = 0; w < W; ++w) out.key[(uint64_t)w * out.stride + r] = reg.key[(uint64_t)w * reg.stride + src];
+    static_cast<T *>(out.amp)[r] = static_cast<const T *>(reg.amp)[src];
+    if (keep_ids) out.id[r] = reg.id[src];
 }
 
 // ---------------------------------------------------------------- annihilation
-template <int W>
-__global__ void __launch_bounds__(kThreads) k_seg_flags(const uint64_t *__restrict__ key, uint64_t stride, uint32_t n,
+// Records are sorted by rank (equal ranks = equal determinants, ascending rank = ascending
+// key).  Segment heads:
+__global__ void __launch_bounds__(kThreads) k_seg_flags(const uint64_t *__restrict__ rank, uint32_t n,
                                                         uint32_t *__restrict__ flag)
 {
     const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
     if (r >= n) return;
-    bool head = (r == 0);
-    if (!head) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) head |= key[(uint64_t)w * stride + r] != key[(uint64_t)w * stride + r - 1];
-    }
-    flag[r] = head ? 1u : 0u;
+    flag[r] = (r == 0 || rank[r] != rank[r - 1]) ? 1u : 0u;
 }
 
 __global__ void __launch_bounds__(kThreads) k_seg_starts(const uint32_t *__restrict__ flag, const uint32_t *__restrict__ incl,
@@ -513,16 +602,15 @@ __global__ void __launch_bounds__(kThreads) k_seg_starts(const uint32_t *__restr
     if (r == n - 1) sc->n_seg = incl[r];
 }
 
-// One lane per determinant: left fold of its records in id order (they are contiguous and
-// in id order after the stable sort), then look it up in the store.  A hit adds to that
-// entry, the reference adds to N_0, a miss becomes a new excitor at insertion point ins.
-template <int W, typename T>
-__global__ void __launch_bounds__(kThreads) k_seg_fold(const SysDev S, const uint64_t *__restrict__ key, uint64_t stride,
-                                                       const uint32_t *__restrict__ idx, const T *__restrict__ ramp, uint32_t n,
-                                                       const uint32_t *__restrict__ start, const uint64_t *__restrict__ skey,
-                                                       uint64_t sstride, uint64_t ne, double *__restrict__ delta,
-                                                       uint32_t *__restrict__ is_new, uint64_t *__restrict__ ins,
-                                                       double *__restrict__ seg_sum, Scratch *sc)
+// One lane per determinant: left fold of its records in id order (contiguous and in id
+// order after the stable sort), then a binary search of its rank in the store.  A hit adds
+// to that entry, the reference (rank 0) adds to N_0, a miss becomes a new excitor.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_seg_fold(const uint64_t *__restrict__ rank, const uint32_t *__restrict__ idx,
+                                                       const T *__restrict__ ramp, uint32_t n, const uint32_t *__restrict__ start,
+                                                       const uint64_t *__restrict__ srank, uint64_t ne,
+                                                       double *__restrict__ delta, uint32_t *__restrict__ is_new,
+                                                       uint64_t *__restrict__ ins, double *__restrict__ seg_sum, Scratch *sc)
 {
     const uint32_t s = blockIdx.x * kThreads + threadIdx.x;
     const uint32_t nseg = sc->n_seg;
@@ -530,34 +618,22 @@ __global__ void __launch_bounds__(kThreads) k_seg_fold(const SysDev S, const uin
     const uint32_t r0 = start[s], r1 = (s + 1 < nseg) ? start[s + 1] : n;
     double acc = (double)ramp[idx[r0]];
     for (uint32_t r = r0 + 1; r < r1; ++r) acc += (double)ramp[idx[r]];
-    uint64_t d[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) d[w] = key[(uint64_t)w * stride + r0];
+    const uint64_t rk = rank[r0];
     uint32_t fresh = 0;
     uint64_t pos = 0;
-    if (key_equal<W>(d, S.hf)) {
+    if (rk == 0) {
         sc->hf_sum = acc;
         sc->hf_hit = 1;
     } else {
-        uint64_t l0 = 0, h0 = ne;  // first store entry >= d
+        uint64_t l0 = 0, h0 = ne;  // first store entry with rank >= rk
         while (l0 < h0) {
             const uint64_t mid = (l0 + h0) >> 1;
-            uint64_t e[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) e[w] = skey[(uint64_t)w * sstride + mid];
-            if (key_cmp<W>(e, d) < 0)
+            if (srank[mid] < rk)
                 l0 = mid + 1;
             else
                 h0 = mid;
         }
-        bool found = false;
-        if (l0 < ne) {
-            uint64_t e[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) e[w] = skey[(uint64_t)w * sstride + l0];
-            found = key_equal<W>(e, d);
-        }
-        if (found)
+        if (l0 < ne && srank[l0] == rk)
             delta[l0] = acc;
         else
             fresh = 1;
@@ -569,12 +645,13 @@ __global__ void __launch_bounds__(kThreads) k_seg_fold(const SysDev S, const uin
 }
 
 template <int W>
-__global__ void __launch_bounds__(kThreads) k_new_compact(const uint64_t *__restrict__ key, uint64_t stride,
+__global__ void __launch_bounds__(kThreads) k_new_compact(const uint64_t *__restrict__ rank, const uint32_t *__restrict__ idx,
+                                                          const uint64_t *__restrict__ rkey, uint64_t rstride,
                                                           const uint32_t *__restrict__ start, const uint32_t *__restrict__ is_new,
                                                           const uint32_t *__restrict__ new_pos, const uint64_t *__restrict__ ins,
                                                           const double *__restrict__ seg_sum, uint64_t *__restrict__ nkey,
-                                                          uint64_t nstride, uint64_t *__restrict__ nins, double *__restrict__ nsum,
-                                                          Scratch *sc)
+                                                          uint64_t *__restrict__ nrank, uint64_t nstride,
+                                                          uint64_t *__restrict__ nins, double *__restrict__ nsum, Scratch *sc)
 {
     const uint32_t s = blockIdx.x * kThreads + threadIdx.x;
     const uint32_t nseg = sc->n_seg;
@@ -582,8 +659,11 @@ __global__ void __launch_bounds__(kThreads) k_new_compact(const uint64_t *__rest
     if (s == nseg - 1) sc->n_new = new_pos[s] + is_new[s];
     if (!is_new[s]) return;
     const uint32_t j = new_pos[s];
+    const uint32_t r0 = start[s];
+    const uint32_t src = idx[r0];  // any record of the segment carries its bitstring
 #pragma unroll
-    for (int w = 0; w < W; ++w) nkey[(uint64_t)w * nstride + j] = key[(uint64_t)w * stride + start[s]];
+    for (int w = 0; w < W; ++w) nkey[(uint64_t)w * nstride + j] = rkey[(uint64_t)w * rstride + src];
+    nrank[j] = rank[r0];
     nins[j] = ins[s];
     nsum[j] = seg_sum[s];
 }
@@ -592,11 +672,13 @@ __global__ void __launch_bounds__(kThreads) k_new_compact(const uint64_t *__rest
 // Store entry i lands at i + #(new with ins <= i); new entry j at ins_j + j.
 template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_merge(const SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
-                                                    const T *__restrict__ sK, uint64_t sstride, uint64_t ne,
-                                                    const double *__restrict__ delta, const uint64_t *__restrict__ nkey,
+                                                    const T *__restrict__ sK, const uint64_t *__restrict__ srank,
+                                                    uint64_t sstride, uint64_t ne, const double *__restrict__ delta,
+                                                    const uint64_t *__restrict__ nkey, const uint64_t *__restrict__ nrank,
                                                     uint64_t nstride, const uint64_t *__restrict__ nins,
                                                     const double *__restrict__ nsum, uint64_t *__restrict__ mkey,
-                                                    T *__restrict__ mamp, T *__restrict__ mK, uint64_t mstride, Scratch *sc)
+                                                    T *__restrict__ mamp, T *__restrict__ mK, uint64_t *__restrict__ mrank,
+                                                    uint64_t mstride, Scratch *sc)
 {
     const uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     const uint64_t nn = sc->n_new;
@@ -615,6 +697,7 @@ __global__ void __launch_bounds__(kThreads) k_merge(const SysDev S, const uint64
         for (int w = 0; w < W; ++w) mkey[(uint64_t)w * mstride + pos] = skey[(uint64_t)w * sstride + t];
         mamp[pos] = (T)((double)samp[t] + delta[t]);
         mK[pos] = sK[t];
+        mrank[pos] = srank[t];
     } else {
         const uint64_t j = t - ne;
         const uint64_t pos = nins[j] + j;
@@ -626,6 +709,7 @@ __global__ void __launch_bounds__(kThreads) k_merge(const SysDev S, const uint64
         }
         mamp[pos] = (T)nsum[j];
         mK[pos] = diagonal<W, T>(S, d);
+        mrank[pos] = nrank[j];
     }
 }
 
@@ -650,9 +734,10 @@ __global__ void __launch_bounds__(kThreads) k_round(T *__restrict__ amp, uint64_
 
 template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_compact(const uint64_t *__restrict__ mkey, const T *__restrict__ mamp,
-                                                      const T *__restrict__ mK, uint64_t mstride, uint64_t ne,
-                                                      const uint32_t *__restrict__ keep, const uint32_t *__restrict__ pos,
-                                                      uint64_t *__restrict__ okey, T *__restrict__ oamp, T *__restrict__ oK,
+                                                      const T *__restrict__ mK, const uint64_t *__restrict__ mrank,
+                                                      uint64_t mstride, uint64_t ne, const uint32_t *__restrict__ keep,
+                                                      const uint32_t *__restrict__ pos, uint64_t *__restrict__ okey,
+                                                      T *__restrict__ oamp, T *__restrict__ oK, uint64_t *__restrict__ orank,
                                                       uint64_t ostride, double *__restrict__ abs_part, Scratch *sc)
 {
     const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -664,6 +749,7 @@ __global__ void __launch_bounds__(kThreads) k_compact(const uint64_t *__restrict
         for (int w = 0; w < W; ++w) okey[(uint64_t)w * ostride + p] = mkey[(uint64_t)w * mstride + k];
         oamp[p] = mamp[k];
         oK[p] = mK[k];
+        orank[p] = mrank[k];
         a = fabs((double)mamp[k]);
     }
     if (k == n - 1) sc->n_out = pos[k] + keep[k];
@@ -680,12 +766,6 @@ __global__ void __launch_bounds__(kThreads) k_reduce_partials(const double *__re
     if (threadIdx.x == 0) *out = s;
 }
 
-__global__ void k_widen(const uint32_t *__restrict__ c32, uint64_t *__restrict__ c64, uint64_t n)
-{
-    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i < n) c64[i] = c32[i];
-}
-
 template <typename V>
 __global__ void k_fill(V *p, uint64_t n, V v)
 {
@@ -693,10 +773,10 @@ __global__ void k_fill(V *p, uint64_t n, V v)
     if (i < n) p[i] = v;
 }
 
-// Diagonal of imported / new store entries.
+// Diagonal and truncated-space rank of imported store entries.
 template <int W, typename T>
-__global__ void __launch_bounds__(kThreads) k_store_diag(const SysDev S, const uint64_t *__restrict__ key, uint64_t stride,
-                                                         uint64_t n, T *__restrict__ K)
+__global__ void __launch_bounds__(kThreads) k_store_init(const SysDev S, const uint64_t *__restrict__ key, uint64_t stride,
+                                                         uint64_t n, T *__restrict__ K, uint64_t *__restrict__ rank)
 {
     const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
@@ -704,6 +784,7 @@ __global__ void __launch_bounds__(kThreads) k_store_diag(const SysDev S, const u
 #pragma unroll
     for (int w = 0; w < W; ++w) d[w] = key[(uint64_t)w * stride + i];
     K[i] = diagonal<W, T>(S, d);
+    rank[i] = space_rank<W>(S, d);
 }
 
 // (PQ|RS) = sum_L B_LPQ B_LRS (the Cholesky-built two-electron table), summed over L in order.

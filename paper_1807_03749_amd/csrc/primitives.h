@@ -122,6 +122,47 @@ __global__ void __launch_bounds__(kThreads) k_scan_tile(const V *__restrict__ in
     }
 }
 
+// One block scans up to a few tiles in sequence, carrying the running total: one launch
+// instead of three for the small scans of a step (radix histograms, flags of short lists).
+template <typename V>
+__global__ void __launch_bounds__(kThreads) k_scan_small(const V *__restrict__ in, V *__restrict__ out, uint64_t n,
+                                                         int inclusive)
+{
+    __shared__ V buf[kScanTile];
+    V carry = 0;
+    for (uint64_t base = 0; base < n; base += kScanTile) {
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint64_t g = base + (uint64_t)i * kThreads + threadIdx.x;
+            buf[i * kThreads + threadIdx.x] = (g < n) ? in[g] : V(0);
+        }
+        __syncthreads();
+        V loc[kScanItems];
+        V sum = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            loc[i] = buf[threadIdx.x * kScanItems + i];
+            sum += loc[i];
+        }
+        V total;
+        V run = block_exclusive_scan(sum, &total) + carry;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const V x = loc[i];
+            buf[threadIdx.x * kScanItems + i] = inclusive ? run + x : run;
+            run += x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint64_t g = base + (uint64_t)i * kThreads + threadIdx.x;
+            if (g < n) out[g] = buf[i * kThreads + threadIdx.x];
+        }
+        carry += total;
+        __syncthreads();
+    }
+}
+
 // ----------------------------------------------------------------- radix sort
 // Keys are W words in SoA layout (word w of item i at key[w * stride + i]).  One pass sorts
 // by the 8-bit digit at bit `shift` of word `word`, stably.

@@ -103,7 +103,7 @@ def test_first_step_from_empty_store_and_zero_selections():
 def test_edge_options():
     """No rounding at all (zero cutoff and threshold) and very large multi-spawn counts."""
     S, R, g = make_pair("ueg", 14, 2, dict(full_noncomposite=True, spawn_cutoff=0.0, occupation_threshold=0.0,
-                                           min_spawn_attempts=1, multispawn_threshold=0.002, init_pop=100.0, seed=5),
+                                           min_spawn_attempts=1, multispawn_threshold=0.002, noncomposite_threshold=0.05, init_pop=100.0, seed=5),
                         n2_max=2)
     st = evolve_oracle(R, 6, 0.005, 100)
     gs, os_ = compare_step(S, R, g, 0.005, 0.0, int(round(st["n_total"])))
@@ -113,7 +113,7 @@ def test_edge_options():
 
 def test_attempt_overflow_rolls_back():
     """More than 2^30-2 attempts on one cluster: EOVERFLOW and the state is unchanged."""
-    S, R, g = make_pair("ueg", 14, 2, dict(full_noncomposite=True, multispawn_threshold=1e-9, init_pop=10.0), n2_max=2)
+    S, R, g = make_pair("ueg", 14, 2, dict(full_noncomposite=True, noncomposite_threshold=1e-9, init_pop=10.0), n2_max=2)
     before = g.ccmc_export()
     with pytest.raises(ccmc.CCMCError) as e:
         g.ccmc_step(0.005, 0.0, 10)
