@@ -41,6 +41,48 @@ HBM_KERNELS = {"radix_scatter", "radix_hist", "gather", "seg_fold", "merge", "co
                "noncomposite"}
 
 
+class _Roctx:
+    """roctxProfilerResume/Pause around the timed steps, so that a profiler started with
+    --selected-regions sees exactly the timed region (no-op without a profiler)."""
+
+    def __init__(self, enabled: bool):
+        self.lib = None
+        if enabled:
+            import ctypes
+            for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so", "libroctx64.so"):
+                try:
+                    self.lib = ctypes.CDLL(name)
+                    break
+                except OSError:
+                    continue
+
+    def resume(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerResume(0)
+
+    def pause(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerPause(0)
+
+
+ROCTX = _Roctx(False)
+
+
+def calibrate_copy(gib: float = 1.0, reps: int = 5):
+    """A plain device-to-device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    ROCTX.resume()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    ROCTX.pause()
+    print(json.dumps({"calibrate_copy_bytes": n * 4, "reps": reps}))
+
+
 def make_state(w: inputs.Workload, precision: str, init_pop: float):
     kw = dict(precision=precision, full_noncomposite=int(w.full_noncomposite),
               min_spawn_attempts=w.min_spawn_attempts, multispawn_threshold=w.multispawn_threshold,
@@ -82,6 +124,7 @@ def run_leg(w: inputs.Workload, precision: str, steps: int, warmup: int, log, pr
         state.ccmc_profile(True)
         state.ccmc_profile_read()
     attempts = selections = spawns = 0
+    ROCTX.resume()
     t0 = time.perf_counter()
     for _ in range(steps):
         st = state.ccmc_step(w.tau, ctl.shift, nsel)
@@ -91,6 +134,7 @@ def run_leg(w: inputs.Workload, precision: str, steps: int, warmup: int, log, pr
         selections += st["n_selections"]
         spawns += st["n_spawns"]
     elapsed = time.perf_counter() - t0
+    ROCTX.pause()
     prof = state.ccmc_profile_read() if profile else {}
     state.ccmc_profile(False)
     keys, amps, n0, step = state.ccmc_export()
@@ -203,7 +247,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--roctx-region", action="store_true",
+                    help="mark the timed steps for a profiler run with --selected-regions")
+    ap.add_argument("--no-kernel-timing", action="store_true", help="no HIP-event timing in the timed region")
+    ap.add_argument("--calibrate-copy", action="store_true", help="only run a 1 GiB device copy (counter scaling)")
     args = ap.parse_args()
+    global ROCTX
+    ROCTX = _Roctx(args.roctx_region)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU only "
               f"(the multi-GPU design is described, not built)", file=sys.stderr)
@@ -211,7 +264,7 @@ def main():
     log = (lambda m: None) if args.quiet else (lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     w = inputs.WORKLOADS[args.workload]
     log(f"workload {w.name} precision {args.precision}: growing to {w.target_population:.0e}")
-    main_leg = run_leg(w, args.precision, args.steps, args.warmup, log)
+    main_leg = run_leg(w, args.precision, args.steps, args.warmup, log, profile=not args.no_kernel_timing)
     value = main_leg["attempts"] / main_leg["seconds"]
     log(f"{args.precision}: {value:.4e} attempts/s, {1e3 * main_leg['seconds'] / args.steps:.3f} ms/step")
     for k, p in sorted(main_leg["profile"].items(), key=lambda kv: -kv[1]["ms"]):

@@ -80,9 +80,9 @@ struct ccmc_state {
     DevBuf q, P, guide, delta;
     DevBuf ikey, iA, ideath, in, ilevel, icnt, ioff;
     uint64_t icap = 0;
-    DevBuf num_part, abs_part;
-    DevBuf block_item, gcount, gspawn, gdeath, gor, boff;
-    DevBuf rrank, rkey, ramp, rid;  // per-block record regions
+    DevBuf num_part, att_part, disc_part, max_part, abs_part;
+    DevBuf block_item, gcount, gspawn, gdeath, boff;
+    DevBuf rkey, ramp, rid;  // per-block record regions
     uint64_t rcap = 0;              // region slots
     DevBuf drank, dkey, damp, did, sr[2], sidx[2], hist, hoff;
     DevBuf flag, incl, start, is_new, new_pos, ins, seg_sum, nkey, nrank, nins, nsum, keep, pos;
@@ -549,23 +549,30 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     Items<T> it{ptr<uint64_t>(st->ikey), ptr<T>(st->iA), ptr<T>(st->ideath), ptr<uint32_t>(st->in),
                 ptr<uint8_t>(st->ilevel), ptr<uint64_t>(st->icnt), st->icap};
     const unsigned nb_fnc = fnc ? grid_for(n_fnc) : 0, nb_sel = n_sel ? grid_for(n_sel) : 0;
-    TRY(ensure(st, st->num_part, (size_t)(nb_fnc + nb_sel + 1) * sizeof(double)));
-    double *num_part = ptr<double>(st->num_part);
+    const size_t nparts = (size_t)(nb_fnc + nb_sel + 1);
+    TRY(ensure(st, st->num_part, nparts * sizeof(double)));
+    TRY(ensure(st, st->att_part, nparts * sizeof(uint64_t)));
+    TRY(ensure(st, st->disc_part, nparts * sizeof(uint64_t)));
+    TRY(ensure(st, st->max_part, nparts * sizeof(uint64_t)));
+    ItemPartials part{ptr<double>(st->num_part), ptr<uint64_t>(st->att_part), ptr<uint64_t>(st->disc_part),
+                      ptr<uint64_t>(st->max_part)};
+    ItemPartials part_sel{part.num + nb_fnc, part.att + nb_fnc, part.disc + nb_fnc, part.maxn + nb_fnc};
     const double item_bytes = kb + 2 * tb + 13.0;  // key, A, death, n, level, slot count
     if (fnc) {
         launch(st, "noncomposite", n_fnc * (kb + 2 * tb + item_bytes), (double)n_fnc, [&] {
-            k_noncomposite<W, T><<<nb_fnc, kThreads, 0, s>>>(st->sd, skey, samp, sK, scap, ne, st->n0, a, it, num_part, sc);
+            k_noncomposite<W, T><<<nb_fnc, kThreads, 0, s>>>(st->sd, skey, samp, sK, scap, ne, st->n0, a, it, part, sc);
         });
     }
     if (n_sel) {
         launch(st, "select", n_sel * item_bytes, (double)n_sel, [&] {
             k_select<W, T><<<nb_sel, kThreads, 0, s>>>(st->sd, skey, samp, scap, ne, ptr<uint64_t>(st->P),
-                                                        ptr<uint32_t>(st->guide), st->n0, a, it, n_fnc, num_part + nb_fnc, sc);
+                                                        ptr<uint32_t>(st->guide), st->n0, a, it, n_fnc, part_sel, sc);
         });
+    } else {
+        k_fill<uint64_t><<<1, 1, 0, s>>>(it.cnt + n_items, 1, 0ull);
     }
-    k_fill<uint64_t><<<1, 1, 0, s>>>(it.cnt + n_items, 1, 0ull);
     TRY(scan<uint64_t>(st, it.cnt, ptr<uint64_t>(st->ioff), n_items + 1, false));
-    k_reduce_partials<<<1, kThreads, 0, s>>>(num_part, nb_fnc + nb_sel, &sc->num);
+    k_item_stats<<<1, kThreads, 0, s>>>(part, nb_fnc + nb_sel, sc);
     HIP_TRY(hipMemcpyAsync(st->hpinned, ptr<uint64_t>(st->ioff) + n_items, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(st->hscratch, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -590,15 +597,14 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
         const uint64_t nc = std::max<uint64_t>(nblk * kGenSlots, st->rcap + st->rcap / 2);
         const uint64_t nb = nc / kGenSlots + 2;
         TRY(ensure(st, st->rkey, nc * W * sizeof(uint64_t)));
-        TRY(ensure(st, st->rrank, nc * sizeof(uint64_t)));
         TRY(ensure(st, st->ramp, nc * sizeof(T)));
-        for (DevBuf *b : {&st->block_item, &st->gor}) TRY(ensure(st, *b, nb * sizeof(uint64_t)));
+        TRY(ensure(st, st->block_item, nb * sizeof(uint64_t)));
         for (DevBuf *b : {&st->gcount, &st->gspawn, &st->gdeath, &st->boff}) TRY(ensure(st, *b, nb * sizeof(uint32_t)));
         st->rcap = nc;
     }
     if (ids && st->rid.bytes < st->rcap * sizeof(uint64_t)) TRY(ensure(st, st->rid, st->rcap * sizeof(uint64_t)));
-    Records reg{ptr<uint64_t>(st->rrank), ptr<uint64_t>(st->rkey), st->ramp.p, ptr<uint64_t>(st->rid), st->rcap};
-    GenStats gst{ptr<uint32_t>(st->gcount), ptr<uint32_t>(st->gspawn), ptr<uint32_t>(st->gdeath), ptr<uint64_t>(st->gor)};
+    Records reg{nullptr, ptr<uint64_t>(st->rkey), st->ramp.p, ptr<uint64_t>(st->rid), st->rcap};
+    GenStats gst{ptr<uint32_t>(st->gcount), ptr<uint32_t>(st->gspawn), ptr<uint32_t>(st->gdeath)};
     if (nblk) {
         k_block_items<<<grid_for(nblk + 1), kThreads, 0, s>>>(ptr<uint64_t>(st->ioff), n_items, nblk, n_slots,
                                                              ptr<uint64_t>(st->block_item));
@@ -607,7 +613,6 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
                                                                  ptr<uint64_t>(st->block_item), n_fnc, n_slots, a, reg,
                                                                  ids ? 1 : 0, gst);
         });
-        k_fill<uint32_t><<<1, 1, 0, s>>>(gst.count + nblk, 1, 0u);
         TRY(scan<uint32_t>(st, gst.count, ptr<uint32_t>(st->boff), nblk + 1, false));
         k_gen_stats<<<1, kThreads, 0, s>>>(gst, ptr<uint32_t>(st->boff), nblk, sc);
     }
@@ -631,7 +636,8 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     Records rec{ptr<uint64_t>(st->drank), ptr<uint64_t>(st->dkey), st->damp.p, ptr<uint64_t>(st->did), dc};
     if (nrec) {
         launch(st, "gather", 2.0 * nrec * (kb + 8.0 + tb + (ids ? 8.0 : 0.0)), (double)nrec, [&] {
-            k_gather<W, T><<<grid_for(nrec), kThreads, 0, s>>>(reg, ptr<uint32_t>(st->boff), nblk, rec, ids ? 1 : 0, sc);
+            k_gather<W, T><<<grid_for(nrec), kThreads, 0, s>>>(st->sd, reg, ptr<uint32_t>(st->boff), nblk, rec, ids ? 1 : 0,
+                                                               sc);
         });
     }
 
@@ -646,8 +652,7 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     TRY(ensure(st, st->pos, (ne + nrec + 1) * sizeof(uint32_t)));
 
     // (a11) stable LSD radix sort of (rank, record index) over the rank digits that vary
-    int top = 0;
-    while (top < 64 && (scr.rank_or >> top)) ++top;
+    const int top = st->rank_bits;
     std::vector<int> passes;
     for (int sh = 0; sh < top; sh += 8) passes.push_back(sh);
     if (passes.empty()) passes.push_back(0);
@@ -928,9 +933,8 @@ void destroy(ccmc_state *st)
     DevBuf *bufs[] = {&st->t_grid, &st->t_nvec, &st->t_vq, &st->t_h, &st->t_eri, &st->t_fock, &st->t_vpair,
                       &st->t_binv, &st->t_bino, &st->skey[0], &st->skey[1], &st->samp[0], &st->samp[1], &st->sK[0],
                       &st->sK[1], &st->srank[0], &st->srank[1], &st->q, &st->P, &st->guide, &st->delta, &st->ikey,
-                      &st->iA, &st->ideath, &st->in, &st->ilevel, &st->icnt, &st->ioff, &st->num_part, &st->abs_part,
-                      &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->gor, &st->boff, &st->rrank,
-                      &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
+                      &st->iA, &st->ideath, &st->in, &st->ilevel, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,
+                      &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->boff, &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
                       &st->sidx[0], &st->sidx[1], &st->hist, &st->hoff, &st->flag, &st->incl, &st->start, &st->is_new,
                       &st->new_pos, &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->keep,
                       &st->pos, &st->scratch};

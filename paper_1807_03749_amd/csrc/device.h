@@ -364,17 +364,19 @@ __device__ __forceinline__ double size_prob(int s, int lo, int hi)
     return (s < hi) ? ldexp(1.0, -(s - lo + 1)) : ldexp(1.0, -(hi - lo));
 }
 
-// pair (x < y) of rank r in lexicographic order over n items
+// Pair (x < y) of rank r in lexicographic order over n items.  Row x starts at
+// S(x) = x (2n - x - 1) / 2; x is the root of S(x) = r rounded down, then corrected by one
+// step either way against rounding of the square root.
 __device__ __forceinline__ void unrank_pair(int n, uint32_t r, int &x, int &y)
 {
-    x = 0;
-    uint32_t row = (uint32_t)(n - 1);
-    while (r >= row) {
-        r -= row;
-        ++x;
-        --row;
-    }
-    y = x + 1 + (int)r;
+    const double b = 2.0 * n - 1.0;
+    int t = (int)floor(0.5 * (b - sqrt(b * b - 8.0 * (double)r)));
+    t = t < 0 ? 0 : (t > n - 2 ? n - 2 : t);
+    auto start = [n](int v) { return (uint32_t)(v * (2 * n - v - 1) / 2); };
+    if (start(t) > r) --t;
+    else if (t + 1 <= n - 2 && start(t + 1) <= r) ++t;
+    x = t;
+    y = x + 1 + (int)(r - start(t));
 }
 
 }  // namespace ccmc

@@ -54,6 +54,32 @@ struct StepArgs {
     int fnc;
 };
 
+// Per-block partial statistics of the item kernels, reduced by k_item_stats.
+struct ItemPartials {
+    double *num;       // projected-energy numerator
+    uint64_t *att;     // spawning attempts
+    uint64_t *disc;    // discarded selections
+    uint64_t *maxn;    // largest attempt count
+};
+
+template <typename V>
+__device__ __forceinline__ V block_reduce_max(V v)
+{
+    __shared__ V wave_max[kWaves];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const V o = __shfl_down(v, off, 64);
+        v = o > v ? o : v;
+    }
+    if (lane_id() == 0) wave_max[wave_id()] = v;
+    __syncthreads();
+    V m = wave_max[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) m = wave_max[w] > m ? wave_max[w] : m;
+    __syncthreads();
+    return m;
+}
+
 // Items: one per cluster that may emit records.  SoA key layout with stride `stride`.
 template <typename T>
 struct Items {
@@ -136,8 +162,7 @@ __global__ void __launch_bounds__(kThreads) k_guide(const uint64_t *__restrict__
 template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_noncomposite(SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
                                                            const T *__restrict__ sK, uint64_t sstride, uint64_t ne, double n0,
-                                                           StepArgs a, Items<T> it, double *__restrict__ num_part,
-                                                           Scratch *sc)
+                                                           StepArgs a, Items<T> it, ItemPartials part, Scratch *sc)
 {
     const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     double num = 0.0;
@@ -176,11 +201,13 @@ __global__ void __launch_bounds__(kThreads) k_noncomposite(SysDev S, const uint6
     }
     const double bnum = block_reduce_sum(num);
     const uint64_t batt = block_reduce_sum(att);
+    const uint64_t bmax = block_reduce_max(mx);
     if (threadIdx.x == 0) {
-        num_part[blockIdx.x] = bnum;
-        atomicAdd((unsigned long long *)&sc->n_attempts, (unsigned long long)batt);
+        part.num[blockIdx.x] = bnum;
+        part.att[blockIdx.x] = batt;
+        part.disc[blockIdx.x] = 0;
+        part.maxn[blockIdx.x] = bmax;
     }
-    if (mx) atomicMax((unsigned long long *)&sc->max_n, (unsigned long long)mx);
 }
 
 // --------------------------------------------------------------- sampled clusters
@@ -192,8 +219,7 @@ template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_select(SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
                                                      uint64_t sstride, uint64_t ne, const uint64_t *__restrict__ P,
                                                      const uint32_t *__restrict__ guide, double n0, StepArgs a,
-                                                     Items<T> it, uint64_t item_base, double *__restrict__ num_part,
-                                                     Scratch *sc)
+                                                     Items<T> it, uint64_t item_base, ItemPartials part, Scratch *sc)
 {
     const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     double num = 0.0;
@@ -204,51 +230,96 @@ __global__ void __launch_bounds__(kThreads) k_select(SysDev S, const uint64_t *_
         Draws r(a.key0, a.key1, kSelect, (uint32_t)k, 0u, a.step);
         const int lo = a.fnc ? 2 : 0, hi = S.l + 2;
         const int s = draw_size(uniform53(r.get(0)), lo, hi);
-        uint64_t idx[kMaxClusterSize];
         bool ok = !(s > 0 && Q == 0);
-        for (int c = 0; c < s && ok; ++c) {
-            const uint64_t x = below(r.get(1 + c), Q);
-            const uint64_t gb = x >> gsh;
-            uint64_t l0 = guide[gb], h0 = (uint64_t)guide[gb + 1] + 1;  // first i with P[i] > x
-            while (l0 < h0) {
-                const uint64_t mid = (l0 + h0) >> 1;
-                if (P[mid] > x)
-                    h0 = mid;
-                else
-                    l0 = mid + 1;
+        // Every draw of the cluster first; then the loads they need are issued together (one
+        // latency chain per cluster instead of one per excitor).
+        uint64_t xs[kMaxClusterSize];
+        uint32_t l0[kMaxClusterSize], h0[kMaxClusterSize];
+#pragma unroll
+        for (int c = 0; c < kMaxClusterSize; ++c) {
+            xs[c] = 0;
+            l0[c] = h0[c] = 0;
+            if (c < s && ok) xs[c] = below(r.get(1 + c), Q);
+        }
+#pragma unroll
+        for (int c = 0; c < kMaxClusterSize; ++c) {
+            if (c < s && ok) {
+                const uint64_t gb = xs[c] >> gsh;
+                l0[c] = guide[gb];
+                h0[c] = guide[gb + 1] + 1u;
             }
-            idx[c] = l0;
-            for (int b = 0; b < c; ++b) ok &= (idx[b] != l0);
+        }
+        // lock-step binary searches: first i in [l0, h0) with P[i] > x
+        for (bool more = ok && s > 0; more;) {
+            more = false;
+#pragma unroll
+            for (int c = 0; c < kMaxClusterSize; ++c) {
+                if (c < s && l0[c] < h0[c]) {
+                    const uint32_t mid = (l0[c] + h0[c]) >> 1;
+                    if (P[mid] > xs[c])
+                        h0[c] = mid;
+                    else
+                        l0[c] = mid + 1;
+                    more |= l0[c] < h0[c];
+                }
+            }
+        }
+        // repeated excitors: discarded (Sec. II)
+#pragma unroll
+        for (int c = 1; c < kMaxClusterSize; ++c)
+#pragma unroll
+            for (int b = 0; b < c; ++b)
+                if (c < s) ok &= (l0[b] != l0[c]);
+        // selection probability and product of amplitudes, in draw order
+        double fact = 1.0;
+        for (int c = 2; c <= s; ++c) fact *= (double)c;
+        double p = (double)a.n_sel * size_prob(s, lo, hi) * fact;
+        T prod = (T)n0;
+#pragma unroll
+        for (int c = 0; c < kMaxClusterSize; ++c) {
+            if (c < s && ok) {
+                const uint32_t i = l0[c];
+                const uint64_t qi = P[i] - (i ? P[i - 1] : 0);
+                const T ni = samp[i];
+                p *= (double)qi / (double)Q;
+                if (c == 0)
+                    prod = ni;
+                else
+                    prod *= ni / (T)n0;
+            }
         }
         uint64_t d[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) d[w] = S.hf[w];
         int e = 0;
         // apply c_{X_s} first: annihilate holes ascending, then create particles descending
-        for (int c = s - 1; c >= 0 && ok; --c) {
+#pragma unroll
+        for (int cc = 0; cc < kMaxClusterSize; ++cc) {
+            const int c = s - 1 - cc;
+            if (c < 0 || !ok) continue;
             uint64_t x[W];
 #pragma unroll
-            for (int w = 0; w < W; ++w) x[w] = skey[(uint64_t)w * sstride + idx[c]];
+            for (int w = 0; w < W; ++w) x[w] = skey[(uint64_t)w * sstride + l0[c]];
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 uint64_t h = S.hf[w] & ~x[w];
                 while (h) {
-                    const int p = 64 * w + __ffsll((long long)h) - 1;
+                    const int q = 64 * w + __ffsll((long long)h) - 1;
                     h &= h - 1;
-                    if (!bit_test<W>(d, p)) ok = false;
-                    e += count_below<W>(d, p);
-                    bit_flip<W>(d, p);
+                    if (!bit_test<W>(d, q)) ok = false;
+                    e += count_below<W>(d, q);
+                    bit_flip<W>(d, q);
                 }
             }
 #pragma unroll
             for (int w = W - 1; w >= 0; --w) {
                 uint64_t pm = x[w] & ~S.hf[w];
                 while (pm) {
-                    const int p = 64 * w + 63 - __clzll((long long)pm);
-                    pm &= ~(1ull << (p & 63));
-                    if (bit_test<W>(d, p)) ok = false;
-                    e += count_below<W>(d, p);
-                    bit_flip<W>(d, p);
+                    const int q = 64 * w + 63 - __clzll((long long)pm);
+                    pm &= ~(1ull << (q & 63));
+                    if (bit_test<W>(d, q)) ok = false;
+                    e += count_below<W>(d, q);
+                    bit_flip<W>(d, q);
                 }
             }
         }
@@ -258,22 +329,10 @@ __global__ void __launch_bounds__(kThreads) k_select(SysDev S, const uint64_t *_
         uint64_t cnt = 0;
         T A = T(0), death = T(0);
         if (ok) {
-            // sign of c_X1..c_Xs |HF> = sigma s_D(X) |D_X>
+            // sign of c_X1..c_Xs |HF> = sigma s_D(X) |D_X>; the cluster amplitude is
+            // t_HF^(1-s) prod t_i with that sign (a sign flip is exact in either order)
             const int sigma = ((e & 1) ? -1 : 1) * excitor_sign<W>(S, d);
-            double fact = 1.0;
-            for (int c = 2; c <= s; ++c) fact *= (double)c;
-            double p = (double)a.n_sel * size_prob(s, lo, hi) * fact;
-            for (int c = 0; c < s; ++c) {
-                const uint64_t qi = P[idx[c]] - (idx[c] ? P[idx[c] - 1] : 0);
-                p *= (double)qi / (double)Q;
-            }
-            T Ac;
-            if (s == 0) {
-                Ac = (T)n0;
-            } else {
-                Ac = (T)sigma * samp[idx[0]];
-                for (int c = 1; c < s; ++c) Ac *= samp[idx[c]] / (T)n0;
-            }
+            const T Ac = (s == 0) ? (T)n0 : (sigma < 0 ? -prod : prod);
             A = Ac / (T)p;
             n = attempt_count<T>(A, a.thr_cluster, a.kmin, &sc->err);
             cnt = (uint64_t)n + 1;
@@ -296,12 +355,14 @@ __global__ void __launch_bounds__(kThreads) k_select(SysDev S, const uint64_t *_
     const double bnum = block_reduce_sum(num);
     const uint64_t batt = block_reduce_sum(att);
     const uint64_t bdisc = block_reduce_sum(disc);
+    const uint64_t bmax = block_reduce_max(mx);
     if (threadIdx.x == 0) {
-        num_part[blockIdx.x] = bnum;
-        atomicAdd((unsigned long long *)&sc->n_attempts, (unsigned long long)batt);
-        atomicAdd((unsigned long long *)&sc->n_discarded, (unsigned long long)bdisc);
+        part.num[blockIdx.x] = bnum;
+        part.att[blockIdx.x] = batt;
+        part.disc[blockIdx.x] = bdisc;
+        part.maxn[blockIdx.x] = bmax;
     }
-    if (mx) atomicMax((unsigned long long *)&sc->max_n, (unsigned long long)mx);
+    if (k == 0) it.cnt[item_base + a.n_sel] = 0;  // closing entry of the slot-count scan
 }
 
 // ----------------------------------------------------------------- generation
@@ -422,7 +483,6 @@ struct GenStats {
     uint32_t *count;    // records of each block
     uint32_t *spawns;
     uint32_t *deaths;
-    uint64_t *rank_or;
 };
 
 template <int W, typename T>
@@ -432,7 +492,6 @@ __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, co
 {
     __shared__ uint64_t s_off[kGenLdsItems + 1];
     __shared__ uint32_t wave_tot[kWaves];
-    __shared__ uint64_t wave_or[kWaves];
     T *ramp = static_cast<T *>(rec.amp);
     const uint64_t g0 = (uint64_t)blockIdx.x * kGenSlots;
     const uint64_t lo = block_item[blockIdx.x], hi = block_item[blockIdx.x + 1];
@@ -441,13 +500,12 @@ __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, co
         for (uint64_t t = threadIdx.x; t <= hi - lo + 1; t += kThreads) s_off[t] = off[lo + t];
     __syncthreads();
     uint32_t base = 0, spawns = 0, deaths = 0;
-    uint64_t rank_or = 0;
     for (int rd = 0; rd < kGenRounds; ++rd) {
         const uint64_t g = g0 + (uint64_t)rd * kThreads + threadIdx.x;
         bool emit = false;
         uint64_t tgt[W];
         T x = T(0);
-        uint64_t id = 0, rk = 0;
+        uint64_t id = 0;
         if (g < n_slots) {
             uint64_t item;
             if (lds) {  // last item in [lo, hi] whose offset is <= g, searched in LDS
@@ -490,10 +548,6 @@ __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, co
                                            slot - 1, a, tgt, x);
                 spawns += emit ? 1u : 0u;
             }
-            if (emit) {
-                rk = space_rank<W>(S, tgt);
-                rank_or |= rk;
-            }
             id = ((nc ? 0ull : 1ull) << 62) | ((uint64_t)k << 30) | (uint64_t)slot;
         }
         // compaction in slot order
@@ -508,7 +562,6 @@ __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, co
         }
         if (emit) {
             const uint64_t dst = g0 + base + before + (uint32_t)lanes_below(m);
-            rec.rank[dst] = rk;
 #pragma unroll
             for (int w = 0; w < W; ++w) rec.key[(uint64_t)w * rec.stride + dst] = tgt[w];
             ramp[dst] = x;
@@ -519,40 +572,28 @@ __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, co
     }
     const uint32_t bs = block_reduce_sum(spawns);
     const uint32_t bd = block_reduce_sum(deaths);
-    uint64_t ro = rank_or;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) ro |= __shfl_xor(ro, o, 64);
-    if (lane_id() == 0) wave_or[wave_id()] = ro;
-    __syncthreads();
     if (threadIdx.x == 0) {
         gs.count[blockIdx.x] = base;
         gs.spawns[blockIdx.x] = bs;
         gs.deaths[blockIdx.x] = bd;
-        gs.rank_or[blockIdx.x] = wave_or[0] | wave_or[1] | wave_or[2] | wave_or[3];
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) gs.count[gridDim.x] = 0;  // closing entry of the scan
 }
 
 // Sums of the per-block generation statistics (one block).
 __global__ void __launch_bounds__(kThreads) k_gen_stats(GenStats gs, const uint32_t *__restrict__ boff, uint64_t n_blocks,
                                                         Scratch *sc)
 {
-    uint64_t sp = 0, de = 0, ro = 0;
+    uint64_t sp = 0, de = 0;
     for (uint64_t b = threadIdx.x; b < n_blocks; b += kThreads) {
         sp += gs.spawns[b];
         de += gs.deaths[b];
-        ro |= gs.rank_or[b];
     }
     sp = block_reduce_sum(sp);
     de = block_reduce_sum(de);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) ro |= __shfl_xor(ro, o, 64);
-    __shared__ uint64_t wo[kWaves];
-    if (lane_id() == 0) wo[wave_id()] = ro;
-    __syncthreads();
     if (threadIdx.x == 0) {
         sc->n_spawns = sp;
         sc->n_deaths = de;
-        sc->rank_or = wo[0] | wo[1] | wo[2] | wo[3];
         sc->n_rec = boff[n_blocks];
     }
 }
@@ -560,8 +601,8 @@ __global__ void __launch_bounds__(kThreads) k_gen_stats(GenStats gs, const uint3
 // Dense layout of the records: output position r comes from the block b with
 // boff[b] <= r < boff[b+1], at slot position r - boff[b] of its region.
 template <int W, typename T>
-__global__ void __launch_bounds__(kThreads) k_gather(Records reg, const uint32_t *__restrict__ boff, uint64_t n_blocks,
-                                                     Records out, int keep_ids, const Scratch *sc)
+__global__ void __launch_bounds__(kThreads) k_gather(const SysDev S, Records reg, const uint32_t *__restrict__ boff,
+                                                     uint64_t n_blocks, Records out, int keep_ids, const Scratch *sc)
 {
     const uint64_t r = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     if (r >= sc->n_rec) return;
@@ -575,9 +616,13 @@ __global__ void __launch_bounds__(kThreads) k_gather(Records reg, const uint32_t
     }
     const uint64_t b = l0 - 1;
     const uint64_t src = b * kGenSlots + (r - boff[b]);
-    out.rank[r] = reg.rank[src];
+    uint64_t d[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) out.key[(uint64_t)w * out.stride + r] = reg.key[(uint64_t)w * reg.stride + src];
+    for (int w = 0; w < W; ++w) {
+        d[w] = reg.key[(uint64_t)w * reg.stride + src];
+        out.key[(uint64_t)w * out.stride + r] = d[w];
+    }
+    out.rank[r] = space_rank<W>(S, d);
     static_cast<T *>(out.amp)[r] = static_cast<const T *>(reg.amp)[src];
     if (keep_ids) out.id[r] = reg.id[src];
 }
@@ -764,6 +809,29 @@ __global__ void __launch_bounds__(kThreads) k_reduce_partials(const double *__re
     for (uint64_t i = threadIdx.x; i < n; i += kThreads) s += part[i];
     s = block_reduce_sum(s);
     if (threadIdx.x == 0) *out = s;
+}
+
+// Fixed-order reduction of the item kernels' per-block partials (one block).
+__global__ void __launch_bounds__(kThreads) k_item_stats(ItemPartials part, uint64_t n, Scratch *sc)
+{
+    double num = 0.0;
+    uint64_t att = 0, disc = 0, mx = 0;
+    for (uint64_t i = threadIdx.x; i < n; i += kThreads) {
+        num += part.num[i];
+        att += part.att[i];
+        disc += part.disc[i];
+        mx = part.maxn[i] > mx ? part.maxn[i] : mx;
+    }
+    num = block_reduce_sum(num);
+    att = block_reduce_sum(att);
+    disc = block_reduce_sum(disc);
+    mx = block_reduce_max(mx);
+    if (threadIdx.x == 0) {
+        sc->num = num;
+        sc->n_attempts = att;
+        sc->n_discarded = disc;
+        sc->max_n = mx;
+    }
 }
 
 template <typename V>
