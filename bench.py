@@ -108,10 +108,19 @@ def grow(state, w: inputs.Workload, log, max_steps: int = 20000, tau_grow_factor
     return st, max_steps
 
 
-def run_leg(w: inputs.Workload, precision: str, steps: int, warmup: int, log, profile: bool = True):
+def run_leg(w: inputs.Workload, precision: str, steps: int, warmup: int, log, profile: bool = True,
+            load_state: str | None = None, save_state: str | None = None):
     state = make_state(w, precision, init_pop=max(100.0, w.target_population / 50))
-    st, ngrow = grow(state, w, log)
-    ctl = driver.ShiftControl(target=w.target_population, tau=w.tau)
+    if load_state:
+        z = np.load(load_state)
+        state.ccmc_import(z["keys"], z["amps"], float(z["n_ref"]), int(z["step"]))
+        st = {"n_total": float(np.abs(z["amps"]).sum() + abs(float(z["n_ref"])))}
+        ngrow = 0
+        shift0 = float(z["shift"])
+    else:
+        st, ngrow = grow(state, w, log)
+        shift0 = 0.0
+    ctl = driver.ShiftControl(target=w.target_population, tau=w.tau, shift=shift0)
     ctl.varying = True
     ctl._anchor = 0
     ctl.history = [st["n_total"]]
@@ -120,6 +129,9 @@ def run_leg(w: inputs.Workload, precision: str, steps: int, warmup: int, log, pr
         st = state.ccmc_step(w.tau, ctl.shift, nsel)
         ctl.update(st["n_total"])
         nsel = driver.selections(st["n_total"])
+    if save_state:
+        keys, amps, n0, step = state.ccmc_export()
+        np.savez(save_state, keys=keys, amps=amps, n_ref=n0, step=step, shift=ctl.shift)
     if profile:
         state.ccmc_profile(True)
         state.ccmc_profile_read()
@@ -251,6 +263,8 @@ def main():
                     help="mark the timed steps for a profiler run with --selected-regions")
     ap.add_argument("--no-kernel-timing", action="store_true", help="no HIP-event timing in the timed region")
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a 1 GiB device copy (counter scaling)")
+    ap.add_argument("--save-state", help="write the equilibrated store (after warm-up) to this .npz")
+    ap.add_argument("--load-state", help="start from a store written by --save-state instead of growing one")
     args = ap.parse_args()
     global ROCTX
     ROCTX = _Roctx(args.roctx_region)
@@ -264,7 +278,8 @@ def main():
     log = (lambda m: None) if args.quiet else (lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     w = inputs.WORKLOADS[args.workload]
     log(f"workload {w.name} precision {args.precision}: growing to {w.target_population:.0e}")
-    main_leg = run_leg(w, args.precision, args.steps, args.warmup, log, profile=not args.no_kernel_timing)
+    main_leg = run_leg(w, args.precision, args.steps, args.warmup, log, profile=not args.no_kernel_timing,
+                       load_state=args.load_state, save_state=args.save_state)
     value = main_leg["attempts"] / main_leg["seconds"]
     log(f"{args.precision}: {value:.4e} attempts/s, {1e3 * main_leg['seconds'] / args.steps:.3f} ms/step")
     for k, p in sorted(main_leg["profile"].items(), key=lambda kv: -kv[1]["ms"]):

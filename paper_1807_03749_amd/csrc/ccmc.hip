@@ -28,10 +28,14 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// A timed launch; its work is unit_bytes x the count it covers, known when it is resolved
+// (a count produced on the device is read back at the end of the step).
 struct Pending {
     const char *name;
     hipEvent_t a, b;
-    double bytes, items;
+    double unit_bytes;
+    const uint64_t *count;  // live count, or null for `fixed`
+    uint64_t fixed;
 };
 
 struct Accum {
@@ -87,6 +91,8 @@ struct ccmc_state {
     DevBuf drank, dkey, damp, did, sr[2], sidx[2], hist, hoff;
     DevBuf flag, incl, start, is_new, new_pos, ins, seg_sum, nkey, nrank, nins, nsum, keep, pos;
     uint64_t dcap = 0;  // dense record capacity
+    uint64_t slot_hint = 1 << 16, rec_hint = 1 << 14;  // capacities planned for the next step
+    uint64_t cnt_slots = 0, cnt_rec = 0, cnt_merged = 0;  // live counts of the last step
     std::vector<DevBuf> scan_tmp;
     DevBuf scratch;
     Scratch *hscratch = nullptr;  // pinned
@@ -180,13 +186,13 @@ hipEvent_t take_event(ccmc_state *st)
 }
 
 template <class F>
-void launch(ccmc_state *st, const char *name, double bytes, double items, F &&f)
+void launch(ccmc_state *st, const char *name, double unit_bytes, const uint64_t *count, uint64_t fixed, F &&f)
 {
     if (!st->prof) {
         f();
         return;
     }
-    Pending p{name, take_event(st), take_event(st), bytes, items};
+    Pending p{name, take_event(st), take_event(st), unit_bytes, count, fixed};
     (void)hipEventRecord(p.a, st->stream);
     f();
     (void)hipEventRecord(p.b, st->stream);
@@ -199,11 +205,12 @@ void resolve_profile(ccmc_state *st)
         float ms = 0;
         (void)hipEventSynchronize(p.b);
         (void)hipEventElapsedTime(&ms, p.a, p.b);
+        const double n = (double)(p.count ? *p.count : p.fixed);
         Accum &a = st->accum[p.name];
         a.launches++;
         a.ms += ms;
-        a.bytes += p.bytes;
-        a.items += p.items;
+        a.bytes += p.unit_bytes * n;
+        a.items += n;
         st->ev_pool.push_back(p.a);
         st->ev_pool.push_back(p.b);
     }
@@ -211,13 +218,13 @@ void resolve_profile(ccmc_state *st)
 }
 
 // --------------------------------------------------------------------------- scan
-template <typename V>
-ccmc_status scan(ccmc_state *st, const V *in, V *out, uint64_t n, bool inclusive, int level = 0)
+template <typename V, typename Src>
+ccmc_status scan_src(ccmc_state *st, Src in, V *out, uint64_t n, bool inclusive, int level = 0)
 {
     if (n == 0) return CCMC_OK;
     const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
-    if (tiles <= 16) {
-        k_scan_small<V><<<1, kThreads, 0, st->stream>>>(in, out, n, inclusive ? 1 : 0);
+    if (tiles <= 2) {
+        k_scan_small<V, Src><<<1, kThreads, 0, st->stream>>>(in, out, n, inclusive ? 1 : 0);
         return CCMC_OK;
     }
     if ((int)st->scan_tmp.size() < 2 * (level + 1)) st->scan_tmp.resize(2 * (level + 1));
@@ -225,10 +232,16 @@ ccmc_status scan(ccmc_state *st, const V *in, V *out, uint64_t n, bool inclusive
     TRY(ensure(st, st->scan_tmp[2 * level + 1], tiles * sizeof(V)));
     V *part = ptr<V>(st->scan_tmp[2 * level]);
     V *poff = ptr<V>(st->scan_tmp[2 * level + 1]);
-    k_scan_reduce<V><<<(unsigned)tiles, kThreads, 0, st->stream>>>(in, n, part);
-    TRY(scan<V>(st, part, poff, tiles, false, level + 1));
-    k_scan_tile<V><<<(unsigned)tiles, kThreads, 0, st->stream>>>(in, out, n, poff, inclusive ? 1 : 0);
+    k_scan_reduce<V, Src><<<(unsigned)tiles, kThreads, 0, st->stream>>>(in, n, part);
+    TRY(scan_src<V>(st, ArraySrc<V>{part}, poff, tiles, false, level + 1));
+    k_scan_tile<V, Src><<<(unsigned)tiles, kThreads, 0, st->stream>>>(in, out, n, poff, inclusive ? 1 : 0);
     return CCMC_OK;
+}
+
+template <typename V>
+ccmc_status scan(ccmc_state *st, const V *in, V *out, uint64_t n, bool inclusive)
+{
+    return scan_src<V>(st, ArraySrc<V>{in}, out, n, inclusive);
 }
 
 // ------------------------------------------------------------------------ systems
@@ -491,9 +504,15 @@ ccmc_status ensure_store(ccmc_state *st, uint64_t n)
 }
 
 // ---------------------------------------------------------------------- the step
+// One attempt at a step.  Sizes produced on the device (record slots, records, new
+// determinants, survivors) are never read back in the middle: kernels read them from device
+// memory, and grids cover capacities planned from the previous step.  If a count exceeds
+// its capacity, the overflow bit turns the final compaction into a no-op; the host then
+// grows the buffers and the step is replayed with the same Philox counters (*replay).
 template <int W, typename T>
-ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, ccmc_stats *out)
+ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, ccmc_stats *out, bool *replay)
 {
+    *replay = false;
     hipStream_t s = st->stream;
     const uint64_t ne = st->ne;
     const bool fnc = st->opt.full_noncomposite != 0;
@@ -502,6 +521,7 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     const int c = st->cur;
     const double kb = (double)(W * 8);  // bytes of one bitstring
     const double tb = (double)sizeof(T);
+    const bool ids = st->opt.keep_spawn_ids != 0;
 
     StepArgs a;
     a.tau = tau;
@@ -517,24 +537,14 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     a.n_sel = n_sel;
     a.fnc = fnc ? 1 : 0;
 
-    Scratch *sc = ptr<Scratch>(st->scratch);
-    HIP_TRY(hipMemsetAsync(sc, 0, sizeof(Scratch), s));
-    const uint64_t *skey = ptr<uint64_t>(st->skey[c]);
-    const T *samp = ptr<T>(st->samp[c]);
-    const T *sK = ptr<T>(st->sK[c]);
-    const uint64_t scap = st->scap;
-
-    // (a1) selection weights, their inclusive prefix and the guide table of the draws
-    if (ne) {
-        launch(st, "weights", ne * (tb + 8.0), (double)ne, [&] {
-            k_weights<T><<<grid_for(ne), kThreads, 0, s>>>(samp, ne, ptr<uint64_t>(st->q), sc);
-        });
-        TRY(scan<uint64_t>(st, ptr<uint64_t>(st->q), ptr<uint64_t>(st->P), ne, true));
+    // ---- capacities for this step (all allocation happens here, before any launch)
+    const uint64_t slot_cap = std::max<uint64_t>(kGenSlots, (st->slot_hint + kGenSlots - 1) / kGenSlots * kGenSlots);
+    const uint64_t nblk_cap = slot_cap / kGenSlots;
+    const uint64_t rec_cap = std::max<uint64_t>(1, std::min<uint64_t>(st->rec_hint, slot_cap));
+    if (slot_cap + ne + 1 >= (1ull << 32)) {
+        st->err = "more than 2^32 record slots in one step";
+        return CCMC_EOVERFLOW;
     }
-    k_guide_setup<<<1, 1, 0, s>>>(ptr<uint64_t>(st->P), ne, sc);
-    if (ne && n_sel) k_guide<<<grid_for(2 * ne + 2), kThreads, 0, s>>>(ptr<uint64_t>(st->P), ne, sc, ptr<uint32_t>(st->guide));
-
-    // items: non-composite (FNC) then sampled clusters
     if (n_items + 1 > st->icap) {
         const uint64_t nc = std::max<uint64_t>(n_items + 1, st->icap + st->icap / 2);
         TRY(ensure(st, st->ikey, nc * W * sizeof(uint64_t)));
@@ -546,55 +556,8 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
         TRY(ensure(st, st->ioff, nc * sizeof(uint64_t)));
         st->icap = nc;
     }
-    Items<T> it{ptr<uint64_t>(st->ikey), ptr<T>(st->iA), ptr<T>(st->ideath), ptr<uint32_t>(st->in),
-                ptr<uint8_t>(st->ilevel), ptr<uint64_t>(st->icnt), st->icap};
-    const unsigned nb_fnc = fnc ? grid_for(n_fnc) : 0, nb_sel = n_sel ? grid_for(n_sel) : 0;
-    const size_t nparts = (size_t)(nb_fnc + nb_sel + 1);
-    TRY(ensure(st, st->num_part, nparts * sizeof(double)));
-    TRY(ensure(st, st->att_part, nparts * sizeof(uint64_t)));
-    TRY(ensure(st, st->disc_part, nparts * sizeof(uint64_t)));
-    TRY(ensure(st, st->max_part, nparts * sizeof(uint64_t)));
-    ItemPartials part{ptr<double>(st->num_part), ptr<uint64_t>(st->att_part), ptr<uint64_t>(st->disc_part),
-                      ptr<uint64_t>(st->max_part)};
-    ItemPartials part_sel{part.num + nb_fnc, part.att + nb_fnc, part.disc + nb_fnc, part.maxn + nb_fnc};
-    const double item_bytes = kb + 2 * tb + 13.0;  // key, A, death, n, level, slot count
-    if (fnc) {
-        launch(st, "noncomposite", n_fnc * (kb + 2 * tb + item_bytes), (double)n_fnc, [&] {
-            k_noncomposite<W, T><<<nb_fnc, kThreads, 0, s>>>(st->sd, skey, samp, sK, scap, ne, st->n0, a, it, part, sc);
-        });
-    }
-    if (n_sel) {
-        launch(st, "select", n_sel * item_bytes, (double)n_sel, [&] {
-            k_select<W, T><<<nb_sel, kThreads, 0, s>>>(st->sd, skey, samp, scap, ne, ptr<uint64_t>(st->P),
-                                                        ptr<uint32_t>(st->guide), st->n0, a, it, n_fnc, part_sel, sc);
-        });
-    } else {
-        k_fill<uint64_t><<<1, 1, 0, s>>>(it.cnt + n_items, 1, 0ull);
-    }
-    TRY(scan<uint64_t>(st, it.cnt, ptr<uint64_t>(st->ioff), n_items + 1, false));
-    k_item_stats<<<1, kThreads, 0, s>>>(part, nb_fnc + nb_sel, sc);
-    HIP_TRY(hipMemcpyAsync(st->hpinned, ptr<uint64_t>(st->ioff) + n_items, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(st->hscratch, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (st->hscratch->err & 1ull) {
-        st->err = "population beyond the fixed-point range of the selection weights";
-        return CCMC_EBLOWUP;
-    }
-    if (st->hscratch->err & 2ull) {
-        st->err = "more than 2^30-2 spawning attempts on one cluster";
-        return CCMC_EOVERFLOW;
-    }
-    const uint64_t n_slots = st->hpinned[0];
-    if (n_slots + ne + 1 >= (1ull << 32)) {
-        st->err = "more than 2^32 record slots in one step";
-        return CCMC_EOVERFLOW;
-    }
-
-    // (a6-a8) records: death and spawning attempts, one lane per slot, compacted per block
-    const bool ids = st->opt.keep_spawn_ids != 0;
-    const uint64_t nblk = (n_slots + kGenSlots - 1) / kGenSlots;
-    if (nblk * kGenSlots > st->rcap) {
-        const uint64_t nc = std::max<uint64_t>(nblk * kGenSlots, st->rcap + st->rcap / 2);
+    if (slot_cap > st->rcap) {
+        const uint64_t nc = slot_cap;
         const uint64_t nb = nc / kGenSlots + 2;
         TRY(ensure(st, st->rkey, nc * W * sizeof(uint64_t)));
         TRY(ensure(st, st->ramp, nc * sizeof(T)));
@@ -603,144 +566,181 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
         st->rcap = nc;
     }
     if (ids && st->rid.bytes < st->rcap * sizeof(uint64_t)) TRY(ensure(st, st->rid, st->rcap * sizeof(uint64_t)));
-    Records reg{nullptr, ptr<uint64_t>(st->rkey), st->ramp.p, ptr<uint64_t>(st->rid), st->rcap};
-    GenStats gst{ptr<uint32_t>(st->gcount), ptr<uint32_t>(st->gspawn), ptr<uint32_t>(st->gdeath)};
-    if (nblk) {
-        k_block_items<<<grid_for(nblk + 1), kThreads, 0, s>>>(ptr<uint64_t>(st->ioff), n_items, nblk, n_slots,
-                                                             ptr<uint64_t>(st->block_item));
-        launch(st, "generate", (double)n_slots * 16.0, (double)n_slots, [&] {
-            k_generate<W, T><<<(unsigned)nblk, kThreads, 0, s>>>(st->sd, it, ptr<uint64_t>(st->ioff),
-                                                                 ptr<uint64_t>(st->block_item), n_fnc, n_slots, a, reg,
-                                                                 ids ? 1 : 0, gst);
-        });
-        TRY(scan<uint32_t>(st, gst.count, ptr<uint32_t>(st->boff), nblk + 1, false));
-        k_gen_stats<<<1, kThreads, 0, s>>>(gst, ptr<uint32_t>(st->boff), nblk, sc);
-    }
-    HIP_TRY(hipMemcpyAsync(st->hscratch, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    Scratch scr = *st->hscratch;
-    const uint64_t nrec = nblk ? scr.n_rec : 0;
-    if (nrec + 1 > st->dcap || ne + nrec + 1 > st->dcap) {
-        const uint64_t nc = std::max<uint64_t>(std::max(nrec, ne) + 1, st->dcap + st->dcap / 2);
+    if (rec_cap + 1 > st->dcap) {
+        const uint64_t nc = rec_cap + 1;
         for (DevBuf *b : {&st->dkey, &st->nkey}) TRY(ensure(st, *b, nc * W * sizeof(uint64_t)));
         TRY(ensure(st, st->damp, nc * sizeof(T)));
         for (DevBuf *b : {&st->drank, &st->sr[0], &st->sr[1], &st->ins, &st->nins, &st->nrank})
             TRY(ensure(st, *b, nc * sizeof(uint64_t)));
-        for (DevBuf *b : {&st->sidx[0], &st->sidx[1], &st->flag, &st->incl, &st->start, &st->is_new, &st->new_pos})
-            TRY(ensure(st, *b, nc * sizeof(uint32_t)));
+        for (DevBuf *b : {&st->sidx[0], &st->sidx[1], &st->is_new, &st->new_pos}) TRY(ensure(st, *b, nc * sizeof(uint32_t)));
         for (DevBuf *b : {&st->seg_sum, &st->nsum}) TRY(ensure(st, *b, nc * sizeof(double)));
         st->dcap = nc;
     }
     if (ids && st->did.bytes < st->dcap * sizeof(uint64_t)) TRY(ensure(st, st->did, st->dcap * sizeof(uint64_t)));
-    const uint64_t dc = st->dcap;
-    Records rec{ptr<uint64_t>(st->drank), ptr<uint64_t>(st->dkey), st->damp.p, ptr<uint64_t>(st->did), dc};
-    if (nrec) {
-        launch(st, "gather", 2.0 * nrec * (kb + 8.0 + tb + (ids ? 8.0 : 0.0)), (double)nrec, [&] {
-            k_gather<W, T><<<grid_for(nrec), kThreads, 0, s>>>(st->sd, reg, ptr<uint32_t>(st->boff), nblk, rec, ids ? 1 : 0,
-                                                               sc);
-        });
-    }
-
-    // the store must be able to take every new determinant
-    TRY(ensure_store<W, T>(st, ne + nrec + 1));
-    skey = ptr<uint64_t>(st->skey[c]);
-    samp = ptr<T>(st->samp[c]);
-    sK = ptr<T>(st->sK[c]);
-    const uint64_t *srank = ptr<uint64_t>(st->srank[c]);
-    const uint64_t S2 = st->scap;
-    TRY(ensure(st, st->keep, (ne + nrec + 1) * sizeof(uint32_t)));
-    TRY(ensure(st, st->pos, (ne + nrec + 1) * sizeof(uint32_t)));
-
-    // (a11) stable LSD radix sort of (rank, record index) over the rank digits that vary
-    const int top = st->rank_bits;
-    std::vector<int> passes;
-    for (int sh = 0; sh < top; sh += 8) passes.push_back(sh);
-    if (passes.empty()) passes.push_back(0);
-    const uint32_t n32 = (uint32_t)nrec;
-    const uint32_t tiles = (uint32_t)std::max<uint64_t>(1, (nrec + kSortTile - 1) / kSortTile);
+    const uint64_t mcap = ne + rec_cap;  // merged store capacity of this step
+    TRY(ensure_store<W, T>(st, mcap + 1));
+    TRY(ensure(st, st->keep, (mcap + 1) * sizeof(uint32_t)));
+    TRY(ensure(st, st->pos, (mcap + 1) * sizeof(uint32_t)));
+    const uint32_t tiles = (uint32_t)((rec_cap + kSortTile - 1) / kSortTile);
     TRY(ensure(st, st->hist, (size_t)256 * tiles * sizeof(uint32_t)));
     TRY(ensure(st, st->hoff, (size_t)256 * tiles * sizeof(uint32_t)));
+    const unsigned nb_fnc = fnc ? grid_for(n_fnc) : 0, nb_sel = n_sel ? grid_for(n_sel) : 0;
+    const size_t nparts = (size_t)(nb_fnc + nb_sel + 1);
+    TRY(ensure(st, st->num_part, nparts * sizeof(double)));
+    TRY(ensure(st, st->att_part, nparts * sizeof(uint64_t)));
+    TRY(ensure(st, st->disc_part, nparts * sizeof(uint64_t)));
+    TRY(ensure(st, st->max_part, nparts * sizeof(uint64_t)));
+    TRY(ensure(st, st->abs_part, (grid_for(mcap) + 1) * sizeof(double)));
+
+    const uint64_t scap = st->scap;
+    const uint64_t *skey = ptr<uint64_t>(st->skey[c]);
+    const T *samp = ptr<T>(st->samp[c]);
+    const T *sK = ptr<T>(st->sK[c]);
+    const uint64_t *srank = ptr<uint64_t>(st->srank[c]);
+    Scratch *sc = ptr<Scratch>(st->scratch);
+    k_fill<uint64_t><<<1, 64, 0, s>>>(reinterpret_cast<uint64_t *>(sc), sizeof(Scratch) / 8, 0ull);
+
+    // ---- (a1) selection weights, formed inside the scan of their prefix; guide table
+    if (ne) {
+        launch(st, "weights_scan", tb + 8.0, nullptr, ne, [&] {
+            (void)scan_src<uint64_t>(st, WeightSrc<T>{samp, sc}, ptr<uint64_t>(st->P), ne, true);
+        });
+        if (n_sel) k_guide<<<grid_for(ne + 1), kThreads, 0, s>>>(ptr<uint64_t>(st->P), ne, sc, ptr<uint32_t>(st->guide));
+    }
+
+    // ---- (a2-a5, a9, a10) items: non-composite (FNC) then sampled clusters
+    Items<T> it{ptr<uint64_t>(st->ikey), ptr<T>(st->iA), ptr<T>(st->ideath), ptr<uint32_t>(st->in),
+                ptr<uint8_t>(st->ilevel), ptr<uint64_t>(st->icnt), st->icap};
+    ItemPartials part{ptr<double>(st->num_part), ptr<uint64_t>(st->att_part), ptr<uint64_t>(st->disc_part),
+                      ptr<uint64_t>(st->max_part)};
+    ItemPartials part_sel{part.num + nb_fnc, part.att + nb_fnc, part.disc + nb_fnc, part.maxn + nb_fnc};
+    const double item_bytes = kb + 2 * tb + 13.0;  // key, A, death, n, level, slot count
+    if (fnc) {
+        launch(st, "noncomposite", kb + 2 * tb + item_bytes, nullptr, n_fnc, [&] {
+            k_noncomposite<W, T><<<nb_fnc, kThreads, 0, s>>>(st->sd, skey, samp, sK, scap, ne, st->n0, a, it, part, sc);
+        });
+    }
+    if (n_sel) {
+        launch(st, "select", item_bytes, nullptr, n_sel, [&] {
+            k_select<W, T><<<nb_sel, kThreads, 0, s>>>(st->sd, skey, samp, scap, ne, ptr<uint64_t>(st->P),
+                                                        ptr<uint32_t>(st->guide), st->n0, a, it, n_fnc, part_sel, sc);
+        });
+    } else {
+        k_fill<uint64_t><<<1, 1, 0, s>>>(it.cnt + n_items, 1, 0ull);
+    }
+    k_item_stats<<<1, kThreads, 0, s>>>(part, nb_fnc + nb_sel, sc);
+    TRY(scan<uint64_t>(st, it.cnt, ptr<uint64_t>(st->ioff), n_items + 1, false));
+
+    // ---- (a6-a8) records: death and spawning attempts, one lane per slot, compacted per block
+    Records reg{nullptr, ptr<uint64_t>(st->rkey), st->ramp.p, ptr<uint64_t>(st->rid), st->rcap};
+    GenStats gst{ptr<uint32_t>(st->gcount), ptr<uint32_t>(st->gspawn), ptr<uint32_t>(st->gdeath)};
+    k_block_items<<<grid_for(nblk_cap + 1), kThreads, 0, s>>>(ptr<uint64_t>(st->ioff), n_items, slot_cap,
+                                                             ptr<uint64_t>(st->block_item), sc);
+    launch(st, "generate", kb + tb, &st->cnt_rec, 0, [&] {
+        k_generate<W, T><<<(unsigned)nblk_cap, kThreads, 0, s>>>(st->sd, it, ptr<uint64_t>(st->ioff),
+                                                                 ptr<uint64_t>(st->block_item), n_fnc, n_items, slot_cap, a,
+                                                                 reg, ids ? 1 : 0, gst);
+    });
+    TRY(scan<uint32_t>(st, gst.count, ptr<uint32_t>(st->boff), nblk_cap + 1, false));
+    k_gen_stats<<<1, kThreads, 0, s>>>(gst, ptr<uint32_t>(st->boff), nblk_cap, rec_cap, sc);
+    const uint64_t dc = st->dcap;
+    Records rec{ptr<uint64_t>(st->drank), ptr<uint64_t>(st->dkey), st->damp.p, ptr<uint64_t>(st->did), dc};
+    launch(st, "gather", 2.0 * (kb + tb + (ids ? 8.0 : 0.0)) + 8.0, &st->cnt_rec, 0, [&] {
+        k_gather<W, T><<<grid_for(rec_cap), kThreads, 0, s>>>(st->sd, reg, ptr<uint32_t>(st->boff), nblk_cap, rec,
+                                                              ids ? 1 : 0, sc);
+    });
+
+    // ---- (a11) stable LSD radix sort of (rank, record index) over the rank bits
+    const uint64_t *n_live = &sc->n_live;
     const uint64_t *kin = ptr<uint64_t>(st->drank);
     const uint32_t *iin = nullptr;
     int ob = 0;
-    if (nrec) {
-        for (int sh : passes) {
-            uint64_t *kout = ptr<uint64_t>(st->sr[ob]);
-            uint32_t *iout = ptr<uint32_t>(st->sidx[ob]);
-            launch(st, "radix_hist", nrec * 8.0, (double)nrec, [&] {
-                k_radix_hist<1><<<tiles, kThreads, 0, s>>>(kin, dc, n32, 0, sh, ptr<uint32_t>(st->hist), tiles);
-            });
-            TRY(scan<uint32_t>(st, ptr<uint32_t>(st->hist), ptr<uint32_t>(st->hoff), (uint64_t)256 * tiles, false));
-            launch(st, "radix_scatter", nrec * (2 * 8.0 + (iin ? 8.0 : 4.0)), (double)nrec, [&] {
-                k_radix_scatter<1><<<tiles, kThreads, 0, s>>>(kin, iin, kout, iout, dc, n32, 0, sh, ptr<uint32_t>(st->hoff),
-                                                              tiles);
-            });
-            kin = kout;
-            iin = iout;
-            ob ^= 1;
-        }
+    for (int sh = 0; sh < std::max(st->rank_bits, 1); sh += 8) {
+        uint64_t *kout = ptr<uint64_t>(st->sr[ob]);
+        uint32_t *iout = ptr<uint32_t>(st->sidx[ob]);
+        launch(st, "radix_hist", 8.0, &st->cnt_rec, 0, [&] {
+            k_radix_hist<1><<<tiles, kThreads, 0, s>>>(kin, dc, n_live, 0, sh, ptr<uint32_t>(st->hist), tiles);
+        });
+        TRY(scan<uint32_t>(st, ptr<uint32_t>(st->hist), ptr<uint32_t>(st->hoff), (uint64_t)256 * tiles, false));
+        launch(st, "radix_scatter", 2 * 8.0 + (iin ? 8.0 : 4.0), &st->cnt_rec, 0, [&] {
+            k_radix_scatter<1><<<tiles, kThreads, 0, s>>>(kin, iin, kout, iout, dc, n_live, 0, sh, ptr<uint32_t>(st->hoff),
+                                                          tiles);
+        });
+        kin = kout;
+        iin = iout;
+        ob ^= 1;
     }
     const uint64_t *sorted_rank = kin;
     const uint32_t *sorted_idx = iin;
 
-    // (a12) segments: heads, left fold in record order, store lookup by rank
+    // ---- (a12) runs of equal determinants: left fold in record order, store lookup by rank
     double *delta = ptr<double>(st->delta);
-    if (ne) k_fill<double><<<grid_for(ne), kThreads, 0, s>>>(delta, ne, 0.0);
-    if (nrec) {
-        uint32_t *flag = ptr<uint32_t>(st->flag), *incl = ptr<uint32_t>(st->incl), *start = ptr<uint32_t>(st->start);
-        k_seg_flags<<<grid_for(nrec), kThreads, 0, s>>>(sorted_rank, n32, flag);
-        TRY(scan<uint32_t>(st, flag, incl, nrec, true));
-        k_seg_starts<<<grid_for(nrec), kThreads, 0, s>>>(flag, incl, n32, start, sc);
-        k_fill<uint32_t><<<grid_for(nrec), kThreads, 0, s>>>(ptr<uint32_t>(st->is_new), nrec, 0u);
-        launch(st, "seg_fold", nrec * (8.0 + 4.0 + tb), (double)nrec, [&] {
-            k_seg_fold<T><<<grid_for(nrec), kThreads, 0, s>>>(sorted_rank, sorted_idx, ptr<T>(st->damp), n32, start, srank, ne,
-                                                              delta, ptr<uint32_t>(st->is_new), ptr<uint64_t>(st->ins),
-                                                              ptr<double>(st->seg_sum), sc);
-        });
-        TRY(scan<uint32_t>(st, ptr<uint32_t>(st->is_new), ptr<uint32_t>(st->new_pos), nrec, false));
-        k_new_compact<W><<<grid_for(nrec), kThreads, 0, s>>>(sorted_rank, sorted_idx, ptr<uint64_t>(st->dkey), dc, start,
-                                                             ptr<uint32_t>(st->is_new), ptr<uint32_t>(st->new_pos),
-                                                             ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum),
-                                                             ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), dc,
-                                                             ptr<uint64_t>(st->nins), ptr<double>(st->nsum), sc);
-    }
-    // merge into the other store buffer, round, compact back into the current buffer
+    launch(st, "seg_fold", 8.0 + 4.0 + tb, &st->cnt_rec, 0, [&] {
+        k_seg_fold<T><<<grid_for(rec_cap), kThreads, 0, s>>>(sorted_rank, sorted_idx, ptr<T>(st->damp), rec_cap, srank, ne,
+                                                             delta, ptr<uint32_t>(st->is_new), ptr<uint64_t>(st->ins),
+                                                             ptr<double>(st->seg_sum), sc);
+    });
+    TRY(scan<uint32_t>(st, ptr<uint32_t>(st->is_new), ptr<uint32_t>(st->new_pos), rec_cap, false));
+    k_new_compact<W><<<grid_for(rec_cap), kThreads, 0, s>>>(sorted_rank, sorted_idx, ptr<uint64_t>(st->dkey), dc, rec_cap,
+                                                            ptr<uint32_t>(st->is_new), ptr<uint32_t>(st->new_pos),
+                                                            ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum),
+                                                            ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), dc,
+                                                            ptr<uint64_t>(st->nins), ptr<double>(st->nsum), sc);
+
+    // ---- (a12, a13) merge and round into the other store buffer, compact back into this one
     const int m = 1 - c;
+    const uint64_t S2 = st->scap;
     uint64_t *mkey = ptr<uint64_t>(st->skey[m]);
     T *mamp = ptr<T>(st->samp[m]);
     T *mK = ptr<T>(st->sK[m]);
     uint64_t *mrank = ptr<uint64_t>(st->srank[m]);
-    const uint64_t nmax = ne + nrec;
+    uint32_t *keep = ptr<uint32_t>(st->keep), *pos = ptr<uint32_t>(st->pos);
     const double eb = kb + 2 * tb + 8.0;  // one store entry: key, amplitude, diagonal, rank
-    if (nmax) {
-        launch(st, "merge", (double)nmax * 2.0 * eb, (double)nmax, [&] {
-            k_merge<W, T><<<grid_for(nmax), kThreads, 0, s>>>(st->sd, skey, samp, sK, srank, S2, ne, delta,
-                                                              ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), dc,
-                                                              ptr<uint64_t>(st->nins), ptr<double>(st->nsum), mkey, mamp, mK,
-                                                              mrank, S2, sc);
-        });
-        uint32_t *keep = ptr<uint32_t>(st->keep), *pos = ptr<uint32_t>(st->pos);
-        launch(st, "round", (double)nmax * (2 * tb + 4.0), (double)nmax, [&] {
-            k_round<T><<<grid_for(nmax), kThreads, 0, s>>>(mamp, ne, a, keep, sc);
-        });
-        TRY(scan<uint32_t>(st, keep, pos, nmax, false));
-        TRY(ensure(st, st->abs_part, grid_for(nmax) * sizeof(double)));
-        launch(st, "compact", (double)nmax * 2.0 * eb, (double)nmax, [&] {
-            k_compact<W, T><<<grid_for(nmax), kThreads, 0, s>>>(mkey, mamp, mK, mrank, S2, ne, keep, pos,
-                                                                ptr<uint64_t>(st->skey[c]), ptr<T>(st->samp[c]),
-                                                                ptr<T>(st->sK[c]), ptr<uint64_t>(st->srank[c]), S2,
-                                                                ptr<double>(st->abs_part), sc);
-        });
-        k_reduce_partials<<<1, kThreads, 0, s>>>(ptr<double>(st->abs_part), grid_for(nmax), &sc->n_total);
-    }
+    launch(st, "merge", 2.0 * eb, &st->cnt_merged, 0, [&] {
+        k_merge<W, T><<<grid_for(mcap), kThreads, 0, s>>>(st->sd, skey, samp, sK, srank, S2, ne, delta,
+                                                          ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), dc,
+                                                          ptr<uint64_t>(st->nins), ptr<double>(st->nsum), mkey, mamp, mK, mrank,
+                                                          S2, mcap, a, keep, sc);
+    });
+    TRY(scan<uint32_t>(st, keep, pos, mcap, false));
+    launch(st, "compact", 2.0 * eb, &st->cnt_merged, 0, [&] {
+        k_compact<W, T><<<grid_for(mcap), kThreads, 0, s>>>(mkey, mamp, mK, mrank, S2, mcap, keep, pos,
+                                                            ptr<uint64_t>(st->skey[c]), ptr<T>(st->samp[c]), ptr<T>(st->sK[c]),
+                                                            ptr<uint64_t>(st->srank[c]), S2, delta, ptr<double>(st->abs_part),
+                                                            sc);
+    });
+    k_reduce_partials<<<1, kThreads, 0, s>>>(ptr<double>(st->abs_part), grid_for(mcap), &sc->n_total);
+
+    // ---- (a14) the one synchronisation of the step
     HIP_TRY(hipMemcpyAsync(st->hscratch, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    scr = *st->hscratch;
+    const Scratch scr = *st->hscratch;
+    st->cnt_slots = scr.n_slots;
+    st->cnt_rec = scr.n_live;
+    st->cnt_merged = ne + scr.n_new;
     if (st->prof) resolve_profile(st);
-
+    // plan the next step's capacities from this one
+    st->slot_hint = std::max(st->slot_hint, scr.n_slots + scr.n_slots / 4 + 4096);
+    st->rec_hint = std::max(st->rec_hint, scr.n_rec + scr.n_rec / 4 + 4096);
+    if (scr.err) {
+        // the compaction did not run; clear the sums the fold may have left behind
+        if (ne) k_fill<double><<<grid_for(ne), kThreads, 0, s>>>(delta, ne, 0.0);
+        HIP_TRY(hipStreamSynchronize(s));
+        if (scr.err & kErrBlowup) {
+            st->err = "population beyond the fixed-point range of the selection weights";
+            return CCMC_EBLOWUP;
+        }
+        if (scr.err & kErrAttempts) {
+            st->err = "more than 2^30-2 spawning attempts on one cluster";
+            return CCMC_EOVERFLOW;
+        }
+        *replay = true;  // a capacity was exceeded: grow and replay
+        return CCMC_OK;
+    }
+    const uint64_t nrec = scr.n_live;
     const double n0_old = st->n0;
     if (scr.hf_hit) st->n0 = st->n0 + scr.hf_sum;
-    st->ne = nmax ? scr.n_out : 0;
+    st->ne = scr.n_out;
     st->step += 1;
     st->last_num = scr.num;
     st->last_den = n0_old;
@@ -761,6 +761,18 @@ ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
         out->eproj_den = n0_old;
     }
     return CCMC_OK;
+}
+
+template <int W, typename T>
+ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, ccmc_stats *out)
+{
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        bool replay = false;
+        TRY(step_once<W, T>(st, tau, shift, n_sel, out, &replay));
+        if (!replay) return CCMC_OK;
+    }
+    st->err = "step capacity did not converge";
+    return CCMC_ENOMEM;
 }
 
 template <int W, typename T>
@@ -821,6 +833,7 @@ ccmc_status import_impl(ccmc_state *st, const uint64_t *keys, const double *amps
         HIP_TRY(hipMemcpy(st->samp[c].p, ta.data(), n * sizeof(T), hipMemcpyHostToDevice));
         k_store_init<W, T><<<grid_for(n), kThreads, 0, st->stream>>>(st->sd, ptr<uint64_t>(st->skey[c]), cap, n,
                                                                      ptr<T>(st->sK[c]), ptr<uint64_t>(st->srank[c]));
+        k_fill<double><<<grid_for(n), kThreads, 0, st->stream>>>(ptr<double>(st->delta), n, 0.0);
         HIP_TRY(hipStreamSynchronize(st->stream));
     }
     st->ne = n;

@@ -20,17 +20,20 @@ namespace ccmc {
 constexpr int kGenRounds = 4;                       // rounds of 256 slots per generation block
 constexpr int kGenSlots = kThreads * kGenRounds;    // slots (and region capacity) per block
 
+constexpr uint64_t kErrBlowup = 1, kErrAttempts = 2, kErrSlotCap = 4, kErrRecCap = 8;
+
 // Device-side scalars of one step.
 struct Scratch {
     uint64_t qtot;
-    uint64_t err;             // bit 0: |N| too large; bit 1: too many attempts on a cluster
+    uint64_t err;             // kErr* bits; any bit makes the final compaction a no-op
     uint64_t n_discarded;
     uint64_t n_attempts;
     uint64_t n_spawns;
     uint64_t n_deaths;
     uint64_t max_n;
+    uint64_t n_slots;         // record slots of the step (deaths + attempts)
     uint64_t n_rec;           // records emitted by the step
-    uint64_t rank_or;         // OR of all record ranks (digits that can vary)
+    uint64_t n_live;          // records the annihilation works on (0 after an overflow)
     uint64_t guide_n;         // entries of the selection guide table
     uint32_t guide_shift;
     uint32_t n_seg;
@@ -99,7 +102,7 @@ __device__ __forceinline__ uint32_t attempt_count(T A, double thr, uint32_t kmin
     if (thr > 0) {
         const double f = floor(fabs((double)A) / thr);
         if (!(f <= (double)kMaxAttempts)) {
-            atomicOr((unsigned long long *)err, 2ull);
+            atomicOr((unsigned long long *)err, (unsigned long long)kErrAttempts);
             return kMaxAttempts;
         }
         if ((uint32_t)f > k) k = (uint32_t)f;
@@ -108,52 +111,58 @@ __device__ __forceinline__ uint32_t attempt_count(T A, double thr, uint32_t kmin
 }
 
 // ------------------------------------------------------------------------ weights
-// q_i = max(1, rint(|N_i| 2^24)): the prefix of q is exact, so the excitor drawn for a
-// given random number does not depend on the summation order (Sec. II: probability
-// |t_i| / (N_tot - t_HF)).
+// q_i = max(1, rint(|N_i| 2^24)), formed while the inclusive prefix P is scanned: the prefix
+// is exact, so the excitor drawn for a given random number does not depend on the
+// summation order (Sec. II: probability |t_i| / (N_tot - t_HF)).
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_weights(const T *__restrict__ amp, uint64_t n, uint64_t *__restrict__ q,
-                                                      Scratch *sc)
-{
-    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
-    const double a = fabs((double)amp[i]);
-    if (!(a < 0x1.0p28)) atomicOr((unsigned long long *)&sc->err, 1ull);
-    double w = rint(a * 16777216.0);
-    if (w < 1.0) w = 1.0;
-    q[i] = (uint64_t)fmin(w, 0x1.0p60);
-}
+struct WeightSrc {
+    const T *amp;
+    Scratch *sc;
+    __device__ __forceinline__ uint64_t operator()(uint64_t i) const
+    {
+        const double a = fabs((double)amp[i]);
+        if (!(a < 0x1.0p28)) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrBlowup);
+        double w = rint(a * 16777216.0);
+        if (w < 1.0) w = 1.0;
+        return (uint64_t)fmin(w, 0x1.0p40);
+    }
+};
 
 // Q and the guide table of the excitor draws.  A draw r in [0, Q) falls in bucket r >> shift;
 // guide[b] is the first excitor whose prefix exceeds b << shift, so the drawn excitor lies
 // in [guide[b], guide[b+1]] -- a short search instead of one over the whole store.  With
 // about two buckets per excitor the range is usually a single entry.
-__global__ void k_guide_setup(const uint64_t *__restrict__ P, uint64_t n, Scratch *sc)
+__device__ __forceinline__ uint32_t guide_shift(uint64_t Q, uint64_t n)
 {
-    const uint64_t Q = n ? P[n - 1] : 0;
-    sc->qtot = Q;
-    if (Q > (1ull << 53)) atomicOr((unsigned long long *)&sc->err, 1ull);
     uint32_t sh = 0;
     while (sh < 63 && (Q >> sh) + 2 > 2 * n + 2) ++sh;
-    sc->guide_shift = sh;
-    sc->guide_n = n ? (Q >> sh) + 2 : 0;
+    return sh;
 }
 
-__global__ void __launch_bounds__(kThreads) k_guide(const uint64_t *__restrict__ P, uint64_t n, const Scratch *sc,
+// Built by scattering: bucket b holds the first i with P[i] > b << shift, so excitor i owns
+// the buckets b with P[i-1] <= b << shift < P[i] (usually none, one or two); lane n writes
+// the closing entries.  No search, one lane per excitor.
+__global__ void __launch_bounds__(kThreads) k_guide(const uint64_t *__restrict__ P, uint64_t n, Scratch *sc,
                                                     uint32_t *__restrict__ guide)
 {
-    const uint64_t b = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (b >= sc->guide_n) return;
-    const uint64_t x = b << sc->guide_shift;
-    uint64_t l0 = 0, h0 = n;  // first i with P[i] > x
-    while (l0 < h0) {
-        const uint64_t mid = (l0 + h0) >> 1;
-        if (P[mid] > x)
-            h0 = mid;
-        else
-            l0 = mid + 1;
+    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint64_t Q = n ? P[n - 1] : 0;
+    const uint32_t sh = guide_shift(Q, n);
+    const uint64_t nb = n ? (Q >> sh) + 2 : 0;
+    if (i == 0) {
+        sc->qtot = Q;
+        sc->guide_shift = sh;
+        sc->guide_n = nb;
+        if (Q > (1ull << 53)) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrBlowup);
     }
-    guide[b] = (uint32_t)(l0 < n ? l0 : n - 1);
+    if (i > n || n == 0) return;
+    const uint64_t unit = 1ull << sh;
+    if (i == n) {  // buckets at or beyond Q
+        for (uint64_t b = (Q + unit - 1) >> sh; b < nb; ++b) guide[b] = (uint32_t)(n - 1);
+        return;
+    }
+    const uint64_t lo = i ? P[i - 1] : 0, hi = P[i];
+    for (uint64_t b = (lo + unit - 1) >> sh; (b << sh) < hi && b < nb; ++b) guide[b] = (uint32_t)i;
 }
 
 // ------------------------------------------------------- non-composite items (FNC)
@@ -459,11 +468,19 @@ __device__ __forceinline__ bool spawn_attempt(const SysDev &S, const uint64_t *d
 
 // First item of each generation block (last item whose offset is <= the block's first slot);
 // entry n_blocks holds the item of the last slot.
-__global__ void __launch_bounds__(kThreads) k_block_items(const uint64_t *__restrict__ off, uint64_t n_items, uint64_t n_blocks,
-                                                          uint64_t n_slots, uint64_t *__restrict__ block_item)
+// The live slot count is off[n_items]; blocks beyond it (up to the region capacity) idle.
+__global__ void __launch_bounds__(kThreads) k_block_items(const uint64_t *__restrict__ off, uint64_t n_items,
+                                                          uint64_t slot_cap, uint64_t *__restrict__ block_item, Scratch *sc)
 {
     const uint64_t u = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (u > n_blocks) return;
+    const uint64_t n_slots_all = off[n_items];
+    if (u == 0) {
+        sc->n_slots = n_slots_all;
+        if (n_slots_all > slot_cap) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrSlotCap);
+    }
+    const uint64_t n_slots = n_slots_all < slot_cap ? n_slots_all : slot_cap;
+    const uint64_t n_blocks = (n_slots + kGenSlots - 1) / kGenSlots;
+    if (u > n_blocks || n_slots == 0) return;
     const uint64_t g = u < n_blocks ? u * kGenSlots : n_slots - 1;
     uint64_t l0 = 0, h0 = n_items + 1;
     while (l0 < h0) {
@@ -488,12 +505,19 @@ struct GenStats {
 template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, const uint64_t *__restrict__ off,
                                                        const uint64_t *__restrict__ block_item, uint64_t n_fnc,
-                                                       uint64_t n_slots, StepArgs a, Records rec, int keep_ids, GenStats gs)
+                                                       uint64_t n_items, uint64_t slot_cap, StepArgs a, Records rec,
+                                                       int keep_ids, GenStats gs)
 {
     __shared__ uint64_t s_off[kGenLdsItems + 1];
     __shared__ uint32_t wave_tot[kWaves];
     T *ramp = static_cast<T *>(rec.amp);
     const uint64_t g0 = (uint64_t)blockIdx.x * kGenSlots;
+    const uint64_t n_slots = off[n_items] < slot_cap ? off[n_items] : slot_cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) gs.count[gridDim.x] = 0;  // closing entry of the scan
+    if (g0 >= n_slots) {  // idle block (the grid covers the capacity)
+        if (threadIdx.x == 0) gs.count[blockIdx.x] = gs.spawns[blockIdx.x] = gs.deaths[blockIdx.x] = 0;
+        return;
+    }
     const uint64_t lo = block_item[blockIdx.x], hi = block_item[blockIdx.x + 1];
     const bool lds = hi - lo + 1 <= (uint64_t)kGenLdsItems;
     if (lds)
@@ -577,24 +601,36 @@ __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, co
         gs.spawns[blockIdx.x] = bs;
         gs.deaths[blockIdx.x] = bd;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) gs.count[gridDim.x] = 0;  // closing entry of the scan
 }
 
 // Sums of the per-block generation statistics (one block).
 __global__ void __launch_bounds__(kThreads) k_gen_stats(GenStats gs, const uint32_t *__restrict__ boff, uint64_t n_blocks,
-                                                        Scratch *sc)
+                                                        uint64_t rec_cap, Scratch *sc)
 {
     uint64_t sp = 0, de = 0;
-    for (uint64_t b = threadIdx.x; b < n_blocks; b += kThreads) {
-        sp += gs.spawns[b];
-        de += gs.deaths[b];
+    for (uint64_t b0 = 0; b0 < n_blocks; b0 += 4 * kThreads) {
+        uint32_t x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t b = b0 + (uint64_t)u * kThreads + threadIdx.x;
+            x[u] = b < n_blocks ? gs.spawns[b] : 0u;
+            y[u] = b < n_blocks ? gs.deaths[b] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            sp += x[u];
+            de += y[u];
+        }
     }
     sp = block_reduce_sum(sp);
     de = block_reduce_sum(de);
     if (threadIdx.x == 0) {
         sc->n_spawns = sp;
         sc->n_deaths = de;
-        sc->n_rec = boff[n_blocks];
+        const uint64_t nr = boff[n_blocks];
+        sc->n_rec = nr;
+        if (nr > rec_cap) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrRecCap);
+        sc->n_live = (sc->err & (kErrSlotCap | kErrRecCap)) ? 0 : nr;
     }
 }
 
@@ -605,7 +641,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(const SysDev S, Records reg
                                                      uint64_t n_blocks, Records out, int keep_ids, const Scratch *sc)
 {
     const uint64_t r = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (r >= sc->n_rec) return;
+    if (r >= sc->n_live) return;
     uint64_t l0 = 0, h0 = n_blocks + 1;  // last b with boff[b] <= r
     while (l0 < h0) {
         const uint64_t mid = (l0 + h0) >> 1;
@@ -629,92 +665,97 @@ __global__ void __launch_bounds__(kThreads) k_gather(const SysDev S, Records reg
 
 // ---------------------------------------------------------------- annihilation
 // Records are sorted by rank (equal ranks = equal determinants, ascending rank = ascending
-// key).  Segment heads:
-__global__ void __launch_bounds__(kThreads) k_seg_flags(const uint64_t *__restrict__ rank, uint32_t n,
-                                                        uint32_t *__restrict__ flag)
-{
-    const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
-    if (r >= n) return;
-    flag[r] = (r == 0 || rank[r] != rank[r - 1]) ? 1u : 0u;
-}
-
-__global__ void __launch_bounds__(kThreads) k_seg_starts(const uint32_t *__restrict__ flag, const uint32_t *__restrict__ incl,
-                                                         uint32_t n, uint32_t *__restrict__ start, Scratch *sc)
-{
-    const uint32_t r = blockIdx.x * kThreads + threadIdx.x;
-    if (r >= n) return;
-    if (flag[r]) start[incl[r] - 1] = r;
-    if (r == n - 1) sc->n_seg = incl[r];
-}
-
-// One lane per determinant: left fold of its records in id order (contiguous and in id
-// order after the stable sort), then a binary search of its rank in the store.  A hit adds
-// to that entry, the reference (rank 0) adds to N_0, a miss becomes a new excitor.
+// key).  One lane per record: the first record of each determinant folds the run of its
+// records left to right (they are contiguous and in id order after the stable sort), then
+// looks the rank up in the store.  A hit adds to that entry, the reference (rank 0) adds to
+// N_0, a miss becomes a new excitor at insertion point ins.  Lanes up to the capacity write
+// is_new = 0 so that the scan of is_new needs no live count.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_seg_fold(const uint64_t *__restrict__ rank, const uint32_t *__restrict__ idx,
-                                                       const T *__restrict__ ramp, uint32_t n, const uint32_t *__restrict__ start,
+                                                       const T *__restrict__ ramp, uint64_t cap,
                                                        const uint64_t *__restrict__ srank, uint64_t ne,
                                                        double *__restrict__ delta, uint32_t *__restrict__ is_new,
                                                        uint64_t *__restrict__ ins, double *__restrict__ seg_sum, Scratch *sc)
 {
-    const uint32_t s = blockIdx.x * kThreads + threadIdx.x;
-    const uint32_t nseg = sc->n_seg;
-    if (s >= nseg) return;
-    const uint32_t r0 = start[s], r1 = (s + 1 < nseg) ? start[s + 1] : n;
-    double acc = (double)ramp[idx[r0]];
-    for (uint32_t r = r0 + 1; r < r1; ++r) acc += (double)ramp[idx[r]];
-    const uint64_t rk = rank[r0];
+    const uint64_t r = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= cap) return;
+    const uint64_t n = sc->n_live;
     uint32_t fresh = 0;
-    uint64_t pos = 0;
-    if (rk == 0) {
-        sc->hf_sum = acc;
-        sc->hf_hit = 1;
-    } else {
-        uint64_t l0 = 0, h0 = ne;  // first store entry with rank >= rk
-        while (l0 < h0) {
-            const uint64_t mid = (l0 + h0) >> 1;
-            if (srank[mid] < rk)
-                l0 = mid + 1;
-            else
-                h0 = mid;
+    if (r < n && (r == 0 || rank[r] != rank[r - 1])) {
+        const uint64_t rk = rank[r];
+        double acc = (double)ramp[idx[r]];
+        // the run is walked eight records per round: its ranks, indices and amplitudes are
+        // loaded together, then added in record order
+        bool more = true;
+        for (uint64_t t0 = r + 1; more && t0 < n; t0 += 8) {
+            uint64_t rr[8];
+            uint32_t ii[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                rr[u] = (t0 + u < n) ? rank[t0 + u] : ~0ull;
+                ii[u] = (t0 + u < n) ? idx[t0 + u] : 0u;
+            }
+            T vv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) vv[u] = (rr[u] == rk) ? ramp[ii[u]] : T(0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                more = more && rr[u] == rk;
+                if (more) acc += (double)vv[u];
+            }
         }
-        if (l0 < ne && srank[l0] == rk)
-            delta[l0] = acc;
-        else
-            fresh = 1;
-        pos = l0;
+        uint64_t pos = 0;
+        if (rk == 0) {
+            sc->hf_sum = acc;
+            sc->hf_hit = 1;
+        } else {
+            uint64_t l0 = 0, h0 = ne;  // first store entry with rank >= rk
+            while (l0 < h0) {
+                const uint64_t mid = (l0 + h0) >> 1;
+                if (srank[mid] < rk)
+                    l0 = mid + 1;
+                else
+                    h0 = mid;
+            }
+            if (l0 < ne && srank[l0] == rk)
+                delta[l0] = acc;
+            else
+                fresh = 1;
+            pos = l0;
+        }
+        ins[r] = pos;
+        seg_sum[r] = acc;
     }
-    is_new[s] = fresh;
-    ins[s] = pos;
-    seg_sum[s] = acc;
+    is_new[r] = fresh;
 }
 
 template <int W>
 __global__ void __launch_bounds__(kThreads) k_new_compact(const uint64_t *__restrict__ rank, const uint32_t *__restrict__ idx,
-                                                          const uint64_t *__restrict__ rkey, uint64_t rstride,
-                                                          const uint32_t *__restrict__ start, const uint32_t *__restrict__ is_new,
+                                                          const uint64_t *__restrict__ rkey, uint64_t rstride, uint64_t cap,
+                                                          const uint32_t *__restrict__ is_new,
                                                           const uint32_t *__restrict__ new_pos, const uint64_t *__restrict__ ins,
                                                           const double *__restrict__ seg_sum, uint64_t *__restrict__ nkey,
                                                           uint64_t *__restrict__ nrank, uint64_t nstride,
                                                           uint64_t *__restrict__ nins, double *__restrict__ nsum, Scratch *sc)
 {
-    const uint32_t s = blockIdx.x * kThreads + threadIdx.x;
-    const uint32_t nseg = sc->n_seg;
-    if (s >= nseg) return;
-    if (s == nseg - 1) sc->n_new = new_pos[s] + is_new[s];
-    if (!is_new[s]) return;
-    const uint32_t j = new_pos[s];
-    const uint32_t r0 = start[s];
-    const uint32_t src = idx[r0];  // any record of the segment carries its bitstring
+    const uint64_t r = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (r >= cap) return;
+    if (r == cap - 1) sc->n_new = new_pos[r] + is_new[r];
+    if (!is_new[r]) return;
+    const uint32_t j = new_pos[r];
+    const uint32_t src = idx[r];  // any record of the run carries its bitstring
 #pragma unroll
     for (int w = 0; w < W; ++w) nkey[(uint64_t)w * nstride + j] = rkey[(uint64_t)w * rstride + src];
-    nrank[j] = rank[r0];
-    nins[j] = ins[s];
-    nsum[j] = seg_sum[s];
+    nrank[j] = rank[r];
+    nins[j] = ins[r];
+    nsum[j] = seg_sum[r];
 }
 
-// Merge the store (with its sums added) and the new determinants into key order.
-// Store entry i lands at i + #(new with ins <= i); new entry j at ins_j + j.
+// Merge the store (with its sums added) and the new determinants into key order, then
+// apply real-weight occupation rounding at each merged position k: 0 < |N| < theta becomes
+// +-theta with probability |N| / theta, else 0, from a Philox draw keyed by k (the reference
+// is exempt).  Store entry i lands at i + #(new with ins <= i); new entry j at ins_j + j.
+// Positions beyond the merged size (up to the capacity) get keep = 0.
 template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_merge(const SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
                                                     const T *__restrict__ sK, const uint64_t *__restrict__ srank,
@@ -723,11 +764,18 @@ __global__ void __launch_bounds__(kThreads) k_merge(const SysDev S, const uint64
                                                     uint64_t nstride, const uint64_t *__restrict__ nins,
                                                     const double *__restrict__ nsum, uint64_t *__restrict__ mkey,
                                                     T *__restrict__ mamp, T *__restrict__ mK, uint64_t *__restrict__ mrank,
-                                                    uint64_t mstride, Scratch *sc)
+                                                    uint64_t mstride, uint64_t cap, StepArgs a, uint32_t *__restrict__ keep,
+                                                    Scratch *sc)
 {
     const uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     const uint64_t nn = sc->n_new;
-    if (t >= ne + nn) return;
+    if (t >= cap) return;
+    if (t >= ne + nn) {
+        keep[t] = 0;
+        return;
+    }
+    uint64_t pos;
+    T v;
     if (t < ne) {
         uint64_t l0 = 0, h0 = nn;  // new entries with ins <= t
         while (l0 < h0) {
@@ -737,67 +785,60 @@ __global__ void __launch_bounds__(kThreads) k_merge(const SysDev S, const uint64
             else
                 h0 = mid;
         }
-        const uint64_t pos = t + l0;
+        pos = t + l0;
 #pragma unroll
         for (int w = 0; w < W; ++w) mkey[(uint64_t)w * mstride + pos] = skey[(uint64_t)w * sstride + t];
-        mamp[pos] = (T)((double)samp[t] + delta[t]);
+        v = (T)((double)samp[t] + delta[t]);
         mK[pos] = sK[t];
         mrank[pos] = srank[t];
     } else {
         const uint64_t j = t - ne;
-        const uint64_t pos = nins[j] + j;
+        pos = nins[j] + j;
         uint64_t d[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             d[w] = nkey[(uint64_t)w * nstride + j];
             mkey[(uint64_t)w * mstride + pos] = d[w];
         }
-        mamp[pos] = (T)nsum[j];
+        v = (T)nsum[j];
         mK[pos] = diagonal<W, T>(S, d);
         mrank[pos] = nrank[j];
     }
-}
-
-// Real-weight occupation rounding: 0 < |N| < theta becomes +-theta with probability
-// |N| / theta, else 0, with a Philox draw keyed by the merged position (reference exempt).
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_round(T *__restrict__ amp, uint64_t ne, StepArgs a, uint32_t *__restrict__ keep,
-                                                    Scratch *sc)
-{
-    const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    const uint64_t n = ne + sc->n_new;
-    if (k >= n) return;
-    T v = amp[k];
     if (v != T(0) && fabs((double)v) < a.theta) {
-        Draws r(a.key0, a.key1, kRound, (uint32_t)k, 0u, a.step);
+        Draws r(a.key0, a.key1, kRound, (uint32_t)pos, 0u, a.step);
         const double u = uniform53(r.get(0));
         v = (u < fabs((double)v) / a.theta) ? (T)copysign(a.theta, (double)v) : T(0);
-        amp[k] = v;
     }
-    keep[k] = (v != T(0)) ? 1u : 0u;
+    mamp[pos] = v;
+    keep[pos] = (v != T(0)) ? 1u : 0u;
 }
 
+// Compaction of the merged store back into the current buffer (the only write to the
+// state; skipped after any error, so that a failed step leaves the state unchanged).  The
+// per-entry sum buffer of the next step is cleared on the way.
 template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_compact(const uint64_t *__restrict__ mkey, const T *__restrict__ mamp,
                                                       const T *__restrict__ mK, const uint64_t *__restrict__ mrank,
-                                                      uint64_t mstride, uint64_t ne, const uint32_t *__restrict__ keep,
+                                                      uint64_t mstride, uint64_t cap, const uint32_t *__restrict__ keep,
                                                       const uint32_t *__restrict__ pos, uint64_t *__restrict__ okey,
                                                       T *__restrict__ oamp, T *__restrict__ oK, uint64_t *__restrict__ orank,
-                                                      uint64_t ostride, double *__restrict__ abs_part, Scratch *sc)
+                                                      uint64_t ostride, double *__restrict__ delta,
+                                                      double *__restrict__ abs_part, Scratch *sc)
 {
     const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    const uint64_t n = ne + sc->n_new;
+    const bool ok = sc->err == 0;
     double a = 0.0;
-    if (k < n && keep[k]) {
+    if (ok && k < cap && keep[k]) {
         const uint32_t p = pos[k];
 #pragma unroll
         for (int w = 0; w < W; ++w) okey[(uint64_t)w * ostride + p] = mkey[(uint64_t)w * mstride + k];
         oamp[p] = mamp[k];
         oK[p] = mK[k];
         orank[p] = mrank[k];
+        delta[p] = 0.0;
         a = fabs((double)mamp[k]);
     }
-    if (k == n - 1) sc->n_out = pos[k] + keep[k];
+    if (ok && k == cap - 1) sc->n_out = pos[k] + keep[k];
     a = block_reduce_sum(a);
     if (threadIdx.x == 0) abs_part[blockIdx.x] = a;
 }
@@ -816,11 +857,25 @@ __global__ void __launch_bounds__(kThreads) k_item_stats(ItemPartials part, uint
 {
     double num = 0.0;
     uint64_t att = 0, disc = 0, mx = 0;
-    for (uint64_t i = threadIdx.x; i < n; i += kThreads) {
-        num += part.num[i];
-        att += part.att[i];
-        disc += part.disc[i];
-        mx = part.maxn[i] > mx ? part.maxn[i] : mx;
+    for (uint64_t i0 = 0; i0 < n; i0 += 4 * kThreads) {
+        double a[4];
+        uint64_t b[4], c[4], d[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * kThreads + threadIdx.x;
+            const bool in = i < n;
+            a[u] = in ? part.num[i] : 0.0;
+            b[u] = in ? part.att[i] : 0;
+            c[u] = in ? part.disc[i] : 0;
+            d[u] = in ? part.maxn[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            num += a[u];
+            att += b[u];
+            disc += c[u];
+            mx = d[u] > mx ? d[u] : mx;
+        }
     }
     num = block_reduce_sum(num);
     att = block_reduce_sum(att);

@@ -71,15 +71,23 @@ __device__ __forceinline__ V block_reduce_sum(V v)
 }
 
 // -------------------------------------------------------------------------- scan
+// Scans read their input through a source functor: a plain array, or a transform of
+// another array (the selection weights are formed while being scanned).
 template <typename V>
-__global__ void __launch_bounds__(kThreads) k_scan_reduce(const V *__restrict__ in, uint64_t n, V *__restrict__ part)
+struct ArraySrc {
+    const V *p;
+    __device__ __forceinline__ V operator()(uint64_t i) const { return p[i]; }
+};
+
+template <typename V, typename Src>
+__global__ void __launch_bounds__(kThreads) k_scan_reduce(Src in, uint64_t n, V *__restrict__ part)
 {
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
     V s = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const uint64_t g = base + (uint64_t)i * kThreads + threadIdx.x;
-        if (g < n) s += in[g];
+        if (g < n) s += in(g);
     }
     s = block_reduce_sum(s);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -87,8 +95,8 @@ __global__ void __launch_bounds__(kThreads) k_scan_reduce(const V *__restrict__ 
 
 // Scan of one tile, staged through LDS so that global loads and stores stay coalesced
 // while each thread scans kScanItems consecutive values.
-template <typename V>
-__global__ void __launch_bounds__(kThreads) k_scan_tile(const V *__restrict__ in, V *__restrict__ out, uint64_t n,
+template <typename V, typename Src>
+__global__ void __launch_bounds__(kThreads) k_scan_tile(Src in, V *__restrict__ out, uint64_t n,
                                                         const V *__restrict__ tile_offset, int inclusive)
 {
     __shared__ V buf[kScanTile];
@@ -96,7 +104,7 @@ __global__ void __launch_bounds__(kThreads) k_scan_tile(const V *__restrict__ in
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const uint64_t g = base + (uint64_t)i * kThreads + threadIdx.x;
-        buf[i * kThreads + threadIdx.x] = (g < n) ? in[g] : V(0);
+        buf[i * kThreads + threadIdx.x] = (g < n) ? in(g) : V(0);
     }
     __syncthreads();
     V loc[kScanItems];
@@ -124,9 +132,8 @@ __global__ void __launch_bounds__(kThreads) k_scan_tile(const V *__restrict__ in
 
 // One block scans up to a few tiles in sequence, carrying the running total: one launch
 // instead of three for the small scans of a step (radix histograms, flags of short lists).
-template <typename V>
-__global__ void __launch_bounds__(kThreads) k_scan_small(const V *__restrict__ in, V *__restrict__ out, uint64_t n,
-                                                         int inclusive)
+template <typename V, typename Src>
+__global__ void __launch_bounds__(kThreads) k_scan_small(Src in, V *__restrict__ out, uint64_t n, int inclusive)
 {
     __shared__ V buf[kScanTile];
     V carry = 0;
@@ -134,7 +141,7 @@ __global__ void __launch_bounds__(kThreads) k_scan_small(const V *__restrict__ i
 #pragma unroll
         for (int i = 0; i < kScanItems; ++i) {
             const uint64_t g = base + (uint64_t)i * kThreads + threadIdx.x;
-            buf[i * kThreads + threadIdx.x] = (g < n) ? in[g] : V(0);
+            buf[i * kThreads + threadIdx.x] = (g < n) ? in(g) : V(0);
         }
         __syncthreads();
         V loc[kScanItems];
@@ -179,11 +186,14 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active)
     return peers;
 }
 
+// The live item count is read from device memory (*n_live); the grid covers a capacity and
+// tiles beyond the count contribute empty histograms.
 template <int W>
-__global__ void __launch_bounds__(kThreads) k_radix_hist(const uint64_t *__restrict__ key, uint64_t stride, uint32_t n,
-                                                         int word, int shift, uint32_t *__restrict__ hist,
-                                                         uint32_t n_tiles)
+__global__ void __launch_bounds__(kThreads) k_radix_hist(const uint64_t *__restrict__ key, uint64_t stride,
+                                                         const uint64_t *__restrict__ n_live, int word, int shift,
+                                                         uint32_t *__restrict__ hist, uint32_t n_tiles)
 {
+    const uint64_t n = *n_live;
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -208,9 +218,11 @@ __global__ void __launch_bounds__(kThreads) k_radix_hist(const uint64_t *__restr
 template <int W>
 __global__ void __launch_bounds__(kThreads) k_radix_scatter(const uint64_t *__restrict__ key_in, const uint32_t *__restrict__ idx_in,
                                                             uint64_t *__restrict__ key_out, uint32_t *__restrict__ idx_out,
-                                                            uint64_t stride, uint32_t n, int word, int shift,
-                                                            const uint32_t *__restrict__ offsets, uint32_t n_tiles)
+                                                            uint64_t stride, const uint64_t *__restrict__ n_live, int word,
+                                                            int shift, const uint32_t *__restrict__ offsets, uint32_t n_tiles)
 {
+    const uint64_t n = *n_live;
+    if ((uint64_t)blockIdx.x * kSortTile >= n) return;  // empty tile (uniform per block)
     __shared__ uint32_t run[256];
     __shared__ uint32_t wave_cnt[kWaves][256];
     run[threadIdx.x] = offsets[(uint64_t)threadIdx.x * n_tiles + blockIdx.x];
