@@ -37,7 +37,7 @@ ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # Algorithmic 32-bit operations of one spawning attempt (Philox block, generator, element,
 # signs, amplitude) -- the per-unit figure of the generation kernel (see the design notes).
 OPS_PER_ATTEMPT = 300.0
-HBM_KERNELS = {"radix_scatter", "radix_hist", "gather", "seg_fold", "merge", "compact", "round", "weights",
+HBM_KERNELS = {"radix_ghist", "radix_onesweep", "gather", "seg_fold", "merge", "compact", "weights_scan",
                "noncomposite"}
 
 
@@ -177,7 +177,7 @@ def roofline(prof: dict):
 
 def annihilation_roofline(prof: dict):
     """Achieved HBM bandwidth of the sort / reduce / merge kernels taken together."""
-    names = [n for n in ("radix_hist", "radix_scatter", "gather", "seg_fold", "merge", "round", "compact")
+    names = [n for n in ("gather", "radix_ghist", "radix_onesweep", "seg_fold", "merge", "compact")
              if n in prof]
     ms = sum(prof[n]["ms"] for n in names)
     by = sum(prof[n]["bytes"] for n in names)

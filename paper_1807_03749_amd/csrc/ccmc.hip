@@ -81,22 +81,20 @@ struct ccmc_state {
     uint64_t step = 0;
     double last_num = 0, last_den = 0;
     // per-step buffers
-    DevBuf q, P, guide, delta;
+    DevBuf P, guide, delta;
     DevBuf ikey, iA, ideath, in, ilevel, icnt, ioff;
     uint64_t icap = 0;
     DevBuf num_part, att_part, disc_part, max_part, abs_part;
     DevBuf block_item, gcount, gspawn, gdeath, boff;
     DevBuf rkey, ramp, rid;  // per-block record regions
     uint64_t rcap = 0;              // region slots
-    DevBuf drank, dkey, damp, did, sr[2], sidx[2], hist, hoff;
-    DevBuf flag, incl, start, is_new, new_pos, ins, seg_sum, nkey, nrank, nins, nsum, keep, pos;
+    DevBuf drank, dkey, damp, did, sr[2], sidx[2];
+    DevBuf is_new, new_pos, ins, seg_sum, nkey, nrank, nins, nsum, keep, pos;
     uint64_t dcap = 0;  // dense record capacity
     uint64_t slot_hint = 1 << 16, rec_hint = 1 << 14;  // capacities planned for the next step
     uint64_t cnt_slots = 0, cnt_rec = 0, cnt_merged = 0;  // live counts of the last step
-    std::vector<DevBuf> scan_tmp;
-    DevBuf scratch;
+    DevBuf lb;  // step scalars, tickets, radix histograms and look-back status words
     Scratch *hscratch = nullptr;  // pinned
-    uint64_t *hpinned = nullptr;  // pinned small readbacks
     // last step's spawn list (keep_spawn_ids)
     uint64_t last_nrec = 0;
     int last_rec_buf = -1;
@@ -218,31 +216,17 @@ void resolve_profile(ccmc_state *st)
 }
 
 // --------------------------------------------------------------------------- scan
+// Single-launch look-back scan; status must hold ceil(n / kScanTile) zeroed words.
 template <typename V, typename Src>
-ccmc_status scan_src(ccmc_state *st, Src in, V *out, uint64_t n, bool inclusive, int level = 0)
+void scan_lb(ccmc_state *st, Src in, V *out, uint64_t n, bool inclusive, uint64_t *status, uint64_t *ticket,
+             uint64_t *total)
 {
-    if (n == 0) return CCMC_OK;
+    if (!n) return;
     const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
-    if (tiles <= 2) {
-        k_scan_small<V, Src><<<1, kThreads, 0, st->stream>>>(in, out, n, inclusive ? 1 : 0);
-        return CCMC_OK;
-    }
-    if ((int)st->scan_tmp.size() < 2 * (level + 1)) st->scan_tmp.resize(2 * (level + 1));
-    TRY(ensure(st, st->scan_tmp[2 * level], tiles * sizeof(V)));
-    TRY(ensure(st, st->scan_tmp[2 * level + 1], tiles * sizeof(V)));
-    V *part = ptr<V>(st->scan_tmp[2 * level]);
-    V *poff = ptr<V>(st->scan_tmp[2 * level + 1]);
-    k_scan_reduce<V, Src><<<(unsigned)tiles, kThreads, 0, st->stream>>>(in, n, part);
-    TRY(scan_src<V>(st, ArraySrc<V>{part}, poff, tiles, false, level + 1));
-    k_scan_tile<V, Src><<<(unsigned)tiles, kThreads, 0, st->stream>>>(in, out, n, poff, inclusive ? 1 : 0);
-    return CCMC_OK;
+    k_scan_lb<V, Src><<<(unsigned)tiles, kThreads, 0, st->stream>>>(in, out, n, inclusive ? 1 : 0, status, ticket, total);
 }
 
-template <typename V>
-ccmc_status scan(ccmc_state *st, const V *in, V *out, uint64_t n, bool inclusive)
-{
-    return scan_src<V>(st, ArraySrc<V>{in}, out, n, inclusive);
-}
+uint64_t scan_tiles(uint64_t n) { return (n + kScanTile - 1) / kScanTile; }
 
 // ------------------------------------------------------------------------ systems
 int words_for(int M) { return (M + 63) / 64; }
@@ -495,7 +479,6 @@ ccmc_status ensure_store(ccmc_state *st, uint64_t n)
     TRY(ensure(st, st->samp[1 - c], nc * sizeof(T)));
     TRY(ensure(st, st->sK[1 - c], nc * sizeof(T)));
     TRY(ensure(st, st->srank[1 - c], nc * sizeof(uint64_t)));
-    TRY(ensure(st, st->q, nc * sizeof(uint64_t)));
     TRY(ensure(st, st->P, nc * sizeof(uint64_t)));
     TRY(ensure(st, st->guide, (2 * nc + 4) * sizeof(uint32_t)));
     TRY(ensure(st, st->delta, nc * sizeof(double)));
@@ -581,29 +564,47 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     TRY(ensure_store<W, T>(st, mcap + 1));
     TRY(ensure(st, st->keep, (mcap + 1) * sizeof(uint32_t)));
     TRY(ensure(st, st->pos, (mcap + 1) * sizeof(uint32_t)));
-    const uint32_t tiles = (uint32_t)((rec_cap + kSortTile - 1) / kSortTile);
-    TRY(ensure(st, st->hist, (size_t)256 * tiles * sizeof(uint32_t)));
-    TRY(ensure(st, st->hoff, (size_t)256 * tiles * sizeof(uint32_t)));
+    const uint64_t tiles = (rec_cap + kSortTile - 1) / kSortTile;
+    const int passes = std::max(1, (st->rank_bits + 7) / 8);
     const unsigned nb_fnc = fnc ? grid_for(n_fnc) : 0, nb_sel = n_sel ? grid_for(n_sel) : 0;
     const size_t nparts = (size_t)(nb_fnc + nb_sel + 1);
     TRY(ensure(st, st->num_part, nparts * sizeof(double)));
     TRY(ensure(st, st->att_part, nparts * sizeof(uint64_t)));
     TRY(ensure(st, st->disc_part, nparts * sizeof(uint64_t)));
     TRY(ensure(st, st->max_part, nparts * sizeof(uint64_t)));
-    TRY(ensure(st, st->abs_part, (grid_for(mcap) + 1) * sizeof(double)));
+    const unsigned nb_abs = grid_for(mcap);
+    TRY(ensure(st, st->abs_part, (nb_abs + 1) * sizeof(double)));
+
+    // One zeroed area per step: the step scalars, the scan tickets, the look-back status
+    // words of every scan and radix pass, and the radix histograms (64-bit words).
+    enum { kTkWeights, kTkOff, kTkBoff, kTkNew, kTkKeep, kTkRadix, kTickets = kTkRadix + 8 };
+    const uint64_t w_scratch = (sizeof(Scratch) + 7) / 8;
+    const uint64_t o_tick = w_scratch;
+    const uint64_t o_weights = o_tick + kTickets;
+    const uint64_t o_off = o_weights + scan_tiles(ne);
+    const uint64_t o_boff = o_off + scan_tiles(n_items + 1);
+    const uint64_t o_new = o_boff + scan_tiles(nblk_cap + 1);
+    const uint64_t o_keep = o_new + scan_tiles(rec_cap);
+    const uint64_t o_ghist = o_keep + scan_tiles(mcap);
+    const uint64_t o_rstat = o_ghist + (uint64_t)passes * 128;
+    const uint64_t lb_words = o_rstat + (uint64_t)passes * tiles * 256;
+    TRY(ensure(st, st->lb, lb_words * sizeof(uint64_t)));
+    uint64_t *lb = ptr<uint64_t>(st->lb);
+    uint64_t *tick = lb + o_tick;
+    Scratch *sc = reinterpret_cast<Scratch *>(lb);
+    k_fill<uint64_t><<<grid_for(lb_words), kThreads, 0, s>>>(lb, lb_words, 0ull);
 
     const uint64_t scap = st->scap;
     const uint64_t *skey = ptr<uint64_t>(st->skey[c]);
     const T *samp = ptr<T>(st->samp[c]);
     const T *sK = ptr<T>(st->sK[c]);
     const uint64_t *srank = ptr<uint64_t>(st->srank[c]);
-    Scratch *sc = ptr<Scratch>(st->scratch);
-    k_fill<uint64_t><<<1, 64, 0, s>>>(reinterpret_cast<uint64_t *>(sc), sizeof(Scratch) / 8, 0ull);
 
     // ---- (a1) selection weights, formed inside the scan of their prefix; guide table
     if (ne) {
         launch(st, "weights_scan", tb + 8.0, nullptr, ne, [&] {
-            (void)scan_src<uint64_t>(st, WeightSrc<T>{samp, sc}, ptr<uint64_t>(st->P), ne, true);
+            scan_lb<uint64_t>(st, WeightSrc<T>{samp, sc}, ptr<uint64_t>(st->P), ne, true, lb + o_weights,
+                              tick + kTkWeights, nullptr);
         });
         if (n_sel) k_guide<<<grid_for(ne + 1), kThreads, 0, s>>>(ptr<uint64_t>(st->P), ne, sc, ptr<uint32_t>(st->guide));
     }
@@ -628,8 +629,8 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     } else {
         k_fill<uint64_t><<<1, 1, 0, s>>>(it.cnt + n_items, 1, 0ull);
     }
-    k_item_stats<<<1, kThreads, 0, s>>>(part, nb_fnc + nb_sel, sc);
-    TRY(scan<uint64_t>(st, it.cnt, ptr<uint64_t>(st->ioff), n_items + 1, false));
+    scan_lb<uint64_t>(st, ArraySrc<uint64_t>{it.cnt}, ptr<uint64_t>(st->ioff), n_items + 1, false, lb + o_off,
+                      tick + kTkOff, &sc->n_slots);
 
     // ---- (a6-a8) records: death and spawning attempts, one lane per slot, compacted per block
     Records reg{nullptr, ptr<uint64_t>(st->rkey), st->ramp.p, ptr<uint64_t>(st->rid), st->rcap};
@@ -641,30 +642,32 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
                                                                  ptr<uint64_t>(st->block_item), n_fnc, n_items, slot_cap, a,
                                                                  reg, ids ? 1 : 0, gst);
     });
-    TRY(scan<uint32_t>(st, gst.count, ptr<uint32_t>(st->boff), nblk_cap + 1, false));
-    k_gen_stats<<<1, kThreads, 0, s>>>(gst, ptr<uint32_t>(st->boff), nblk_cap, rec_cap, sc);
+    scan_lb<uint32_t>(st, ArraySrc<uint32_t>{gst.count}, ptr<uint32_t>(st->boff), nblk_cap + 1, false, lb + o_boff,
+                      tick + kTkBoff, &sc->n_rec);
     const uint64_t dc = st->dcap;
     Records rec{ptr<uint64_t>(st->drank), ptr<uint64_t>(st->dkey), st->damp.p, ptr<uint64_t>(st->did), dc};
     launch(st, "gather", 2.0 * (kb + tb + (ids ? 8.0 : 0.0)) + 8.0, &st->cnt_rec, 0, [&] {
-        k_gather<W, T><<<grid_for(rec_cap), kThreads, 0, s>>>(st->sd, reg, ptr<uint32_t>(st->boff), nblk_cap, rec,
+        k_gather<W, T><<<grid_for(rec_cap), kThreads, 0, s>>>(st->sd, reg, ptr<uint32_t>(st->boff), nblk_cap, rec_cap, rec,
                                                               ids ? 1 : 0, sc);
     });
 
-    // ---- (a11) stable LSD radix sort of (rank, record index) over the rank bits
+    // ---- (a11) stable LSD radix sort of (rank, record index): one histogram launch for all
+    // passes, then one single-sweep launch per 8-bit digit
     const uint64_t *n_live = &sc->n_live;
+    uint32_t *ghist = reinterpret_cast<uint32_t *>(lb + o_ghist);
+    launch(st, "radix_ghist", 8.0, &st->cnt_rec, 0, [&] {
+        k_radix_ghist<<<(unsigned)tiles, kThreads, 0, s>>>(ptr<uint64_t>(st->drank), n_live, passes, ghist);
+    });
     const uint64_t *kin = ptr<uint64_t>(st->drank);
     const uint32_t *iin = nullptr;
     int ob = 0;
-    for (int sh = 0; sh < std::max(st->rank_bits, 1); sh += 8) {
+    for (int p = 0; p < passes; ++p) {
         uint64_t *kout = ptr<uint64_t>(st->sr[ob]);
         uint32_t *iout = ptr<uint32_t>(st->sidx[ob]);
-        launch(st, "radix_hist", 8.0, &st->cnt_rec, 0, [&] {
-            k_radix_hist<1><<<tiles, kThreads, 0, s>>>(kin, dc, n_live, 0, sh, ptr<uint32_t>(st->hist), tiles);
-        });
-        TRY(scan<uint32_t>(st, ptr<uint32_t>(st->hist), ptr<uint32_t>(st->hoff), (uint64_t)256 * tiles, false));
-        launch(st, "radix_scatter", 2 * 8.0 + (iin ? 8.0 : 4.0), &st->cnt_rec, 0, [&] {
-            k_radix_scatter<1><<<tiles, kThreads, 0, s>>>(kin, iin, kout, iout, dc, n_live, 0, sh, ptr<uint32_t>(st->hoff),
-                                                          tiles);
+        launch(st, "radix_onesweep", 2 * 8.0 + (iin ? 8.0 : 4.0), &st->cnt_rec, 0, [&] {
+            k_radix_onesweep<<<(unsigned)tiles, kThreads, 0, s>>>(kin, iin, kout, iout, n_live, 8 * p, ghist + 256 * p,
+                                                                  lb + o_rstat + (uint64_t)p * tiles * 256,
+                                                                  tick + kTkRadix + p);
         });
         kin = kout;
         iin = iout;
@@ -680,7 +683,8 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
                                                              delta, ptr<uint32_t>(st->is_new), ptr<uint64_t>(st->ins),
                                                              ptr<double>(st->seg_sum), sc);
     });
-    TRY(scan<uint32_t>(st, ptr<uint32_t>(st->is_new), ptr<uint32_t>(st->new_pos), rec_cap, false));
+    scan_lb<uint32_t>(st, ArraySrc<uint32_t>{ptr<uint32_t>(st->is_new)}, ptr<uint32_t>(st->new_pos), rec_cap, false,
+                      lb + o_new, tick + kTkNew, &sc->n_new);
     k_new_compact<W><<<grid_for(rec_cap), kThreads, 0, s>>>(sorted_rank, sorted_idx, ptr<uint64_t>(st->dkey), dc, rec_cap,
                                                             ptr<uint32_t>(st->is_new), ptr<uint32_t>(st->new_pos),
                                                             ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum),
@@ -702,14 +706,15 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
                                                           ptr<uint64_t>(st->nins), ptr<double>(st->nsum), mkey, mamp, mK, mrank,
                                                           S2, mcap, a, keep, sc);
     });
-    TRY(scan<uint32_t>(st, keep, pos, mcap, false));
+    scan_lb<uint32_t>(st, ArraySrc<uint32_t>{keep}, pos, mcap, false, lb + o_keep, tick + kTkKeep, &sc->n_out);
     launch(st, "compact", 2.0 * eb, &st->cnt_merged, 0, [&] {
-        k_compact<W, T><<<grid_for(mcap), kThreads, 0, s>>>(mkey, mamp, mK, mrank, S2, mcap, keep, pos,
-                                                            ptr<uint64_t>(st->skey[c]), ptr<T>(st->samp[c]), ptr<T>(st->sK[c]),
-                                                            ptr<uint64_t>(st->srank[c]), S2, delta, ptr<double>(st->abs_part),
-                                                            sc);
+        k_compact<W, T><<<nb_abs, kThreads, 0, s>>>(mkey, mamp, mK, mrank, S2, mcap, keep, pos,
+                                                    ptr<uint64_t>(st->skey[c]), ptr<T>(st->samp[c]), ptr<T>(st->sK[c]),
+                                                    ptr<uint64_t>(st->srank[c]), S2, delta, ptr<double>(st->abs_part), sc);
     });
-    k_reduce_partials<<<1, kThreads, 0, s>>>(ptr<double>(st->abs_part), grid_for(mcap), &sc->n_total);
+
+    // ---- (a14) the step's statistics in one fixed-order reduction
+    k_final<<<1, kThreads, 0, s>>>(part, nb_fnc + nb_sel, gst, nblk_cap, ptr<double>(st->abs_part), nb_abs, sc);
 
     // ---- (a14) the one synchronisation of the step
     HIP_TRY(hipMemcpyAsync(st->hscratch, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
@@ -945,21 +950,19 @@ void destroy(ccmc_state *st)
     if (st->stream) (void)hipStreamSynchronize(st->stream);
     DevBuf *bufs[] = {&st->t_grid, &st->t_nvec, &st->t_vq, &st->t_h, &st->t_eri, &st->t_fock, &st->t_vpair,
                       &st->t_binv, &st->t_bino, &st->skey[0], &st->skey[1], &st->samp[0], &st->samp[1], &st->sK[0],
-                      &st->sK[1], &st->srank[0], &st->srank[1], &st->q, &st->P, &st->guide, &st->delta, &st->ikey,
+                      &st->sK[1], &st->srank[0], &st->srank[1], &st->P, &st->guide, &st->delta, &st->ikey,
                       &st->iA, &st->ideath, &st->in, &st->ilevel, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,
                       &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->boff, &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
-                      &st->sidx[0], &st->sidx[1], &st->hist, &st->hoff, &st->flag, &st->incl, &st->start, &st->is_new,
+                      &st->sidx[0], &st->sidx[1], &st->is_new,
                       &st->new_pos, &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->keep,
-                      &st->pos, &st->scratch};
+                      &st->pos, &st->lb};
     for (DevBuf *b : bufs) release(st, *b);
-    for (auto &b : st->scan_tmp) release(st, b);
     for (auto &p : st->pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
     }
     for (auto e : st->ev_pool) (void)hipEventDestroy(e);
     if (st->hscratch) (void)hipHostFree(st->hscratch);
-    if (st->hpinned) (void)hipHostFree(st->hpinned);
     if (st->own_stream && st->stream) (void)hipStreamDestroy(st->stream);
     delete st;
 }
@@ -1041,12 +1044,10 @@ ccmc_status ccmc_init(const ccmc_system *sys, const ccmc_integrals *ints, int tr
         st->own_stream = true;
     }
     ccmc_status rc = CCMC_OK;
-    if (hipHostMalloc((void **)&st->hscratch, sizeof(Scratch)) != hipSuccess ||
-        hipHostMalloc((void **)&st->hpinned, 64) != hipSuccess) {
+    if (hipHostMalloc((void **)&st->hscratch, sizeof(Scratch)) != hipSuccess) {
         st->err = "hipHostMalloc failed";
         rc = CCMC_EDEVICE;
     }
-    if (rc == CCMC_OK) rc = ensure(st, st->scratch, sizeof(Scratch));
     if (rc == CCMC_OK) rc = dispatch<SystemF>(st, st, ints);
     if (rc == CCMC_OK) rc = dispatch<StoreF>(st, st, (uint64_t)1024);
     if (rc != CCMC_OK) {

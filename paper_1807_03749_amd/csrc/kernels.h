@@ -1,16 +1,22 @@
 // kernels.h -- the CCMC time-step kernels (Spencer et al., arXiv:1807.03749, Sec. II & IV).
 //
-// One step, in launch order:
-//   k_weights        fixed-point selection weights q_i of the store          (a1)
-//   k_noncomposite   reference + every excitor as explicit items (FNC)        (a5, a9, a10)
-//   k_select         cluster size, excitor draws, collapse, amplitude         (a2, a3, a4, a9, a10)
-//   k_generate       one lane per record slot: death or spawning attempt      (a6, a7, a8)
-//   k_gather         concatenate per-block record regions                    (a8)
-//   radix sort       stable LSD sort of the records by determinant            (a11)
-//   k_seg_*          segment heads, left fold in record order, store lookup   (a12)
-//   k_merge          merge sums and new determinants into the sorted store    (a12)
-//   k_round          occupation rounding, then compaction                     (a13)
-//   k_stats_*        FP64 population and projected-energy reductions          (a14)
+// One step, in launch order (scans are single launches with decoupled look-back):
+//   k_fill           clear the step scalars and look-back status words
+//   weights scan     fixed-point selection weights q_i and their prefix          (a1)
+//   k_guide          bucket table of the prefix for the excitor draws           (a2)
+//   k_noncomposite   reference + every excitor as explicit items (FNC)          (a4, a5, a9, a10)
+//   k_select         cluster size, excitor draws, collapse, amplitude           (a2, a3, a4, a9, a10)
+//   slot scan        record slots per item (1 death + n attempts)
+//   k_block_items    first item of each generation block
+//   k_generate       one lane per record slot: death or spawning attempt        (a6, a7, a8)
+//   region scan      records per generation block
+//   k_gather         dense records and their truncated-space rank               (a8)
+//   radix sort       stable LSD sort of (rank, record index)                    (a11)
+//   k_seg_fold       left fold of each run in record order, store lookup        (a12)
+//   new scan, k_new_compact   determinants not in the store
+//   k_merge          merge, then occupation rounding                            (a12, a13)
+//   keep scan, k_compact      survivors back into the store
+//   k_final          FP64 population, projected-energy and count reductions    (a14)
 #pragma once
 #include "device.h"
 #include "primitives.h"
@@ -22,7 +28,7 @@ constexpr int kGenSlots = kThreads * kGenRounds;    // slots (and region capacit
 
 constexpr uint64_t kErrBlowup = 1, kErrAttempts = 2, kErrSlotCap = 4, kErrRecCap = 8;
 
-// Device-side scalars of one step.
+// Device-side scalars of one step (all 64-bit words, cleared at the start of the step).
 struct Scratch {
     uint64_t qtot;
     uint64_t err;             // kErr* bits; any bit makes the final compaction a no-op
@@ -35,12 +41,10 @@ struct Scratch {
     uint64_t n_rec;           // records emitted by the step
     uint64_t n_live;          // records the annihilation works on (0 after an overflow)
     uint64_t guide_n;         // entries of the selection guide table
-    uint32_t guide_shift;
-    uint32_t n_seg;
-    uint32_t n_new;
-    uint32_t hf_hit;
-    uint32_t n_out;
-    uint32_t pad;
+    uint64_t guide_shift;
+    uint64_t n_new;           // new determinants
+    uint64_t hf_hit;
+    uint64_t n_out;           // excitors after the step
     double hf_sum;
     double n_total;
     double num;
@@ -57,7 +61,7 @@ struct StepArgs {
     int fnc;
 };
 
-// Per-block partial statistics of the item kernels, reduced by k_item_stats.
+// Per-block partial statistics of the item kernels, reduced by k_final.
 struct ItemPartials {
     double *num;       // projected-energy numerator
     uint64_t *att;     // spawning attempts
@@ -235,7 +239,7 @@ __global__ void __launch_bounds__(kThreads) k_select(SysDev S, const uint64_t *_
     uint64_t att = 0, disc = 0, mx = 0;
     if (k < a.n_sel) {
         const uint64_t Q = sc->qtot;
-        const uint32_t gsh = sc->guide_shift;
+        const uint32_t gsh = (uint32_t)sc->guide_shift;
         Draws r(a.key0, a.key1, kSelect, (uint32_t)k, 0u, a.step);
         const int lo = a.fnc ? 2 : 0, hi = S.l + 2;
         const int s = draw_size(uniform53(r.get(0)), lo, hi);
@@ -474,10 +478,7 @@ __global__ void __launch_bounds__(kThreads) k_block_items(const uint64_t *__rest
 {
     const uint64_t u = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     const uint64_t n_slots_all = off[n_items];
-    if (u == 0) {
-        sc->n_slots = n_slots_all;
-        if (n_slots_all > slot_cap) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrSlotCap);
-    }
+    if (u == 0 && n_slots_all > slot_cap) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrSlotCap);
     const uint64_t n_slots = n_slots_all < slot_cap ? n_slots_all : slot_cap;
     const uint64_t n_blocks = (n_slots + kGenSlots - 1) / kGenSlots;
     if (u > n_blocks || n_slots == 0) return;
@@ -603,45 +604,22 @@ __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, co
     }
 }
 
-// Sums of the per-block generation statistics (one block).
-__global__ void __launch_bounds__(kThreads) k_gen_stats(GenStats gs, const uint32_t *__restrict__ boff, uint64_t n_blocks,
-                                                        uint64_t rec_cap, Scratch *sc)
-{
-    uint64_t sp = 0, de = 0;
-    for (uint64_t b0 = 0; b0 < n_blocks; b0 += 4 * kThreads) {
-        uint32_t x[4], y[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint64_t b = b0 + (uint64_t)u * kThreads + threadIdx.x;
-            x[u] = b < n_blocks ? gs.spawns[b] : 0u;
-            y[u] = b < n_blocks ? gs.deaths[b] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            sp += x[u];
-            de += y[u];
-        }
-    }
-    sp = block_reduce_sum(sp);
-    de = block_reduce_sum(de);
-    if (threadIdx.x == 0) {
-        sc->n_spawns = sp;
-        sc->n_deaths = de;
-        const uint64_t nr = boff[n_blocks];
-        sc->n_rec = nr;
-        if (nr > rec_cap) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrRecCap);
-        sc->n_live = (sc->err & (kErrSlotCap | kErrRecCap)) ? 0 : nr;
-    }
-}
-
 // Dense layout of the records: output position r comes from the block b with
 // boff[b] <= r < boff[b+1], at slot position r - boff[b] of its region.
 template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_gather(const SysDev S, Records reg, const uint32_t *__restrict__ boff,
-                                                     uint64_t n_blocks, Records out, int keep_ids, const Scratch *sc)
+                                                     uint64_t n_blocks, uint64_t rec_cap, Records out, int keep_ids, Scratch *sc)
 {
     const uint64_t r = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (r >= sc->n_live) return;
+    // records the annihilation works on: all of them, or none after a capacity overflow
+    const uint64_t nr = sc->n_rec;
+    const bool over = nr > rec_cap || (sc->err & kErrSlotCap);
+    const uint64_t live = over ? 0 : nr;
+    if (r == 0) {
+        sc->n_live = live;
+        if (nr > rec_cap) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrRecCap);
+    }
+    if (r >= live) return;
     uint64_t l0 = 0, h0 = n_blocks + 1;  // last b with boff[b] <= r
     while (l0 < h0) {
         const uint64_t mid = (l0 + h0) >> 1;
@@ -740,7 +718,6 @@ __global__ void __launch_bounds__(kThreads) k_new_compact(const uint64_t *__rest
 {
     const uint64_t r = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     if (r >= cap) return;
-    if (r == cap - 1) sc->n_new = new_pos[r] + is_new[r];
     if (!is_new[r]) return;
     const uint32_t j = new_pos[r];
     const uint32_t src = idx[r];  // any record of the run carries its bitstring
@@ -838,32 +815,25 @@ __global__ void __launch_bounds__(kThreads) k_compact(const uint64_t *__restrict
         delta[p] = 0.0;
         a = fabs((double)mamp[k]);
     }
-    if (ok && k == cap - 1) sc->n_out = pos[k] + keep[k];
     a = block_reduce_sum(a);
     if (threadIdx.x == 0) abs_part[blockIdx.x] = a;
 }
 
-// Fixed-order FP64 reduction of per-block partials by one block.
-__global__ void __launch_bounds__(kThreads) k_reduce_partials(const double *__restrict__ part, uint64_t n, double *__restrict__ out)
+// The step's statistics in one fixed-order reduction (one block): the item kernels'
+// partials, the generation blocks' spawn and death counts, and the per-block |N| sums of
+// the compacted store.
+__global__ void __launch_bounds__(kThreads) k_final(ItemPartials part, uint64_t n_parts, GenStats gs, uint64_t n_gen,
+                                                    const double *__restrict__ abs_part, uint64_t n_abs, Scratch *sc)
 {
-    double s = 0.0;
-    for (uint64_t i = threadIdx.x; i < n; i += kThreads) s += part[i];
-    s = block_reduce_sum(s);
-    if (threadIdx.x == 0) *out = s;
-}
-
-// Fixed-order reduction of the item kernels' per-block partials (one block).
-__global__ void __launch_bounds__(kThreads) k_item_stats(ItemPartials part, uint64_t n, Scratch *sc)
-{
-    double num = 0.0;
-    uint64_t att = 0, disc = 0, mx = 0;
-    for (uint64_t i0 = 0; i0 < n; i0 += 4 * kThreads) {
+    double num = 0.0, tot = 0.0;
+    uint64_t att = 0, disc = 0, mx = 0, sp = 0, de = 0;
+    for (uint64_t i0 = 0; i0 < n_parts; i0 += 4 * kThreads) {
         double a[4];
         uint64_t b[4], c[4], d[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint64_t i = i0 + (uint64_t)u * kThreads + threadIdx.x;
-            const bool in = i < n;
+            const bool in = i < n_parts;
             a[u] = in ? part.num[i] : 0.0;
             b[u] = in ? part.att[i] : 0;
             c[u] = in ? part.disc[i] : 0;
@@ -877,15 +847,45 @@ __global__ void __launch_bounds__(kThreads) k_item_stats(ItemPartials part, uint
             mx = d[u] > mx ? d[u] : mx;
         }
     }
+    for (uint64_t i0 = 0; i0 < n_gen; i0 += 4 * kThreads) {
+        uint32_t x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * kThreads + threadIdx.x;
+            x[u] = i < n_gen ? gs.spawns[i] : 0u;
+            y[u] = i < n_gen ? gs.deaths[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            sp += x[u];
+            de += y[u];
+        }
+    }
+    for (uint64_t i0 = 0; i0 < n_abs; i0 += 4 * kThreads) {
+        double x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * kThreads + threadIdx.x;
+            x[u] = i < n_abs ? abs_part[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) tot += x[u];
+    }
     num = block_reduce_sum(num);
+    tot = block_reduce_sum(tot);
     att = block_reduce_sum(att);
     disc = block_reduce_sum(disc);
+    sp = block_reduce_sum(sp);
+    de = block_reduce_sum(de);
     mx = block_reduce_max(mx);
     if (threadIdx.x == 0) {
         sc->num = num;
+        sc->n_total = tot;
         sc->n_attempts = att;
         sc->n_discarded = disc;
         sc->max_n = mx;
+        sc->n_spawns = sp;
+        sc->n_deaths = de;
     }
 }
 

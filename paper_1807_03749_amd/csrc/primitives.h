@@ -1,7 +1,9 @@
 // primitives.h -- device-wide building blocks on gfx950 (64-lane wavefronts):
-//   * exclusive / inclusive prefix scan of u32 / u64 arrays (reduce-then-scan, LDS staged)
-//   * stable LSD radix sort of multi-word bitstring keys with a u32 payload, 8-bit digits,
-//     digit ranks from wavefront ballots ("match" of equal digits) and LDS counters.
+//   * exclusive / inclusive prefix scan of u32 / u64 arrays in one launch (LDS-staged tiles,
+//     decoupled look-back between tiles)
+//   * stable LSD radix sort of 64-bit keys with a u32 payload, 8-bit digits: one histogram
+//     launch for all passes, then one single-sweep launch per digit; digit ranks from
+//     wavefront ballots ("match" of equal digits) and LDS counters.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -79,28 +81,61 @@ struct ArraySrc {
     __device__ __forceinline__ V operator()(uint64_t i) const { return p[i]; }
 };
 
-template <typename V, typename Src>
-__global__ void __launch_bounds__(kThreads) k_scan_reduce(Src in, uint64_t n, V *__restrict__ part)
+// ------------------------------------------------------- single-pass scans and sorts
+// Decoupled look-back (a tile publishes its total, then sums its predecessors' published
+// totals until one carries an inclusive prefix).  Each status word holds a 2-bit flag and a
+// 62-bit value, so relaxed agent-scope atomics suffice: release / acquire would write back
+// or invalidate the XCD's whole L2 at every publish and poll.  Tiles are taken in ticket
+// order, so every tile waited on belongs to a block that is already running.  The status
+// words must be zero before the launch.
+constexpr uint64_t kLbAggregate = 1ull << 62, kLbInclusive = 2ull << 62, kLbValue = (1ull << 62) - 1;
+
+__device__ __forceinline__ void lb_publish(uint64_t *w, uint64_t flag, uint64_t v)
 {
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
-    V s = 0;
-#pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        const uint64_t g = base + (uint64_t)i * kThreads + threadIdx.x;
-        if (g < n) s += in(g);
-    }
-    s = block_reduce_sum(s);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    __hip_atomic_store(w, flag | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Scan of one tile, staged through LDS so that global loads and stores stay coalesced
-// while each thread scans kScanItems consecutive values.
+// Exclusive prefix of tile t from its predecessors' status words, by one wavefront.
+__device__ __forceinline__ uint64_t lb_wave_lookback(uint64_t *status, uint64_t t)
+{
+    const int lane = lane_id();
+    uint64_t excl = 0;
+    int64_t base = (int64_t)t - 1;
+    while (base >= 0) {
+        const int64_t p = base - lane;
+        const uint64_t w = p >= 0 ? __hip_atomic_load(&status[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kLbInclusive;
+        const uint64_t flag = w & ~kLbValue;
+        const uint64_t incl = __ballot(flag == kLbInclusive);
+        const uint64_t pend = __ballot(flag == 0);
+        const int first = incl ? __ffsll((long long)incl) - 1 : 64;
+        const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
+        if (pend & need) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        uint64_t v = lane <= first ? (w & kLbValue) : 0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        excl += v;
+        if (first < 64) break;
+        base -= 64;
+    }
+    return excl;
+}
+
+// Single-launch scan of n values (n_tiles = ceil(n / kScanTile) blocks); the grand total
+// goes to *total when given.
 template <typename V, typename Src>
-__global__ void __launch_bounds__(kThreads) k_scan_tile(Src in, V *__restrict__ out, uint64_t n,
-                                                        const V *__restrict__ tile_offset, int inclusive)
+__global__ void __launch_bounds__(kThreads) k_scan_lb(Src in, V *__restrict__ out, uint64_t n, int inclusive,
+                                                      uint64_t *__restrict__ status, uint64_t *__restrict__ ticket,
+                                                      uint64_t *__restrict__ total)
 {
     __shared__ V buf[kScanTile];
-    const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    __shared__ uint64_t s_tile, s_prefix;
+    if (threadIdx.x == 0) s_tile = atomicAdd((unsigned long long *)ticket, 1ull);
+    __syncthreads();
+    const uint64_t t = s_tile;
+    const uint64_t base = t * kScanTile;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const uint64_t g = base + (uint64_t)i * kThreads + threadIdx.x;
@@ -114,8 +149,19 @@ __global__ void __launch_bounds__(kThreads) k_scan_tile(Src in, V *__restrict__ 
         loc[i] = buf[threadIdx.x * kScanItems + i];
         sum += loc[i];
     }
-    V total;
-    V run = block_exclusive_scan(sum, &total) + (tile_offset ? tile_offset[blockIdx.x] : V(0));
+    V tile_total;
+    const V excl_in_tile = block_exclusive_scan(sum, &tile_total);
+    if (wave_id() == 0) {
+        if (lane_id() == 0) lb_publish(&status[t], t == 0 ? kLbInclusive : kLbAggregate, (uint64_t)tile_total);
+        const uint64_t prefix = t == 0 ? 0 : lb_wave_lookback(status, t);
+        if (lane_id() == 0) {
+            if (t > 0) lb_publish(&status[t], kLbInclusive, prefix + (uint64_t)tile_total);
+            s_prefix = prefix;
+            if (total && base + kScanTile >= n) *total = prefix + (uint64_t)tile_total;
+        }
+    }
+    __syncthreads();
+    V run = excl_in_tile + (V)s_prefix;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const V x = loc[i];
@@ -127,46 +173,6 @@ __global__ void __launch_bounds__(kThreads) k_scan_tile(Src in, V *__restrict__ 
     for (int i = 0; i < kScanItems; ++i) {
         const uint64_t g = base + (uint64_t)i * kThreads + threadIdx.x;
         if (g < n) out[g] = buf[i * kThreads + threadIdx.x];
-    }
-}
-
-// One block scans up to a few tiles in sequence, carrying the running total: one launch
-// instead of three for the small scans of a step (radix histograms, flags of short lists).
-template <typename V, typename Src>
-__global__ void __launch_bounds__(kThreads) k_scan_small(Src in, V *__restrict__ out, uint64_t n, int inclusive)
-{
-    __shared__ V buf[kScanTile];
-    V carry = 0;
-    for (uint64_t base = 0; base < n; base += kScanTile) {
-#pragma unroll
-        for (int i = 0; i < kScanItems; ++i) {
-            const uint64_t g = base + (uint64_t)i * kThreads + threadIdx.x;
-            buf[i * kThreads + threadIdx.x] = (g < n) ? in(g) : V(0);
-        }
-        __syncthreads();
-        V loc[kScanItems];
-        V sum = 0;
-#pragma unroll
-        for (int i = 0; i < kScanItems; ++i) {
-            loc[i] = buf[threadIdx.x * kScanItems + i];
-            sum += loc[i];
-        }
-        V total;
-        V run = block_exclusive_scan(sum, &total) + carry;
-#pragma unroll
-        for (int i = 0; i < kScanItems; ++i) {
-            const V x = loc[i];
-            buf[threadIdx.x * kScanItems + i] = inclusive ? run + x : run;
-            run += x;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < kScanItems; ++i) {
-            const uint64_t g = base + (uint64_t)i * kThreads + threadIdx.x;
-            if (g < n) out[g] = buf[i * kThreads + threadIdx.x];
-        }
-        carry += total;
-        __syncthreads();
     }
 }
 
@@ -186,66 +192,79 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active)
     return peers;
 }
 
-// The live item count is read from device memory (*n_live); the grid covers a capacity and
-// tiles beyond the count contribute empty histograms.
-template <int W>
-__global__ void __launch_bounds__(kThreads) k_radix_hist(const uint64_t *__restrict__ key, uint64_t stride,
-                                                         const uint64_t *__restrict__ n_live, int word, int shift,
-                                                         uint32_t *__restrict__ hist, uint32_t n_tiles)
+// ------------------------------------------------------------ onesweep radix passes
+// Digit histograms of every pass in one read of the keys (they do not depend on the order),
+// aggregated per wavefront and per block before one global atomic per bin.
+__global__ void __launch_bounds__(kThreads) k_radix_ghist(const uint64_t *__restrict__ key, const uint64_t *__restrict__ n_live,
+                                                          int passes, uint32_t *__restrict__ ghist)
 {
     const uint64_t n = *n_live;
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    __shared__ uint32_t h[8][256];
+    for (int p = 0; p < passes; ++p) h[p][threadIdx.x] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
-    const uint64_t *kw = key + (uint64_t)word * stride;
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
-        const bool valid = g < n;
-        const uint32_t d = valid ? (uint32_t)((kw[g] >> shift) & 0xFFu) : 0u;
-        const uint64_t active = __ballot(valid);
-        if (valid) {
-            const uint64_t peers = match_digit(d, active);
-            if (lanes_below(peers) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    if (base < n) {
+        for (int r = 0; r < kSortItems; ++r) {
+            const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
+            const bool valid = g < n;
+            const uint64_t k = valid ? key[g] : 0;
+            const uint64_t active = __ballot(valid);
+            for (int p = 0; p < passes; ++p) {
+                const uint32_t d = (uint32_t)((k >> (8 * p)) & 0xFFu);
+                if (valid) {
+                    const uint64_t peers = match_digit(d, active);
+                    if (lanes_below(peers) == 0) atomicAdd(&h[p][d], (uint32_t)__popcll(peers));
+                }
+            }
         }
     }
     __syncthreads();
-    hist[(uint64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+    for (int p = 0; p < passes; ++p)
+        if (h[p][threadIdx.x]) atomicAdd(&ghist[p * 256 + threadIdx.x], h[p][threadIdx.x]);
 }
 
-// Stable scatter: rank of an item = global digit offset of this tile + items of the same
-// digit in earlier rounds + in earlier waves of this round + in lower lanes of this wave.
-template <int W>
-__global__ void __launch_bounds__(kThreads) k_radix_scatter(const uint64_t *__restrict__ key_in, const uint32_t *__restrict__ idx_in,
-                                                            uint64_t *__restrict__ key_out, uint32_t *__restrict__ idx_out,
-                                                            uint64_t stride, const uint64_t *__restrict__ n_live, int word,
-                                                            int shift, const uint32_t *__restrict__ offsets, uint32_t n_tiles)
+// One stable pass by the digit at `shift`: a tile ranks its keys locally (round by round, as
+// by wavefront digit matching), publishes its per-digit counts, looks back digit by digit over the
+// earlier tiles, and scatters to digit base + earlier tiles + local rank.  status holds
+// 256 words per tile and must be zero before the launch.
+__global__ void __launch_bounds__(kThreads) k_radix_onesweep(const uint64_t *__restrict__ key_in, const uint32_t *__restrict__ idx_in,
+                                                             uint64_t *__restrict__ key_out, uint32_t *__restrict__ idx_out,
+                                                             const uint64_t *__restrict__ n_live, int shift,
+                                                             const uint32_t *__restrict__ ghist, uint64_t *__restrict__ status,
+                                                             uint64_t *__restrict__ ticket)
 {
-    const uint64_t n = *n_live;
-    if ((uint64_t)blockIdx.x * kSortTile >= n) return;  // empty tile (uniform per block)
     __shared__ uint32_t run[256];
     __shared__ uint32_t wave_cnt[kWaves][256];
-    run[threadIdx.x] = offsets[(uint64_t)threadIdx.x * n_tiles + blockIdx.x];
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
-    const uint64_t *kw = key_in + (uint64_t)word * stride;
+    __shared__ uint32_t dig_base[256];
+    __shared__ uint64_t s_tile;
+    const uint64_t n = *n_live;
+    if (threadIdx.x == 0) s_tile = atomicAdd((unsigned long long *)ticket, 1ull);
+    run[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t t = s_tile;
+    const uint64_t base = t * kSortTile;
+    if (base >= n) return;  // tiles beyond the live count: nobody waits on them
+    uint64_t k[kSortItems];
+    uint32_t ix[kSortItems];
+    uint16_t rk[kSortItems];
     for (int r = 0; r < kSortItems; ++r) {
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) wave_cnt[w][threadIdx.x] = 0;
         __syncthreads();
         const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
         const bool valid = g < n;
-        const uint32_t d = valid ? (uint32_t)((kw[g] >> shift) & 0xFFu) : 0u;
+        k[r] = valid ? key_in[g] : 0;
+        ix[r] = valid ? (idx_in ? idx_in[g] : (uint32_t)g) : 0u;
+        const uint32_t d = (uint32_t)((k[r] >> shift) & 0xFFu);
         const uint64_t active = __ballot(valid);
-        uint64_t peers = 0;
         int rank = 0;
         if (valid) {
-            peers = match_digit(d, active);
+            const uint64_t peers = match_digit(d, active);
             rank = lanes_below(peers);
             if (rank == 0) wave_cnt[wave_id()][d] = (uint32_t)__popcll(peers);
         }
         __syncthreads();
         {
-            // per digit: exclusive prefix over waves, then advance the running offset
             const int dd = threadIdx.x;
             uint32_t acc = run[dd];
 #pragma unroll
@@ -257,13 +276,39 @@ __global__ void __launch_bounds__(kThreads) k_radix_scatter(const uint64_t *__re
             run[dd] = acc;
         }
         __syncthreads();
-        if (valid) {
-            const uint32_t dst = wave_cnt[wave_id()][d] + (uint32_t)rank;
-#pragma unroll
-            for (int w = 0; w < W; ++w) key_out[(uint64_t)w * stride + dst] = key_in[(uint64_t)w * stride + g];
-            idx_out[dst] = idx_in ? idx_in[g] : (uint32_t)g;
-        }
+        rk[r] = (uint16_t)(valid ? wave_cnt[wave_id()][d] + (uint32_t)rank : 0u);
         __syncthreads();
+    }
+    // global base of each digit: exclusive prefix of the pass histogram over digits
+    uint32_t all_digits;
+    const uint32_t gbase = block_exclusive_scan(ghist[threadIdx.x], &all_digits);
+    // digit d: publish this tile's count, then sum the earlier tiles' counts
+    {
+        const int d = threadIdx.x;
+        const uint32_t cnt = run[d];
+        uint64_t *st = status + t * 256;
+        lb_publish(&st[d], t == 0 ? kLbInclusive : kLbAggregate, cnt);
+        uint64_t excl = 0;
+        for (int64_t p = (int64_t)t - 1; p >= 0; --p) {
+            uint64_t w;
+            do {
+                w = __hip_atomic_load(&status[p * 256 + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } while ((w & ~kLbValue) == 0);
+            excl += w & kLbValue;
+            if ((w & ~kLbValue) == kLbInclusive) break;
+        }
+        if (t > 0) lb_publish(&st[d], kLbInclusive, excl + cnt);
+        dig_base[d] = gbase + (uint32_t)excl;
+    }
+    __syncthreads();
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
+        if (g < n) {
+            const uint32_t d = (uint32_t)((k[r] >> shift) & 0xFFu);
+            const uint32_t dst = dig_base[d] + rk[r];
+            key_out[dst] = k[r];
+            idx_out[dst] = ix[r];
+        }
     }
 }
 
