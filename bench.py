@@ -34,11 +34,12 @@ METRIC = "cluster spawn attempts/s on 1 MI355X; FP32 vs FP64 at equal E_proj err
 HBM_PEAK_GBS = 8000.0
 # Plain 32-bit vector ALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
-# Algorithmic 32-bit operations of one spawning attempt (Philox block, generator, element,
-# signs, amplitude) -- the per-unit figure of the generation kernel (see the design notes).
-OPS_PER_ATTEMPT = 300.0
-HBM_KERNELS = {"radix_ghist", "radix_onesweep", "gather", "seg_fold", "merge", "compact", "weights_scan",
-               "noncomposite"}
+# Algorithmic lane operations of one spawning attempt: Philox4x32-10 blocks (10 rounds of two
+# 32x32 multiplies (4 ops), 4 xors and 2 key adds = 100 ops per block) -- 2 blocks for the UEG
+# generator's three 64-bit draws, 3 for the molecular generator's five -- plus about 100
+# (UEG) / 150 (molecular) for the excitation, the Slater-Condon element, the signs, the
+# amplitude and the cutoff rounding.
+OPS_PER_ATTEMPT = {"ueg": 300.0, "mol": 450.0}
 
 
 class _Roctx:
@@ -109,7 +110,7 @@ def grow(state, w: inputs.Workload, log, max_steps: int = 20000, tau_grow_factor
 
 
 def run_leg(w: inputs.Workload, precision: str, steps: int, warmup: int, log, profile: bool = True,
-            load_state: str | None = None, save_state: str | None = None):
+            load_state: str | None = None, save_state: str | None = None, breakdown_steps: int = 20):
     state = make_state(w, precision, init_pop=max(100.0, w.target_population / 50))
     if load_state:
         z = np.load(load_state)
@@ -132,53 +133,114 @@ def run_leg(w: inputs.Workload, precision: str, steps: int, warmup: int, log, pr
     if save_state:
         keys, amps, n0, step = state.ccmc_export()
         np.savez(save_state, keys=keys, amps=amps, n_ref=n0, step=step, shift=ctl.shift)
+
+    def steps_(k):
+        nonlocal st, nsel
+        att = sel = sp = 0
+        for _ in range(k):
+            st = state.ccmc_step(w.tau, ctl.shift, nsel)
+            ctl.update(st["n_total"])
+            nsel = driver.selections(st["n_total"])
+            att += st["n_spawn_attempts"]
+            sel += st["n_selections"]
+            sp += st["n_spawns"]
+        return att, sel, sp
+
+    # per-kernel breakdown: every launch timed with events (not the timed region)
+    breakdown = {}
+    dominant = None
     if profile:
-        state.ccmc_profile(True)
+        state.ccmc_profile("*")
+        steps_(min(steps, breakdown_steps))
+        breakdown = state.ccmc_profile_read()
+        state.ccmc_profile(None)
+        dominant = max(breakdown.items(), key=lambda kv: kv[1]["ms"])[0]
+    # the timed region: only the dominant kernel carries events
+    if dominant:
+        state.ccmc_profile(dominant)
         state.ccmc_profile_read()
-    attempts = selections = spawns = 0
     ROCTX.resume()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        st = state.ccmc_step(w.tau, ctl.shift, nsel)
-        ctl.update(st["n_total"])
-        nsel = driver.selections(st["n_total"])
-        attempts += st["n_spawn_attempts"]
-        selections += st["n_selections"]
-        spawns += st["n_spawns"]
+    attempts, selections, spawns = steps_(steps)
     elapsed = time.perf_counter() - t0
     ROCTX.pause()
-    prof = state.ccmc_profile_read() if profile else {}
-    state.ccmc_profile(False)
+    timed = state.ccmc_profile_read() if dominant else {}
+    state.ccmc_profile(None)
     keys, amps, n0, step = state.ccmc_export()
     out = dict(attempts=attempts, selections=selections, spawns=spawns, seconds=elapsed, grow_steps=ngrow,
-               n_total=st["n_total"], n_ref=st["n_ref"], excitors=st["n_excitors"], shift=ctl.shift, profile=prof,
-               memory=state.ccmc_memory())
+               n_total=st["n_total"], n_ref=st["n_ref"], excitors=st["n_excitors"], shift=ctl.shift,
+               profile=breakdown, timed=timed, memory=state.ccmc_memory())
     state.close()
     return out
 
 
-def roofline(prof: dict):
-    """Roofline entry for the kernel with the most time in the timed region."""
-    if not prof:
+def source_hash() -> str:
+    """SHA-256 of the HIP sources and the C ABI header: counter figures taken on other
+    sources do not describe the kernels that run now."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1807_03749_amd", "csrc")
+    for f in sorted(os.listdir(csrc)) + ["../../include/ccmc.h"]:
+        path = os.path.normpath(os.path.join(csrc, f))
+        if path.endswith((".h", ".hip")):
+            with open(path, "rb") as fh:
+                h.update(os.path.basename(path).encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/<kernel>_<workload>_traffic.txt: FETCH_SIZE and WRITE_SIZE per dispatch,
+    scaled by the same counters on a copy of known size), or None when the summary is
+    missing or was taken on other sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
         return None
-    name, p = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    kv = {}
+    with open(path) as f:
+        for ln in f:
+            if "=" in ln and not ln.lstrip().startswith("#"):
+                k, v = ln.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def roofline(timed: dict, w: inputs.Workload):
+    """Roofline entry for the dominant kernel, from its HIP-event durations in the timed
+    region.  generate is bound by the vector ALUs: its algorithmic work is the integer and
+    FP operations of one spawning attempt (OPS_PER_ATTEMPT); every other kernel is priced
+    by its algorithmic HBM bytes against the 8 TB/s peak."""
+    if not timed:
+        return None
+    name, p = max(timed.items(), key=lambda kv: kv[1]["ms"])
     avg_s = p["ms"] / p["launches"] / 1e3
-    if name in HBM_KERNELS:
-        achieved = p["bytes"] / p["launches"] / avg_s / 1e9
-        peak = HBM_PEAK_GBS
-        r = dict(bound="hbm", achieved=achieved, peak=peak, unit="GB/s")
+    if name == "generate":
+        ops = OPS_PER_ATTEMPT[w.system]
+        achieved = p["items"] / p["launches"] * ops / avg_s / 1e9
+        r = dict(bound="alu", achieved=achieved, peak=ALU_PEAK_GOPS, unit="Gop/s",
+                 ops_per_attempt=ops, attempts_per_launch=p["items"] / p["launches"])
     else:
-        achieved = p["items"] / p["launches"] * OPS_PER_ATTEMPT / avg_s / 1e9
-        r = dict(bound="alu", achieved=achieved, peak=ALU_PEAK_GOPS, unit="Gop/s")
-    r.update(frac=r["achieved"] / r["peak"], traffic=None, kernel=name, launches=p["launches"],
-             avg_ms=p["ms"] / p["launches"], bytes_per_launch=p["bytes"] / p["launches"])
+        achieved = p["bytes"] / p["launches"] / avg_s / 1e9
+        r = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s")
+    r.update(frac=r["achieved"] / r["peak"], traffic=measured_traffic(name, w.name), kernel=name,
+             launches=p["launches"], avg_ms=p["ms"] / p["launches"],
+             algorithmic_bytes_per_launch=p["bytes"] / p["launches"])
     return r
 
 
+ANNIHILATION = ("gather", "radix_ghist", "radix_onesweep", "seg_fold", "new_scan", "new_compact", "merge",
+                "keep_scan", "compact")
+
+
 def annihilation_roofline(prof: dict):
-    """Achieved HBM bandwidth of the sort / reduce / merge kernels taken together."""
-    names = [n for n in ("gather", "radix_ghist", "radix_onesweep", "seg_fold", "merge", "compact")
-             if n in prof]
+    """Algorithmic HBM bandwidth of the annihilation kernels (sort, fold, merge, rounding,
+    compaction) taken together, from the per-kernel breakdown."""
+    names = [n for n in ANNIHILATION if n in prof]
     ms = sum(prof[n]["ms"] for n in names)
     by = sum(prof[n]["bytes"] for n in names)
     if ms <= 0:
@@ -282,8 +344,10 @@ def main():
                        load_state=args.load_state, save_state=args.save_state)
     value = main_leg["attempts"] / main_leg["seconds"]
     log(f"{args.precision}: {value:.4e} attempts/s, {1e3 * main_leg['seconds'] / args.steps:.3f} ms/step")
-    for k, p in sorted(main_leg["profile"].items(), key=lambda kv: -kv[1]["ms"]):
+    prof = main_leg["profile"]
+    for k, p in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]):
         log(f"  {k:16s} {p['ms'] / max(p['launches'], 1):8.4f} ms avg  x{p['launches']}")
+    nb = max(1, prof.get("gather", {}).get("launches", 0))
     out = {
         "metric": METRIC,
         "value": value,
@@ -302,12 +366,17 @@ def main():
                    "target_population": w.target_population, "full_noncomposite": w.full_noncomposite,
                    "min_spawn_attempts": w.min_spawn_attempts, "excitors": main_leg["excitors"],
                    "n_total": main_leg["n_total"], "selections_per_step": main_leg["selections"] / args.steps,
-                   "spawns_per_step": main_leg["spawns"] / args.steps, "parallelism": "1 GPU"},
-        "roofline": roofline(main_leg["profile"]),
-        "annihilation_roofline": annihilation_roofline(main_leg["profile"]),
+                   "spawns_per_step": main_leg["spawns"] / args.steps,
+                   "records_per_step": prof.get("gather", {}).get("items", 0) / nb, "parallelism": "1 GPU"},
+        "roofline": roofline(main_leg["timed"], w),
+        "annihilation_roofline": annihilation_roofline(prof),
         "kernels": {k: dict(avg_ms=p["ms"] / max(p["launches"], 1), launches=p["launches"],
-                            share=p["ms"] / max(1e-9, sum(q["ms"] for q in main_leg["profile"].values())))
-                    for k, p in main_leg["profile"].items()},
+                            items_per_launch=p["items"] / max(p["launches"], 1),
+                            bytes_per_launch=p["bytes"] / max(p["launches"], 1),
+                            share=p["ms"] / max(1e-9, sum(q["ms"] for q in prof.values())))
+                    for k, p in prof.items()},
+        "breakdown_note": "per-kernel figures from a separate pass with every launch timed by HIP events; "
+                          "the timed region carries events on the dominant kernel only",
         "device_memory_bytes": main_leg["memory"],
     }
     if not args.no_fp32 and args.precision == "fp64":

@@ -172,9 +172,12 @@ ccmc_status ccmc_spawns_size(const ccmc_state *st, uint64_t *n);
 ccmc_status ccmc_export_spawns(const ccmc_state *st, uint64_t *keys, double *amps, uint64_t *ids,
                                uint64_t capacity, uint64_t *n);
 
-/* Kernel timing: enable (1) or disable (0) HIP-event timing of every launch on the state's
- * stream; ccmc_profile_read copies up to `capacity` accumulated entries and resets them. */
-ccmc_status ccmc_profile(ccmc_state *st, int enable);
+/* Kernel timing with HIP events recorded on the state's stream around each timed launch.
+ * kernels: NULL or "" turns timing off; "*" times every launch of the step; otherwise a
+ * comma-separated list of the kernel names that ccmc_profile_read reports (e.g. "generate")
+ * times those only, so that the rest of the step runs without events.  ccmc_profile_read
+ * copies up to `capacity` accumulated entries and resets them. */
+ccmc_status ccmc_profile(ccmc_state *st, const char *kernels);
 ccmc_status ccmc_profile_read(ccmc_state *st, ccmc_kernel_time *out, int capacity, int *n);
 
 /* Sizes of the state's system: electrons N, spin orbitals M (for the UEG derived from

@@ -94,7 +94,7 @@ def lib():
             "ccmc_import": (st, [vp, _u64p, _f64p, C.c_uint64, C.c_double, C.c_uint64]),
             "ccmc_spawns_size": (st, [vp, C.POINTER(C.c_uint64)]),
             "ccmc_export_spawns": (st, [vp, _u64p, _f64p, _u64p, C.c_uint64, C.POINTER(C.c_uint64)]),
-            "ccmc_profile": (st, [vp, C.c_int]),
+            "ccmc_profile": (st, [vp, C.c_char_p]),
             "ccmc_profile_read": (st, [vp, C.POINTER(ccmc_kernel_time), C.c_int, C.POINTER(C.c_int)]),
             "ccmc_memory": (st, [vp, C.POINTER(C.c_uint64)]),
             "ccmc_dims": (st, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
@@ -216,8 +216,13 @@ class State:
 
     records = ccmc_export_spawns
 
-    def ccmc_profile(self, enable: bool = True):
-        self._check(lib().ccmc_profile(self._h, int(enable)))
+    def ccmc_profile(self, kernels="*"):
+        """Time launches with HIP events: "*" every launch, a comma-separated list of kernel
+        names, or None / False to stop."""
+        if kernels is True:
+            kernels = "*"
+        arg = kernels.encode() if kernels else None
+        self._check(lib().ccmc_profile(self._h, arg))
 
     def ccmc_profile_read(self) -> dict:
         buf = (ccmc_kernel_time * 64)()

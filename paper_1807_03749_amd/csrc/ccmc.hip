@@ -30,12 +30,22 @@ struct DevBuf {
 
 // A timed launch; its work is unit_bytes x the count it covers, known when it is resolved
 // (a count produced on the device is read back at the end of the step).
-struct Pending {
-    const char *name;
-    hipEvent_t a, b;
+// Work of one launch for the profile: algorithmic bytes = unit_bytes x count, work units =
+// *items (or the same count).  Counts produced on the device are read after the step's
+// synchronisation, through pointers to the host copies of the step's sizes.
+struct Work {
     double unit_bytes;
     const uint64_t *count;  // live count, or null for `fixed`
     uint64_t fixed;
+    const uint64_t *items = nullptr;
+    double unit_bytes2 = 0;  // plus unit_bytes2 x *count2
+    const uint64_t *count2 = nullptr;
+};
+
+struct Pending {
+    const char *name;
+    hipEvent_t a, b;
+    Work w;
 };
 
 struct Accum {
@@ -92,7 +102,7 @@ struct ccmc_state {
     DevBuf is_new, new_pos, ins, seg_sum, nkey, nrank, nins, nsum, keep, pos;
     uint64_t dcap = 0;  // dense record capacity
     uint64_t slot_hint = 1 << 16, rec_hint = 1 << 14;  // capacities planned for the next step
-    uint64_t cnt_slots = 0, cnt_rec = 0, cnt_merged = 0;  // live counts of the last step
+    uint64_t cnt_slots = 0, cnt_rec = 0, cnt_merged = 0, cnt_new = 0, cnt_att = 0, cnt_live_items = 0;  // live counts of the last step
     DevBuf lb;  // step scalars, tickets, radix histograms and look-back status words
     Scratch *hscratch = nullptr;  // pinned
     // last step's spawn list (keep_spawn_ids)
@@ -101,6 +111,7 @@ struct ccmc_state {
     size_t bytes_held = 0;
     std::string err;
     bool prof = false;
+    std::string prof_names;  // "*" or ",name,name,": the launches timed
     std::vector<Pending> pending;
     std::vector<hipEvent_t> ev_pool;
     std::map<std::string, Accum> accum;
@@ -183,14 +194,19 @@ hipEvent_t take_event(ccmc_state *st)
     return e;
 }
 
-template <class F>
-void launch(ccmc_state *st, const char *name, double unit_bytes, const uint64_t *count, uint64_t fixed, F &&f)
+bool profiled(const ccmc_state *st, const char *name)
 {
-    if (!st->prof) {
+    return st->prof_names == "*" || st->prof_names.find("," + std::string(name) + ",") != std::string::npos;
+}
+
+template <class F>
+void launch(ccmc_state *st, const char *name, Work w, F &&f)
+{
+    if (!st->prof || !profiled(st, name)) {
         f();
         return;
     }
-    Pending p{name, take_event(st), take_event(st), unit_bytes, count, fixed};
+    Pending p{name, take_event(st), take_event(st), w};
     (void)hipEventRecord(p.a, st->stream);
     f();
     (void)hipEventRecord(p.b, st->stream);
@@ -203,12 +219,12 @@ void resolve_profile(ccmc_state *st)
         float ms = 0;
         (void)hipEventSynchronize(p.b);
         (void)hipEventElapsedTime(&ms, p.a, p.b);
-        const double n = (double)(p.count ? *p.count : p.fixed);
+        const double n = (double)(p.w.count ? *p.w.count : p.w.fixed);
         Accum &a = st->accum[p.name];
         a.launches++;
         a.ms += ms;
-        a.bytes += p.unit_bytes * n;
-        a.items += n;
+        a.bytes += p.w.unit_bytes * n + (p.w.count2 ? p.w.unit_bytes2 * (double)*p.w.count2 : 0.0);
+        a.items += p.w.items ? (double)*p.w.items : n;
         st->ev_pool.push_back(p.a);
         st->ev_pool.push_back(p.b);
     }
@@ -217,13 +233,14 @@ void resolve_profile(ccmc_state *st)
 
 // --------------------------------------------------------------------------- scan
 // Single-launch look-back scan; status must hold ceil(n / kScanTile) zeroed words.
-template <typename V, typename Src>
-void scan_lb(ccmc_state *st, Src in, V *out, uint64_t n, bool inclusive, uint64_t *status, uint64_t *ticket,
+template <typename V, typename Src, typename Out>
+void scan_lb(ccmc_state *st, Src in, Out out, uint64_t n, bool inclusive, uint64_t *status, uint64_t *ticket,
              uint64_t *total)
 {
     if (!n) return;
     const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
-    k_scan_lb<V, Src><<<(unsigned)tiles, kThreads, 0, st->stream>>>(in, out, n, inclusive ? 1 : 0, status, ticket, total);
+    k_scan_lb<V, Src, Out><<<(unsigned)tiles, kThreads, 0, st->stream>>>(in, out, n, inclusive ? 1 : 0, status, ticket,
+                                                                         total);
 }
 
 uint64_t scan_tiles(uint64_t n) { return (n + kScanTile - 1) / kScanTile; }
@@ -565,7 +582,7 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     TRY(ensure(st, st->keep, (mcap + 1) * sizeof(uint32_t)));
     TRY(ensure(st, st->pos, (mcap + 1) * sizeof(uint32_t)));
     const uint64_t tiles = (rec_cap + kSortTile - 1) / kSortTile;
-    const int passes = std::max(1, (st->rank_bits + 7) / 8);
+    const int passes = std::max(1, (st->rank_bits + kRadixBits - 1) / kRadixBits);
     const unsigned nb_fnc = fnc ? grid_for(n_fnc) : 0, nb_sel = n_sel ? grid_for(n_sel) : 0;
     const size_t nparts = (size_t)(nb_fnc + nb_sel + 1);
     TRY(ensure(st, st->num_part, nparts * sizeof(double)));
@@ -586,13 +603,15 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     const uint64_t o_new = o_boff + scan_tiles(nblk_cap + 1);
     const uint64_t o_keep = o_new + scan_tiles(rec_cap);
     const uint64_t o_ghist = o_keep + scan_tiles(mcap);
-    const uint64_t o_rstat = o_ghist + (uint64_t)passes * 128;
-    const uint64_t lb_words = o_rstat + (uint64_t)passes * tiles * 256;
+    const uint64_t o_rstat = o_ghist + (uint64_t)passes * kRadixBins / 2;
+    const uint64_t lb_words = o_rstat + (uint64_t)passes * tiles * kRadixBins;
     TRY(ensure(st, st->lb, lb_words * sizeof(uint64_t)));
     uint64_t *lb = ptr<uint64_t>(st->lb);
     uint64_t *tick = lb + o_tick;
     Scratch *sc = reinterpret_cast<Scratch *>(lb);
-    k_fill<uint64_t><<<grid_for(lb_words), kThreads, 0, s>>>(lb, lb_words, 0ull);
+    launch(st, "clear", Work{8.0, nullptr, lb_words}, [&] {
+        k_fill<uint64_t><<<grid_for(lb_words), kThreads, 0, s>>>(lb, lb_words, 0ull);
+    });
 
     const uint64_t scap = st->scap;
     const uint64_t *skey = ptr<uint64_t>(st->skey[c]);
@@ -602,11 +621,13 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
 
     // ---- (a1) selection weights, formed inside the scan of their prefix; guide table
     if (ne) {
-        launch(st, "weights_scan", tb + 8.0, nullptr, ne, [&] {
-            scan_lb<uint64_t>(st, WeightSrc<T>{samp, sc}, ptr<uint64_t>(st->P), ne, true, lb + o_weights,
+        launch(st, "weights_scan", Work{tb + 8.0, nullptr, ne}, [&] {
+            scan_lb<uint64_t>(st, WeightSrc<T>{samp, sc}, ArrayOut<uint64_t>{ptr<uint64_t>(st->P)}, ne, true, lb + o_weights,
                               tick + kTkWeights, nullptr);
         });
-        if (n_sel) k_guide<<<grid_for(ne + 1), kThreads, 0, s>>>(ptr<uint64_t>(st->P), ne, sc, ptr<uint32_t>(st->guide));
+        launch(st, "guide", Work{16.0, nullptr, ne}, [&] {
+            k_guide<<<grid_for(ne + 1), kThreads, 0, s>>>(ptr<uint64_t>(st->P), ne, sc, ptr<uint32_t>(st->guide));
+        });
     }
 
     // ---- (a2-a5, a9, a10) items: non-composite (FNC) then sampled clusters
@@ -614,48 +635,49 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
                 ptr<uint8_t>(st->ilevel), ptr<uint64_t>(st->icnt), st->icap};
     ItemPartials part{ptr<double>(st->num_part), ptr<uint64_t>(st->att_part), ptr<uint64_t>(st->disc_part),
                       ptr<uint64_t>(st->max_part)};
-    ItemPartials part_sel{part.num + nb_fnc, part.att + nb_fnc, part.disc + nb_fnc, part.maxn + nb_fnc};
     const double item_bytes = kb + 2 * tb + 13.0;  // key, A, death, n, level, slot count
-    if (fnc) {
-        launch(st, "noncomposite", kb + 2 * tb + item_bytes, nullptr, n_fnc, [&] {
-            k_noncomposite<W, T><<<nb_fnc, kThreads, 0, s>>>(st->sd, skey, samp, sK, scap, ne, st->n0, a, it, part, sc);
+    if (n_items) {
+        // bytes: each item written (plus, for the non-composite ones, the store entry read)
+        launch(st, "items", Work{item_bytes, nullptr, n_items}, [&] {
+            k_items<W, T><<<nb_fnc + nb_sel, kThreads, 0, s>>>(st->sd, skey, samp, sK, scap, ne, ptr<uint64_t>(st->P),
+                                                               ptr<uint32_t>(st->guide), st->n0, a, it, nb_fnc, n_fnc,
+                                                               part, sc);
         });
     }
-    if (n_sel) {
-        launch(st, "select", item_bytes, nullptr, n_sel, [&] {
-            k_select<W, T><<<nb_sel, kThreads, 0, s>>>(st->sd, skey, samp, scap, ne, ptr<uint64_t>(st->P),
-                                                        ptr<uint32_t>(st->guide), st->n0, a, it, n_fnc, part_sel, sc);
-        });
-    } else {
-        k_fill<uint64_t><<<1, 1, 0, s>>>(it.cnt + n_items, 1, 0ull);
-    }
-    scan_lb<uint64_t>(st, ArraySrc<uint64_t>{it.cnt}, ptr<uint64_t>(st->ioff), n_items + 1, false, lb + o_off,
-                      tick + kTkOff, &sc->n_slots);
+    if (!n_sel) k_fill<uint64_t><<<1, 1, 0, s>>>(it.cnt + n_items, 1, 0ull);
+    launch(st, "slot_scan", Work{16.0, nullptr, n_items + 1}, [&] {
+        scan_lb<uint64_t>(st, ArraySrc<uint64_t>{it.cnt},
+                          SlotOut{ptr<uint64_t>(st->ioff), ptr<uint64_t>(st->block_item), slot_cap}, n_items + 1, false,
+                          lb + o_off, tick + kTkOff, &sc->n_slots);
+    });
 
     // ---- (a6-a8) records: death and spawning attempts, one lane per slot, compacted per block
     Records reg{nullptr, ptr<uint64_t>(st->rkey), st->ramp.p, ptr<uint64_t>(st->rid), st->rcap};
     GenStats gst{ptr<uint32_t>(st->gcount), ptr<uint32_t>(st->gspawn), ptr<uint32_t>(st->gdeath)};
-    k_block_items<<<grid_for(nblk_cap + 1), kThreads, 0, s>>>(ptr<uint64_t>(st->ioff), n_items, slot_cap,
-                                                             ptr<uint64_t>(st->block_item), sc);
-    launch(st, "generate", kb + tb, &st->cnt_rec, 0, [&] {
+    // bytes: the records written and each live item read once (key, A, death, n, offset);
+    // work units: spawning attempts
+    launch(st, "generate", Work{kb + tb + (ids ? 8.0 : 0.0), &st->cnt_rec, 0, &st->cnt_att, kb + 2 * tb + 12.0,
+                                &st->cnt_live_items}, [&] {
         k_generate<W, T><<<(unsigned)nblk_cap, kThreads, 0, s>>>(st->sd, it, ptr<uint64_t>(st->ioff),
                                                                  ptr<uint64_t>(st->block_item), n_fnc, n_items, slot_cap, a,
-                                                                 reg, ids ? 1 : 0, gst);
+                                                                 reg, ids ? 1 : 0, gst, sc);
     });
-    scan_lb<uint32_t>(st, ArraySrc<uint32_t>{gst.count}, ptr<uint32_t>(st->boff), nblk_cap + 1, false, lb + o_boff,
-                      tick + kTkBoff, &sc->n_rec);
+    launch(st, "region_scan", Work{8.0, nullptr, nblk_cap + 1}, [&] {
+        scan_lb<uint32_t>(st, ArraySrc<uint32_t>{gst.count}, ArrayOut<uint32_t>{ptr<uint32_t>(st->boff)}, nblk_cap + 1,
+                          false, lb + o_boff, tick + kTkBoff, &sc->n_rec);
+    });
     const uint64_t dc = st->dcap;
     Records rec{ptr<uint64_t>(st->drank), ptr<uint64_t>(st->dkey), st->damp.p, ptr<uint64_t>(st->did), dc};
-    launch(st, "gather", 2.0 * (kb + tb + (ids ? 8.0 : 0.0)) + 8.0, &st->cnt_rec, 0, [&] {
+    launch(st, "gather", Work{2.0 * (kb + tb + (ids ? 8.0 : 0.0)) + 8.0, &st->cnt_rec, 0}, [&] {
         k_gather<W, T><<<grid_for(rec_cap), kThreads, 0, s>>>(st->sd, reg, ptr<uint32_t>(st->boff), nblk_cap, rec_cap, rec,
                                                               ids ? 1 : 0, sc);
     });
 
     // ---- (a11) stable LSD radix sort of (rank, record index): one histogram launch for all
-    // passes, then one single-sweep launch per 8-bit digit
+    // passes, then one single-sweep launch per digit
     const uint64_t *n_live = &sc->n_live;
     uint32_t *ghist = reinterpret_cast<uint32_t *>(lb + o_ghist);
-    launch(st, "radix_ghist", 8.0, &st->cnt_rec, 0, [&] {
+    launch(st, "radix_ghist", Work{8.0, &st->cnt_rec, 0}, [&] {
         k_radix_ghist<<<(unsigned)tiles, kThreads, 0, s>>>(ptr<uint64_t>(st->drank), n_live, passes, ghist);
     });
     const uint64_t *kin = ptr<uint64_t>(st->drank);
@@ -664,9 +686,10 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     for (int p = 0; p < passes; ++p) {
         uint64_t *kout = ptr<uint64_t>(st->sr[ob]);
         uint32_t *iout = ptr<uint32_t>(st->sidx[ob]);
-        launch(st, "radix_onesweep", 2 * 8.0 + (iin ? 8.0 : 4.0), &st->cnt_rec, 0, [&] {
-            k_radix_onesweep<<<(unsigned)tiles, kThreads, 0, s>>>(kin, iin, kout, iout, n_live, 8 * p, ghist + 256 * p,
-                                                                  lb + o_rstat + (uint64_t)p * tiles * 256,
+        launch(st, "radix_onesweep", Work{2 * 8.0 + (iin ? 8.0 : 4.0), &st->cnt_rec, 0}, [&] {
+            k_radix_onesweep<<<(unsigned)tiles, kThreads, 0, s>>>(kin, iin, kout, iout, n_live, kRadixBits * p,
+                                                                  ghist + kRadixBins * p,
+                                                                  lb + o_rstat + (uint64_t)p * tiles * kRadixBins,
                                                                   tick + kTkRadix + p);
         });
         kin = kout;
@@ -678,18 +701,22 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
 
     // ---- (a12) runs of equal determinants: left fold in record order, store lookup by rank
     double *delta = ptr<double>(st->delta);
-    launch(st, "seg_fold", 8.0 + 4.0 + tb, &st->cnt_rec, 0, [&] {
+    launch(st, "seg_fold", Work{8.0 + 4.0 + tb + 4.0, &st->cnt_rec, 0}, [&] {
         k_seg_fold<T><<<grid_for(rec_cap), kThreads, 0, s>>>(sorted_rank, sorted_idx, ptr<T>(st->damp), rec_cap, srank, ne,
                                                              delta, ptr<uint32_t>(st->is_new), ptr<uint64_t>(st->ins),
                                                              ptr<double>(st->seg_sum), sc);
     });
-    scan_lb<uint32_t>(st, ArraySrc<uint32_t>{ptr<uint32_t>(st->is_new)}, ptr<uint32_t>(st->new_pos), rec_cap, false,
-                      lb + o_new, tick + kTkNew, &sc->n_new);
-    k_new_compact<W><<<grid_for(rec_cap), kThreads, 0, s>>>(sorted_rank, sorted_idx, ptr<uint64_t>(st->dkey), dc, rec_cap,
-                                                            ptr<uint32_t>(st->is_new), ptr<uint32_t>(st->new_pos),
-                                                            ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum),
-                                                            ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), dc,
-                                                            ptr<uint64_t>(st->nins), ptr<double>(st->nsum), sc);
+    launch(st, "new_scan", Work{8.0, &st->cnt_rec, 0}, [&] {
+        scan_lb<uint32_t>(st, ArraySrc<uint32_t>{ptr<uint32_t>(st->is_new)}, ArrayOut<uint32_t>{ptr<uint32_t>(st->new_pos)},
+                          rec_cap, false, lb + o_new, tick + kTkNew, &sc->n_new);
+    });
+    launch(st, "new_compact", Work{2.0 * (kb + 24.0) + 8.0, &st->cnt_new, 0}, [&] {
+        k_new_compact<W><<<grid_for(rec_cap), kThreads, 0, s>>>(sorted_rank, sorted_idx, ptr<uint64_t>(st->dkey), dc, rec_cap,
+                                                                ptr<uint32_t>(st->is_new), ptr<uint32_t>(st->new_pos),
+                                                                ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum),
+                                                                ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), dc,
+                                                                ptr<uint64_t>(st->nins), ptr<double>(st->nsum), sc);
+    });
 
     // ---- (a12, a13) merge and round into the other store buffer, compact back into this one
     const int m = 1 - c;
@@ -700,21 +727,26 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     uint64_t *mrank = ptr<uint64_t>(st->srank[m]);
     uint32_t *keep = ptr<uint32_t>(st->keep), *pos = ptr<uint32_t>(st->pos);
     const double eb = kb + 2 * tb + 8.0;  // one store entry: key, amplitude, diagonal, rank
-    launch(st, "merge", 2.0 * eb, &st->cnt_merged, 0, [&] {
+    launch(st, "merge", Work{2.0 * eb + 12.0, &st->cnt_merged, 0}, [&] {
         k_merge<W, T><<<grid_for(mcap), kThreads, 0, s>>>(st->sd, skey, samp, sK, srank, S2, ne, delta,
                                                           ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), dc,
                                                           ptr<uint64_t>(st->nins), ptr<double>(st->nsum), mkey, mamp, mK, mrank,
                                                           S2, mcap, a, keep, sc);
     });
-    scan_lb<uint32_t>(st, ArraySrc<uint32_t>{keep}, pos, mcap, false, lb + o_keep, tick + kTkKeep, &sc->n_out);
-    launch(st, "compact", 2.0 * eb, &st->cnt_merged, 0, [&] {
+    launch(st, "keep_scan", Work{8.0, &st->cnt_merged, 0}, [&] {
+        scan_lb<uint32_t>(st, ArraySrc<uint32_t>{keep}, ArrayOut<uint32_t>{pos}, mcap, false, lb + o_keep, tick + kTkKeep,
+                          &sc->n_out);
+    });
+    launch(st, "compact", Work{2.0 * eb + 8.0, &st->cnt_merged, 0}, [&] {
         k_compact<W, T><<<nb_abs, kThreads, 0, s>>>(mkey, mamp, mK, mrank, S2, mcap, keep, pos,
                                                     ptr<uint64_t>(st->skey[c]), ptr<T>(st->samp[c]), ptr<T>(st->sK[c]),
                                                     ptr<uint64_t>(st->srank[c]), S2, delta, ptr<double>(st->abs_part), sc);
     });
 
     // ---- (a14) the step's statistics in one fixed-order reduction
-    k_final<<<1, kThreads, 0, s>>>(part, nb_fnc + nb_sel, gst, nblk_cap, ptr<double>(st->abs_part), nb_abs, sc);
+    launch(st, "final", Work{0.0, nullptr, 0}, [&] {
+        k_final<<<1, kFinalThreads, 0, s>>>(part, nb_fnc + nb_sel, gst, nblk_cap, ptr<double>(st->abs_part), nb_abs, sc);
+    });
 
     // ---- (a14) the one synchronisation of the step
     HIP_TRY(hipMemcpyAsync(st->hscratch, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
@@ -723,6 +755,9 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     st->cnt_slots = scr.n_slots;
     st->cnt_rec = scr.n_live;
     st->cnt_merged = ne + scr.n_new;
+    st->cnt_new = scr.n_new;
+    st->cnt_att = scr.n_attempts;
+    st->cnt_live_items = scr.n_slots - scr.n_attempts;
     if (st->prof) resolve_profile(st);
     // plan the next step's capacities from this one
     st->slot_hint = std::max(st->slot_hint, scr.n_slots + scr.n_slots / 4 + 4096);
@@ -1150,10 +1185,20 @@ ccmc_status ccmc_export_spawns(const ccmc_state *st, uint64_t *keys, double *amp
     return CCMC_OK;
 }
 
-ccmc_status ccmc_profile(ccmc_state *st, int enable)
+ccmc_status ccmc_profile(ccmc_state *st, const char *kernels)
 {
     if (!st) return CCMC_EINVAL;
-    st->prof = enable != 0;
+    st->prof = kernels != nullptr && kernels[0] != 0;
+    if (!st->prof) {
+        st->prof_names.clear();
+    } else if (std::string(kernels) == "*") {
+        st->prof_names = "*";
+    } else {
+        std::string k;
+        for (const char *c = kernels; *c; ++c)
+            if (*c != ' ') k += *c;
+        st->prof_names = "," + k + ",";
+    }
     return CCMC_OK;
 }
 

@@ -4,10 +4,9 @@
 //   k_fill           clear the step scalars and look-back status words
 //   weights scan     fixed-point selection weights q_i and their prefix          (a1)
 //   k_guide          bucket table of the prefix for the excitor draws           (a2)
-//   k_noncomposite   reference + every excitor as explicit items (FNC)          (a4, a5, a9, a10)
-//   k_select         cluster size, excitor draws, collapse, amplitude           (a2, a3, a4, a9, a10)
-//   slot scan        record slots per item (1 death + n attempts)
-//   k_block_items    first item of each generation block
+//   k_items          non-composite items (FNC): reference + every excitor        (a4, a5, a9, a10)
+//                    and sampled clusters: size, excitor draws, collapse, amplitude  (a2, a3, a4, a9, a10)
+//   slot scan        record slots per item (1 death + n attempts), first item per block
 //   k_generate       one lane per record slot: death or spawning attempt        (a6, a7, a8)
 //   region scan      records per generation block
 //   k_gather         dense records and their truncated-space rank               (a8)
@@ -69,10 +68,10 @@ struct ItemPartials {
     uint64_t *maxn;    // largest attempt count
 };
 
-template <typename V>
+template <typename V, int NW = kWaves>
 __device__ __forceinline__ V block_reduce_max(V v)
 {
-    __shared__ V wave_max[kWaves];
+    __shared__ V wave_max[NW];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const V o = __shfl_down(v, off, 64);
@@ -82,7 +81,7 @@ __device__ __forceinline__ V block_reduce_max(V v)
     __syncthreads();
     V m = wave_max[0];
 #pragma unroll
-    for (int w = 1; w < kWaves; ++w) m = wave_max[w] > m ? wave_max[w] : m;
+    for (int w = 1; w < NW; ++w) m = wave_max[w] > m ? wave_max[w] : m;
     __syncthreads();
     return m;
 }
@@ -122,13 +121,17 @@ template <typename T>
 struct WeightSrc {
     const T *amp;
     Scratch *sc;
+    static constexpr uint64_t kCap = 1ull << 52;  // |N_i| >= 2^28 (or NaN) is a blow-up
     __device__ __forceinline__ uint64_t operator()(uint64_t i) const
     {
         const double a = fabs((double)amp[i]);
-        if (!(a < 0x1.0p28)) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrBlowup);
         double w = rint(a * 16777216.0);
-        if (w < 1.0) w = 1.0;
-        return (uint64_t)fmin(w, 0x1.0p40);
+        w = w < 1.0 ? 1.0 : w;
+        return (uint64_t)fmin(w, (double)kCap);  // NaN -> kCap
+    }
+    __device__ __forceinline__ void check(uint64_t q) const
+    {
+        if (q >= kCap) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrBlowup);
     }
 };
 
@@ -144,8 +147,8 @@ __device__ __forceinline__ uint32_t guide_shift(uint64_t Q, uint64_t n)
 }
 
 // Built by scattering: bucket b holds the first i with P[i] > b << shift, so excitor i owns
-// the buckets b with P[i-1] <= b << shift < P[i] (usually none, one or two); lane n writes
-// the closing entries.  No search, one lane per excitor.
+// the buckets b with P[i-1] <= b << shift < P[i] (usually none, one or two; a large
+// amplitude owns many, written by its whole wavefront); lane n writes the closing entries.
 __global__ void __launch_bounds__(kThreads) k_guide(const uint64_t *__restrict__ P, uint64_t n, Scratch *sc,
                                                     uint32_t *__restrict__ guide)
 {
@@ -159,25 +162,29 @@ __global__ void __launch_bounds__(kThreads) k_guide(const uint64_t *__restrict__
         sc->guide_n = nb;
         if (Q > (1ull << 53)) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrBlowup);
     }
-    if (i > n || n == 0) return;
     const uint64_t unit = 1ull << sh;
-    if (i == n) {  // buckets at or beyond Q
-        for (uint64_t b = (Q + unit - 1) >> sh; b < nb; ++b) guide[b] = (uint32_t)(n - 1);
-        return;
+    uint64_t b0 = 0, b1 = 0;
+    if (n && i < n) {
+        const uint64_t lo = i ? P[i - 1] : 0, hi = P[i];
+        b0 = (lo + unit - 1) >> sh;
+        b1 = (hi + unit - 1) >> sh;  // buckets with b << shift < hi
+        b1 = b1 < nb ? b1 : nb;
+    } else if (n && i == n) {  // buckets at or beyond Q
+        b0 = (Q + unit - 1) >> sh;
+        b1 = nb;
     }
-    const uint64_t lo = i ? P[i - 1] : 0, hi = P[i];
-    for (uint64_t b = (lo + unit - 1) >> sh; (b << sh) < hi && b < nb; ++b) guide[b] = (uint32_t)i;
+    wave_fill_ranges<uint32_t>(guide, b0, b1, (uint32_t)(i < n ? i : n - 1));
 }
 
 // ------------------------------------------------------- non-composite items (FNC)
 // Item 0 is the reference (A = N_0, K = 0), item i+1 the store entry i (A = N_i);
 // p = 1 for all of them (Sec. IV.B).
 template <int W, typename T>
-__global__ void __launch_bounds__(kThreads) k_noncomposite(SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
+__device__ __forceinline__ void noncomposite_block(unsigned blk, const SysDev &S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
                                                            const T *__restrict__ sK, uint64_t sstride, uint64_t ne, double n0,
                                                            StepArgs a, Items<T> it, ItemPartials part, Scratch *sc)
 {
-    const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint64_t k = (uint64_t)blk * kThreads + threadIdx.x;
     double num = 0.0;
     uint64_t att = 0, mx = 0;
     if (k <= ne) {
@@ -216,10 +223,10 @@ __global__ void __launch_bounds__(kThreads) k_noncomposite(SysDev S, const uint6
     const uint64_t batt = block_reduce_sum(att);
     const uint64_t bmax = block_reduce_max(mx);
     if (threadIdx.x == 0) {
-        part.num[blockIdx.x] = bnum;
-        part.att[blockIdx.x] = batt;
-        part.disc[blockIdx.x] = 0;
-        part.maxn[blockIdx.x] = bmax;
+        part.num[blk] = bnum;
+        part.att[blk] = batt;
+        part.disc[blk] = 0;
+        part.maxn[blk] = bmax;
     }
 }
 
@@ -229,12 +236,12 @@ __global__ void __launch_bounds__(kThreads) k_noncomposite(SysDev S, const uint6
 // discarded (Sec. II).  The product of the excitors is collapsed by applying them to the
 // reference one operator at a time; a repeated hole or particle makes it vanish.
 template <int W, typename T>
-__global__ void __launch_bounds__(kThreads) k_select(SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
+__device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
                                                      uint64_t sstride, uint64_t ne, const uint64_t *__restrict__ P,
                                                      const uint32_t *__restrict__ guide, double n0, StepArgs a,
                                                      Items<T> it, uint64_t item_base, ItemPartials part, Scratch *sc)
 {
-    const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint64_t k = (uint64_t)blk * kThreads + threadIdx.x;
     double num = 0.0;
     uint64_t att = 0, disc = 0, mx = 0;
     if (k < a.n_sel) {
@@ -370,12 +377,30 @@ __global__ void __launch_bounds__(kThreads) k_select(SysDev S, const uint64_t *_
     const uint64_t bdisc = block_reduce_sum(disc);
     const uint64_t bmax = block_reduce_max(mx);
     if (threadIdx.x == 0) {
-        part.num[blockIdx.x] = bnum;
-        part.att[blockIdx.x] = batt;
-        part.disc[blockIdx.x] = bdisc;
-        part.maxn[blockIdx.x] = bmax;
+        part.num[blk] = bnum;
+        part.att[blk] = batt;
+        part.disc[blk] = bdisc;
+        part.maxn[blk] = bmax;
     }
     if (k == 0) it.cnt[item_base + a.n_sel] = 0;  // closing entry of the slot-count scan
+}
+
+// One launch for both kinds of item: blocks [0, nb_fnc) are the non-composite items, the
+// rest the sampled clusters (their selection k = (block - nb_fnc) * 256 + thread).
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_items(SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
+                                                    const T *__restrict__ sK, uint64_t sstride, uint64_t ne,
+                                                    const uint64_t *__restrict__ P, const uint32_t *__restrict__ guide,
+                                                    double n0, StepArgs a, Items<T> it, unsigned nb_fnc, uint64_t n_fnc,
+                                                    ItemPartials part, Scratch *sc)
+{
+    if (blockIdx.x < nb_fnc) {
+        noncomposite_block<W, T>(blockIdx.x, S, skey, samp, sK, sstride, ne, n0, a, it, part, sc);
+    } else {
+        const unsigned b = blockIdx.x - nb_fnc;
+        ItemPartials ps{part.num + nb_fnc, part.att + nb_fnc, part.disc + nb_fnc, part.maxn + nb_fnc};
+        select_block<W, T>(b, S, skey, samp, sstride, ne, P, guide, n0, a, it, n_fnc, ps, sc);
+    }
 }
 
 // ----------------------------------------------------------------- generation
@@ -470,29 +495,24 @@ __device__ __forceinline__ bool spawn_attempt(const SysDev &S, const uint64_t *d
     return true;
 }
 
-// First item of each generation block (last item whose offset is <= the block's first slot);
-// entry n_blocks holds the item of the last slot.
-// The live slot count is off[n_items]; blocks beyond it (up to the region capacity) idle.
-__global__ void __launch_bounds__(kThreads) k_block_items(const uint64_t *__restrict__ off, uint64_t n_items,
-                                                          uint64_t slot_cap, uint64_t *__restrict__ block_item, Scratch *sc)
-{
-    const uint64_t u = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    const uint64_t n_slots_all = off[n_items];
-    if (u == 0 && n_slots_all > slot_cap) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrSlotCap);
-    const uint64_t n_slots = n_slots_all < slot_cap ? n_slots_all : slot_cap;
-    const uint64_t n_blocks = (n_slots + kGenSlots - 1) / kGenSlots;
-    if (u > n_blocks || n_slots == 0) return;
-    const uint64_t g = u < n_blocks ? u * kGenSlots : n_slots - 1;
-    uint64_t l0 = 0, h0 = n_items + 1;
-    while (l0 < h0) {
-        const uint64_t mid = (l0 + h0) >> 1;
-        if (off[mid] > g)
-            h0 = mid;
-        else
-            l0 = mid + 1;
+// Output of the record-slot scan: the slot offset of every item, and the first item of each
+// generation block (the item whose slot range holds the block's first slot), scattered by
+// the items themselves -- slots beyond the capacity belong to no block.
+struct SlotOut {
+    uint64_t *p;
+    uint64_t *block_item;
+    uint64_t slot_cap;
+    __device__ __forceinline__ void item(uint64_t i, uint64_t excl, uint64_t x, bool valid) const
+    {
+        uint64_t b0 = 0, b1 = 0;
+        if (valid && x) {
+            const uint64_t end = excl + x < slot_cap ? excl + x : slot_cap;
+            b0 = (excl + kGenSlots - 1) / kGenSlots;
+            b1 = end > 0 ? (end - 1) / kGenSlots + 1 : 0;  // blocks whose first slot is < end
+        }
+        wave_fill_ranges<uint64_t>(block_item, b0, b1, i);
     }
-    block_item[u] = l0 - 1;
-}
+};
 
 constexpr int kGenLdsItems = 2048;
 
@@ -507,19 +527,26 @@ template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, const uint64_t *__restrict__ off,
                                                        const uint64_t *__restrict__ block_item, uint64_t n_fnc,
                                                        uint64_t n_items, uint64_t slot_cap, StepArgs a, Records rec,
-                                                       int keep_ids, GenStats gs)
+                                                       int keep_ids, GenStats gs, Scratch *sc)
 {
     __shared__ uint64_t s_off[kGenLdsItems + 1];
     __shared__ uint32_t wave_tot[kWaves];
     T *ramp = static_cast<T *>(rec.amp);
     const uint64_t g0 = (uint64_t)blockIdx.x * kGenSlots;
-    const uint64_t n_slots = off[n_items] < slot_cap ? off[n_items] : slot_cap;
-    if (blockIdx.x == 0 && threadIdx.x == 0) gs.count[gridDim.x] = 0;  // closing entry of the scan
+    const uint64_t n_all = off[n_items];
+    const uint64_t n_slots = n_all < slot_cap ? n_all : slot_cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        gs.count[gridDim.x] = 0;  // closing entry of the scan
+        if (n_all > slot_cap) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrSlotCap);
+    }
     if (g0 >= n_slots) {  // idle block (the grid covers the capacity)
         if (threadIdx.x == 0) gs.count[blockIdx.x] = gs.spawns[blockIdx.x] = gs.deaths[blockIdx.x] = 0;
         return;
     }
-    const uint64_t lo = block_item[blockIdx.x], hi = block_item[blockIdx.x + 1];
+    // items of this block: from the one holding its first slot to the one holding the next
+    // block's first slot (for the last block: every remaining item)
+    const uint64_t lo = block_item[blockIdx.x];
+    const uint64_t hi = g0 + kGenSlots < n_slots ? block_item[blockIdx.x + 1] : n_items - 1;
     const bool lds = hi - lo + 1 <= (uint64_t)kGenLdsItems;
     if (lds)
         for (uint64_t t = threadIdx.x; t <= hi - lo + 1; t += kThreads) s_off[t] = off[lo + t];
@@ -669,13 +696,15 @@ __global__ void __launch_bounds__(kThreads) k_seg_fold(const uint64_t *__restric
             uint64_t rr[8];
             uint32_t ii[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                rr[u] = (t0 + u < n) ? rank[t0 + u] : ~0ull;
-                ii[u] = (t0 + u < n) ? idx[t0 + u] : 0u;
+            for (int u = 0; u < 8; ++u) {  // clamped indices: unconditional loads
+                const uint64_t tc = t0 + u < n ? t0 + u : n - 1;
+                rr[u] = rank[tc];
+                ii[u] = idx[tc];
+                rr[u] = t0 + u < n ? rr[u] : ~0ull;
             }
             T vv[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) vv[u] = (rr[u] == rk) ? ramp[ii[u]] : T(0);
+            for (int u = 0; u < 8; ++u) vv[u] = ramp[ii[u]];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 more = more && rr[u] == rk;
@@ -819,65 +848,79 @@ __global__ void __launch_bounds__(kThreads) k_compact(const uint64_t *__restrict
     if (threadIdx.x == 0) abs_part[blockIdx.x] = a;
 }
 
-// The step's statistics in one fixed-order reduction (one block): the item kernels'
-// partials, the generation blocks' spawn and death counts, and the per-block |N| sums of
-// the compacted store.
-__global__ void __launch_bounds__(kThreads) k_final(ItemPartials part, uint64_t n_parts, GenStats gs, uint64_t n_gen,
-                                                    const double *__restrict__ abs_part, uint64_t n_abs, Scratch *sc)
+// The step's statistics in one fixed-order reduction (one block of kFinalThreads): the item
+// kernels' partials, the generation blocks' spawn and death counts, and the per-block |N|
+// sums of the compacted store.
+constexpr int kFinalThreads = 256;
+constexpr int kFinalWaves = kFinalThreads / 64;
+
+__global__ void __launch_bounds__(kFinalThreads) k_final(ItemPartials part, uint64_t n_parts, GenStats gs, uint64_t n_gen,
+                                                         const double *__restrict__ abs_part, uint64_t n_abs, Scratch *sc)
 {
+    constexpr int U = 8;  // loads in flight per array and thread
+    constexpr uint64_t T = kFinalThreads;
     double num = 0.0, tot = 0.0;
     uint64_t att = 0, disc = 0, mx = 0, sp = 0, de = 0;
-    for (uint64_t i0 = 0; i0 < n_parts; i0 += 4 * kThreads) {
-        double a[4];
-        uint64_t b[4], c[4], d[4];
+    for (uint64_t i0 = 0; i0 < n_parts; i0 += U * T) {
+        double a[U];
+        uint64_t b[U], c[U], d[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint64_t i = i0 + (uint64_t)u * kThreads + threadIdx.x;
+        for (int u = 0; u < U; ++u) {  // clamped indices: unconditional loads, then select
+            const uint64_t i = i0 + (uint64_t)u * T + threadIdx.x;
             const bool in = i < n_parts;
-            a[u] = in ? part.num[i] : 0.0;
-            b[u] = in ? part.att[i] : 0;
-            c[u] = in ? part.disc[i] : 0;
-            d[u] = in ? part.maxn[i] : 0;
+            const uint64_t ic = in ? i : n_parts - 1;
+            a[u] = part.num[ic];
+            b[u] = part.att[ic];
+            c[u] = part.disc[ic];
+            d[u] = part.maxn[ic];
+            a[u] = in ? a[u] : 0.0;
+            b[u] = in ? b[u] : 0;
+            c[u] = in ? c[u] : 0;
+            d[u] = in ? d[u] : 0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             num += a[u];
             att += b[u];
             disc += c[u];
             mx = d[u] > mx ? d[u] : mx;
         }
     }
-    for (uint64_t i0 = 0; i0 < n_gen; i0 += 4 * kThreads) {
-        uint32_t x[4], y[4];
+    for (uint64_t i0 = 0; i0 < n_gen; i0 += 2 * U * T) {
+        uint32_t x[2 * U], y[2 * U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint64_t i = i0 + (uint64_t)u * kThreads + threadIdx.x;
-            x[u] = i < n_gen ? gs.spawns[i] : 0u;
-            y[u] = i < n_gen ? gs.deaths[i] : 0u;
+        for (int u = 0; u < 2 * U; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * T + threadIdx.x;
+            const uint64_t ic = i < n_gen ? i : n_gen - 1;
+            x[u] = gs.spawns[ic];
+            y[u] = gs.deaths[ic];
+            x[u] = i < n_gen ? x[u] : 0u;
+            y[u] = i < n_gen ? y[u] : 0u;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 2 * U; ++u) {
             sp += x[u];
             de += y[u];
         }
     }
-    for (uint64_t i0 = 0; i0 < n_abs; i0 += 4 * kThreads) {
-        double x[4];
+    for (uint64_t i0 = 0; i0 < n_abs; i0 += 2 * U * T) {
+        double x[2 * U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint64_t i = i0 + (uint64_t)u * kThreads + threadIdx.x;
-            x[u] = i < n_abs ? abs_part[i] : 0.0;
+        for (int u = 0; u < 2 * U; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * T + threadIdx.x;
+            x[u] = abs_part[i < n_abs ? i : n_abs - 1];
+            x[u] = i < n_abs ? x[u] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) tot += x[u];
+        for (int u = 0; u < 2 * U; ++u) tot += x[u];
     }
-    num = block_reduce_sum(num);
-    tot = block_reduce_sum(tot);
-    att = block_reduce_sum(att);
-    disc = block_reduce_sum(disc);
-    sp = block_reduce_sum(sp);
-    de = block_reduce_sum(de);
-    mx = block_reduce_max(mx);
+    num = block_reduce_sum<double, kFinalWaves>(num);
+    tot = block_reduce_sum<double, kFinalWaves>(tot);
+    att = block_reduce_sum<uint64_t, kFinalWaves>(att);
+    disc = block_reduce_sum<uint64_t, kFinalWaves>(disc);
+    sp = block_reduce_sum<uint64_t, kFinalWaves>(sp);
+    de = block_reduce_sum<uint64_t, kFinalWaves>(de);
+    mx = block_reduce_max<uint64_t, kFinalWaves>(mx);
     if (threadIdx.x == 0) {
         sc->num = num;
         sc->n_total = tot;

@@ -1,7 +1,7 @@
 // primitives.h -- device-wide building blocks on gfx950 (64-lane wavefronts):
 //   * exclusive / inclusive prefix scan of u32 / u64 arrays in one launch (LDS-staged tiles,
 //     decoupled look-back between tiles)
-//   * stable LSD radix sort of 64-bit keys with a u32 payload, 8-bit digits: one histogram
+//   * stable LSD radix sort of 64-bit keys with a u32 payload, 9-bit digits: one histogram
 //     launch for all passes, then one single-sweep launch per digit; digit ranks from
 //     wavefront ballots ("match" of equal digits) and LDS counters.
 #pragma once
@@ -16,6 +16,8 @@ constexpr int kScanItems = 8;           // items per thread in scans
 constexpr int kScanTile = kThreads * kScanItems;
 constexpr int kSortItems = 8;           // rounds of 256 keys per radix tile
 constexpr int kSortTile = kThreads * kSortItems;
+constexpr int kRadixBits = 9;           // digit width of the radix sort
+constexpr int kRadixBins = 1 << kRadixBits;
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
@@ -57,17 +59,18 @@ __device__ __forceinline__ V block_exclusive_scan(V v, V *total)
     return before + inc - v;
 }
 
-template <typename V>
+// Sum over a block of NW wavefronts (fixed order: lanes by shuffle tree, then waves 0..NW-1).
+template <typename V, int NW = kWaves>
 __device__ __forceinline__ V block_reduce_sum(V v)
 {
-    __shared__ V wave_tot[kWaves];
+    __shared__ V wave_tot[NW];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     if (lane_id() == 0) wave_tot[wave_id()] = v;
     __syncthreads();
     V all = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) all += wave_tot[w];
+    for (int w = 0; w < NW; ++w) all += wave_tot[w];
     __syncthreads();
     return all;
 }
@@ -75,10 +78,12 @@ __device__ __forceinline__ V block_reduce_sum(V v)
 // -------------------------------------------------------------------------- scan
 // Scans read their input through a source functor: a plain array, or a transform of
 // another array (the selection weights are formed while being scanned).
+// check(v) sees every loaded value once all loads of the tile are in flight.
 template <typename V>
 struct ArraySrc {
     const V *p;
     __device__ __forceinline__ V operator()(uint64_t i) const { return p[i]; }
+    __device__ __forceinline__ void check(V) const {}
 };
 
 // ------------------------------------------------------- single-pass scans and sorts
@@ -123,10 +128,37 @@ __device__ __forceinline__ uint64_t lb_wave_lookback(uint64_t *status, uint64_t 
     return excl;
 }
 
+// Fill dst[b] = v for b in [b0, b1), one range per lane; called by every lane of the wave.
+// Short ranges are written by their own lane, long ones by the whole wavefront in turn, so
+// that one long range does not serialise the wave.
+template <typename D>
+__device__ __forceinline__ void wave_fill_ranges(D *__restrict__ dst, uint64_t b0, uint64_t b1, D v)
+{
+    const bool big = b1 > b0 + 8;
+    if (!big)
+        for (uint64_t b = b0; b < b1; ++b) dst[b] = v;
+    uint64_t m = __ballot(big);
+    while (m) {
+        const int l = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const uint64_t lb0 = __shfl(b0, l, 64), lb1 = __shfl(b1, l, 64);
+        const D lv = __shfl(v, l, 64);
+        for (uint64_t b = lb0 + (uint64_t)lane_id(); b < lb1; b += 64) dst[b] = lv;
+    }
+}
+
+// Scan outputs: the array, plus a per-item hook that sees each item's exclusive prefix and
+// value (called by every lane, in lockstep over the lane's items).
+template <typename V>
+struct ArrayOut {
+    V *p;
+    __device__ __forceinline__ void item(uint64_t, V, V, bool) const {}
+};
+
 // Single-launch scan of n values (n_tiles = ceil(n / kScanTile) blocks); the grand total
 // goes to *total when given.
-template <typename V, typename Src>
-__global__ void __launch_bounds__(kThreads) k_scan_lb(Src in, V *__restrict__ out, uint64_t n, int inclusive,
+template <typename V, typename Src, typename Out>
+__global__ void __launch_bounds__(kThreads) k_scan_lb(Src in, Out out, uint64_t n, int inclusive,
                                                       uint64_t *__restrict__ status, uint64_t *__restrict__ ticket,
                                                       uint64_t *__restrict__ total)
 {
@@ -136,11 +168,19 @@ __global__ void __launch_bounds__(kThreads) k_scan_lb(Src in, V *__restrict__ ou
     __syncthreads();
     const uint64_t t = s_tile;
     const uint64_t base = t * kScanTile;
+    V ld[kScanItems];
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
+        // clamped index: the loads are unconditional and all in flight at once (a guarded
+        // load is compiled into a branch that waits for it)
         const uint64_t g = base + (uint64_t)i * kThreads + threadIdx.x;
-        buf[i * kThreads + threadIdx.x] = (g < n) ? in(g) : V(0);
+        const V v = in(g < n ? g : n - 1);
+        ld[i] = (g < n) ? v : V(0);
     }
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) in.check(ld[i]);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) buf[i * kThreads + threadIdx.x] = ld[i];
     __syncthreads();
     V loc[kScanItems];
     V sum = 0;
@@ -165,6 +205,8 @@ __global__ void __launch_bounds__(kThreads) k_scan_lb(Src in, V *__restrict__ ou
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const V x = loc[i];
+        const uint64_t g = base + (uint64_t)threadIdx.x * kScanItems + i;
+        out.item(g, run, x, g < n);
         buf[threadIdx.x * kScanItems + i] = inclusive ? run + x : run;
         run += x;
     }
@@ -172,7 +214,7 @@ __global__ void __launch_bounds__(kThreads) k_scan_lb(Src in, V *__restrict__ ou
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         const uint64_t g = base + (uint64_t)i * kThreads + threadIdx.x;
-        if (g < n) out[g] = buf[i * kThreads + threadIdx.x];
+        if (g < n) out.p[g] = buf[i * kThreads + threadIdx.x];
     }
 }
 
@@ -185,7 +227,7 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active)
 {
     uint64_t peers = active;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < kRadixBits; ++b) {
         const uint64_t m = __ballot((d >> b) & 1u);
         peers &= ((d >> b) & 1u) ? m : ~m;
     }
@@ -193,24 +235,34 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active)
 }
 
 // ------------------------------------------------------------ onesweep radix passes
+// Keys are 64-bit, sorted by kRadixBits-bit digits from the least significant up.
 // Digit histograms of every pass in one read of the keys (they do not depend on the order),
 // aggregated per wavefront and per block before one global atomic per bin.
+constexpr int kRadixMaxPasses = (64 + kRadixBits - 1) / kRadixBits;
+
 __global__ void __launch_bounds__(kThreads) k_radix_ghist(const uint64_t *__restrict__ key, const uint64_t *__restrict__ n_live,
                                                           int passes, uint32_t *__restrict__ ghist)
 {
     const uint64_t n = *n_live;
-    __shared__ uint32_t h[8][256];
-    for (int p = 0; p < passes; ++p) h[p][threadIdx.x] = 0;
+    __shared__ uint32_t h[kRadixMaxPasses][kRadixBins];
+    for (int p = 0; p < passes; ++p)
+        for (int d = threadIdx.x; d < kRadixBins; d += kThreads) h[p][d] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
     if (base < n) {
+        uint64_t k[kSortItems];
+#pragma unroll
+        for (int r = 0; r < kSortItems; ++r) {
+            const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
+            k[r] = key[g < n ? g : n - 1];  // clamped: unconditional loads
+        }
+#pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
             const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
             const bool valid = g < n;
-            const uint64_t k = valid ? key[g] : 0;
             const uint64_t active = __ballot(valid);
             for (int p = 0; p < passes; ++p) {
-                const uint32_t d = (uint32_t)((k >> (8 * p)) & 0xFFu);
+                const uint32_t d = (uint32_t)((k[r] >> (kRadixBits * p)) & (kRadixBins - 1));
                 if (valid) {
                     const uint64_t peers = match_digit(d, active);
                     if (lanes_below(peers) == 0) atomicAdd(&h[p][d], (uint32_t)__popcll(peers));
@@ -220,26 +272,31 @@ __global__ void __launch_bounds__(kThreads) k_radix_ghist(const uint64_t *__rest
     }
     __syncthreads();
     for (int p = 0; p < passes; ++p)
-        if (h[p][threadIdx.x]) atomicAdd(&ghist[p * 256 + threadIdx.x], h[p][threadIdx.x]);
+        for (int d = threadIdx.x; d < kRadixBins; d += kThreads)
+            if (h[p][d]) atomicAdd(&ghist[p * kRadixBins + d], h[p][d]);
 }
 
-// One stable pass by the digit at `shift`: a tile ranks its keys locally (round by round, as
-// by wavefront digit matching), publishes its per-digit counts, looks back digit by digit over the
-// earlier tiles, and scatters to digit base + earlier tiles + local rank.  status holds
-// 256 words per tile and must be zero before the launch.
+// One stable pass by the digit at `shift`: a tile ranks its keys locally (round by round, by
+// wavefront digit matching), publishes its per-digit counts, looks back over the earlier
+// tiles digit by digit, and scatters to digit base + earlier tiles + local rank.  status
+// holds kRadixBins words per tile and must be zero before the launch.  Each thread owns the
+// digits threadIdx.x + j * kThreads.
+constexpr int kDigitsPerThread = kRadixBins / kThreads;
+
 __global__ void __launch_bounds__(kThreads) k_radix_onesweep(const uint64_t *__restrict__ key_in, const uint32_t *__restrict__ idx_in,
                                                              uint64_t *__restrict__ key_out, uint32_t *__restrict__ idx_out,
                                                              const uint64_t *__restrict__ n_live, int shift,
                                                              const uint32_t *__restrict__ ghist, uint64_t *__restrict__ status,
                                                              uint64_t *__restrict__ ticket)
 {
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wave_cnt[kWaves][256];
-    __shared__ uint32_t dig_base[256];
+    __shared__ uint32_t run[kRadixBins];
+    __shared__ uint32_t wave_cnt[kWaves][kRadixBins];
+    __shared__ uint32_t dig_base[kRadixBins];
     __shared__ uint64_t s_tile;
     const uint64_t n = *n_live;
     if (threadIdx.x == 0) s_tile = atomicAdd((unsigned long long *)ticket, 1ull);
-    run[threadIdx.x] = 0;
+#pragma unroll
+    for (int j = 0; j < kDigitsPerThread; ++j) run[threadIdx.x + j * kThreads] = 0;
     __syncthreads();
     const uint64_t t = s_tile;
     const uint64_t base = t * kSortTile;
@@ -247,15 +304,23 @@ __global__ void __launch_bounds__(kThreads) k_radix_onesweep(const uint64_t *__r
     uint64_t k[kSortItems];
     uint32_t ix[kSortItems];
     uint16_t rk[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {  // all loads in flight before the ranking rounds
+        const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
+        const uint64_t gc = g < n ? g : n - 1;  // clamped: unconditional loads
+        k[r] = key_in[gc];
+        ix[r] = idx_in ? idx_in[gc] : (uint32_t)g;
+    }
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) wave_cnt[w][threadIdx.x] = 0;
+        for (int w = 0; w < kWaves; ++w)
+#pragma unroll
+            for (int j = 0; j < kDigitsPerThread; ++j) wave_cnt[w][threadIdx.x + j * kThreads] = 0;
         __syncthreads();
         const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
         const bool valid = g < n;
-        k[r] = valid ? key_in[g] : 0;
-        ix[r] = valid ? (idx_in ? idx_in[g] : (uint32_t)g) : 0u;
-        const uint32_t d = (uint32_t)((k[r] >> shift) & 0xFFu);
+        const uint32_t d = (uint32_t)((k[r] >> shift) & (kRadixBins - 1));
         const uint64_t active = __ballot(valid);
         int rank = 0;
         if (valid) {
@@ -264,8 +329,9 @@ __global__ void __launch_bounds__(kThreads) k_radix_onesweep(const uint64_t *__r
             if (rank == 0) wave_cnt[wave_id()][d] = (uint32_t)__popcll(peers);
         }
         __syncthreads();
-        {
-            const int dd = threadIdx.x;
+#pragma unroll
+        for (int j = 0; j < kDigitsPerThread; ++j) {
+            const int dd = threadIdx.x + j * kThreads;
             uint32_t acc = run[dd];
 #pragma unroll
             for (int w = 0; w < kWaves; ++w) {
@@ -279,32 +345,61 @@ __global__ void __launch_bounds__(kThreads) k_radix_onesweep(const uint64_t *__r
         rk[r] = (uint16_t)(valid ? wave_cnt[wave_id()][d] + (uint32_t)rank : 0u);
         __syncthreads();
     }
-    // global base of each digit: exclusive prefix of the pass histogram over digits
-    uint32_t all_digits;
-    const uint32_t gbase = block_exclusive_scan(ghist[threadIdx.x], &all_digits);
-    // digit d: publish this tile's count, then sum the earlier tiles' counts
+    // global base of each digit: exclusive prefix of the pass histogram over the digits
+    // (thread x holds digits x and x + kThreads, ...; scanned in digit order)
+    uint32_t gbase[kDigitsPerThread];
     {
-        const int d = threadIdx.x;
-        const uint32_t cnt = run[d];
-        uint64_t *st = status + t * 256;
-        lb_publish(&st[d], t == 0 ? kLbInclusive : kLbAggregate, cnt);
-        uint64_t excl = 0;
-        for (int64_t p = (int64_t)t - 1; p >= 0; --p) {
-            uint64_t w;
-            do {
-                w = __hip_atomic_load(&status[p * 256 + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } while ((w & ~kLbValue) == 0);
-            excl += w & kLbValue;
-            if ((w & ~kLbValue) == kLbInclusive) break;
+        uint32_t carry = 0;
+#pragma unroll
+        for (int j = 0; j < kDigitsPerThread; ++j) {
+            uint32_t tot;
+            gbase[j] = carry + block_exclusive_scan(ghist[threadIdx.x + j * kThreads], &tot);
+            carry += tot;
         }
-        if (t > 0) lb_publish(&st[d], kLbInclusive, excl + cnt);
-        dig_base[d] = gbase + (uint32_t)excl;
+    }
+    // publish this tile's counts, then sum the earlier tiles' counts (both digit chains of a
+    // thread advance together)
+    uint64_t *st = status + t * kRadixBins;
+    uint32_t cnt[kDigitsPerThread];
+    uint64_t excl[kDigitsPerThread];
+    int64_t pp[kDigitsPerThread];
+#pragma unroll
+    for (int j = 0; j < kDigitsPerThread; ++j) {
+        cnt[j] = run[threadIdx.x + j * kThreads];
+        lb_publish(&st[threadIdx.x + j * kThreads], t == 0 ? kLbInclusive : kLbAggregate, cnt[j]);
+        excl[j] = 0;
+        pp[j] = (int64_t)t - 1;
+    }
+    for (;;) {
+        bool busy = false;
+#pragma unroll
+        for (int j = 0; j < kDigitsPerThread; ++j) {
+            if (pp[j] < 0) continue;
+            const uint64_t w = __hip_atomic_load(&status[(uint64_t)pp[j] * kRadixBins + threadIdx.x + j * kThreads],
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t flag = w & ~kLbValue;
+            if (flag == 0) {
+                busy = true;  // not published yet: poll again
+                continue;
+            }
+            excl[j] += w & kLbValue;
+            pp[j] = flag == kLbInclusive ? -1 : pp[j] - 1;
+            busy |= pp[j] >= 0;
+        }
+        if (!busy) break;
+    }
+#pragma unroll
+    for (int j = 0; j < kDigitsPerThread; ++j) {
+        const int d = threadIdx.x + j * kThreads;
+        if (t > 0) lb_publish(&st[d], kLbInclusive, excl[j] + cnt[j]);
+        dig_base[d] = gbase[j] + (uint32_t)excl[j];
     }
     __syncthreads();
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
         if (g < n) {
-            const uint32_t d = (uint32_t)((k[r] >> shift) & 0xFFu);
+            const uint32_t d = (uint32_t)((k[r] >> shift) & (kRadixBins - 1));
             const uint32_t dst = dig_base[d] + rk[r];
             key_out[dst] = k[r];
             idx_out[dst] = ix[r];

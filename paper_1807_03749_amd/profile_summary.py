@@ -1,0 +1,127 @@
+"""Turn rocprofv3 CSV output into the short text summaries kept with the project.
+
+  python -m paper_1807_03749_amd.profile_summary stats <run>_kernel_stats.csv --command "..." --out FILE
+      per-kernel dispatch statistics (calls, total / average / min / max duration, share)
+
+  python -m paper_1807_03749_amd.profile_summary traffic --kernel k_generate --name generate
+      --workload W --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv
+      --copy-bytes N --command "..." --out FILE
+      HBM bytes per dispatch of one kernel: FETCH_SIZE and WRITE_SIZE (KiB per dispatch,
+      averaged over its dispatches), each scaled by expected / measured of the same counter
+      on device copies of N bytes (a read of N and a write of N bytes per copy).
+
+The summaries record the hash of the HIP sources they were taken on; bench.py uses a
+traffic figure only while that hash still matches.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import datetime
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _rows(path):
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name: str) -> str:
+    n = name.replace("void ", "").replace("ccmc::", "")
+    depth, out = 0, []
+    for ch in n:  # drop the parameter list, keep template arguments
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def _source_hash() -> str:
+    sys.path.insert(0, ROOT)
+    import bench  # noqa: E402  (the hash function lives with its only reader)
+    return bench.source_hash()
+
+
+def stats(args):
+    rows = _rows(args.csv)
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# rocprofv3 kernel statistics  ({datetime.date.today().isoformat()})",
+             f"# command: {args.command}",
+             f"# source_hash = {_source_hash()}",
+             f"# {'kernel':58s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} {'share':>6s}"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        t = float(r["TotalDurationNs"])
+        lines.append(f"  {_short(r['Name'])[:58]:58s} {int(r['Calls']):7d} {t / 1e6:10.3f} "
+                     f"{float(r['AverageNs']) / 1e3:9.2f} {float(r['MinNs']) / 1e3:9.2f} "
+                     f"{float(r['MaxNs']) / 1e3:9.2f} {100 * t / tot:5.1f}%")
+    _write(args.out, lines)
+
+
+def _per_dispatch(path, counter, match):
+    vals = {}
+    for r in _rows(path):
+        if r["Counter_Name"] != counter or not match(r["Kernel_Name"]):
+            continue
+        vals[r["Dispatch_Id"]] = vals.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    return list(vals.values())
+
+
+def traffic(args):
+    kern = lambda n: args.kernel in n
+    copy = lambda n: "copy" in n.lower()
+    f = _per_dispatch(args.fetch, "FETCH_SIZE", kern)
+    w = _per_dispatch(args.write, "WRITE_SIZE", kern)
+    cf = _per_dispatch(args.copy_fetch, "FETCH_SIZE", copy)
+    cw = _per_dispatch(args.copy_write, "WRITE_SIZE", copy)
+    if not (f and w and cf and cw):
+        raise SystemExit("traffic: a counter file holds no matching dispatch")
+    exp_kib = args.copy_bytes * args.copy_reps / 1024.0
+    sf, sw = exp_kib / sum(cf), exp_kib / sum(cw)
+    fk, wk = sum(f) / len(f), sum(w) / len(w)
+    hbm = (fk * sf + wk * sw) * 1024.0
+    lines = [f"# HBM traffic of {args.kernel} ({args.name}) on {args.workload}  ({datetime.date.today().isoformat()})",
+             f"# command: {args.command}",
+             f"source_hash = {_source_hash()}",
+             f"dispatches_fetch = {len(f)}",
+             f"dispatches_write = {len(w)}",
+             f"fetch_kib_per_dispatch = {fk:.1f}",
+             f"write_kib_per_dispatch = {wk:.1f}",
+             f"copy_bytes = {args.copy_bytes} x {args.copy_reps} copies",
+             f"copy_fetch_kib_measured = {sum(cf):.1f}  (expected {exp_kib:.1f}, scale {sf:.4f})",
+             f"copy_write_kib_measured = {sum(cw):.1f}  (expected {exp_kib:.1f}, scale {sw:.4f})",
+             f"hbm_bytes_per_launch = {hbm:.0f}"]
+    _write(args.out, lines)
+
+
+def _write(out, lines):
+    text = "\n".join(lines) + "\n"
+    if out:
+        with open(out, "w") as f:
+            f.write(text)
+    print(text, end="")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--command", required=True)
+    s.add_argument("--out")
+    t = sub.add_parser("traffic")
+    for a in ("--kernel", "--name", "--workload", "--fetch", "--write", "--copy-fetch", "--copy-write", "--command"):
+        t.add_argument(a, required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--copy-reps", type=int, default=5)
+    t.add_argument("--out")
+    args = ap.parse_args()
+    (stats if args.cmd == "stats" else traffic)(args)
+
+
+if __name__ == "__main__":
+    main()

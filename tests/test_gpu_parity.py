@@ -191,3 +191,19 @@ def test_full_size_step_ueg14_114_ccsdt():
     _say(f"[parity] full size: {len(keys)} excitors, N_tot {np.abs(amps).sum() + n0:.3e}")
     gs, os_ = compare_step(S, R, g, 0.002, 0.0, int(round(np.abs(amps).sum() + n0)))
     _say(f"[parity] full size ok: {gs['n_spawn_attempts']} attempts, {gs['n_spawns']} spawns")
+
+
+def test_large_amplitudes_select_identically():
+    """Excitors with |N_i| far above 2^16 (fixed-point weights up to 2^46): the prefix of the
+    selection weights and the draws stay identical to the oracle's."""
+    # multi-spawn off for the sampled clusters: their |A| is ~1e7 here
+    S, R, g = make_pair("ueg", 14, 2, dict(full_noncomposite=True, min_spawn_attempts=2, multispawn_threshold=0.0,
+                                           noncomposite_threshold=1e3, init_pop=300.0, seed=21), n2_max=2)
+    evolve_oracle(R, 20, 0.005, 300)
+    keys, amps, n0, step = R.export_state()
+    amps = np.array(amps, dtype=np.float64)
+    amps[0] = 3.1e6
+    amps[len(amps) // 2] = -7.7e5
+    R.import_state(keys, amps, n0, step)
+    gs, os_ = compare_step(S, R, g, 0.005, 0.0, 4000)
+    _say(f"[parity] large amplitudes ok ({gs['n_spawn_attempts']} attempts)")
