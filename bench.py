@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import platform
 import sys
@@ -249,6 +250,51 @@ def annihilation_roofline(prof: dict):
                 unit="GB/s", frac=by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS)
 
 
+def precision_study(w: inputs.Workload, steps: int, equil: int, log):
+    """FP64 against FP32 amplitudes at equal E_proj error: each precision grows its own
+    population, equilibrates for `equil` steps under shift control, then records the E_proj
+    terms of `steps` steps.  Reblocked E_proj and its standard error give the FP32 shift in
+    units of the combined error, and -- since the error falls as 1/sqrt(time) -- the time each
+    precision needs to reach the larger of the two errors."""
+    res = {}
+    for prec in ("fp64", "fp32"):
+        state = make_state(w, prec, init_pop=max(100.0, w.target_population / 50))
+        st, ngrow = grow(state, w, log)
+        ctl = driver.ShiftControl(target=w.target_population, tau=w.tau)
+        ctl.update(st["n_total"])
+        nsel = driver.selections(st["n_total"])
+        for _ in range(equil):
+            st = state.ccmc_step(w.tau, ctl.shift, nsel)
+            ctl.update(st["n_total"])
+            nsel = driver.selections(st["n_total"])
+        num = np.empty(steps)
+        den = np.empty(steps)
+        attempts = 0
+        t0 = time.perf_counter()
+        for i in range(steps):
+            st = state.ccmc_step(w.tau, ctl.shift, nsel)
+            ctl.update(st["n_total"])
+            nsel = driver.selections(st["n_total"])
+            num[i] = st["eproj_num"]
+            den[i] = st["eproj_den"]
+            attempts += st["n_spawn_attempts"]
+        el = time.perf_counter() - t0
+        e, err, lv = driver.reblock_ratio(num, den)
+        res[prec] = dict(e_proj=e, error=err, block_level=lv, steps=steps, seconds=el,
+                         attempts_per_s=attempts / el, ms_per_step=1e3 * el / steps, shift=ctl.shift,
+                         n_total=st["n_total"], excitors=st["n_excitors"])
+        log(f"precision {prec}: E_proj {e:.6f} +- {err:.6f} ({steps} steps, {1e3 * el / steps:.3f} ms/step)")
+        state.close()
+    a, b = res["fp64"], res["fp32"]
+    comb = math.sqrt(a["error"] ** 2 + b["error"] ** 2)
+    target = max(a["error"], b["error"])
+    t = {p: res[p]["seconds"] * (res[p]["error"] / target) ** 2 for p in res}
+    return dict(workload=w.name, equilibration_steps=equil, fp64=a, fp32=b,
+                fp32_shift_in_sigma=(b["e_proj"] - a["e_proj"]) / comb if comb > 0 else None,
+                equal_error=target, seconds_to_equal_error=t,
+                fp32_speedup_at_equal_error=t["fp64"] / t["fp32"] if t["fp32"] > 0 else None)
+
+
 def cpu_baseline(w: inputs.Workload, seconds: float, log):
     """The CPU oracle, timed on this host on a bounded sample of the same workload: the
     whole truncated space occupied with seeded amplitudes (N_tot = target), stepped until
@@ -327,6 +373,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true", help="only run a 1 GiB device copy (counter scaling)")
     ap.add_argument("--save-state", help="write the equilibrated store (after warm-up) to this .npz")
     ap.add_argument("--load-state", help="start from a store written by --save-state instead of growing one")
+    ap.add_argument("--study-steps", type=int, default=50000,
+                    help="steps per precision of the FP64 / FP32 equal-error study (0: skip)")
+    ap.add_argument("--study-equil", type=int, default=4000, help="equilibration steps before the study")
     args = ap.parse_args()
     global ROCTX
     ROCTX = _Roctx(args.roctx_region)
@@ -384,6 +433,9 @@ def main():
         f32 = run_leg(w, "fp32", args.steps, args.warmup, log, profile=False)
         out["fp32"] = dict(value=f32["attempts"] / f32["seconds"], ms_per_step=1e3 * f32["seconds"] / args.steps,
                            excitors=f32["excitors"], n_total=f32["n_total"])
+    if args.study_steps > 0 and args.precision == "fp64" and not args.no_fp32:
+        log("precision study")
+        out["precision_study"] = precision_study(w, args.study_steps, args.study_equil, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, log)
     print(json.dumps(out))

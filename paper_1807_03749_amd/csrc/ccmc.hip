@@ -91,7 +91,10 @@ struct ccmc_state {
     uint64_t step = 0;
     double last_num = 0, last_den = 0;
     // per-step buffers
-    DevBuf P, guide, delta;
+    DevBuf P, guide, delta, rtab;
+    uint64_t rt_n = 0;   // rank-table buckets
+    uint32_t rsh = 0;    // rank-table shift
+    uint64_t last_q = 0; // Q of the last step (sizes the next selection guide)
     DevBuf ikey, iA, ideath, in, ilevel, icnt, ioff;
     uint64_t icap = 0;
     DevBuf num_part, att_part, disc_part, max_part, abs_part;
@@ -462,6 +465,10 @@ ccmc_status upload_system(ccmc_state *st, const ccmc_integrals *ints)
 }
 
 // ------------------------------------------------------------------------ the store
+// Entries of the selection guide for a store capacity: several times the buckets the shift
+// aims at, so that Q may grow between steps before draws fall past the table.
+uint64_t guide_cap(uint64_t scap) { return 2 * scap + 8; }
+
 // Grow the store (both buffers) to hold n entries, keeping the current contents.
 template <int W, typename T>
 ccmc_status ensure_store(ccmc_state *st, uint64_t n)
@@ -497,13 +504,23 @@ ccmc_status ensure_store(ccmc_state *st, uint64_t n)
     TRY(ensure(st, st->sK[1 - c], nc * sizeof(T)));
     TRY(ensure(st, st->srank[1 - c], nc * sizeof(uint64_t)));
     TRY(ensure(st, st->P, nc * sizeof(uint64_t)));
-    TRY(ensure(st, st->guide, (2 * nc + 4) * sizeof(uint32_t)));
+    TRY(ensure(st, st->guide, guide_cap(nc) * sizeof(uint32_t)));
     TRY(ensure(st, st->delta, nc * sizeof(double)));
+    // rank table: about one bucket per store entry, at most one per rank
+    int rt_bits = 1;
+    while (rt_bits < 40 && (1ull << rt_bits) < nc) ++rt_bits;
+    rt_bits = std::min(rt_bits, std::max(st->rank_bits, 1));
+    st->rt_n = 1ull << rt_bits;
+    st->rsh = (uint32_t)std::max(0, st->rank_bits - rt_bits);
+    TRY(ensure(st, st->rtab, (st->rt_n + 1) * sizeof(uint32_t)));
     st->scap = nc;
     return CCMC_OK;
 }
 
 // ---------------------------------------------------------------------- the step
+constexpr uint64_t kMaxFinalParts = 512;
+  // blocks of the first stage of the final reduction
+
 // One attempt at a step.  Sizes produced on the device (record slots, records, new
 // determinants, survivors) are never read back in the middle: kernels read them from device
 // memory, and grids cover capacities planned from the previous step.  If a count exceeds
@@ -536,6 +553,15 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     a.key1 = (uint32_t)(st->opt.seed >> 32);
     a.n_sel = n_sel;
     a.fnc = fnc ? 1 : 0;
+    {
+        // guide shift from the last step's Q (any shift gives the same draws; this one keeps
+        // about one bucket per two excitors, so that large amplitudes own few buckets)
+        const uint64_t q_est = st->last_q ? st->last_q : (ne << 24);
+        uint32_t sh = 0;
+        while (sh < 63 && (q_est >> sh) + 2 > ne / 2 + 2) ++sh;
+        a.gsh = sh;
+        a.gcap = guide_cap(st->scap);
+    }
 
     // ---- capacities for this step (all allocation happens here, before any launch)
     const uint64_t slot_cap = std::max<uint64_t>(kGenSlots, (st->slot_hint + kGenSlots - 1) / kGenSlots * kGenSlots);
@@ -604,7 +630,10 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     const uint64_t o_keep = o_new + scan_tiles(rec_cap);
     const uint64_t o_ghist = o_keep + scan_tiles(mcap);
     const uint64_t o_rstat = o_ghist + (uint64_t)passes * kRadixBins / 2;
-    const uint64_t lb_words = o_rstat + (uint64_t)passes * tiles * kRadixBins;
+    const uint64_t o_fold = o_rstat + (uint64_t)passes * tiles * kRadixBins;
+    const uint64_t fold_tiles = (rec_cap + kFoldTile - 1) / kFoldTile;
+    const uint64_t o_fin = o_fold + 3 * fold_tiles;
+    const uint64_t lb_words = o_fin + kMaxFinalParts * (sizeof(FinalPart) / 8);
     TRY(ensure(st, st->lb, lb_words * sizeof(uint64_t)));
     uint64_t *lb = ptr<uint64_t>(st->lb);
     uint64_t *tick = lb + o_tick;
@@ -619,14 +648,13 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     const T *sK = ptr<T>(st->sK[c]);
     const uint64_t *srank = ptr<uint64_t>(st->srank[c]);
 
-    // ---- (a1) selection weights, formed inside the scan of their prefix; guide table
+    // ---- (a1) selection weights, formed inside the scan of their prefix, with the
+    // excitor-draw guide and the store's rank table
     if (ne) {
-        launch(st, "weights_scan", Work{tb + 8.0, nullptr, ne}, [&] {
-            scan_lb<uint64_t>(st, WeightSrc<T>{samp, sc}, ArrayOut<uint64_t>{ptr<uint64_t>(st->P)}, ne, true, lb + o_weights,
-                              tick + kTkWeights, nullptr);
-        });
-        launch(st, "guide", Work{16.0, nullptr, ne}, [&] {
-            k_guide<<<grid_for(ne + 1), kThreads, 0, s>>>(ptr<uint64_t>(st->P), ne, sc, ptr<uint32_t>(st->guide));
+        const WeightOut wo{ptr<uint64_t>(st->P), ptr<uint32_t>(st->guide), a.gcap, a.gsh, ne};
+        // bytes: amplitude read, prefix written, about two guide entries
+        launch(st, "weights_scan", Work{tb + 16.0, nullptr, ne}, [&] {
+            scan_lb<uint64_t>(st, WeightSrc<T>{samp, sc}, wo, ne, true, lb + o_weights, tick + kTkWeights, &sc->qtot);
         });
     }
 
@@ -636,12 +664,16 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     ItemPartials part{ptr<double>(st->num_part), ptr<uint64_t>(st->att_part), ptr<uint64_t>(st->disc_part),
                       ptr<uint64_t>(st->max_part)};
     const double item_bytes = kb + 2 * tb + 13.0;  // key, A, death, n, level, slot count
-    if (n_items) {
+    // the store's rank table for the lookups of the annihilation (built only with a store)
+    const RankTable rt{srank, ne, ptr<uint32_t>(st->rtab), st->rt_n, st->rsh};
+    const unsigned nb_rt = ne ? grid_for(st->rt_n) : 0;
+    if (n_items || nb_rt) {
         // bytes: each item written (plus, for the non-composite ones, the store entry read)
         launch(st, "items", Work{item_bytes, nullptr, n_items}, [&] {
-            k_items<W, T><<<nb_fnc + nb_sel, kThreads, 0, s>>>(st->sd, skey, samp, sK, scap, ne, ptr<uint64_t>(st->P),
-                                                               ptr<uint32_t>(st->guide), st->n0, a, it, nb_fnc, n_fnc,
-                                                               part, sc);
+            k_items<W, T><<<nb_fnc + nb_sel + nb_rt, kThreads, 0, s>>>(st->sd, skey, samp, sK, scap, ne,
+                                                                       ptr<uint64_t>(st->P), ptr<uint32_t>(st->guide),
+                                                                       st->n0, a, it, nb_fnc, n_fnc, nb_fnc + nb_sel, rt,
+                                                                       part, sc);
         });
     }
     if (!n_sel) k_fill<uint64_t><<<1, 1, 0, s>>>(it.cnt + n_items, 1, 0ull);
@@ -701,10 +733,17 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
 
     // ---- (a12) runs of equal determinants: left fold in record order, store lookup by rank
     double *delta = ptr<double>(st->delta);
+    FoldTiles ft{reinterpret_cast<double *>(lb + o_fold), reinterpret_cast<uint32_t *>(lb + o_fold + fold_tiles),
+                 lb + o_fold + 2 * fold_tiles};
     launch(st, "seg_fold", Work{8.0 + 4.0 + tb + 4.0, &st->cnt_rec, 0}, [&] {
-        k_seg_fold<T><<<grid_for(rec_cap), kThreads, 0, s>>>(sorted_rank, sorted_idx, ptr<T>(st->damp), rec_cap, srank, ne,
-                                                             delta, ptr<uint32_t>(st->is_new), ptr<uint64_t>(st->ins),
-                                                             ptr<double>(st->seg_sum), sc);
+        k_seg_fold<T><<<(unsigned)fold_tiles, kThreads, 0, s>>>(sorted_rank, sorted_idx, ptr<T>(st->damp), rec_cap, srank, ne,
+                                                               delta, ptr<uint32_t>(st->is_new), ptr<uint64_t>(st->ins),
+                                                               ptr<double>(st->seg_sum), ptr<uint32_t>(st->rtab), st->rt_n,
+                                                               st->rsh, ft, sc);
+    });
+    launch(st, "seg_close", Work{24.0, nullptr, fold_tiles}, [&] {
+        k_seg_close<<<grid_for(fold_tiles), kThreads, 0, s>>>(sorted_rank, fold_tiles, srank, ne, delta,
+                                                             ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum), ft, sc);
     });
     launch(st, "new_scan", Work{8.0, &st->cnt_rec, 0}, [&] {
         scan_lb<uint32_t>(st, ArraySrc<uint32_t>{ptr<uint32_t>(st->is_new)}, ArrayOut<uint32_t>{ptr<uint32_t>(st->new_pos)},
@@ -744,14 +783,21 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     });
 
     // ---- (a14) the step's statistics in one fixed-order reduction
+    const uint64_t n_parts = nb_fnc + nb_sel;
+    const uint64_t fin_blocks = std::min<uint64_t>(
+        kMaxFinalParts, std::max<uint64_t>(1, (std::max({n_parts, nblk_cap, (uint64_t)nb_abs}) + 1023) / 1024));
+    FinalPart *fin = reinterpret_cast<FinalPart *>(lb + o_fin);
     launch(st, "final", Work{0.0, nullptr, 0}, [&] {
-        k_final<<<1, kFinalThreads, 0, s>>>(part, nb_fnc + nb_sel, gst, nblk_cap, ptr<double>(st->abs_part), nb_abs, sc);
+        k_final_part<<<(unsigned)fin_blocks, kThreads, 0, s>>>(part, n_parts, gst, nblk_cap, ptr<double>(st->abs_part), nb_abs,
+                                                               fin);
+        k_final<<<1, kThreads, 0, s>>>(fin, fin_blocks, sc);
     });
 
     // ---- (a14) the one synchronisation of the step
     HIP_TRY(hipMemcpyAsync(st->hscratch, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const Scratch scr = *st->hscratch;
+    st->last_q = scr.qtot;
     st->cnt_slots = scr.n_slots;
     st->cnt_rec = scr.n_live;
     st->cnt_merged = ne + scr.n_new;
@@ -879,6 +925,7 @@ ccmc_status import_impl(ccmc_state *st, const uint64_t *keys, const double *amps
     st->ne = n;
     st->n0 = n_ref;
     st->step = step;
+    st->last_q = 0;
     st->last_rec_buf = -1;
     st->last_nrec = 0;
     return CCMC_OK;
@@ -985,7 +1032,7 @@ void destroy(ccmc_state *st)
     if (st->stream) (void)hipStreamSynchronize(st->stream);
     DevBuf *bufs[] = {&st->t_grid, &st->t_nvec, &st->t_vq, &st->t_h, &st->t_eri, &st->t_fock, &st->t_vpair,
                       &st->t_binv, &st->t_bino, &st->skey[0], &st->skey[1], &st->samp[0], &st->samp[1], &st->sK[0],
-                      &st->sK[1], &st->srank[0], &st->srank[1], &st->P, &st->guide, &st->delta, &st->ikey,
+                      &st->sK[1], &st->srank[0], &st->srank[1], &st->P, &st->guide, &st->delta, &st->rtab, &st->ikey,
                       &st->iA, &st->ideath, &st->in, &st->ilevel, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,
                       &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->boff, &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
                       &st->sidx[0], &st->sidx[1], &st->is_new,

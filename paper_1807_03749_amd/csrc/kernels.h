@@ -2,8 +2,8 @@
 //
 // One step, in launch order (scans are single launches with decoupled look-back):
 //   k_fill           clear the step scalars and look-back status words
-//   weights scan     fixed-point selection weights q_i and their prefix          (a1)
-//   k_guide          bucket table of the prefix for the excitor draws           (a2)
+//   weights scan     fixed-point selection weights q_i and their prefix, with    (a1)
+//                    the excitor-draw guide
 //   k_items          non-composite items (FNC): reference + every excitor        (a4, a5, a9, a10)
 //                    and sampled clusters: size, excitor draws, collapse, amplitude  (a2, a3, a4, a9, a10)
 //   slot scan        record slots per item (1 death + n attempts), first item per block
@@ -39,8 +39,8 @@ struct Scratch {
     uint64_t n_slots;         // record slots of the step (deaths + attempts)
     uint64_t n_rec;           // records emitted by the step
     uint64_t n_live;          // records the annihilation works on (0 after an overflow)
-    uint64_t guide_n;         // entries of the selection guide table
-    uint64_t guide_shift;
+    uint64_t spare0;
+    uint64_t spare1;
     uint64_t n_new;           // new determinants
     uint64_t hf_hit;
     uint64_t n_out;           // excitors after the step
@@ -58,6 +58,8 @@ struct StepArgs {
     uint32_t key0, key1;
     uint64_t n_sel;
     int fnc;
+    uint32_t gsh;             // shift of the selection guide
+    uint64_t gcap;            // entries of the selection guide
 };
 
 // Per-block partial statistics of the item kernels, reduced by k_final.
@@ -135,45 +137,58 @@ struct WeightSrc {
     }
 };
 
-// Q and the guide table of the excitor draws.  A draw r in [0, Q) falls in bucket r >> shift;
-// guide[b] is the first excitor whose prefix exceeds b << shift, so the drawn excitor lies
-// in [guide[b], guide[b+1]] -- a short search instead of one over the whole store.  With
-// about two buckets per excitor the range is usually a single entry.
-__device__ __forceinline__ uint32_t guide_shift(uint64_t Q, uint64_t n)
-{
-    uint32_t sh = 0;
-    while (sh < 63 && (Q >> sh) + 2 > 2 * n + 2) ++sh;
-    return sh;
-}
+// The guide of the excitor draws, built while the weights are scanned (one lane per excitor
+// g, exclusive prefix lo, inclusive prefix hi = P[g]): a draw x in [0, Q) falls in bucket
+// x >> gsh, and guide[b] is the first excitor whose prefix exceeds b << gsh, so the drawn
+// excitor lies in [guide[b], guide[b+1]] -- a short search instead of one over the whole
+// store.  Excitor g owns the buckets with lo <= b << gsh < hi; the last one also owns the two
+// closing buckets.  The shift comes from the host (from the previous step's Q), so buckets
+// past the capacity gcap may exist: draws there search from guide[gcap - 1] to the end.
+struct WeightOut {
+    uint64_t *p;
+    uint32_t *guide;
+    uint64_t gcap;
+    uint32_t gsh;
+    uint64_t n;
+    __device__ __forceinline__ void item(uint64_t g, uint64_t lo, uint64_t x, bool valid) const
+    {
+        uint64_t b0 = 0, b1 = 0;
+        if (valid) {
+            const uint64_t unit = 1ull << gsh, hi = lo + x;
+            b0 = (lo + unit - 1) >> gsh;
+            b1 = g + 1 == n ? (hi >> gsh) + 2 : (hi + unit - 1) >> gsh;
+            b1 = b1 < gcap ? b1 : gcap;
+            b0 = b0 < b1 ? b0 : b1;
+        }
+        wave_fill_ranges<uint32_t>(guide, b0, b1, (uint32_t)g);
+    }
+};
 
-// Built by scattering: bucket b holds the first i with P[i] > b << shift, so excitor i owns
-// the buckets b with P[i-1] <= b << shift < P[i] (usually none, one or two; a large
-// amplitude owns many, written by its whole wavefront); lane n writes the closing entries.
-__global__ void __launch_bounds__(kThreads) k_guide(const uint64_t *__restrict__ P, uint64_t n, Scratch *sc,
-                                                    uint32_t *__restrict__ guide)
+// The rank table of the store lookups: rtab[c] is the first store entry whose rank is at
+// least c << rsh, so a rank r lies in [rtab[r >> rsh], rtab[(r >> rsh) + 1]].  One lane per
+// bucket (binary search); these lanes ride along in the items launch, which waits on memory.
+struct RankTable {
+    const uint64_t *srank;
+    uint64_t ne;
+    uint32_t *rtab;
+    uint64_t rt_n;
+    uint32_t rsh;
+};
+
+__device__ __forceinline__ void rank_table_block(unsigned blk, const RankTable &rt)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    const uint64_t Q = n ? P[n - 1] : 0;
-    const uint32_t sh = guide_shift(Q, n);
-    const uint64_t nb = n ? (Q >> sh) + 2 : 0;
-    if (i == 0) {
-        sc->qtot = Q;
-        sc->guide_shift = sh;
-        sc->guide_n = nb;
-        if (Q > (1ull << 53)) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrBlowup);
+    const uint64_t c = (uint64_t)blk * kThreads + threadIdx.x;
+    if (c >= rt.rt_n) return;
+    const uint64_t key = c << rt.rsh;
+    uint64_t l0 = 0, h0 = rt.ne;
+    while (l0 < h0) {
+        const uint64_t mid = (l0 + h0) >> 1;
+        if (rt.srank[mid] < key)
+            l0 = mid + 1;
+        else
+            h0 = mid;
     }
-    const uint64_t unit = 1ull << sh;
-    uint64_t b0 = 0, b1 = 0;
-    if (n && i < n) {
-        const uint64_t lo = i ? P[i - 1] : 0, hi = P[i];
-        b0 = (lo + unit - 1) >> sh;
-        b1 = (hi + unit - 1) >> sh;  // buckets with b << shift < hi
-        b1 = b1 < nb ? b1 : nb;
-    } else if (n && i == n) {  // buckets at or beyond Q
-        b0 = (Q + unit - 1) >> sh;
-        b1 = nb;
-    }
-    wave_fill_ranges<uint32_t>(guide, b0, b1, (uint32_t)(i < n ? i : n - 1));
+    rt.rtab[c] = (uint32_t)l0;
 }
 
 // ------------------------------------------------------- non-composite items (FNC)
@@ -246,7 +261,7 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
     uint64_t att = 0, disc = 0, mx = 0;
     if (k < a.n_sel) {
         const uint64_t Q = sc->qtot;
-        const uint32_t gsh = (uint32_t)sc->guide_shift;
+        const uint32_t gsh = a.gsh;
         Draws r(a.key0, a.key1, kSelect, (uint32_t)k, 0u, a.step);
         const int lo = a.fnc ? 2 : 0, hi = S.l + 2;
         const int s = draw_size(uniform53(r.get(0)), lo, hi);
@@ -265,8 +280,13 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
         for (int c = 0; c < kMaxClusterSize; ++c) {
             if (c < s && ok) {
                 const uint64_t gb = xs[c] >> gsh;
-                l0[c] = guide[gb];
-                h0[c] = guide[gb + 1] + 1u;
+                if (gb + 1 < a.gcap) {
+                    l0[c] = guide[gb];
+                    h0[c] = guide[gb + 1] + 1u;
+                } else {  // past the table: search to the end
+                    l0[c] = guide[a.gcap - 1];
+                    h0[c] = (uint32_t)ne;
+                }
             }
         }
         // lock-step binary searches: first i in [l0, h0) with P[i] > x
@@ -385,15 +405,23 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
     if (k == 0) it.cnt[item_base + a.n_sel] = 0;  // closing entry of the slot-count scan
 }
 
-// One launch for both kinds of item: blocks [0, nb_fnc) are the non-composite items, the
-// rest the sampled clusters (their selection k = (block - nb_fnc) * 256 + thread).
+// One launch for both kinds of item: blocks [0, nb_fnc) are the non-composite items, blocks
+// [nb_fnc, nb_items) the sampled clusters (selection k = (block - nb_fnc) * 256 + thread), and
+// the blocks after them build the store's rank table.
 template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_items(SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
                                                     const T *__restrict__ sK, uint64_t sstride, uint64_t ne,
                                                     const uint64_t *__restrict__ P, const uint32_t *__restrict__ guide,
                                                     double n0, StepArgs a, Items<T> it, unsigned nb_fnc, uint64_t n_fnc,
-                                                    ItemPartials part, Scratch *sc)
+                                                    unsigned nb_items, RankTable rt, ItemPartials part, Scratch *sc)
 {
+    if (blockIdx.x >= nb_items) {  // trailing blocks: the rank table for the annihilation
+        rank_table_block(blockIdx.x - nb_items, rt);
+        return;
+    }
+    // a prefix beyond 2^53 makes the selection probabilities inexact: refuse the step
+    if (blockIdx.x == 0 && threadIdx.x == 0 && sc->qtot > (1ull << 53))
+        atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrBlowup);
     if (blockIdx.x < nb_fnc) {
         noncomposite_block<W, T>(blockIdx.x, S, skey, samp, sK, sstride, ne, n0, a, it, part, sc);
     } else {
@@ -670,70 +698,207 @@ __global__ void __launch_bounds__(kThreads) k_gather(const SysDev S, Records reg
 
 // ---------------------------------------------------------------- annihilation
 // Records are sorted by rank (equal ranks = equal determinants, ascending rank = ascending
-// key).  One lane per record: the first record of each determinant folds the run of its
-// records left to right (they are contiguous and in id order after the stable sort), then
-// looks the rank up in the store.  A hit adds to that entry, the reference (rank 0) adds to
-// N_0, a miss becomes a new excitor at insertion point ins.  Lanes up to the capacity write
-// is_new = 0 so that the scan of is_new needs no live count.
+// key) and, within a determinant, by record id (the sort is stable).  The contributions to a
+// determinant are summed in record order in two levels: each thread left-folds the pieces of
+// runs among its kFoldItems consecutive records, and a run's head then adds the pieces of the
+// following threads and tiles in order.  The grouping is fixed by the tiling, so the sums are
+// reproducible and equal the plain left fold up to rounding order.  The head of each run looks
+// its rank up in the store: a hit adds to that entry, the reference (rank 0) adds to N_0, a
+// miss becomes a new excitor at insertion point ins.  A run that continues past its tile is
+// left "open": its head is finished by k_seg_close once every tile's leading piece is known.
+constexpr int kFoldItems = 8;
+constexpr int kFoldTile = kThreads * kFoldItems;
+constexpr uint64_t kNoOpen = ~0ull;
+
+struct FoldTiles {
+    double *lead;       // per tile: left fold of its records before its first run head
+    uint32_t *has_head; // per tile: any run head in the tile
+    uint64_t *open;     // per tile: record index of its open head, or kNoOpen
+};
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_seg_fold(const uint64_t *__restrict__ rank, const uint32_t *__restrict__ idx,
                                                        const T *__restrict__ ramp, uint64_t cap,
                                                        const uint64_t *__restrict__ srank, uint64_t ne,
                                                        double *__restrict__ delta, uint32_t *__restrict__ is_new,
-                                                       uint64_t *__restrict__ ins, double *__restrict__ seg_sum, Scratch *sc)
+                                                       uint64_t *__restrict__ ins, double *__restrict__ seg_sum,
+                                                       const uint32_t *__restrict__ rtab, uint64_t rt_n, uint32_t rsh,
+                                                       FoldTiles ft, Scratch *sc)
 {
-    const uint64_t r = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (r >= cap) return;
+    __shared__ double s_lead[kThreads];
+    __shared__ uint32_t s_head[kThreads];
+    __shared__ uint64_t s_open;
     const uint64_t n = sc->n_live;
-    uint32_t fresh = 0;
-    if (r < n && (r == 0 || rank[r] != rank[r - 1])) {
-        const uint64_t rk = rank[r];
-        double acc = (double)ramp[idx[r]];
-        // the run is walked eight records per round: its ranks, indices and amplitudes are
-        // loaded together, then added in record order
-        bool more = true;
-        for (uint64_t t0 = r + 1; more && t0 < n; t0 += 8) {
-            uint64_t rr[8];
-            uint32_t ii[8];
+    const uint64_t base = (uint64_t)blockIdx.x * kFoldTile;
+    const uint64_t r0 = base + (uint64_t)threadIdx.x * kFoldItems;
+    // is_new covers the whole capacity, so that its scan needs no live count
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {  // clamped indices: unconditional loads
-                const uint64_t tc = t0 + u < n ? t0 + u : n - 1;
-                rr[u] = rank[tc];
-                ii[u] = idx[tc];
-                rr[u] = t0 + u < n ? rr[u] : ~0ull;
-            }
-            T vv[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) vv[u] = ramp[ii[u]];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                more = more && rr[u] == rk;
-                if (more) acc += (double)vv[u];
-            }
+    for (int i = 0; i < kFoldItems; ++i)
+        if (r0 + i < cap) is_new[r0 + i] = 0;
+    if (base >= n) {
+        if (threadIdx.x == 0) {
+            ft.lead[blockIdx.x] = 0.0;
+            ft.has_head[blockIdx.x] = 0;
+            ft.open[blockIdx.x] = kNoOpen;
         }
-        uint64_t pos = 0;
-        if (rk == 0) {
-            sc->hf_sum = acc;
-            sc->hf_hit = 1;
-        } else {
-            uint64_t l0 = 0, h0 = ne;  // first store entry with rank >= rk
-            while (l0 < h0) {
-                const uint64_t mid = (l0 + h0) >> 1;
-                if (srank[mid] < rk)
-                    l0 = mid + 1;
-                else
-                    h0 = mid;
-            }
-            if (l0 < ne && srank[l0] == rk)
-                delta[l0] = acc;
-            else
-                fresh = 1;
-            pos = l0;
-        }
-        ins[r] = pos;
-        seg_sum[r] = acc;
+        return;
     }
-    is_new[r] = fresh;
+    if (threadIdx.x == 0) s_open = kNoOpen;
+    // this thread's records, the one before and the one after (clamped: unconditional loads)
+    uint64_t rr[kFoldItems + 1];
+    uint32_t ii[kFoldItems];
+#pragma unroll
+    for (int i = 0; i <= kFoldItems; ++i) {
+        const uint64_t r = r0 + i;
+        rr[i] = rank[r < n ? r : n - 1];
+        rr[i] = r < n ? rr[i] : ~0ull;
+    }
+    const uint64_t rprev = r0 ? rank[r0 - 1 < n ? r0 - 1 : n - 1] : ~0ull;
+#pragma unroll
+    for (int i = 0; i < kFoldItems; ++i) ii[i] = idx[r0 + i < n ? r0 + i : n - 1];
+    double v[kFoldItems];
+#pragma unroll
+    for (int i = 0; i < kFoldItems; ++i) v[i] = (double)ramp[ii[i]];
+    bool head[kFoldItems];
+    uint32_t any = 0;
+#pragma unroll
+    for (int i = 0; i < kFoldItems; ++i) {
+        const bool valid = r0 + i < n;
+        head[i] = valid && (r0 + i == 0 || rr[i] != (i ? rr[i - 1] : (r0 + i - 1 < n ? rprev : ~0ull)));
+        any |= head[i] ? 1u : 0u;
+    }
+    // leading piece: this thread's records before its first head (all of them if none)
+    double lead = 0.0;
+    {
+        bool in_lead = true;
+#pragma unroll
+        for (int i = 0; i < kFoldItems; ++i) {
+            in_lead = in_lead && !head[i] && (r0 + i < n);
+            if (in_lead) lead += v[i];
+        }
+    }
+    s_lead[threadIdx.x] = lead;
+    s_head[threadIdx.x] = any;
+    __syncthreads();
+    // runs that start here: fold the rest of this thread's piece, then the following pieces
+    double acc[kFoldItems];
+    bool open[kFoldItems];
+#pragma unroll
+    for (int i = 0; i < kFoldItems; ++i) {
+        acc[i] = 0.0;
+        open[i] = false;
+        if (!head[i]) continue;
+        const uint64_t rk = rr[i];
+        double sum = v[i];
+        int m = i + 1;
+        bool more = true;
+#pragma unroll
+        for (int q = 1; q < kFoldItems; ++q) {
+            if (q <= i) continue;
+            more = more && rr[q] == rk;
+            if (more) {
+                sum += v[q];
+                m = q + 1;
+            }
+        }
+        if (m == kFoldItems && rr[kFoldItems] == rk) {  // the run continues into the next thread
+            int k = threadIdx.x + 1;
+            for (; k < kThreads; ++k) {
+                sum += s_lead[k];
+                if (s_head[k]) break;
+            }
+            // past the tile end: continues if the next tile starts with the same rank
+            open[i] = k == kThreads && base + kFoldTile < n && rank[base + kFoldTile] == rk;
+        }
+        acc[i] = sum;
+    }
+    // store lookups of all heads of this thread in lock step: first entry with rank >= rk,
+    // within the range the rank table gives
+    uint32_t lo[kFoldItems], hi[kFoldItems];
+#pragma unroll
+    for (int i = 0; i < kFoldItems; ++i) {
+        lo[i] = hi[i] = 0;
+        if (head[i] && rr[i] != 0 && ne) {
+            const uint64_t c = rr[i] >> rsh;
+            lo[i] = rtab[c];
+            hi[i] = c + 1 < rt_n ? rtab[c + 1] : (uint32_t)ne;
+        }
+    }
+    for (bool busy = true; busy;) {
+        busy = false;
+#pragma unroll
+        for (int i = 0; i < kFoldItems; ++i) {
+            if (lo[i] < hi[i]) {
+                const uint32_t mid = (lo[i] + hi[i]) >> 1;
+                if (srank[mid] < rr[i])
+                    lo[i] = mid + 1;
+                else
+                    hi[i] = mid;
+                busy |= lo[i] < hi[i];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kFoldItems; ++i) {
+        if (!head[i]) continue;
+        const uint64_t rk = rr[i];
+        const uint64_t r = r0 + i;
+        const uint64_t pos = lo[i];
+        const bool hit = rk != 0 && pos < ne && srank[pos] == rk;
+        ins[r] = pos;
+        seg_sum[r] = acc[i];
+        if (rk != 0 && !hit) is_new[r] = 1;
+        if (open[i]) {
+            s_open = r;  // at most one per tile: the run of the tile's last record
+        } else if (rk == 0) {
+            sc->hf_sum = acc[i];
+            sc->hf_hit = 1;
+        } else if (hit) {
+            delta[pos] = acc[i];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tl = 0.0;  // the tile's leading piece, in record order
+        uint32_t hh = 0;
+        for (int k = 0; k < kThreads; ++k) {
+            tl += s_lead[k];
+            if (s_head[k]) {
+                hh = 1;
+                break;
+            }
+        }
+        ft.lead[blockIdx.x] = tl;
+        ft.has_head[blockIdx.x] = hh;
+        ft.open[blockIdx.x] = s_open;
+    }
+}
+
+// Finish the open runs: add the leading pieces of the following tiles until one holds a head.
+// One lane per tile.
+__global__ void __launch_bounds__(kThreads) k_seg_close(const uint64_t *__restrict__ rank, uint64_t n_tiles,
+                                                        const uint64_t *__restrict__ srank, uint64_t ne,
+                                                        double *__restrict__ delta, const uint64_t *__restrict__ ins,
+                                                        double *__restrict__ seg_sum, FoldTiles ft, Scratch *sc)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint64_t r = ft.open[t];
+    if (r == kNoOpen) return;
+    double acc = seg_sum[r];
+    for (uint64_t k = t + 1; k < n_tiles; ++k) {
+        acc += ft.lead[k];
+        if (ft.has_head[k]) break;
+    }
+    seg_sum[r] = acc;
+    const uint64_t rk = rank[r];
+    if (rk == 0) {
+        sc->hf_sum = acc;
+        sc->hf_hit = 1;
+    } else {
+        const uint64_t pos = ins[r];
+        if (pos < ne && srank[pos] == rk) delta[pos] = acc;
+    }
 }
 
 template <int W>
@@ -848,27 +1013,39 @@ __global__ void __launch_bounds__(kThreads) k_compact(const uint64_t *__restrict
     if (threadIdx.x == 0) abs_part[blockIdx.x] = a;
 }
 
-// The step's statistics in one fixed-order reduction (one block of kFinalThreads): the item
-// kernels' partials, the generation blocks' spawn and death counts, and the per-block |N|
-// sums of the compacted store.
-constexpr int kFinalThreads = 256;
-constexpr int kFinalWaves = kFinalThreads / 64;
+// The step's statistics in a fixed-order two-stage reduction: block b of k_final_part sums
+// the b-th contiguous chunk of every partial array (the item kernels' per-block partials, the
+// generation blocks' spawn and death counts, the per-block |N| sums of the compacted store);
+// k_final adds the chunk sums in chunk order.
+struct FinalPart {
+    double num, tot;
+    uint64_t att, disc, mx, sp, de, pad;
+};
 
-__global__ void __launch_bounds__(kFinalThreads) k_final(ItemPartials part, uint64_t n_parts, GenStats gs, uint64_t n_gen,
-                                                         const double *__restrict__ abs_part, uint64_t n_abs, Scratch *sc)
+__device__ __forceinline__ void chunk_of(uint64_t n, uint64_t g, uint64_t &lo, uint64_t &hi)
 {
-    constexpr int U = 8;  // loads in flight per array and thread
-    constexpr uint64_t T = kFinalThreads;
+    const uint64_t c = (n + gridDim.x - 1) / gridDim.x;
+    lo = g * c < n ? g * c : n;
+    hi = lo + c < n ? lo + c : n;
+}
+
+__global__ void __launch_bounds__(kThreads) k_final_part(ItemPartials part, uint64_t n_parts, GenStats gs, uint64_t n_gen,
+                                                         const double *__restrict__ abs_part, uint64_t n_abs,
+                                                         FinalPart *__restrict__ out)
+{
+    constexpr int U = 4;  // loads in flight per array and thread
     double num = 0.0, tot = 0.0;
     uint64_t att = 0, disc = 0, mx = 0, sp = 0, de = 0;
-    for (uint64_t i0 = 0; i0 < n_parts; i0 += U * T) {
+    uint64_t lo, hi;
+    chunk_of(n_parts, blockIdx.x, lo, hi);
+    for (uint64_t i0 = lo; i0 < hi; i0 += U * kThreads) {
         double a[U];
         uint64_t b[U], c[U], d[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {  // clamped indices: unconditional loads, then select
-            const uint64_t i = i0 + (uint64_t)u * T + threadIdx.x;
-            const bool in = i < n_parts;
-            const uint64_t ic = in ? i : n_parts - 1;
+            const uint64_t i = i0 + (uint64_t)u * kThreads + threadIdx.x;
+            const bool in = i < hi;
+            const uint64_t ic = in ? i : hi - 1;
             a[u] = part.num[ic];
             b[u] = part.att[ic];
             c[u] = part.disc[ic];
@@ -886,16 +1063,17 @@ __global__ void __launch_bounds__(kFinalThreads) k_final(ItemPartials part, uint
             mx = d[u] > mx ? d[u] : mx;
         }
     }
-    for (uint64_t i0 = 0; i0 < n_gen; i0 += 2 * U * T) {
+    chunk_of(n_gen, blockIdx.x, lo, hi);
+    for (uint64_t i0 = lo; i0 < hi; i0 += 2 * U * kThreads) {
         uint32_t x[2 * U], y[2 * U];
 #pragma unroll
         for (int u = 0; u < 2 * U; ++u) {
-            const uint64_t i = i0 + (uint64_t)u * T + threadIdx.x;
-            const uint64_t ic = i < n_gen ? i : n_gen - 1;
+            const uint64_t i = i0 + (uint64_t)u * kThreads + threadIdx.x;
+            const uint64_t ic = i < hi ? i : hi - 1;
             x[u] = gs.spawns[ic];
             y[u] = gs.deaths[ic];
-            x[u] = i < n_gen ? x[u] : 0u;
-            y[u] = i < n_gen ? y[u] : 0u;
+            x[u] = i < hi ? x[u] : 0u;
+            y[u] = i < hi ? y[u] : 0u;
         }
 #pragma unroll
         for (int u = 0; u < 2 * U; ++u) {
@@ -903,33 +1081,51 @@ __global__ void __launch_bounds__(kFinalThreads) k_final(ItemPartials part, uint
             de += y[u];
         }
     }
-    for (uint64_t i0 = 0; i0 < n_abs; i0 += 2 * U * T) {
+    chunk_of(n_abs, blockIdx.x, lo, hi);
+    for (uint64_t i0 = lo; i0 < hi; i0 += 2 * U * kThreads) {
         double x[2 * U];
 #pragma unroll
         for (int u = 0; u < 2 * U; ++u) {
-            const uint64_t i = i0 + (uint64_t)u * T + threadIdx.x;
-            x[u] = abs_part[i < n_abs ? i : n_abs - 1];
-            x[u] = i < n_abs ? x[u] : 0.0;
+            const uint64_t i = i0 + (uint64_t)u * kThreads + threadIdx.x;
+            x[u] = abs_part[i < hi ? i : hi - 1];
+            x[u] = i < hi ? x[u] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 2 * U; ++u) tot += x[u];
     }
-    num = block_reduce_sum<double, kFinalWaves>(num);
-    tot = block_reduce_sum<double, kFinalWaves>(tot);
-    att = block_reduce_sum<uint64_t, kFinalWaves>(att);
-    disc = block_reduce_sum<uint64_t, kFinalWaves>(disc);
-    sp = block_reduce_sum<uint64_t, kFinalWaves>(sp);
-    de = block_reduce_sum<uint64_t, kFinalWaves>(de);
-    mx = block_reduce_max<uint64_t, kFinalWaves>(mx);
-    if (threadIdx.x == 0) {
-        sc->num = num;
-        sc->n_total = tot;
-        sc->n_attempts = att;
-        sc->n_discarded = disc;
-        sc->max_n = mx;
-        sc->n_spawns = sp;
-        sc->n_deaths = de;
+    FinalPart r;
+    r.num = block_reduce_sum(num);
+    r.tot = block_reduce_sum(tot);
+    r.att = block_reduce_sum(att);
+    r.disc = block_reduce_sum(disc);
+    r.sp = block_reduce_sum(sp);
+    r.de = block_reduce_sum(de);
+    r.mx = block_reduce_max(mx);
+    r.pad = 0;
+    if (threadIdx.x == 0) out[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(kThreads) k_final(const FinalPart *__restrict__ in, uint64_t n, Scratch *sc)
+{
+    if (threadIdx.x != 0) return;
+    FinalPart a{};
+    for (uint64_t i = 0; i < n; ++i) {
+        const FinalPart b = in[i];
+        a.num += b.num;
+        a.tot += b.tot;
+        a.att += b.att;
+        a.disc += b.disc;
+        a.sp += b.sp;
+        a.de += b.de;
+        a.mx = b.mx > a.mx ? b.mx : a.mx;
     }
+    sc->num = a.num;
+    sc->n_total = a.tot;
+    sc->n_attempts = a.att;
+    sc->n_discarded = a.disc;
+    sc->max_n = a.mx;
+    sc->n_spawns = a.sp;
+    sc->n_deaths = a.de;
 }
 
 template <typename V>

@@ -276,11 +276,14 @@ __global__ void __launch_bounds__(kThreads) k_radix_ghist(const uint64_t *__rest
             if (h[p][d]) atomicAdd(&ghist[p * kRadixBins + d], h[p][d]);
 }
 
-// One stable pass by the digit at `shift`: a tile ranks its keys locally (round by round, by
-// wavefront digit matching), publishes its per-digit counts, looks back over the earlier
-// tiles digit by digit, and scatters to digit base + earlier tiles + local rank.  status
-// holds kRadixBins words per tile and must be zero before the launch.  Each thread owns the
-// digits threadIdx.x + j * kThreads.
+// One stable pass by the digit at `shift`.  Wavefront w of a tile owns the tile's keys
+// [w * 64 * kSortItems, (w + 1) * 64 * kSortItems), 64 per round, and ranks them against its
+// own LDS digit counters (no block barrier between rounds: a wavefront's LDS accesses are in
+// order).  The tile then combines its wavefronts' counts, publishes its per-digit counts,
+// looks back over the earlier tiles digit by digit, and scatters each key to
+// digit base + earlier tiles + earlier wavefronts + rank in its wavefront.  status holds
+// kRadixBins words per tile and must be zero before the launch.  Thread x also owns the
+// digits x + j * kThreads of the per-digit work.
 constexpr int kDigitsPerThread = kRadixBins / kThreads;
 
 __global__ void __launch_bounds__(kThreads) k_radix_onesweep(const uint64_t *__restrict__ key_in, const uint32_t *__restrict__ idx_in,
@@ -289,64 +292,62 @@ __global__ void __launch_bounds__(kThreads) k_radix_onesweep(const uint64_t *__r
                                                              const uint32_t *__restrict__ ghist, uint64_t *__restrict__ status,
                                                              uint64_t *__restrict__ ticket)
 {
-    __shared__ uint32_t run[kRadixBins];
-    __shared__ uint32_t wave_cnt[kWaves][kRadixBins];
+    __shared__ uint32_t wave_cnt[kWaves][kRadixBins];  // per wavefront: digit counts, then offsets
     __shared__ uint32_t dig_base[kRadixBins];
     __shared__ uint64_t s_tile;
     const uint64_t n = *n_live;
     if (threadIdx.x == 0) s_tile = atomicAdd((unsigned long long *)ticket, 1ull);
+    const int w = wave_id(), lane = lane_id();
 #pragma unroll
-    for (int j = 0; j < kDigitsPerThread; ++j) run[threadIdx.x + j * kThreads] = 0;
+    for (int j = 0; j < kRadixBins / 64; ++j) wave_cnt[w][lane + 64 * j] = 0;
     __syncthreads();
     const uint64_t t = s_tile;
     const uint64_t base = t * kSortTile;
     if (base >= n) return;  // tiles beyond the live count: nobody waits on them
+    const uint64_t wbase = base + (uint64_t)w * 64 * kSortItems;
     uint64_t k[kSortItems];
     uint32_t ix[kSortItems];
     uint16_t rk[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {  // all loads in flight before the ranking rounds
-        const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
+        const uint64_t g = wbase + (uint64_t)r * 64 + lane;
         const uint64_t gc = g < n ? g : n - 1;  // clamped: unconditional loads
         k[r] = key_in[gc];
         ix[r] = idx_in ? idx_in[gc] : (uint32_t)g;
     }
+    uint32_t *cnt = wave_cnt[w];
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w)
-#pragma unroll
-            for (int j = 0; j < kDigitsPerThread; ++j) wave_cnt[w][threadIdx.x + j * kThreads] = 0;
-        __syncthreads();
-        const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
+        const uint64_t g = wbase + (uint64_t)r * 64 + lane;
         const bool valid = g < n;
         const uint32_t d = (uint32_t)((k[r] >> shift) & (kRadixBins - 1));
         const uint64_t active = __ballot(valid);
-        int rank = 0;
+        uint32_t rank = 0;
         if (valid) {
             const uint64_t peers = match_digit(d, active);
-            rank = lanes_below(peers);
-            if (rank == 0) wave_cnt[wave_id()][d] = (uint32_t)__popcll(peers);
+            const uint32_t before = cnt[d];  // read by every peer before the leader's update
+            const int below = lanes_below(peers);
+            rank = before + (uint32_t)below;
+            if (below == 0) cnt[d] = before + (uint32_t)__popcll(peers);
         }
-        __syncthreads();
+        rk[r] = (uint16_t)rank;
+    }
+    __syncthreads();
+    // per digit: exclusive prefix over the wavefronts, and the tile's count
+    uint32_t tile_cnt[kDigitsPerThread];
 #pragma unroll
-        for (int j = 0; j < kDigitsPerThread; ++j) {
-            const int dd = threadIdx.x + j * kThreads;
-            uint32_t acc = run[dd];
+    for (int j = 0; j < kDigitsPerThread; ++j) {
+        const int dd = threadIdx.x + j * kThreads;
+        uint32_t acc = 0;
 #pragma unroll
-            for (int w = 0; w < kWaves; ++w) {
-                const uint32_t c = wave_cnt[w][dd];
-                wave_cnt[w][dd] = acc;
-                acc += c;
-            }
-            run[dd] = acc;
+        for (int ww = 0; ww < kWaves; ++ww) {
+            const uint32_t c = wave_cnt[ww][dd];
+            wave_cnt[ww][dd] = acc;
+            acc += c;
         }
-        __syncthreads();
-        rk[r] = (uint16_t)(valid ? wave_cnt[wave_id()][d] + (uint32_t)rank : 0u);
-        __syncthreads();
+        tile_cnt[j] = acc;
     }
     // global base of each digit: exclusive prefix of the pass histogram over the digits
-    // (thread x holds digits x and x + kThreads, ...; scanned in digit order)
     uint32_t gbase[kDigitsPerThread];
     {
         uint32_t carry = 0;
@@ -357,16 +358,14 @@ __global__ void __launch_bounds__(kThreads) k_radix_onesweep(const uint64_t *__r
             carry += tot;
         }
     }
-    // publish this tile's counts, then sum the earlier tiles' counts (both digit chains of a
+    // publish this tile's counts, then sum the earlier tiles' counts (the digit chains of a
     // thread advance together)
     uint64_t *st = status + t * kRadixBins;
-    uint32_t cnt[kDigitsPerThread];
     uint64_t excl[kDigitsPerThread];
     int64_t pp[kDigitsPerThread];
 #pragma unroll
     for (int j = 0; j < kDigitsPerThread; ++j) {
-        cnt[j] = run[threadIdx.x + j * kThreads];
-        lb_publish(&st[threadIdx.x + j * kThreads], t == 0 ? kLbInclusive : kLbAggregate, cnt[j]);
+        lb_publish(&st[threadIdx.x + j * kThreads], t == 0 ? kLbInclusive : kLbAggregate, tile_cnt[j]);
         excl[j] = 0;
         pp[j] = (int64_t)t - 1;
     }
@@ -375,14 +374,14 @@ __global__ void __launch_bounds__(kThreads) k_radix_onesweep(const uint64_t *__r
 #pragma unroll
         for (int j = 0; j < kDigitsPerThread; ++j) {
             if (pp[j] < 0) continue;
-            const uint64_t w = __hip_atomic_load(&status[(uint64_t)pp[j] * kRadixBins + threadIdx.x + j * kThreads],
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t flag = w & ~kLbValue;
+            const uint64_t sw = __hip_atomic_load(&status[(uint64_t)pp[j] * kRadixBins + threadIdx.x + j * kThreads],
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t flag = sw & ~kLbValue;
             if (flag == 0) {
                 busy = true;  // not published yet: poll again
                 continue;
             }
-            excl[j] += w & kLbValue;
+            excl[j] += sw & kLbValue;
             pp[j] = flag == kLbInclusive ? -1 : pp[j] - 1;
             busy |= pp[j] >= 0;
         }
@@ -391,16 +390,16 @@ __global__ void __launch_bounds__(kThreads) k_radix_onesweep(const uint64_t *__r
 #pragma unroll
     for (int j = 0; j < kDigitsPerThread; ++j) {
         const int d = threadIdx.x + j * kThreads;
-        if (t > 0) lb_publish(&st[d], kLbInclusive, excl[j] + cnt[j]);
+        if (t > 0) lb_publish(&st[d], kLbInclusive, excl[j] + tile_cnt[j]);
         dig_base[d] = gbase[j] + (uint32_t)excl[j];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
-        const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
+        const uint64_t g = wbase + (uint64_t)r * 64 + lane;
         if (g < n) {
             const uint32_t d = (uint32_t)((k[r] >> shift) & (kRadixBins - 1));
-            const uint32_t dst = dig_base[d] + rk[r];
+            const uint32_t dst = dig_base[d] + wave_cnt[w][d] + rk[r];
             key_out[dst] = k[r];
             idx_out[dst] = ix[r];
         }
