@@ -138,6 +138,19 @@ ccmc_status ccmc_init(const ccmc_system *sys, const ccmc_integrals *ints, int tr
 ccmc_status ccmc_step(ccmc_state *st, double tau, double shift, uint64_t n_attempts,
                       ccmc_stats *out);
 
+/* Steps of n states in shared launches, for serving many solves at once: state i takes one
+ * step exactly as ccmc_step(states[i], tau[i], shift[i], n_attempts[i], out + i) would alone
+ * (each block of a launch works on one state's data with that state's Philox key), and
+ * out[i] (out may be NULL) receives its statistics.  States with the same bitstring words
+ * and precision share every launch; each such group runs on the stream of its first state
+ * after the work already queued on the others' streams.  A state may appear once.
+ * Errors: EINVAL for bad arguments (no state changes).  Otherwise each state succeeds or
+ * fails on its own, with ccmc_step's errors: a failed state is unchanged and
+ * ccmc_last_error(states[i]) is non-empty exactly for the failed states; the others complete
+ * their step.  The first failure's status is returned. */
+ccmc_status ccmc_step_batch(ccmc_state *const *states, int n, const double *tau, const double *shift,
+                            const uint64_t *n_attempts, ccmc_stats *out);
+
 /* Projected-energy estimator terms of the last step (Sec. II, eq. 7): E_proj is the ratio of
  * the means of eproj_num and eproj_den over the equilibrated steps.  e_hf receives the
  * Hartree-Fock energy.  Any output pointer may be NULL. */

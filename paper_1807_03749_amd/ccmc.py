@@ -63,7 +63,8 @@ class ccmc_kernel_time(C.Structure):
                 ("items", C.c_double)]
 
 
-EXPORTED = ["ccmc_options_default", "ccmc_init", "ccmc_step", "ccmc_energy", "ccmc_free", "ccmc_last_error",
+EXPORTED = ["ccmc_options_default", "ccmc_init", "ccmc_step", "ccmc_step_batch", "ccmc_energy", "ccmc_free",
+            "ccmc_last_error",
             "ccmc_export_size", "ccmc_export", "ccmc_import", "ccmc_spawns_size", "ccmc_export_spawns",
             "ccmc_profile", "ccmc_profile_read", "ccmc_dims", "ccmc_memory"]
 
@@ -85,6 +86,8 @@ def lib():
             "ccmc_init": (st, [C.POINTER(ccmc_system), C.POINTER(ccmc_integrals), C.c_int, C.POINTER(ccmc_options),
                                C.POINTER(vp)]),
             "ccmc_step": (st, [vp, C.c_double, C.c_double, C.c_uint64, C.POINTER(ccmc_stats)]),
+            "ccmc_step_batch": (st, [C.POINTER(vp), C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_uint64), C.POINTER(ccmc_stats)]),
             "ccmc_energy": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
             "ccmc_free": (None, [vp]),
             "ccmc_last_error": (C.c_char_p, [vp]),
@@ -117,6 +120,9 @@ def options(**kw) -> ccmc_options:
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
     return o
+
+
+CCMC_EINVAL_STATUS = -1
 
 
 class State:
@@ -235,3 +241,26 @@ class State:
         b = C.c_uint64()
         self._check(lib().ccmc_memory(self._h, C.byref(b)))
         return b.value
+
+
+def ccmc_step_batch(states, tau, shift, n_attempts):
+    """One step of every state in shared launches (``ccmc_step_batch``).  Returns a list with
+    each state's statistics dict, or the CCMCError of that state when its step failed (the
+    state is then unchanged); raises on invalid arguments."""
+    n = len(states)
+    if n == 0:
+        return []
+    hs = (C.c_void_p * n)(*[s_._h for s_ in states])
+    ta = (C.c_double * n)(*[float(x) for x in tau])
+    sa = (C.c_double * n)(*[float(x) for x in shift])
+    na = (C.c_uint64 * n)(*[int(x) for x in n_attempts])
+    outs = (ccmc_stats * n)()
+    rc = lib().ccmc_step_batch(hs, n, ta, sa, na, outs)
+    if rc == CCMC_EINVAL_STATUS:
+        raise CCMCError(rc, "; ".join(filter(None, (lib().ccmc_last_error(h).decode() for h in hs))) or
+                        "ccmc_step_batch: invalid arguments")
+    res = []
+    for i, st in enumerate(states):
+        err = lib().ccmc_last_error(hs[i]).decode()
+        res.append(CCMCError(rc, err) if (rc != 0 and err) else outs[i].as_dict())
+    return res

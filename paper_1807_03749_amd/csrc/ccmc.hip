@@ -45,7 +45,7 @@ struct Work {
 struct Pending {
     const char *name;
     hipEvent_t a, b;
-    Work w;
+    std::vector<Work> w;  // one per state of the launch
 };
 
 struct Accum {
@@ -107,7 +107,12 @@ struct ccmc_state {
     uint64_t slot_hint = 1 << 16, rec_hint = 1 << 14;  // capacities planned for the next step
     uint64_t cnt_slots = 0, cnt_rec = 0, cnt_merged = 0, cnt_new = 0, cnt_att = 0, cnt_live_items = 0;  // live counts of the last step
     DevBuf lb;  // step scalars, tickets, radix histograms and look-back status words
-    Scratch *hscratch = nullptr;  // pinned
+    // batched steps led by this state: argument tables and the batch's step scalars
+    DevBuf arg_dev, batch_scr;
+    uint8_t *arg_host = nullptr;  // pinned
+    size_t arg_hcap = 0;
+    Scratch *batch_hscr = nullptr;  // pinned
+    size_t batch_hcap = 0;
     // last step's spawn list (keep_spawn_ids)
     uint64_t last_nrec = 0;
     int last_rec_buf = -1;
@@ -203,7 +208,7 @@ bool profiled(const ccmc_state *st, const char *name)
 }
 
 template <class F>
-void launch(ccmc_state *st, const char *name, Work w, F &&f)
+void launch(ccmc_state *st, const char *name, const std::vector<Work> &w, F &&f)
 {
     if (!st->prof || !profiled(st, name)) {
         f();
@@ -222,12 +227,14 @@ void resolve_profile(ccmc_state *st)
         float ms = 0;
         (void)hipEventSynchronize(p.b);
         (void)hipEventElapsedTime(&ms, p.a, p.b);
-        const double n = (double)(p.w.count ? *p.w.count : p.w.fixed);
         Accum &a = st->accum[p.name];
         a.launches++;
         a.ms += ms;
-        a.bytes += p.w.unit_bytes * n + (p.w.count2 ? p.w.unit_bytes2 * (double)*p.w.count2 : 0.0);
-        a.items += p.w.items ? (double)*p.w.items : n;
+        for (const Work &w : p.w) {
+            const double n = (double)(w.count ? *w.count : w.fixed);
+            a.bytes += w.unit_bytes * n + (w.count2 ? w.unit_bytes2 * (double)*w.count2 : 0.0);
+            a.items += w.items ? (double)*w.items : n;
+        }
         st->ev_pool.push_back(p.a);
         st->ev_pool.push_back(p.b);
     }
@@ -235,17 +242,7 @@ void resolve_profile(ccmc_state *st)
 }
 
 // --------------------------------------------------------------------------- scan
-// Single-launch look-back scan; status must hold ceil(n / kScanTile) zeroed words.
-template <typename V, typename Src, typename Out>
-void scan_lb(ccmc_state *st, Src in, Out out, uint64_t n, bool inclusive, uint64_t *status, uint64_t *ticket,
-             uint64_t *total)
-{
-    if (!n) return;
-    const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
-    k_scan_lb<V, Src, Out><<<(unsigned)tiles, kThreads, 0, st->stream>>>(in, out, n, inclusive ? 1 : 0, status, ticket,
-                                                                         total);
-}
-
+// Tiles of a single-launch look-back scan of n values.
 uint64_t scan_tiles(uint64_t n) { return (n + kScanTile - 1) / kScanTile; }
 
 // ------------------------------------------------------------------------ systems
@@ -505,7 +502,9 @@ ccmc_status ensure_store(ccmc_state *st, uint64_t n)
     TRY(ensure(st, st->srank[1 - c], nc * sizeof(uint64_t)));
     TRY(ensure(st, st->P, nc * sizeof(uint64_t)));
     TRY(ensure(st, st->guide, guide_cap(nc) * sizeof(uint32_t)));
+    // the per-entry sums start at zero (a grown buffer holds no contents)
     TRY(ensure(st, st->delta, nc * sizeof(double)));
+    k_fill<double><<<grid_for(nc), kThreads, 0, st->stream>>>(ptr<double>(st->delta), nc, 0.0);
     // rank table: about one bucket per store entry, at most one per rank
     int rt_bits = 1;
     while (rt_bits < 40 && (1ull << rt_bits) < nc) ++rt_bits;
@@ -518,31 +517,48 @@ ccmc_status ensure_store(ccmc_state *st, uint64_t n)
 }
 
 // ---------------------------------------------------------------------- the step
-constexpr uint64_t kMaxFinalParts = 512;
-  // blocks of the first stage of the final reduction
+constexpr uint64_t kMaxFinalParts = 512;  // blocks of the first stage of the final reduction
 
-// One attempt at a step.  Sizes produced on the device (record slots, records, new
-// determinants, survivors) are never read back in the middle: kernels read them from device
-// memory, and grids cover capacities planned from the previous step.  If a count exceeds
-// its capacity, the overflow bit turns the final compaction into a no-op; the host then
-// grows the buffers and the step is replayed with the same Philox counters (*replay).
+// Per-state plan of one batched step: sizes, capacities, the layout of the step area and
+// every pointer the kernels need.  Planning allocates; nothing is launched before every state
+// of the batch has been planned.
 template <int W, typename T>
-ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, ccmc_stats *out, bool *replay)
-{
-    *replay = false;
-    hipStream_t s = st->stream;
-    const uint64_t ne = st->ne;
-    const bool fnc = st->opt.full_noncomposite != 0;
-    const uint64_t n_fnc = fnc ? ne + 1 : 0;
-    const uint64_t n_items = n_fnc + n_sel;
-    const int c = st->cur;
-    const double kb = (double)(W * 8);  // bytes of one bitstring
-    const double tb = (double)sizeof(T);
-    const bool ids = st->opt.keep_spawn_ids != 0;
+struct Plan {
+    ccmc_state *st = nullptr;
+    double tau = 0, shift = 0;
+    uint64_t n_sel = 0;
+    ccmc_stats *out = nullptr;
+    StepArgs a{};
+    bool fnc = false, ids = false;
+    int c = 0, passes = 1;
+    uint64_t ne = 0, n_fnc = 0, n_items = 0, slot_cap = 0, nblk_cap = 0, rec_cap = 0, mcap = 0, tiles = 0;
+    uint64_t fold_tiles = 0, fin_blocks = 1, n_parts = 0, lb_words = 0;
+    unsigned nb_fnc = 0, nb_sel = 0, nb_rt = 0, nb_abs = 0;
+    uint64_t o_tick = 0, o_weights = 0, o_off = 0, o_boff = 0, o_new = 0, o_keep = 0, o_ghist = 0, o_rstat = 0;
+    uint64_t o_fold = 0, o_fin = 0;
+    uint64_t *lb = nullptr;
+    Scratch *sc = nullptr;
+    ccmc_status rc = CCMC_OK;  // this state's outcome
+    bool replay = false;       // a capacity overflowed: grow and step again
+};
 
-    StepArgs a;
-    a.tau = tau;
-    a.shift = shift;
+enum { kTkWeights, kTkOff, kTkBoff, kTkNew, kTkKeep, kTkRadix, kTickets = kTkRadix + kRadixMaxPasses };
+
+// Sizes and capacities of one state's step (all allocation happens here).
+template <int W, typename T>
+ccmc_status plan_sizes(Plan<W, T> &p)
+{
+    ccmc_state *st = p.st;
+    const uint64_t ne = st->ne;
+    p.ne = ne;
+    p.fnc = st->opt.full_noncomposite != 0;
+    p.ids = st->opt.keep_spawn_ids != 0;
+    p.n_fnc = p.fnc ? ne + 1 : 0;
+    p.n_items = p.n_fnc + p.n_sel;
+    p.c = st->cur;
+    StepArgs &a = p.a;
+    a.tau = p.tau;
+    a.shift = p.shift;
     a.cutoff = st->opt.spawn_cutoff;
     a.theta = st->opt.occupation_threshold;
     a.thr_cluster = st->opt.multispawn_threshold;
@@ -551,8 +567,8 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
     a.step = (uint32_t)(st->step & 0x0FFFFFFFu);
     a.key0 = (uint32_t)st->opt.seed;
     a.key1 = (uint32_t)(st->opt.seed >> 32);
-    a.n_sel = n_sel;
-    a.fnc = fnc ? 1 : 0;
+    a.n_sel = p.n_sel;
+    a.fnc = p.fnc ? 1 : 0;
     {
         // guide shift from the last step's Q (any shift gives the same draws; this one keeps
         // about one bucket per two excitors, so that large amplitudes own few buckets)
@@ -560,19 +576,16 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
         uint32_t sh = 0;
         while (sh < 63 && (q_est >> sh) + 2 > ne / 2 + 2) ++sh;
         a.gsh = sh;
-        a.gcap = guide_cap(st->scap);
     }
-
-    // ---- capacities for this step (all allocation happens here, before any launch)
-    const uint64_t slot_cap = std::max<uint64_t>(kGenSlots, (st->slot_hint + kGenSlots - 1) / kGenSlots * kGenSlots);
-    const uint64_t nblk_cap = slot_cap / kGenSlots;
-    const uint64_t rec_cap = std::max<uint64_t>(1, std::min<uint64_t>(st->rec_hint, slot_cap));
-    if (slot_cap + ne + 1 >= (1ull << 32)) {
+    p.slot_cap = std::max<uint64_t>(kGenSlots, (st->slot_hint + kGenSlots - 1) / kGenSlots * kGenSlots);
+    p.nblk_cap = p.slot_cap / kGenSlots;
+    p.rec_cap = std::max<uint64_t>(1, std::min<uint64_t>(st->rec_hint, p.slot_cap));
+    if (p.slot_cap + ne + 1 >= (1ull << 32)) {
         st->err = "more than 2^32 record slots in one step";
         return CCMC_EOVERFLOW;
     }
-    if (n_items + 1 > st->icap) {
-        const uint64_t nc = std::max<uint64_t>(n_items + 1, st->icap + st->icap / 2);
+    if (p.n_items + 1 > st->icap) {
+        const uint64_t nc = std::max<uint64_t>(p.n_items + 1, st->icap + st->icap / 2);
         TRY(ensure(st, st->ikey, nc * W * sizeof(uint64_t)));
         TRY(ensure(st, st->iA, nc * sizeof(T)));
         TRY(ensure(st, st->ideath, nc * sizeof(T)));
@@ -582,8 +595,8 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
         TRY(ensure(st, st->ioff, nc * sizeof(uint64_t)));
         st->icap = nc;
     }
-    if (slot_cap > st->rcap) {
-        const uint64_t nc = slot_cap;
+    if (p.slot_cap > st->rcap) {
+        const uint64_t nc = p.slot_cap;
         const uint64_t nb = nc / kGenSlots + 2;
         TRY(ensure(st, st->rkey, nc * W * sizeof(uint64_t)));
         TRY(ensure(st, st->ramp, nc * sizeof(T)));
@@ -591,9 +604,9 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
         for (DevBuf *b : {&st->gcount, &st->gspawn, &st->gdeath, &st->boff}) TRY(ensure(st, *b, nb * sizeof(uint32_t)));
         st->rcap = nc;
     }
-    if (ids && st->rid.bytes < st->rcap * sizeof(uint64_t)) TRY(ensure(st, st->rid, st->rcap * sizeof(uint64_t)));
-    if (rec_cap + 1 > st->dcap) {
-        const uint64_t nc = rec_cap + 1;
+    if (p.ids && st->rid.bytes < st->rcap * sizeof(uint64_t)) TRY(ensure(st, st->rid, st->rcap * sizeof(uint64_t)));
+    if (p.rec_cap + 1 > st->dcap) {
+        const uint64_t nc = p.rec_cap + 1;
         for (DevBuf *b : {&st->dkey, &st->nkey}) TRY(ensure(st, *b, nc * W * sizeof(uint64_t)));
         TRY(ensure(st, st->damp, nc * sizeof(T)));
         for (DevBuf *b : {&st->drank, &st->sr[0], &st->sr[1], &st->ins, &st->nins, &st->nrank})
@@ -602,263 +615,574 @@ ccmc_status step_once(ccmc_state *st, double tau, double shift, uint64_t n_sel, 
         for (DevBuf *b : {&st->seg_sum, &st->nsum}) TRY(ensure(st, *b, nc * sizeof(double)));
         st->dcap = nc;
     }
-    if (ids && st->did.bytes < st->dcap * sizeof(uint64_t)) TRY(ensure(st, st->did, st->dcap * sizeof(uint64_t)));
-    const uint64_t mcap = ne + rec_cap;  // merged store capacity of this step
-    TRY(ensure_store<W, T>(st, mcap + 1));
-    TRY(ensure(st, st->keep, (mcap + 1) * sizeof(uint32_t)));
-    TRY(ensure(st, st->pos, (mcap + 1) * sizeof(uint32_t)));
-    const uint64_t tiles = (rec_cap + kSortTile - 1) / kSortTile;
-    const int passes = std::max(1, (st->rank_bits + kRadixBits - 1) / kRadixBits);
-    const unsigned nb_fnc = fnc ? grid_for(n_fnc) : 0, nb_sel = n_sel ? grid_for(n_sel) : 0;
-    const size_t nparts = (size_t)(nb_fnc + nb_sel + 1);
+    if (p.ids && st->did.bytes < st->dcap * sizeof(uint64_t)) TRY(ensure(st, st->did, st->dcap * sizeof(uint64_t)));
+    p.mcap = ne + p.rec_cap;  // merged store capacity of this step
+    TRY(ensure_store<W, T>(st, p.mcap + 1));
+    p.a.gcap = guide_cap(st->scap);
+    TRY(ensure(st, st->keep, (p.mcap + 1) * sizeof(uint32_t)));
+    TRY(ensure(st, st->pos, (p.mcap + 1) * sizeof(uint32_t)));
+    p.tiles = (p.rec_cap + kSortTile - 1) / kSortTile;
+    p.fold_tiles = (p.rec_cap + kFoldTile - 1) / kFoldTile;
+    p.passes = std::max(1, (st->rank_bits + kRadixBits - 1) / kRadixBits);
+    p.nb_fnc = p.fnc ? grid_for(p.n_fnc) : 0;
+    p.nb_sel = p.n_sel ? grid_for(p.n_sel) : 0;
+    p.nb_rt = ne ? grid_for(st->rt_n) : 0;
+    p.n_parts = p.nb_fnc + p.nb_sel;
+    const size_t nparts = (size_t)(p.n_parts + 1);
     TRY(ensure(st, st->num_part, nparts * sizeof(double)));
     TRY(ensure(st, st->att_part, nparts * sizeof(uint64_t)));
     TRY(ensure(st, st->disc_part, nparts * sizeof(uint64_t)));
     TRY(ensure(st, st->max_part, nparts * sizeof(uint64_t)));
-    const unsigned nb_abs = grid_for(mcap);
-    TRY(ensure(st, st->abs_part, (nb_abs + 1) * sizeof(double)));
-
-    // One zeroed area per step: the step scalars, the scan tickets, the look-back status
-    // words of every scan and radix pass, and the radix histograms (64-bit words).
-    enum { kTkWeights, kTkOff, kTkBoff, kTkNew, kTkKeep, kTkRadix, kTickets = kTkRadix + 8 };
-    const uint64_t w_scratch = (sizeof(Scratch) + 7) / 8;
-    const uint64_t o_tick = w_scratch;
-    const uint64_t o_weights = o_tick + kTickets;
-    const uint64_t o_off = o_weights + scan_tiles(ne);
-    const uint64_t o_boff = o_off + scan_tiles(n_items + 1);
-    const uint64_t o_new = o_boff + scan_tiles(nblk_cap + 1);
-    const uint64_t o_keep = o_new + scan_tiles(rec_cap);
-    const uint64_t o_ghist = o_keep + scan_tiles(mcap);
-    const uint64_t o_rstat = o_ghist + (uint64_t)passes * kRadixBins / 2;
-    const uint64_t o_fold = o_rstat + (uint64_t)passes * tiles * kRadixBins;
-    const uint64_t fold_tiles = (rec_cap + kFoldTile - 1) / kFoldTile;
-    const uint64_t o_fin = o_fold + 3 * fold_tiles;
-    const uint64_t lb_words = o_fin + kMaxFinalParts * (sizeof(FinalPart) / 8);
-    TRY(ensure(st, st->lb, lb_words * sizeof(uint64_t)));
-    uint64_t *lb = ptr<uint64_t>(st->lb);
-    uint64_t *tick = lb + o_tick;
-    Scratch *sc = reinterpret_cast<Scratch *>(lb);
-    launch(st, "clear", Work{8.0, nullptr, lb_words}, [&] {
-        k_fill<uint64_t><<<grid_for(lb_words), kThreads, 0, s>>>(lb, lb_words, 0ull);
-    });
-
-    const uint64_t scap = st->scap;
-    const uint64_t *skey = ptr<uint64_t>(st->skey[c]);
-    const T *samp = ptr<T>(st->samp[c]);
-    const T *sK = ptr<T>(st->sK[c]);
-    const uint64_t *srank = ptr<uint64_t>(st->srank[c]);
-
-    // ---- (a1) selection weights, formed inside the scan of their prefix, with the
-    // excitor-draw guide and the store's rank table
-    if (ne) {
-        const WeightOut wo{ptr<uint64_t>(st->P), ptr<uint32_t>(st->guide), a.gcap, a.gsh, ne};
-        // bytes: amplitude read, prefix written, about two guide entries
-        launch(st, "weights_scan", Work{tb + 16.0, nullptr, ne}, [&] {
-            scan_lb<uint64_t>(st, WeightSrc<T>{samp, sc}, wo, ne, true, lb + o_weights, tick + kTkWeights, &sc->qtot);
-        });
-    }
-
-    // ---- (a2-a5, a9, a10) items: non-composite (FNC) then sampled clusters
-    Items<T> it{ptr<uint64_t>(st->ikey), ptr<T>(st->iA), ptr<T>(st->ideath), ptr<uint32_t>(st->in),
-                ptr<uint8_t>(st->ilevel), ptr<uint64_t>(st->icnt), st->icap};
-    ItemPartials part{ptr<double>(st->num_part), ptr<uint64_t>(st->att_part), ptr<uint64_t>(st->disc_part),
-                      ptr<uint64_t>(st->max_part)};
-    const double item_bytes = kb + 2 * tb + 13.0;  // key, A, death, n, level, slot count
-    // the store's rank table for the lookups of the annihilation (built only with a store)
-    const RankTable rt{srank, ne, ptr<uint32_t>(st->rtab), st->rt_n, st->rsh};
-    const unsigned nb_rt = ne ? grid_for(st->rt_n) : 0;
-    if (n_items || nb_rt) {
-        // bytes: each item written (plus, for the non-composite ones, the store entry read)
-        launch(st, "items", Work{item_bytes, nullptr, n_items}, [&] {
-            k_items<W, T><<<nb_fnc + nb_sel + nb_rt, kThreads, 0, s>>>(st->sd, skey, samp, sK, scap, ne,
-                                                                       ptr<uint64_t>(st->P), ptr<uint32_t>(st->guide),
-                                                                       st->n0, a, it, nb_fnc, n_fnc, nb_fnc + nb_sel, rt,
-                                                                       part, sc);
-        });
-    }
-    if (!n_sel) k_fill<uint64_t><<<1, 1, 0, s>>>(it.cnt + n_items, 1, 0ull);
-    launch(st, "slot_scan", Work{16.0, nullptr, n_items + 1}, [&] {
-        scan_lb<uint64_t>(st, ArraySrc<uint64_t>{it.cnt},
-                          SlotOut{ptr<uint64_t>(st->ioff), ptr<uint64_t>(st->block_item), slot_cap}, n_items + 1, false,
-                          lb + o_off, tick + kTkOff, &sc->n_slots);
-    });
-
-    // ---- (a6-a8) records: death and spawning attempts, one lane per slot, compacted per block
-    Records reg{nullptr, ptr<uint64_t>(st->rkey), st->ramp.p, ptr<uint64_t>(st->rid), st->rcap};
-    GenStats gst{ptr<uint32_t>(st->gcount), ptr<uint32_t>(st->gspawn), ptr<uint32_t>(st->gdeath)};
-    // bytes: the records written and each live item read once (key, A, death, n, offset);
-    // work units: spawning attempts
-    launch(st, "generate", Work{kb + tb + (ids ? 8.0 : 0.0), &st->cnt_rec, 0, &st->cnt_att, kb + 2 * tb + 12.0,
-                                &st->cnt_live_items}, [&] {
-        k_generate<W, T><<<(unsigned)nblk_cap, kThreads, 0, s>>>(st->sd, it, ptr<uint64_t>(st->ioff),
-                                                                 ptr<uint64_t>(st->block_item), n_fnc, n_items, slot_cap, a,
-                                                                 reg, ids ? 1 : 0, gst, sc);
-    });
-    launch(st, "region_scan", Work{8.0, nullptr, nblk_cap + 1}, [&] {
-        scan_lb<uint32_t>(st, ArraySrc<uint32_t>{gst.count}, ArrayOut<uint32_t>{ptr<uint32_t>(st->boff)}, nblk_cap + 1,
-                          false, lb + o_boff, tick + kTkBoff, &sc->n_rec);
-    });
-    const uint64_t dc = st->dcap;
-    Records rec{ptr<uint64_t>(st->drank), ptr<uint64_t>(st->dkey), st->damp.p, ptr<uint64_t>(st->did), dc};
-    launch(st, "gather", Work{2.0 * (kb + tb + (ids ? 8.0 : 0.0)) + 8.0, &st->cnt_rec, 0}, [&] {
-        k_gather<W, T><<<grid_for(rec_cap), kThreads, 0, s>>>(st->sd, reg, ptr<uint32_t>(st->boff), nblk_cap, rec_cap, rec,
-                                                              ids ? 1 : 0, sc);
-    });
-
-    // ---- (a11) stable LSD radix sort of (rank, record index): one histogram launch for all
-    // passes, then one single-sweep launch per digit
-    const uint64_t *n_live = &sc->n_live;
-    uint32_t *ghist = reinterpret_cast<uint32_t *>(lb + o_ghist);
-    launch(st, "radix_ghist", Work{8.0, &st->cnt_rec, 0}, [&] {
-        k_radix_ghist<<<(unsigned)tiles, kThreads, 0, s>>>(ptr<uint64_t>(st->drank), n_live, passes, ghist);
-    });
-    const uint64_t *kin = ptr<uint64_t>(st->drank);
-    const uint32_t *iin = nullptr;
-    int ob = 0;
-    for (int p = 0; p < passes; ++p) {
-        uint64_t *kout = ptr<uint64_t>(st->sr[ob]);
-        uint32_t *iout = ptr<uint32_t>(st->sidx[ob]);
-        launch(st, "radix_onesweep", Work{2 * 8.0 + (iin ? 8.0 : 4.0), &st->cnt_rec, 0}, [&] {
-            k_radix_onesweep<<<(unsigned)tiles, kThreads, 0, s>>>(kin, iin, kout, iout, n_live, kRadixBits * p,
-                                                                  ghist + kRadixBins * p,
-                                                                  lb + o_rstat + (uint64_t)p * tiles * kRadixBins,
-                                                                  tick + kTkRadix + p);
-        });
-        kin = kout;
-        iin = iout;
-        ob ^= 1;
-    }
-    const uint64_t *sorted_rank = kin;
-    const uint32_t *sorted_idx = iin;
-
-    // ---- (a12) runs of equal determinants: left fold in record order, store lookup by rank
-    double *delta = ptr<double>(st->delta);
-    FoldTiles ft{reinterpret_cast<double *>(lb + o_fold), reinterpret_cast<uint32_t *>(lb + o_fold + fold_tiles),
-                 lb + o_fold + 2 * fold_tiles};
-    launch(st, "seg_fold", Work{8.0 + 4.0 + tb + 4.0, &st->cnt_rec, 0}, [&] {
-        k_seg_fold<T><<<(unsigned)fold_tiles, kThreads, 0, s>>>(sorted_rank, sorted_idx, ptr<T>(st->damp), rec_cap, srank, ne,
-                                                               delta, ptr<uint32_t>(st->is_new), ptr<uint64_t>(st->ins),
-                                                               ptr<double>(st->seg_sum), ptr<uint32_t>(st->rtab), st->rt_n,
-                                                               st->rsh, ft, sc);
-    });
-    launch(st, "seg_close", Work{24.0, nullptr, fold_tiles}, [&] {
-        k_seg_close<<<grid_for(fold_tiles), kThreads, 0, s>>>(sorted_rank, fold_tiles, srank, ne, delta,
-                                                             ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum), ft, sc);
-    });
-    launch(st, "new_scan", Work{8.0, &st->cnt_rec, 0}, [&] {
-        scan_lb<uint32_t>(st, ArraySrc<uint32_t>{ptr<uint32_t>(st->is_new)}, ArrayOut<uint32_t>{ptr<uint32_t>(st->new_pos)},
-                          rec_cap, false, lb + o_new, tick + kTkNew, &sc->n_new);
-    });
-    launch(st, "new_compact", Work{2.0 * (kb + 24.0) + 8.0, &st->cnt_new, 0}, [&] {
-        k_new_compact<W><<<grid_for(rec_cap), kThreads, 0, s>>>(sorted_rank, sorted_idx, ptr<uint64_t>(st->dkey), dc, rec_cap,
-                                                                ptr<uint32_t>(st->is_new), ptr<uint32_t>(st->new_pos),
-                                                                ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum),
-                                                                ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), dc,
-                                                                ptr<uint64_t>(st->nins), ptr<double>(st->nsum), sc);
-    });
-
-    // ---- (a12, a13) merge and round into the other store buffer, compact back into this one
-    const int m = 1 - c;
-    const uint64_t S2 = st->scap;
-    uint64_t *mkey = ptr<uint64_t>(st->skey[m]);
-    T *mamp = ptr<T>(st->samp[m]);
-    T *mK = ptr<T>(st->sK[m]);
-    uint64_t *mrank = ptr<uint64_t>(st->srank[m]);
-    uint32_t *keep = ptr<uint32_t>(st->keep), *pos = ptr<uint32_t>(st->pos);
-    const double eb = kb + 2 * tb + 8.0;  // one store entry: key, amplitude, diagonal, rank
-    launch(st, "merge", Work{2.0 * eb + 12.0, &st->cnt_merged, 0}, [&] {
-        k_merge<W, T><<<grid_for(mcap), kThreads, 0, s>>>(st->sd, skey, samp, sK, srank, S2, ne, delta,
-                                                          ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), dc,
-                                                          ptr<uint64_t>(st->nins), ptr<double>(st->nsum), mkey, mamp, mK, mrank,
-                                                          S2, mcap, a, keep, sc);
-    });
-    launch(st, "keep_scan", Work{8.0, &st->cnt_merged, 0}, [&] {
-        scan_lb<uint32_t>(st, ArraySrc<uint32_t>{keep}, ArrayOut<uint32_t>{pos}, mcap, false, lb + o_keep, tick + kTkKeep,
-                          &sc->n_out);
-    });
-    launch(st, "compact", Work{2.0 * eb + 8.0, &st->cnt_merged, 0}, [&] {
-        k_compact<W, T><<<nb_abs, kThreads, 0, s>>>(mkey, mamp, mK, mrank, S2, mcap, keep, pos,
-                                                    ptr<uint64_t>(st->skey[c]), ptr<T>(st->samp[c]), ptr<T>(st->sK[c]),
-                                                    ptr<uint64_t>(st->srank[c]), S2, delta, ptr<double>(st->abs_part), sc);
-    });
-
-    // ---- (a14) the step's statistics in one fixed-order reduction
-    const uint64_t n_parts = nb_fnc + nb_sel;
-    const uint64_t fin_blocks = std::min<uint64_t>(
-        kMaxFinalParts, std::max<uint64_t>(1, (std::max({n_parts, nblk_cap, (uint64_t)nb_abs}) + 1023) / 1024));
-    FinalPart *fin = reinterpret_cast<FinalPart *>(lb + o_fin);
-    launch(st, "final", Work{0.0, nullptr, 0}, [&] {
-        k_final_part<<<(unsigned)fin_blocks, kThreads, 0, s>>>(part, n_parts, gst, nblk_cap, ptr<double>(st->abs_part), nb_abs,
-                                                               fin);
-        k_final<<<1, kThreads, 0, s>>>(fin, fin_blocks, sc);
-    });
-
-    // ---- (a14) the one synchronisation of the step
-    HIP_TRY(hipMemcpyAsync(st->hscratch, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const Scratch scr = *st->hscratch;
-    st->last_q = scr.qtot;
-    st->cnt_slots = scr.n_slots;
-    st->cnt_rec = scr.n_live;
-    st->cnt_merged = ne + scr.n_new;
-    st->cnt_new = scr.n_new;
-    st->cnt_att = scr.n_attempts;
-    st->cnt_live_items = scr.n_slots - scr.n_attempts;
-    if (st->prof) resolve_profile(st);
-    // plan the next step's capacities from this one
-    st->slot_hint = std::max(st->slot_hint, scr.n_slots + scr.n_slots / 4 + 4096);
-    st->rec_hint = std::max(st->rec_hint, scr.n_rec + scr.n_rec / 4 + 4096);
-    if (scr.err) {
-        // the compaction did not run; clear the sums the fold may have left behind
-        if (ne) k_fill<double><<<grid_for(ne), kThreads, 0, s>>>(delta, ne, 0.0);
-        HIP_TRY(hipStreamSynchronize(s));
-        if (scr.err & kErrBlowup) {
-            st->err = "population beyond the fixed-point range of the selection weights";
-            return CCMC_EBLOWUP;
-        }
-        if (scr.err & kErrAttempts) {
-            st->err = "more than 2^30-2 spawning attempts on one cluster";
-            return CCMC_EOVERFLOW;
-        }
-        *replay = true;  // a capacity was exceeded: grow and replay
-        return CCMC_OK;
-    }
-    const uint64_t nrec = scr.n_live;
-    const double n0_old = st->n0;
-    if (scr.hf_hit) st->n0 = st->n0 + scr.hf_sum;
-    st->ne = scr.n_out;
-    st->step += 1;
-    st->last_num = scr.num;
-    st->last_den = n0_old;
-    st->last_nrec = nrec;
-    st->last_rec_buf = ids ? 1 : -1;
-    if (out) {
-        out->step = st->step;
-        out->n_selections = n_sel;
-        out->n_discarded = scr.n_discarded;
-        out->n_spawn_attempts = scr.n_attempts;
-        out->n_spawns = scr.n_spawns;
-        out->n_deaths = scr.n_deaths;
-        out->n_excitors = st->ne;
-        out->max_attempts_per_cluster = scr.max_n;
-        out->n_total = scr.n_total + std::fabs(st->n0);
-        out->n_ref = st->n0;
-        out->eproj_num = scr.num;
-        out->eproj_den = n0_old;
-    }
+    p.nb_abs = grid_for(p.mcap);
+    TRY(ensure(st, st->abs_part, (p.nb_abs + 1) * sizeof(double)));
+    p.fin_blocks = std::min<uint64_t>(
+        kMaxFinalParts, std::max<uint64_t>(1, (std::max({p.n_parts, p.nblk_cap, (uint64_t)p.nb_abs}) + 1023) / 1024));
     return CCMC_OK;
 }
 
+// The zeroed step area of one state (64-bit words): the step scalars, the scan tickets, the
+// look-back status words of every scan and radix pass (the batch's number of passes), the
+// radix histograms, the fold's tile summaries and the first stage of the final reduction.
 template <int W, typename T>
-ccmc_status step_impl(ccmc_state *st, double tau, double shift, uint64_t n_sel, ccmc_stats *out)
+ccmc_status plan_area(Plan<W, T> &p, int passes)
 {
-    for (int attempt = 0; attempt < 8; ++attempt) {
-        bool replay = false;
-        TRY(step_once<W, T>(st, tau, shift, n_sel, out, &replay));
-        if (!replay) return CCMC_OK;
+    ccmc_state *st = p.st;
+    p.passes = passes;
+    const uint64_t w_scratch = (sizeof(Scratch) + 7) / 8;
+    p.o_tick = w_scratch;
+    p.o_weights = p.o_tick + kTickets;
+    p.o_off = p.o_weights + scan_tiles(p.ne);
+    p.o_boff = p.o_off + scan_tiles(p.n_items + 1);
+    p.o_new = p.o_boff + scan_tiles(p.nblk_cap + 1);
+    p.o_keep = p.o_new + scan_tiles(p.rec_cap);
+    p.o_ghist = p.o_keep + scan_tiles(p.mcap);
+    p.o_rstat = p.o_ghist + (uint64_t)passes * kRadixBins / 2;
+    p.o_fold = p.o_rstat + (uint64_t)passes * p.tiles * kRadixBins;
+    p.o_fin = p.o_fold + 3 * p.fold_tiles;
+    p.lb_words = p.o_fin + kMaxFinalParts * (sizeof(FinalPart) / 8);
+    TRY(ensure(st, st->lb, p.lb_words * sizeof(uint64_t)));
+    p.lb = ptr<uint64_t>(st->lb);
+    p.sc = reinterpret_cast<Scratch *>(p.lb);
+    return CCMC_OK;
+}
+
+// Argument tables of a batched step: per kernel, the states' argument structs and the
+// block map, staged in host memory and copied to the device in one transfer.
+struct ArgArena {
+    std::vector<uint8_t> host;
+    size_t add(const void *src, size_t bytes)
+    {
+        const size_t off = (host.size() + 63) & ~size_t(63);
+        host.resize(off + bytes);
+        std::memcpy(host.data() + off, src, bytes);
+        return off;
     }
-    st->err = "step capacity did not converge";
-    return CCMC_ENOMEM;
+};
+
+struct LaunchRec {
+    const char *name;
+    uint32_t blocks;
+    size_t off_args, off_map;
+    uint32_t n;
+    std::vector<Work> works;
+    std::function<void(const void *, BatchMap, unsigned)> go;
+};
+
+// Stage one batched kernel: per-state arguments and block counts (states with no blocks are
+// kept in the map with an empty range).
+template <class A, class K>
+void stage(ArgArena &ar, std::vector<LaunchRec> &recs, const char *name, const std::vector<A> &args,
+           const std::vector<uint32_t> &blocks, std::vector<Work> works, K kernel)
+{
+    std::vector<uint32_t> off(blocks.size() + 1, 0);
+    for (size_t i = 0; i < blocks.size(); ++i) off[i + 1] = off[i] + blocks[i];
+    if (off.back() == 0) return;
+    LaunchRec r;
+    r.name = name;
+    r.blocks = off.back();
+    r.off_args = ar.add(args.data(), args.size() * sizeof(A));
+    r.off_map = ar.add(off.data(), off.size() * sizeof(uint32_t));
+    r.n = (uint32_t)blocks.size();
+    r.works = std::move(works);
+    r.go = [kernel](const void *a, BatchMap bm, unsigned g) { kernel(static_cast<const A *>(a), bm, g); };
+    recs.push_back(std::move(r));
+}
+
+// One attempt at a step of every state in `ps` (same words and precision), in shared
+// launches.  Sizes produced on the device (record slots, records, new determinants,
+// survivors) are never read back in the middle: kernels read them from device memory, and
+// grids cover capacities planned from each state's previous step.  If a count exceeds its
+// capacity, the overflow bit turns that state's final compaction into a no-op; the host
+// then grows its buffers and replays its step with the same Philox counters (replay[i]).
+template <int W, typename T>
+ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
+{
+    // plan every state; a state that cannot be planned (no memory, too many slots) drops out
+    // of the batch unchanged
+    std::vector<Plan<W, T>> ps;
+    std::vector<Plan<W, T> *> src;
+    for (Plan<W, T> *q : all) {
+        q->replay = false;
+        q->rc = plan_sizes<W, T>(*q);
+        if (q->rc == CCMC_OK) {
+            ps.push_back(*q);
+            src.push_back(q);
+        }
+    }
+    if (ps.empty()) return CCMC_OK;
+    const size_t n = ps.size();
+    ccmc_state *lead = ps[0].st;
+    ccmc_state *const st = lead;  // errors of the batch's HIP calls are reported on its first state
+    hipStream_t s = lead->stream;
+    int passes = 1;
+    for (auto &p : ps) passes = std::max(passes, p.passes);
+    for (size_t i = 0; i < n; ++i) {
+        src[i]->rc = plan_area<W, T>(ps[i], passes);
+        if (src[i]->rc != CCMC_OK) {  // no memory for its step area: nothing ran; the others go again
+            for (size_t j = 0; j < n; ++j)
+                if (j != i) src[j]->replay = true;
+            return CCMC_OK;
+        }
+    }
+    TRY(ensure(lead, lead->batch_scr, n * sizeof(Scratch)));
+    if (lead->batch_hcap < n) {
+        if (lead->batch_hscr) (void)hipHostFree(lead->batch_hscr);
+        lead->batch_hscr = nullptr;
+        if (hipHostMalloc((void **)&lead->batch_hscr, n * sizeof(Scratch)) != hipSuccess) {
+            lead->batch_hcap = 0;
+            lead->err = "hipHostMalloc failed";
+            return CCMC_EDEVICE;
+        }
+        lead->batch_hcap = n;
+    }
+    Scratch *scr_copy = ptr<Scratch>(lead->batch_scr);
+    const double kb = (double)(W * 8);  // bytes of one bitstring
+    const double tb = (double)sizeof(T);
+    ArgArena ar;
+    std::vector<LaunchRec> recs;
+    std::vector<uint32_t> blk(n);
+    auto works = [&](auto f) {
+        std::vector<Work> w;
+        for (auto &p : ps) w.push_back(f(p));
+        return w;
+    };
+
+    // ---- clear the step areas
+    {
+        std::vector<ClearArgs> args;
+        for (size_t i = 0; i < n; ++i) {
+            args.push_back(ClearArgs{ps[i].lb, ps[i].lb_words});
+            blk[i] = grid_for(ps[i].lb_words);
+        }
+        stage(ar, recs, "clear", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.lb_words}; }),
+              [s](const ClearArgs *a, BatchMap bm, unsigned g) { k_clear<<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    // ---- (a1) selection weights, formed inside the scan of their prefix, with the excitor-draw guide
+    {
+        using A = ScanLbArgs<uint64_t, WeightSrc<T>, WeightOut>;
+        std::vector<A> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            const WeightOut wo{ptr<uint64_t>(st->P), ptr<uint32_t>(st->guide), p.a.gcap, p.a.gsh, p.ne};
+            args.push_back(A{WeightSrc<T>{ptr<T>(st->samp[p.c]), p.sc}, wo, p.ne, 1, p.lb + p.o_weights,
+                             p.lb + p.o_tick + kTkWeights, &p.sc->qtot});
+            blk[i] = (uint32_t)scan_tiles(p.ne);
+        }
+        // bytes: amplitude read, prefix written, about two guide entries
+        stage(ar, recs, "weights_scan", args, blk, works([&](auto &p) { return Work{tb + 16.0, nullptr, p.ne}; }),
+              [s](const A *a, BatchMap bm, unsigned g) { k_scan_lb<uint64_t, WeightSrc<T>, WeightOut><<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    // ---- (a2-a5, a9, a10) items: non-composite (FNC) then sampled clusters; then the rank table
+    const double item_bytes = kb + 2 * tb + 13.0;  // key, A, death, n, level, slot count
+    auto items_of = [&](Plan<W, T> &p) {
+        ccmc_state *st = p.st;
+        return Items<T>{ptr<uint64_t>(st->ikey), ptr<T>(st->iA), ptr<T>(st->ideath), ptr<uint32_t>(st->in),
+                        ptr<uint8_t>(st->ilevel), ptr<uint64_t>(st->icnt), st->icap};
+    };
+    auto parts_of = [&](Plan<W, T> &p) {
+        ccmc_state *st = p.st;
+        return ItemPartials{ptr<double>(st->num_part), ptr<uint64_t>(st->att_part), ptr<uint64_t>(st->disc_part),
+                            ptr<uint64_t>(st->max_part)};
+    };
+    auto gen_of = [&](Plan<W, T> &p) {
+        ccmc_state *st = p.st;
+        return GenStats{ptr<uint32_t>(st->gcount), ptr<uint32_t>(st->gspawn), ptr<uint32_t>(st->gdeath)};
+    };
+    {
+        using A = ItemsArgs<W, T>;
+        std::vector<A> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            const uint64_t *srank = ptr<uint64_t>(st->srank[p.c]);
+            const RankTable rt{srank, p.ne, ptr<uint32_t>(st->rtab), st->rt_n, st->rsh};
+            args.push_back(A{st->sd, ptr<uint64_t>(st->skey[p.c]), ptr<T>(st->samp[p.c]), ptr<T>(st->sK[p.c]), st->scap,
+                             p.ne, ptr<uint64_t>(st->P), ptr<uint32_t>(st->guide), st->n0, p.a, items_of(p), p.nb_fnc,
+                             p.n_fnc, p.nb_fnc + p.nb_sel, rt, parts_of(p), p.sc});
+            blk[i] = p.nb_fnc + p.nb_sel + p.nb_rt;
+        }
+        // bytes: each item written (plus, for the non-composite ones, the store entry read)
+        stage(ar, recs, "items", args, blk, works([&](auto &p) { return Work{item_bytes, nullptr, p.n_items}; }),
+              [s](const A *a, BatchMap bm, unsigned g) { k_items<W, T><<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    {
+        using A = ScanLbArgs<uint64_t, CountSrc<uint64_t>, SlotOut>;
+        std::vector<A> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            args.push_back(A{CountSrc<uint64_t>{ptr<uint64_t>(st->icnt), p.n_items},
+                             SlotOut{ptr<uint64_t>(st->ioff), ptr<uint64_t>(st->block_item), p.slot_cap}, p.n_items + 1, 0,
+                             p.lb + p.o_off, p.lb + p.o_tick + kTkOff, &p.sc->n_slots});
+            blk[i] = (uint32_t)scan_tiles(p.n_items + 1);
+        }
+        stage(ar, recs, "slot_scan", args, blk, works([&](auto &p) { return Work{16.0, nullptr, p.n_items + 1}; }),
+              [s](const A *a, BatchMap bm, unsigned g) { k_scan_lb<uint64_t, CountSrc<uint64_t>, SlotOut><<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    // ---- (a6-a8) records: death and spawning attempts, one lane per slot, compacted per block
+    auto regions_of = [&](Plan<W, T> &p) {
+        ccmc_state *st = p.st;
+        return Records{nullptr, ptr<uint64_t>(st->rkey), st->ramp.p, ptr<uint64_t>(st->rid), st->rcap};
+    };
+    {
+        using A = GenerateArgs<W, T>;
+        std::vector<A> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            args.push_back(A{st->sd, items_of(p), ptr<uint64_t>(st->ioff), ptr<uint64_t>(st->block_item), p.n_fnc,
+                             p.n_items, p.slot_cap, p.a, regions_of(p), p.ids ? 1 : 0, gen_of(p), p.sc});
+            blk[i] = (uint32_t)p.nblk_cap;
+        }
+        // bytes: the records written and each live item read once (key, A, death, n, offset);
+        // work units: spawning attempts
+        stage(ar, recs, "generate", args, blk, works([&](auto &p) {
+                  return Work{kb + tb + (p.ids ? 8.0 : 0.0), &p.st->cnt_rec, 0, &p.st->cnt_att, kb + 2 * tb + 12.0,
+                              &p.st->cnt_live_items};
+              }),
+              [s](const A *a, BatchMap bm, unsigned g) { k_generate<W, T><<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    {
+        using A = ScanLbArgs<uint32_t, CountSrc<uint32_t>, ArrayOut<uint32_t>>;
+        std::vector<A> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            args.push_back(A{CountSrc<uint32_t>{ptr<uint32_t>(st->gcount), p.nblk_cap},
+                             ArrayOut<uint32_t>{ptr<uint32_t>(st->boff)}, p.nblk_cap + 1, 0, p.lb + p.o_boff,
+                             p.lb + p.o_tick + kTkBoff, &p.sc->n_rec});
+            blk[i] = (uint32_t)scan_tiles(p.nblk_cap + 1);
+        }
+        stage(ar, recs, "region_scan", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.nblk_cap + 1}; }),
+              [s](const A *a, BatchMap bm, unsigned g) {
+                  k_scan_lb<uint32_t, CountSrc<uint32_t>, ArrayOut<uint32_t>><<<g, kThreads, 0, s>>>(a, bm);
+              });
+    }
+    auto dense_of = [&](Plan<W, T> &p) {
+        ccmc_state *st = p.st;
+        return Records{ptr<uint64_t>(st->drank), ptr<uint64_t>(st->dkey), st->damp.p, ptr<uint64_t>(st->did), st->dcap};
+    };
+    {
+        using A = GatherArgs<W, T>;
+        std::vector<A> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            args.push_back(A{st->sd, regions_of(p), ptr<uint32_t>(st->boff), p.nblk_cap, p.rec_cap, dense_of(p),
+                             p.ids ? 1 : 0, p.sc});
+            blk[i] = grid_for(p.rec_cap);
+        }
+        stage(ar, recs, "gather", args, blk, works([&](auto &p) {
+                  return Work{2.0 * (kb + tb + (p.ids ? 8.0 : 0.0)) + 8.0, &p.st->cnt_rec, 0};
+              }),
+              [s](const A *a, BatchMap bm, unsigned g) { k_gather<W, T><<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    // ---- (a11) stable LSD radix sort of (rank, record index): one histogram launch for all
+    // passes, then one single-sweep launch per digit
+    {
+        std::vector<RadixGhistArgs> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            args.push_back(RadixGhistArgs{ptr<uint64_t>(p.st->drank), &p.sc->n_live, passes,
+                                          reinterpret_cast<uint32_t *>(p.lb + p.o_ghist)});
+            blk[i] = (uint32_t)p.tiles;
+        }
+        stage(ar, recs, "radix_ghist", args, blk, works([&](auto &p) { return Work{8.0, &p.st->cnt_rec, 0}; }),
+              [s](const RadixGhistArgs *a, BatchMap bm, unsigned g) { k_radix_ghist<<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    for (int pass = 0; pass < passes; ++pass) {
+        std::vector<RadixOnesweepArgs> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            const int ob = pass & 1;
+            const uint64_t *kin = pass == 0 ? ptr<uint64_t>(st->drank) : ptr<uint64_t>(st->sr[ob ^ 1]);
+            const uint32_t *iin = pass == 0 ? nullptr : ptr<uint32_t>(st->sidx[ob ^ 1]);
+            args.push_back(RadixOnesweepArgs{kin, iin, ptr<uint64_t>(st->sr[ob]), ptr<uint32_t>(st->sidx[ob]), &p.sc->n_live,
+                                             kRadixBits * pass,
+                                             reinterpret_cast<const uint32_t *>(p.lb + p.o_ghist) + kRadixBins * pass,
+                                             p.lb + p.o_rstat + (uint64_t)pass * p.tiles * kRadixBins,
+                                             p.lb + p.o_tick + kTkRadix + pass});
+            blk[i] = (uint32_t)p.tiles;
+        }
+        stage(ar, recs, "radix_onesweep", args, blk,
+              works([&](auto &p) { return Work{2 * 8.0 + (pass ? 8.0 : 4.0), &p.st->cnt_rec, 0}; }),
+              [s](const RadixOnesweepArgs *a, BatchMap bm, unsigned g) { k_radix_onesweep<<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    const int sorted = (passes - 1) & 1;  // buffer of the last pass
+    // ---- (a12) runs of equal determinants: fold in record order, store lookup by rank
+    auto fold_of = [&](Plan<W, T> &p) {
+        return FoldTiles{reinterpret_cast<double *>(p.lb + p.o_fold), reinterpret_cast<uint32_t *>(p.lb + p.o_fold + p.fold_tiles),
+                         p.lb + p.o_fold + 2 * p.fold_tiles};
+    };
+    {
+        using A = SegFoldArgs<T>;
+        std::vector<A> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            args.push_back(A{ptr<uint64_t>(st->sr[sorted]), ptr<uint32_t>(st->sidx[sorted]), ptr<T>(st->damp), p.rec_cap,
+                             ptr<uint64_t>(st->srank[p.c]), p.ne, ptr<double>(st->delta), ptr<uint32_t>(st->is_new),
+                             ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum), ptr<uint32_t>(st->rtab), st->rt_n, st->rsh,
+                             fold_of(p), p.sc});
+            blk[i] = (uint32_t)p.fold_tiles;
+        }
+        stage(ar, recs, "seg_fold", args, blk, works([&](auto &p) { return Work{8.0 + 4.0 + tb + 4.0, &p.st->cnt_rec, 0}; }),
+              [s](const A *a, BatchMap bm, unsigned g) { k_seg_fold<T><<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    {
+        std::vector<SegCloseArgs> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            args.push_back(SegCloseArgs{ptr<uint64_t>(st->sr[sorted]), p.fold_tiles, ptr<uint64_t>(st->srank[p.c]), p.ne,
+                                        ptr<double>(st->delta), ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum), fold_of(p),
+                                        p.sc});
+            blk[i] = grid_for(p.fold_tiles);
+        }
+        stage(ar, recs, "seg_close", args, blk, works([&](auto &p) { return Work{24.0, nullptr, p.fold_tiles}; }),
+              [s](const SegCloseArgs *a, BatchMap bm, unsigned g) { k_seg_close<<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    {
+        using A = ScanLbArgs<uint32_t, ArraySrc<uint32_t>, ArrayOut<uint32_t>>;
+        std::vector<A> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            args.push_back(A{ArraySrc<uint32_t>{ptr<uint32_t>(st->is_new)}, ArrayOut<uint32_t>{ptr<uint32_t>(st->new_pos)},
+                             p.rec_cap, 0, p.lb + p.o_new, p.lb + p.o_tick + kTkNew, &p.sc->n_new});
+            blk[i] = (uint32_t)scan_tiles(p.rec_cap);
+        }
+        stage(ar, recs, "new_scan", args, blk, works([&](auto &p) { return Work{8.0, &p.st->cnt_rec, 0}; }),
+              [s](const A *a, BatchMap bm, unsigned g) {
+                  k_scan_lb<uint32_t, ArraySrc<uint32_t>, ArrayOut<uint32_t>><<<g, kThreads, 0, s>>>(a, bm);
+              });
+    }
+    {
+        using A = NewCompactArgs<W>;
+        std::vector<A> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            args.push_back(A{ptr<uint64_t>(st->sr[sorted]), ptr<uint32_t>(st->sidx[sorted]), ptr<uint64_t>(st->dkey), st->dcap,
+                             p.rec_cap, ptr<uint32_t>(st->is_new), ptr<uint32_t>(st->new_pos), ptr<uint64_t>(st->ins),
+                             ptr<double>(st->seg_sum), ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), st->dcap,
+                             ptr<uint64_t>(st->nins), ptr<double>(st->nsum), p.sc});
+            blk[i] = grid_for(p.rec_cap);
+        }
+        stage(ar, recs, "new_compact", args, blk, works([&](auto &p) { return Work{2.0 * (kb + 24.0) + 8.0, &p.st->cnt_new, 0}; }),
+              [s](const A *a, BatchMap bm, unsigned g) { k_new_compact<W><<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    // ---- (a12, a13) merge and round into the other store buffer, compact back into this one
+    const double eb = kb + 2 * tb + 8.0;  // one store entry: key, amplitude, diagonal, rank
+    {
+        using A = MergeArgs<W, T>;
+        std::vector<A> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            const int m = 1 - p.c;
+            args.push_back(A{st->sd, ptr<uint64_t>(st->skey[p.c]), ptr<T>(st->samp[p.c]), ptr<T>(st->sK[p.c]),
+                             ptr<uint64_t>(st->srank[p.c]), st->scap, p.ne, ptr<double>(st->delta), ptr<uint64_t>(st->nkey),
+                             ptr<uint64_t>(st->nrank), st->dcap, ptr<uint64_t>(st->nins), ptr<double>(st->nsum),
+                             ptr<uint64_t>(st->skey[m]), ptr<T>(st->samp[m]), ptr<T>(st->sK[m]), ptr<uint64_t>(st->srank[m]),
+                             st->scap, p.mcap, p.a, ptr<uint32_t>(st->keep), p.sc});
+            blk[i] = grid_for(p.mcap);
+        }
+        stage(ar, recs, "merge", args, blk, works([&](auto &p) { return Work{2.0 * eb + 12.0, &p.st->cnt_merged, 0}; }),
+              [s](const A *a, BatchMap bm, unsigned g) { k_merge<W, T><<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    {
+        using A = ScanLbArgs<uint32_t, ArraySrc<uint32_t>, ArrayOut<uint32_t>>;
+        std::vector<A> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            args.push_back(A{ArraySrc<uint32_t>{ptr<uint32_t>(st->keep)}, ArrayOut<uint32_t>{ptr<uint32_t>(st->pos)}, p.mcap, 0,
+                             p.lb + p.o_keep, p.lb + p.o_tick + kTkKeep, &p.sc->n_out});
+            blk[i] = (uint32_t)scan_tiles(p.mcap);
+        }
+        stage(ar, recs, "keep_scan", args, blk, works([&](auto &p) { return Work{8.0, &p.st->cnt_merged, 0}; }),
+              [s](const A *a, BatchMap bm, unsigned g) {
+                  k_scan_lb<uint32_t, ArraySrc<uint32_t>, ArrayOut<uint32_t>><<<g, kThreads, 0, s>>>(a, bm);
+              });
+    }
+    {
+        using A = CompactArgs<W, T>;
+        std::vector<A> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            const int m = 1 - p.c;
+            args.push_back(A{ptr<uint64_t>(st->skey[m]), ptr<T>(st->samp[m]), ptr<T>(st->sK[m]), ptr<uint64_t>(st->srank[m]),
+                             st->scap, p.mcap, ptr<uint32_t>(st->keep), ptr<uint32_t>(st->pos), ptr<uint64_t>(st->skey[p.c]),
+                             ptr<T>(st->samp[p.c]), ptr<T>(st->sK[p.c]), ptr<uint64_t>(st->srank[p.c]), st->scap,
+                             ptr<double>(st->delta), ptr<double>(st->abs_part), p.sc});
+            blk[i] = p.nb_abs;
+        }
+        stage(ar, recs, "compact", args, blk, works([&](auto &p) { return Work{2.0 * eb + 8.0, &p.st->cnt_merged, 0}; }),
+              [s](const A *a, BatchMap bm, unsigned g) { k_compact<W, T><<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    // ---- (a14) the step's statistics in a fixed-order two-stage reduction
+    {
+        std::vector<FinalPartArgs> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            args.push_back(FinalPartArgs{parts_of(p), p.n_parts, gen_of(p), p.nblk_cap, ptr<double>(p.st->abs_part), p.nb_abs,
+                                         reinterpret_cast<FinalPart *>(p.lb + p.o_fin)});
+            blk[i] = (uint32_t)p.fin_blocks;
+        }
+        stage(ar, recs, "final", args, blk, works([&](auto &) { return Work{0.0, nullptr, 0}; }),
+              [s](const FinalPartArgs *a, BatchMap bm, unsigned g) { k_final_part<<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    {
+        std::vector<FinalArgs> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            args.push_back(FinalArgs{reinterpret_cast<const FinalPart *>(p.lb + p.o_fin), p.fin_blocks, p.sc, scr_copy + i});
+            blk[i] = 1;
+        }
+        stage(ar, recs, "final", args, blk, works([&](auto &) { return Work{0.0, nullptr, 0}; }),
+              [s](const FinalArgs *a, BatchMap bm, unsigned g) { k_final<<<g, kThreads, 0, s>>>(a, bm); });
+    }
+
+    // ---- the argument tables: one copy, then the launches in order
+    TRY(ensure(lead, lead->arg_dev, ar.host.size()));
+    if (lead->arg_hcap < ar.host.size()) {
+        if (lead->arg_host) (void)hipHostFree(lead->arg_host);
+        lead->arg_host = nullptr;
+        const size_t cap = ar.host.size() + ar.host.size() / 2 + 4096;
+        if (hipHostMalloc((void **)&lead->arg_host, cap) != hipSuccess) {
+            lead->arg_hcap = 0;
+            lead->err = "hipHostMalloc failed";
+            return CCMC_EDEVICE;
+        }
+        lead->arg_hcap = cap;
+    }
+    std::memcpy(lead->arg_host, ar.host.data(), ar.host.size());
+    HIP_TRY(hipMemcpyAsync(lead->arg_dev.p, lead->arg_host, ar.host.size(), hipMemcpyHostToDevice, s));
+    const uint8_t *dev = static_cast<const uint8_t *>(lead->arg_dev.p);
+    for (auto &r : recs) {
+        const BatchMap bm{reinterpret_cast<const uint32_t *>(dev + r.off_map), r.n};
+        launch(lead, r.name, r.works, [&] { r.go(dev + r.off_args, bm, r.blocks); });
+    }
+
+    // ---- (a14) the one synchronisation of the step
+    HIP_TRY(hipMemcpyAsync(lead->batch_hscr, scr_copy, n * sizeof(Scratch), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (size_t i = 0; i < n; ++i) {
+        auto &p = ps[i];
+        ccmc_state *st = p.st;
+        const Scratch scr = lead->batch_hscr[i];
+        st->last_q = scr.qtot;
+        st->cnt_slots = scr.n_slots;
+        st->cnt_rec = scr.n_live;
+        st->cnt_merged = p.ne + scr.n_new;
+        st->cnt_new = scr.n_new;
+        st->cnt_att = scr.n_attempts;
+        st->cnt_live_items = scr.n_slots - scr.n_attempts;
+        // plan the next step's capacities from this one
+        st->slot_hint = std::max(st->slot_hint, scr.n_slots + scr.n_slots / 4 + 4096);
+        st->rec_hint = std::max(st->rec_hint, scr.n_rec + scr.n_rec / 4 + 4096);
+        if (scr.err) {
+            // the compaction did not run; clear the sums the fold may have left behind
+            if (p.ne) k_fill<double><<<grid_for(p.ne), kThreads, 0, s>>>(ptr<double>(st->delta), p.ne, 0.0);
+            HIP_TRY(hipStreamSynchronize(s));
+            if (scr.err & kErrBlowup) {
+                st->err = "population beyond the fixed-point range of the selection weights";
+                src[i]->rc = CCMC_EBLOWUP;
+            } else if (scr.err & kErrAttempts) {
+                st->err = "more than 2^30-2 spawning attempts on one cluster";
+                src[i]->rc = CCMC_EOVERFLOW;
+            } else {
+                src[i]->replay = true;  // a capacity was exceeded: grow and replay
+            }
+            continue;
+        }
+        const double n0_old = st->n0;
+        if (scr.hf_hit) st->n0 = st->n0 + scr.hf_sum;
+        st->ne = scr.n_out;
+        st->step += 1;
+        st->last_num = scr.num;
+        st->last_den = n0_old;
+        st->last_nrec = scr.n_live;
+        st->last_rec_buf = p.ids ? 1 : -1;
+        if (p.out) {
+            ccmc_stats *out = p.out;
+            out->step = st->step;
+            out->n_selections = p.n_sel;
+            out->n_discarded = scr.n_discarded;
+            out->n_spawn_attempts = scr.n_attempts;
+            out->n_spawns = scr.n_spawns;
+            out->n_deaths = scr.n_deaths;
+            out->n_excitors = st->ne;
+            out->max_attempts_per_cluster = scr.max_n;
+            out->n_total = scr.n_total + std::fabs(st->n0);
+            out->n_ref = st->n0;
+            out->eproj_num = scr.num;
+            out->eproj_den = n0_old;
+        }
+    }
+    if (lead->prof) resolve_profile(lead);
+    return CCMC_OK;
+}
+
+// Steps of several states (same words and precision) in shared launches; a state whose
+// capacities overflowed steps again, with the others that did, after growing.  A state whose
+// step fails is left unchanged with its error text set; the others complete their step.  The
+// first failure's status is returned.
+template <int W, typename T>
+ccmc_status step_impl(ccmc_state *const *sts, size_t n, const double *tau, const double *shift, const uint64_t *n_sel,
+                      ccmc_stats *const *outs)
+{
+    std::vector<Plan<W, T>> ps(n);
+    std::vector<Plan<W, T> *> live;
+    for (size_t i = 0; i < n; ++i) {
+        ps[i].st = sts[i];
+        ps[i].tau = tau[i];
+        ps[i].shift = shift[i];
+        ps[i].n_sel = n_sel[i];
+        ps[i].out = outs ? outs[i] : nullptr;
+        live.push_back(&ps[i]);
+    }
+    for (int attempt = 0; !live.empty(); ++attempt) {
+        if (attempt == 8) {
+            for (auto *p : live) {
+                p->st->err = "step capacity did not converge";
+                p->rc = CCMC_ENOMEM;
+            }
+            break;
+        }
+        TRY(step_batch_once<W, T>(live));
+        std::vector<Plan<W, T> *> again;
+        for (auto *p : live)
+            if (p->rc == CCMC_OK && p->replay) again.push_back(p);
+        live.swap(again);
+    }
+    for (auto &p : ps)
+        if (p.rc != CCMC_OK) return p.rc;
+    return CCMC_OK;
 }
 
 template <int W, typename T>
@@ -994,9 +1318,10 @@ ccmc_status dispatch(const ccmc_state *st, Args... args)
 
 template <int W, typename T>
 struct StepF {
-    static ccmc_status run(ccmc_state *st, double tau, double shift, uint64_t n, ccmc_stats *out)
+    static ccmc_status run(ccmc_state *const *sts, size_t n, const double *tau, const double *shift, const uint64_t *n_sel,
+                           ccmc_stats *const *outs)
     {
-        return step_impl<W, T>(st, tau, shift, n, out);
+        return step_impl<W, T>(sts, n, tau, shift, n_sel, outs);
     }
 };
 template <int W, typename T>
@@ -1037,14 +1362,15 @@ void destroy(ccmc_state *st)
                       &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->boff, &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
                       &st->sidx[0], &st->sidx[1], &st->is_new,
                       &st->new_pos, &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->keep,
-                      &st->pos, &st->lb};
+                      &st->pos, &st->lb, &st->arg_dev, &st->batch_scr};
     for (DevBuf *b : bufs) release(st, *b);
     for (auto &p : st->pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
     }
     for (auto e : st->ev_pool) (void)hipEventDestroy(e);
-    if (st->hscratch) (void)hipHostFree(st->hscratch);
+    if (st->arg_host) (void)hipHostFree(st->arg_host);
+    if (st->batch_hscr) (void)hipHostFree(st->batch_hscr);
     if (st->own_stream && st->stream) (void)hipStreamDestroy(st->stream);
     delete st;
 }
@@ -1126,10 +1452,6 @@ ccmc_status ccmc_init(const ccmc_system *sys, const ccmc_integrals *ints, int tr
         st->own_stream = true;
     }
     ccmc_status rc = CCMC_OK;
-    if (hipHostMalloc((void **)&st->hscratch, sizeof(Scratch)) != hipSuccess) {
-        st->err = "hipHostMalloc failed";
-        rc = CCMC_EDEVICE;
-    }
     if (rc == CCMC_OK) rc = dispatch<SystemF>(st, st, ints);
     if (rc == CCMC_OK) rc = dispatch<StoreF>(st, st, (uint64_t)1024);
     if (rc != CCMC_OK) {
@@ -1154,7 +1476,64 @@ ccmc_status ccmc_step(ccmc_state *st, double tau, double shift, uint64_t n_attem
         st->err = "ccmc_step: store too large for 32-bit item indices";
         return CCMC_EOVERFLOW;
     }
-    return dispatch<StepF>(st, st, tau, shift, n_attempts, out);
+    ccmc_state *const sts[1] = {st};
+    ccmc_stats *const outs[1] = {out};
+    return dispatch<StepF>(st, sts, (size_t)1, &tau, &shift, &n_attempts, outs);
+}
+
+ccmc_status ccmc_step_batch(ccmc_state *const *states, int n, const double *tau, const double *shift,
+                            const uint64_t *n_attempts, ccmc_stats *out)
+{
+    if (n < 0 || (n > 0 && (!states || !tau || !shift || !n_attempts))) return CCMC_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        ccmc_state *st = states[i];
+        if (!st) return CCMC_EINVAL;
+        st->err.clear();
+        for (int j = 0; j < i; ++j)
+            if (states[j] == st) {
+                st->err = "ccmc_step_batch: a state appears twice";
+                return CCMC_EINVAL;
+            }
+        if (!(tau[i] > 0) || !std::isfinite(tau[i]) || !std::isfinite(shift[i]) || n_attempts[i] > 0xFFFFFFFFull) {
+            st->err = "ccmc_step_batch: need tau > 0, finite shift and n_attempts < 2^32";
+            return CCMC_EINVAL;
+        }
+        if (st->ne + 1 > 0xFFFFFFFFull) {
+            st->err = "ccmc_step_batch: store too large for 32-bit item indices";
+            return CCMC_EOVERFLOW;
+        }
+    }
+    // one batch per (words, precision); each runs on the stream of its first state, after the
+    // work already queued on the others' streams
+    std::vector<char> done(n, 0);
+    ccmc_status rc = CCMC_OK;
+    for (int i = 0; i < n; ++i) {
+        if (done[i]) continue;
+        std::vector<ccmc_state *> g;
+        std::vector<double> gt, gs;
+        std::vector<uint64_t> ga;
+        std::vector<ccmc_stats *> go;
+        for (int j = i; j < n; ++j) {
+            if (done[j] || states[j]->WP != states[i]->WP || states[j]->fp32 != states[i]->fp32) continue;
+            done[j] = 1;
+            g.push_back(states[j]);
+            gt.push_back(tau[j]);
+            gs.push_back(shift[j]);
+            ga.push_back(n_attempts[j]);
+            go.push_back(out ? out + j : nullptr);
+        }
+        for (size_t k = 1; k < g.size(); ++k) {
+            if (g[k]->stream == g[0]->stream) continue;
+            hipEvent_t ev;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return CCMC_EDEVICE;
+            (void)hipEventRecord(ev, g[k]->stream);
+            (void)hipStreamWaitEvent(g[0]->stream, ev, 0);
+            (void)hipEventDestroy(ev);
+        }
+        const ccmc_status r = dispatch<StepF>(g[0], g.data(), g.size(), gt.data(), gs.data(), ga.data(), go.data());
+        if (r != CCMC_OK && rc == CCMC_OK) rc = r;
+    }
+    return rc;
 }
 
 ccmc_status ccmc_energy(const ccmc_state *st, double *e_hf, double *eproj_num, double *eproj_den)

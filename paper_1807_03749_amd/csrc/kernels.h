@@ -409,26 +409,55 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
 // [nb_fnc, nb_items) the sampled clusters (selection k = (block - nb_fnc) * 256 + thread), and
 // the blocks after them build the store's rank table.
 template <int W, typename T>
-__global__ void __launch_bounds__(kThreads) k_items(SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
+__device__ __forceinline__ void items_body(uint32_t blk, uint32_t nblk, SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
                                                     const T *__restrict__ sK, uint64_t sstride, uint64_t ne,
                                                     const uint64_t *__restrict__ P, const uint32_t *__restrict__ guide,
                                                     double n0, StepArgs a, Items<T> it, unsigned nb_fnc, uint64_t n_fnc,
                                                     unsigned nb_items, RankTable rt, ItemPartials part, Scratch *sc)
 {
-    if (blockIdx.x >= nb_items) {  // trailing blocks: the rank table for the annihilation
-        rank_table_block(blockIdx.x - nb_items, rt);
+    if (blk >= nb_items) {  // trailing blocks: the rank table for the annihilation
+        rank_table_block(blk - nb_items, rt);
         return;
     }
     // a prefix beyond 2^53 makes the selection probabilities inexact: refuse the step
-    if (blockIdx.x == 0 && threadIdx.x == 0 && sc->qtot > (1ull << 53))
+    if (blk == 0 && threadIdx.x == 0 && sc->qtot > (1ull << 53))
         atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrBlowup);
-    if (blockIdx.x < nb_fnc) {
-        noncomposite_block<W, T>(blockIdx.x, S, skey, samp, sK, sstride, ne, n0, a, it, part, sc);
+    if (blk < nb_fnc) {
+        noncomposite_block<W, T>(blk, S, skey, samp, sK, sstride, ne, n0, a, it, part, sc);
     } else {
-        const unsigned b = blockIdx.x - nb_fnc;
+        const unsigned b = blk - nb_fnc;
         ItemPartials ps{part.num + nb_fnc, part.att + nb_fnc, part.disc + nb_fnc, part.maxn + nb_fnc};
         select_block<W, T>(b, S, skey, samp, sstride, ne, P, guide, n0, a, it, n_fnc, ps, sc);
     }
+}
+
+template <int W, typename T>
+struct ItemsArgs {
+    SysDev S;
+    const uint64_t *skey;
+    const T *samp;
+    const T *sK;
+    uint64_t sstride;
+    uint64_t ne;
+    const uint64_t *P;
+    const uint32_t *guide;
+    double n0;
+    StepArgs a;
+    Items<T> it;
+    unsigned nb_fnc;
+    uint64_t n_fnc;
+    unsigned nb_items;
+    RankTable rt;
+    ItemPartials part;
+    Scratch *sc;
+};
+
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_items(const ItemsArgs<W, T> *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const ItemsArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
+    items_body<W, T>(blk, nblk, A.S, A.skey, A.samp, A.sK, A.sstride, A.ne, A.P, A.guide, A.n0, A.a, A.it, A.nb_fnc, A.n_fnc, A.nb_items, A.rt, A.part, A.sc);
 }
 
 // ----------------------------------------------------------------- generation
@@ -552,7 +581,7 @@ struct GenStats {
 };
 
 template <int W, typename T>
-__global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, const uint64_t *__restrict__ off,
+__device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDev S, Items<T> it, const uint64_t *__restrict__ off,
                                                        const uint64_t *__restrict__ block_item, uint64_t n_fnc,
                                                        uint64_t n_items, uint64_t slot_cap, StepArgs a, Records rec,
                                                        int keep_ids, GenStats gs, Scratch *sc)
@@ -560,21 +589,21 @@ __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, co
     __shared__ uint64_t s_off[kGenLdsItems + 1];
     __shared__ uint32_t wave_tot[kWaves];
     T *ramp = static_cast<T *>(rec.amp);
-    const uint64_t g0 = (uint64_t)blockIdx.x * kGenSlots;
+    const uint64_t g0 = (uint64_t)blk * kGenSlots;
     const uint64_t n_all = off[n_items];
     const uint64_t n_slots = n_all < slot_cap ? n_all : slot_cap;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        gs.count[gridDim.x] = 0;  // closing entry of the scan
+    if (blk == 0 && threadIdx.x == 0) {
+        gs.count[nblk] = 0;  // closing entry of the scan
         if (n_all > slot_cap) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrSlotCap);
     }
     if (g0 >= n_slots) {  // idle block (the grid covers the capacity)
-        if (threadIdx.x == 0) gs.count[blockIdx.x] = gs.spawns[blockIdx.x] = gs.deaths[blockIdx.x] = 0;
+        if (threadIdx.x == 0) gs.count[blk] = gs.spawns[blk] = gs.deaths[blk] = 0;
         return;
     }
     // items of this block: from the one holding its first slot to the one holding the next
     // block's first slot (for the last block: every remaining item)
-    const uint64_t lo = block_item[blockIdx.x];
-    const uint64_t hi = g0 + kGenSlots < n_slots ? block_item[blockIdx.x + 1] : n_items - 1;
+    const uint64_t lo = block_item[blk];
+    const uint64_t hi = g0 + kGenSlots < n_slots ? block_item[blk + 1] : n_items - 1;
     const bool lds = hi - lo + 1 <= (uint64_t)kGenLdsItems;
     if (lds)
         for (uint64_t t = threadIdx.x; t <= hi - lo + 1; t += kThreads) s_off[t] = off[lo + t];
@@ -653,19 +682,43 @@ __global__ void __launch_bounds__(kThreads) k_generate(SysDev S, Items<T> it, co
     const uint32_t bs = block_reduce_sum(spawns);
     const uint32_t bd = block_reduce_sum(deaths);
     if (threadIdx.x == 0) {
-        gs.count[blockIdx.x] = base;
-        gs.spawns[blockIdx.x] = bs;
-        gs.deaths[blockIdx.x] = bd;
+        gs.count[blk] = base;
+        gs.spawns[blk] = bs;
+        gs.deaths[blk] = bd;
     }
+}
+
+template <int W, typename T>
+struct GenerateArgs {
+    SysDev S;
+    Items<T> it;
+    const uint64_t *off;
+    const uint64_t *block_item;
+    uint64_t n_fnc;
+    uint64_t n_items;
+    uint64_t slot_cap;
+    StepArgs a;
+    Records rec;
+    int keep_ids;
+    GenStats gs;
+    Scratch *sc;
+};
+
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_generate(const GenerateArgs<W, T> *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const GenerateArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
+    generate_body<W, T>(blk, nblk, A.S, A.it, A.off, A.block_item, A.n_fnc, A.n_items, A.slot_cap, A.a, A.rec, A.keep_ids, A.gs, A.sc);
 }
 
 // Dense layout of the records: output position r comes from the block b with
 // boff[b] <= r < boff[b+1], at slot position r - boff[b] of its region.
 template <int W, typename T>
-__global__ void __launch_bounds__(kThreads) k_gather(const SysDev S, Records reg, const uint32_t *__restrict__ boff,
+__device__ __forceinline__ void gather_body(uint32_t blk, uint32_t nblk, const SysDev S, Records reg, const uint32_t *__restrict__ boff,
                                                      uint64_t n_blocks, uint64_t rec_cap, Records out, int keep_ids, Scratch *sc)
 {
-    const uint64_t r = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint64_t r = (uint64_t)blk * kThreads + threadIdx.x;
     // records the annihilation works on: all of them, or none after a capacity overflow
     const uint64_t nr = sc->n_rec;
     const bool over = nr > rec_cap || (sc->err & kErrSlotCap);
@@ -696,6 +749,26 @@ __global__ void __launch_bounds__(kThreads) k_gather(const SysDev S, Records reg
     if (keep_ids) out.id[r] = reg.id[src];
 }
 
+template <int W, typename T>
+struct GatherArgs {
+    const SysDev S;
+    Records reg;
+    const uint32_t *boff;
+    uint64_t n_blocks;
+    uint64_t rec_cap;
+    Records out;
+    int keep_ids;
+    Scratch *sc;
+};
+
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_gather(const GatherArgs<W, T> *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const GatherArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
+    gather_body<W, T>(blk, nblk, A.S, A.reg, A.boff, A.n_blocks, A.rec_cap, A.out, A.keep_ids, A.sc);
+}
+
 // ---------------------------------------------------------------- annihilation
 // Records are sorted by rank (equal ranks = equal determinants, ascending rank = ascending
 // key) and, within a determinant, by record id (the sort is stable).  The contributions to a
@@ -717,7 +790,7 @@ struct FoldTiles {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_seg_fold(const uint64_t *__restrict__ rank, const uint32_t *__restrict__ idx,
+__device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ rank, const uint32_t *__restrict__ idx,
                                                        const T *__restrict__ ramp, uint64_t cap,
                                                        const uint64_t *__restrict__ srank, uint64_t ne,
                                                        double *__restrict__ delta, uint32_t *__restrict__ is_new,
@@ -729,7 +802,7 @@ __global__ void __launch_bounds__(kThreads) k_seg_fold(const uint64_t *__restric
     __shared__ uint32_t s_head[kThreads];
     __shared__ uint64_t s_open;
     const uint64_t n = sc->n_live;
-    const uint64_t base = (uint64_t)blockIdx.x * kFoldTile;
+    const uint64_t base = (uint64_t)blk * kFoldTile;
     const uint64_t r0 = base + (uint64_t)threadIdx.x * kFoldItems;
     // is_new covers the whole capacity, so that its scan needs no live count
 #pragma unroll
@@ -737,9 +810,9 @@ __global__ void __launch_bounds__(kThreads) k_seg_fold(const uint64_t *__restric
         if (r0 + i < cap) is_new[r0 + i] = 0;
     if (base >= n) {
         if (threadIdx.x == 0) {
-            ft.lead[blockIdx.x] = 0.0;
-            ft.has_head[blockIdx.x] = 0;
-            ft.open[blockIdx.x] = kNoOpen;
+            ft.lead[blk] = 0.0;
+            ft.has_head[blk] = 0;
+            ft.open[blk] = kNoOpen;
         }
         return;
     }
@@ -868,20 +941,47 @@ __global__ void __launch_bounds__(kThreads) k_seg_fold(const uint64_t *__restric
                 break;
             }
         }
-        ft.lead[blockIdx.x] = tl;
-        ft.has_head[blockIdx.x] = hh;
-        ft.open[blockIdx.x] = s_open;
+        ft.lead[blk] = tl;
+        ft.has_head[blk] = hh;
+        ft.open[blk] = s_open;
     }
+}
+
+template <typename T>
+struct SegFoldArgs {
+    const uint64_t *rank;
+    const uint32_t *idx;
+    const T *ramp;
+    uint64_t cap;
+    const uint64_t *srank;
+    uint64_t ne;
+    double *delta;
+    uint32_t *is_new;
+    uint64_t *ins;
+    double *seg_sum;
+    const uint32_t *rtab;
+    uint64_t rt_n;
+    uint32_t rsh;
+    FoldTiles ft;
+    Scratch *sc;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_seg_fold(const SegFoldArgs<T> *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const SegFoldArgs<T> &A = args[batch_state(bm, blk, nblk)];
+    seg_fold_body<T>(blk, nblk, A.rank, A.idx, A.ramp, A.cap, A.srank, A.ne, A.delta, A.is_new, A.ins, A.seg_sum, A.rtab, A.rt_n, A.rsh, A.ft, A.sc);
 }
 
 // Finish the open runs: add the leading pieces of the following tiles until one holds a head.
 // One lane per tile.
-__global__ void __launch_bounds__(kThreads) k_seg_close(const uint64_t *__restrict__ rank, uint64_t n_tiles,
+__device__ __forceinline__ void seg_close_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ rank, uint64_t n_tiles,
                                                         const uint64_t *__restrict__ srank, uint64_t ne,
                                                         double *__restrict__ delta, const uint64_t *__restrict__ ins,
                                                         double *__restrict__ seg_sum, FoldTiles ft, Scratch *sc)
 {
-    const uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint64_t t = (uint64_t)blk * kThreads + threadIdx.x;
     if (t >= n_tiles) return;
     const uint64_t r = ft.open[t];
     if (r == kNoOpen) return;
@@ -901,8 +1001,27 @@ __global__ void __launch_bounds__(kThreads) k_seg_close(const uint64_t *__restri
     }
 }
 
+struct SegCloseArgs {
+    const uint64_t *rank;
+    uint64_t n_tiles;
+    const uint64_t *srank;
+    uint64_t ne;
+    double *delta;
+    const uint64_t *ins;
+    double *seg_sum;
+    FoldTiles ft;
+    Scratch *sc;
+};
+
+__global__ void __launch_bounds__(kThreads) k_seg_close(const SegCloseArgs *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const SegCloseArgs &A = args[batch_state(bm, blk, nblk)];
+    seg_close_body(blk, nblk, A.rank, A.n_tiles, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.ft, A.sc);
+}
+
 template <int W>
-__global__ void __launch_bounds__(kThreads) k_new_compact(const uint64_t *__restrict__ rank, const uint32_t *__restrict__ idx,
+__device__ __forceinline__ void new_compact_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ rank, const uint32_t *__restrict__ idx,
                                                           const uint64_t *__restrict__ rkey, uint64_t rstride, uint64_t cap,
                                                           const uint32_t *__restrict__ is_new,
                                                           const uint32_t *__restrict__ new_pos, const uint64_t *__restrict__ ins,
@@ -910,7 +1029,7 @@ __global__ void __launch_bounds__(kThreads) k_new_compact(const uint64_t *__rest
                                                           uint64_t *__restrict__ nrank, uint64_t nstride,
                                                           uint64_t *__restrict__ nins, double *__restrict__ nsum, Scratch *sc)
 {
-    const uint64_t r = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint64_t r = (uint64_t)blk * kThreads + threadIdx.x;
     if (r >= cap) return;
     if (!is_new[r]) return;
     const uint32_t j = new_pos[r];
@@ -922,13 +1041,40 @@ __global__ void __launch_bounds__(kThreads) k_new_compact(const uint64_t *__rest
     nsum[j] = seg_sum[r];
 }
 
+template <int W>
+struct NewCompactArgs {
+    const uint64_t *rank;
+    const uint32_t *idx;
+    const uint64_t *rkey;
+    uint64_t rstride;
+    uint64_t cap;
+    const uint32_t *is_new;
+    const uint32_t *new_pos;
+    const uint64_t *ins;
+    const double *seg_sum;
+    uint64_t *nkey;
+    uint64_t *nrank;
+    uint64_t nstride;
+    uint64_t *nins;
+    double *nsum;
+    Scratch *sc;
+};
+
+template <int W>
+__global__ void __launch_bounds__(kThreads) k_new_compact(const NewCompactArgs<W> *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const NewCompactArgs<W> &A = args[batch_state(bm, blk, nblk)];
+    new_compact_body<W>(blk, nblk, A.rank, A.idx, A.rkey, A.rstride, A.cap, A.is_new, A.new_pos, A.ins, A.seg_sum, A.nkey, A.nrank, A.nstride, A.nins, A.nsum, A.sc);
+}
+
 // Merge the store (with its sums added) and the new determinants into key order, then
 // apply real-weight occupation rounding at each merged position k: 0 < |N| < theta becomes
 // +-theta with probability |N| / theta, else 0, from a Philox draw keyed by k (the reference
 // is exempt).  Store entry i lands at i + #(new with ins <= i); new entry j at ins_j + j.
 // Positions beyond the merged size (up to the capacity) get keep = 0.
 template <int W, typename T>
-__global__ void __launch_bounds__(kThreads) k_merge(const SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
+__device__ __forceinline__ void merge_body(uint32_t blk, uint32_t nblk, const SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
                                                     const T *__restrict__ sK, const uint64_t *__restrict__ srank,
                                                     uint64_t sstride, uint64_t ne, const double *__restrict__ delta,
                                                     const uint64_t *__restrict__ nkey, const uint64_t *__restrict__ nrank,
@@ -938,7 +1084,7 @@ __global__ void __launch_bounds__(kThreads) k_merge(const SysDev S, const uint64
                                                     uint64_t mstride, uint64_t cap, StepArgs a, uint32_t *__restrict__ keep,
                                                     Scratch *sc)
 {
-    const uint64_t t = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint64_t t = (uint64_t)blk * kThreads + threadIdx.x;
     const uint64_t nn = sc->n_new;
     if (t >= cap) return;
     if (t >= ne + nn) {
@@ -984,11 +1130,45 @@ __global__ void __launch_bounds__(kThreads) k_merge(const SysDev S, const uint64
     keep[pos] = (v != T(0)) ? 1u : 0u;
 }
 
+template <int W, typename T>
+struct MergeArgs {
+    const SysDev S;
+    const uint64_t *skey;
+    const T *samp;
+    const T *sK;
+    const uint64_t *srank;
+    uint64_t sstride;
+    uint64_t ne;
+    const double *delta;
+    const uint64_t *nkey;
+    const uint64_t *nrank;
+    uint64_t nstride;
+    const uint64_t *nins;
+    const double *nsum;
+    uint64_t *mkey;
+    T *mamp;
+    T *mK;
+    uint64_t *mrank;
+    uint64_t mstride;
+    uint64_t cap;
+    StepArgs a;
+    uint32_t *keep;
+    Scratch *sc;
+};
+
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_merge(const MergeArgs<W, T> *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const MergeArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
+    merge_body<W, T>(blk, nblk, A.S, A.skey, A.samp, A.sK, A.srank, A.sstride, A.ne, A.delta, A.nkey, A.nrank, A.nstride, A.nins, A.nsum, A.mkey, A.mamp, A.mK, A.mrank, A.mstride, A.cap, A.a, A.keep, A.sc);
+}
+
 // Compaction of the merged store back into the current buffer (the only write to the
 // state; skipped after any error, so that a failed step leaves the state unchanged).  The
 // per-entry sum buffer of the next step is cleared on the way.
 template <int W, typename T>
-__global__ void __launch_bounds__(kThreads) k_compact(const uint64_t *__restrict__ mkey, const T *__restrict__ mamp,
+__device__ __forceinline__ void compact_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ mkey, const T *__restrict__ mamp,
                                                       const T *__restrict__ mK, const uint64_t *__restrict__ mrank,
                                                       uint64_t mstride, uint64_t cap, const uint32_t *__restrict__ keep,
                                                       const uint32_t *__restrict__ pos, uint64_t *__restrict__ okey,
@@ -996,7 +1176,7 @@ __global__ void __launch_bounds__(kThreads) k_compact(const uint64_t *__restrict
                                                       uint64_t ostride, double *__restrict__ delta,
                                                       double *__restrict__ abs_part, Scratch *sc)
 {
-    const uint64_t k = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint64_t k = (uint64_t)blk * kThreads + threadIdx.x;
     const bool ok = sc->err == 0;
     double a = 0.0;
     if (ok && k < cap && keep[k]) {
@@ -1010,7 +1190,35 @@ __global__ void __launch_bounds__(kThreads) k_compact(const uint64_t *__restrict
         a = fabs((double)mamp[k]);
     }
     a = block_reduce_sum(a);
-    if (threadIdx.x == 0) abs_part[blockIdx.x] = a;
+    if (threadIdx.x == 0) abs_part[blk] = a;
+}
+
+template <int W, typename T>
+struct CompactArgs {
+    const uint64_t *mkey;
+    const T *mamp;
+    const T *mK;
+    const uint64_t *mrank;
+    uint64_t mstride;
+    uint64_t cap;
+    const uint32_t *keep;
+    const uint32_t *pos;
+    uint64_t *okey;
+    T *oamp;
+    T *oK;
+    uint64_t *orank;
+    uint64_t ostride;
+    double *delta;
+    double *abs_part;
+    Scratch *sc;
+};
+
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_compact(const CompactArgs<W, T> *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const CompactArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
+    compact_body<W, T>(blk, nblk, A.mkey, A.mamp, A.mK, A.mrank, A.mstride, A.cap, A.keep, A.pos, A.okey, A.oamp, A.oK, A.orank, A.ostride, A.delta, A.abs_part, A.sc);
 }
 
 // The step's statistics in a fixed-order two-stage reduction: block b of k_final_part sums
@@ -1022,14 +1230,14 @@ struct FinalPart {
     uint64_t att, disc, mx, sp, de, pad;
 };
 
-__device__ __forceinline__ void chunk_of(uint64_t n, uint64_t g, uint64_t &lo, uint64_t &hi)
+__device__ __forceinline__ void chunk_of(uint64_t n, uint64_t g, uint64_t nb, uint64_t &lo, uint64_t &hi)
 {
-    const uint64_t c = (n + gridDim.x - 1) / gridDim.x;
+    const uint64_t c = (n + nb - 1) / nb;
     lo = g * c < n ? g * c : n;
     hi = lo + c < n ? lo + c : n;
 }
 
-__global__ void __launch_bounds__(kThreads) k_final_part(ItemPartials part, uint64_t n_parts, GenStats gs, uint64_t n_gen,
+__device__ __forceinline__ void final_part_body(uint32_t blk, uint32_t nblk, ItemPartials part, uint64_t n_parts, GenStats gs, uint64_t n_gen,
                                                          const double *__restrict__ abs_part, uint64_t n_abs,
                                                          FinalPart *__restrict__ out)
 {
@@ -1037,7 +1245,7 @@ __global__ void __launch_bounds__(kThreads) k_final_part(ItemPartials part, uint
     double num = 0.0, tot = 0.0;
     uint64_t att = 0, disc = 0, mx = 0, sp = 0, de = 0;
     uint64_t lo, hi;
-    chunk_of(n_parts, blockIdx.x, lo, hi);
+    chunk_of(n_parts, blk, nblk, lo, hi);
     for (uint64_t i0 = lo; i0 < hi; i0 += U * kThreads) {
         double a[U];
         uint64_t b[U], c[U], d[U];
@@ -1063,7 +1271,7 @@ __global__ void __launch_bounds__(kThreads) k_final_part(ItemPartials part, uint
             mx = d[u] > mx ? d[u] : mx;
         }
     }
-    chunk_of(n_gen, blockIdx.x, lo, hi);
+    chunk_of(n_gen, blk, nblk, lo, hi);
     for (uint64_t i0 = lo; i0 < hi; i0 += 2 * U * kThreads) {
         uint32_t x[2 * U], y[2 * U];
 #pragma unroll
@@ -1081,7 +1289,7 @@ __global__ void __launch_bounds__(kThreads) k_final_part(ItemPartials part, uint
             de += y[u];
         }
     }
-    chunk_of(n_abs, blockIdx.x, lo, hi);
+    chunk_of(n_abs, blk, nblk, lo, hi);
     for (uint64_t i0 = lo; i0 < hi; i0 += 2 * U * kThreads) {
         double x[2 * U];
 #pragma unroll
@@ -1102,10 +1310,28 @@ __global__ void __launch_bounds__(kThreads) k_final_part(ItemPartials part, uint
     r.de = block_reduce_sum(de);
     r.mx = block_reduce_max(mx);
     r.pad = 0;
-    if (threadIdx.x == 0) out[blockIdx.x] = r;
+    if (threadIdx.x == 0) out[blk] = r;
 }
 
-__global__ void __launch_bounds__(kThreads) k_final(const FinalPart *__restrict__ in, uint64_t n, Scratch *sc)
+struct FinalPartArgs {
+    ItemPartials part;
+    uint64_t n_parts;
+    GenStats gs;
+    uint64_t n_gen;
+    const double *abs_part;
+    uint64_t n_abs;
+    FinalPart *out;
+};
+
+__global__ void __launch_bounds__(kThreads) k_final_part(const FinalPartArgs *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const FinalPartArgs &A = args[batch_state(bm, blk, nblk)];
+    final_part_body(blk, nblk, A.part, A.n_parts, A.gs, A.n_gen, A.abs_part, A.n_abs, A.out);
+}
+
+__device__ __forceinline__ void final_body(uint32_t blk, uint32_t nblk, const FinalPart *__restrict__ in, uint64_t n, Scratch *sc,
+                                           Scratch *copy)
 {
     if (threadIdx.x != 0) return;
     FinalPart a{};
@@ -1126,6 +1352,35 @@ __global__ void __launch_bounds__(kThreads) k_final(const FinalPart *__restrict_
     sc->max_n = a.mx;
     sc->n_spawns = a.sp;
     sc->n_deaths = a.de;
+    *copy = *sc;  // the batch's scalars side by side, for one copy to the host
+}
+
+struct FinalArgs {
+    const FinalPart *in;
+    uint64_t n;
+    Scratch *sc;
+    Scratch *copy;
+};
+
+__global__ void __launch_bounds__(kThreads) k_final(const FinalArgs *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const FinalArgs &A = args[batch_state(bm, blk, nblk)];
+    final_body(blk, nblk, A.in, A.n, A.sc, A.copy);
+}
+
+// Clear each state's step area.
+struct ClearArgs {
+    uint64_t *p;
+    uint64_t n;
+};
+
+__global__ void __launch_bounds__(kThreads) k_clear(const ClearArgs *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const ClearArgs &A = args[batch_state(bm, blk, nblk)];
+    const uint64_t i = (uint64_t)blk * kThreads + threadIdx.x;
+    if (i < A.n) A.p[i] = 0;
 }
 
 template <typename V>

@@ -19,6 +19,30 @@ constexpr int kSortTile = kThreads * kSortItems;
 constexpr int kRadixBits = 9;           // digit width of the radix sort
 constexpr int kRadixBins = 1 << kRadixBits;
 
+// ------------------------------------------------------------------ batched launches
+// One launch serves the states of a batch: state s owns the blocks [off[s], off[s+1]) and
+// reads its arguments from args[s].  Each kernel's body sees its block index within its state
+// (blk) and its state's block count (nblk) in place of blockIdx.x and gridDim.x.
+struct BatchMap {
+    const uint32_t *off;  // n + 1 entries, off[0] = 0
+    uint32_t n;
+};
+
+__device__ __forceinline__ uint32_t batch_state(const BatchMap &bm, uint32_t &blk, uint32_t &nblk)
+{
+    uint32_t lo = 0, hi = bm.n;  // last s with off[s] <= blockIdx.x
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (bm.off[mid] <= blockIdx.x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    blk = blockIdx.x - bm.off[lo];
+    nblk = bm.off[lo + 1] - bm.off[lo];
+    return lo;
+}
+
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
 
@@ -83,6 +107,20 @@ template <typename V>
 struct ArraySrc {
     const V *p;
     __device__ __forceinline__ V operator()(uint64_t i) const { return p[i]; }
+    __device__ __forceinline__ void check(V) const {}
+};
+
+// n counts followed by a closing zero (scanned over n + 1 entries, so that the total lands
+// at index n of the exclusive output).
+template <typename V>
+struct CountSrc {
+    const V *p;
+    uint64_t n;
+    __device__ __forceinline__ V operator()(uint64_t i) const
+    {
+        const V v = p[i < n ? i : 0];  // unconditional load
+        return i < n ? v : V(0);
+    }
     __device__ __forceinline__ void check(V) const {}
 };
 
@@ -158,7 +196,7 @@ struct ArrayOut {
 // Single-launch scan of n values (n_tiles = ceil(n / kScanTile) blocks); the grand total
 // goes to *total when given.
 template <typename V, typename Src, typename Out>
-__global__ void __launch_bounds__(kThreads) k_scan_lb(Src in, Out out, uint64_t n, int inclusive,
+__device__ __forceinline__ void scan_lb_body(uint32_t blk, uint32_t nblk, Src in, Out out, uint64_t n, int inclusive,
                                                       uint64_t *__restrict__ status, uint64_t *__restrict__ ticket,
                                                       uint64_t *__restrict__ total)
 {
@@ -218,6 +256,25 @@ __global__ void __launch_bounds__(kThreads) k_scan_lb(Src in, Out out, uint64_t 
     }
 }
 
+template <typename V, typename Src, typename Out>
+struct ScanLbArgs {
+    Src in;
+    Out out;
+    uint64_t n;
+    int inclusive;
+    uint64_t *status;
+    uint64_t *ticket;
+    uint64_t *total;
+};
+
+template <typename V, typename Src, typename Out>
+__global__ void __launch_bounds__(kThreads) k_scan_lb(const ScanLbArgs<V, Src, Out> *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const ScanLbArgs<V, Src, Out> &A = args[batch_state(bm, blk, nblk)];
+    scan_lb_body<V, Src, Out>(blk, nblk, A.in, A.out, A.n, A.inclusive, A.status, A.ticket, A.total);
+}
+
 // ----------------------------------------------------------------- radix sort
 // Keys are W words in SoA layout (word w of item i at key[w * stride + i]).  One pass sorts
 // by the 8-bit digit at bit `shift` of word `word`, stably.
@@ -240,7 +297,7 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active)
 // aggregated per wavefront and per block before one global atomic per bin.
 constexpr int kRadixMaxPasses = (64 + kRadixBits - 1) / kRadixBits;
 
-__global__ void __launch_bounds__(kThreads) k_radix_ghist(const uint64_t *__restrict__ key, const uint64_t *__restrict__ n_live,
+__device__ __forceinline__ void radix_ghist_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ key, const uint64_t *__restrict__ n_live,
                                                           int passes, uint32_t *__restrict__ ghist)
 {
     const uint64_t n = *n_live;
@@ -248,7 +305,7 @@ __global__ void __launch_bounds__(kThreads) k_radix_ghist(const uint64_t *__rest
     for (int p = 0; p < passes; ++p)
         for (int d = threadIdx.x; d < kRadixBins; d += kThreads) h[p][d] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    const uint64_t base = (uint64_t)blk * kSortTile;
     if (base < n) {
         uint64_t k[kSortItems];
 #pragma unroll
@@ -276,6 +333,20 @@ __global__ void __launch_bounds__(kThreads) k_radix_ghist(const uint64_t *__rest
             if (h[p][d]) atomicAdd(&ghist[p * kRadixBins + d], h[p][d]);
 }
 
+struct RadixGhistArgs {
+    const uint64_t *key;
+    const uint64_t *n_live;
+    int passes;
+    uint32_t *ghist;
+};
+
+__global__ void __launch_bounds__(kThreads) k_radix_ghist(const RadixGhistArgs *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const RadixGhistArgs &A = args[batch_state(bm, blk, nblk)];
+    radix_ghist_body(blk, nblk, A.key, A.n_live, A.passes, A.ghist);
+}
+
 // One stable pass by the digit at `shift`.  Wavefront w of a tile owns the tile's keys
 // [w * 64 * kSortItems, (w + 1) * 64 * kSortItems), 64 per round, and ranks them against its
 // own LDS digit counters (no block barrier between rounds: a wavefront's LDS accesses are in
@@ -286,7 +357,7 @@ __global__ void __launch_bounds__(kThreads) k_radix_ghist(const uint64_t *__rest
 // digits x + j * kThreads of the per-digit work.
 constexpr int kDigitsPerThread = kRadixBins / kThreads;
 
-__global__ void __launch_bounds__(kThreads) k_radix_onesweep(const uint64_t *__restrict__ key_in, const uint32_t *__restrict__ idx_in,
+__device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ key_in, const uint32_t *__restrict__ idx_in,
                                                              uint64_t *__restrict__ key_out, uint32_t *__restrict__ idx_out,
                                                              const uint64_t *__restrict__ n_live, int shift,
                                                              const uint32_t *__restrict__ ghist, uint64_t *__restrict__ status,
@@ -404,6 +475,25 @@ __global__ void __launch_bounds__(kThreads) k_radix_onesweep(const uint64_t *__r
             idx_out[dst] = ix[r];
         }
     }
+}
+
+struct RadixOnesweepArgs {
+    const uint64_t *key_in;
+    const uint32_t *idx_in;
+    uint64_t *key_out;
+    uint32_t *idx_out;
+    const uint64_t *n_live;
+    int shift;
+    const uint32_t *ghist;
+    uint64_t *status;
+    uint64_t *ticket;
+};
+
+__global__ void __launch_bounds__(kThreads) k_radix_onesweep(const RadixOnesweepArgs *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const RadixOnesweepArgs &A = args[batch_state(bm, blk, nblk)];
+    radix_onesweep_body(blk, nblk, A.key_in, A.idx_in, A.key_out, A.idx_out, A.n_live, A.shift, A.ghist, A.status, A.ticket);
 }
 
 }  // namespace ccmc
