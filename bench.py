@@ -295,6 +295,25 @@ def precision_study(w: inputs.Workload, steps: int, equil: int, log):
                 fp32_speedup_at_equal_error=t["fp64"] / t["fp32"] if t["fp32"] > 0 else None)
 
 
+def serving_benchmark(n_requests: int, max_steps: int, tol: float, budget: float, slots: int, log):
+    """The served stream: Poisson arrivals (mean 2/s) of UEG 14-electron solves with FP32
+    amplitudes and FP64 energy reductions, admitted by HBM budget and stepped together in
+    shared launches until each one's reblocked E_proj error is below `tol` (or `max_steps`)."""
+    from paper_1807_03749_amd import serve
+    reqs = serve.requests_from_stream(inputs.serving_stream(n_requests), precision="fp32")
+    srv = serve.Server(hbm_budget=budget, max_active=slots, tol=tol, max_steps=max_steps, log=log)
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    out = serve.summary(res, wall)
+    out.update(batch_steps=srv.batch_steps, state_steps=srv.state_steps, max_steps=max_steps, tol=tol,
+               hbm_budget=budget, slots=slots,
+               per_request=[dict(id=r.request_id, arrival=round(r.arrival, 3), tte=round(r.time_to_energy, 3),
+                                 steps=r.steps, e=r.energy, err=r.error, ok=r.converged,
+                                 **({"failed": r.failed} if r.failed else {})) for r in res])
+    return out
+
+
 def cpu_baseline(w: inputs.Workload, seconds: float, log):
     """The CPU oracle, timed on this host on a bounded sample of the same workload: the
     whole truncated space occupied with seeded amplitudes (N_tot = target), stepped until
@@ -376,6 +395,13 @@ def main():
     ap.add_argument("--study-steps", type=int, default=50000,
                     help="steps per precision of the FP64 / FP32 equal-error study (0: skip)")
     ap.add_argument("--study-equil", type=int, default=4000, help="equilibration steps before the study")
+    ap.add_argument("--serve", action="store_true", help="also run the served stream (continuous batching)")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-max-steps", type=int, default=20000)
+    ap.add_argument("--serve-tol", type=float, default=1e-4)
+    ap.add_argument("--serve-budget", type=float, default=64e9, help="HBM budget of the server (bytes)")
+    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-only", action="store_true", help="only the served stream")
     args = ap.parse_args()
     global ROCTX
     ROCTX = _Roctx(args.roctx_region)
@@ -387,6 +413,11 @@ def main():
               f"(the multi-GPU design is described, not built)", file=sys.stderr)
         sys.exit(2)
     log = (lambda m: None) if args.quiet else (lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+    if args.serve_only:
+        sv = serving_benchmark(args.serve_requests, args.serve_max_steps, args.serve_tol, args.serve_budget,
+                               args.serve_slots, log)
+        print(json.dumps({"metric": "served CCMC solves: time to energy", "serving": sv}))
+        return
     w = inputs.WORKLOADS[args.workload]
     log(f"workload {w.name} precision {args.precision}: growing to {w.target_population:.0e}")
     main_leg = run_leg(w, args.precision, args.steps, args.warmup, log, profile=not args.no_kernel_timing,
@@ -436,6 +467,10 @@ def main():
     if args.study_steps > 0 and args.precision == "fp64" and not args.no_fp32:
         log("precision study")
         out["precision_study"] = precision_study(w, args.study_steps, args.study_equil, log)
+    if args.serve:
+        log("served stream")
+        out["serving"] = serving_benchmark(args.serve_requests, args.serve_max_steps, args.serve_tol,
+                                           args.serve_budget, args.serve_slots, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, log)
     print(json.dumps(out))

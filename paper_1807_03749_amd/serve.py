@@ -1,0 +1,200 @@
+"""Continuous-batching server of CCMC solves on one GPU.
+
+Requests arrive over time.  Each one is a full CCMC calculation: grow the population with the
+shift held at zero until it reaches the target, vary the shift to hold it there (Sec. II),
+skip an equilibration window, then accumulate the projected-energy terms until their
+reblocked standard error falls below a tolerance (Computational Methods).  The server keeps
+every admitted solve's excitor store resident on the device between steps, and every
+iteration steps all active solves together in shared launches (``ccmc_step_batch``).
+
+Admission is by device memory: a request is admitted when a slot is free and its estimated
+footprint fits the remaining HBM budget; its state is created with that estimate (times a
+safety factor) as its own budget, so a solve that outgrows it fails alone with ENOMEM.
+Finished solves free their memory at once, so waiting requests join the running batch
+between two steps -- continuous batching, not a queue of whole runs.
+
+Each solve's result does not depend on what else is in the batch: its steps use its own
+store and its own Philox key, and the shift and selection count come from its own
+statistics, so a solve served in a mix returns exactly the energy it returns alone.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import ccmc, driver
+
+
+@dataclass
+class Request:
+    request_id: int
+    arrival: float          # seconds after the start of the stream
+    system: dict            # ccmc.State keyword arguments (system, n_electrons, truncation, ...)
+    target: float           # target population
+    tau: float
+    seed: int
+    precision: str = "fp32"
+
+
+@dataclass
+class Solve:
+    req: Request
+    state: object
+    est_bytes: int
+    ctl: driver.ShiftControl
+    nsel: int
+    admitted: float
+    steps: int = 0
+    varying_since: int = -1
+    num: list = field(default_factory=list)
+    den: list = field(default_factory=list)
+    attempts: int = 0
+
+
+@dataclass
+class Result:
+    request_id: int
+    arrival: float
+    admitted: float
+    finished: float
+    steps: int
+    energy: float
+    error: float
+    converged: bool
+    attempts: int
+    failed: str = ""
+
+    @property
+    def time_to_energy(self) -> float:
+        return self.finished - self.arrival
+
+
+def estimate_bytes(req: Request) -> int:
+    """Device memory of a solve at its target population: a fixed part plus about 300 bytes
+    per unit of population (store, items, record regions and sort buffers; measured at
+    N = 1e6 for 14 electrons in 114 spin orbitals), doubled for the FP64 amplitudes."""
+    per = 300.0 * (2.0 if req.precision == "fp64" else 1.0)
+    return int(32e6 + per * req.target)
+
+
+class Server:
+    def __init__(self, hbm_budget: float = 64e9, max_active: int = 32, tol: float = 1e-4, equil: int = 500,
+                 min_samples: int = 512, check_every: int = 256, max_steps: int = 20000, safety: float = 4.0,
+                 clock=time.perf_counter, sleep=time.sleep, log=None):
+        self.hbm_budget = hbm_budget
+        self.max_active = max_active
+        self.tol = tol
+        self.equil = equil
+        self.min_samples = min_samples
+        self.check_every = check_every
+        self.max_steps = max_steps
+        self.safety = safety
+        self.clock = clock
+        self.sleep = sleep
+        self.log = log or (lambda m: None)
+        self.batch_steps = 0
+        self.state_steps = 0
+
+    # ------------------------------------------------------------------------ one solve
+    def _start(self, req: Request, now: float) -> Solve:
+        est = estimate_bytes(req)
+        kw = dict(req.system)
+        system, nel, trunc = kw.pop("system"), kw.pop("n_electrons"), kw.pop("truncation")
+        init_pop = max(10.0, req.target / 5.0)  # the walk starts on the reference (Sec. II)
+        st = ccmc.State(system, nel, trunc, precision=req.precision, seed=req.seed, init_pop=init_pop,
+                        hbm_budget_bytes=int(self.safety * est), **kw)
+        ctl = driver.ShiftControl(target=req.target, tau=req.tau)
+        return Solve(req=req, state=st, est_bytes=est, ctl=ctl, nsel=driver.selections(init_pop), admitted=now)
+
+    def _advance(self, s: Solve, stats: dict) -> bool:
+        """Book one step's statistics; True when the solve is finished."""
+        s.steps += 1
+        s.attempts += stats["n_spawn_attempts"]
+        was = s.ctl.varying
+        s.ctl.update(stats["n_total"])
+        if s.ctl.varying and not was:
+            s.varying_since = s.steps
+        s.nsel = driver.selections(stats["n_total"])
+        if s.varying_since >= 0 and s.steps - s.varying_since > self.equil:
+            s.num.append(stats["eproj_num"])
+            s.den.append(stats["eproj_den"])
+            if len(s.num) >= self.min_samples and len(s.num) % self.check_every == 0:
+                _, err, _ = driver.reblock_ratio(np.array(s.num), np.array(s.den))
+                if err < self.tol:
+                    return True
+        return s.steps >= self.max_steps
+
+    def _finish(self, s: Solve, now: float, failed: str = "") -> Result:
+        e = err = float("nan")
+        if len(s.num) >= 16:
+            e, err, _ = driver.reblock_ratio(np.array(s.num), np.array(s.den))
+        s.state.close()
+        return Result(s.req.request_id, s.req.arrival, s.admitted, now, s.steps, e, err,
+                      bool(err < self.tol) and not failed, s.attempts, failed)
+
+    # ------------------------------------------------------------------------ the loop
+    def run(self, requests: list[Request]) -> list[Result]:
+        """Serve `requests` (arrival times relative to the call) to completion."""
+        pending = sorted(requests, key=lambda r: r.arrival)
+        waiting: list[Request] = []
+        active: list[Solve] = []
+        results: list[Result] = []
+        t0 = self.clock()
+        used = 0
+        while pending or waiting or active:
+            now = self.clock() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.pop(0))
+            # admission: in arrival order, while memory and slots allow
+            for req in list(waiting):
+                est = estimate_bytes(req)
+                if len(active) < self.max_active and used + est <= self.hbm_budget:
+                    waiting.remove(req)
+                    active.append(self._start(req, now))
+                    used += est
+                    self.log(f"admit {req.request_id} at {now:.2f}s ({len(active)} active)")
+            if not active:
+                if pending:
+                    self.sleep(max(0.0, pending[0].arrival - (self.clock() - t0)))
+                continue
+            res = ccmc.ccmc_step_batch([s.state for s in active], [s.req.tau for s in active],
+                                       [s.ctl.shift for s in active], [s.nsel for s in active])
+            self.batch_steps += 1
+            self.state_steps += len(active)
+            now = self.clock() - t0
+            keep = []
+            for s, r in zip(active, res):
+                if isinstance(r, Exception):
+                    results.append(self._finish(s, now, failed=str(r)))
+                    used -= s.est_bytes
+                elif self._advance(s, r):
+                    results.append(self._finish(s, now))
+                    used -= s.est_bytes
+                    self.log(f"done {s.req.request_id} at {now:.2f}s after {s.steps} steps")
+                else:
+                    keep.append(s)
+            active = keep
+        return sorted(results, key=lambda r: r.request_id)
+
+
+def requests_from_stream(stream: list[dict], precision: str = "fp32") -> list[Request]:
+    """Requests from ``inputs.serving_stream`` records (UEG, 14 electrons)."""
+    out = []
+    for d in stream:
+        system = dict(system="ueg", n_electrons=14, truncation=d["truncation"], n2_max=d["n2_max"], rs=d["rs"])
+        out.append(Request(d["request_id"], d["arrival"], system, d["target_population"], d["tau"], d["seed"],
+                           precision))
+    return out
+
+
+def summary(results: list[Result], wall: float) -> dict:
+    tte = np.array([r.time_to_energy for r in results])
+    conv = [r for r in results if r.converged]
+    return dict(requests=len(results), converged=len(conv), failed=sum(1 for r in results if r.failed),
+                p50_time_to_energy_s=float(np.percentile(tte, 50)) if len(tte) else None,
+                p99_time_to_energy_s=float(np.percentile(tte, 99)) if len(tte) else None,
+                attempts_per_s=sum(r.attempts for r in results) / wall if wall > 0 else None,
+                wall_s=wall, mean_steps=float(np.mean([r.steps for r in results])) if results else None)
