@@ -61,14 +61,19 @@ typedef struct {
 } ccmc_system;
 
 /* Molecular integrals (host, copied at init): h[n][n] symmetric one-electron integrals and
- * Cholesky vectors chol[n_chol][n][n] (each symmetric), so that the chemists' two-electron
- * integrals are (pq|rs) = sum_L chol[L][p][q] chol[L][r][s]; the library builds that table on
- * the device.  Pass NULL for the UEG. */
+ * the chemists' two-electron integrals (pq|rs), either as the full table eri[n][n][n][n]
+ * (8-fold symmetric) or as Cholesky vectors chol[n_chol][n][n] (each symmetric) with
+ * (pq|rs) = sum_L chol[L][p][q] chol[L][r][s], which the library contracts on the device.
+ * eri takes precedence when both are given; give at least one.  e_core is a constant (e.g.
+ * nuclear repulsion) added to the reference energy that ccmc_energy reports; every other
+ * energy is relative to E_HF.  Pass NULL for the UEG. */
 typedef struct {
     int n_spatial;
     const double *h;
     const double *chol;
     int n_chol;
+    const double *eri;
+    double e_core;
 } ccmc_integrals;
 
 /* Sampling options.  Defaults (ccmc_options_default): FP64, original selection, k_min 1,
@@ -153,7 +158,7 @@ ccmc_status ccmc_step_batch(ccmc_state *const *states, int n, const double *tau,
 
 /* Projected-energy estimator terms of the last step (Sec. II, eq. 7): E_proj is the ratio of
  * the means of eproj_num and eproj_den over the equilibrated steps.  e_hf receives the
- * Hartree-Fock energy.  Any output pointer may be NULL. */
+ * Hartree-Fock energy (plus e_core for molecular systems).  Any output pointer may be NULL. */
 ccmc_status ccmc_energy(const ccmc_state *st, double *e_hf, double *eproj_num, double *eproj_den);
 
 /* Release the state and all its device memory.  NULL is ignored. */

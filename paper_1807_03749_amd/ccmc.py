@@ -37,7 +37,7 @@ class ccmc_system(C.Structure):
 
 class ccmc_integrals(C.Structure):
     _fields_ = [("n_spatial", C.c_int), ("h", C.POINTER(C.c_double)), ("chol", C.POINTER(C.c_double)),
-                ("n_chol", C.c_int)]
+                ("n_chol", C.c_int), ("eri", C.POINTER(C.c_double)), ("e_core", C.c_double)]
 
 
 class ccmc_options(C.Structure):
@@ -129,7 +129,8 @@ class State:
     """One CCMC calculation resident on the GPU (wraps ``ccmc_state*``)."""
 
     def __init__(self, system: str, n_electrons: int, truncation: int, *, n2_max: int = 0, rs: float = 1.0,
-                 h: np.ndarray | None = None, chol: np.ndarray | None = None, **opts):
+                 h: np.ndarray | None = None, chol: np.ndarray | None = None, eri: np.ndarray | None = None,
+                 e_core: float = 0.0, **opts):
         self._h = None
         sysc = ccmc_system()
         sysc.kind = CCMC_UEG if system == "ueg" else CCMC_MOLECULAR
@@ -140,10 +141,12 @@ class State:
         self._keep = []
         if system != "ueg":
             h = np.ascontiguousarray(h, np.float64)
-            chol = np.ascontiguousarray(chol, np.float64)
-            self._keep += [h, chol]
-            ints = ccmc_integrals(h.shape[0], h.ctypes.data_as(C.POINTER(C.c_double)),
-                                  chol.ctypes.data_as(C.POINTER(C.c_double)), chol.shape[0])
+            dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+            chol = np.ascontiguousarray(chol, np.float64) if chol is not None else None
+            eri = np.ascontiguousarray(eri, np.float64) if eri is not None else None
+            self._keep += [h, chol, eri]
+            ints = ccmc_integrals(h.shape[0], dp(h), dp(chol), chol.shape[0] if chol is not None else 0, dp(eri),
+                                  float(e_core))
             sysc.n_spin_orbitals = 2 * h.shape[0]
         self.options = options(**opts)
         handle = C.c_void_p()

@@ -64,6 +64,7 @@ struct HostSys {
     std::vector<double> h;   // molecular [nsp][nsp]
     std::vector<double> fock, vpair;
     double ehf = 0;
+    double e_core = 0;  // constant added to reported absolute energies
 };
 
 }  // namespace
@@ -329,10 +330,12 @@ bool build_mol(HostSys &hs, int nel, const ccmc_integrals *ints, std::string &er
 {
     const int n = ints->n_spatial;
     if (nel < 2 || (nel & 1) || n < 1 || nel > 2 * n || 2 * n > 64 * kMaxWords || !ints->h ||
-        ints->n_chol < 0 || (ints->n_chol > 0 && !ints->chol)) {
+        ints->n_chol < 0 || (ints->n_chol > 0 && !ints->chol) || (!ints->eri && ints->n_chol == 0) ||
+        !std::isfinite(ints->e_core)) {
         err = "molecular: invalid sizes or null integral arrays";
         return false;
     }
+    hs.e_core = ints->e_core;
     hs.kind = CCMC_MOLECULAR;
     hs.nel = nel;
     hs.nsp = n;
@@ -340,7 +343,8 @@ bool build_mol(HostSys &hs, int nel, const ccmc_integrals *ints, std::string &er
     hs.h.assign(ints->h, ints->h + (size_t)n * n);
     const int M = hs.M;
     const size_t nn = (size_t)n * n;
-    auto eri = [&](int P, int Q, int R, int S) {  // (PQ|RS), summed over L in order
+    auto eri = [&](int P, int Q, int R, int S) {  // (PQ|RS): given, or summed over L in order
+        if (ints->eri) return ints->eri[((size_t)P * n + Q) * nn + (size_t)R * n + S];
         double v = 0.0;
         for (int L = 0; L < ints->n_chol; ++L) v += ints->chol[L * nn + (size_t)P * n + Q] * ints->chol[L * nn + (size_t)R * n + S];
         return v;
@@ -447,15 +451,19 @@ ccmc_status upload_system(ccmc_state *st, const ccmc_integrals *ints)
         TRY(upload_table<T>(st, st->t_h, hs.h));
         S.h = st->t_h.p;
         const uint64_t n = hs.nsp, n4 = n * n * n * n;
-        DevBuf chol;
-        const size_t cb = std::max<size_t>(1, (size_t)ints->n_chol * n * n) * sizeof(double);
-        TRY(ensure(st, chol, cb));
-        if (ints->n_chol > 0)
+        if (ints->eri) {  // the full table as given
+            TRY(upload_table<T>(st, st->t_eri, std::vector<double>(ints->eri, ints->eri + n4)));
+        } else {          // built on the device from the Cholesky vectors
+            DevBuf chol;
+            const size_t cb = std::max<size_t>(1, (size_t)ints->n_chol * n * n) * sizeof(double);
+            TRY(ensure(st, chol, cb));
             HIP_TRY(hipMemcpy(chol.p, ints->chol, (size_t)ints->n_chol * n * n * sizeof(double), hipMemcpyHostToDevice));
-        TRY(ensure(st, st->t_eri, n4 * sizeof(T)));
-        k_build_eri<T><<<grid_for(n4), kThreads, 0, st->stream>>>(ptr<double>(chol), (int)n, ints->n_chol, ptr<T>(st->t_eri));
-        HIP_TRY(hipStreamSynchronize(st->stream));
-        release(st, chol);
+            TRY(ensure(st, st->t_eri, n4 * sizeof(T)));
+            k_build_eri<T><<<grid_for(n4), kThreads, 0, st->stream>>>(ptr<double>(chol), (int)n, ints->n_chol,
+                                                                      ptr<T>(st->t_eri));
+            HIP_TRY(hipStreamSynchronize(st->stream));
+            release(st, chol);
+        }
         S.eri = st->t_eri.p;
     }
     return CCMC_OK;
@@ -1539,7 +1547,7 @@ ccmc_status ccmc_step_batch(ccmc_state *const *states, int n, const double *tau,
 ccmc_status ccmc_energy(const ccmc_state *st, double *e_hf, double *eproj_num, double *eproj_den)
 {
     if (!st) return CCMC_EINVAL;
-    if (e_hf) *e_hf = st->hs.ehf;
+    if (e_hf) *e_hf = st->hs.ehf + st->hs.e_core;
     if (eproj_num) *eproj_num = st->last_num;
     if (eproj_den) *eproj_den = st->last_den;
     return CCMC_OK;

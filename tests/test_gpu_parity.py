@@ -207,3 +207,32 @@ def test_large_amplitudes_select_identically():
     R.import_state(keys, amps, n0, step)
     gs, os_ = compare_step(S, R, g, 0.005, 0.0, 4000)
     _say(f"[parity] large amplitudes ok ({gs['n_spawn_attempts']} attempts)")
+
+
+def test_full_eri_table_matches_cholesky_input():
+    """The same molecule given as a full (pq|rs) table and as Cholesky vectors: identical
+    records and store after a step from the same state (the table is the contraction of the
+    vectors, summed in the same order), and e_core shifts only the reported E_HF."""
+    h, B = inputs.molecule_like(n_spatial=8, n_electrons=6, n_chol=12, seed=31)
+    n = h.shape[0]
+    eri = np.zeros((n, n, n, n))
+    for L in range(B.shape[0]):  # summed over L in order, like the library
+        eri += np.einsum("pq,rs->pqrs", B[L], B[L])
+    S = orc.System.molecular(6, h, B)
+    R = orc.Run(S, 2, orc.RunOptions(init_pop=200.0, seed=8))
+    st = evolve_oracle(R, 20, 0.01, 200)
+    keys, amps, n0, step = R.export_state()
+    a = ccmc.State("mol", 6, 2, h=h, chol=B, keep_spawn_ids=1, init_pop=200.0, seed=8)
+    b = ccmc.State("mol", 6, 2, h=h, eri=eri, e_core=3.25, keep_spawn_ids=1, init_pop=200.0, seed=8)
+    assert abs(b.ccmc_energy()[0] - a.ccmc_energy()[0] - 3.25) < 1e-9
+    nsel = int(round(st["n_total"]))
+    for g in (a, b):
+        g.ccmc_import(keys, amps, n0, step)
+        g.ccmc_step(0.01, 0.0, nsel)
+    ka, aa, ia = a.ccmc_export_spawns()
+    kb, ab, ib = b.ccmc_export_spawns()
+    assert np.array_equal(ia, ib) and np.array_equal(ka, kb)
+    np.testing.assert_allclose(ab, aa, rtol=1e-12, atol=0)
+    sa, sb = a.ccmc_export(), b.ccmc_export()
+    assert np.array_equal(sa[0], sb[0])
+    np.testing.assert_allclose(sb[1], sa[1], rtol=1e-12, atol=1e-12)
