@@ -473,14 +473,20 @@ struct Records {
     uint64_t stride;
 };
 
-template <int W, typename T>
-__device__ __forceinline__ bool spawn_attempt(const SysDev &S, const uint64_t *d, T A, uint32_t n, uint32_t purpose,
-                                              uint32_t k, uint32_t m, const StepArgs &a, uint64_t *tgt, T &x)
+// A spawning attempt in two halves.  gen_excitation draws the excitation of determinant d
+// (Philox stream (purpose, k, m)) and applies it: false for a null draw or a target beyond
+// the truncation level (Sec. II), else the target bitstring and the orbitals (j = tb = -1 for
+// a single).  spawn_amount then evaluates the Slater-Condon element and the spawned amount
+// -dtau H_tc s_D(c) s_D(t) A / (n p_gen) (Sec. II sign rule, Sec. IV.C), with the stochastic
+// rounding of amounts below the spawn cutoff; false when nothing is spawned.
+template <int W>
+__device__ __forceinline__ bool gen_excitation(const SysDev &S, const uint64_t *d, uint32_t purpose, uint32_t k,
+                                               uint32_t m, const StepArgs &a, uint64_t *tgt, int &i, int &j, int &ta,
+                                               int &tb)
 {
     Draws r(a.key0, a.key1, purpose, k, m, a.step);
     const int N = S.nel;
-    int i, j = -1, ta, tb = -1, ridx;
-    double pgen;
+    j = tb = -1;
     if (S.kind == kSystemUEG) {
         const uint32_t pr = (uint32_t)below(r.get(0), S.npairs);
         const int alpha = (int)below(r.get(1), S.half);
@@ -498,8 +504,6 @@ __device__ __forceinline__ bool spawn_attempt(const SysDev &S, const uint64_t *d
         if (beta < 0) return false;
         tb = 2 * beta + (j & 1);
         if (tb == ta || bit_test<W>(d, tb)) return false;
-        pgen = (((i & 1) == (j & 1)) ? 2.0 : 1.0) / ((double)S.npairs * (double)S.half);
-        ridx = 2;
     } else {
         const bool single = uniform53(r.get(0)) < S.p_single;
         if (single) {
@@ -507,7 +511,6 @@ __device__ __forceinline__ bool spawn_attempt(const SysDev &S, const uint64_t *d
             i = select_bit<W>(d, xa);
             ta = 2 * (int)below(r.get(2), S.half) + (i & 1);
             if (bit_test<W>(d, ta)) return false;
-            pgen = S.p_single / ((double)N * (double)S.half);
         } else {
             int xa, ya;
             unrank_pair(N, (uint32_t)below(r.get(1), S.npairs), xa, ya);
@@ -516,10 +519,7 @@ __device__ __forceinline__ bool spawn_attempt(const SysDev &S, const uint64_t *d
             ta = 2 * (int)below(r.get(2), S.half) + (i & 1);
             tb = 2 * (int)below(r.get(3), S.half) + (j & 1);
             if (ta == tb || bit_test<W>(d, ta) || bit_test<W>(d, tb)) return false;
-            pgen = (1.0 - S.p_single) * (((i & 1) == (j & 1)) ? 2.0 : 1.0) /
-                   ((double)S.npairs * (double)S.half * (double)S.half);
         }
-        ridx = 4;
     }
 #pragma unroll
     for (int w = 0; w < W; ++w) tgt[w] = d[w];
@@ -530,7 +530,27 @@ __device__ __forceinline__ bool spawn_attempt(const SysDev &S, const uint64_t *d
         bit_flip<W>(tgt, tb);
     }
     // spawns beyond the truncation level are discarded (Sec. II)
-    if (level_of<W>(S, tgt) > S.l) return false;
+    return level_of<W>(S, tgt) <= S.l;
+}
+
+template <int W, typename T>
+__device__ __forceinline__ bool spawn_amount(const SysDev &S, const uint64_t *d, const uint64_t *tgt, int i, int j, int ta,
+                                             int tb, T A, uint32_t n, uint32_t purpose, uint32_t k, uint32_t m,
+                                             const StepArgs &a, T &x)
+{
+    double pgen;
+    int ridx;
+    if (S.kind == kSystemUEG) {
+        pgen = (((i & 1) == (j & 1)) ? 2.0 : 1.0) / ((double)S.npairs * (double)S.half);
+        ridx = 2;
+    } else if (j < 0) {
+        pgen = S.p_single / ((double)S.nel * (double)S.half);
+        ridx = 4;
+    } else {
+        pgen = (1.0 - S.p_single) * (((i & 1) == (j & 1)) ? 2.0 : 1.0) /
+               ((double)S.npairs * (double)S.half * (double)S.half);
+        ridx = 4;
+    }
     T H;
     if (j < 0) {
         H = single_element<W, T>(S, d, i, ta);
@@ -543,6 +563,7 @@ __device__ __forceinline__ bool spawn_attempt(const SysDev &S, const uint64_t *d
     x = -(T)a.tau * H * (T)sc * (T)st * A / ((T)n * (T)pgen);
     if (x == T(0)) return false;
     if (fabs((double)x) < a.cutoff) {
+        Draws r(a.key0, a.key1, purpose, k, m, a.step);
         const double u = uniform53(r.get(ridx));
         if (u < fabs((double)x) / a.cutoff)
             x = (T)copysign(a.cutoff, (double)x);
@@ -580,14 +601,25 @@ struct GenStats {
     uint32_t *deaths;
 };
 
+// One block covers kGenSlots consecutive record slots.  Pass 1, one lane per slot: find the
+// slot's item, and keep the slot as a candidate if it is a non-zero death or an attempt whose
+// excitation is valid (compacted into LDS in slot order).  Pass 2, one lane per candidate:
+// evaluate the element and the spawned amount, and write the records in slot order into the
+// block's region.  Splitting the two halves keeps every lane of pass 2 busy: only a small
+// fraction of the attempts survive pass 1.
+constexpr uint32_t kCandDeath = 1u << 31;
+
 template <int W, typename T>
 __device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDev S, Items<T> it, const uint64_t *__restrict__ off,
                                                        const uint64_t *__restrict__ block_item, uint64_t n_fnc,
                                                        uint64_t n_items, uint64_t slot_cap, StepArgs a, Records rec,
                                                        int keep_ids, GenStats gs, Scratch *sc)
 {
-    __shared__ uint64_t s_off[kGenLdsItems + 1];
+    __shared__ uint32_t s_off[kGenLdsItems + 1];  // item offsets relative to the first item's
     __shared__ uint32_t wave_tot[kWaves];
+    __shared__ uint32_t c_item[kGenSlots];  // candidate: item
+    __shared__ uint32_t c_slot[kGenSlots];  // candidate: slot in its item (kCandDeath: the death)
+    __shared__ uint64_t c_orb[kGenSlots];   // candidate: i, j, a, b (16 bits each)
     T *ramp = static_cast<T *>(rec.amp);
     const uint64_t g0 = (uint64_t)blk * kGenSlots;
     const uint64_t n_all = off[n_items];
@@ -605,23 +637,28 @@ __device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDe
     const uint64_t lo = block_item[blk];
     const uint64_t hi = g0 + kGenSlots < n_slots ? block_item[blk + 1] : n_items - 1;
     const bool lds = hi - lo + 1 <= (uint64_t)kGenLdsItems;
+    const uint64_t obase = off[lo];  // <= g0; every slot of the block is below obase + 2^31
     if (lds)
-        for (uint64_t t = threadIdx.x; t <= hi - lo + 1; t += kThreads) s_off[t] = off[lo + t];
+        for (uint64_t t = threadIdx.x; t <= hi - lo + 1; t += kThreads) {
+            const uint64_t r = off[lo + t] - obase;
+            s_off[t] = r < 0xFFFFFFFFull ? (uint32_t)r : 0xFFFFFFFFu;
+        }
     __syncthreads();
-    uint32_t base = 0, spawns = 0, deaths = 0;
+    // ---- pass 1: candidates
+    uint32_t nc_total = 0;
     for (int rd = 0; rd < kGenRounds; ++rd) {
         const uint64_t g = g0 + (uint64_t)rd * kThreads + threadIdx.x;
-        bool emit = false;
-        uint64_t tgt[W];
-        T x = T(0);
-        uint64_t id = 0;
+        bool keep = false;
+        uint32_t item32 = 0, slot = 0;
+        uint64_t orb = 0;
         if (g < n_slots) {
             uint64_t item;
             if (lds) {  // last item in [lo, hi] whose offset is <= g, searched in LDS
+                const uint32_t gr = (uint32_t)(g - obase);
                 uint32_t l0 = 0, h0 = (uint32_t)(hi - lo + 1);
                 while (l0 < h0) {
                     const uint32_t mid = (l0 + h0) >> 1;
-                    if (s_off[mid] > g)
+                    if (s_off[mid] > gr)
                         h0 = mid;
                     else
                         l0 = mid + 1;
@@ -638,30 +675,85 @@ __device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDe
                 }
                 item = l0 - 1;
             }
-            const uint32_t slot = (uint32_t)(g - off[item]);
+            item32 = (uint32_t)item;
+            slot = (uint32_t)(g - off[item]);
+            if (slot == 0) {
+                keep = it.death[item] != T(0);
+                slot = kCandDeath;
+            } else {
+                const bool nc = item < n_fnc;
+                const uint32_t k = (uint32_t)(nc ? item : item - n_fnc);
+                uint64_t d[W], tgt[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) d[w] = it.key[(uint64_t)w * it.stride + item];
+                int i, j, ta, tb;
+                keep = gen_excitation<W>(S, d, nc ? kSpawnNonComposite : kSpawnSampled, k, slot - 1, a, tgt, i, j, ta, tb);
+                orb = (uint64_t)(uint16_t)i | ((uint64_t)(uint16_t)j << 16) | ((uint64_t)(uint16_t)ta << 32) |
+                      ((uint64_t)(uint16_t)tb << 48);
+            }
+        }
+        // compaction in slot order
+        const uint64_t mk = __ballot(keep);
+        if (lane_id() == 0) wave_tot[wave_id()] = (uint32_t)__popcll(mk);
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            if (w < wave_id()) before += wave_tot[w];
+            total += wave_tot[w];
+        }
+        if (keep) {
+            const uint32_t q = nc_total + before + (uint32_t)lanes_below(mk);
+            c_item[q] = item32;
+            c_slot[q] = slot;
+            c_orb[q] = orb;
+        }
+        nc_total += total;
+        __syncthreads();
+    }
+    // ---- pass 2: amounts of the candidates, records in slot order
+    uint32_t base = 0, spawns = 0, deaths = 0;
+    for (uint32_t e0 = 0; e0 < nc_total; e0 += kThreads) {
+        const uint32_t e = e0 + threadIdx.x;
+        bool emit = false;
+        uint64_t tgt[W];
+        T x = T(0);
+        uint64_t id = 0;
+        if (e < nc_total) {
+            const uint64_t item = c_item[e];
+            const uint32_t cs = c_slot[e];
             const bool nc = item < n_fnc;
             const uint32_t k = (uint32_t)(nc ? item : item - n_fnc);
             uint64_t d[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) d[w] = it.key[(uint64_t)w * it.stride + item];
-            if (slot == 0) {
+            if (cs == kCandDeath) {
                 x = it.death[item];
-                if (x != T(0)) {
-                    emit = true;
 #pragma unroll
-                    for (int w = 0; w < W; ++w) tgt[w] = d[w];
-                    ++deaths;
-                }
+                for (int w = 0; w < W; ++w) tgt[w] = d[w];
+                emit = true;
+                ++deaths;
+                id = ((nc ? 0ull : 1ull) << 62) | ((uint64_t)k << 30);
             } else {
-                emit = spawn_attempt<W, T>(S, d, it.A[item], it.n[item], nc ? kSpawnNonComposite : kSpawnSampled, k,
-                                           slot - 1, a, tgt, x);
+                const uint64_t orb = c_orb[e];
+                const int i = (int16_t)(orb & 0xFFFF), j = (int16_t)((orb >> 16) & 0xFFFF);
+                const int ta = (int16_t)((orb >> 32) & 0xFFFF), tb = (int16_t)((orb >> 48) & 0xFFFF);
+#pragma unroll
+                for (int w = 0; w < W; ++w) tgt[w] = d[w];
+                bit_flip<W>(tgt, i);
+                bit_flip<W>(tgt, ta);
+                if (j >= 0) {
+                    bit_flip<W>(tgt, j);
+                    bit_flip<W>(tgt, tb);
+                }
+                emit = spawn_amount<W, T>(S, d, tgt, i, j, ta, tb, it.A[item], it.n[item],
+                                          nc ? kSpawnNonComposite : kSpawnSampled, k, cs - 1, a, x);
                 spawns += emit ? 1u : 0u;
+                id = ((nc ? 0ull : 1ull) << 62) | ((uint64_t)k << 30) | (uint64_t)cs;
             }
-            id = ((nc ? 0ull : 1ull) << 62) | ((uint64_t)k << 30) | (uint64_t)slot;
         }
-        // compaction in slot order
-        const uint64_t m = __ballot(emit);
-        if (lane_id() == 0) wave_tot[wave_id()] = (uint32_t)__popcll(m);
+        const uint64_t mk = __ballot(emit);
+        if (lane_id() == 0) wave_tot[wave_id()] = (uint32_t)__popcll(mk);
         __syncthreads();
         uint32_t before = 0, total = 0;
 #pragma unroll
@@ -670,7 +762,7 @@ __device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDe
             total += wave_tot[w];
         }
         if (emit) {
-            const uint64_t dst = g0 + base + before + (uint32_t)lanes_below(m);
+            const uint64_t dst = g0 + base + before + (uint32_t)lanes_below(mk);
 #pragma unroll
             for (int w = 0; w < W; ++w) rec.key[(uint64_t)w * rec.stride + dst] = tgt[w];
             ramp[dst] = x;

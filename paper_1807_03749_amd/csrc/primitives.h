@@ -14,7 +14,7 @@ constexpr int kThreads = 256;           // 4 wavefronts of 64
 constexpr int kWaves = kThreads / 64;
 constexpr int kScanItems = 8;           // items per thread in scans
 constexpr int kScanTile = kThreads * kScanItems;
-constexpr int kSortItems = 8;           // rounds of 256 keys per radix tile
+constexpr int kSortItems = 8;           // keys per thread of a radix tile
 constexpr int kSortTile = kThreads * kSortItems;
 constexpr int kRadixBits = 9;           // digit width of the radix sort
 constexpr int kRadixBins = 1 << kRadixBits;
