@@ -102,7 +102,7 @@ struct ccmc_state {
     DevBuf block_item, gcount, gspawn, gdeath, boff;
     DevBuf rkey, ramp, rid;  // per-block record regions
     uint64_t rcap = 0;              // region slots
-    DevBuf drank, dkey, damp, did, sr[2], sidx[2];
+    DevBuf drank, dkey, damp, did, sr[2], sidx[2], tile_region;
     DevBuf is_new, new_pos, ins, seg_sum, nkey, nrank, nins, nsum, keep, pos;
     uint64_t dcap = 0;  // dense record capacity
     uint64_t slot_hint = 1 << 16, rec_hint = 1 << 14;  // capacities planned for the next step
@@ -621,6 +621,7 @@ ccmc_status plan_sizes(Plan<W, T> &p)
             TRY(ensure(st, *b, nc * sizeof(uint64_t)));
         for (DevBuf *b : {&st->sidx[0], &st->sidx[1], &st->is_new, &st->new_pos}) TRY(ensure(st, *b, nc * sizeof(uint32_t)));
         for (DevBuf *b : {&st->seg_sum, &st->nsum}) TRY(ensure(st, *b, nc * sizeof(double)));
+        TRY(ensure(st, st->tile_region, (nc / kGatherTile + 2) * sizeof(uint32_t)));
         st->dcap = nc;
     }
     if (p.ids && st->did.bytes < st->dcap * sizeof(uint64_t)) TRY(ensure(st, st->did, st->dcap * sizeof(uint64_t)));
@@ -872,19 +873,20 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
               [s](const A *a, BatchMap bm, unsigned g) { k_generate<W, T><<<g, kThreads, 0, s>>>(a, bm); });
     }
     {
-        using A = ScanLbArgs<uint32_t, CountSrc<uint32_t>, ArrayOut<uint32_t>>;
+        using A = ScanLbArgs<uint32_t, CountSrc<uint32_t>, RegionOut>;
         std::vector<A> args;
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
             ccmc_state *st = p.st;
             args.push_back(A{CountSrc<uint32_t>{ptr<uint32_t>(st->gcount), p.nblk_cap},
-                             ArrayOut<uint32_t>{ptr<uint32_t>(st->boff)}, p.nblk_cap + 1, 0, p.lb + p.o_boff,
-                             p.lb + p.o_tick + kTkBoff, &p.sc->n_rec});
+                             RegionOut{ptr<uint32_t>(st->boff), ptr<uint32_t>(st->tile_region), st->dcap / kGatherTile + 2},
+                             p.nblk_cap + 1, 0,
+                             p.lb + p.o_boff, p.lb + p.o_tick + kTkBoff, &p.sc->n_rec});
             blk[i] = (uint32_t)scan_tiles(p.nblk_cap + 1);
         }
         stage(ar, recs, "region_scan", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.nblk_cap + 1}; }),
               [s](const A *a, BatchMap bm, unsigned g) {
-                  k_scan_lb<uint32_t, CountSrc<uint32_t>, ArrayOut<uint32_t>><<<g, kThreads, 0, s>>>(a, bm);
+                  k_scan_lb<uint32_t, CountSrc<uint32_t>, RegionOut><<<g, kThreads, 0, s>>>(a, bm);
               });
     }
     auto dense_of = [&](Plan<W, T> &p) {
@@ -897,9 +899,9 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
             ccmc_state *st = p.st;
-            args.push_back(A{st->sd, regions_of(p), ptr<uint32_t>(st->boff), p.nblk_cap, p.rec_cap, dense_of(p),
-                             p.ids ? 1 : 0, p.sc});
-            blk[i] = grid_for(p.rec_cap);
+            args.push_back(A{st->sd, regions_of(p), ptr<uint32_t>(st->boff), ptr<uint32_t>(st->tile_region), p.nblk_cap,
+                             p.rec_cap, dense_of(p), p.ids ? 1 : 0, p.sc});
+            blk[i] = grid_for(p.rec_cap, kGatherTile);
         }
         stage(ar, recs, "gather", args, blk, works([&](auto &p) {
                   return Work{2.0 * (kb + tb + (p.ids ? 8.0 : 0.0)) + 8.0, &p.st->cnt_rec, 0};
@@ -1368,7 +1370,7 @@ void destroy(ccmc_state *st)
                       &st->sK[1], &st->srank[0], &st->srank[1], &st->P, &st->guide, &st->delta, &st->rtab, &st->ikey,
                       &st->iA, &st->ideath, &st->in, &st->ilevel, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,
                       &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->boff, &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
-                      &st->sidx[0], &st->sidx[1], &st->is_new,
+                      &st->sidx[0], &st->sidx[1], &st->tile_region, &st->is_new,
                       &st->new_pos, &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->keep,
                       &st->pos, &st->lb, &st->arg_dev, &st->batch_scr};
     for (DevBuf *b : bufs) release(st, *b);

@@ -804,41 +804,94 @@ __global__ void __launch_bounds__(kThreads) k_generate(const GenerateArgs<W, T> 
     generate_body<W, T>(blk, nblk, A.S, A.it, A.off, A.block_item, A.n_fnc, A.n_items, A.slot_cap, A.a, A.rec, A.keep_ids, A.gs, A.sc);
 }
 
-// Dense layout of the records: output position r comes from the block b with
-// boff[b] <= r < boff[b+1], at slot position r - boff[b] of its region.
+// Dense layout of the records.  Output position r belongs to the region q (generation block
+// q) with boff[q] <= r < boff[q+1], at slot position r - boff[q] of that region.  Block b
+// writes the outputs [b * kGatherTile, (b + 1) * kGatherTile): its first region comes from
+// tile_region (scattered by the region scan), the region offsets of its range are staged in
+// LDS and each output finds its region there.  The truncated-space rank of each record (the
+// sort key) is computed on the way.
+constexpr int kGatherTile = 256;
+constexpr int kGatherLds = 2048;
+
+// Output of the region scan: the record offset of every region, and the region holding the
+// first output of each gather tile, scattered by the regions themselves.
+struct RegionOut {
+    uint32_t *p;
+    uint32_t *tile_region;
+    uint64_t cap;  // entries of tile_region (records past the dense capacity are never gathered)
+    __device__ __forceinline__ void item(uint64_t q, uint32_t excl, uint32_t x, bool valid) const
+    {
+        uint64_t b0 = 0, b1 = 0;
+        if (valid && x) {
+            b0 = (excl + kGatherTile - 1) / kGatherTile;
+            b1 = ((uint64_t)excl + x - 1) / kGatherTile + 1;  // tiles whose first output is < excl + x
+            b1 = b1 < cap ? b1 : cap;
+            b0 = b0 < b1 ? b0 : b1;
+        }
+        wave_fill_ranges<uint32_t>(tile_region, b0, b1, (uint32_t)q);
+    }
+};
+
 template <int W, typename T>
 __device__ __forceinline__ void gather_body(uint32_t blk, uint32_t nblk, const SysDev S, Records reg, const uint32_t *__restrict__ boff,
-                                                     uint64_t n_blocks, uint64_t rec_cap, Records out, int keep_ids, Scratch *sc)
+                                            const uint32_t *__restrict__ tile_region, uint64_t n_blocks, uint64_t rec_cap,
+                                            Records out, int keep_ids, Scratch *sc)
 {
-    const uint64_t r = (uint64_t)blk * kThreads + threadIdx.x;
+    __shared__ uint32_t s_b[kGatherLds + 1];
     // records the annihilation works on: all of them, or none after a capacity overflow
     const uint64_t nr = sc->n_rec;
     const bool over = nr > rec_cap || (sc->err & kErrSlotCap);
     const uint64_t live = over ? 0 : nr;
-    if (r == 0) {
+    if (blk == 0 && threadIdx.x == 0) {
         sc->n_live = live;
         if (nr > rec_cap) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrRecCap);
     }
-    if (r >= live) return;
-    uint64_t l0 = 0, h0 = n_blocks + 1;  // last b with boff[b] <= r
-    while (l0 < h0) {
-        const uint64_t mid = (l0 + h0) >> 1;
-        if (boff[mid] > r)
-            h0 = mid;
-        else
-            l0 = mid + 1;
-    }
-    const uint64_t b = l0 - 1;
-    const uint64_t src = b * kGenSlots + (r - boff[b]);
-    uint64_t d[W];
+    const uint64_t o0 = (uint64_t)blk * kGatherTile;
+    if (o0 >= live) return;
+    const uint64_t o1 = o0 + kGatherTile < live ? o0 + kGatherTile : live;
+    const uint32_t qa = tile_region[blk];
+    const uint32_t qb = o1 < live ? tile_region[blk + 1] : (uint32_t)(n_blocks - 1);
+    const uint32_t nq = qb - qa + 1;  // regions [qa, qb] hold this tile's outputs
+    const bool lds = nq + 1 <= (uint32_t)kGatherLds;
+    if (lds)
+        for (uint32_t t = threadIdx.x; t <= nq; t += kThreads) s_b[t] = boff[qa + t];
+    __syncthreads();
+    for (uint64_t r = o0 + threadIdx.x; r < o1; r += kThreads) {
+        uint32_t l0, h0, q;
+        if (lds) {  // last q in [qa, qb] with boff[q] <= r
+            l0 = 0;
+            h0 = nq;
+            while (l0 < h0) {
+                const uint32_t mid = (l0 + h0) >> 1;
+                if (s_b[mid] > r)
+                    h0 = mid;
+                else
+                    l0 = mid + 1;
+            }
+            q = qa + l0 - 1;
+        } else {
+            l0 = qa;
+            h0 = qb + 1;
+            while (l0 < h0) {
+                const uint32_t mid = (l0 + h0) >> 1;
+                if (boff[mid] > r)
+                    h0 = mid;
+                else
+                    l0 = mid + 1;
+            }
+            q = l0 - 1;
+        }
+        const uint64_t src = (uint64_t)q * kGenSlots + (r - (lds ? s_b[q - qa] : boff[q]));
+        uint64_t d[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-        d[w] = reg.key[(uint64_t)w * reg.stride + src];
-        out.key[(uint64_t)w * out.stride + r] = d[w];
+        for (int w = 0; w < W; ++w) {
+            d[w] = reg.key[(uint64_t)w * reg.stride + src];
+            out.key[(uint64_t)w * out.stride + r] = d[w];
+        }
+        out.rank[r] = space_rank<W>(S, d);
+        static_cast<T *>(out.amp)[r] = static_cast<const T *>(reg.amp)[src];
+        if (keep_ids) out.id[r] = reg.id[src];
     }
-    out.rank[r] = space_rank<W>(S, d);
-    static_cast<T *>(out.amp)[r] = static_cast<const T *>(reg.amp)[src];
-    if (keep_ids) out.id[r] = reg.id[src];
 }
 
 template <int W, typename T>
@@ -846,6 +899,7 @@ struct GatherArgs {
     const SysDev S;
     Records reg;
     const uint32_t *boff;
+    const uint32_t *tile_region;
     uint64_t n_blocks;
     uint64_t rec_cap;
     Records out;
@@ -858,7 +912,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(const GatherArgs<W, T> *__r
 {
     uint32_t blk, nblk;
     const GatherArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
-    gather_body<W, T>(blk, nblk, A.S, A.reg, A.boff, A.n_blocks, A.rec_cap, A.out, A.keep_ids, A.sc);
+    gather_body<W, T>(blk, nblk, A.S, A.reg, A.boff, A.tile_region, A.n_blocks, A.rec_cap, A.out, A.keep_ids, A.sc);
 }
 
 // ---------------------------------------------------------------- annihilation
