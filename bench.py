@@ -41,6 +41,12 @@ ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # (UEG) / 150 (molecular) for the excitation, the Slater-Condon element, the signs, the
 # amplitude and the cutoff rounding.
 OPS_PER_ATTEMPT = {"ueg": 300.0, "mol": 450.0}
+# Algorithmic lane operations of one item of the items kernel (a sampled cluster or a
+# non-composite item): about two Philox blocks for the size and the excitor draws (E[blocks]
+# = 2.2 for CCSDT composites, s in [2, 5]) = 220, plus about 80 for the prefix searches, the
+# collapse with its sign, the level and the amplitude.
+OPS_PER_ITEM = 300.0
+ALU_KERNELS = {"generate": ("attempt", lambda w: OPS_PER_ATTEMPT[w.system]), "items": ("item", lambda w: OPS_PER_ITEM)}
 
 
 class _Roctx:
@@ -213,18 +219,20 @@ def measured_traffic(kernel: str, workload: str):
 
 def roofline(timed: dict, w: inputs.Workload):
     """Roofline entry for the dominant kernel, from its HIP-event durations in the timed
-    region.  generate is bound by the vector ALUs: its algorithmic work is the integer and
-    FP operations of one spawning attempt (OPS_PER_ATTEMPT); every other kernel is priced
-    by its algorithmic HBM bytes against the 8 TB/s peak."""
+    region.  generate and items are bound by the vector ALUs: their algorithmic work is the
+    integer and FP operations of one spawning attempt (OPS_PER_ATTEMPT) or one item
+    (OPS_PER_ITEM); every other kernel is priced by its algorithmic HBM bytes against the
+    8 TB/s peak."""
     if not timed:
         return None
     name, p = max(timed.items(), key=lambda kv: kv[1]["ms"])
     avg_s = p["ms"] / p["launches"] / 1e3
-    if name == "generate":
-        ops = OPS_PER_ATTEMPT[w.system]
+    if name in ALU_KERNELS:
+        unit, ops_of = ALU_KERNELS[name]
+        ops = ops_of(w)
         achieved = p["items"] / p["launches"] * ops / avg_s / 1e9
-        r = dict(bound="alu", achieved=achieved, peak=ALU_PEAK_GOPS, unit="Gop/s",
-                 ops_per_attempt=ops, attempts_per_launch=p["items"] / p["launches"])
+        r = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_GOPS, "unit": "Gop/s",
+             f"ops_per_{unit}": ops, f"{unit}s_per_launch": p["items"] / p["launches"]}
     else:
         achieved = p["bytes"] / p["launches"] / avg_s / 1e9
         r = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s")
