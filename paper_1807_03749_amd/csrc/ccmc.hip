@@ -472,7 +472,7 @@ ccmc_status upload_system(ccmc_state *st, const ccmc_integrals *ints)
 // ------------------------------------------------------------------------ the store
 // Entries of the selection guide for a store capacity: several times the buckets the shift
 // aims at, so that Q may grow between steps before draws fall past the table.
-uint64_t guide_cap(uint64_t scap) { return 2 * scap + 8; }
+uint64_t guide_cap(uint64_t scap) { return 4 * scap + 8; }
 
 // Grow the store (both buffers) to hold n entries, keeping the current contents.
 template <int W, typename T>
@@ -579,10 +579,10 @@ ccmc_status plan_sizes(Plan<W, T> &p)
     a.fnc = p.fnc ? 1 : 0;
     {
         // guide shift from the last step's Q (any shift gives the same draws; this one keeps
-        // about one bucket per two excitors, so that large amplitudes own few buckets)
+        // about two buckets per excitor)
         const uint64_t q_est = st->last_q ? st->last_q : (ne << 24);
         uint32_t sh = 0;
-        while (sh < 63 && (q_est >> sh) + 2 > ne / 2 + 2) ++sh;
+        while (sh < 63 && (q_est >> sh) + 2 > 2 * ne + 2) ++sh;
         a.gsh = sh;
     }
     p.slot_cap = std::max<uint64_t>(kGenSlots, (st->slot_hint + kGenSlots - 1) / kGenSlots * kGenSlots);
@@ -786,21 +786,34 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         stage(ar, recs, "clear", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.lb_words}; }),
               [s](const ClearArgs *a, BatchMap bm, unsigned g) { k_clear<<<g, kThreads, 0, s>>>(a, bm); });
     }
-    // ---- (a1) selection weights, formed inside the scan of their prefix, with the excitor-draw guide
+    // ---- (a1) selection weights, formed inside the scan of their prefix; the draw guide
     {
-        using A = ScanLbArgs<uint64_t, WeightSrc<T>, WeightOut>;
+        using A = ScanLbArgs<uint64_t, WeightSrc<T>, ArrayOut<uint64_t>>;
         std::vector<A> args;
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
             ccmc_state *st = p.st;
-            const WeightOut wo{ptr<uint64_t>(st->P), ptr<uint32_t>(st->guide), p.a.gcap, p.a.gsh, p.ne};
-            args.push_back(A{WeightSrc<T>{ptr<T>(st->samp[p.c]), p.sc}, wo, p.ne, 1, p.lb + p.o_weights,
-                             p.lb + p.o_tick + kTkWeights, &p.sc->qtot});
+            args.push_back(A{WeightSrc<T>{ptr<T>(st->samp[p.c]), p.sc}, ArrayOut<uint64_t>{ptr<uint64_t>(st->P)}, p.ne, 1,
+                             p.lb + p.o_weights, p.lb + p.o_tick + kTkWeights, &p.sc->qtot});
             blk[i] = (uint32_t)scan_tiles(p.ne);
         }
-        // bytes: amplitude read, prefix written, about two guide entries
-        stage(ar, recs, "weights_scan", args, blk, works([&](auto &p) { return Work{tb + 16.0, nullptr, p.ne}; }),
-              [s](const A *a, BatchMap bm, unsigned g) { k_scan_lb<uint64_t, WeightSrc<T>, WeightOut><<<g, kThreads, 0, s>>>(a, bm); });
+        // bytes: amplitude read, prefix written
+        stage(ar, recs, "weights_scan", args, blk, works([&](auto &p) { return Work{tb + 8.0, nullptr, p.ne}; }),
+              [s](const A *a, BatchMap bm, unsigned g) {
+                  k_scan_lb<uint64_t, WeightSrc<T>, ArrayOut<uint64_t>><<<g, kThreads, 0, s>>>(a, bm);
+              });
+    }
+    {
+        std::vector<GuideArgs> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            args.push_back(GuideArgs{ptr<uint64_t>(st->P), ptr<uint32_t>(st->guide), p.a.gcap, p.a.gsh, p.ne});
+            blk[i] = p.n_sel && p.ne ? grid_for(p.ne) : 0;
+        }
+        // bytes: prefix read, about one guide entry per two excitors
+        stage(ar, recs, "guide", args, blk, works([&](auto &p) { return Work{10.0, nullptr, p.ne}; }),
+              [s](const GuideArgs *a, BatchMap bm, unsigned g) { k_guide<<<g, kThreads, 0, s>>>(a, bm); });
     }
     // ---- (a2-a5, a9, a10) items: non-composite (FNC) then sampled clusters; then the rank table
     const double item_bytes = kb + 2 * tb + 13.0;  // key, A, death, n, level, slot count

@@ -2,8 +2,8 @@
 //
 // One step, in launch order (scans are single launches with decoupled look-back):
 //   k_fill           clear the step scalars and look-back status words
-//   weights scan     fixed-point selection weights q_i and their prefix, with    (a1)
-//                    the excitor-draw guide
+//   weights scan     fixed-point selection weights q_i and their prefix          (a1)
+//   k_guide          bucket table of the prefix for the excitor draws           (a2)
 //   k_items          non-composite items (FNC): reference + every excitor        (a4, a5, a9, a10)
 //                    and sampled clusters: size, excitor draws, collapse, amplitude  (a2, a3, a4, a9, a10)
 //   slot scan        record slots per item (1 death + n attempts), first item per block
@@ -137,32 +137,37 @@ struct WeightSrc {
     }
 };
 
-// The guide of the excitor draws, built while the weights are scanned (one lane per excitor
-// g, exclusive prefix lo, inclusive prefix hi = P[g]): a draw x in [0, Q) falls in bucket
-// x >> gsh, and guide[b] is the first excitor whose prefix exceeds b << gsh, so the drawn
-// excitor lies in [guide[b], guide[b+1]] -- a short search instead of one over the whole
-// store.  Excitor g owns the buckets with lo <= b << gsh < hi; the last one also owns the two
-// closing buckets.  The shift comes from the host (from the previous step's Q), so buckets
-// past the capacity gcap may exist: draws there search from guide[gcap - 1] to the end.
-struct WeightOut {
-    uint64_t *p;
+// The guide of the excitor draws, one lane per excitor g (exclusive prefix lo = P[g-1],
+// inclusive prefix hi = P[g]): a draw x in [0, Q) falls in bucket x >> gsh, and guide[b] is the
+// first excitor whose prefix exceeds b << gsh, so the drawn excitor lies in
+// [guide[b], guide[b+1]] -- a short search instead of one over the whole store.  Excitor g
+// owns the buckets with lo <= b << gsh < hi (a large amplitude owns many: its wavefront writes
+// them together); the last one also owns the two closing buckets.  The shift comes from the
+// host (from the previous step's Q), so buckets past the capacity gcap may exist: draws there
+// search from guide[gcap - 1] to the end.
+struct GuideArgs {
+    const uint64_t *P;
     uint32_t *guide;
     uint64_t gcap;
     uint32_t gsh;
     uint64_t n;
-    __device__ __forceinline__ void item(uint64_t g, uint64_t lo, uint64_t x, bool valid) const
-    {
-        uint64_t b0 = 0, b1 = 0;
-        if (valid) {
-            const uint64_t unit = 1ull << gsh, hi = lo + x;
-            b0 = (lo + unit - 1) >> gsh;
-            b1 = g + 1 == n ? (hi >> gsh) + 2 : (hi + unit - 1) >> gsh;
-            b1 = b1 < gcap ? b1 : gcap;
-            b0 = b0 < b1 ? b0 : b1;
-        }
-        wave_fill_ranges<uint32_t>(guide, b0, b1, (uint32_t)g);
-    }
 };
+
+__global__ void __launch_bounds__(kThreads) k_guide(const GuideArgs *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const GuideArgs &A = args[batch_state(bm, blk, nblk)];
+    const uint64_t g = (uint64_t)blk * kThreads + threadIdx.x;
+    uint64_t b0 = 0, b1 = 0;
+    if (g < A.n) {
+        const uint64_t unit = 1ull << A.gsh, lo = g ? A.P[g - 1] : 0, hi = A.P[g];
+        b0 = (lo + unit - 1) >> A.gsh;
+        b1 = g + 1 == A.n ? (hi >> A.gsh) + 2 : (hi + unit - 1) >> A.gsh;
+        b1 = b1 < A.gcap ? b1 : A.gcap;
+        b0 = b0 < b1 ? b0 : b1;
+    }
+    wave_fill_ranges<uint32_t>(A.guide, b0, b1, (uint32_t)g);
+}
 
 // The rank table of the store lookups: rtab[c] is the first store entry whose rank is at
 // least c << rsh, so a rank r lies in [rtab[r >> rsh], rtab[(r >> rsh) + 1]].  One lane per
