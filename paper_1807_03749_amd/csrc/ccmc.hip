@@ -103,7 +103,7 @@ struct ccmc_state {
     DevBuf rkey, ramp, rid;  // per-block record regions
     uint64_t rcap = 0;              // region slots
     DevBuf drank, dkey, damp, did, sr[2], sidx[2], tile_region;
-    DevBuf is_new, new_pos, ins, seg_sum, nkey, nrank, nins, nsum, keep, pos;
+    DevBuf ins, seg_sum, nkey, nrank, nins, nsum, keep, pos;
     uint64_t dcap = 0;  // dense record capacity
     uint64_t slot_hint = 1 << 16, rec_hint = 1 << 14;  // capacities planned for the next step
     uint64_t cnt_slots = 0, cnt_rec = 0, cnt_merged = 0, cnt_new = 0, cnt_att = 0, cnt_live_items = 0;  // live counts of the last step
@@ -542,7 +542,7 @@ struct Plan {
     uint64_t ne = 0, n_fnc = 0, n_items = 0, slot_cap = 0, nblk_cap = 0, rec_cap = 0, mcap = 0, tiles = 0;
     uint64_t fold_tiles = 0, fin_blocks = 1, n_parts = 0, lb_words = 0;
     unsigned nb_fnc = 0, nb_sel = 0, nb_rt = 0, nb_abs = 0;
-    uint64_t o_tick = 0, o_weights = 0, o_off = 0, o_boff = 0, o_new = 0, o_keep = 0, o_ghist = 0, o_rstat = 0;
+    uint64_t o_tick = 0, o_weights = 0, o_off = 0, o_boff = 0, o_keep = 0, o_ghist = 0, o_rstat = 0;
     uint64_t o_fold = 0, o_fin = 0;
     uint64_t *lb = nullptr;
     Scratch *sc = nullptr;
@@ -550,7 +550,7 @@ struct Plan {
     bool replay = false;       // a capacity overflowed: grow and step again
 };
 
-enum { kTkWeights, kTkOff, kTkBoff, kTkNew, kTkKeep, kTkRadix, kTickets = kTkRadix + kRadixMaxPasses };
+enum { kTkWeights, kTkOff, kTkBoff, kTkFold, kTkKeep, kTkRadix, kTickets = kTkRadix + kRadixMaxPasses };
 
 // Sizes and capacities of one state's step (all allocation happens here).
 template <int W, typename T>
@@ -619,7 +619,7 @@ ccmc_status plan_sizes(Plan<W, T> &p)
         TRY(ensure(st, st->damp, nc * sizeof(T)));
         for (DevBuf *b : {&st->drank, &st->sr[0], &st->sr[1], &st->ins, &st->nins, &st->nrank})
             TRY(ensure(st, *b, nc * sizeof(uint64_t)));
-        for (DevBuf *b : {&st->sidx[0], &st->sidx[1], &st->is_new, &st->new_pos}) TRY(ensure(st, *b, nc * sizeof(uint32_t)));
+        for (DevBuf *b : {&st->sidx[0], &st->sidx[1]}) TRY(ensure(st, *b, nc * sizeof(uint32_t)));
         for (DevBuf *b : {&st->seg_sum, &st->nsum}) TRY(ensure(st, *b, nc * sizeof(double)));
         TRY(ensure(st, st->tile_region, (nc / kGatherTile + 2) * sizeof(uint32_t)));
         st->dcap = nc;
@@ -662,12 +662,11 @@ ccmc_status plan_area(Plan<W, T> &p, int passes)
     p.o_weights = p.o_tick + kTickets;
     p.o_off = p.o_weights + scan_tiles(p.ne);
     p.o_boff = p.o_off + scan_tiles(p.n_items + 1);
-    p.o_new = p.o_boff + scan_tiles(p.nblk_cap + 1);
-    p.o_keep = p.o_new + scan_tiles(p.rec_cap);
+    p.o_keep = p.o_boff + scan_tiles(p.nblk_cap + 1);
     p.o_ghist = p.o_keep + scan_tiles(p.mcap);
     p.o_rstat = p.o_ghist + (uint64_t)passes * kRadixBins / 2;
     p.o_fold = p.o_rstat + (uint64_t)passes * p.tiles * kRadixBins;
-    p.o_fin = p.o_fold + 3 * p.fold_tiles;
+    p.o_fin = p.o_fold + 5 * p.fold_tiles;  // lead, has_head, open, open_new, look-back status
     p.lb_words = p.o_fin + kMaxFinalParts * (sizeof(FinalPart) / 8);
     TRY(ensure(st, st->lb, p.lb_words * sizeof(uint64_t)));
     p.lb = ptr<uint64_t>(st->lb);
@@ -956,23 +955,27 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
     const int sorted = (passes - 1) & 1;  // buffer of the last pass
     // ---- (a12) runs of equal determinants: fold in record order, store lookup by rank
     auto fold_of = [&](Plan<W, T> &p) {
-        return FoldTiles{reinterpret_cast<double *>(p.lb + p.o_fold), reinterpret_cast<uint32_t *>(p.lb + p.o_fold + p.fold_tiles),
-                         p.lb + p.o_fold + 2 * p.fold_tiles};
+        uint64_t *f = p.lb + p.o_fold;
+        const uint64_t nt = p.fold_tiles;
+        return FoldTiles{reinterpret_cast<double *>(f), reinterpret_cast<uint32_t *>(f + nt), f + 2 * nt, f + 3 * nt,
+                         f + 4 * nt, p.lb + p.o_tick + kTkFold};
     };
     {
-        using A = SegFoldArgs<T>;
+        using A = SegFoldArgs<W, T>;
         std::vector<A> args;
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
             ccmc_state *st = p.st;
+            const NewDets nd{ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), ptr<uint64_t>(st->nins), ptr<double>(st->nsum),
+                             st->dcap, ptr<uint64_t>(st->dkey), st->dcap};
             args.push_back(A{ptr<uint64_t>(st->sr[sorted]), ptr<uint32_t>(st->sidx[sorted]), ptr<T>(st->damp), p.rec_cap,
-                             ptr<uint64_t>(st->srank[p.c]), p.ne, ptr<double>(st->delta), ptr<uint32_t>(st->is_new),
-                             ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum), ptr<uint32_t>(st->rtab), st->rt_n, st->rsh,
-                             fold_of(p), p.sc});
+                             ptr<uint64_t>(st->srank[p.c]), p.ne, ptr<double>(st->delta), ptr<uint64_t>(st->ins),
+                             ptr<double>(st->seg_sum), ptr<uint32_t>(st->rtab), st->rt_n, st->rsh, fold_of(p), nd, p.sc});
             blk[i] = (uint32_t)p.fold_tiles;
         }
-        stage(ar, recs, "seg_fold", args, blk, works([&](auto &p) { return Work{8.0 + 4.0 + tb + 4.0, &p.st->cnt_rec, 0}; }),
-              [s](const A *a, BatchMap bm, unsigned g) { k_seg_fold<T><<<g, kThreads, 0, s>>>(a, bm); });
+        // bytes: rank, index, gathered amount and (per head) the new-determinant entry
+        stage(ar, recs, "seg_fold", args, blk, works([&](auto &p) { return Work{8.0 + 4.0 + tb, &p.st->cnt_rec, 0, nullptr, kb + 24.0, &p.st->cnt_new}; }),
+              [s](const A *a, BatchMap bm, unsigned g) { k_seg_fold<W, T><<<g, kThreads, 0, s>>>(a, bm); });
     }
     {
         std::vector<SegCloseArgs> args;
@@ -980,42 +983,12 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             auto &p = ps[i];
             ccmc_state *st = p.st;
             args.push_back(SegCloseArgs{ptr<uint64_t>(st->sr[sorted]), p.fold_tiles, ptr<uint64_t>(st->srank[p.c]), p.ne,
-                                        ptr<double>(st->delta), ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum), fold_of(p),
-                                        p.sc});
+                                        ptr<double>(st->delta), ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum),
+                                        ptr<double>(st->nsum), fold_of(p), p.sc});
             blk[i] = grid_for(p.fold_tiles);
         }
         stage(ar, recs, "seg_close", args, blk, works([&](auto &p) { return Work{24.0, nullptr, p.fold_tiles}; }),
               [s](const SegCloseArgs *a, BatchMap bm, unsigned g) { k_seg_close<<<g, kThreads, 0, s>>>(a, bm); });
-    }
-    {
-        using A = ScanLbArgs<uint32_t, ArraySrc<uint32_t>, ArrayOut<uint32_t>>;
-        std::vector<A> args;
-        for (size_t i = 0; i < n; ++i) {
-            auto &p = ps[i];
-            ccmc_state *st = p.st;
-            args.push_back(A{ArraySrc<uint32_t>{ptr<uint32_t>(st->is_new)}, ArrayOut<uint32_t>{ptr<uint32_t>(st->new_pos)},
-                             p.rec_cap, 0, p.lb + p.o_new, p.lb + p.o_tick + kTkNew, &p.sc->n_new});
-            blk[i] = (uint32_t)scan_tiles(p.rec_cap);
-        }
-        stage(ar, recs, "new_scan", args, blk, works([&](auto &p) { return Work{8.0, &p.st->cnt_rec, 0}; }),
-              [s](const A *a, BatchMap bm, unsigned g) {
-                  k_scan_lb<uint32_t, ArraySrc<uint32_t>, ArrayOut<uint32_t>><<<g, kThreads, 0, s>>>(a, bm);
-              });
-    }
-    {
-        using A = NewCompactArgs<W>;
-        std::vector<A> args;
-        for (size_t i = 0; i < n; ++i) {
-            auto &p = ps[i];
-            ccmc_state *st = p.st;
-            args.push_back(A{ptr<uint64_t>(st->sr[sorted]), ptr<uint32_t>(st->sidx[sorted]), ptr<uint64_t>(st->dkey), st->dcap,
-                             p.rec_cap, ptr<uint32_t>(st->is_new), ptr<uint32_t>(st->new_pos), ptr<uint64_t>(st->ins),
-                             ptr<double>(st->seg_sum), ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), st->dcap,
-                             ptr<uint64_t>(st->nins), ptr<double>(st->nsum), p.sc});
-            blk[i] = grid_for(p.rec_cap);
-        }
-        stage(ar, recs, "new_compact", args, blk, works([&](auto &p) { return Work{2.0 * (kb + 24.0) + 8.0, &p.st->cnt_new, 0}; }),
-              [s](const A *a, BatchMap bm, unsigned g) { k_new_compact<W><<<g, kThreads, 0, s>>>(a, bm); });
     }
     // ---- (a12, a13) merge and round into the other store buffer, compact back into this one
     const double eb = kb + 2 * tb + 8.0;  // one store entry: key, amplitude, diagonal, rank
@@ -1383,8 +1356,8 @@ void destroy(ccmc_state *st)
                       &st->sK[1], &st->srank[0], &st->srank[1], &st->P, &st->guide, &st->delta, &st->rtab, &st->ikey,
                       &st->iA, &st->ideath, &st->in, &st->ilevel, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,
                       &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->boff, &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
-                      &st->sidx[0], &st->sidx[1], &st->tile_region, &st->is_new,
-                      &st->new_pos, &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->keep,
+                      &st->sidx[0], &st->sidx[1], &st->tile_region,
+                      &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->keep,
                       &st->pos, &st->lb, &st->arg_dev, &st->batch_scr};
     for (DevBuf *b : bufs) release(st, *b);
     for (auto &p : st->pending) {

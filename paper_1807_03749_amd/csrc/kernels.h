@@ -11,8 +11,8 @@
 //   region scan      records per generation block
 //   k_gather         dense records and their truncated-space rank               (a8)
 //   radix sort       stable LSD sort of (rank, record index)                    (a11)
-//   k_seg_fold       left fold of each run in record order, store lookup        (a12)
-//   new scan, k_new_compact   determinants not in the store
+//   k_seg_fold       sum of each run in record order, store lookup, new         (a12)
+//                    determinants numbered by look-back; k_seg_close for runs across tiles
 //   k_merge          merge, then occupation rounding                            (a12, a13)
 //   keep scan, k_compact      survivors back into the store
 //   k_final          FP64 population, projected-energy and count reductions    (a14)
@@ -938,32 +938,48 @@ struct FoldTiles {
     double *lead;       // per tile: left fold of its records before its first run head
     uint32_t *has_head; // per tile: any run head in the tile
     uint64_t *open;     // per tile: record index of its open head, or kNoOpen
+    uint64_t *open_new; // per tile: new-determinant index of its open head (if new)
+    uint64_t *status;   // per tile: look-back status of the count of new determinants
+    uint64_t *ticket;
 };
 
-template <typename T>
+// The determinants that are not in the store, in rank order: bitstring, rank, insertion
+// point in the store and summed amount.
+struct NewDets {
+    uint64_t *key;
+    uint64_t *rank;
+    uint64_t *ins;
+    double *sum;
+    uint64_t stride;
+    const uint64_t *rkey;  // dense record bitstrings (stride rstride)
+    uint64_t rstride;
+};
+
+template <int W, typename T>
 __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ rank, const uint32_t *__restrict__ idx,
                                                        const T *__restrict__ ramp, uint64_t cap,
                                                        const uint64_t *__restrict__ srank, uint64_t ne,
-                                                       double *__restrict__ delta, uint32_t *__restrict__ is_new,
-                                                       uint64_t *__restrict__ ins, double *__restrict__ seg_sum,
+                                                       double *__restrict__ delta, uint64_t *__restrict__ ins,
+                                                       double *__restrict__ seg_sum,
                                                        const uint32_t *__restrict__ rtab, uint64_t rt_n, uint32_t rsh,
-                                                       FoldTiles ft, Scratch *sc)
+                                                       FoldTiles ft, NewDets nd, Scratch *sc)
 {
     __shared__ double s_lead[kThreads];
     __shared__ uint32_t s_head[kThreads];
-    __shared__ uint64_t s_open;
+    __shared__ uint64_t s_open, s_open_new, s_tile, s_prefix;
     const uint64_t n = sc->n_live;
-    const uint64_t base = (uint64_t)blk * kFoldTile;
+    // tiles in ticket order: the look-back over the counts of new determinants only waits
+    // for tiles that are already running
+    if (threadIdx.x == 0) s_tile = atomicAdd((unsigned long long *)ft.ticket, 1ull);
+    __syncthreads();
+    const uint64_t tile = s_tile;
+    const uint64_t base = tile * kFoldTile;
     const uint64_t r0 = base + (uint64_t)threadIdx.x * kFoldItems;
-    // is_new covers the whole capacity, so that its scan needs no live count
-#pragma unroll
-    for (int i = 0; i < kFoldItems; ++i)
-        if (r0 + i < cap) is_new[r0 + i] = 0;
     if (base >= n) {
         if (threadIdx.x == 0) {
-            ft.lead[blk] = 0.0;
-            ft.has_head[blk] = 0;
-            ft.open[blk] = kNoOpen;
+            ft.lead[tile] = 0.0;
+            ft.has_head[tile] = 0;
+            ft.open[tile] = kNoOpen;
         }
         return;
     }
@@ -1062,22 +1078,53 @@ __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const
             }
         }
     }
+    // new determinants of this thread, numbered in record order across the tiles
+    bool fresh[kFoldItems];
+    uint32_t n_fresh = 0;
+#pragma unroll
+    for (int i = 0; i < kFoldItems; ++i) {
+        const uint64_t rk = rr[i];
+        const uint64_t pos = lo[i];
+        fresh[i] = head[i] && rk != 0 && !(pos < ne && srank[pos] == rk);
+        n_fresh += fresh[i] ? 1u : 0u;
+    }
+    uint32_t tile_fresh;
+    uint32_t j = block_exclusive_scan(n_fresh, &tile_fresh);
+    if (wave_id() == 0) {
+        if (lane_id() == 0)
+            lb_publish(&ft.status[tile], tile == 0 ? kLbInclusive : kLbAggregate, (uint64_t)tile_fresh);
+        const uint64_t prefix = tile == 0 ? 0 : lb_wave_lookback(ft.status, tile);
+        if (lane_id() == 0) {
+            if (tile > 0) lb_publish(&ft.status[tile], kLbInclusive, prefix + tile_fresh);
+            s_prefix = prefix;
+            if (base + kFoldTile >= n) sc->n_new = prefix + tile_fresh;  // the last live tile
+        }
+    }
+    __syncthreads();
+    const uint64_t jbase = s_prefix;
 #pragma unroll
     for (int i = 0; i < kFoldItems; ++i) {
         if (!head[i]) continue;
         const uint64_t rk = rr[i];
         const uint64_t r = r0 + i;
         const uint64_t pos = lo[i];
-        const bool hit = rk != 0 && pos < ne && srank[pos] == rk;
         ins[r] = pos;
         seg_sum[r] = acc[i];
-        if (rk != 0 && !hit) is_new[r] = 1;
+        if (fresh[i]) {
+            const uint64_t jj = jbase + j++;
+#pragma unroll
+            for (int w = 0; w < W; ++w) nd.key[(uint64_t)w * nd.stride + jj] = nd.rkey[(uint64_t)w * nd.rstride + ii[i]];
+            nd.rank[jj] = rk;
+            nd.ins[jj] = pos;
+            nd.sum[jj] = acc[i];
+            if (open[i]) s_open_new = jj;
+        }
         if (open[i]) {
             s_open = r;  // at most one per tile: the run of the tile's last record
         } else if (rk == 0) {
             sc->hf_sum = acc[i];
             sc->hf_hit = 1;
-        } else if (hit) {
+        } else if (!fresh[i]) {
             delta[pos] = acc[i];
         }
     }
@@ -1092,13 +1139,14 @@ __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const
                 break;
             }
         }
-        ft.lead[blk] = tl;
-        ft.has_head[blk] = hh;
-        ft.open[blk] = s_open;
+        ft.lead[tile] = tl;
+        ft.has_head[tile] = hh;
+        ft.open[tile] = s_open;
+        ft.open_new[tile] = s_open_new;
     }
 }
 
-template <typename T>
+template <int W, typename T>
 struct SegFoldArgs {
     const uint64_t *rank;
     const uint32_t *idx;
@@ -1107,22 +1155,23 @@ struct SegFoldArgs {
     const uint64_t *srank;
     uint64_t ne;
     double *delta;
-    uint32_t *is_new;
     uint64_t *ins;
     double *seg_sum;
     const uint32_t *rtab;
     uint64_t rt_n;
     uint32_t rsh;
     FoldTiles ft;
+    NewDets nd;
     Scratch *sc;
 };
 
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_seg_fold(const SegFoldArgs<T> *__restrict__ args, BatchMap bm)
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_seg_fold(const SegFoldArgs<W, T> *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
-    const SegFoldArgs<T> &A = args[batch_state(bm, blk, nblk)];
-    seg_fold_body<T>(blk, nblk, A.rank, A.idx, A.ramp, A.cap, A.srank, A.ne, A.delta, A.is_new, A.ins, A.seg_sum, A.rtab, A.rt_n, A.rsh, A.ft, A.sc);
+    const SegFoldArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
+    seg_fold_body<W, T>(blk, nblk, A.rank, A.idx, A.ramp, A.cap, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.rtab, A.rt_n,
+                        A.rsh, A.ft, A.nd, A.sc);
 }
 
 // Finish the open runs: add the leading pieces of the following tiles until one holds a head.
@@ -1130,7 +1179,8 @@ __global__ void __launch_bounds__(kThreads) k_seg_fold(const SegFoldArgs<T> *__r
 __device__ __forceinline__ void seg_close_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ rank, uint64_t n_tiles,
                                                         const uint64_t *__restrict__ srank, uint64_t ne,
                                                         double *__restrict__ delta, const uint64_t *__restrict__ ins,
-                                                        double *__restrict__ seg_sum, FoldTiles ft, Scratch *sc)
+                                                        double *__restrict__ seg_sum, double *__restrict__ nsum, FoldTiles ft,
+                                                        Scratch *sc)
 {
     const uint64_t t = (uint64_t)blk * kThreads + threadIdx.x;
     if (t >= n_tiles) return;
@@ -1148,7 +1198,10 @@ __device__ __forceinline__ void seg_close_body(uint32_t blk, uint32_t nblk, cons
         sc->hf_hit = 1;
     } else {
         const uint64_t pos = ins[r];
-        if (pos < ne && srank[pos] == rk) delta[pos] = acc;
+        if (pos < ne && srank[pos] == rk)
+            delta[pos] = acc;
+        else
+            nsum[ft.open_new[t]] = acc;
     }
 }
 
@@ -1160,6 +1213,7 @@ struct SegCloseArgs {
     double *delta;
     const uint64_t *ins;
     double *seg_sum;
+    double *nsum;
     FoldTiles ft;
     Scratch *sc;
 };
@@ -1168,55 +1222,7 @@ __global__ void __launch_bounds__(kThreads) k_seg_close(const SegCloseArgs *__re
 {
     uint32_t blk, nblk;
     const SegCloseArgs &A = args[batch_state(bm, blk, nblk)];
-    seg_close_body(blk, nblk, A.rank, A.n_tiles, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.ft, A.sc);
-}
-
-template <int W>
-__device__ __forceinline__ void new_compact_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ rank, const uint32_t *__restrict__ idx,
-                                                          const uint64_t *__restrict__ rkey, uint64_t rstride, uint64_t cap,
-                                                          const uint32_t *__restrict__ is_new,
-                                                          const uint32_t *__restrict__ new_pos, const uint64_t *__restrict__ ins,
-                                                          const double *__restrict__ seg_sum, uint64_t *__restrict__ nkey,
-                                                          uint64_t *__restrict__ nrank, uint64_t nstride,
-                                                          uint64_t *__restrict__ nins, double *__restrict__ nsum, Scratch *sc)
-{
-    const uint64_t r = (uint64_t)blk * kThreads + threadIdx.x;
-    if (r >= cap) return;
-    if (!is_new[r]) return;
-    const uint32_t j = new_pos[r];
-    const uint32_t src = idx[r];  // any record of the run carries its bitstring
-#pragma unroll
-    for (int w = 0; w < W; ++w) nkey[(uint64_t)w * nstride + j] = rkey[(uint64_t)w * rstride + src];
-    nrank[j] = rank[r];
-    nins[j] = ins[r];
-    nsum[j] = seg_sum[r];
-}
-
-template <int W>
-struct NewCompactArgs {
-    const uint64_t *rank;
-    const uint32_t *idx;
-    const uint64_t *rkey;
-    uint64_t rstride;
-    uint64_t cap;
-    const uint32_t *is_new;
-    const uint32_t *new_pos;
-    const uint64_t *ins;
-    const double *seg_sum;
-    uint64_t *nkey;
-    uint64_t *nrank;
-    uint64_t nstride;
-    uint64_t *nins;
-    double *nsum;
-    Scratch *sc;
-};
-
-template <int W>
-__global__ void __launch_bounds__(kThreads) k_new_compact(const NewCompactArgs<W> *__restrict__ args, BatchMap bm)
-{
-    uint32_t blk, nblk;
-    const NewCompactArgs<W> &A = args[batch_state(bm, blk, nblk)];
-    new_compact_body<W>(blk, nblk, A.rank, A.idx, A.rkey, A.rstride, A.cap, A.is_new, A.new_pos, A.ins, A.seg_sum, A.nkey, A.nrank, A.nstride, A.nins, A.nsum, A.sc);
+    seg_close_body(blk, nblk, A.rank, A.n_tiles, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.nsum, A.ft, A.sc);
 }
 
 // Merge the store (with its sums added) and the new determinants into key order, then
