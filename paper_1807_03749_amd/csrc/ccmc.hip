@@ -103,7 +103,7 @@ struct ccmc_state {
     DevBuf rkey, ramp, rid;  // per-block record regions
     uint64_t rcap = 0;              // region slots
     DevBuf drank, dkey, damp, did, sr[2], sidx[2], tile_region;
-    DevBuf ins, seg_sum, nkey, nrank, nins, nsum, keep, pos;
+    DevBuf ins, seg_sum, nkey, nrank, nins, nsum;
     uint64_t dcap = 0;  // dense record capacity
     uint64_t slot_hint = 1 << 16, rec_hint = 1 << 14;  // capacities planned for the next step
     uint64_t cnt_slots = 0, cnt_rec = 0, cnt_merged = 0, cnt_new = 0, cnt_att = 0, cnt_live_items = 0;  // live counts of the last step
@@ -542,7 +542,7 @@ struct Plan {
     uint64_t ne = 0, n_fnc = 0, n_items = 0, slot_cap = 0, nblk_cap = 0, rec_cap = 0, mcap = 0, tiles = 0;
     uint64_t fold_tiles = 0, fin_blocks = 1, n_parts = 0, lb_words = 0;
     unsigned nb_fnc = 0, nb_sel = 0, nb_rt = 0, nb_abs = 0;
-    uint64_t o_tick = 0, o_weights = 0, o_off = 0, o_boff = 0, o_keep = 0, o_ghist = 0, o_rstat = 0;
+    uint64_t o_tick = 0, o_weights = 0, o_off = 0, o_boff = 0, o_merge = 0, o_ghist = 0, o_rstat = 0;
     uint64_t o_fold = 0, o_fin = 0;
     uint64_t *lb = nullptr;
     Scratch *sc = nullptr;
@@ -550,7 +550,7 @@ struct Plan {
     bool replay = false;       // a capacity overflowed: grow and step again
 };
 
-enum { kTkWeights, kTkOff, kTkBoff, kTkFold, kTkKeep, kTkRadix, kTickets = kTkRadix + kRadixMaxPasses };
+enum { kTkWeights, kTkOff, kTkBoff, kTkFold, kTkMerge, kTkRadix, kTickets = kTkRadix + kRadixMaxPasses };
 
 // Sizes and capacities of one state's step (all allocation happens here).
 template <int W, typename T>
@@ -628,8 +628,6 @@ ccmc_status plan_sizes(Plan<W, T> &p)
     p.mcap = ne + p.rec_cap;  // merged store capacity of this step
     TRY(ensure_store<W, T>(st, p.mcap + 1));
     p.a.gcap = guide_cap(st->scap);
-    TRY(ensure(st, st->keep, (p.mcap + 1) * sizeof(uint32_t)));
-    TRY(ensure(st, st->pos, (p.mcap + 1) * sizeof(uint32_t)));
     p.tiles = (p.rec_cap + kSortTile - 1) / kSortTile;
     p.fold_tiles = (p.rec_cap + kFoldTile - 1) / kFoldTile;
     p.passes = std::max(1, (st->rank_bits + kRadixBits - 1) / kRadixBits);
@@ -642,7 +640,7 @@ ccmc_status plan_sizes(Plan<W, T> &p)
     TRY(ensure(st, st->att_part, nparts * sizeof(uint64_t)));
     TRY(ensure(st, st->disc_part, nparts * sizeof(uint64_t)));
     TRY(ensure(st, st->max_part, nparts * sizeof(uint64_t)));
-    p.nb_abs = grid_for(p.mcap);
+    p.nb_abs = grid_for(p.mcap, kMergeTile);
     TRY(ensure(st, st->abs_part, (p.nb_abs + 1) * sizeof(double)));
     p.fin_blocks = std::min<uint64_t>(
         kMaxFinalParts, std::max<uint64_t>(1, (std::max({p.n_parts, p.nblk_cap, (uint64_t)p.nb_abs}) + 1023) / 1024));
@@ -662,8 +660,8 @@ ccmc_status plan_area(Plan<W, T> &p, int passes)
     p.o_weights = p.o_tick + kTickets;
     p.o_off = p.o_weights + scan_tiles(p.ne);
     p.o_boff = p.o_off + scan_tiles(p.n_items + 1);
-    p.o_keep = p.o_boff + scan_tiles(p.nblk_cap + 1);
-    p.o_ghist = p.o_keep + scan_tiles(p.mcap);
+    p.o_merge = p.o_boff + scan_tiles(p.nblk_cap + 1);
+    p.o_ghist = p.o_merge + grid_for(p.mcap, kMergeTile);
     p.o_rstat = p.o_ghist + (uint64_t)passes * kRadixBins / 2;
     p.o_fold = p.o_rstat + (uint64_t)passes * p.tiles * kRadixBins;
     p.o_fin = p.o_fold + 5 * p.fold_tiles;  // lead, has_head, open, open_new, look-back status
@@ -779,10 +777,10 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
     {
         std::vector<ClearArgs> args;
         for (size_t i = 0; i < n; ++i) {
-            args.push_back(ClearArgs{ps[i].lb, ps[i].lb_words});
-            blk[i] = grid_for(ps[i].lb_words);
+            args.push_back(ClearArgs{ps[i].lb, ps[i].lb_words, ptr<double>(ps[i].st->delta), ps[i].ne});
+            blk[i] = grid_for(ps[i].lb_words + ps[i].ne);
         }
-        stage(ar, recs, "clear", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.lb_words}; }),
+        stage(ar, recs, "clear", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.lb_words + p.ne}; }),
               [s](const ClearArgs *a, BatchMap bm, unsigned g) { k_clear<<<g, kThreads, 0, s>>>(a, bm); });
     }
     // ---- (a1) selection weights, formed inside the scan of their prefix; the draw guide
@@ -990,7 +988,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         stage(ar, recs, "seg_close", args, blk, works([&](auto &p) { return Work{24.0, nullptr, p.fold_tiles}; }),
               [s](const SegCloseArgs *a, BatchMap bm, unsigned g) { k_seg_close<<<g, kThreads, 0, s>>>(a, bm); });
     }
-    // ---- (a12, a13) merge and round into the other store buffer, compact back into this one
+    // ---- (a12, a13) merge, round and compact into the other store buffer
     const double eb = kb + 2 * tb + 8.0;  // one store entry: key, amplitude, diagonal, rank
     {
         using A = MergeArgs<W, T>;
@@ -999,46 +997,18 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             auto &p = ps[i];
             ccmc_state *st = p.st;
             const int m = 1 - p.c;
-            args.push_back(A{st->sd, ptr<uint64_t>(st->skey[p.c]), ptr<T>(st->samp[p.c]), ptr<T>(st->sK[p.c]),
-                             ptr<uint64_t>(st->srank[p.c]), st->scap, p.ne, ptr<double>(st->delta), ptr<uint64_t>(st->nkey),
-                             ptr<uint64_t>(st->nrank), st->dcap, ptr<uint64_t>(st->nins), ptr<double>(st->nsum),
-                             ptr<uint64_t>(st->skey[m]), ptr<T>(st->samp[m]), ptr<T>(st->sK[m]), ptr<uint64_t>(st->srank[m]),
-                             st->scap, p.mcap, p.a, ptr<uint32_t>(st->keep), p.sc});
-            blk[i] = grid_for(p.mcap);
+            const StoreCols in{ptr<uint64_t>(st->skey[p.c]), st->samp[p.c].p, st->sK[p.c].p, ptr<uint64_t>(st->srank[p.c]),
+                               st->scap};
+            const StoreCols out{ptr<uint64_t>(st->skey[m]), st->samp[m].p, st->sK[m].p, ptr<uint64_t>(st->srank[m]), st->scap};
+            args.push_back(A{st->sd, in, p.ne, ptr<double>(st->delta), ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank),
+                             st->dcap, ptr<uint64_t>(st->nins), ptr<double>(st->nsum), out, p.a, p.lb + p.o_merge,
+                             p.lb + p.o_tick + kTkMerge, ptr<double>(st->abs_part), p.sc});
+            blk[i] = std::min(p.nb_abs, kMergeBlocks);
         }
-        stage(ar, recs, "merge", args, blk, works([&](auto &p) { return Work{2.0 * eb + 12.0, &p.st->cnt_merged, 0}; }),
+        // bytes: each merged entry read (store entry and its sum, or a new determinant) and
+        // each survivor written
+        stage(ar, recs, "merge", args, blk, works([&](auto &p) { return Work{2.0 * eb + 8.0, &p.st->cnt_merged, 0}; }),
               [s](const A *a, BatchMap bm, unsigned g) { k_merge<W, T><<<g, kThreads, 0, s>>>(a, bm); });
-    }
-    {
-        using A = ScanLbArgs<uint32_t, ArraySrc<uint32_t>, ArrayOut<uint32_t>>;
-        std::vector<A> args;
-        for (size_t i = 0; i < n; ++i) {
-            auto &p = ps[i];
-            ccmc_state *st = p.st;
-            args.push_back(A{ArraySrc<uint32_t>{ptr<uint32_t>(st->keep)}, ArrayOut<uint32_t>{ptr<uint32_t>(st->pos)}, p.mcap, 0,
-                             p.lb + p.o_keep, p.lb + p.o_tick + kTkKeep, &p.sc->n_out});
-            blk[i] = (uint32_t)scan_tiles(p.mcap);
-        }
-        stage(ar, recs, "keep_scan", args, blk, works([&](auto &p) { return Work{8.0, &p.st->cnt_merged, 0}; }),
-              [s](const A *a, BatchMap bm, unsigned g) {
-                  k_scan_lb<uint32_t, ArraySrc<uint32_t>, ArrayOut<uint32_t>><<<g, kThreads, 0, s>>>(a, bm);
-              });
-    }
-    {
-        using A = CompactArgs<W, T>;
-        std::vector<A> args;
-        for (size_t i = 0; i < n; ++i) {
-            auto &p = ps[i];
-            ccmc_state *st = p.st;
-            const int m = 1 - p.c;
-            args.push_back(A{ptr<uint64_t>(st->skey[m]), ptr<T>(st->samp[m]), ptr<T>(st->sK[m]), ptr<uint64_t>(st->srank[m]),
-                             st->scap, p.mcap, ptr<uint32_t>(st->keep), ptr<uint32_t>(st->pos), ptr<uint64_t>(st->skey[p.c]),
-                             ptr<T>(st->samp[p.c]), ptr<T>(st->sK[p.c]), ptr<uint64_t>(st->srank[p.c]), st->scap,
-                             ptr<double>(st->delta), ptr<double>(st->abs_part), p.sc});
-            blk[i] = p.nb_abs;
-        }
-        stage(ar, recs, "compact", args, blk, works([&](auto &p) { return Work{2.0 * eb + 8.0, &p.st->cnt_merged, 0}; }),
-              [s](const A *a, BatchMap bm, unsigned g) { k_compact<W, T><<<g, kThreads, 0, s>>>(a, bm); });
     }
     // ---- (a14) the step's statistics in a fixed-order two-stage reduction
     {
@@ -1046,7 +1016,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
             args.push_back(FinalPartArgs{parts_of(p), p.n_parts, gen_of(p), p.nblk_cap, ptr<double>(p.st->abs_part), p.nb_abs,
-                                         reinterpret_cast<FinalPart *>(p.lb + p.o_fin)});
+                                         p.sc, p.ne, reinterpret_cast<FinalPart *>(p.lb + p.o_fin)});
             blk[i] = (uint32_t)p.fin_blocks;
         }
         stage(ar, recs, "final", args, blk, works([&](auto &) { return Work{0.0, nullptr, 0}; }),
@@ -1119,6 +1089,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         const double n0_old = st->n0;
         if (scr.hf_hit) st->n0 = st->n0 + scr.hf_sum;
         st->ne = scr.n_out;
+        st->cur = 1 - p.c;  // the merged store was written into the other buffer
         st->step += 1;
         st->last_num = scr.num;
         st->last_den = n0_old;
@@ -1357,8 +1328,7 @@ void destroy(ccmc_state *st)
                       &st->iA, &st->ideath, &st->in, &st->ilevel, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,
                       &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->boff, &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
                       &st->sidx[0], &st->sidx[1], &st->tile_region,
-                      &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->keep,
-                      &st->pos, &st->lb, &st->arg_dev, &st->batch_scr};
+                      &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->lb, &st->arg_dev, &st->batch_scr};
     for (DevBuf *b : bufs) release(st, *b);
     for (auto &p : st->pending) {
         (void)hipEventDestroy(p.a);

@@ -287,7 +287,13 @@ __device__ __forceinline__ T reference_element(const SysDev &S, const uint64_t *
 
 // K_D = H_DD - E_HF from the holes I and particles A of D:
 // sum_A f_a - sum_I f_i + sum_{a<b} <ab||ab> + sum_{i<j} <ij||ij> - sum_{a,i} <ai||ai>.
-template <int W, typename T>
+// With IssueAll, up to kDiagFast holes and particles every table load is issued before the
+// first add (clamped indices, absent terms added as zero, so the sum and its order are those
+// of the plain loops): for callers with few waves to hide the latency of dependent loads.
+// Callers at full occupancy keep the plain loops, which hold fewer registers.
+constexpr int kDiagFast = 4;
+
+template <int W, typename T, bool IssueAll = false>
 __device__ __forceinline__ T diagonal(const SysDev &S, const uint64_t *d)
 {
     int hole[kMaxClusterSize], part[kMaxClusterSize], nh = 0, np = 0;
@@ -307,6 +313,49 @@ __device__ __forceinline__ T diagonal(const SysDev &S, const uint64_t *d)
     const T *V = static_cast<const T *>(S.vpair);
     const size_t M = (size_t)S.M;
     T k = T(0);
+    if (IssueAll && np <= kDiagFast && nh <= kDiagFast) {
+        constexpr int F = kDiagFast;
+        int pa[F], ho[F];
+#pragma unroll
+        for (int x = 0; x < F; ++x) {
+            pa[x] = x < np ? part[x] : 0;
+            ho[x] = x < nh ? hole[x] : 0;
+        }
+        T fp[F], fh[F], vpp[F * (F - 1) / 2], vhh[F * (F - 1) / 2], vph[F * F];
+#pragma unroll
+        for (int x = 0; x < F; ++x) {
+            fp[x] = f[pa[x]];
+            fh[x] = f[ho[x]];
+        }
+#pragma unroll
+        for (int a = 0, c = 0; a < F; ++a)
+#pragma unroll
+            for (int b = a + 1; b < F; ++b, ++c) {
+                vpp[c] = V[pa[a] * M + pa[b]];
+                vhh[c] = V[ho[a] * M + ho[b]];
+            }
+#pragma unroll
+        for (int a = 0; a < F; ++a)
+#pragma unroll
+            for (int i = 0; i < F; ++i) vph[a * F + i] = V[pa[a] * M + ho[i]];
+#pragma unroll
+        for (int a = 0; a < F; ++a) k += a < np ? fp[a] : T(0);
+#pragma unroll
+        for (int i = 0; i < F; ++i) k -= i < nh ? fh[i] : T(0);
+#pragma unroll
+        for (int a = 0, c = 0; a < F; ++a)
+#pragma unroll
+            for (int b = a + 1; b < F; ++b, ++c) k += b < np ? vpp[c] : T(0);
+#pragma unroll
+        for (int a = 0, c = 0; a < F; ++a)
+#pragma unroll
+            for (int b = a + 1; b < F; ++b, ++c) k += b < nh ? vhh[c] : T(0);
+#pragma unroll
+        for (int a = 0; a < F; ++a)
+#pragma unroll
+            for (int i = 0; i < F; ++i) k -= (a < np && i < nh) ? vph[a * F + i] : T(0);
+        return k;
+    }
     for (int a = 0; a < np; ++a) k += f[part[a]];
     for (int i = 0; i < nh; ++i) k -= f[hole[i]];
     for (int a = 0; a < np; ++a)

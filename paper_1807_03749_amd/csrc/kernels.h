@@ -13,8 +13,8 @@
 //   radix sort       stable LSD sort of (rank, record index)                    (a11)
 //   k_seg_fold       sum of each run in record order, store lookup, new         (a12)
 //                    determinants numbered by look-back; k_seg_close for runs across tiles
-//   k_merge          merge, then occupation rounding                            (a12, a13)
-//   keep scan, k_compact      survivors back into the store
+//   k_merge          merge, occupation rounding and compaction into the other    (a12, a13)
+//                    store buffer (look-back for the output positions)
 //   k_final          FP64 population, projected-energy and count reductions    (a14)
 #pragma once
 #include "device.h"
@@ -30,7 +30,7 @@ constexpr uint64_t kErrBlowup = 1, kErrAttempts = 2, kErrSlotCap = 4, kErrRecCap
 // Device-side scalars of one step (all 64-bit words, cleared at the start of the step).
 struct Scratch {
     uint64_t qtot;
-    uint64_t err;             // kErr* bits; any bit makes the final compaction a no-op
+    uint64_t err;             // kErr* bits; any bit fails the step (the current store is left as it was)
     uint64_t n_discarded;
     uint64_t n_attempts;
     uint64_t n_spawns;
@@ -1225,76 +1225,202 @@ __global__ void __launch_bounds__(kThreads) k_seg_close(const SegCloseArgs *__re
     seg_close_body(blk, nblk, A.rank, A.n_tiles, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.nsum, A.ft, A.sc);
 }
 
-// Merge the store (with its sums added) and the new determinants into key order, then
-// apply real-weight occupation rounding at each merged position k: 0 < |N| < theta becomes
-// +-theta with probability |N| / theta, else 0, from a Philox draw keyed by k (the reference
-// is exempt).  Store entry i lands at i + #(new with ins <= i); new entry j at ins_j + j.
-// Positions beyond the merged size (up to the capacity) get keep = 0.
-template <int W, typename T>
-__device__ __forceinline__ void merge_body(uint32_t blk, uint32_t nblk, const SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
-                                                    const T *__restrict__ sK, const uint64_t *__restrict__ srank,
-                                                    uint64_t sstride, uint64_t ne, const double *__restrict__ delta,
-                                                    const uint64_t *__restrict__ nkey, const uint64_t *__restrict__ nrank,
-                                                    uint64_t nstride, const uint64_t *__restrict__ nins,
-                                                    const double *__restrict__ nsum, uint64_t *__restrict__ mkey,
-                                                    T *__restrict__ mamp, T *__restrict__ mK, uint64_t *__restrict__ mrank,
-                                                    uint64_t mstride, uint64_t cap, StepArgs a, uint32_t *__restrict__ keep,
-                                                    Scratch *sc)
+// Merge the store (with its sums added) and the new determinants into key order, round, and
+// compact into the other store buffer, in one pass over the merged positions.  Merged
+// position p holds new determinant j when ins_j + j = p (new determinant j lands after the
+// ins_j store entries below it and the j new ones before it), else store entry p - #(new
+// before p).  Real-weight occupation rounding at merged position p: 0 < |N| < theta becomes
+// +-theta with probability |N| / theta, else 0, from a Philox draw keyed by p (the reference
+// is exempt).  Survivors get their output position from a scan over the tiles (decoupled
+// look-back in ticket order) and are written compacted; the per-tile |N| sums feed the
+// population total.  The current buffer is only read, so a failed step leaves it intact.
+struct StoreCols {
+    uint64_t *key;
+    void *amp;
+    void *K;
+    uint64_t *rank;
+    uint64_t stride;
+};
+
+constexpr int kMergeItems = 4;  // merged positions per thread, one per row of the tile
+constexpr int kMergeTile = kThreads * kMergeItems;
+constexpr unsigned kMergeBlocks = 1024;  // resident blocks of the merge (per state)
+
+// #{j < n : ins[j] + j < P} by one wavefront.  ins[j] + j (the merged position of new
+// determinant j) is strictly increasing, so a 64-way search narrows [lo, hi] by 64 per round.
+__device__ __forceinline__ uint64_t wave_new_before(const uint64_t *__restrict__ ins, uint64_t n, uint64_t P)
 {
-    const uint64_t t = (uint64_t)blk * kThreads + threadIdx.x;
+    uint64_t lo = 0, hi = n;  // the answer lies in [lo, hi]
+    while (hi > lo) {
+        const uint64_t step = (hi - lo + 63) >> 6;
+        const uint64_t idx = lo + (uint64_t)lane_id() * step;
+        const uint64_t c = idx < hi ? idx : hi - 1;
+        const bool below = idx < hi && ins[c] + c < P;
+        const uint64_t nb = (uint64_t)__popcll(__ballot(below));
+        if (nb == 0) break;  // the probe at lo fails: the answer is lo
+        const uint64_t nhi = lo + nb * step;
+        lo += (nb - 1) * step + 1;
+        hi = nhi < hi ? nhi : hi;
+    }
+    return lo;
+}
+
+// Merged position p of a tile is row p / kThreads, thread p % kThreads, so every row is read
+// and written with coalesced accesses.  The tile's new determinants are scattered into LDS by
+// position; counts "before p" (new determinants, survivors) come from per-row ballots.
+template <int W, typename T>
+__device__ __forceinline__ void merge_body(uint32_t blk, uint32_t nblk, const SysDev S, StoreCols in, uint64_t ne,
+                                           const double *__restrict__ delta, const uint64_t *__restrict__ nkey,
+                                           const uint64_t *__restrict__ nrank, uint64_t nstride,
+                                           const uint64_t *__restrict__ nins, const double *__restrict__ nsum, StoreCols out,
+                                           StepArgs a, uint64_t *__restrict__ status, uint64_t *__restrict__ ticket,
+                                           double *__restrict__ abs_part, Scratch *sc)
+{
+    __shared__ uint64_t s_tile, s_prefix, s_j[2];
+    __shared__ uint16_t s_new[kMergeTile];                 // 1 + (j - j0) of the new determinant at a position, or 0
+    __shared__ uint32_t s_cnt[kMergeItems][kWaves];        // per row and wave: new determinants, then survivors
+    __shared__ T s_K[kMergeTile];                          // diagonal elements of the tile's new determinants
     const uint64_t nn = sc->n_new;
-    if (t >= cap) return;
-    if (t >= ne + nn) {
-        keep[t] = 0;
-        return;
-    }
-    uint64_t pos;
-    T v;
-    if (t < ne) {
-        uint64_t l0 = 0, h0 = nn;  // new entries with ins <= t
-        while (l0 < h0) {
-            const uint64_t mid = (l0 + h0) >> 1;
-            if (nins[mid] <= t)
-                l0 = mid + 1;
-            else
-                h0 = mid;
+    const uint64_t total = ne + nn;
+    // A step already in error (a capacity overflow upstream) is abandoned by every block
+    // alike, before any index is formed from its possibly incomplete records.
+    if (sc->err) return;
+    const int w = wave_id(), lane = lane_id();
+    // Blocks take tiles in ticket order until the merged store is covered: a tile waits
+    // only on tiles taken before it, all held by running blocks.
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd((unsigned long long *)ticket, 1ull);
+        for (int i = threadIdx.x; i < kMergeTile; i += kThreads) s_new[i] = 0;
+        __syncthreads();
+        const uint64_t tile = s_tile;
+        const uint64_t P0 = tile * kMergeTile;
+        if (P0 >= total) return;
+        if (w < 2) {
+            const uint64_t P = w == 0 ? P0 : (P0 + kMergeTile < total ? P0 + kMergeTile : total);
+            const uint64_t j = wave_new_before(nins, nn, P);
+            if (lane == 0) s_j[w] = j;
         }
-        pos = t + l0;
+        __syncthreads();
+        const uint64_t j0 = s_j[0], j1 = s_j[1];
+        // the new determinants, by one thread each: position and diagonal element
+        for (uint64_t j = j0 + threadIdx.x; j < j1; j += kThreads) {
+            const uint64_t o = nins[j] + j - P0;  // in [0, kMergeTile) by the choice of j0 and j1
+            uint64_t d[W];
 #pragma unroll
-        for (int w = 0; w < W; ++w) mkey[(uint64_t)w * mstride + pos] = skey[(uint64_t)w * sstride + t];
-        v = (T)((double)samp[t] + delta[t]);
-        mK[pos] = sK[t];
-        mrank[pos] = srank[t];
-    } else {
-        const uint64_t j = t - ne;
-        pos = nins[j] + j;
-        uint64_t d[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            d[w] = nkey[(uint64_t)w * nstride + j];
-            mkey[(uint64_t)w * mstride + pos] = d[w];
+            for (int x = 0; x < W; ++x) d[x] = nkey[(uint64_t)x * nstride + j];
+            if (o < kMergeTile && j - j0 < kMergeTile) {
+                s_new[o] = (uint16_t)(j - j0 + 1);
+                s_K[j - j0] = diagonal<W, T, true>(S, d);
+            }
         }
-        v = (T)nsum[j];
-        mK[pos] = diagonal<W, T>(S, d);
-        mrank[pos] = nrank[j];
+        __syncthreads();
+        uint32_t f[kMergeItems];
+#pragma unroll
+        for (int u = 0; u < kMergeItems; ++u) {
+            f[u] = s_new[u * kThreads + threadIdx.x];
+            const uint64_t m = __ballot(f[u] != 0);
+            if (lane == 0) s_cnt[u][w] = (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        T v[kMergeItems];
+        uint64_t src[kMergeItems];
+        double abs_sum = 0.0;
+        {
+            uint64_t nb = j0;  // new determinants in the rows before the current one
+#pragma unroll
+            for (int u = 0; u < kMergeItems; ++u) {
+                uint64_t below_w = 0, in_row = 0;
+#pragma unroll
+                for (int x = 0; x < kWaves; ++x) {
+                    if (x < w) below_w += s_cnt[u][x];
+                    in_row += s_cnt[u][x];
+                }
+                const uint64_t m = __ballot(f[u] != 0);
+                const uint64_t p = P0 + (uint64_t)u * kThreads + threadIdx.x;
+                v[u] = T(0);
+                src[u] = 0;
+                if (f[u] != 0) {
+                    src[u] = j0 + f[u] - 1;
+                    v[u] = (T)nsum[src[u]];
+                } else if (p < total) {
+                    src[u] = p - (nb + below_w + (uint64_t)lanes_below(m));
+                    v[u] = (T)((double)static_cast<const T *>(in.amp)[src[u]] + delta[src[u]]);
+                }
+                if (v[u] != T(0) && fabs((double)v[u]) < a.theta) {
+                    Draws r(a.key0, a.key1, kRound, (uint32_t)p, 0u, a.step);
+                    const double uu = uniform53(r.get(0));
+                    v[u] = (uu < fabs((double)v[u]) / a.theta) ? (T)copysign(a.theta, (double)v[u]) : T(0);
+                }
+                abs_sum += fabs((double)v[u]);
+                nb += in_row;
+            }
+        }
+        __syncthreads();  // the new-determinant counts are read; s_cnt takes the survivor counts
+#pragma unroll
+        for (int u = 0; u < kMergeItems; ++u) {
+            const uint64_t m = __ballot(v[u] != T(0));
+            if (lane == 0) s_cnt[u][w] = (uint32_t)__popcll(m);
+        }
+        const double tile_abs = block_reduce_sum(abs_sum);  // its barriers also publish s_cnt
+        uint64_t tile_keep = 0;
+#pragma unroll
+        for (int u = 0; u < kMergeItems; ++u)
+#pragma unroll
+            for (int x = 0; x < kWaves; ++x) tile_keep += s_cnt[u][x];
+        if (w == 0) {
+            if (lane == 0) lb_publish(&status[tile], tile == 0 ? kLbInclusive : kLbAggregate, tile_keep);
+            const uint64_t prefix = tile == 0 ? 0 : lb_wave_lookback(status, tile);
+            if (lane == 0) {
+                if (tile > 0) lb_publish(&status[tile], kLbInclusive, prefix + tile_keep);
+                s_prefix = prefix;
+                if (P0 + kMergeTile >= total) sc->n_out = prefix + tile_keep;  // the last tile
+                abs_part[tile] = tile_abs;
+            }
+        }
+        __syncthreads();
+        // survivors' columns: every row's loads first, then the stores
+        uint64_t dk[kMergeItems][W], rk[kMergeItems];
+        T K[kMergeItems];
+#pragma unroll
+        for (int u = 0; u < kMergeItems; ++u) {
+            const bool nw = f[u] != 0;
+            const uint64_t *kb = nw ? nkey : in.key;
+            const uint64_t ks = nw ? nstride : in.stride;
+            const uint64_t c = v[u] != T(0) ? src[u] : 0;  // a row slot without a survivor loads entry 0
+#pragma unroll
+            for (int x = 0; x < W; ++x) dk[u][x] = kb[(uint64_t)x * ks + c];
+            rk[u] = (nw ? nrank : in.rank)[c];
+            const T k_new = s_K[nw ? f[u] - 1 : 0];
+            K[u] = nw ? k_new : static_cast<const T *>(in.K)[c];
+        }
+        uint64_t q = s_prefix;  // survivors before the current row
+#pragma unroll
+        for (int u = 0; u < kMergeItems; ++u) {
+            const uint64_t m = __ballot(v[u] != T(0));
+            uint64_t before = 0, in_row = 0;
+#pragma unroll
+            for (int x = 0; x < kWaves; ++x) {
+                if (x < w) before += s_cnt[u][x];
+                in_row += s_cnt[u][x];
+            }
+            if (v[u] != T(0)) {
+                const uint64_t o = q + before + (uint64_t)lanes_below(m);
+#pragma unroll
+                for (int x = 0; x < W; ++x) out.key[(uint64_t)x * out.stride + o] = dk[u][x];
+                static_cast<T *>(out.amp)[o] = v[u];
+                static_cast<T *>(out.K)[o] = K[u];
+                out.rank[o] = rk[u];
+            }
+            q += in_row;
+        }
+        __syncthreads();  // LDS is reused by the next tile
     }
-    if (v != T(0) && fabs((double)v) < a.theta) {
-        Draws r(a.key0, a.key1, kRound, (uint32_t)pos, 0u, a.step);
-        const double u = uniform53(r.get(0));
-        v = (u < fabs((double)v) / a.theta) ? (T)copysign(a.theta, (double)v) : T(0);
-    }
-    mamp[pos] = v;
-    keep[pos] = (v != T(0)) ? 1u : 0u;
 }
 
 template <int W, typename T>
 struct MergeArgs {
-    const SysDev S;
-    const uint64_t *skey;
-    const T *samp;
-    const T *sK;
-    const uint64_t *srank;
-    uint64_t sstride;
+    SysDev S;
+    StoreCols in;
     uint64_t ne;
     const double *delta;
     const uint64_t *nkey;
@@ -1302,14 +1428,11 @@ struct MergeArgs {
     uint64_t nstride;
     const uint64_t *nins;
     const double *nsum;
-    uint64_t *mkey;
-    T *mamp;
-    T *mK;
-    uint64_t *mrank;
-    uint64_t mstride;
-    uint64_t cap;
+    StoreCols out;
     StepArgs a;
-    uint32_t *keep;
+    uint64_t *status;
+    uint64_t *ticket;
+    double *abs_part;
     Scratch *sc;
 };
 
@@ -1318,64 +1441,8 @@ __global__ void __launch_bounds__(kThreads) k_merge(const MergeArgs<W, T> *__res
 {
     uint32_t blk, nblk;
     const MergeArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
-    merge_body<W, T>(blk, nblk, A.S, A.skey, A.samp, A.sK, A.srank, A.sstride, A.ne, A.delta, A.nkey, A.nrank, A.nstride, A.nins, A.nsum, A.mkey, A.mamp, A.mK, A.mrank, A.mstride, A.cap, A.a, A.keep, A.sc);
-}
-
-// Compaction of the merged store back into the current buffer (the only write to the
-// state; skipped after any error, so that a failed step leaves the state unchanged).  The
-// per-entry sum buffer of the next step is cleared on the way.
-template <int W, typename T>
-__device__ __forceinline__ void compact_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ mkey, const T *__restrict__ mamp,
-                                                      const T *__restrict__ mK, const uint64_t *__restrict__ mrank,
-                                                      uint64_t mstride, uint64_t cap, const uint32_t *__restrict__ keep,
-                                                      const uint32_t *__restrict__ pos, uint64_t *__restrict__ okey,
-                                                      T *__restrict__ oamp, T *__restrict__ oK, uint64_t *__restrict__ orank,
-                                                      uint64_t ostride, double *__restrict__ delta,
-                                                      double *__restrict__ abs_part, Scratch *sc)
-{
-    const uint64_t k = (uint64_t)blk * kThreads + threadIdx.x;
-    const bool ok = sc->err == 0;
-    double a = 0.0;
-    if (ok && k < cap && keep[k]) {
-        const uint32_t p = pos[k];
-#pragma unroll
-        for (int w = 0; w < W; ++w) okey[(uint64_t)w * ostride + p] = mkey[(uint64_t)w * mstride + k];
-        oamp[p] = mamp[k];
-        oK[p] = mK[k];
-        orank[p] = mrank[k];
-        delta[p] = 0.0;
-        a = fabs((double)mamp[k]);
-    }
-    a = block_reduce_sum(a);
-    if (threadIdx.x == 0) abs_part[blk] = a;
-}
-
-template <int W, typename T>
-struct CompactArgs {
-    const uint64_t *mkey;
-    const T *mamp;
-    const T *mK;
-    const uint64_t *mrank;
-    uint64_t mstride;
-    uint64_t cap;
-    const uint32_t *keep;
-    const uint32_t *pos;
-    uint64_t *okey;
-    T *oamp;
-    T *oK;
-    uint64_t *orank;
-    uint64_t ostride;
-    double *delta;
-    double *abs_part;
-    Scratch *sc;
-};
-
-template <int W, typename T>
-__global__ void __launch_bounds__(kThreads) k_compact(const CompactArgs<W, T> *__restrict__ args, BatchMap bm)
-{
-    uint32_t blk, nblk;
-    const CompactArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
-    compact_body<W, T>(blk, nblk, A.mkey, A.mamp, A.mK, A.mrank, A.mstride, A.cap, A.keep, A.pos, A.okey, A.oamp, A.oK, A.orank, A.ostride, A.delta, A.abs_part, A.sc);
+    merge_body<W, T>(blk, nblk, A.S, A.in, A.ne, A.delta, A.nkey, A.nrank, A.nstride, A.nins, A.nsum, A.out, A.a, A.status,
+                     A.ticket, A.abs_part, A.sc);
 }
 
 // The step's statistics in a fixed-order two-stage reduction: block b of k_final_part sums
@@ -1396,8 +1463,12 @@ __device__ __forceinline__ void chunk_of(uint64_t n, uint64_t g, uint64_t nb, ui
 
 __device__ __forceinline__ void final_part_body(uint32_t blk, uint32_t nblk, ItemPartials part, uint64_t n_parts, GenStats gs, uint64_t n_gen,
                                                          const double *__restrict__ abs_part, uint64_t n_abs,
-                                                         FinalPart *__restrict__ out)
+                                                         const Scratch *sc, uint64_t ne, FinalPart *__restrict__ out)
 {
+    {  // the merge wrote the absolute sums of the tiles covering the merged store only
+        const uint64_t live = (ne + sc->n_new + kMergeTile - 1) / kMergeTile;
+        n_abs = live < n_abs ? live : n_abs;
+    }
     constexpr int U = 4;  // loads in flight per array and thread
     double num = 0.0, tot = 0.0;
     uint64_t att = 0, disc = 0, mx = 0, sp = 0, de = 0;
@@ -1477,6 +1548,8 @@ struct FinalPartArgs {
     uint64_t n_gen;
     const double *abs_part;
     uint64_t n_abs;
+    const Scratch *sc;
+    uint64_t ne;
     FinalPart *out;
 };
 
@@ -1484,7 +1557,7 @@ __global__ void __launch_bounds__(kThreads) k_final_part(const FinalPartArgs *__
 {
     uint32_t blk, nblk;
     const FinalPartArgs &A = args[batch_state(bm, blk, nblk)];
-    final_part_body(blk, nblk, A.part, A.n_parts, A.gs, A.n_gen, A.abs_part, A.n_abs, A.out);
+    final_part_body(blk, nblk, A.part, A.n_parts, A.gs, A.n_gen, A.abs_part, A.n_abs, A.sc, A.ne, A.out);
 }
 
 __device__ __forceinline__ void final_body(uint32_t blk, uint32_t nblk, const FinalPart *__restrict__ in, uint64_t n, Scratch *sc,
@@ -1526,10 +1599,12 @@ __global__ void __launch_bounds__(kThreads) k_final(const FinalArgs *__restrict_
     final_body(blk, nblk, A.in, A.n, A.sc, A.copy);
 }
 
-// Clear each state's step area.
+// Clear each state's step area and the per-entry sums of its store.
 struct ClearArgs {
     uint64_t *p;
     uint64_t n;
+    double *delta;
+    uint64_t ne;
 };
 
 __global__ void __launch_bounds__(kThreads) k_clear(const ClearArgs *__restrict__ args, BatchMap bm)
@@ -1537,7 +1612,10 @@ __global__ void __launch_bounds__(kThreads) k_clear(const ClearArgs *__restrict_
     uint32_t blk, nblk;
     const ClearArgs &A = args[batch_state(bm, blk, nblk)];
     const uint64_t i = (uint64_t)blk * kThreads + threadIdx.x;
-    if (i < A.n) A.p[i] = 0;
+    if (i < A.n)
+        A.p[i] = 0;
+    else if (i - A.n < A.ne)
+        A.delta[i - A.n] = 0.0;
 }
 
 template <typename V>
