@@ -242,8 +242,7 @@ def roofline(timed: dict, w: inputs.Workload):
     return r
 
 
-ANNIHILATION = ("gather", "radix_ghist", "radix_onesweep", "seg_fold", "new_scan", "new_compact", "merge",
-                "keep_scan", "compact")
+ANNIHILATION = ("gather", "radix_ghist", "radix_onesweep", "seg_fold", "seg_close", "merge")
 
 
 def annihilation_roofline(prof: dict):
