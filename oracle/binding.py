@@ -44,6 +44,9 @@ class Options(C.Structure):
         ("init_pop", C.c_double),
         ("p_single", C.c_double),
         ("seed", C.c_uint64),
+        ("n_ranks", C.c_uint32),
+        ("move_shift", C.c_uint32),
+        ("hash_seed", C.c_uint32),
     ]
 
 
@@ -111,6 +114,12 @@ def lib():
                                       C.POINTER(C.c_double)]),
             "orc_death": (C.c_double, [vp, _u64p, C.c_double, C.c_double, C.c_double]),
             "orc_philox": (None, [_u32p, _u32p, _u32p]),
+            "orc_cluster_ranked": (C.c_int, [vp, C.c_int, _u64p, C.c_uint64, C.c_uint64, C.c_uint32, C.c_int, _u64p,
+                                             C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_uint64)]),
+            "orc_murmur2": (C.c_uint32, [C.c_char_p, C.c_int, C.c_uint32]),
+            "orc_placement": (C.c_uint32, [C.c_int, _u64p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32]),
+            "orc_codistribution": (C.c_int, [C.c_int, _u64p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p,
+                                             C.c_int, _u64p, _u64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -129,6 +138,28 @@ def philox(ctr, key) -> np.ndarray:
     out = np.zeros(4, np.uint32)
     lib().orc_philox(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
     return out
+
+
+def murmur2(data: bytes, seed: int) -> int:
+    return int(lib().orc_murmur2(bytes(data), len(data), int(seed)))
+
+
+def placement(det, i_tau: int, n_ranks: int, move_shift: int, seed: int) -> int:
+    d = np.ascontiguousarray(det, np.uint64)
+    return int(lib().orc_placement(len(d), d, int(i_tau), int(n_ranks), int(move_shift), int(seed)))
+
+
+def codistribution(keys, n_ranks: int, move_shift: int, seed: int, checkpoints):
+    """Sums over pairs i < j of c_ij and c_ij^2 at each checkpoint (c_ij: iterations on the
+    same processor)."""
+    keys = np.ascontiguousarray(np.asarray(keys, np.uint64))
+    n, W = keys.shape
+    cp = np.ascontiguousarray(checkpoints, np.uint64)
+    s1 = np.zeros(len(cp), np.uint64)
+    s2 = np.zeros(len(cp), np.uint64)
+    _check(lib().orc_codistribution(W, keys.ravel(), n, int(n_ranks), int(move_shift), int(seed), cp, len(cp), s1, s2),
+           "codistribution")
+    return s1, s2
 
 
 def weight(amp: float) -> int:
@@ -227,12 +258,16 @@ class RunOptions:
     init_pop: float = 10.0
     p_single: float = 0.1
     seed: int = 1234
+    n_ranks: int = 1
+    move_shift: int = 5
+    hash_seed: int = 0
 
     def to_c(self) -> Options:
         return Options(int(self.full_noncomposite), int(self.min_spawn_attempts),
                        float(self.multispawn_threshold), float(self.noncomposite_threshold),
                        float(self.spawn_cutoff), float(self.occupation_threshold), float(self.init_pop),
-                       float(self.p_single), int(self.seed))
+                       float(self.p_single), int(self.seed), int(self.n_ranks), int(self.move_shift),
+                       int(self.hash_seed))
 
 
 class Run:
@@ -292,6 +327,16 @@ class Run:
         ok = lib().orc_cluster(self._h, s, arr, int(n_sel), int(composite), det,
                                C.byref(A), C.byref(L), C.byref(n))
         _check(ok, "cluster")
+        return (det, A.value, L.value, n.value) if ok else None
+
+    def cluster_ranked(self, idx, count: int, qnorm: int, n_ranks: int, composite: bool):
+        s = len(idx)
+        arr = np.ascontiguousarray(idx, np.uint64) if s else np.zeros(1, np.uint64)
+        det = np.zeros(self.system.W, np.uint64)
+        A, L, n = C.c_double(), C.c_int(), C.c_uint64()
+        ok = lib().orc_cluster_ranked(self._h, s, arr, int(count), int(qnorm), int(n_ranks), int(composite), det,
+                                      C.byref(A), C.byref(L), C.byref(n))
+        _check(ok, "cluster_ranked")
         return (det, A.value, L.value, n.value) if ok else None
 
     def attempts(self, A: float, noncomposite: bool) -> int:

@@ -483,6 +483,95 @@ static uint64_t below(uint64_t v, uint64_t n)
     return (uint64_t)(((unsigned __int128)v * (unsigned __int128)n) >> 64);
 }
 
+/* ------------------------------------------------------------ virtual processors */
+/* MurmurHash2 (Austin Appleby; 32-bit, public domain): 4-byte little-endian blocks, each
+ * mixed by multiply-xorshift-multiply and folded into h = h * m ^ k; the 1-3 tail bytes; a
+ * final avalanche. */
+uint32_t orc_murmur2(const void *key, int len, uint32_t seed)
+{
+    const uint32_t m = 0x5bd1e995u;
+    const unsigned char *b = (const unsigned char *)key;
+    uint32_t h = seed ^ (uint32_t)len;
+    while (len >= 4) {
+        uint32_t k = (uint32_t)b[0] | (uint32_t)b[1] << 8 | (uint32_t)b[2] << 16 | (uint32_t)b[3] << 24;
+        k *= m;
+        k ^= k >> 24;
+        k *= m;
+        h *= m;
+        h ^= k;
+        b += 4;
+        len -= 4;
+    }
+    if (len == 3) h ^= (uint32_t)b[2] << 16;
+    if (len >= 2) h ^= (uint32_t)b[1] << 8;
+    if (len >= 1) {
+        h ^= (uint32_t)b[0];
+        h *= m;
+    }
+    h ^= h >> 13;
+    h *= m;
+    h ^= h >> 15;
+    return h;
+}
+
+static uint32_t hash_det(int W, const uint64_t *d, uint32_t seed)
+{
+    unsigned char buf[8 * MAXW];
+    for (int w = 0; w < W; ++w)
+        for (int c = 0; c < 8; ++c) buf[8 * w + c] = (unsigned char)(d[w] >> (8 * c));
+    return orc_murmur2(buf, 8 * W, seed);
+}
+
+/* eq. ccmc_dist (Sec. III.A). */
+uint32_t orc_placement(int W, const uint64_t *det, uint64_t i_tau, uint32_t n_ranks, uint32_t move_shift,
+                       uint32_t seed)
+{
+    if (n_ranks <= 1) return 0;
+    uint64_t o = move_shift >= 64 ? 0 : ((uint64_t)hash_det(W, det, seed) + i_tau) >> move_shift;
+    uint64_t d[MAXW];
+    memcpy(d, det, sizeof(uint64_t) * (size_t)W);
+    d[0] ^= o;
+    return hash_det(W, d, seed) % n_ranks;
+}
+
+int orc_codistribution(int W, const uint64_t *keys, uint64_t n, uint32_t n_ranks, uint32_t move_shift,
+                       uint32_t seed, const uint64_t *checkpoints, int n_checkpoints, uint64_t *sum_c,
+                       uint64_t *sum_c2)
+{
+    if (W < 1 || W > MAXW || n_checkpoints < 1) return ORC_EINVAL;
+    for (int c = 1; c < n_checkpoints; ++c)
+        if (checkpoints[c] < checkpoints[c - 1]) return ORC_EINVAL;
+    uint64_t T = checkpoints[n_checkpoints - 1];
+    uint32_t *pl = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+    uint64_t *cnt = (uint64_t *)calloc((size_t)(n * (n ? n - 1 : 0) / 2 + 1), sizeof(uint64_t));
+    if (!pl || !cnt) {
+        free(pl);
+        free(cnt);
+        return ORC_ENOMEM;
+    }
+    for (int c = 0; c < n_checkpoints; ++c) sum_c[c] = sum_c2[c] = 0;
+    int next = 0;
+    for (uint64_t t = 0; t <= T && next < n_checkpoints; ++t) {
+        while (next < n_checkpoints && checkpoints[next] == t) {  /* iterations 0 .. t-1 counted */
+            uint64_t k = 0;
+            for (uint64_t i = 0; i < n; ++i)
+                for (uint64_t j = i + 1; j < n; ++j, ++k) {
+                    sum_c[next] += cnt[k];
+                    sum_c2[next] += cnt[k] * cnt[k];
+                }
+            ++next;
+        }
+        if (t == T) break;
+        for (uint64_t i = 0; i < n; ++i) pl[i] = orc_placement(W, keys + i * W, t, n_ranks, move_shift, seed);
+        uint64_t k = 0;
+        for (uint64_t i = 0; i < n; ++i)
+            for (uint64_t j = i + 1; j < n; ++j, ++k) cnt[k] += pl[i] == pl[j];
+    }
+    free(pl);
+    free(cnt);
+    return 0;
+}
+
 /* --------------------------------------------------------------------------- runs */
 
 uint64_t orc_weight(double amp)
@@ -654,8 +743,9 @@ int orc_attempts(const orc_run *R, double A, int noncomposite, uint64_t *n)
     return 0;
 }
 
-int orc_cluster(const orc_run *R, int s, const uint64_t *idx, uint64_t n_sel, int composite,
-                uint64_t *det, double *A, int *level, uint64_t *n_attempts)
+int orc_cluster_ranked(const orc_run *R, int s, const uint64_t *idx, uint64_t count, uint64_t qnorm,
+                       uint32_t n_ranks, int composite, uint64_t *det, double *A, int *level,
+                       uint64_t *n_attempts)
 {
     const orc_system *S = R->sys;
     int W = S->W;
@@ -677,11 +767,21 @@ int orc_cluster(const orc_run *R, int s, const uint64_t *idx, uint64_t n_sel, in
     }
     int L = orc_excitation_level(S, det);
     if (L > R->l + 2) return 0;
-    /* expected number of times this cluster is drawn in n_sel selections */
+    /* expected number of times this cluster is drawn in `count` selections */
     double fact = 1.0;
     for (int a = 2; a <= s; ++a) fact *= (double)a;
-    double p = (double)n_sel * size_prob(s, lo, hi) * fact;
-    for (int a = 0; a < s; ++a) p *= (double)R->q[idx[a]] / (double)R->qtot;
+    double p = (double)count * size_prob(s, lo, hi) * fact;
+    for (int a = 0; a < s; ++a) p *= (double)R->q[idx[a]] / (double)qnorm;
+    /* N_p processors (Sec. III.A): times N_p^(1-s) */
+    if (n_ranks > 1) {
+        if (s == 0) {
+            p *= (double)n_ranks;
+        } else {
+            double d = 1.0;
+            for (int a = 1; a < s; ++a) d *= (double)n_ranks;
+            p /= d;
+        }
+    }
     /* cluster amplitude t_HF^(1-s) prod t_i with the collapse sign (Sec. II, eq. 2) */
     double Ac;
     if (s == 0) {
@@ -694,6 +794,12 @@ int orc_cluster(const orc_run *R, int s, const uint64_t *idx, uint64_t n_sel, in
     *level = L;
     if (orc_attempts(R, *A, 0, n_attempts)) return ORC_EOVERFLOW;
     return 1;
+}
+
+int orc_cluster(const orc_run *R, int s, const uint64_t *idx, uint64_t n_sel, int composite,
+                uint64_t *det, double *A, int *level, uint64_t *n_attempts)
+{
+    return orc_cluster_ranked(R, s, idx, n_sel, R->qtot, 1, composite, det, A, level, n_attempts);
 }
 
 double orc_death(const orc_run *R, const uint64_t *det, double A, double tau, double shift)
@@ -917,42 +1023,85 @@ int orc_step(orc_run *R, double tau, double shift, uint64_t n_sel, orc_stats *st
                 return rc;
         }
     }
+    /* virtual processors (Sec. III.A): where each excitor sits this step, and the total
+     * weight of each processor's excitors */
+    const uint32_t np = R->opt.n_ranks > 1 ? R->opt.n_ranks : 1;
+    uint32_t *where = NULL;
+    uint64_t *qrank = NULL;
+    if (np > 1) {
+        where = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(R->n + 1));
+        qrank = (uint64_t *)calloc(np, sizeof(uint64_t));
+        if (!where || !qrank) {
+            free(where);
+            free(qrank);
+            return ORC_ENOMEM;
+        }
+        for (uint64_t i = 0; i < R->n; ++i) {
+            where[i] = orc_placement(W, R->keys + i * W, R->step, np, R->opt.move_shift, R->opt.hash_seed);
+            qrank[where[i]] += R->q[i];
+        }
+    }
     for (uint64_t k = 0; k < n_sel; ++k) {
         int lo = fnc ? 2 : 0, hi = R->l + 2;
         int s = draw_size(uniform(draw(R, PURPOSE_SELECT, k, 0, 0)), lo, hi);
         uint64_t idx[8];
         int ok = 1;
+        /* one processor: selection k is made by processor k mod N_p from its own excitors,
+         * which make count = the number of selections on that processor */
+        const uint32_t rank = (uint32_t)(k % np);
+        const uint64_t qnorm = np > 1 ? qrank[rank] : R->qtot;
+        const uint64_t count = np > 1 ? n_sel / np + (rank < n_sel % np ? 1 : 0) : n_sel;
         for (int a = 0; a < s; ++a) {
-            if (R->qtot == 0) {
+            if (qnorm == 0) {
                 ok = 0;
                 break;
             }
-            /* excitor with P[i-1] <= r < P[i] */
-            uint64_t r = below(draw(R, PURPOSE_SELECT, k, 0, 1 + a), R->qtot);
-            uint64_t lo_i = 0, hi_i = R->n;
-            while (lo_i < hi_i) {
-                uint64_t mid = (lo_i + hi_i) / 2;
-                if (R->pref[mid] > r)
-                    hi_i = mid;
-                else
-                    lo_i = mid + 1;
+            uint64_t r = below(draw(R, PURPOSE_SELECT, k, 0, 1 + a), qnorm);
+            if (np == 1) {
+                /* excitor with P[i-1] <= r < P[i] */
+                uint64_t lo_i = 0, hi_i = R->n;
+                while (lo_i < hi_i) {
+                    uint64_t mid = (lo_i + hi_i) / 2;
+                    if (R->pref[mid] > r)
+                        hi_i = mid;
+                    else
+                        lo_i = mid + 1;
+                }
+                idx[a] = lo_i;
+            } else {
+                /* the processor's excitors in store order, each owning q_i values of r */
+                uint64_t acc = 0, i = 0;
+                for (; i < R->n; ++i) {
+                    if (where[i] != rank) continue;
+                    acc += R->q[i];
+                    if (acc > r) break;
+                }
+                idx[a] = i;
             }
-            idx[a] = lo_i;
         }
         uint64_t det[MAXW], n = 0;
         double A = 0.0;
         int L = 0;
         if (ok) {
-            ok = orc_cluster(R, s, idx, n_sel, fnc, det, &A, &L, &n);
-            if (ok < 0) return ok;
+            ok = orc_cluster_ranked(R, s, idx, count, qnorm, np, fnc, det, &A, &L, &n);
+            if (ok < 0) {
+                free(where);
+                free(qrank);
+                return ok;
+            }
         }
         if (!ok) {
             ++discarded;
             continue;
         }
-        if ((rc = process_item(R, 1, PURPOSE_SPAWN_SAMPLED, k, det, A, L, n, tau, shift, &acc)))
+        if ((rc = process_item(R, 1, PURPOSE_SPAWN_SAMPLED, k, det, A, L, n, tau, shift, &acc))) {
+            free(where);
+            free(qrank);
             return rc;
+        }
     }
+    free(where);
+    free(qrank);
 
     /* annihilation (Sec. II): group records by key, sum each group in id order */
     g_sort_w = W;

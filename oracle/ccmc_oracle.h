@@ -58,6 +58,13 @@ typedef struct {
     double init_pop;                /* initial reference amplitude N_0 */
     double p_single;                /* molecular generator: probability of a single */
     uint64_t seed;                  /* Philox key */
+    /* Virtual processors (Sec. III.A, eq. ccmc_dist): 0 or 1 = one processor.  With
+     * n_ranks = N_p > 1 every excitor sits on processor p(D, i_tau) and each selection
+     * builds its cluster from the excitors of one processor only. */
+    uint32_t n_ranks;
+    uint32_t move_shift;            /* nu_move: an excitor may move every 2^nu_move steps;
+                                       >= 64 never (the static eq. fciqmc_dist) */
+    uint32_t hash_seed;             /* MurmurHash2 seed of the placement */
 } orc_options;
 
 typedef struct {
@@ -111,6 +118,20 @@ int orc_step(orc_run *, double tau, double shift, uint64_t n_sel, orc_stats *st)
 int orc_records_size(const orc_run *, uint64_t *n);
 int orc_records(const orc_run *, uint64_t *keys, double *amps, uint64_t *ids);
 
+/* ---- placement of excitors on virtual processors (Sec. III.A) ---- */
+/* MurmurHash2 (Austin Appleby, 32-bit, public domain) of len bytes. */
+uint32_t orc_murmur2(const void *key, int len, uint32_t seed);
+/* eq. ccmc_dist: o = (hash(D) + i_tau) >> nu_move; p = hash(D xor o) mod N_p, hashing the
+ * W words of D as 8W little-endian bytes (word 0 first) and xoring o into word 0. */
+uint32_t orc_placement(int W, const uint64_t *det, uint64_t i_tau, uint32_t n_ranks, uint32_t move_shift,
+                       uint32_t seed);
+/* Co-location of n excitors (keys[n][W]) over iterations i_tau = 0 .. T-1: for each
+ * checkpoint T_c (ascending, <= T), the sums over pairs i < j of c_ij and c_ij^2, where
+ * c_ij counts the iterations before T_c with p(D_i) = p(D_j). */
+int orc_codistribution(int W, const uint64_t *keys, uint64_t n, uint32_t n_ranks, uint32_t move_shift,
+                       uint32_t seed, const uint64_t *checkpoints, int n_checkpoints, uint64_t *sum_c,
+                       uint64_t *sum_c2);
+
 /* ---- components, exposed so that tests can enumerate every random outcome ---- */
 /* Fixed-point selection weight of a store amplitude. */
 uint64_t orc_weight(double amp);
@@ -119,6 +140,13 @@ uint64_t orc_weight(double amp);
  * Returns 1 with det/A/level/n filled, or 0 when the cluster is discarded. */
 int orc_cluster(const orc_run *, int s, const uint64_t *idx, uint64_t n_sel, int composite,
                 uint64_t *det, double *A, int *level, uint64_t *n_attempts);
+/* The same cluster drawn on one of N_p processors: `count` selections were made on that
+ * processor and its excitors' weights sum to qnorm; the selection probability carries the
+ * factor N_p^(1-s) (the s excitors share the processor with probability N_p^(1-s), and each
+ * processor makes 1/N_p of the selections: N_p^-s relative to one processor's own draws). */
+int orc_cluster_ranked(const orc_run *, int s, const uint64_t *idx, uint64_t count, uint64_t qnorm,
+                       uint32_t n_ranks, int composite, uint64_t *det, double *A, int *level,
+                       uint64_t *n_attempts);
 /* Attempt counts: cluster rule and non-composite rule. */
 int orc_attempts(const orc_run *, double A, int noncomposite, uint64_t *n);
 /* One spawning attempt from det with effective amplitude A and n attempts, given explicit
