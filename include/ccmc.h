@@ -78,7 +78,8 @@ typedef struct {
 
 /* Sampling options.  Defaults (ccmc_options_default): FP64, original selection, k_min 1,
  * multi-spawn off, non-composite threshold 1, spawn cutoff 0.01, occupation threshold 1,
- * init_pop 10, p_single 0.1, seed 1234, no budget, default stream, no spawn ids. */
+ * init_pop 10, p_single 0.1, seed 1234, no budget, default stream, no spawn ids, one
+ * processor (n_ranks 1, move_shift 5, hash_seed 0). */
 typedef struct {
     int precision;                 /* CCMC_FP64 or CCMC_FP32 (amplitudes, spawns, integrals) */
     int full_noncomposite;         /* 1: full non-composite sampling (Sec. IV.B) */
@@ -93,6 +94,17 @@ typedef struct {
     uint64_t hbm_budget_bytes;     /* 0: no limit; else device memory the state may hold */
     void *hip_stream;              /* hipStream_t to run on; NULL: the library's own stream */
     int keep_spawn_ids;            /* 1: keep the last step's spawn list for ccmc_export_spawns */
+    /* Virtual processors (Sec. III.A, eq. ccmc_dist), emulated on the one GPU.  With
+     * n_ranks = N_p > 1 excitor D sits on processor p(D, i_tau) = hash(D xor o) mod N_p with
+     * o = (hash(D) + i_tau) >> move_shift (hash: MurmurHash2 with hash_seed over the W words of
+     * D as 8W little-endian bytes, o xored into word 0; i_tau the step index), and selection k
+     * of a step is made by processor k mod N_p from its own excitors, with its selection
+     * probability scaled by N_p^(1-s).  Non-composite items (full non-composite sampling),
+     * spawning and annihilation are unchanged.  n_ranks 0 or 1: one processor; at most 512.
+     * move_shift >= 64: excitors never move (eq. fciqmc_dist). */
+    uint32_t n_ranks;
+    uint32_t move_shift;
+    uint32_t hash_seed;
 } ccmc_options;
 
 typedef struct {
@@ -165,8 +177,24 @@ ccmc_status ccmc_energy(const ccmc_state *st, double *e_hf, double *eproj_num, d
 void ccmc_free(ccmc_state *st);
 
 /* Text of the last error on this state ("" if none); valid until the next call on it.
- * With st == NULL: the last error of a failed ccmc_init on this thread. */
+ * With st == NULL: the last error of a failed ccmc_init or ccmc_codistribution on this
+ * thread. */
 const char *ccmc_last_error(const ccmc_state *st);
+
+/* Co-location statistics of the placement eq. ccmc_dist (Sec. III.A; the analysis of the
+ * co-distribution figure).  keys: host array [n][n_words] of distinct determinants (word 0
+ * least significant).  For iterations i_tau = 0 .. T-1 (T = the last checkpoint) every
+ * excitor is placed on one of n_ranks processors (move_shift, hash_seed as in
+ * ccmc_options); c_ij counts the iterations before a checkpoint T_c at which excitors i and
+ * j share a processor.  For each checkpoint (host array, ascending, 1 to 64 of them) the
+ * host outputs receive sum over pairs i < j of c_ij and of c_ij^2 (exact integers): the mean
+ * co-location probability is sum_c / (T_c n (n-1) / 2).  Runs on the current device and
+ * allocates n T 2-byte placements there (n T <= 2^31, T <= 2^24, 1 <= n_ranks <= 65535);
+ * CCMC_EINVAL on bad arguments, CCMC_ENOMEM / CCMC_EDEVICE from HIP, with
+ * ccmc_last_error(NULL) explaining. */
+ccmc_status ccmc_codistribution(int n_words, const uint64_t *keys, uint64_t n, uint32_t n_ranks,
+                                uint32_t move_shift, uint32_t hash_seed, const uint64_t *checkpoints,
+                                int n_checkpoints, uint64_t *sum_c, uint64_t *sum_c2);
 
 /* Number of excitors in the store; then ccmc_export copies the store (keys[n][W] in key
  * order and amplitudes as FP64), N_0 and the step index into host arrays of `capacity`

@@ -45,7 +45,8 @@ class ccmc_options(C.Structure):
                 ("multispawn_threshold", C.c_double), ("noncomposite_threshold", C.c_double),
                 ("spawn_cutoff", C.c_double), ("occupation_threshold", C.c_double), ("init_pop", C.c_double),
                 ("p_single", C.c_double), ("seed", C.c_uint64), ("hbm_budget_bytes", C.c_uint64),
-                ("hip_stream", C.c_void_p), ("keep_spawn_ids", C.c_int)]
+                ("hip_stream", C.c_void_p), ("keep_spawn_ids", C.c_int), ("n_ranks", C.c_uint32),
+                ("move_shift", C.c_uint32), ("hash_seed", C.c_uint32)]
 
 
 class ccmc_stats(C.Structure):
@@ -66,7 +67,7 @@ class ccmc_kernel_time(C.Structure):
 EXPORTED = ["ccmc_options_default", "ccmc_init", "ccmc_step", "ccmc_step_batch", "ccmc_energy", "ccmc_free",
             "ccmc_last_error",
             "ccmc_export_size", "ccmc_export", "ccmc_import", "ccmc_spawns_size", "ccmc_export_spawns",
-            "ccmc_profile", "ccmc_profile_read", "ccmc_dims", "ccmc_memory"]
+            "ccmc_profile", "ccmc_profile_read", "ccmc_dims", "ccmc_memory", "ccmc_codistribution"]
 
 _lib = None
 _u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
@@ -101,6 +102,8 @@ def lib():
             "ccmc_profile_read": (st, [vp, C.POINTER(ccmc_kernel_time), C.c_int, C.POINTER(C.c_int)]),
             "ccmc_memory": (st, [vp, C.POINTER(C.c_uint64)]),
             "ccmc_dims": (st, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+            "ccmc_codistribution": (st, [C.c_int, _u64p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p,
+                                         C.c_int, _u64p, _u64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -267,3 +270,20 @@ def ccmc_step_batch(states, tau, shift, n_attempts):
         err = lib().ccmc_last_error(hs[i]).decode()
         res.append(CCMCError(rc, err) if (rc != 0 and err) else outs[i].as_dict())
     return res
+
+
+def ccmc_codistribution(keys, n_ranks: int, move_shift: int, hash_seed: int, checkpoints):
+    """Co-location sums of the placement over iterations 0 .. T-1 (``ccmc_codistribution``):
+    for each checkpoint, the sums over pairs i < j of c_ij and c_ij^2."""
+    keys = np.ascontiguousarray(np.asarray(keys, np.uint64))
+    if keys.ndim != 2:
+        raise ValueError("keys must be [n][n_words]")
+    cp = np.ascontiguousarray(checkpoints, np.uint64)
+    s1 = np.zeros(len(cp), np.uint64)
+    s2 = np.zeros(len(cp), np.uint64)
+    kk = keys.ravel() if keys.size else np.zeros(1, np.uint64)
+    rc = lib().ccmc_codistribution(keys.shape[1], kk, keys.shape[0], int(n_ranks), int(move_shift), int(hash_seed), cp,
+                                   len(cp), s1, s2)
+    if rc != 0:
+        raise CCMCError(rc, lib().ccmc_last_error(None).decode())
+    return s1, s2

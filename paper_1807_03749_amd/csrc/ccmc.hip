@@ -93,6 +93,7 @@ struct ccmc_state {
     double last_num = 0, last_den = 0;
     // per-step buffers
     DevBuf P, guide, delta, rtab;
+    DevBuf vkey[2], perm, seg;  // virtual processors: placement keys, the partition, its segments
     uint64_t rt_n = 0;   // rank-table buckets
     uint32_t rsh = 0;    // rank-table shift
     uint64_t last_q = 0; // Q of the last step (sizes the next selection guide)
@@ -510,6 +511,11 @@ ccmc_status ensure_store(ccmc_state *st, uint64_t n)
     TRY(ensure(st, st->srank[1 - c], nc * sizeof(uint64_t)));
     TRY(ensure(st, st->P, nc * sizeof(uint64_t)));
     TRY(ensure(st, st->guide, guide_cap(nc) * sizeof(uint32_t)));
+    if (st->opt.n_ranks > 1) {
+        for (DevBuf *b : {&st->vkey[0], &st->vkey[1]}) TRY(ensure(st, *b, nc * sizeof(uint64_t)));
+        TRY(ensure(st, st->perm, nc * sizeof(uint32_t)));
+        TRY(ensure(st, st->seg, (kMaxRanks + 2) * sizeof(uint32_t)));
+    }
     // the per-entry sums start at zero (a grown buffer holds no contents)
     TRY(ensure(st, st->delta, nc * sizeof(double)));
     k_fill<double><<<grid_for(nc), kThreads, 0, st->stream>>>(ptr<double>(st->delta), nc, 0.0);
@@ -544,13 +550,16 @@ struct Plan {
     unsigned nb_fnc = 0, nb_sel = 0, nb_rt = 0, nb_abs = 0;
     uint64_t o_tick = 0, o_weights = 0, o_off = 0, o_boff = 0, o_merge = 0, o_ghist = 0, o_rstat = 0;
     uint64_t o_fold = 0, o_fin = 0;
+    bool ranked = false;     // virtual processors: the store is partitioned by processor
+    uint64_t ptiles = 0;     // radix tiles of the partition
+    uint64_t o_pghist = 0, o_pstat = 0;
     uint64_t *lb = nullptr;
     Scratch *sc = nullptr;
     ccmc_status rc = CCMC_OK;  // this state's outcome
     bool replay = false;       // a capacity overflowed: grow and step again
 };
 
-enum { kTkWeights, kTkOff, kTkBoff, kTkFold, kTkMerge, kTkRadix, kTickets = kTkRadix + kRadixMaxPasses };
+enum { kTkWeights, kTkOff, kTkBoff, kTkFold, kTkMerge, kTkPlace, kTkRadix, kTickets = kTkRadix + kRadixMaxPasses };
 
 // Sizes and capacities of one state's step (all allocation happens here).
 template <int W, typename T>
@@ -577,6 +586,9 @@ ccmc_status plan_sizes(Plan<W, T> &p)
     a.key1 = (uint32_t)(st->opt.seed >> 32);
     a.n_sel = p.n_sel;
     a.fnc = p.fnc ? 1 : 0;
+    p.ranked = st->opt.n_ranks > 1;
+    a.n_ranks = p.ranked ? st->opt.n_ranks : 1;
+    p.ptiles = p.ranked ? (ne + kSortTile - 1) / kSortTile : 0;
     {
         // guide shift from the last step's Q (any shift gives the same draws; this one keeps
         // about two buckets per excitor)
@@ -664,7 +676,9 @@ ccmc_status plan_area(Plan<W, T> &p, int passes)
     p.o_ghist = p.o_merge + grid_for(p.mcap, kMergeTile);
     p.o_rstat = p.o_ghist + (uint64_t)passes * kRadixBins / 2;
     p.o_fold = p.o_rstat + (uint64_t)passes * p.tiles * kRadixBins;
-    p.o_fin = p.o_fold + 5 * p.fold_tiles;  // lead, has_head, open, open_new, look-back status
+    p.o_pghist = p.o_fold + 5 * p.fold_tiles;  // lead, has_head, open, open_new, look-back status
+    p.o_pstat = p.o_pghist + kRadixBins / 2;
+    p.o_fin = p.o_pstat + p.ptiles * kRadixBins;
     p.lb_words = p.o_fin + kMaxFinalParts * (sizeof(FinalPart) / 8);
     TRY(ensure(st, st->lb, p.lb_words * sizeof(uint64_t)));
     p.lb = ptr<uint64_t>(st->lb);
@@ -783,6 +797,45 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         stage(ar, recs, "clear", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.lb_words + p.ne}; }),
               [s](const ClearArgs *a, BatchMap bm, unsigned g) { k_clear<<<g, kThreads, 0, s>>>(a, bm); });
     }
+    // ---- virtual processors (Sec. III.A): place every excitor, then partition the store by
+    // processor with one stable radix pass (store order within each processor)
+    {
+        std::vector<PlaceArgs<W>> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            args.push_back(PlaceArgs<W>{ptr<uint64_t>(st->skey[p.c]), st->scap, p.ne, st->step, st->opt.n_ranks,
+                                        st->opt.move_shift, st->opt.hash_seed, ptr<uint64_t>(st->vkey[0]), p.sc});
+            blk[i] = p.ranked ? grid_for(p.ne) : 0;
+        }
+        stage(ar, recs, "place", args, blk, works([&](auto &p) { return Work{kb + 8.0, nullptr, p.ranked ? p.ne : 0}; }),
+              [s](const PlaceArgs<W> *a, BatchMap bm, unsigned g) { k_place<W><<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    {
+        std::vector<RadixGhistArgs> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            args.push_back(RadixGhistArgs{ptr<uint64_t>(p.st->vkey[0]), &p.sc->n_place, 1,
+                                          reinterpret_cast<uint32_t *>(p.lb + p.o_pghist)});
+            blk[i] = (uint32_t)p.ptiles;
+        }
+        stage(ar, recs, "place_ghist", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.ranked ? p.ne : 0}; }),
+              [s](const RadixGhistArgs *a, BatchMap bm, unsigned g) { k_radix_ghist<<<g, kThreads, 0, s>>>(a, bm); });
+    }
+    {
+        std::vector<RadixOnesweepArgs> args;
+        for (size_t i = 0; i < n; ++i) {
+            auto &p = ps[i];
+            ccmc_state *st = p.st;
+            args.push_back(RadixOnesweepArgs{ptr<uint64_t>(st->vkey[0]), nullptr, ptr<uint64_t>(st->vkey[1]),
+                                             ptr<uint32_t>(st->perm), &p.sc->n_place, 0,
+                                             reinterpret_cast<const uint32_t *>(p.lb + p.o_pghist), p.lb + p.o_pstat,
+                                             p.lb + p.o_tick + kTkPlace});
+            blk[i] = (uint32_t)p.ptiles;
+        }
+        stage(ar, recs, "place_sweep", args, blk, works([&](auto &p) { return Work{20.0, nullptr, p.ranked ? p.ne : 0}; }),
+              [s](const RadixOnesweepArgs *a, BatchMap bm, unsigned g) { k_radix_onesweep<<<g, kThreads, 0, s>>>(a, bm); });
+    }
     // ---- (a1) selection weights, formed inside the scan of their prefix; the draw guide
     {
         using A = ScanLbArgs<uint64_t, WeightSrc<T>, ArrayOut<uint64_t>>;
@@ -790,7 +843,8 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
             ccmc_state *st = p.st;
-            args.push_back(A{WeightSrc<T>{ptr<T>(st->samp[p.c]), p.sc}, ArrayOut<uint64_t>{ptr<uint64_t>(st->P)}, p.ne, 1,
+            const uint32_t *perm = p.ranked ? ptr<uint32_t>(st->perm) : nullptr;
+            args.push_back(A{WeightSrc<T>{ptr<T>(st->samp[p.c]), p.sc, perm}, ArrayOut<uint64_t>{ptr<uint64_t>(st->P)}, p.ne, 1,
                              p.lb + p.o_weights, p.lb + p.o_tick + kTkWeights, &p.sc->qtot});
             blk[i] = (uint32_t)scan_tiles(p.ne);
         }
@@ -805,7 +859,9 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
             ccmc_state *st = p.st;
-            args.push_back(GuideArgs{ptr<uint64_t>(st->P), ptr<uint32_t>(st->guide), p.a.gcap, p.a.gsh, p.ne});
+            args.push_back(GuideArgs{ptr<uint64_t>(st->P), ptr<uint32_t>(st->guide), p.a.gcap, p.a.gsh, p.ne,
+                                     p.ranked ? ptr<uint64_t>(st->vkey[1]) : nullptr,
+                                     p.ranked ? ptr<uint32_t>(st->seg) : nullptr, p.a.n_ranks});
             blk[i] = p.n_sel && p.ne ? grid_for(p.ne) : 0;
         }
         // bytes: prefix read, about one guide entry per two excitors
@@ -837,7 +893,9 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             const uint64_t *srank = ptr<uint64_t>(st->srank[p.c]);
             const RankTable rt{srank, p.ne, ptr<uint32_t>(st->rtab), st->rt_n, st->rsh};
             args.push_back(A{st->sd, ptr<uint64_t>(st->skey[p.c]), ptr<T>(st->samp[p.c]), ptr<T>(st->sK[p.c]), st->scap,
-                             p.ne, ptr<uint64_t>(st->P), ptr<uint32_t>(st->guide), st->n0, p.a, items_of(p), p.nb_fnc,
+                             p.ne, ptr<uint64_t>(st->P), ptr<uint32_t>(st->guide),
+                             Ranks{p.ranked ? ptr<uint32_t>(st->perm) : nullptr, p.ranked ? ptr<uint32_t>(st->seg) : nullptr},
+                             st->n0, p.a, items_of(p), p.nb_fnc,
                              p.n_fnc, p.nb_fnc + p.nb_sel, rt, parts_of(p), p.sc});
             blk[i] = p.nb_fnc + p.nb_sel + p.nb_rt;
         }
@@ -1328,7 +1386,8 @@ void destroy(ccmc_state *st)
                       &st->iA, &st->ideath, &st->in, &st->ilevel, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,
                       &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->boff, &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
                       &st->sidx[0], &st->sidx[1], &st->tile_region,
-                      &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->lb, &st->arg_dev, &st->batch_scr};
+                      &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->lb, &st->arg_dev, &st->batch_scr,
+                      &st->vkey[0], &st->vkey[1], &st->perm, &st->seg};
     for (DevBuf *b : bufs) release(st, *b);
     for (auto &p : st->pending) {
         (void)hipEventDestroy(p.a);
@@ -1344,7 +1403,88 @@ void destroy(ccmc_state *st)
 }  // namespace
 
 // =========================================================================== C ABI
+namespace {
+template <int W>
+void codist_launch(const uint64_t *keys, uint64_t n, uint64_t T, uint32_t n_ranks, uint32_t move_shift, uint32_t seed,
+                   uint16_t *pl, const uint64_t *cps, int ncp, unsigned long long *sums, hipStream_t s)
+{
+    const uint64_t m = n * T;
+    if (m) k_codist_place<W><<<(unsigned)((m + kThreads - 1) / kThreads), kThreads, 0, s>>>(keys, n, T, n_ranks, move_shift, seed, pl);
+    const dim3 g((unsigned)((n + kThreads - 1) / kThreads), (unsigned)((n + kCoRows - 1) / kCoRows));
+    if (n) k_codist_pairs<<<g, kThreads, 0, s>>>(pl, n, cps, ncp, sums);
+}
+}  // namespace
+
 extern "C" {
+
+
+ccmc_status ccmc_codistribution(int n_words, const uint64_t *keys, uint64_t n, uint32_t n_ranks, uint32_t move_shift,
+                                uint32_t hash_seed, const uint64_t *checkpoints, int n_checkpoints, uint64_t *sum_c,
+                                uint64_t *sum_c2)
+{
+    g_init_error.clear();
+    if (n_words < 1 || n_words > kMaxWords || n_checkpoints < 1 || n_checkpoints > 64 || n_ranks < 1 ||
+        n_ranks > 65535 || !checkpoints || !sum_c || !sum_c2 || (n && !keys)) {
+        g_init_error = "ccmc_codistribution: invalid argument";
+        return CCMC_EINVAL;
+    }
+    for (int c = 1; c < n_checkpoints; ++c)
+        if (checkpoints[c] < checkpoints[c - 1]) {
+            g_init_error = "ccmc_codistribution: checkpoints must ascend";
+            return CCMC_EINVAL;
+        }
+    const uint64_t T = checkpoints[n_checkpoints - 1];
+    if (T > (1ull << 24) || (n && T > (1ull << 31) / n) || n > (1ull << 31)) {
+        g_init_error = "ccmc_codistribution: more than 2^31 placements or 2^24 iterations";
+        return CCMC_EINVAL;
+    }
+    hipStream_t s = nullptr;
+    void *dk = nullptr, *dpl = nullptr, *dcp = nullptr, *dsum = nullptr;
+    auto fail = [&](hipError_t e) {
+        g_init_error = std::string("ccmc_codistribution: ") + hipGetErrorString(e);
+        (void)hipFree(dk);
+        (void)hipFree(dpl);
+        (void)hipFree(dcp);
+        (void)hipFree(dsum);
+        return e == hipErrorOutOfMemory ? CCMC_ENOMEM : CCMC_EDEVICE;
+    };
+    hipError_t e;
+    const size_t kbytes = (size_t)(n ? n : 1) * n_words * sizeof(uint64_t);
+    if ((e = hipMalloc(&dk, kbytes)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&dpl, (size_t)(n * T ? n * T : 1) * sizeof(uint16_t))) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&dcp, n_checkpoints * sizeof(uint64_t))) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&dsum, 2 * n_checkpoints * sizeof(uint64_t))) != hipSuccess) return fail(e);
+    if (n && (e = hipMemcpy(dk, keys, n * n_words * sizeof(uint64_t), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+    if ((e = hipMemcpy(dcp, checkpoints, n_checkpoints * sizeof(uint64_t), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    if ((e = hipMemset(dsum, 0, 2 * n_checkpoints * sizeof(uint64_t))) != hipSuccess) return fail(e);
+    auto *K = static_cast<const uint64_t *>(dk);
+    auto *PL = static_cast<uint16_t *>(dpl);
+    auto *CP = static_cast<const uint64_t *>(dcp);
+    auto *SU = static_cast<unsigned long long *>(dsum);
+    switch (n_words) {
+    case 1: codist_launch<1>(K, n, T, n_ranks, move_shift, hash_seed, PL, CP, n_checkpoints, SU, s); break;
+    case 2: codist_launch<2>(K, n, T, n_ranks, move_shift, hash_seed, PL, CP, n_checkpoints, SU, s); break;
+    case 3: codist_launch<3>(K, n, T, n_ranks, move_shift, hash_seed, PL, CP, n_checkpoints, SU, s); break;
+    case 4: codist_launch<4>(K, n, T, n_ranks, move_shift, hash_seed, PL, CP, n_checkpoints, SU, s); break;
+    case 5: codist_launch<5>(K, n, T, n_ranks, move_shift, hash_seed, PL, CP, n_checkpoints, SU, s); break;
+    case 6: codist_launch<6>(K, n, T, n_ranks, move_shift, hash_seed, PL, CP, n_checkpoints, SU, s); break;
+    case 7: codist_launch<7>(K, n, T, n_ranks, move_shift, hash_seed, PL, CP, n_checkpoints, SU, s); break;
+    default: codist_launch<8>(K, n, T, n_ranks, move_shift, hash_seed, PL, CP, n_checkpoints, SU, s); break;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+    std::vector<uint64_t> h(2 * n_checkpoints);
+    if ((e = hipMemcpy(h.data(), dsum, h.size() * sizeof(uint64_t), hipMemcpyDeviceToHost)) != hipSuccess) return fail(e);
+    for (int c = 0; c < n_checkpoints; ++c) {
+        sum_c[c] = h[2 * c];
+        sum_c2[c] = h[2 * c + 1];
+    }
+    (void)hipFree(dk);
+    (void)hipFree(dpl);
+    (void)hipFree(dcp);
+    (void)hipFree(dsum);
+    return CCMC_OK;
+}
 
 ccmc_status ccmc_options_default(ccmc_options *opt)
 {
@@ -1360,6 +1500,9 @@ ccmc_status ccmc_options_default(ccmc_options *opt)
     opt->init_pop = 10.0;
     opt->p_single = 0.1;
     opt->seed = 1234;
+    opt->n_ranks = 1;
+    opt->move_shift = 5;
+    opt->hash_seed = 0;
     return CCMC_OK;
 }
 
@@ -1379,6 +1522,10 @@ ccmc_status ccmc_init(const ccmc_system *sys, const ccmc_integrals *ints, int tr
     if (opt->min_spawn_attempts < 1 || !(opt->spawn_cutoff >= 0) || !(opt->occupation_threshold >= 0) ||
         !(opt->p_single >= 0 && opt->p_single <= 1) || !std::isfinite(opt->init_pop)) {
         g_init_error = "ccmc_init: invalid sampling options";
+        return CCMC_EINVAL;
+    }
+    if (opt->n_ranks > kMaxRanks) {
+        g_init_error = "ccmc_init: n_ranks above 512";
         return CCMC_EINVAL;
     }
     ccmc_state *st = new ccmc_state();

@@ -285,6 +285,48 @@ __device__ __forceinline__ T reference_element(const SysDev &S, const uint64_t *
     return double_element<W, T>(S, d, parts[0], parts[1], holes[0], holes[1]);
 }
 
+// ------------------------------------------------ virtual processors (Sec. III.A)
+// MurmurHash2 (A. Appleby, 32-bit) of the W words of d read as 8W little-endian bytes: two
+// 4-byte blocks per word, low half first.  8W is a multiple of 4, so there is no tail.
+template <int W>
+__device__ __forceinline__ uint32_t murmur2_det(const uint64_t *d, uint32_t seed)
+{
+    constexpr uint32_t m = 0x5bd1e995u;
+    uint32_t h = seed ^ (uint32_t)(8 * W);
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            uint32_t k = (uint32_t)(d[w] >> (32 * half));
+            k *= m;
+            k ^= k >> 24;
+            k *= m;
+            h *= m;
+            h ^= k;
+        }
+    h ^= h >> 13;
+    h *= m;
+    h ^= h >> 15;
+    return h;
+}
+
+constexpr uint32_t kMaxRanks = 512;  // one radix pass partitions the store by processor
+
+// eq. ccmc_dist: o = (hash(D) + i_tau) >> nu_move, p = hash(D xor o) mod N_p, with o xored
+// into word 0; nu_move >= 64 leaves o = 0 (the static placement hash(D) mod N_p).
+template <int W>
+__device__ __forceinline__ uint32_t placement(const uint64_t *d, uint64_t i_tau, uint32_t n_ranks,
+                                              uint32_t move_shift, uint32_t seed)
+{
+    if (n_ranks <= 1) return 0;
+    const uint64_t o = move_shift >= 64 ? 0 : ((uint64_t)murmur2_det<W>(d, seed) + i_tau) >> move_shift;
+    uint64_t x[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = d[w];
+    x[0] ^= o;
+    return murmur2_det<W>(x, seed) % n_ranks;
+}
+
 // K_D = H_DD - E_HF from the holes I and particles A of D:
 // sum_A f_a - sum_I f_i + sum_{a<b} <ab||ab> + sum_{i<j} <ij||ij> - sum_{a,i} <ai||ai>.
 // With IssueAll, up to kDiagFast holes and particles every table load is issued before the

@@ -39,7 +39,7 @@ struct Scratch {
     uint64_t n_slots;         // record slots of the step (deaths + attempts)
     uint64_t n_rec;           // records emitted by the step
     uint64_t n_live;          // records the annihilation works on (0 after an overflow)
-    uint64_t spare0;
+    uint64_t n_place;         // excitors partitioned by virtual processor (the store size)
     uint64_t spare1;
     uint64_t n_new;           // new determinants
     uint64_t hf_hit;
@@ -60,6 +60,15 @@ struct StepArgs {
     int fnc;
     uint32_t gsh;             // shift of the selection guide
     uint64_t gcap;            // entries of the selection guide
+    uint32_t n_ranks;         // virtual processors (1: none)
+};
+
+// The store partitioned by virtual processor: perm[j] is the store index at position j of
+// the partition (processors in order, store order within each) and processor r holds
+// positions [seg[r], seg[r + 1]).  Unused with one processor.
+struct Ranks {
+    const uint32_t *perm;
+    const uint32_t *seg;
 };
 
 // Per-block partial statistics of the item kernels, reduced by k_final.
@@ -123,10 +132,11 @@ template <typename T>
 struct WeightSrc {
     const T *amp;
     Scratch *sc;
+    const uint32_t *perm;  // weights in the order of the processor partition, or store order
     static constexpr uint64_t kCap = 1ull << 52;  // |N_i| >= 2^28 (or NaN) is a blow-up
     __device__ __forceinline__ uint64_t operator()(uint64_t i) const
     {
-        const double a = fabs((double)amp[i]);
+        const double a = fabs((double)amp[perm ? perm[i] : i]);
         double w = rint(a * 16777216.0);
         w = w < 1.0 ? 1.0 : w;
         return (uint64_t)fmin(w, (double)kCap);  // NaN -> kCap
@@ -151,6 +161,11 @@ struct GuideArgs {
     uint64_t gcap;
     uint32_t gsh;
     uint64_t n;
+    // virtual processors: the sorted processor of each partition position, and the segment
+    // starts to fill (seg[r] = first position whose processor is at least r, r <= n_ranks)
+    const uint64_t *vsorted;
+    uint32_t *seg;
+    uint32_t n_ranks;
 };
 
 __global__ void __launch_bounds__(kThreads) k_guide(const GuideArgs *__restrict__ args, BatchMap bm)
@@ -167,6 +182,47 @@ __global__ void __launch_bounds__(kThreads) k_guide(const GuideArgs *__restrict_
         b0 = b0 < b1 ? b0 : b1;
     }
     wave_fill_ranges<uint32_t>(A.guide, b0, b1, (uint32_t)g);
+    if (A.n_ranks > 1) {
+        uint64_t r0 = 0, r1 = 0, e0 = 0, e1 = 0;
+        if (g < A.n) {
+            const uint64_t r = A.vsorted[g];
+            r0 = g ? A.vsorted[g - 1] + 1 : 0;  // processors (previous, r] start at g
+            r1 = r + 1;
+            if (g + 1 == A.n) {  // processors after the last one start at n
+                e0 = r + 1;
+                e1 = (uint64_t)A.n_ranks + 1;
+            }
+        }
+        wave_fill_ranges<uint32_t>(A.seg, r0, r1, (uint32_t)g);
+        wave_fill_ranges<uint32_t>(A.seg, e0, e1, (uint32_t)A.n);
+    }
+}
+
+// Processor of every store entry this step (eq. ccmc_dist), as the key of the one-pass radix
+// partition; also the partition's length for the radix kernels.
+template <int W>
+struct PlaceArgs {
+    const uint64_t *key;
+    uint64_t stride;
+    uint64_t ne;
+    uint64_t i_tau;
+    uint32_t n_ranks, move_shift, seed;
+    uint64_t *vkey;
+    Scratch *sc;
+};
+
+template <int W>
+__global__ void __launch_bounds__(kThreads) k_place(const PlaceArgs<W> *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    const PlaceArgs<W> &A = args[batch_state(bm, blk, nblk)];
+    const uint64_t i = (uint64_t)blk * kThreads + threadIdx.x;
+    if (i == 0) A.sc->n_place = A.ne;
+    if (i >= A.ne) return;
+    uint64_t d[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) d[w] = A.key[(uint64_t)w * A.stride + i];
+    A.vkey[i] = placement<W>(d, A.i_tau, A.n_ranks, A.move_shift, A.seed);
 }
 
 // The rank table of the store lookups: rtab[c] is the first store entry whose rank is at
@@ -194,6 +250,73 @@ __device__ __forceinline__ void rank_table_block(unsigned blk, const RankTable &
             h0 = mid;
     }
     rt.rtab[c] = (uint32_t)l0;
+}
+
+// ------------------------------------- co-location of excitors over iterations (Sec. III.A)
+// pl[t * n + i] = processor of excitor i at iteration t, for t < T.
+template <int W>
+__global__ void __launch_bounds__(kThreads) k_codist_place(const uint64_t *__restrict__ keys, uint64_t n, uint64_t T,
+                                                           uint32_t n_ranks, uint32_t move_shift, uint32_t seed,
+                                                           uint16_t *__restrict__ pl)
+{
+    const uint64_t x = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (x >= n * T) return;
+    const uint64_t t = x / n, i = x - t * n;
+    uint64_t d[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) d[w] = keys[i * W + w];
+    pl[x] = (uint16_t)placement<W>(d, t, n_ranks, move_shift, seed);
+}
+
+// Pair counts c_ij = #{t < T_c : pl[t][i] = pl[t][j]} for i < j, summed (c and c^2) at each
+// checkpoint T_c.  A block holds kCoRows excitors i against 256 excitors j, one j per thread
+// with a counter per i; blocks entirely on or below the diagonal exit.  Integer sums, so the
+// result does not depend on the order of the atomic additions.
+constexpr int kCoRows = 16;
+
+__global__ void __launch_bounds__(kThreads) k_codist_pairs(const uint16_t *__restrict__ pl, uint64_t n,
+                                                           const uint64_t *__restrict__ cps, int ncp,
+                                                           unsigned long long *__restrict__ sums)
+{
+    const uint64_t i0 = (uint64_t)blockIdx.y * kCoRows;
+    const uint64_t jb = (uint64_t)blockIdx.x * kThreads;
+    if (jb + kThreads <= i0 + 1) return;  // every j of the block is <= every i
+    const uint64_t j = jb + threadIdx.x;
+    const bool jv = j < n;
+    uint32_t c[kCoRows];
+#pragma unroll
+    for (int r = 0; r < kCoRows; ++r) c[r] = 0;
+    const uint64_t T = cps[ncp - 1];
+    int next = 0;
+    for (uint64_t t = 0;; ++t) {
+        while (next < ncp && cps[next] == t) {
+            uint64_t s1 = 0, s2 = 0;
+#pragma unroll
+            for (int r = 0; r < kCoRows; ++r) {
+                const uint64_t i = i0 + r;
+                if (jv && i < j) {
+                    s1 += c[r];
+                    s2 += (uint64_t)c[r] * c[r];
+                }
+            }
+            s1 = block_reduce_sum(s1);
+            s2 = block_reduce_sum(s2);
+            if (threadIdx.x == 0) {
+                atomicAdd(&sums[2 * next], (unsigned long long)s1);
+                atomicAdd(&sums[2 * next + 1], (unsigned long long)s2);
+            }
+            ++next;
+        }
+        if (t >= T) break;
+        const uint16_t *row = pl + t * n;
+        const uint32_t rj = jv ? row[j] : 0x10000u;
+#pragma unroll
+        for (int r = 0; r < kCoRows; ++r) {
+            const uint64_t i = i0 + r;
+            const uint32_t ri = row[i < n ? i : n - 1];
+            c[r] += (i < n && ri == rj) ? 1u : 0u;
+        }
+    }
 }
 
 // ------------------------------------------------------- non-composite items (FNC)
@@ -258,14 +381,24 @@ __device__ __forceinline__ void noncomposite_block(unsigned blk, const SysDev &S
 template <int W, typename T>
 __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
                                                      uint64_t sstride, uint64_t ne, const uint64_t *__restrict__ P,
-                                                     const uint32_t *__restrict__ guide, double n0, StepArgs a,
+                                                     const uint32_t *__restrict__ guide, Ranks rk, double n0, StepArgs a,
                                                      Items<T> it, uint64_t item_base, ItemPartials part, Scratch *sc)
 {
     const uint64_t k = (uint64_t)blk * kThreads + threadIdx.x;
     double num = 0.0;
     uint64_t att = 0, disc = 0, mx = 0;
     if (k < a.n_sel) {
-        const uint64_t Q = sc->qtot;
+        // With N_p virtual processors selection k is made by processor k mod N_p, whose
+        // excitors hold the prefix range [base, base + Q) of the partition's weights and
+        // which makes `count` of the step's selections (Sec. III.A).
+        uint64_t Q = sc->qtot, base = 0, count = a.n_sel;
+        if (a.n_ranks > 1) {
+            const uint32_t rank = (uint32_t)(k % a.n_ranks);
+            const uint32_t s0 = ne ? rk.seg[rank] : 0, s1 = ne ? rk.seg[rank + 1] : 0;
+            base = s0 ? P[s0 - 1] : 0;
+            Q = (s1 ? P[s1 - 1] : 0) - base;
+            count = a.n_sel / a.n_ranks + (rank < a.n_sel % a.n_ranks ? 1 : 0);
+        }
         const uint32_t gsh = a.gsh;
         Draws r(a.key0, a.key1, kSelect, (uint32_t)k, 0u, a.step);
         const int lo = a.fnc ? 2 : 0, hi = S.l + 2;
@@ -279,7 +412,7 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
         for (int c = 0; c < kMaxClusterSize; ++c) {
             xs[c] = 0;
             l0[c] = h0[c] = 0;
-            if (c < s && ok) xs[c] = below(r.get(1 + c), Q);
+            if (c < s && ok) xs[c] = base + below(r.get(1 + c), Q);
         }
 #pragma unroll
         for (int c = 0; c < kMaxClusterSize; ++c) {
@@ -315,22 +448,34 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
 #pragma unroll
             for (int b = 0; b < c; ++b)
                 if (c < s) ok &= (l0[b] != l0[c]);
-        // selection probability and product of amplitudes, in draw order
+        // selection probability and product of amplitudes, in draw order; l0 becomes the
+        // store index of each draw
         double fact = 1.0;
         for (int c = 2; c <= s; ++c) fact *= (double)c;
-        double p = (double)a.n_sel * size_prob(s, lo, hi) * fact;
+        double p = (double)count * size_prob(s, lo, hi) * fact;
         T prod = (T)n0;
 #pragma unroll
         for (int c = 0; c < kMaxClusterSize; ++c) {
             if (c < s && ok) {
                 const uint32_t i = l0[c];
                 const uint64_t qi = P[i] - (i ? P[i - 1] : 0);
-                const T ni = samp[i];
+                if (a.n_ranks > 1) l0[c] = rk.perm[i];
+                const T ni = samp[l0[c]];
                 p *= (double)qi / (double)Q;
                 if (c == 0)
                     prod = ni;
                 else
                     prod *= ni / (T)n0;
+            }
+        }
+        // the s excitors share one of N_p processors: times N_p^(1-s) (Sec. III.A)
+        if (a.n_ranks > 1) {
+            if (s == 0) {
+                p *= (double)a.n_ranks;
+            } else {
+                double dd = 1.0;
+                for (int c = 1; c < s; ++c) dd *= (double)a.n_ranks;
+                p /= dd;
             }
         }
         uint64_t d[W];
@@ -417,7 +562,7 @@ template <int W, typename T>
 __device__ __forceinline__ void items_body(uint32_t blk, uint32_t nblk, SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
                                                     const T *__restrict__ sK, uint64_t sstride, uint64_t ne,
                                                     const uint64_t *__restrict__ P, const uint32_t *__restrict__ guide,
-                                                    double n0, StepArgs a, Items<T> it, unsigned nb_fnc, uint64_t n_fnc,
+                                                    Ranks rk, double n0, StepArgs a, Items<T> it, unsigned nb_fnc, uint64_t n_fnc,
                                                     unsigned nb_items, RankTable rt, ItemPartials part, Scratch *sc)
 {
     if (blk >= nb_items) {  // trailing blocks: the rank table for the annihilation
@@ -432,7 +577,7 @@ __device__ __forceinline__ void items_body(uint32_t blk, uint32_t nblk, SysDev S
     } else {
         const unsigned b = blk - nb_fnc;
         ItemPartials ps{part.num + nb_fnc, part.att + nb_fnc, part.disc + nb_fnc, part.maxn + nb_fnc};
-        select_block<W, T>(b, S, skey, samp, sstride, ne, P, guide, n0, a, it, n_fnc, ps, sc);
+        select_block<W, T>(b, S, skey, samp, sstride, ne, P, guide, rk, n0, a, it, n_fnc, ps, sc);
     }
 }
 
@@ -446,6 +591,7 @@ struct ItemsArgs {
     uint64_t ne;
     const uint64_t *P;
     const uint32_t *guide;
+    Ranks rk;
     double n0;
     StepArgs a;
     Items<T> it;
@@ -462,7 +608,7 @@ __global__ void __launch_bounds__(kThreads) k_items(const ItemsArgs<W, T> *__res
 {
     uint32_t blk, nblk;
     const ItemsArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
-    items_body<W, T>(blk, nblk, A.S, A.skey, A.samp, A.sK, A.sstride, A.ne, A.P, A.guide, A.n0, A.a, A.it, A.nb_fnc, A.n_fnc, A.nb_items, A.rt, A.part, A.sc);
+    items_body<W, T>(blk, nblk, A.S, A.skey, A.samp, A.sK, A.sstride, A.ne, A.P, A.guide, A.rk, A.n0, A.a, A.it, A.nb_fnc, A.n_fnc, A.nb_items, A.rt, A.part, A.sc);
 }
 
 // ----------------------------------------------------------------- generation

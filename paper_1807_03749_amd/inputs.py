@@ -124,3 +124,41 @@ def state_amplitudes(levels, target: float, seed: int = PHILOX_SEED, decay: floa
     mag = np.maximum(mag, 1.0)
     sign = np.where(rng.random(len(levels)) < 0.5, -1.0, 1.0)
     return sign * mag
+
+
+def ueg_ccsd_determinants(n_electrons: int = 14, n2_max: int = 8) -> np.ndarray:
+    """The determinants of a closed-shell 3D UEG CCSD space as bitstrings [n][W]: the
+    reference and every double excitation with total momentum and S_z conserved (momentum
+    forbids singles).  Plane waves |n|^2 <= n2_max sorted by (|n|^2, n_x, n_y, n_z); spin
+    orbital p = 2 * wave + spin; the reference fills spin orbitals 0 .. N-1; spin orbital p is
+    bit p & 63 of word p >> 6.  For 14 electrons and n2_max = 8 (186 spin orbitals) these are
+    the 3813 excitors of the co-distribution study (Sec. III.A).  The set is an input of that
+    study, listed in key order."""
+    r = int(np.floor(np.sqrt(n2_max)))
+    waves = sorted((x * x + y * y + z * z, x, y, z) for x in range(-r, r + 1) for y in range(-r, r + 1)
+                   for z in range(-r, r + 1) if x * x + y * y + z * z <= n2_max)
+    k = np.array([w[1:] for w in waves], dtype=np.int64)
+    M = 2 * len(waves)
+    W = (M + 63) // 64
+    occ = list(range(n_electrons))
+    virt = list(range(n_electrons, M))
+    index = {(tuple(k[p >> 1]), p & 1): p for p in range(M)}
+    dets = [tuple(occ)]
+    for ai, i in enumerate(occ):
+        for j in occ[ai + 1:]:
+            ktot = k[i >> 1] + k[j >> 1]
+            stot = (i & 1) + (j & 1)
+            for a in virt:
+                sb = stot - (a & 1)
+                if sb not in (0, 1):
+                    continue
+                b = index.get((tuple(ktot - k[a >> 1]), sb))
+                if b is None or b <= a or b < n_electrons:
+                    continue
+                dets.append(tuple(sorted(set(occ) - {i, j} | {a, b})))
+    out = np.zeros((len(dets), W), np.uint64)
+    for n, d in enumerate(dets):
+        for p in d:
+            out[n, p >> 6] |= np.uint64(1 << (p & 63))
+    order = sorted(range(len(dets)), key=lambda x: tuple(int(w) for w in out[x][::-1]))
+    return out[order]

@@ -222,3 +222,21 @@ def test_ranked_step_matches_enumeration_at_one_placement(fnc):
     for d in dets:
         i = idx[d]
         assert abs(mean[i] - exact[d]) <= 5 * err[i] + 1e-12 * abs(exact[d]), (d, mean[i], exact[d], err[i])
+
+
+def test_ccsd_determinant_set_of_the_codistribution_study():
+    """The input set of the co-distribution study: 3813 distinct determinants for 14e/186so
+    (the count printed in Sec. III.A), all within CCSD and momentum-conserving (each double
+    couples to the reference)."""
+    rows = {(int(r[0]), int(r[1]), int(r[2])): int(r[3]) for r in
+            (ln.split() for ln in open(os.path.join(GOLDEN, "ueg_space_sizes.txt")) if ln.strip() and ln[0] != "#")}
+    dets = inputs.ueg_ccsd_determinants(14, 8)
+    assert len(dets) == rows[(14, 186, 2)] and len({tuple(d) for d in dets}) == len(dets)
+    S = ob.System.ueg(14, 8, 1.0)
+    assert S.W == dets.shape[1]
+    levels = [S.level(d) for d in dets]
+    assert levels.count(0) == 1 and set(levels) == {0, 2}
+    rng = np.random.default_rng(1)
+    for d in dets[rng.choice(len(dets), 40, replace=False)]:
+        if S.level(d) == 2:
+            assert S.hamiltonian(S.hf, d) != 0.0
