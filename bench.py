@@ -91,10 +91,13 @@ def calibrate_copy(gib: float = 1.0, reps: int = 5):
     print(json.dumps({"calibrate_copy_bytes": n * 4, "reps": reps}))
 
 
+VIRTUAL = dict(n_ranks=1, move_shift=5)  # virtual processors of every state (--n-ranks, --move-shift)
+
+
 def make_state(w: inputs.Workload, precision: str, init_pop: float):
     kw = dict(precision=precision, full_noncomposite=int(w.full_noncomposite),
               min_spawn_attempts=w.min_spawn_attempts, multispawn_threshold=w.multispawn_threshold,
-              noncomposite_threshold=w.noncomposite_threshold, init_pop=init_pop, seed=w.seed)
+              noncomposite_threshold=w.noncomposite_threshold, init_pop=init_pop, seed=w.seed, **VIRTUAL)
     if w.system == "ueg":
         return ccmc.State("ueg", w.n_electrons, w.truncation, n2_max=w.n2_max, rs=w.rs, **kw)
     h, B = inputs.molecule_like(n_spatial=w.n_spatial, n_electrons=w.n_electrons, n_chol=w.n_chol)
@@ -409,6 +412,9 @@ def main():
     ap.add_argument("--serve-budget", type=float, default=64e9, help="HBM budget of the server (bytes)")
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--serve-only", action="store_true", help="only the served stream")
+    ap.add_argument("--n-ranks", type=int, default=1,
+                    help="virtual processors of eq. ccmc_dist (selection restricted to one processor's excitors)")
+    ap.add_argument("--move-shift", type=int, default=5, help="nu_move of the virtual processors")
     args = ap.parse_args()
     global ROCTX
     ROCTX = _Roctx(args.roctx_region)
@@ -420,6 +426,7 @@ def main():
               f"(the multi-GPU design is described, not built)", file=sys.stderr)
         sys.exit(2)
     log = (lambda m: None) if args.quiet else (lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+    VIRTUAL.update(n_ranks=args.n_ranks, move_shift=args.move_shift)
     if args.serve_only:
         sv = serving_benchmark(args.serve_requests, args.serve_max_steps, args.serve_tol, args.serve_budget,
                                args.serve_slots, log)
@@ -454,7 +461,8 @@ def main():
                    "min_spawn_attempts": w.min_spawn_attempts, "excitors": main_leg["excitors"],
                    "n_total": main_leg["n_total"], "selections_per_step": main_leg["selections"] / args.steps,
                    "spawns_per_step": main_leg["spawns"] / args.steps,
-                   "records_per_step": prof.get("gather", {}).get("items", 0) / nb, "parallelism": "1 GPU"},
+                   "records_per_step": prof.get("gather", {}).get("items", 0) / nb, "parallelism": "1 GPU",
+                   **({"virtual_processors": args.n_ranks, "move_shift": args.move_shift} if args.n_ranks > 1 else {})},
         "roofline": roofline(main_leg["timed"], w),
         "annihilation_roofline": annihilation_roofline(prof),
         "kernels": {k: dict(avg_ms=p["ms"] / max(p["launches"], 1), launches=p["launches"],
