@@ -279,9 +279,11 @@ def precision_study(w: inputs.Workload, steps: int, equil: int, log):
             nsel = driver.selections(st["n_total"])
         num = np.empty(steps)
         den = np.empty(steps)
+        shifts = np.empty(steps)
         attempts = 0
         t0 = time.perf_counter()
         for i in range(steps):
+            shifts[i] = ctl.shift
             st = state.ccmc_step(w.tau, ctl.shift, nsel)
             ctl.update(st["n_total"])
             nsel = driver.selections(st["n_total"])
@@ -290,9 +292,12 @@ def precision_study(w: inputs.Workload, steps: int, equil: int, log):
             attempts += st["n_spawn_attempts"]
         el = time.perf_counter() - t0
         e, err, lv = driver.reblock_ratio(num, den)
+        # population-control check: E(K) reweighted over the last K steps
+        rw = driver.reweight(num, den, shifts, w.tau, memories=(0, 50, 200, 1000, 4000))
         res[prec] = dict(e_proj=e, error=err, block_level=lv, steps=steps, seconds=el,
                          attempts_per_s=attempts / el, ms_per_step=1e3 * el / steps, shift=ctl.shift,
-                         n_total=st["n_total"], excitors=st["n_excitors"])
+                         n_total=st["n_total"], excitors=st["n_excitors"],
+                         reweighted=[dict(memory=k, e_proj=x, error=y) for k, x, y in rw])
         log(f"precision {prec}: E_proj {e:.6f} +- {err:.6f} ({steps} steps, {1e3 * el / steps:.3f} ms/step)")
         state.close()
     a, b = res["fp64"], res["fp32"]

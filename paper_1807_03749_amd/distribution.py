@@ -94,7 +94,7 @@ def bias_study(configs, target: float = 2e5, equil: int = 4000, samples: int = 3
     """Run every configuration to `samples` recorded steps after growth and `equil` steps of
     shift control; returns one dict per configuration (energy, reblocked error, reference
     fraction, steps)."""
-    states, ctls, nsel, since, num, den, ref = [], [], [], [], [], [], []
+    states, ctls, nsel, since, num, den, ref, shf = [], [], [], [], [], [], [], []
     for i, c in enumerate(configs):
         st = ccmc.State("ueg", 14, 3, n2_max=4, rs=c["rs"], full_noncomposite=1, init_pop=target / 10.0,
                         seed=seed + 7919 * i, n_ranks=c["n_ranks"], move_shift=c["move_shift"], hash_seed=seed)
@@ -105,15 +105,17 @@ def bias_study(configs, target: float = 2e5, equil: int = 4000, samples: int = 3
         num.append([])
         den.append([])
         ref.append([])
+        shf.append([])
     n = len(configs)
     done = [False] * n
     t0 = time.perf_counter()
     it = 0
     while not all(done):
         active = [i for i in range(n) if not done[i]]
-        res = ccmc.ccmc_step_batch([states[i] for i in active], [configs[i]["tau"] for i in active],
-                                   [ctls[i].shift for i in active], [nsel[i] for i in active])
-        for i, r in zip(active, res):
+        used = [ctls[i].shift for i in active]
+        res = ccmc.ccmc_step_batch([states[i] for i in active], [configs[i]["tau"] for i in active], used,
+                                   [nsel[i] for i in active])
+        for i, r, s_used in zip(active, res, used):
             if isinstance(r, Exception):
                 raise r
             was = ctls[i].varying
@@ -124,6 +126,7 @@ def bias_study(configs, target: float = 2e5, equil: int = 4000, samples: int = 3
             if since[i] >= 0 and it - since[i] > equil:
                 num[i].append(r["eproj_num"])
                 den[i].append(r["eproj_den"])
+                shf[i].append(s_used)
                 ref[i].append(abs(r["n_ref"]) / r["n_total"])
                 done[i] = len(num[i]) >= samples
             elif since[i] < 0 and it >= grow_max:
@@ -135,8 +138,11 @@ def bias_study(configs, target: float = 2e5, equil: int = 4000, samples: int = 3
     out = []
     for i, c in enumerate(configs):
         e, err, lvl = driver.reblock_ratio(np.array(num[i]), np.array(den[i]))
+        rw = driver.reweight(np.array(num[i]), np.array(den[i]), np.array(shf[i]), c["tau"],
+                             memories=(0, 100, 1000, 5000))
         out.append(dict(c, energy=e, error=err, block_level=lvl, samples=len(num[i]),
-                        reference_fraction=float(np.mean(ref[i])), shift=ctls[i].shift))
+                        reference_fraction=float(np.mean(ref[i])), shift=ctls[i].shift,
+                        reweighted=[dict(memory=k, energy=x, error=y) for k, x, y in rw]))
         states[i].close()
     # each processor count against the one-processor run of the same r_s and time step
     for o in out:

@@ -88,6 +88,36 @@ def reblock_ratio(num: np.ndarray, den: np.ndarray):
     return float(e), float(math.sqrt(max(var, 0.0))), lv
 
 
+def reweight(num: np.ndarray, den: np.ndarray, shift: np.ndarray, tau: float, memories=(0, 10, 20, 50, 100, 200)):
+    """Population-control reweighting of the projected energy (the analysis the paper uses to
+    check its energies, after Umrigar, Nightingale & Runge 1993 and Vigor et al. 2015).
+
+    With the shift S(t) in force at step t, the population of step t was multiplied by
+    prod exp(delta_tau (S(t') - S_bar)) over the earlier steps relative to a run held at the
+    mean shift S_bar.  Undoing that over the last K steps gives the weights
+    W_t(K) = exp(-delta_tau sum_{j=1..K} (S(t-j) - S_bar)), and the estimate
+    E(K) = sum_t W_t num_t / sum_t W_t den_t over the steps t >= K of the series (reblocked as a
+    ratio).  K = 0 is the plain estimate; an E(K) flat in K within its error shows no
+    population-control bias.  Returns [(K, E, error)]."""
+    num = np.asarray(num, dtype=np.float64)
+    den = np.asarray(den, dtype=np.float64)
+    shift = np.asarray(shift, dtype=np.float64)
+    if not (len(num) == len(den) == len(shift)):
+        raise ValueError("num, den and shift must have one entry per step")
+    dev = shift - shift.mean()
+    c = np.concatenate([[0.0], np.cumsum(dev)])  # c[t] = sum of dev over steps < t
+    out = []
+    for K in memories:
+        if K >= len(num) - 16:
+            continue
+        t = np.arange(K, len(num))
+        logw = -tau * (c[t] - c[t - K])
+        w = np.exp(logw - logw.max())
+        e, err, _ = reblock_ratio(w * num[t], w * den[t])
+        out.append((int(K), e, err))
+    return out
+
+
 # -------------------------------------------------------------------------- run loop
 
 @dataclass
