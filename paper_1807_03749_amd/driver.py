@@ -73,19 +73,17 @@ def reblock_mean(x: np.ndarray):
 
 
 def reblock_ratio(num: np.ndarray, den: np.ndarray):
-    """Ratio of means E = <num>/<den> with its standard error from the blocked covariance of
-    (num, den) at the larger of the two optimal levels, by first-order propagation."""
+    """Ratio of means E = <num>/<den> with its standard error: the linearised series
+    x_t = num_t - E den_t is blocked and the error of its mean, divided by <den>, is the error
+    of E (first-order propagation; blocking x rather than num and den separately picks the
+    block length from the ratio's own correlation time, not from the slower fluctuations of
+    the population that num and den share).  Returns (E, error, optimal level)."""
     num = np.asarray(num, dtype=np.float64)
     den = np.asarray(den, dtype=np.float64)
-    _, _, on, _ = reblock_mean(num)
-    _, _, od, _ = reblock_mean(den)
-    lv = max(on, od)
-    xy = _blocks(np.stack([num, den], axis=1))[min(lv, len(_blocks(num)) - 1)]
     mn, md = num.mean(), den.mean()
-    c = np.cov(xy.T, ddof=1) / len(xy)
     e = mn / md
-    var = e * e * (c[0, 0] / mn ** 2 + c[1, 1] / md ** 2 - 2 * c[0, 1] / (mn * md))
-    return float(e), float(math.sqrt(max(var, 0.0))), lv
+    _, se, lv, _ = reblock_mean(num - e * den)
+    return float(e), float(abs(se / md)), lv
 
 
 def reweight(num: np.ndarray, den: np.ndarray, shift: np.ndarray, tau: float, memories=(0, 10, 20, 50, 100, 200)):

@@ -58,3 +58,15 @@ def test_reweighting_constant_shift_is_plain_ratio():
     num = -0.25 * den + rng.normal(0.0, 1.0, n)
     for k, e, _ in driver.reweight(num, den, np.full(n, -0.1), 0.005, memories=(0, 7, 100)):
         assert abs(e - num[k:].sum() / den[k:].sum()) <= 1e-12
+
+
+def test_ratio_error_independent_samples():
+    """Independent samples: the error of <num>/<den> is sigma / (sqrt(n) <den>) when
+    num = E den + noise of deviation sigma."""
+    rng = np.random.default_rng(4)
+    n, sigma = 1 << 16, 3.0
+    den = 200.0 + rng.normal(0.0, 4.0, n)
+    num = -0.4 * den + rng.normal(0.0, sigma, n)
+    e, err, _ = driver.reblock_ratio(num, den)
+    assert abs(err / (sigma / math.sqrt(n) / 200.0) - 1.0) < 0.15
+    assert abs(e + 0.4) < 5 * err
