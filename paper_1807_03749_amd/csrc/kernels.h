@@ -270,25 +270,31 @@ __global__ void __launch_bounds__(kThreads) k_codist_place(const uint64_t *__res
 
 // Pair counts c_ij = #{t < T_c : pl[t][i] = pl[t][j]} for i < j, summed (c and c^2) at each
 // checkpoint T_c.  A block holds kCoRows excitors i against 256 excitors j, one j per thread
-// with a counter per i; blocks entirely on or below the diagonal exit.  Integer sums, so the
-// result does not depend on the order of the atomic additions.
-constexpr int kCoRows = 16;
+// with a counter per i; blocks entirely on or below the diagonal exit.  Iterations run in
+// chunks of up to kCoChunk that end at checkpoints: the chunk's i rows are staged in LDS
+// (every thread reads the same word: a broadcast) and each thread loads its j's placements
+// for the chunk before comparing.  Absent excitors carry values no placement takes.  Integer
+// sums, so the result does not depend on the order of the atomic additions.
+constexpr int kCoRows = 32, kCoChunk = 32;
 
 __global__ void __launch_bounds__(kThreads) k_codist_pairs(const uint16_t *__restrict__ pl, uint64_t n,
                                                            const uint64_t *__restrict__ cps, int ncp,
                                                            unsigned long long *__restrict__ sums)
 {
+    __shared__ uint4 s_i[kCoChunk][kCoRows / 4];
     const uint64_t i0 = (uint64_t)blockIdx.y * kCoRows;
     const uint64_t jb = (uint64_t)blockIdx.x * kThreads;
     if (jb + kThreads <= i0 + 1) return;  // every j of the block is <= every i
     const uint64_t j = jb + threadIdx.x;
     const bool jv = j < n;
+    const uint64_t jc = jv ? j : n - 1;
     uint32_t c[kCoRows];
 #pragma unroll
     for (int r = 0; r < kCoRows; ++r) c[r] = 0;
     const uint64_t T = cps[ncp - 1];
     int next = 0;
-    for (uint64_t t = 0;; ++t) {
+    uint64_t t = 0;
+    for (;;) {
         while (next < ncp && cps[next] == t) {
             uint64_t s1 = 0, s2 = 0;
 #pragma unroll
@@ -308,14 +314,39 @@ __global__ void __launch_bounds__(kThreads) k_codist_pairs(const uint16_t *__res
             ++next;
         }
         if (t >= T) break;
-        const uint16_t *row = pl + t * n;
-        const uint32_t rj = jv ? row[j] : 0x10000u;
-#pragma unroll
-        for (int r = 0; r < kCoRows; ++r) {
+        const uint64_t end = cps[next] - t < (uint64_t)kCoChunk ? cps[next] : t + kCoChunk;  // next <= ncp - 1 here
+        const int len = (int)(end - t);
+        // stage rows i0 .. i0 + kCoRows of iterations t .. end - 1
+        uint32_t *si = reinterpret_cast<uint32_t *>(&s_i[0][0]);
+        for (int x = threadIdx.x; x < kCoChunk * kCoRows; x += kThreads) {
+            const int tc = x / kCoRows, r = x - tc * kCoRows;
             const uint64_t i = i0 + r;
-            const uint32_t ri = row[i < n ? i : n - 1];
-            c[r] += (i < n && ri == rj) ? 1u : 0u;
+            const uint64_t ic = i < n ? i : n - 1;
+            const uint32_t v = pl[(t + (tc < len ? tc : 0)) * n + ic];
+            si[x] = (i < n && tc < len) ? v : 0xFFFFFFFFu;
         }
+        uint32_t rj[kCoChunk];
+#pragma unroll
+        for (int tc = 0; tc < kCoChunk; ++tc) {
+            const uint32_t v = pl[(t + (tc < len ? tc : 0)) * n + jc];
+            rj[tc] = jv ? v : 0xFFFFFFFEu;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tc = 0; tc < kCoChunk; ++tc) {
+            if (tc < len) {
+#pragma unroll
+                for (int q = 0; q < kCoRows / 4; ++q) {
+                    const uint4 v = s_i[tc][q];
+                    c[4 * q + 0] += v.x == rj[tc];
+                    c[4 * q + 1] += v.y == rj[tc];
+                    c[4 * q + 2] += v.z == rj[tc];
+                    c[4 * q + 3] += v.w == rj[tc];
+                }
+            }
+        }
+        __syncthreads();
+        t = end;
     }
 }
 

@@ -28,8 +28,13 @@ SOLVES = [
     dict(system="ueg", n_electrons=14, truncation=2, n2_max=2, rs=5.0, init_pop=200.0, seed=14, precision="fp32"),
     dict(system="ueg", n_electrons=14, truncation=2, n2_max=4, rs=1.0, init_pop=400.0, seed=15, precision="fp32",
          full_noncomposite=1),
+    # virtual processors (Sec. III.A) in the same batch
+    dict(system="ueg", n_electrons=14, truncation=3, n2_max=4, rs=0.5, init_pop=500.0, seed=16, full_noncomposite=1,
+         n_ranks=24, move_shift=2),
+    dict(system="ueg", n_electrons=14, truncation=2, n2_max=2, rs=1.0, init_pop=300.0, seed=17, n_ranks=240,
+         move_shift=0),
 ]
-TAU = [0.005, 0.002, 0.002, 0.005, 0.005]
+TAU = [0.005, 0.002, 0.002, 0.005, 0.005, 0.002, 0.005]
 
 
 def _make(cfg):
@@ -57,7 +62,7 @@ def _drive(states, starts, steps, batched):
 
 
 def test_batch_equals_alone():
-    starts = [0, 3, 5, 1, 8]
+    starts = [0, 3, 5, 1, 8, 2, 6]
     alone = _drive([_make(c) for c in SOLVES], starts, 25, batched=False)
     mixed = _drive([_make(c) for c in SOLVES], starts, 25, batched=True)
     for i, (a, b) in enumerate(zip(alone, mixed)):

@@ -39,6 +39,12 @@ CASES = [
     ("ueg54_246_ccsd_fnc_ms8", dict(system="ueg", n_el=54, n2_max=9), 2,
      dict(full_noncomposite=True, min_spawn_attempts=8, multispawn_threshold=1.0, init_pop=300.0, seed=11),
      0.001, 12, 300),
+    ("ueg14_186_ccsd_fnc_w3", dict(system="ueg", n_el=14, n2_max=8), 2,
+     dict(full_noncomposite=True, min_spawn_attempts=2, multispawn_threshold=1.0, init_pop=300.0, seed=31), 0.002,
+     15, 300),
+    ("ueg14_358_ccsdtq_fnc_w6", dict(system="ueg", n_el=14, n2_max=12), 4,
+     dict(full_noncomposite=True, min_spawn_attempts=1, multispawn_threshold=1.0, init_pop=300.0, seed=358), 0.003,
+     12, 300),
     ("mol4_12_ccsd_original", dict(system="mol", n_el=4, n_spatial=6, n_chol=8, mol_seed=4), 2,
      dict(init_pop=300.0, p_single=0.3, seed=5), 0.01, 40, 300),
     ("mol16_92_ccsdtq_fnc_ms8", dict(system="mol", n_el=16, n_spatial=46, n_chol=138), 4,
