@@ -455,6 +455,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": 1e3 * main_leg["seconds"] / args.steps,
+        "selections_per_s": main_leg["selections"] / main_leg["seconds"],
+        "spawns_per_s": main_leg["spawns"] / main_leg["seconds"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

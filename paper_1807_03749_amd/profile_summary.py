@@ -10,6 +10,15 @@
       averaged over its dispatches), each scaled by expected / measured of the same counter
       on device copies of N bytes (a read of N and a write of N bytes per copy).
 
+  python -m paper_1807_03749_amd.profile_summary valu --pmc P.csv --kernels k_items,k_generate
+      --simds 1024 --xcds 8 --workload W --command "..." --out FILE
+      vector-ALU use per kernel from one counter pass (SQ_WAVES, SQ_INSTS_VALU,
+      SQ_ACTIVE_INST_VALU, SQ_WAVE_CYCLES, SQ_WAIT_INST_ANY, GRBM_GUI_ACTIVE): VALU instructions
+      per wave, VALU busy = 4 SQ_ACTIVE_INST_VALU / (SIMDs x GRBM_GUI_ACTIVE / XCDs) (the
+      active-instruction counter counts in units of four cycles, the wave64 issue time on a
+      16-lane SIMD; GRBM_GUI_ACTIVE arrives summed over the XCDs), and the fraction of wave
+      time spent waiting.
+
 The summaries record the hash of the HIP sources they were taken on; bench.py uses a
 traffic figure only while that hash still matches.
 """
@@ -98,6 +107,27 @@ def traffic(args):
     _write(args.out, lines)
 
 
+def valu(args):
+    names = [k for k in args.kernels.split(",") if k]
+    counters = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES", "SQ_WAIT_INST_ANY",
+                "GRBM_GUI_ACTIVE")
+    lines = [f"# vector-ALU use on {args.workload}  ({datetime.date.today().isoformat()})",
+             f"# command: {args.command}",
+             f"source_hash = {_source_hash()}",
+             f"simds = {args.simds}, xcds = {args.xcds} (GRBM_GUI_ACTIVE is divided by the XCDs)",
+             f"# {'kernel':12s} {'dispatches':>10s} {'waves':>9s} {'valu_insts/wave':>16s} {'valu_busy':>10s} {'wait/wave_cycles':>17s}"]
+    for k in names:
+        per = {c: _per_dispatch(args.pmc, c, lambda n, k=k: k in n) for c in counters}
+        if not per["SQ_WAVES"]:
+            raise SystemExit(f"valu: no dispatch of {k}")
+        av = {c: sum(v) / len(v) for c, v in per.items() if v}
+        busy = 4.0 * av["SQ_ACTIVE_INST_VALU"] / (args.simds * av["GRBM_GUI_ACTIVE"] / args.xcds)
+        lines.append(f"  {k:12s} {len(per['SQ_WAVES']):10d} {av['SQ_WAVES']:9.0f} "
+                     f"{av['SQ_INSTS_VALU'] / av['SQ_WAVES']:16.1f} {100 * busy:9.1f}% "
+                     f"{100 * av['SQ_WAIT_INST_ANY'] / av['SQ_WAVE_CYCLES']:16.1f}%")
+    _write(args.out, lines)
+
+
 def _write(out, lines):
     text = "\n".join(lines) + "\n"
     if out:
@@ -119,8 +149,14 @@ def main():
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--copy-reps", type=int, default=5)
     t.add_argument("--out")
+    v = sub.add_parser("valu")
+    for a in ("--pmc", "--kernels", "--workload", "--command"):
+        v.add_argument(a, required=True)
+    v.add_argument("--simds", type=int, default=1024)
+    v.add_argument("--xcds", type=int, default=8)
+    v.add_argument("--out")
     args = ap.parse_args()
-    (stats if args.cmd == "stats" else traffic)(args)
+    {"stats": stats, "traffic": traffic, "valu": valu}[args.cmd](args)
 
 
 if __name__ == "__main__":
