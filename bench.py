@@ -418,7 +418,7 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--serve-only", action="store_true", help="only the served stream")
     ap.add_argument("--n-ranks", type=int, default=1,
-                    help="virtual processors of eq. ccmc_dist (selection restricted to one processor's excitors)")
+                    help="virtual processors of eq. 9 (selection restricted to one processor's excitors)")
     ap.add_argument("--move-shift", type=int, default=5, help="nu_move of the virtual processors")
     args = ap.parse_args()
     global ROCTX

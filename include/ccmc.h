@@ -94,14 +94,14 @@ typedef struct {
     uint64_t hbm_budget_bytes;     /* 0: no limit; else device memory the state may hold */
     void *hip_stream;              /* hipStream_t to run on; NULL: the library's own stream */
     int keep_spawn_ids;            /* 1: keep the last step's spawn list for ccmc_export_spawns */
-    /* Virtual processors (Sec. III.A, eq. ccmc_dist), emulated on the one GPU.  With
+    /* Virtual processors (Sec. III, eq. 9), emulated on the one GPU.  With
      * n_ranks = N_p > 1 excitor D sits on processor p(D, i_tau) = hash(D xor o) mod N_p with
      * o = (hash(D) + i_tau) >> move_shift (hash: MurmurHash2 with hash_seed over the W words of
      * D as 8W little-endian bytes, o xored into word 0; i_tau the step index), and selection k
      * of a step is made by processor k mod N_p from its own excitors, with its selection
      * probability scaled by N_p^(1-s).  Non-composite items (full non-composite sampling),
      * spawning and annihilation are unchanged.  n_ranks 0 or 1: one processor; at most 512.
-     * move_shift >= 64: excitors never move (eq. fciqmc_dist). */
+     * move_shift >= 64: excitors never move (eq. 8). */
     uint32_t n_ranks;
     uint32_t move_shift;
     uint32_t hash_seed;
@@ -181,7 +181,7 @@ void ccmc_free(ccmc_state *st);
  * thread. */
 const char *ccmc_last_error(const ccmc_state *st);
 
-/* Co-location statistics of the placement eq. ccmc_dist (Sec. III.A; the analysis of the
+/* Co-location statistics of the placement eq. 9 (Sec. III; the analysis of the
  * co-distribution figure).  keys: host array [n][n_words] of distinct determinants (word 0
  * least significant).  For iterations i_tau = 0 .. T-1 (T = the last checkpoint) every
  * excitor is placed on one of n_ranks processors (move_shift, hash_seed as in

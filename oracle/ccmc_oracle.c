@@ -522,7 +522,7 @@ static uint32_t hash_det(int W, const uint64_t *d, uint32_t seed)
     return orc_murmur2(buf, 8 * W, seed);
 }
 
-/* eq. ccmc_dist (Sec. III.A). */
+/* eq. 9 (Sec. III). */
 uint32_t orc_placement(int W, const uint64_t *det, uint64_t i_tau, uint32_t n_ranks, uint32_t move_shift,
                        uint32_t seed)
 {
@@ -772,7 +772,7 @@ int orc_cluster_ranked(const orc_run *R, int s, const uint64_t *idx, uint64_t co
     for (int a = 2; a <= s; ++a) fact *= (double)a;
     double p = (double)count * size_prob(s, lo, hi) * fact;
     for (int a = 0; a < s; ++a) p *= (double)R->q[idx[a]] / (double)qnorm;
-    /* N_p processors (Sec. III.A): times N_p^(1-s) */
+    /* N_p processors (Sec. III): times N_p^(1-s) */
     if (n_ranks > 1) {
         if (s == 0) {
             p *= (double)n_ranks;
@@ -1023,7 +1023,7 @@ int orc_step(orc_run *R, double tau, double shift, uint64_t n_sel, orc_stats *st
                 return rc;
         }
     }
-    /* virtual processors (Sec. III.A): where each excitor sits this step, and the total
+    /* virtual processors (Sec. III): where each excitor sits this step, and the total
      * weight of each processor's excitors */
     const uint32_t np = R->opt.n_ranks > 1 ? R->opt.n_ranks : 1;
     uint32_t *where = NULL;

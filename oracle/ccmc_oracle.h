@@ -58,12 +58,12 @@ typedef struct {
     double init_pop;                /* initial reference amplitude N_0 */
     double p_single;                /* molecular generator: probability of a single */
     uint64_t seed;                  /* Philox key */
-    /* Virtual processors (Sec. III.A, eq. ccmc_dist): 0 or 1 = one processor.  With
+    /* Virtual processors (Sec. III, eq. 9): 0 or 1 = one processor.  With
      * n_ranks = N_p > 1 every excitor sits on processor p(D, i_tau) and each selection
      * builds its cluster from the excitors of one processor only. */
     uint32_t n_ranks;
     uint32_t move_shift;            /* nu_move: an excitor may move every 2^nu_move steps;
-                                       >= 64 never (the static eq. fciqmc_dist) */
+                                       >= 64 never (the static eq. 8) */
     uint32_t hash_seed;             /* MurmurHash2 seed of the placement */
 } orc_options;
 
@@ -118,10 +118,10 @@ int orc_step(orc_run *, double tau, double shift, uint64_t n_sel, orc_stats *st)
 int orc_records_size(const orc_run *, uint64_t *n);
 int orc_records(const orc_run *, uint64_t *keys, double *amps, uint64_t *ids);
 
-/* ---- placement of excitors on virtual processors (Sec. III.A) ---- */
+/* ---- placement of excitors on virtual processors (Sec. III) ---- */
 /* MurmurHash2 (Austin Appleby, 32-bit, public domain) of len bytes. */
 uint32_t orc_murmur2(const void *key, int len, uint32_t seed);
-/* eq. ccmc_dist: o = (hash(D) + i_tau) >> nu_move; p = hash(D xor o) mod N_p, hashing the
+/* eq. 9: o = (hash(D) + i_tau) >> nu_move; p = hash(D xor o) mod N_p, hashing the
  * W words of D as 8W little-endian bytes (word 0 first) and xoring o into word 0. */
 uint32_t orc_placement(int W, const uint64_t *det, uint64_t i_tau, uint32_t n_ranks, uint32_t move_shift,
                        uint32_t seed);

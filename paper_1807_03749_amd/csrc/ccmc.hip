@@ -797,7 +797,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         stage(ar, recs, "clear", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.lb_words + p.ne}; }),
               [s](const ClearArgs *a, BatchMap bm, unsigned g) { k_clear<<<g, kThreads, 0, s>>>(a, bm); });
     }
-    // ---- virtual processors (Sec. III.A): place every excitor, then partition the store by
+    // ---- virtual processors (Sec. III): place every excitor, then partition the store by
     // processor with one stable radix pass (store order within each processor)
     {
         std::vector<PlaceArgs<W>> args;

@@ -285,7 +285,7 @@ __device__ __forceinline__ T reference_element(const SysDev &S, const uint64_t *
     return double_element<W, T>(S, d, parts[0], parts[1], holes[0], holes[1]);
 }
 
-// ------------------------------------------------ virtual processors (Sec. III.A)
+// ------------------------------------------------ virtual processors (Sec. III)
 // MurmurHash2 (A. Appleby, 32-bit) of the W words of d read as 8W little-endian bytes: two
 // 4-byte blocks per word, low half first.  8W is a multiple of 4, so there is no tail.
 template <int W>
@@ -312,7 +312,7 @@ __device__ __forceinline__ uint32_t murmur2_det(const uint64_t *d, uint32_t seed
 
 constexpr uint32_t kMaxRanks = 512;  // one radix pass partitions the store by processor
 
-// eq. ccmc_dist: o = (hash(D) + i_tau) >> nu_move, p = hash(D xor o) mod N_p, with o xored
+// eq. 9: o = (hash(D) + i_tau) >> nu_move, p = hash(D xor o) mod N_p, with o xored
 // into word 0; nu_move >= 64 leaves o = 0 (the static placement hash(D) mod N_p).
 template <int W>
 __device__ __forceinline__ uint32_t placement(const uint64_t *d, uint64_t i_tau, uint32_t n_ranks,

@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(kThreads) k_guide(const GuideArgs *__restrict_
     }
 }
 
-// Processor of every store entry this step (eq. ccmc_dist), as the key of the one-pass radix
+// Processor of every store entry this step (eq. 9), as the key of the one-pass radix
 // partition; also the partition's length for the radix kernels.
 template <int W>
 struct PlaceArgs {
@@ -252,7 +252,7 @@ __device__ __forceinline__ void rank_table_block(unsigned blk, const RankTable &
     rt.rtab[c] = (uint32_t)l0;
 }
 
-// ------------------------------------- co-location of excitors over iterations (Sec. III.A)
+// ------------------------------------- co-location of excitors over iterations (Sec. III.B)
 // pl[t * n + i] = processor of excitor i at iteration t, for t < T.
 template <int W>
 __global__ void __launch_bounds__(kThreads) k_codist_place(const uint64_t *__restrict__ keys, uint64_t n, uint64_t T,
@@ -421,7 +421,7 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
     if (k < a.n_sel) {
         // With N_p virtual processors selection k is made by processor k mod N_p, whose
         // excitors hold the prefix range [base, base + Q) of the partition's weights and
-        // which makes `count` of the step's selections (Sec. III.A).
+        // which makes `count` of the step's selections (Sec. III).
         uint64_t Q = sc->qtot, base = 0, count = a.n_sel;
         if (a.n_ranks > 1) {
             const uint32_t rank = (uint32_t)(k % a.n_ranks);
@@ -499,7 +499,7 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
                     prod *= ni / (T)n0;
             }
         }
-        // the s excitors share one of N_p processors: times N_p^(1-s) (Sec. III.A)
+        // the s excitors share one of N_p processors: times N_p^(1-s) (Sec. III)
         if (a.n_ranks > 1) {
             if (s == 0) {
                 p *= (double)a.n_ranks;

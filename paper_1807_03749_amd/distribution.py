@@ -1,9 +1,9 @@
 """The distributed algorithm's placement of excitors, and its bias, studied on one GPU
-(Sec. III.A).
+(Sec. III: the placement of eq. 9; Sec. III.B: its co-distribution figure and bias study).
 
 Two studies, both run through the C ABI:
 
-* co-location: the 3813 excitors of the 14e/186so UEG CCSD space are placed by eq. ccmc_dist
+* co-location: the 3813 excitors of the 14e/186so UEG CCSD space are placed by eq. 9
   for iterations 0 .. T-1; for each N_p and nu_move the mean and the standard deviation over
   all pairs of p_ij(T), the fraction of those iterations in which excitors i and j shared a
   processor, rescaled as in the co-distribution figure: mean * N_p (1 is exact), standard

@@ -132,7 +132,7 @@ def ueg_ccsd_determinants(n_electrons: int = 14, n2_max: int = 8) -> np.ndarray:
     forbids singles).  Plane waves |n|^2 <= n2_max sorted by (|n|^2, n_x, n_y, n_z); spin
     orbital p = 2 * wave + spin; the reference fills spin orbitals 0 .. N-1; spin orbital p is
     bit p & 63 of word p >> 6.  For 14 electrons and n2_max = 8 (186 spin orbitals) these are
-    the 3813 excitors of the co-distribution study (Sec. III.A).  The set is an input of that
+    the 3813 excitors of the co-distribution study (Sec. III.B).  The set is an input of that
     study, listed in key order."""
     r = int(np.floor(np.sqrt(n2_max)))
     waves = sorted((x * x + y * y + z * z, x, y, z) for x in range(-r, r + 1) for y in range(-r, r + 1)

@@ -28,7 +28,7 @@ SOLVES = [
     dict(system="ueg", n_electrons=14, truncation=2, n2_max=2, rs=5.0, init_pop=200.0, seed=14, precision="fp32"),
     dict(system="ueg", n_electrons=14, truncation=2, n2_max=4, rs=1.0, init_pop=400.0, seed=15, precision="fp32",
          full_noncomposite=1),
-    # virtual processors (Sec. III.A) in the same batch
+    # virtual processors (Sec. III) in the same batch
     dict(system="ueg", n_electrons=14, truncation=3, n2_max=4, rs=0.5, init_pop=500.0, seed=16, full_noncomposite=1,
          n_ranks=24, move_shift=2),
     dict(system="ueg", n_electrons=14, truncation=2, n2_max=2, rs=1.0, init_pop=300.0, seed=17, n_ranks=240,

@@ -1,4 +1,4 @@
-"""Virtual processors on the GPU (Sec. III.A, eq. ccmc_dist) against the CPU oracle.
+"""Virtual processors on the GPU (Sec. III, eq. 9) against the CPU oracle.
 
 Ranked steps compare exactly like the one-processor parity cases (records, ids and keys
 bit-exact, amplitudes to 1e-12; see parity_util), at step indices where excitors move.  The

@@ -34,7 +34,7 @@ MUTATIONS = [
      "x = copysign(0.5 * R->opt.spawn_cutoff, x);", "full_step_mean"),
     ("excitor draws cover half the weight", "uint64_t r = below(draw(R, PURPOSE_SELECT, k, 0, 1 + a), qnorm);",
      "uint64_t r = below(draw(R, PURPOSE_SELECT, k, 0, 1 + a), qnorm / 2);", "full_step_mean"),
-    # virtual processors (Sec. III.A)
+    # virtual processors (Sec. III)
     ("MurmurHash2 tail byte shifted", "if (len == 3) h ^= (uint32_t)b[2] << 16;",
      "if (len == 3) h ^= (uint32_t)b[2] << 8;", "murmur2", PLACE),
     ("offset never applied", "    d[0] ^= o;\n", "    d[0] ^= 0;\n", "moves_only", PLACE),

@@ -1,8 +1,8 @@
-"""Pins of the oracle's virtual processors (Sec. III.A, eq. ccmc_dist) against things other
+"""Pins of the oracle's virtual processors (Sec. III, eq. 9) against things other
 than itself (no GPU).
 
 * MurmurHash2: SMHasher's published verification value (tests/golden/murmur2_verification.txt).
-* Placement: nu_move >= 64 is the static eq. fciqmc_dist, hash(D) mod N_p; with nu_move the
+* Placement: nu_move >= 64 is the static eq. 8, hash(D) mod N_p; with nu_move the
   processor can change only where (hash(D) + i_tau) crosses a multiple of 2^nu_move; the
   processors are evenly used.
 * Co-location sums: brute force over pairs and iterations.
@@ -113,7 +113,7 @@ def test_codistribution_sums_brute_force():
 
 
 def test_codistribution_mean_is_one_over_np():
-    """The long-time co-location frequency of two excitors is 1/N_p (Sec. III.A)."""
+    """The long-time co-location frequency of two excitors is 1/N_p (Sec. III.B)."""
     rng = np.random.default_rng(7)
     dets = _random_dets(rng, 120, 2, 114)
     npairs = len(dets) * (len(dets) - 1) // 2
@@ -226,7 +226,7 @@ def test_ranked_step_matches_enumeration_at_one_placement(fnc):
 
 def test_ccsd_determinant_set_of_the_codistribution_study():
     """The input set of the co-distribution study: 3813 distinct determinants for 14e/186so
-    (the count printed in Sec. III.A), all within CCSD and momentum-conserving (each double
+    (the count printed in Sec. III.B), all within CCSD and momentum-conserving (each double
     couples to the reference)."""
     rows = {(int(r[0]), int(r[1]), int(r[2])): int(r[3]) for r in
             (ln.split() for ln in open(os.path.join(GOLDEN, "ueg_space_sizes.txt")) if ln.strip() and ln[0] != "#")}
