@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -110,11 +111,13 @@ struct ccmc_state {
     uint64_t cnt_slots = 0, cnt_rec = 0, cnt_merged = 0, cnt_new = 0, cnt_att = 0, cnt_live_items = 0;  // live counts of the last step
     DevBuf lb;  // step scalars, tickets, radix histograms and look-back status words
     // batched steps led by this state: argument tables and the batch's step scalars
-    DevBuf arg_dev, batch_scr;
+    DevBuf arg_dev;
     uint8_t *arg_host = nullptr;  // pinned
     size_t arg_hcap = 0;
-    Scratch *batch_hscr = nullptr;  // pinned
+    Scratch *batch_hscr = nullptr;  // pinned, coherent: written by k_final
+    Scratch *batch_hdev = nullptr;  // its device address
     size_t batch_hcap = 0;
+    uint64_t batch_seq = 0;         // sequence number of the last batch this state led
     // last step's spawn list (keep_spawn_ids)
     uint64_t last_nrec = 0;
     int last_rec_buf = -1;
@@ -764,18 +767,21 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             return CCMC_OK;
         }
     }
-    TRY(ensure(lead, lead->batch_scr, n * sizeof(Scratch)));
     if (lead->batch_hcap < n) {
         if (lead->batch_hscr) (void)hipHostFree(lead->batch_hscr);
-        lead->batch_hscr = nullptr;
-        if (hipHostMalloc((void **)&lead->batch_hscr, n * sizeof(Scratch)) != hipSuccess) {
-            lead->batch_hcap = 0;
+        lead->batch_hscr = lead->batch_hdev = nullptr;
+        lead->batch_hcap = 0;
+        if (hipHostMalloc((void **)&lead->batch_hscr, n * sizeof(Scratch), hipHostMallocMapped | hipHostMallocCoherent) !=
+                hipSuccess ||
+            hipHostGetDevicePointer((void **)&lead->batch_hdev, lead->batch_hscr, 0) != hipSuccess) {
             lead->err = "hipHostMalloc failed";
             return CCMC_EDEVICE;
         }
+        std::memset(lead->batch_hscr, 0, n * sizeof(Scratch));
         lead->batch_hcap = n;
     }
-    Scratch *scr_copy = ptr<Scratch>(lead->batch_scr);
+    Scratch *scr_copy = lead->batch_hdev;
+    const uint64_t seq = ++lead->batch_seq;
     const double kb = (double)(W * 8);  // bytes of one bitstring
     const double tb = (double)sizeof(T);
     ArgArena ar;
@@ -1084,7 +1090,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         std::vector<FinalArgs> args;
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
-            args.push_back(FinalArgs{reinterpret_cast<const FinalPart *>(p.lb + p.o_fin), p.fin_blocks, p.sc, scr_copy + i});
+            args.push_back(FinalArgs{reinterpret_cast<const FinalPart *>(p.lb + p.o_fin), p.fin_blocks, p.sc, scr_copy + i, seq});
             blk[i] = 1;
         }
         stage(ar, recs, "final", args, blk, works([&](auto &) { return Work{0.0, nullptr, 0}; }),
@@ -1112,9 +1118,24 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         launch(lead, r.name, r.works, [&] { r.go(dev + r.off_args, bm, r.blocks); });
     }
 
-    // ---- (a14) the one synchronisation of the step
-    HIP_TRY(hipMemcpyAsync(lead->batch_hscr, scr_copy, n * sizeof(Scratch), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    // ---- (a14) the one synchronisation of the step: k_final writes each state's scalars into
+    // pinned host memory and then the batch's sequence number; the host polls for it (and,
+    // every few thousand polls, asks whether the stream has ended without writing it)
+    for (size_t i = 0; i < n; ++i) {
+        const volatile uint64_t *flag = &lead->batch_hscr[i].seq;
+        for (uint32_t polls = 1; *flag != seq; ++polls) {
+            if ((polls & 4095) == 0) {
+                const hipError_t q = hipStreamQuery(s);
+                if (q == hipErrorNotReady) continue;
+                HIP_TRY(q);
+                if (*flag != seq) {
+                    lead->err = "the step's scalars did not reach the host";
+                    return CCMC_EDEVICE;
+                }
+            }
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
     for (size_t i = 0; i < n; ++i) {
         auto &p = ps[i];
         ccmc_state *st = p.st;
@@ -1386,7 +1407,7 @@ void destroy(ccmc_state *st)
                       &st->iA, &st->ideath, &st->in, &st->ilevel, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,
                       &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->boff, &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
                       &st->sidx[0], &st->sidx[1], &st->tile_region,
-                      &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->lb, &st->arg_dev, &st->batch_scr,
+                      &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->lb, &st->arg_dev,
                       &st->vkey[0], &st->vkey[1], &st->perm, &st->seg};
     for (DevBuf *b : bufs) release(st, *b);
     for (auto &p : st->pending) {

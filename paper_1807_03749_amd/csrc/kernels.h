@@ -40,7 +40,7 @@ struct Scratch {
     uint64_t n_rec;           // records emitted by the step
     uint64_t n_live;          // records the annihilation works on (0 after an overflow)
     uint64_t n_place;         // excitors partitioned by virtual processor (the store size)
-    uint64_t spare1;
+    uint64_t seq;             // host copy only: the batch's sequence number, written last
     uint64_t n_new;           // new determinants
     uint64_t hf_hit;
     uint64_t n_out;           // excitors after the step
@@ -1738,7 +1738,7 @@ __global__ void __launch_bounds__(kThreads) k_final_part(const FinalPartArgs *__
 }
 
 __device__ __forceinline__ void final_body(uint32_t blk, uint32_t nblk, const FinalPart *__restrict__ in, uint64_t n, Scratch *sc,
-                                           Scratch *copy)
+                                           Scratch *copy, uint64_t seq)
 {
     if (threadIdx.x != 0) return;
     FinalPart a{};
@@ -1759,21 +1759,27 @@ __device__ __forceinline__ void final_body(uint32_t blk, uint32_t nblk, const Fi
     sc->max_n = a.mx;
     sc->n_spawns = a.sp;
     sc->n_deaths = a.de;
-    *copy = *sc;  // the batch's scalars side by side, for one copy to the host
+    // The step's scalars go straight to the host's pinned copy; the batch's sequence number is
+    // stored last, behind a system-scope release, so the host that sees it sees the rest.
+    Scratch c = *sc;
+    c.seq = 0;  // no batch has number 0: the host waits for the release below
+    *copy = c;
+    __hip_atomic_store(&copy->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 struct FinalArgs {
     const FinalPart *in;
     uint64_t n;
     Scratch *sc;
-    Scratch *copy;
+    Scratch *copy;  // device address of the host's pinned copy
+    uint64_t seq;
 };
 
 __global__ void __launch_bounds__(kThreads) k_final(const FinalArgs *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
     const FinalArgs &A = args[batch_state(bm, blk, nblk)];
-    final_body(blk, nblk, A.in, A.n, A.sc, A.copy);
+    final_body(blk, nblk, A.in, A.n, A.sc, A.copy, A.seq);
 }
 
 // Clear each state's step area and the per-entry sums of its store.
