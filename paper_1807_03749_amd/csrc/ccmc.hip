@@ -114,7 +114,7 @@ struct ccmc_state {
     DevBuf arg_dev;
     uint8_t *arg_host = nullptr;  // pinned
     size_t arg_hcap = 0;
-    Scratch *batch_hscr = nullptr;  // pinned, coherent: written by k_final
+    Scratch *batch_hscr = nullptr;  // pinned, coherent: written by k_final_part
     Scratch *batch_hdev = nullptr;  // its device address
     size_t batch_hcap = 0;
     uint64_t batch_seq = 0;         // sequence number of the last batch this state led
@@ -562,7 +562,7 @@ struct Plan {
     bool replay = false;       // a capacity overflowed: grow and step again
 };
 
-enum { kTkWeights, kTkOff, kTkBoff, kTkFold, kTkMerge, kTkPlace, kTkRadix, kTickets = kTkRadix + kRadixMaxPasses };
+enum { kTkWeights, kTkOff, kTkBoff, kTkFold, kTkMerge, kTkPlace, kTkFinal, kTkRadix, kTickets = kTkRadix + kRadixMaxPasses };
 
 // Sizes and capacities of one state's step (all allocation happens here).
 template <int W, typename T>
@@ -1080,21 +1080,12 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
             args.push_back(FinalPartArgs{parts_of(p), p.n_parts, gen_of(p), p.nblk_cap, ptr<double>(p.st->abs_part), p.nb_abs,
-                                         p.sc, p.ne, reinterpret_cast<FinalPart *>(p.lb + p.o_fin)});
+                                         p.sc, p.ne, reinterpret_cast<FinalPart *>(p.lb + p.o_fin),
+                                         p.lb + p.o_tick + kTkFinal, scr_copy + i, seq});
             blk[i] = (uint32_t)p.fin_blocks;
         }
         stage(ar, recs, "final", args, blk, works([&](auto &) { return Work{0.0, nullptr, 0}; }),
               [s](const FinalPartArgs *a, BatchMap bm, unsigned g) { k_final_part<<<g, kThreads, 0, s>>>(a, bm); });
-    }
-    {
-        std::vector<FinalArgs> args;
-        for (size_t i = 0; i < n; ++i) {
-            auto &p = ps[i];
-            args.push_back(FinalArgs{reinterpret_cast<const FinalPart *>(p.lb + p.o_fin), p.fin_blocks, p.sc, scr_copy + i, seq});
-            blk[i] = 1;
-        }
-        stage(ar, recs, "final", args, blk, works([&](auto &) { return Work{0.0, nullptr, 0}; }),
-              [s](const FinalArgs *a, BatchMap bm, unsigned g) { k_final<<<g, kThreads, 0, s>>>(a, bm); });
     }
 
     // ---- the argument tables: one copy, then the launches in order
@@ -1118,7 +1109,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         launch(lead, r.name, r.works, [&] { r.go(dev + r.off_args, bm, r.blocks); });
     }
 
-    // ---- (a14) the one synchronisation of the step: k_final writes each state's scalars into
+    // ---- (a14) the one synchronisation of the step: k_final_part writes each state's scalars into
     // pinned host memory and then the batch's sequence number; the host polls for it (and,
     // every few thousand polls, asks whether the stream has ended without writing it)
     for (size_t i = 0; i < n; ++i) {

@@ -15,7 +15,7 @@
 //                    determinants numbered by look-back; k_seg_close for runs across tiles
 //   k_merge          merge, occupation rounding and compaction into the other    (a12, a13)
 //                    store buffer (look-back for the output positions)
-//   k_final          FP64 population, projected-energy and count reductions    (a14)
+//   k_final_part     FP64 population, projected-energy and count reductions    (a14)
 #pragma once
 #include "device.h"
 #include "primitives.h"
@@ -71,7 +71,7 @@ struct Ranks {
     const uint32_t *seg;
 };
 
-// Per-block partial statistics of the item kernels, reduced by k_final.
+// Per-block partial statistics of the item kernels, reduced by k_final_part.
 struct ItemPartials {
     double *num;       // projected-energy numerator
     uint64_t *att;     // spawning attempts
@@ -1625,7 +1625,7 @@ __global__ void __launch_bounds__(kThreads) k_merge(const MergeArgs<W, T> *__res
 // The step's statistics in a fixed-order two-stage reduction: block b of k_final_part sums
 // the b-th contiguous chunk of every partial array (the item kernels' per-block partials, the
 // generation blocks' spawn and death counts, the per-block |N| sums of the compacted store);
-// k_final adds the chunk sums in chunk order.
+// the last block to finish adds the chunk sums in chunk order.
 struct FinalPart {
     double num, tot;
     uint64_t att, disc, mx, sp, de, pad;
@@ -1718,25 +1718,6 @@ __device__ __forceinline__ void final_part_body(uint32_t blk, uint32_t nblk, Ite
     if (threadIdx.x == 0) out[blk] = r;
 }
 
-struct FinalPartArgs {
-    ItemPartials part;
-    uint64_t n_parts;
-    GenStats gs;
-    uint64_t n_gen;
-    const double *abs_part;
-    uint64_t n_abs;
-    const Scratch *sc;
-    uint64_t ne;
-    FinalPart *out;
-};
-
-__global__ void __launch_bounds__(kThreads) k_final_part(const FinalPartArgs *__restrict__ args, BatchMap bm)
-{
-    uint32_t blk, nblk;
-    const FinalPartArgs &A = args[batch_state(bm, blk, nblk)];
-    final_part_body(blk, nblk, A.part, A.n_parts, A.gs, A.n_gen, A.abs_part, A.n_abs, A.sc, A.ne, A.out);
-}
-
 __device__ __forceinline__ void final_body(uint32_t blk, uint32_t nblk, const FinalPart *__restrict__ in, uint64_t n, Scratch *sc,
                                            Scratch *copy, uint64_t seq)
 {
@@ -1767,19 +1748,36 @@ __device__ __forceinline__ void final_body(uint32_t blk, uint32_t nblk, const Fi
     __hip_atomic_store(&copy->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-struct FinalArgs {
-    const FinalPart *in;
-    uint64_t n;
+struct FinalPartArgs {
+    ItemPartials part;
+    uint64_t n_parts;
+    GenStats gs;
+    uint64_t n_gen;
+    const double *abs_part;
+    uint64_t n_abs;
     Scratch *sc;
-    Scratch *copy;  // device address of the host's pinned copy
+    uint64_t ne;
+    FinalPart *out;
+    uint64_t *done;  // blocks of this state finished (zero before the launch)
+    Scratch *copy;   // device address of the host's pinned copy of the scalars
     uint64_t seq;
 };
 
-__global__ void __launch_bounds__(kThreads) k_final(const FinalArgs *__restrict__ args, BatchMap bm)
+// Both stages of the reduction in one launch: each block publishes its part and counts
+// itself done (an acquire-release atomic); the block that finishes last sums the parts in
+// block order and hands the scalars to the host.
+__global__ void __launch_bounds__(kThreads) k_final_part(const FinalPartArgs *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
-    const FinalArgs &A = args[batch_state(bm, blk, nblk)];
-    final_body(blk, nblk, A.in, A.n, A.sc, A.copy, A.seq);
+    const FinalPartArgs &A = args[batch_state(bm, blk, nblk)];
+    final_part_body(blk, nblk, A.part, A.n_parts, A.gs, A.n_gen, A.abs_part, A.n_abs, A.sc, A.ne, A.out);
+    __shared__ bool s_last;
+    if (threadIdx.x == 0) {
+        const uint64_t before = __hip_atomic_fetch_add(A.done, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = before + 1 == nblk;
+    }
+    __syncthreads();
+    if (s_last) final_body(blk, nblk, A.out, nblk, A.sc, A.copy, A.seq);
 }
 
 // Clear each state's step area and the per-entry sums of its store.
