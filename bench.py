@@ -325,7 +325,8 @@ def serving_benchmark(n_requests: int, max_steps: int, tol: float, budget: float
                hbm_budget=budget, slots=slots,
                per_request=[dict(id=r.request_id, arrival=round(r.arrival, 3), tte=round(r.time_to_energy, 3),
                                  steps=r.steps, e=r.energy, err=r.error, ok=r.converged,
-                                 **({"failed": r.failed} if r.failed else {})) for r in res])
+                                 **({"failed": r.failed} if r.failed else {}),
+                                 **({"grown": r.grown} if r.grown else {})) for r in res])
     return out
 
 

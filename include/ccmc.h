@@ -233,6 +233,12 @@ ccmc_status ccmc_dims(const ccmc_state *st, int *n_electrons, int *n_spin_orbita
 /* Device memory currently held by the state, in bytes. */
 ccmc_status ccmc_memory(const ccmc_state *st, uint64_t *bytes);
 
+/* Change the state's device-memory budget (hbm_budget_bytes; 0 = no limit).  A step that
+ * failed with CCMC_ENOMEM left the state unchanged, so a caller with memory to spare can raise
+ * the budget and step again.  A budget below ccmc_memory is accepted: it only stops further
+ * growth.  CCMC_EINVAL for a NULL state. */
+ccmc_status ccmc_set_budget(ccmc_state *st, uint64_t hbm_budget_bytes);
+
 #ifdef __cplusplus
 }
 #endif

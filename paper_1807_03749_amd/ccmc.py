@@ -67,7 +67,8 @@ class ccmc_kernel_time(C.Structure):
 EXPORTED = ["ccmc_options_default", "ccmc_init", "ccmc_step", "ccmc_step_batch", "ccmc_energy", "ccmc_free",
             "ccmc_last_error",
             "ccmc_export_size", "ccmc_export", "ccmc_import", "ccmc_spawns_size", "ccmc_export_spawns",
-            "ccmc_profile", "ccmc_profile_read", "ccmc_dims", "ccmc_memory", "ccmc_codistribution"]
+            "ccmc_profile", "ccmc_profile_read", "ccmc_dims", "ccmc_memory", "ccmc_set_budget",
+            "ccmc_codistribution"]
 
 _lib = None
 _u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
@@ -101,6 +102,7 @@ def lib():
             "ccmc_profile": (st, [vp, C.c_char_p]),
             "ccmc_profile_read": (st, [vp, C.POINTER(ccmc_kernel_time), C.c_int, C.POINTER(C.c_int)]),
             "ccmc_memory": (st, [vp, C.POINTER(C.c_uint64)]),
+            "ccmc_set_budget": (st, [vp, C.c_uint64]),
             "ccmc_dims": (st, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
             "ccmc_codistribution": (st, [C.c_int, _u64p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p,
                                          C.c_int, _u64p, _u64p]),
@@ -126,6 +128,7 @@ def options(**kw) -> ccmc_options:
 
 
 CCMC_EINVAL_STATUS = -1
+CCMC_ENOMEM_STATUS = -2
 
 
 class State:
@@ -242,6 +245,10 @@ class State:
         self._check(lib().ccmc_profile_read(self._h, buf, 64, C.byref(n)))
         return {buf[i].name.decode(): dict(launches=buf[i].launches, ms=buf[i].ms, bytes=buf[i].bytes,
                                            items=buf[i].items) for i in range(n.value)}
+
+    def ccmc_set_budget(self, hbm_budget_bytes: int):
+        self._check(lib().ccmc_set_budget(self._h, int(hbm_budget_bytes)))
+        self.options.hbm_budget_bytes = int(hbm_budget_bytes)
 
     def ccmc_memory(self) -> int:
         b = C.c_uint64()

@@ -1790,4 +1790,11 @@ ccmc_status ccmc_memory(const ccmc_state *st, uint64_t *bytes)
     return CCMC_OK;
 }
 
+ccmc_status ccmc_set_budget(ccmc_state *st, uint64_t hbm_budget_bytes)
+{
+    if (!st) return CCMC_EINVAL;
+    st->opt.hbm_budget_bytes = hbm_budget_bytes;
+    return CCMC_OK;
+}
+
 }  // extern "C"

@@ -9,7 +9,9 @@ iteration steps all active solves together in shared launches (``ccmc_step_batch
 
 Admission is by device memory: a request is admitted when a slot is free and its estimated
 footprint fits the remaining HBM budget; its state is created with that estimate (times a
-safety factor) as its own budget, so a solve that outgrows it fails alone with ENOMEM.
+safety factor) as its own budget.  A solve that outgrows it (a step that fails with ENOMEM and
+leaves the state unchanged) gets its reservation doubled and steps again, as long as the
+server's budget has room; otherwise it fails alone.
 Finished solves free their memory at once, so waiting requests join the running batch
 between two steps -- continuous batching, not a queue of whole runs.
 
@@ -49,6 +51,7 @@ class Solve:
     admitted: float
     steps: int = 0
     varying_since: int = -1
+    grown: int = 0          # times its memory reservation was doubled
     num: list = field(default_factory=list)
     den: list = field(default_factory=list)
     attempts: int = 0
@@ -66,6 +69,7 @@ class Result:
     converged: bool
     attempts: int
     failed: str = ""
+    grown: int = 0          # times the solve's memory reservation was doubled
 
     @property
     def time_to_energy(self) -> float:
@@ -133,7 +137,7 @@ class Server:
             e, err, _ = driver.reblock_ratio(np.array(s.num), np.array(s.den))
         s.state.close()
         return Result(s.req.request_id, s.req.arrival, s.admitted, now, s.steps, e, err,
-                      bool(err < self.tol) and not failed, s.attempts, failed)
+                      bool(err < self.tol) and not failed, s.attempts, failed, s.grown)
 
     # ------------------------------------------------------------------------ the loop
     def run(self, requests: list[Request]) -> list[Result]:
@@ -168,6 +172,15 @@ class Server:
             keep = []
             for s, r in zip(active, res):
                 if isinstance(r, Exception):
+                    if getattr(r, "status", None) == ccmc.CCMC_ENOMEM_STATUS and used + s.est_bytes <= self.hbm_budget:
+                        # the step was rolled back: double the reservation and step again
+                        used += s.est_bytes
+                        s.est_bytes *= 2
+                        s.grown += 1
+                        s.state.ccmc_set_budget(int(self.safety * s.est_bytes))
+                        keep.append(s)
+                        self.log(f"grow {s.req.request_id} to {s.est_bytes / 1e6:.0f} MB at {now:.2f}s")
+                        continue
                     results.append(self._finish(s, now, failed=str(r)))
                     used -= s.est_bytes
                 elif self._advance(s, r):
@@ -194,6 +207,7 @@ def summary(results: list[Result], wall: float) -> dict:
     tte = np.array([r.time_to_energy for r in results])
     conv = [r for r in results if r.converged]
     return dict(requests=len(results), converged=len(conv), failed=sum(1 for r in results if r.failed),
+                reservations_grown=sum(r.grown for r in results),
                 p50_time_to_energy_s=float(np.percentile(tte, 50)) if len(tte) else None,
                 p99_time_to_energy_s=float(np.percentile(tte, 99)) if len(tte) else None,
                 attempts_per_s=sum(r.attempts for r in results) / wall if wall > 0 else None,

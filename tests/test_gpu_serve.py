@@ -69,3 +69,20 @@ def test_admission_respects_memory_budget():
     spans = sorted((r.admitted, r.finished) for r in res)
     for (a0, f0), (a1, f1) in zip(spans, spans[1:]):
         assert a1 >= f0
+
+
+def test_outgrown_reservation_is_doubled_and_the_result_unchanged():
+    """A per-solve budget far below what the solve needs: each step that fails with ENOMEM leaves
+    the state unchanged, the server doubles the reservation and steps again, and the solve ends
+    with exactly the result it gets with room to spare."""
+    req = _requests()[0]
+    kw = dict(hbm_budget=8e9, max_active=3, tol=1e-9, equil=50, min_samples=64, check_every=64, max_steps=300)
+    c1, c2 = FakeClock(), FakeClock()
+    roomy = serve.Server(clock=c1, sleep=c1.sleep, **kw).run([req])[0]
+    tight = serve.Server(clock=c2, sleep=c2.sleep, safety=0.1, **kw).run([req])[0]
+    assert not roomy.failed and not tight.failed, tight.failed
+    assert tight.grown >= 1 and roomy.grown == 0
+    assert (tight.steps, tight.attempts, tight.energy, tight.error) == (roomy.steps, roomy.attempts, roomy.energy,
+                                                                        roomy.error)
+    print(f"[serve] reservation doubled {tight.grown} times, same result", flush=True)
+    sys.stdout.flush()
