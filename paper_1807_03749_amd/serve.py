@@ -10,8 +10,9 @@ iteration steps all active solves together in shared launches (``ccmc_step_batch
 Admission is by device memory: a request is admitted when a slot is free and its estimated
 footprint fits the remaining HBM budget; its state is created with that estimate (times a
 safety factor) as its own budget.  A solve that outgrows it (a step that fails with ENOMEM and
-leaves the state unchanged) gets its reservation doubled and steps again, as long as the
-server's budget has room; otherwise it fails alone.
+leaves the state unchanged) gets its reservation doubled and steps again, up to `max_grow`
+times and as long as the server's budget has room; otherwise it fails alone.  So does a solve
+whose population runs away beyond what one step can select (2^32 selections).
 Finished solves free their memory at once, so waiting requests join the running batch
 between two steps -- continuous batching, not a queue of whole runs.
 
@@ -87,7 +88,7 @@ def estimate_bytes(req: Request) -> int:
 class Server:
     def __init__(self, hbm_budget: float = 64e9, max_active: int = 32, tol: float = 1e-4, equil: int = 500,
                  min_samples: int = 512, check_every: int = 256, max_steps: int = 20000, safety: float = 4.0,
-                 clock=time.perf_counter, sleep=time.sleep, log=None):
+                 max_grow: int = 3, clock=time.perf_counter, sleep=time.sleep, log=None):
         self.hbm_budget = hbm_budget
         self.max_active = max_active
         self.tol = tol
@@ -96,6 +97,7 @@ class Server:
         self.check_every = check_every
         self.max_steps = max_steps
         self.safety = safety
+        self.max_grow = max_grow
         self.clock = clock
         self.sleep = sleep
         self.log = log or (lambda m: None)
@@ -164,6 +166,14 @@ class Server:
                 if pending:
                     self.sleep(max(0.0, pending[0].arrival - (self.clock() - t0)))
                 continue
+            # a population beyond one step's selection range (or a shift gone non-finite) ends
+            # that solve alone, before it could invalidate the batch's arguments
+            for s in [s for s in active if not (s.nsel < (1 << 32) and math.isfinite(s.ctl.shift))]:
+                active.remove(s)
+                results.append(self._finish(s, now, failed="population beyond 2^32 selections per step"))
+                used -= s.est_bytes
+            if not active:
+                continue
             res = ccmc.ccmc_step_batch([s.state for s in active], [s.req.tau for s in active],
                                        [s.ctl.shift for s in active], [s.nsel for s in active])
             self.batch_steps += 1
@@ -172,7 +182,8 @@ class Server:
             keep = []
             for s, r in zip(active, res):
                 if isinstance(r, Exception):
-                    if getattr(r, "status", None) == ccmc.CCMC_ENOMEM_STATUS and used + s.est_bytes <= self.hbm_budget:
+                    if (getattr(r, "status", None) == ccmc.CCMC_ENOMEM_STATUS and s.grown < self.max_grow
+                            and used + s.est_bytes <= self.hbm_budget):
                         # the step was rolled back: double the reservation and step again
                         used += s.est_bytes
                         s.est_bytes *= 2

@@ -79,7 +79,7 @@ def test_outgrown_reservation_is_doubled_and_the_result_unchanged():
     kw = dict(hbm_budget=8e9, max_active=3, tol=1e-9, equil=50, min_samples=64, check_every=64, max_steps=300)
     c1, c2 = FakeClock(), FakeClock()
     roomy = serve.Server(clock=c1, sleep=c1.sleep, **kw).run([req])[0]
-    tight = serve.Server(clock=c2, sleep=c2.sleep, safety=0.1, **kw).run([req])[0]
+    tight = serve.Server(clock=c2, sleep=c2.sleep, safety=0.1, max_grow=20, **kw).run([req])[0]
     assert not roomy.failed and not tight.failed, tight.failed
     assert tight.grown >= 1 and roomy.grown == 0
     assert (tight.steps, tight.attempts, tight.energy, tight.error) == (roomy.steps, roomy.attempts, roomy.energy,
