@@ -98,7 +98,7 @@ struct ccmc_state {
     uint64_t rt_n = 0;   // rank-table buckets
     uint32_t rsh = 0;    // rank-table shift
     uint64_t last_q = 0; // Q of the last step (sizes the next selection guide)
-    DevBuf ikey, iA, ideath, in, ilevel, icnt, ioff;
+    DevBuf ikey, iA, ideath, in, icnt, ioff;
     uint64_t icap = 0;
     DevBuf num_part, att_part, disc_part, max_part, abs_part;
     DevBuf block_item, gcount, gspawn, gdeath, boff;
@@ -613,7 +613,6 @@ ccmc_status plan_sizes(Plan<W, T> &p)
         TRY(ensure(st, st->iA, nc * sizeof(T)));
         TRY(ensure(st, st->ideath, nc * sizeof(T)));
         TRY(ensure(st, st->in, nc * sizeof(uint32_t)));
-        TRY(ensure(st, st->ilevel, nc));
         TRY(ensure(st, st->icnt, nc * sizeof(uint64_t)));
         TRY(ensure(st, st->ioff, nc * sizeof(uint64_t)));
         st->icap = nc;
@@ -875,11 +874,10 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
               [s](const GuideArgs *a, BatchMap bm, unsigned g) { k_guide<<<g, kThreads, 0, s>>>(a, bm); });
     }
     // ---- (a2-a5, a9, a10) items: non-composite (FNC) then sampled clusters; then the rank table
-    const double item_bytes = kb + 2 * tb + 13.0;  // key, A, death, n, level, slot count
     auto items_of = [&](Plan<W, T> &p) {
         ccmc_state *st = p.st;
         return Items<T>{ptr<uint64_t>(st->ikey), ptr<T>(st->iA), ptr<T>(st->ideath), ptr<uint32_t>(st->in),
-                        ptr<uint8_t>(st->ilevel), ptr<uint64_t>(st->icnt), st->icap};
+                        ptr<uint64_t>(st->icnt), st->icap};
     };
     auto parts_of = [&](Plan<W, T> &p) {
         ccmc_state *st = p.st;
@@ -905,8 +903,10 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
                              p.n_fnc, p.nb_fnc + p.nb_sel, rt, parts_of(p), p.sc});
             blk[i] = p.nb_fnc + p.nb_sel + p.nb_rt;
         }
-        // bytes: each item written (plus, for the non-composite ones, the store entry read)
-        stage(ar, recs, "items", args, blk, works([&](auto &p) { return Work{item_bytes, nullptr, p.n_items}; }),
+        // bytes: every item's slot count, and key, A, death and n of each live item
+        stage(ar, recs, "items", args, blk, works([&](auto &p) {
+                  return Work{8.0, nullptr, p.n_items, nullptr, kb + 2 * tb + 4.0, &p.st->cnt_live_items};
+              }),
               [s](const A *a, BatchMap bm, unsigned g) { k_items<W, T><<<g, kThreads, 0, s>>>(a, bm); });
     }
     {
@@ -1395,7 +1395,7 @@ void destroy(ccmc_state *st)
     DevBuf *bufs[] = {&st->t_grid, &st->t_nvec, &st->t_vq, &st->t_h, &st->t_eri, &st->t_fock, &st->t_vpair,
                       &st->t_binv, &st->t_bino, &st->skey[0], &st->skey[1], &st->samp[0], &st->samp[1], &st->sK[0],
                       &st->sK[1], &st->srank[0], &st->srank[1], &st->P, &st->guide, &st->delta, &st->rtab, &st->ikey,
-                      &st->iA, &st->ideath, &st->in, &st->ilevel, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,
+                      &st->iA, &st->ideath, &st->in, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,
                       &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->boff, &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
                       &st->sidx[0], &st->sidx[1], &st->tile_region,
                       &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->lb, &st->arg_dev,

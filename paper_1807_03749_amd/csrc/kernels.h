@@ -104,8 +104,8 @@ struct Items {
     T *A;
     T *death;      // death amount -tau (K - S) A, 0 when none
     uint32_t *n;   // spawning attempts
-    uint8_t *level;
-    uint64_t *cnt; // record slots: n + 1 (slot 0 = death), 0 when discarded
+    uint64_t *cnt; // record slots: n + 1 (slot 0 = death), 0 when discarded; a discarded
+                   // item's other fields are not written (nothing reads an item without slots)
     uint64_t stride;
 };
 
@@ -388,7 +388,6 @@ __device__ __forceinline__ void noncomposite_block(unsigned blk, const SysDev &S
         it.A[k] = A;
         it.death[k] = death;
         it.n[k] = n;
-        it.level[k] = (uint8_t)L;
         it.cnt[k] = (uint64_t)n + 1;
         att = n;
         mx = n;
@@ -565,12 +564,13 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
             disc = 1;
         }
         const uint64_t j = item_base + k;
+        if (ok) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) it.key[(uint64_t)w * it.stride + j] = d[w];
-        it.A[j] = A;
-        it.death[j] = death;
-        it.n[j] = n;
-        it.level[j] = (uint8_t)L;
+            for (int w = 0; w < W; ++w) it.key[(uint64_t)w * it.stride + j] = d[w];
+            it.A[j] = A;
+            it.death[j] = death;
+            it.n[j] = n;
+        }
         it.cnt[j] = cnt;
     }
     const double bnum = block_reduce_sum(num);
