@@ -774,7 +774,10 @@ struct SlotOut {
     }
 };
 
-constexpr int kGenLdsItems = 2048;
+// Items of a generation block whose offsets are searched in LDS (more: searched in HBM).
+// With 1536 the block's LDS is 22.6 KB, so 7 blocks fit in a CU's 160 KB; with the register
+// budget of 7 waves per SIMD below, the kernel runs at 7 waves per SIMD instead of 6.
+constexpr int kGenLdsItems = 1536;
 
 // Per-block statistics of the generation kernel (no single-address atomics).
 struct GenStats {
@@ -979,12 +982,33 @@ struct GenerateArgs {
 };
 
 template <int W, typename T>
-__global__ void __launch_bounds__(kThreads) k_generate(const GenerateArgs<W, T> *__restrict__ args, BatchMap bm)
+__device__ __forceinline__ void generate_entry(const GenerateArgs<W, T> *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
     const GenerateArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
     generate_body<W, T>(blk, nblk, A.S, A.it, A.off, A.block_item, A.n_fnc, A.n_items, A.slot_cap, A.a, A.rec, A.keep_ids, A.gs, A.sc);
 }
+
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_generate(const GenerateArgs<W, T> *__restrict__ args, BatchMap bm)
+{
+    generate_entry<W, T>(args, bm);
+}
+
+// Determinants of one or two words fit the register budget of 7 waves per SIMD without
+// spilling (at most 72 VGPRs); wider ones keep the compiler's own budget.
+#define CCMC_GENERATE_7_WAVES(W_, T_)                                                                                  \
+    template <>                                                                                                        \
+    __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7, 7)))                            \
+    k_generate<W_, T_>(const GenerateArgs<W_, T_> *__restrict__ args, BatchMap bm)                                     \
+    {                                                                                                                  \
+        generate_entry<W_, T_>(args, bm);                                                                              \
+    }
+CCMC_GENERATE_7_WAVES(1, float)
+CCMC_GENERATE_7_WAVES(1, double)
+CCMC_GENERATE_7_WAVES(2, float)
+CCMC_GENERATE_7_WAVES(2, double)
+#undef CCMC_GENERATE_7_WAVES
 
 // Dense layout of the records.  Output position r belongs to the region q (generation block
 // q) with boff[q] <= r < boff[q+1], at slot position r - boff[q] of that region.  Block b
