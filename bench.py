@@ -428,8 +428,8 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU only "
-              f"(the multi-GPU design is described, not built)", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported: the library steps a population on one GPU "
+              f"(sharding over several GPUs is designed but not implemented)", file=sys.stderr)
         sys.exit(2)
     log = (lambda m: None) if args.quiet else (lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     VIRTUAL.update(n_ranks=args.n_ranks, move_shift=args.move_shift)
