@@ -708,6 +708,7 @@ struct LaunchRec {
     uint32_t n;
     std::vector<Work> works;
     std::function<void(const void *, BatchMap, unsigned)> go;
+    std::function<void(unsigned)> go_one;  // one state: arguments by value
 };
 
 // Stage one batched kernel: per-state arguments and block counts (states with no blocks are
@@ -726,8 +727,39 @@ void stage(ArgArena &ar, std::vector<LaunchRec> &recs, const char *name, const s
     r.off_map = ar.add(off.data(), off.size() * sizeof(uint32_t));
     r.n = (uint32_t)blocks.size();
     r.works = std::move(works);
-    r.go = [kernel](const void *a, BatchMap bm, unsigned g) { kernel(static_cast<const A *>(a), bm, g); };
+    r.go = [kernel](const void *a, BatchMap bm, unsigned g) { kernel(static_cast<const A *>(a), g, bm); };
+    static_assert(sizeof(A) <= 2048, "kernel arguments by value must stay well inside the 4 KB limit");
+    if (args.size() == 1) {
+        const A one = args[0];
+        r.go_one = [kernel, one](unsigned g) { kernel(one, g); };
+    }
     recs.push_back(std::move(r));
+}
+
+// A batch of states: the argument tables and block maps in one copy to the device, then the
+// launches in order.
+ccmc_status launch_tables(ccmc_state *st, const ArgArena &ar, std::vector<LaunchRec> &recs, hipStream_t s)
+{
+    TRY(ensure(st, st->arg_dev, ar.host.size()));
+    if (st->arg_hcap < ar.host.size()) {
+        if (st->arg_host) (void)hipHostFree(st->arg_host);
+        st->arg_host = nullptr;
+        const size_t cap = ar.host.size() + ar.host.size() / 2 + 4096;
+        if (hipHostMalloc((void **)&st->arg_host, cap) != hipSuccess) {
+            st->arg_hcap = 0;
+            st->err = "hipHostMalloc failed";
+            return CCMC_EDEVICE;
+        }
+        st->arg_hcap = cap;
+    }
+    std::memcpy(st->arg_host, ar.host.data(), ar.host.size());
+    HIP_TRY(hipMemcpyAsync(st->arg_dev.p, st->arg_host, ar.host.size(), hipMemcpyHostToDevice, s));
+    const uint8_t *dev = static_cast<const uint8_t *>(st->arg_dev.p);
+    for (auto &r : recs) {
+        const BatchMap bm{reinterpret_cast<const uint32_t *>(dev + r.off_map), r.n};
+        launch(st, r.name, r.works, [&] { r.go(dev + r.off_args, bm, r.blocks); });
+    }
+    return CCMC_OK;
 }
 
 // One attempt at a step of every state in `ps` (same words and precision), in shared
@@ -800,7 +832,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             blk[i] = grid_for(ps[i].lb_words + ps[i].ne);
         }
         stage(ar, recs, "clear", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.lb_words + p.ne}; }),
-              [s](const ClearArgs *a, BatchMap bm, unsigned g) { k_clear<<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_clear<<<g, kThreads, 0, s>>>(a, bm...); });
     }
     // ---- virtual processors (Sec. III): place every excitor, then partition the store by
     // processor with one stable radix pass (store order within each processor)
@@ -814,7 +846,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             blk[i] = p.ranked ? grid_for(p.ne) : 0;
         }
         stage(ar, recs, "place", args, blk, works([&](auto &p) { return Work{kb + 8.0, nullptr, p.ranked ? p.ne : 0}; }),
-              [s](const PlaceArgs<W> *a, BatchMap bm, unsigned g) { k_place<W><<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_place<W><<<g, kThreads, 0, s>>>(a, bm...); });
     }
     {
         std::vector<RadixGhistArgs> args;
@@ -825,7 +857,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             blk[i] = (uint32_t)p.ptiles;
         }
         stage(ar, recs, "place_ghist", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.ranked ? p.ne : 0}; }),
-              [s](const RadixGhistArgs *a, BatchMap bm, unsigned g) { k_radix_ghist<<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_radix_ghist<<<g, kThreads, 0, s>>>(a, bm...); });
     }
     {
         std::vector<RadixOnesweepArgs> args;
@@ -839,7 +871,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             blk[i] = (uint32_t)p.ptiles;
         }
         stage(ar, recs, "place_sweep", args, blk, works([&](auto &p) { return Work{20.0, nullptr, p.ranked ? p.ne : 0}; }),
-              [s](const RadixOnesweepArgs *a, BatchMap bm, unsigned g) { k_radix_onesweep<<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_radix_onesweep<<<g, kThreads, 0, s>>>(a, bm...); });
     }
     // ---- (a1) selection weights, formed inside the scan of their prefix; the draw guide
     {
@@ -855,8 +887,8 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         }
         // bytes: amplitude read, prefix written
         stage(ar, recs, "weights_scan", args, blk, works([&](auto &p) { return Work{tb + 8.0, nullptr, p.ne}; }),
-              [s](const A *a, BatchMap bm, unsigned g) {
-                  k_scan_lb<uint64_t, WeightSrc<T>, ArrayOut<uint64_t>><<<g, kThreads, 0, s>>>(a, bm);
+              [s](const auto &a, unsigned g, auto... bm) {
+                  k_scan_lb<uint64_t, WeightSrc<T>, ArrayOut<uint64_t>><<<g, kThreads, 0, s>>>(a, bm...);
               });
     }
     {
@@ -871,7 +903,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         }
         // bytes: prefix read, about one guide entry per two excitors
         stage(ar, recs, "guide", args, blk, works([&](auto &p) { return Work{10.0, nullptr, p.ne}; }),
-              [s](const GuideArgs *a, BatchMap bm, unsigned g) { k_guide<<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_guide<<<g, kThreads, 0, s>>>(a, bm...); });
     }
     // ---- (a2-a5, a9, a10) items: non-composite (FNC) then sampled clusters; then the rank table
     auto items_of = [&](Plan<W, T> &p) {
@@ -907,7 +939,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         stage(ar, recs, "items", args, blk, works([&](auto &p) {
                   return Work{8.0, nullptr, p.n_items, nullptr, kb + 2 * tb + 4.0, &p.st->cnt_live_items};
               }),
-              [s](const A *a, BatchMap bm, unsigned g) { k_items<W, T><<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_items<W, T><<<g, kThreads, 0, s>>>(a, bm...); });
     }
     {
         using A = ScanLbArgs<uint64_t, CountSrc<uint64_t>, SlotOut>;
@@ -921,7 +953,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             blk[i] = (uint32_t)scan_tiles(p.n_items + 1);
         }
         stage(ar, recs, "slot_scan", args, blk, works([&](auto &p) { return Work{16.0, nullptr, p.n_items + 1}; }),
-              [s](const A *a, BatchMap bm, unsigned g) { k_scan_lb<uint64_t, CountSrc<uint64_t>, SlotOut><<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_scan_lb<uint64_t, CountSrc<uint64_t>, SlotOut><<<g, kThreads, 0, s>>>(a, bm...); });
     }
     // ---- (a6-a8) records: death and spawning attempts, one lane per slot, compacted per block
     auto regions_of = [&](Plan<W, T> &p) {
@@ -944,7 +976,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
                   return Work{kb + tb + (p.ids ? 8.0 : 0.0), &p.st->cnt_rec, 0, &p.st->cnt_att, kb + 2 * tb + 12.0,
                               &p.st->cnt_live_items};
               }),
-              [s](const A *a, BatchMap bm, unsigned g) { k_generate<W, T><<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_generate<W, T><<<g, kThreads, 0, s>>>(a, bm...); });
     }
     {
         using A = ScanLbArgs<uint32_t, CountSrc<uint32_t>, RegionOut>;
@@ -959,8 +991,8 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             blk[i] = (uint32_t)scan_tiles(p.nblk_cap + 1);
         }
         stage(ar, recs, "region_scan", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.nblk_cap + 1}; }),
-              [s](const A *a, BatchMap bm, unsigned g) {
-                  k_scan_lb<uint32_t, CountSrc<uint32_t>, RegionOut><<<g, kThreads, 0, s>>>(a, bm);
+              [s](const auto &a, unsigned g, auto... bm) {
+                  k_scan_lb<uint32_t, CountSrc<uint32_t>, RegionOut><<<g, kThreads, 0, s>>>(a, bm...);
               });
     }
     auto dense_of = [&](Plan<W, T> &p) {
@@ -980,7 +1012,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         stage(ar, recs, "gather", args, blk, works([&](auto &p) {
                   return Work{2.0 * (kb + tb + (p.ids ? 8.0 : 0.0)) + 8.0, &p.st->cnt_rec, 0};
               }),
-              [s](const A *a, BatchMap bm, unsigned g) { k_gather<W, T><<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_gather<W, T><<<g, kThreads, 0, s>>>(a, bm...); });
     }
     // ---- (a11) stable LSD radix sort of (rank, record index): one histogram launch for all
     // passes, then one single-sweep launch per digit
@@ -993,7 +1025,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             blk[i] = (uint32_t)p.tiles;
         }
         stage(ar, recs, "radix_ghist", args, blk, works([&](auto &p) { return Work{8.0, &p.st->cnt_rec, 0}; }),
-              [s](const RadixGhistArgs *a, BatchMap bm, unsigned g) { k_radix_ghist<<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_radix_ghist<<<g, kThreads, 0, s>>>(a, bm...); });
     }
     for (int pass = 0; pass < passes; ++pass) {
         std::vector<RadixOnesweepArgs> args;
@@ -1012,7 +1044,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         }
         stage(ar, recs, "radix_onesweep", args, blk,
               works([&](auto &p) { return Work{2 * 8.0 + (pass ? 8.0 : 4.0), &p.st->cnt_rec, 0}; }),
-              [s](const RadixOnesweepArgs *a, BatchMap bm, unsigned g) { k_radix_onesweep<<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_radix_onesweep<<<g, kThreads, 0, s>>>(a, bm...); });
     }
     const int sorted = (passes - 1) & 1;  // buffer of the last pass
     // ---- (a12) runs of equal determinants: fold in record order, store lookup by rank
@@ -1037,7 +1069,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         }
         // bytes: rank, index, gathered amount and (per head) the new-determinant entry
         stage(ar, recs, "seg_fold", args, blk, works([&](auto &p) { return Work{8.0 + 4.0 + tb, &p.st->cnt_rec, 0, nullptr, kb + 24.0, &p.st->cnt_new}; }),
-              [s](const A *a, BatchMap bm, unsigned g) { k_seg_fold<W, T><<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_seg_fold<W, T><<<g, kThreads, 0, s>>>(a, bm...); });
     }
     {
         std::vector<SegCloseArgs> args;
@@ -1050,7 +1082,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             blk[i] = grid_for(p.fold_tiles);
         }
         stage(ar, recs, "seg_close", args, blk, works([&](auto &p) { return Work{24.0, nullptr, p.fold_tiles}; }),
-              [s](const SegCloseArgs *a, BatchMap bm, unsigned g) { k_seg_close<<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_seg_close<<<g, kThreads, 0, s>>>(a, bm...); });
     }
     // ---- (a12, a13) merge, round and compact into the other store buffer
     const double eb = kb + 2 * tb + 8.0;  // one store entry: key, amplitude, diagonal, rank
@@ -1072,7 +1104,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         // bytes: each merged entry read (store entry and its sum, or a new determinant) and
         // each survivor written
         stage(ar, recs, "merge", args, blk, works([&](auto &p) { return Work{2.0 * eb + 8.0, &p.st->cnt_merged, 0}; }),
-              [s](const A *a, BatchMap bm, unsigned g) { k_merge<W, T><<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_merge<W, T><<<g, kThreads, 0, s>>>(a, bm...); });
     }
     // ---- (a14) the step's statistics in a fixed-order two-stage reduction
     {
@@ -1085,28 +1117,14 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             blk[i] = (uint32_t)p.fin_blocks;
         }
         stage(ar, recs, "final", args, blk, works([&](auto &) { return Work{0.0, nullptr, 0}; }),
-              [s](const FinalPartArgs *a, BatchMap bm, unsigned g) { k_final_part<<<g, kThreads, 0, s>>>(a, bm); });
+              [s](const auto &a, unsigned g, auto... bm) { k_final_part<<<g, kThreads, 0, s>>>(a, bm...); });
     }
 
-    // ---- the argument tables: one copy, then the launches in order
-    TRY(ensure(lead, lead->arg_dev, ar.host.size()));
-    if (lead->arg_hcap < ar.host.size()) {
-        if (lead->arg_host) (void)hipHostFree(lead->arg_host);
-        lead->arg_host = nullptr;
-        const size_t cap = ar.host.size() + ar.host.size() / 2 + 4096;
-        if (hipHostMalloc((void **)&lead->arg_host, cap) != hipSuccess) {
-            lead->arg_hcap = 0;
-            lead->err = "hipHostMalloc failed";
-            return CCMC_EDEVICE;
-        }
-        lead->arg_hcap = cap;
-    }
-    std::memcpy(lead->arg_host, ar.host.data(), ar.host.size());
-    HIP_TRY(hipMemcpyAsync(lead->arg_dev.p, lead->arg_host, ar.host.size(), hipMemcpyHostToDevice, s));
-    const uint8_t *dev = static_cast<const uint8_t *>(lead->arg_dev.p);
-    for (auto &r : recs) {
-        const BatchMap bm{reinterpret_cast<const uint32_t *>(dev + r.off_map), r.n};
-        launch(lead, r.name, r.works, [&] { r.go(dev + r.off_args, bm, r.blocks); });
+    // ---- one state: the launches in order, arguments by value
+    if (n == 1) {
+        for (auto &r : recs) launch(lead, r.name, r.works, [&] { r.go_one(r.blocks); });
+    } else {
+        TRY(launch_tables(lead, ar, recs, s));
     }
 
     // ---- (a14) the one synchronisation of the step: k_final_part writes each state's scalars into

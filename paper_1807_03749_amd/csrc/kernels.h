@@ -168,10 +168,8 @@ struct GuideArgs {
     uint32_t n_ranks;
 };
 
-__global__ void __launch_bounds__(kThreads) k_guide(const GuideArgs *__restrict__ args, BatchMap bm)
+__device__ __forceinline__ void k_guide_entry(const GuideArgs &A, uint32_t blk, uint32_t nblk)
 {
-    uint32_t blk, nblk;
-    const GuideArgs &A = args[batch_state(bm, blk, nblk)];
     const uint64_t g = (uint64_t)blk * kThreads + threadIdx.x;
     uint64_t b0 = 0, b1 = 0;
     if (g < A.n) {
@@ -198,6 +196,17 @@ __global__ void __launch_bounds__(kThreads) k_guide(const GuideArgs *__restrict_
     }
 }
 
+__global__ void __launch_bounds__(kThreads) k_guide(const GuideArgs *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    k_guide_entry(args[batch_state(bm, blk, nblk)], blk, nblk);
+}
+
+__global__ void __launch_bounds__(kThreads) k_guide(const GuideArgs A)
+{
+    k_guide_entry(A, blockIdx.x, gridDim.x);
+}
+
 // Processor of every store entry this step (eq. 9), as the key of the one-pass radix
 // partition; also the partition's length for the radix kernels.
 template <int W>
@@ -212,10 +221,8 @@ struct PlaceArgs {
 };
 
 template <int W>
-__global__ void __launch_bounds__(kThreads) k_place(const PlaceArgs<W> *__restrict__ args, BatchMap bm)
+__device__ __forceinline__ void k_place_entry(const PlaceArgs<W> &A, uint32_t blk, uint32_t nblk)
 {
-    uint32_t blk, nblk;
-    const PlaceArgs<W> &A = args[batch_state(bm, blk, nblk)];
     const uint64_t i = (uint64_t)blk * kThreads + threadIdx.x;
     if (i == 0) A.sc->n_place = A.ne;
     if (i >= A.ne) return;
@@ -223,6 +230,19 @@ __global__ void __launch_bounds__(kThreads) k_place(const PlaceArgs<W> *__restri
 #pragma unroll
     for (int w = 0; w < W; ++w) d[w] = A.key[(uint64_t)w * A.stride + i];
     A.vkey[i] = placement<W>(d, A.i_tau, A.n_ranks, A.move_shift, A.seed);
+}
+
+template <int W>
+__global__ void __launch_bounds__(kThreads) k_place(const PlaceArgs<W> *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    k_place_entry<W>(args[batch_state(bm, blk, nblk)], blk, nblk);
+}
+
+template <int W>
+__global__ void __launch_bounds__(kThreads) k_place(const PlaceArgs<W> A)
+{
+    k_place_entry<W>(A, blockIdx.x, gridDim.x);
 }
 
 // The rank table of the store lookups: rtab[c] is the first store entry whose rank is at
@@ -635,11 +655,22 @@ struct ItemsArgs {
 };
 
 template <int W, typename T>
+__device__ __forceinline__ void k_items_entry(const ItemsArgs<W, T> &A, uint32_t blk, uint32_t nblk)
+{
+    items_body<W, T>(blk, nblk, A.S, A.skey, A.samp, A.sK, A.sstride, A.ne, A.P, A.guide, A.rk, A.n0, A.a, A.it, A.nb_fnc, A.n_fnc, A.nb_items, A.rt, A.part, A.sc);
+}
+
+template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_items(const ItemsArgs<W, T> *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
-    const ItemsArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
-    items_body<W, T>(blk, nblk, A.S, A.skey, A.samp, A.sK, A.sstride, A.ne, A.P, A.guide, A.rk, A.n0, A.a, A.it, A.nb_fnc, A.n_fnc, A.nb_items, A.rt, A.part, A.sc);
+    k_items_entry<W, T>(args[batch_state(bm, blk, nblk)], blk, nblk);
+}
+
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_items(const ItemsArgs<W, T> A)
+{
+    k_items_entry<W, T>(A, blockIdx.x, gridDim.x);
 }
 
 // ----------------------------------------------------------------- generation
@@ -982,17 +1013,22 @@ struct GenerateArgs {
 };
 
 template <int W, typename T>
-__device__ __forceinline__ void generate_entry(const GenerateArgs<W, T> *__restrict__ args, BatchMap bm)
+__device__ __forceinline__ void k_generate_entry(const GenerateArgs<W, T> &A, uint32_t blk, uint32_t nblk)
 {
-    uint32_t blk, nblk;
-    const GenerateArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
     generate_body<W, T>(blk, nblk, A.S, A.it, A.off, A.block_item, A.n_fnc, A.n_items, A.slot_cap, A.a, A.rec, A.keep_ids, A.gs, A.sc);
 }
 
 template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_generate(const GenerateArgs<W, T> *__restrict__ args, BatchMap bm)
 {
-    generate_entry<W, T>(args, bm);
+    uint32_t blk, nblk;
+    k_generate_entry<W, T>(args[batch_state(bm, blk, nblk)], blk, nblk);
+}
+
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_generate(const GenerateArgs<W, T> A)
+{
+    k_generate_entry<W, T>(A, blockIdx.x, gridDim.x);
 }
 
 // Determinants of one or two words fit the register budget of 7 waves per SIMD without
@@ -1002,7 +1038,14 @@ __global__ void __launch_bounds__(kThreads) k_generate(const GenerateArgs<W, T> 
     __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7, 7)))                            \
     k_generate<W_, T_>(const GenerateArgs<W_, T_> *__restrict__ args, BatchMap bm)                                     \
     {                                                                                                                  \
-        generate_entry<W_, T_>(args, bm);                                                                              \
+        uint32_t blk, nblk;                                                                                            \
+        k_generate_entry<W_, T_>(args[batch_state(bm, blk, nblk)], blk, nblk);                                         \
+    }                                                                                                                  \
+    template <>                                                                                                        \
+    __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7, 7)))                            \
+    k_generate<W_, T_>(const GenerateArgs<W_, T_> A)                                                                   \
+    {                                                                                                                  \
+        k_generate_entry<W_, T_>(A, blockIdx.x, gridDim.x);                                                            \
     }
 CCMC_GENERATE_7_WAVES(1, float)
 CCMC_GENERATE_7_WAVES(1, double)
@@ -1114,11 +1157,22 @@ struct GatherArgs {
 };
 
 template <int W, typename T>
+__device__ __forceinline__ void k_gather_entry(const GatherArgs<W, T> &A, uint32_t blk, uint32_t nblk)
+{
+    gather_body<W, T>(blk, nblk, A.S, A.reg, A.boff, A.tile_region, A.n_blocks, A.rec_cap, A.out, A.keep_ids, A.sc);
+}
+
+template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_gather(const GatherArgs<W, T> *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
-    const GatherArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
-    gather_body<W, T>(blk, nblk, A.S, A.reg, A.boff, A.tile_region, A.n_blocks, A.rec_cap, A.out, A.keep_ids, A.sc);
+    k_gather_entry<W, T>(args[batch_state(bm, blk, nblk)], blk, nblk);
+}
+
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_gather(const GatherArgs<W, T> A)
+{
+    k_gather_entry<W, T>(A, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------- annihilation
@@ -1367,12 +1421,23 @@ struct SegFoldArgs {
 };
 
 template <int W, typename T>
+__device__ __forceinline__ void k_seg_fold_entry(const SegFoldArgs<W, T> &A, uint32_t blk, uint32_t nblk)
+{
+    seg_fold_body<W, T>(blk, nblk, A.rank, A.idx, A.ramp, A.cap, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.rtab, A.rt_n,
+                        A.rsh, A.ft, A.nd, A.sc);
+}
+
+template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_seg_fold(const SegFoldArgs<W, T> *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
-    const SegFoldArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
-    seg_fold_body<W, T>(blk, nblk, A.rank, A.idx, A.ramp, A.cap, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.rtab, A.rt_n,
-                        A.rsh, A.ft, A.nd, A.sc);
+    k_seg_fold_entry<W, T>(args[batch_state(bm, blk, nblk)], blk, nblk);
+}
+
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_seg_fold(const SegFoldArgs<W, T> A)
+{
+    k_seg_fold_entry<W, T>(A, blockIdx.x, gridDim.x);
 }
 
 // Finish the open runs: add the leading pieces of the following tiles until one holds a head.
@@ -1419,11 +1484,20 @@ struct SegCloseArgs {
     Scratch *sc;
 };
 
+__device__ __forceinline__ void k_seg_close_entry(const SegCloseArgs &A, uint32_t blk, uint32_t nblk)
+{
+    seg_close_body(blk, nblk, A.rank, A.n_tiles, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.nsum, A.ft, A.sc);
+}
+
 __global__ void __launch_bounds__(kThreads) k_seg_close(const SegCloseArgs *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
-    const SegCloseArgs &A = args[batch_state(bm, blk, nblk)];
-    seg_close_body(blk, nblk, A.rank, A.n_tiles, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.nsum, A.ft, A.sc);
+    k_seg_close_entry(args[batch_state(bm, blk, nblk)], blk, nblk);
+}
+
+__global__ void __launch_bounds__(kThreads) k_seg_close(const SegCloseArgs A)
+{
+    k_seg_close_entry(A, blockIdx.x, gridDim.x);
 }
 
 // Merge the store (with its sums added) and the new determinants into key order, round, and
@@ -1638,12 +1712,23 @@ struct MergeArgs {
 };
 
 template <int W, typename T>
+__device__ __forceinline__ void k_merge_entry(const MergeArgs<W, T> &A, uint32_t blk, uint32_t nblk)
+{
+    merge_body<W, T>(blk, nblk, A.S, A.in, A.ne, A.delta, A.nkey, A.nrank, A.nstride, A.nins, A.nsum, A.out, A.a, A.status,
+                     A.ticket, A.abs_part, A.sc);
+}
+
+template <int W, typename T>
 __global__ void __launch_bounds__(kThreads) k_merge(const MergeArgs<W, T> *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
-    const MergeArgs<W, T> &A = args[batch_state(bm, blk, nblk)];
-    merge_body<W, T>(blk, nblk, A.S, A.in, A.ne, A.delta, A.nkey, A.nrank, A.nstride, A.nins, A.nsum, A.out, A.a, A.status,
-                     A.ticket, A.abs_part, A.sc);
+    k_merge_entry<W, T>(args[batch_state(bm, blk, nblk)], blk, nblk);
+}
+
+template <int W, typename T>
+__global__ void __launch_bounds__(kThreads) k_merge(const MergeArgs<W, T> A)
+{
+    k_merge_entry<W, T>(A, blockIdx.x, gridDim.x);
 }
 
 // The step's statistics in a fixed-order two-stage reduction: block b of k_final_part sums
@@ -1790,10 +1875,8 @@ struct FinalPartArgs {
 // Both stages of the reduction in one launch: each block publishes its part and counts
 // itself done (an acquire-release atomic); the block that finishes last sums the parts in
 // block order and hands the scalars to the host.
-__global__ void __launch_bounds__(kThreads) k_final_part(const FinalPartArgs *__restrict__ args, BatchMap bm)
+__device__ __forceinline__ void k_final_part_entry(const FinalPartArgs &A, uint32_t blk, uint32_t nblk)
 {
-    uint32_t blk, nblk;
-    const FinalPartArgs &A = args[batch_state(bm, blk, nblk)];
     final_part_body(blk, nblk, A.part, A.n_parts, A.gs, A.n_gen, A.abs_part, A.n_abs, A.sc, A.ne, A.out);
     __shared__ bool s_last;
     if (threadIdx.x == 0) {
@@ -1804,6 +1887,17 @@ __global__ void __launch_bounds__(kThreads) k_final_part(const FinalPartArgs *__
     if (s_last) final_body(blk, nblk, A.out, nblk, A.sc, A.copy, A.seq);
 }
 
+__global__ void __launch_bounds__(kThreads) k_final_part(const FinalPartArgs *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    k_final_part_entry(args[batch_state(bm, blk, nblk)], blk, nblk);
+}
+
+__global__ void __launch_bounds__(kThreads) k_final_part(const FinalPartArgs A)
+{
+    k_final_part_entry(A, blockIdx.x, gridDim.x);
+}
+
 // Clear each state's step area and the per-entry sums of its store.
 struct ClearArgs {
     uint64_t *p;
@@ -1812,15 +1906,24 @@ struct ClearArgs {
     uint64_t ne;
 };
 
-__global__ void __launch_bounds__(kThreads) k_clear(const ClearArgs *__restrict__ args, BatchMap bm)
+__device__ __forceinline__ void k_clear_entry(const ClearArgs &A, uint32_t blk, uint32_t nblk)
 {
-    uint32_t blk, nblk;
-    const ClearArgs &A = args[batch_state(bm, blk, nblk)];
     const uint64_t i = (uint64_t)blk * kThreads + threadIdx.x;
     if (i < A.n)
         A.p[i] = 0;
     else if (i - A.n < A.ne)
         A.delta[i - A.n] = 0.0;
+}
+
+__global__ void __launch_bounds__(kThreads) k_clear(const ClearArgs *__restrict__ args, BatchMap bm)
+{
+    uint32_t blk, nblk;
+    k_clear_entry(args[batch_state(bm, blk, nblk)], blk, nblk);
+}
+
+__global__ void __launch_bounds__(kThreads) k_clear(const ClearArgs A)
+{
+    k_clear_entry(A, blockIdx.x, gridDim.x);
 }
 
 template <typename V>

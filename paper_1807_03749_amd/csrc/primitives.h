@@ -22,7 +22,9 @@ constexpr int kRadixBins = 1 << kRadixBits;
 // ------------------------------------------------------------------ batched launches
 // One launch serves the states of a batch: state s owns the blocks [off[s], off[s+1]) and
 // reads its arguments from args[s].  Each kernel's body sees its block index within its state
-// (blk) and its state's block count (nblk) in place of blockIdx.x and gridDim.x.
+// (blk) and its state's block count (nblk) in place of blockIdx.x and gridDim.x.  Every kernel
+// also has a one-state form that takes its arguments by value: no argument table to copy to
+// the device before the launches, and the pointers in the arguments are known to be global.
 struct BatchMap {
     const uint32_t *off;  // n + 1 entries, off[0] = 0
     uint32_t n;
@@ -268,11 +270,22 @@ struct ScanLbArgs {
 };
 
 template <typename V, typename Src, typename Out>
+__device__ __forceinline__ void k_scan_lb_entry(const ScanLbArgs<V, Src, Out> &A, uint32_t blk, uint32_t nblk)
+{
+    scan_lb_body<V, Src, Out>(blk, nblk, A.in, A.out, A.n, A.inclusive, A.status, A.ticket, A.total);
+}
+
+template <typename V, typename Src, typename Out>
 __global__ void __launch_bounds__(kThreads) k_scan_lb(const ScanLbArgs<V, Src, Out> *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
-    const ScanLbArgs<V, Src, Out> &A = args[batch_state(bm, blk, nblk)];
-    scan_lb_body<V, Src, Out>(blk, nblk, A.in, A.out, A.n, A.inclusive, A.status, A.ticket, A.total);
+    k_scan_lb_entry<V, Src, Out>(args[batch_state(bm, blk, nblk)], blk, nblk);
+}
+
+template <typename V, typename Src, typename Out>
+__global__ void __launch_bounds__(kThreads) k_scan_lb(const ScanLbArgs<V, Src, Out> A)
+{
+    k_scan_lb_entry<V, Src, Out>(A, blockIdx.x, gridDim.x);
 }
 
 // ----------------------------------------------------------------- radix sort
@@ -340,11 +353,20 @@ struct RadixGhistArgs {
     uint32_t *ghist;
 };
 
+__device__ __forceinline__ void k_radix_ghist_entry(const RadixGhistArgs &A, uint32_t blk, uint32_t nblk)
+{
+    radix_ghist_body(blk, nblk, A.key, A.n_live, A.passes, A.ghist);
+}
+
 __global__ void __launch_bounds__(kThreads) k_radix_ghist(const RadixGhistArgs *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
-    const RadixGhistArgs &A = args[batch_state(bm, blk, nblk)];
-    radix_ghist_body(blk, nblk, A.key, A.n_live, A.passes, A.ghist);
+    k_radix_ghist_entry(args[batch_state(bm, blk, nblk)], blk, nblk);
+}
+
+__global__ void __launch_bounds__(kThreads) k_radix_ghist(const RadixGhistArgs A)
+{
+    k_radix_ghist_entry(A, blockIdx.x, gridDim.x);
 }
 
 // One stable pass by the digit at `shift`.  Wavefront w of a tile owns the tile's keys
@@ -489,11 +511,20 @@ struct RadixOnesweepArgs {
     uint64_t *ticket;
 };
 
+__device__ __forceinline__ void k_radix_onesweep_entry(const RadixOnesweepArgs &A, uint32_t blk, uint32_t nblk)
+{
+    radix_onesweep_body(blk, nblk, A.key_in, A.idx_in, A.key_out, A.idx_out, A.n_live, A.shift, A.ghist, A.status, A.ticket);
+}
+
 __global__ void __launch_bounds__(kThreads) k_radix_onesweep(const RadixOnesweepArgs *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
-    const RadixOnesweepArgs &A = args[batch_state(bm, blk, nblk)];
-    radix_onesweep_body(blk, nblk, A.key_in, A.idx_in, A.key_out, A.idx_out, A.n_live, A.shift, A.ghist, A.status, A.ticket);
+    k_radix_onesweep_entry(args[batch_state(bm, blk, nblk)], blk, nblk);
+}
+
+__global__ void __launch_bounds__(kThreads) k_radix_onesweep(const RadixOnesweepArgs A)
+{
+    k_radix_onesweep_entry(A, blockIdx.x, gridDim.x);
 }
 
 }  // namespace ccmc
