@@ -131,37 +131,33 @@ def run_leg(w: inputs.Workload, precision: str, steps: int, warmup: int, log, pr
     else:
         st, ngrow = grow(state, w, log)
         shift0 = 0.0
-    ctl = driver.ShiftControl(target=w.target_population, tau=w.tau, shift=shift0)
-    ctl.varying = True
-    ctl._anchor = 0
-    ctl.history = [st["n_total"]]
+    # population control from here on in the library's own step loop (ccmc_run): the shift
+    # varies from the first step, as driver.ShiftControl would once started at this N_tot
+    ctl = ccmc.ccmc_shift_control.new(w.target_population, shift=shift0, started_at=st["n_total"])
     nsel = driver.selections(st["n_total"])
-    for _ in range(warmup):
-        st = state.ccmc_step(w.tau, ctl.shift, nsel)
-        ctl.update(st["n_total"])
-        nsel = driver.selections(st["n_total"])
+
+    def run(k):
+        nonlocal st, nsel
+        out, nsel = state.ccmc_run(k, w.tau, ctl, nsel)
+        if k:
+            st = out[k - 1].as_dict()
+        return out
+
+    def totals(out, k):
+        return (sum(out[i].n_spawn_attempts for i in range(k)), sum(out[i].n_selections for i in range(k)),
+                sum(out[i].n_spawns for i in range(k)))
+
+    run(warmup)
     if save_state:
         keys, amps, n0, step = state.ccmc_export()
         np.savez(save_state, keys=keys, amps=amps, n_ref=n0, step=step, shift=ctl.shift)
-
-    def steps_(k):
-        nonlocal st, nsel
-        att = sel = sp = 0
-        for _ in range(k):
-            st = state.ccmc_step(w.tau, ctl.shift, nsel)
-            ctl.update(st["n_total"])
-            nsel = driver.selections(st["n_total"])
-            att += st["n_spawn_attempts"]
-            sel += st["n_selections"]
-            sp += st["n_spawns"]
-        return att, sel, sp
 
     # per-kernel breakdown: every launch timed with events (not the timed region)
     breakdown = {}
     dominant = None
     if profile:
         state.ccmc_profile("*")
-        steps_(min(steps, breakdown_steps))
+        run(min(steps, breakdown_steps))
         breakdown = state.ccmc_profile_read()
         state.ccmc_profile(None)
         dominant = max(breakdown.items(), key=lambda kv: kv[1]["ms"])[0]
@@ -171,8 +167,9 @@ def run_leg(w: inputs.Workload, precision: str, steps: int, warmup: int, log, pr
         state.ccmc_profile_read()
     ROCTX.resume()
     t0 = time.perf_counter()
-    attempts, selections, spawns = steps_(steps)
+    out = run(steps)
     elapsed = time.perf_counter() - t0
+    attempts, selections, spawns = totals(out, steps)
     ROCTX.pause()
     timed = state.ccmc_profile_read() if dominant else {}
     state.ccmc_profile(None)

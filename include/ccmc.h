@@ -155,6 +155,38 @@ ccmc_status ccmc_init(const ccmc_system *sys, const ccmc_integrals *ints, int tr
 ccmc_status ccmc_step(ccmc_state *st, double tau, double shift, uint64_t n_attempts,
                       ccmc_stats *out);
 
+/* Population control of a run of steps (the log-growth shift update the paper's method is used
+ * with; the paper cites it without a formula).  The shift stays fixed until N_tot first reaches
+ * `target`; from then on, every `period` steps, S <- S - damping / (period tau) *
+ * ln(N_tot(t) / N_tot(t - period)).  The struct carries the control's whole state, so runs can
+ * be chained; set varying = 0 and shift to the starting shift for a fresh control.
+ * 1 <= period <= 63. */
+typedef struct {
+    double target;
+    double damping;
+    int period;
+    int varying;       /* in/out: 1 once N_tot has reached target */
+    double shift;      /* in/out */
+    int since;         /* in/out: steps since the shift started to vary */
+    double n_hist[64]; /* in/out: N_tot of the last period + 1 steps since then, a ring */
+} ccmc_shift_control;
+
+/* The control's update after a step that ended with N_tot = n_total (host only, no device
+ * call): starts the control at the first n_total >= target, and at every period-th step after
+ * that moves the shift.  CCMC_EINVAL for a NULL control, a period outside [1, 63], tau <= 0
+ * or a non-positive or non-finite n_total. */
+ccmc_status ccmc_shift_update(ccmc_shift_control *ctl, double n_total, double tau);
+
+/* n_steps consecutive steps of one state in a native loop (no return to the caller in between):
+ * step i is ccmc_step(st, tau, ctl->shift, n, out + i) with n = *n_attempts for the first step
+ * and floor(N_tot + 1/2) of the step before for the others (Sec. IV.B: as many selections as
+ * the total amplitude), followed by ccmc_shift_update(ctl, N_tot, tau).  On return
+ * *n_attempts is the selection count of the next step and *n_done the number of steps taken;
+ * out (host, n_steps entries, may be NULL) receives each step's statistics.  Stops at the
+ * first failing step and returns its status (that step leaves the state unchanged). */
+ccmc_status ccmc_run(ccmc_state *st, int n_steps, double tau, ccmc_shift_control *ctl,
+                     uint64_t *n_attempts, ccmc_stats *out, int *n_done);
+
 /* Steps of n states in shared launches, for serving many solves at once: state i takes one
  * step exactly as ccmc_step(states[i], tau[i], shift[i], n_attempts[i], out + i) would alone
  * (each block of a launch works on one state's data with that state's Philox key), and

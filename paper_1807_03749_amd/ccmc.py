@@ -59,6 +59,23 @@ class ccmc_stats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ccmc_shift_control(C.Structure):
+    """The library's population control (``ccmc_shift_update``): the same rule as
+    ``driver.ShiftControl``, with its state held in the struct."""
+    _fields_ = [("target", C.c_double), ("damping", C.c_double), ("period", C.c_int), ("varying", C.c_int),
+                ("shift", C.c_double), ("since", C.c_int), ("n_hist", C.c_double * 64)]
+
+    @classmethod
+    def new(cls, target: float, shift: float = 0.0, damping: float = 0.05, period: int = 10,
+            started_at: float | None = None) -> "ccmc_shift_control":
+        """A fresh control; with `started_at` (an N_tot) it is already varying from that step."""
+        c = cls(target=target, damping=damping, period=period, varying=0, shift=shift, since=0)
+        if started_at is not None:
+            c.varying = 1
+            c.n_hist[0] = started_at
+        return c
+
+
 class ccmc_kernel_time(C.Structure):
     _fields_ = [("name", C.c_char * 40), ("launches", C.c_uint64), ("ms", C.c_double), ("bytes", C.c_double),
                 ("items", C.c_double)]
@@ -68,7 +85,7 @@ EXPORTED = ["ccmc_options_default", "ccmc_init", "ccmc_step", "ccmc_step_batch",
             "ccmc_last_error",
             "ccmc_export_size", "ccmc_export", "ccmc_import", "ccmc_spawns_size", "ccmc_export_spawns",
             "ccmc_profile", "ccmc_profile_read", "ccmc_dims", "ccmc_memory", "ccmc_set_budget",
-            "ccmc_codistribution"]
+            "ccmc_codistribution", "ccmc_shift_update", "ccmc_run"]
 
 _lib = None
 _u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
@@ -106,6 +123,9 @@ def lib():
             "ccmc_dims": (st, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
             "ccmc_codistribution": (st, [C.c_int, _u64p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _u64p,
                                          C.c_int, _u64p, _u64p]),
+            "ccmc_shift_update": (st, [C.POINTER(ccmc_shift_control), C.c_double, C.c_double]),
+            "ccmc_run": (st, [vp, C.c_int, C.c_double, C.POINTER(ccmc_shift_control), C.POINTER(C.c_uint64),
+                              C.POINTER(ccmc_stats), C.POINTER(C.c_int)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -184,6 +204,19 @@ class State:
         return out.as_dict()
 
     step = ccmc_step
+
+    def ccmc_run(self, n_steps: int, tau: float, ctl: ccmc_shift_control, n_attempts: int):
+        """`n_steps` steps in the library's own loop under the population control `ctl`
+        (updated in place).  Returns the per-step statistics (a ctypes array of ccmc_stats)
+        and the next step's selection count."""
+        out = (ccmc_stats * max(n_steps, 1))()
+        n = C.c_uint64(int(n_attempts))
+        done = C.c_int(0)
+        rc = lib().ccmc_run(self._h, int(n_steps), float(tau), C.byref(ctl), C.byref(n), out, C.byref(done))
+        self._check(rc)
+        return out, n.value
+
+    run = ccmc_run
 
     def ccmc_energy(self):
         e, n, d = C.c_double(), C.c_double(), C.c_double()
@@ -277,6 +310,14 @@ def ccmc_step_batch(states, tau, shift, n_attempts):
         err = lib().ccmc_last_error(hs[i]).decode()
         res.append(CCMCError(rc, err) if (rc != 0 and err) else outs[i].as_dict())
     return res
+
+
+def ccmc_shift_update(ctl: ccmc_shift_control, n_total: float, tau: float) -> float:
+    """The library's control update after a step ending at N_tot = n_total (host only)."""
+    rc = lib().ccmc_shift_update(C.byref(ctl), float(n_total), float(tau))
+    if rc != 0:
+        raise CCMCError(rc, "ccmc_shift_update: bad control or population")
+    return ctl.shift
 
 
 def ccmc_codistribution(keys, n_ranks: int, move_shift: int, hash_seed: int, checkpoints):

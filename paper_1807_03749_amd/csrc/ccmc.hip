@@ -1624,6 +1624,57 @@ ccmc_status ccmc_step(ccmc_state *st, double tau, double shift, uint64_t n_attem
     return dispatch<StepF>(st, sts, (size_t)1, &tau, &shift, &n_attempts, outs);
 }
 
+ccmc_status ccmc_shift_update(ccmc_shift_control *ctl, double n_total, double tau)
+{
+    if (!ctl || ctl->period < 1 || ctl->period > 63 || !(tau > 0) || !std::isfinite(tau) || !(n_total > 0) ||
+        !std::isfinite(n_total))
+        return CCMC_EINVAL;
+    const int ring = ctl->period + 1;
+    if (!ctl->varying) {
+        if (n_total < ctl->target) return CCMC_OK;
+        ctl->varying = 1;
+        ctl->since = 0;
+        ctl->n_hist[0] = n_total;
+        return CCMC_OK;
+    }
+    ctl->since += 1;
+    ctl->n_hist[ctl->since % ring] = n_total;
+    if (ctl->since % ctl->period == 0) {
+        const double prev = ctl->n_hist[(ctl->since - ctl->period) % ring];
+        ctl->shift -= ctl->damping / ((double)ctl->period * tau) * std::log(n_total / prev);
+    }
+    return CCMC_OK;
+}
+
+ccmc_status ccmc_run(ccmc_state *st, int n_steps, double tau, ccmc_shift_control *ctl, uint64_t *n_attempts,
+                     ccmc_stats *out, int *n_done)
+{
+    if (!st) return CCMC_EINVAL;
+    if (n_done) *n_done = 0;
+    if (!ctl || !n_attempts || n_steps < 0 || ctl->period < 1 || ctl->period > 63) {
+        st->err = "ccmc_run: need a control with period in [1, 63], n_attempts and n_steps >= 0";
+        return CCMC_EINVAL;
+    }
+    for (int i = 0; i < n_steps; ++i) {
+        ccmc_stats s;
+        const ccmc_status rc = ccmc_step(st, tau, ctl->shift, *n_attempts, &s);
+        if (rc != CCMC_OK) return rc;
+        if (out) out[i] = s;
+        if (n_done) *n_done = i + 1;
+        if (ccmc_shift_update(ctl, s.n_total, tau) != CCMC_OK) {
+            st->err = "ccmc_run: the population vanished or is not finite";
+            return CCMC_EINVAL;
+        }
+        const double next = std::floor(s.n_total + 0.5);
+        if (!(next < 4294967296.0)) {
+            st->err = "ccmc_run: the next step would need 2^32 or more selections";
+            return CCMC_EOVERFLOW;
+        }
+        *n_attempts = (uint64_t)next;
+    }
+    return CCMC_OK;
+}
+
 ccmc_status ccmc_step_batch(ccmc_state *const *states, int n, const double *tau, const double *shift,
                             const uint64_t *n_attempts, ccmc_stats *out)
 {
