@@ -691,6 +691,7 @@ ccmc_status plan_area(Plan<W, T> &p, int passes)
 // Argument tables of a batched step: per kernel, the states' argument structs and the
 // block map, staged in host memory and copied to the device in one transfer.
 struct ArgArena {
+    ccmc_state *now = nullptr;  // one state: each kernel is launched as soon as it is staged
     std::vector<uint8_t> host;
     size_t add(const void *src, size_t bytes)
     {
@@ -708,7 +709,6 @@ struct LaunchRec {
     uint32_t n;
     std::vector<Work> works;
     std::function<void(const void *, BatchMap, unsigned)> go;
-    std::function<void(unsigned)> go_one;  // one state: arguments by value
 };
 
 // Stage one batched kernel: per-state arguments and block counts (states with no blocks are
@@ -720,6 +720,12 @@ void stage(ArgArena &ar, std::vector<LaunchRec> &recs, const char *name, const s
     std::vector<uint32_t> off(blocks.size() + 1, 0);
     for (size_t i = 0; i < blocks.size(); ++i) off[i + 1] = off[i] + blocks[i];
     if (off.back() == 0) return;
+    static_assert(sizeof(A) <= 2048, "kernel arguments by value must stay well inside the 4 KB limit");
+    if (ar.now) {  // one state: launch now with the arguments by value, while the host stages the next
+        const A one = args[0];
+        launch(ar.now, name, works, [&] { kernel(one, off.back()); });
+        return;
+    }
     LaunchRec r;
     r.name = name;
     r.blocks = off.back();
@@ -728,11 +734,6 @@ void stage(ArgArena &ar, std::vector<LaunchRec> &recs, const char *name, const s
     r.n = (uint32_t)blocks.size();
     r.works = std::move(works);
     r.go = [kernel](const void *a, BatchMap bm, unsigned g) { kernel(static_cast<const A *>(a), g, bm); };
-    static_assert(sizeof(A) <= 2048, "kernel arguments by value must stay well inside the 4 KB limit");
-    if (args.size() == 1) {
-        const A one = args[0];
-        r.go_one = [kernel, one](unsigned g) { kernel(one, g); };
-    }
     recs.push_back(std::move(r));
 }
 
@@ -816,6 +817,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
     const double kb = (double)(W * 8);  // bytes of one bitstring
     const double tb = (double)sizeof(T);
     ArgArena ar;
+    ar.now = n == 1 ? lead : nullptr;
     std::vector<LaunchRec> recs;
     std::vector<uint32_t> blk(n);
     auto works = [&](auto f) {
@@ -1120,12 +1122,9 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
               [s](const auto &a, unsigned g, auto... bm) { k_final_part<<<g, kThreads, 0, s>>>(a, bm...); });
     }
 
-    // ---- one state: the launches in order, arguments by value
-    if (n == 1) {
-        for (auto &r : recs) launch(lead, r.name, r.works, [&] { r.go_one(r.blocks); });
-    } else {
-        TRY(launch_tables(lead, ar, recs, s));
-    }
+    // ---- a batch: the argument tables in one copy, then the launches (a single state has
+    // launched each kernel as it was staged)
+    if (n > 1) TRY(launch_tables(lead, ar, recs, s));
 
     // ---- (a14) the one synchronisation of the step: k_final_part writes each state's scalars into
     // pinned host memory and then the batch's sequence number; the host polls for it (and,
