@@ -110,6 +110,7 @@ struct ccmc_state {
     uint64_t slot_hint = 1 << 16, rec_hint = 1 << 14;  // capacities planned for the next step
     uint64_t cnt_slots = 0, cnt_rec = 0, cnt_merged = 0, cnt_new = 0, cnt_att = 0, cnt_live_items = 0;  // live counts of the last step
     DevBuf lb;  // step scalars, tickets, radix histograms and look-back status words
+    size_t lb_clean_bytes = 0;  // leading bytes of lb (and the fold sums) known to be zero
     // batched steps led by this state: argument tables and the batch's step scalars
     DevBuf arg_dev;
     uint8_t *arg_host = nullptr;  // pinned
@@ -682,7 +683,9 @@ ccmc_status plan_area(Plan<W, T> &p, int passes)
     p.o_pstat = p.o_pghist + kRadixBins / 2;
     p.o_fin = p.o_pstat + p.ptiles * kRadixBins;
     p.lb_words = p.o_fin + kMaxFinalParts * (sizeof(FinalPart) / 8);
+    const void *lb_was = st->lb.p;
     TRY(ensure(st, st->lb, p.lb_words * sizeof(uint64_t)));
+    if (st->lb.p != lb_was) st->lb_clean_bytes = 0;  // a new area holds no known contents
     p.lb = ptr<uint64_t>(st->lb);
     p.sc = reinterpret_cast<Scratch *>(p.lb);
     return CCMC_OK;
@@ -826,12 +829,15 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         return w;
     };
 
-    // ---- clear the step areas
+    // ---- clear the step areas (a single state's area was cleared at the end of its last step,
+    // unless the area has been reallocated since)
     {
         std::vector<ClearArgs> args;
         for (size_t i = 0; i < n; ++i) {
+            const bool clean = n == 1 && ps[i].st->lb_clean_bytes >= ps[i].lb_words * sizeof(uint64_t);
             args.push_back(ClearArgs{ps[i].lb, ps[i].lb_words, ptr<double>(ps[i].st->delta), ps[i].ne});
-            blk[i] = grid_for(ps[i].lb_words + ps[i].ne);
+            blk[i] = clean ? 0 : grid_for(ps[i].lb_words + ps[i].ne);
+            ps[i].st->lb_clean_bytes = 0;
         }
         stage(ar, recs, "clear", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.lb_words + p.ne}; }),
               [s](const auto &a, unsigned g, auto... bm) { k_clear<<<g, kThreads, 0, s>>>(a, bm...); });
@@ -1120,6 +1126,17 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         }
         stage(ar, recs, "final", args, blk, works([&](auto &) { return Work{0.0, nullptr, 0}; }),
               [s](const auto &a, unsigned g, auto... bm) { k_final_part<<<g, kThreads, 0, s>>>(a, bm...); });
+    }
+    // ---- a single state clears its whole area and fold sums for the next step now, while the
+    // host reads this step's scalars and plans the next one (the scalars went to host memory)
+    if (n == 1) {
+        ccmc_state *const one = ps[0].st;
+        const uint64_t words = one->lb.bytes / sizeof(uint64_t);
+        const std::vector<ClearArgs> args{ClearArgs{ps[0].lb, words, ptr<double>(one->delta), one->scap}};
+        const std::vector<uint32_t> b1{(uint32_t)grid_for(words + one->scap)};
+        stage(ar, recs, "clear", args, b1, std::vector<Work>{Work{8.0, nullptr, words + one->scap}},
+              [s](const auto &a, unsigned g, auto... bm) { k_clear<<<g, kThreads, 0, s>>>(a, bm...); });
+        one->lb_clean_bytes = words * sizeof(uint64_t);
     }
 
     // ---- a batch: the argument tables in one copy, then the launches (a single state has
