@@ -94,3 +94,27 @@ def test_batch_failure_is_per_state():
     assert isinstance(res[1], ccmc.CCMCError) and res[1].status == -3
     after = bad.ccmc_export()
     assert np.array_equal(before[0], after[0]) and before[2] == after[2] and before[3] == after[3]
+
+
+def test_alternating_alone_and_batched_steps():
+    """A solve stepped alone, then in batches, then alone again (each path clears its step
+    area in its own way) follows, step by step, the same solve stepped alone throughout."""
+    cfg, tau = SOLVES[1], TAU[1]
+    a, b, partner = _make(cfg), _make(cfg), _make(SOLVES[0])
+    na = nb = npart = driver.selections(cfg["init_pop"])
+    plan = ["alone"] * 3 + ["batch"] * 3 + ["alone"] * 4 + ["batch"] * 2 + ["alone"] * 3
+    for t, how in enumerate(plan):
+        ra = b.ccmc_step(tau, 0.0, nb)
+        if how == "alone":
+            rb = a.ccmc_step(tau, 0.0, na)
+        else:
+            rb, rp = ccmc.ccmc_step_batch([a, partner], [tau, TAU[0]], [0.0, 0.0], [na, npart])
+            assert isinstance(rp, dict), rp
+            npart = driver.selections(rp["n_total"])
+        assert isinstance(rb, dict), rb
+        assert ra == rb, (t, how, ra, rb)
+        na, nb = driver.selections(rb["n_total"]), driver.selections(ra["n_total"])
+    ka, aa, ra_, sa = a.ccmc_export()
+    kb, ab, rb_, sb = b.ccmc_export()
+    assert sa == sb == len(plan) and np.array_equal(ka, kb) and np.array_equal(aa, ab) and ra_ == rb_
+    _say(f"[batch] alternating alone/batched: {len(ka)} excitors identical after {len(plan)} steps")
