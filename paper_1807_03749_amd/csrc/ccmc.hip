@@ -249,7 +249,7 @@ void resolve_profile(ccmc_state *st)
 
 // --------------------------------------------------------------------------- scan
 // Tiles of a single-launch look-back scan of n values.
-uint64_t scan_tiles(uint64_t n) { return (n + kScanTile - 1) / kScanTile; }
+uint64_t scan_tiles(uint64_t n, int items = kScanItems) { return (n + (uint64_t)kThreads * items - 1) / ((uint64_t)kThreads * items); }
 
 // ------------------------------------------------------------------------ systems
 int words_for(int M) { return (M + 63) / 64; }
@@ -958,7 +958,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             args.push_back(A{CountSrc<uint64_t>{ptr<uint64_t>(st->icnt), p.n_items},
                              SlotOut{ptr<uint64_t>(st->ioff), ptr<uint64_t>(st->block_item), p.slot_cap}, p.n_items + 1, 0,
                              p.lb + p.o_off, p.lb + p.o_tick + kTkOff, &p.sc->n_slots});
-            blk[i] = (uint32_t)scan_tiles(p.n_items + 1);
+            blk[i] = (uint32_t)scan_tiles(p.n_items + 1, SlotOut::kItems);
         }
         stage(ar, recs, "slot_scan", args, blk, works([&](auto &p) { return Work{16.0, nullptr, p.n_items + 1}; }),
               [s](const auto &a, unsigned g, auto... bm) { k_scan_lb<uint64_t, CountSrc<uint64_t>, SlotOut><<<g, kThreads, 0, s>>>(a, bm...); });

@@ -191,26 +191,29 @@ __device__ __forceinline__ void wave_fill_ranges(D *__restrict__ dst, uint64_t b
 // value (called by every lane, in lockstep over the lane's items).
 template <typename V>
 struct ArrayOut {
+    static constexpr int kItems = kScanItems;  // items per thread of the scan that writes it
     V *p;
     __device__ __forceinline__ void item(uint64_t, V, V, bool) const {}
 };
 
-// Single-launch scan of n values (n_tiles = ceil(n / kScanTile) blocks); the grand total
-// goes to *total when given.
+// Single-launch scan of n values (n_tiles = ceil(n / tile) blocks, tile = 256 Out::kItems
+// values); the grand total goes to *total when given.
 template <typename V, typename Src, typename Out>
 __device__ __forceinline__ void scan_lb_body(uint32_t blk, uint32_t nblk, Src in, Out out, uint64_t n, int inclusive,
                                                       uint64_t *__restrict__ status, uint64_t *__restrict__ ticket,
                                                       uint64_t *__restrict__ total)
 {
-    __shared__ V buf[kScanTile];
+    constexpr int kItems = Out::kItems;
+    constexpr int kTile = kThreads * kItems;
+    __shared__ V buf[kTile];
     __shared__ uint64_t s_tile, s_prefix;
     if (threadIdx.x == 0) s_tile = atomicAdd((unsigned long long *)ticket, 1ull);
     __syncthreads();
     const uint64_t t = s_tile;
-    const uint64_t base = t * kScanTile;
-    V ld[kScanItems];
+    const uint64_t base = t * kTile;
+    V ld[kItems];
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
+    for (int i = 0; i < kItems; ++i) {
         // clamped index: the loads are unconditional and all in flight at once (a guarded
         // load is compiled into a branch that waits for it)
         const uint64_t g = base + (uint64_t)i * kThreads + threadIdx.x;
@@ -218,15 +221,15 @@ __device__ __forceinline__ void scan_lb_body(uint32_t blk, uint32_t nblk, Src in
         ld[i] = (g < n) ? v : V(0);
     }
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) in.check(ld[i]);
+    for (int i = 0; i < kItems; ++i) in.check(ld[i]);
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) buf[i * kThreads + threadIdx.x] = ld[i];
+    for (int i = 0; i < kItems; ++i) buf[i * kThreads + threadIdx.x] = ld[i];
     __syncthreads();
-    V loc[kScanItems];
+    V loc[kItems];
     V sum = 0;
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        loc[i] = buf[threadIdx.x * kScanItems + i];
+    for (int i = 0; i < kItems; ++i) {
+        loc[i] = buf[threadIdx.x * kItems + i];
         sum += loc[i];
     }
     V tile_total;
@@ -237,22 +240,22 @@ __device__ __forceinline__ void scan_lb_body(uint32_t blk, uint32_t nblk, Src in
         if (lane_id() == 0) {
             if (t > 0) lb_publish(&status[t], kLbInclusive, prefix + (uint64_t)tile_total);
             s_prefix = prefix;
-            if (total && base + kScanTile >= n) *total = prefix + (uint64_t)tile_total;
+            if (total && base + kTile >= n) *total = prefix + (uint64_t)tile_total;
         }
     }
     __syncthreads();
     V run = excl_in_tile + (V)s_prefix;
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
+    for (int i = 0; i < kItems; ++i) {
         const V x = loc[i];
-        const uint64_t g = base + (uint64_t)threadIdx.x * kScanItems + i;
+        const uint64_t g = base + (uint64_t)threadIdx.x * kItems + i;
         out.item(g, run, x, g < n);
-        buf[threadIdx.x * kScanItems + i] = inclusive ? run + x : run;
+        buf[threadIdx.x * kItems + i] = inclusive ? run + x : run;
         run += x;
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
+    for (int i = 0; i < kItems; ++i) {
         const uint64_t g = base + (uint64_t)i * kThreads + threadIdx.x;
         if (g < n) out.p[g] = buf[i * kThreads + threadIdx.x];
     }
