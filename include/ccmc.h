@@ -42,7 +42,9 @@ typedef enum {
     CCMC_EOVERFLOW = -3, /* a count exceeded a field width (e.g. > 2^30-2 attempts on one
                             cluster, > 2^32-1 selections); the step was rolled back */
     CCMC_EDEVICE = -4,   /* HIP runtime error */
-    CCMC_EBLOWUP = -5    /* population beyond the fixed-point range of the selection weights */
+    CCMC_EBLOWUP = -5    /* population beyond the fixed-point range of the selection weights, or
+                            (with ccmc_options.blowup_factor > 0) a step that multiplied N_tot by
+                            more than that factor; the step was rolled back */
 } ccmc_status;
 
 enum { CCMC_UEG = 1, CCMC_MOLECULAR = 2 };
@@ -79,7 +81,7 @@ typedef struct {
 /* Sampling options.  Defaults (ccmc_options_default): FP64, original selection, k_min 1,
  * multi-spawn off, non-composite threshold 1, spawn cutoff 0.01, occupation threshold 1,
  * init_pop 10, p_single 0.1, seed 1234, no budget, default stream, no spawn ids, one
- * processor (n_ranks 1, move_shift 5, hash_seed 0). */
+ * processor (n_ranks 1, move_shift 5, hash_seed 0), no growth bound (blowup_factor 0). */
 typedef struct {
     int precision;                 /* CCMC_FP64 or CCMC_FP32 (amplitudes, spawns, integrals) */
     int full_noncomposite;         /* 1: full non-composite sampling (Sec. IV.B) */
@@ -105,6 +107,11 @@ typedef struct {
     uint32_t n_ranks;
     uint32_t move_shift;
     uint32_t hash_seed;
+    /* Blow-up detector (Sec. IV.A: runs below the shoulder population can blow up): a step
+     * whose N_tot after the step exceeds blowup_factor times N_tot before it is rolled back
+     * and fails with CCMC_EBLOWUP (state unchanged).  <= 0: off.  N_tot before the first step
+     * is |init_pop|, after an import |N_0| + sum |N_i| of the imported store. */
+    double blowup_factor;
 } ccmc_options;
 
 typedef struct {
@@ -120,6 +127,12 @@ typedef struct {
     double n_ref;                      /* N_0 after the step (FP64) */
     double eproj_num;                  /* sum over sampled clusters of <D_HF|H|D_c> s_D(c) A (FP64) */
     double eproj_den;                  /* N_0 before the step (FP64) */
+    double ms;                         /* host wall time of the call that took the step, in ms
+                                          (for ccmc_step_batch: of the whole batch) */
+    int32_t status;                    /* this state's outcome: CCMC_OK, or the failure that left
+                                          it unchanged (ccmc_step_batch reports each state's own);
+                                          on failure the other fields are zero */
+    int32_t reserved;
 } ccmc_stats;
 
 /* Per-kernel timing collected with HIP events on the state's stream (ccmc_profile). */

@@ -2,6 +2,9 @@
 
 Flags: -ffp-contract=off keeps the FP64 arithmetic in the order the parity tests assume
 (no fused multiply-add), and the packed-FP32 feature is switched off for all device code.
+hipcc's host pass warns that it does not know that feature ("not a recognized feature for
+this target"); the gfx950 device pass takes it, and tests/test_build_flags.py checks the
+device assembly for packed FP32 instructions.
 """
 from __future__ import annotations
 

@@ -46,14 +46,15 @@ class ccmc_options(C.Structure):
                 ("spawn_cutoff", C.c_double), ("occupation_threshold", C.c_double), ("init_pop", C.c_double),
                 ("p_single", C.c_double), ("seed", C.c_uint64), ("hbm_budget_bytes", C.c_uint64),
                 ("hip_stream", C.c_void_p), ("keep_spawn_ids", C.c_int), ("n_ranks", C.c_uint32),
-                ("move_shift", C.c_uint32), ("hash_seed", C.c_uint32)]
+                ("move_shift", C.c_uint32), ("hash_seed", C.c_uint32), ("blowup_factor", C.c_double)]
 
 
 class ccmc_stats(C.Structure):
     _fields_ = [("step", C.c_uint64), ("n_selections", C.c_uint64), ("n_discarded", C.c_uint64),
                 ("n_spawn_attempts", C.c_uint64), ("n_spawns", C.c_uint64), ("n_deaths", C.c_uint64),
                 ("n_excitors", C.c_uint64), ("max_attempts_per_cluster", C.c_uint64), ("n_total", C.c_double),
-                ("n_ref", C.c_double), ("eproj_num", C.c_double), ("eproj_den", C.c_double)]
+                ("n_ref", C.c_double), ("eproj_num", C.c_double), ("eproj_den", C.c_double), ("ms", C.c_double),
+                ("status", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -307,8 +308,8 @@ def ccmc_step_batch(states, tau, shift, n_attempts):
                         "ccmc_step_batch: invalid arguments")
     res = []
     for i, st in enumerate(states):
-        err = lib().ccmc_last_error(hs[i]).decode()
-        res.append(CCMCError(rc, err) if (rc != 0 and err) else outs[i].as_dict())
+        own = outs[i].status  # each state's own outcome
+        res.append(CCMCError(own, lib().ccmc_last_error(hs[i]).decode()) if own != 0 else outs[i].as_dict())
     return res
 
 

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -90,6 +91,7 @@ struct ccmc_state {
     int cur = 0;
     uint64_t ne = 0;
     double n0 = 0;
+    double last_ntot = 0;  // N_tot after the last step (or at init / import): the blow-up bound's base
     uint64_t step = 0;
     double last_num = 0, last_den = 0;
     // per-step buffers
@@ -1191,7 +1193,22 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             continue;
         }
         const double n0_old = st->n0;
-        if (scr.hf_hit) st->n0 = st->n0 + scr.hf_sum;
+        const double n0_new = scr.hf_hit ? st->n0 + scr.hf_sum : st->n0;
+        const double ntot_new = scr.n_total + std::fabs(n0_new);
+        if (st->opt.blowup_factor > 0 && st->last_ntot > 0 && !(ntot_new <= st->opt.blowup_factor * st->last_ntot)) {
+            // the growth bound: the merged store is left unused, so the state stays as it was
+            if (p.ne) k_fill<double><<<grid_for(p.ne), kThreads, 0, s>>>(ptr<double>(st->delta), p.ne, 0.0);
+            HIP_TRY(hipStreamSynchronize(s));
+            char msg[160];
+            std::snprintf(msg, sizeof msg, "blow-up: the step took N_tot from %.6g to %.6g, above %.6g times", st->last_ntot,
+                          ntot_new, st->opt.blowup_factor);
+            st->err = msg;
+            st->last_rec_buf = -1;
+            src[i]->rc = CCMC_EBLOWUP;
+            continue;
+        }
+        st->n0 = n0_new;
+        st->last_ntot = ntot_new;
         st->ne = scr.n_out;
         st->cur = 1 - p.c;  // the merged store was written into the other buffer
         st->step += 1;
@@ -1201,6 +1218,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
         st->last_rec_buf = p.ids ? 1 : -1;
         if (p.out) {
             ccmc_stats *out = p.out;
+            *out = ccmc_stats{};
             out->step = st->step;
             out->n_selections = p.n_sel;
             out->n_discarded = scr.n_discarded;
@@ -1209,7 +1227,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             out->n_deaths = scr.n_deaths;
             out->n_excitors = st->ne;
             out->max_attempts_per_cluster = scr.max_n;
-            out->n_total = scr.n_total + std::fabs(st->n0);
+            out->n_total = ntot_new;
             out->n_ref = st->n0;
             out->eproj_num = scr.num;
             out->eproj_den = n0_old;
@@ -1227,6 +1245,7 @@ template <int W, typename T>
 ccmc_status step_impl(ccmc_state *const *sts, size_t n, const double *tau, const double *shift, const uint64_t *n_sel,
                       ccmc_stats *const *outs)
 {
+    const auto t0 = std::chrono::steady_clock::now();
     std::vector<Plan<W, T>> ps(n);
     std::vector<Plan<W, T> *> live;
     for (size_t i = 0; i < n; ++i) {
@@ -1245,15 +1264,30 @@ ccmc_status step_impl(ccmc_state *const *sts, size_t n, const double *tau, const
             }
             break;
         }
-        TRY(step_batch_once<W, T>(live));
+        const ccmc_status rb = step_batch_once<W, T>(live);
+        if (rb != CCMC_OK) {  // a HIP failure of the shared launches: every state still in the batch fails
+            for (auto *p : live) {
+                if (p->st != live[0]->st) p->st->err = live[0]->st->err;
+                p->rc = rb;
+            }
+            break;
+        }
         std::vector<Plan<W, T> *> again;
         for (auto *p : live)
             if (p->rc == CCMC_OK && p->replay) again.push_back(p);
         live.swap(again);
     }
-    for (auto &p : ps)
-        if (p.rc != CCMC_OK) return p.rc;
-    return CCMC_OK;
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    ccmc_status first = CCMC_OK;
+    for (auto &p : ps) {
+        if (p.out) {
+            if (p.rc != CCMC_OK) *p.out = ccmc_stats{};
+            p.out->ms = ms;
+            p.out->status = p.rc;
+        }
+        if (p.rc != CCMC_OK && first == CCMC_OK) first = p.rc;
+    }
+    return first;
 }
 
 template <int W, typename T>
@@ -1319,6 +1353,11 @@ ccmc_status import_impl(ccmc_state *st, const uint64_t *keys, const double *amps
     }
     st->ne = n;
     st->n0 = n_ref;
+    {
+        double tot = std::fabs(n_ref);
+        for (uint64_t i = 0; i < n; ++i) tot += std::fabs(amps[i]);
+        st->last_ntot = tot;
+    }
     st->step = step;
     st->last_q = 0;
     st->last_rec_buf = -1;
@@ -1570,6 +1609,10 @@ ccmc_status ccmc_init(const ccmc_system *sys, const ccmc_integrals *ints, int tr
         g_init_error = "ccmc_init: invalid sampling options";
         return CCMC_EINVAL;
     }
+    if (!(opt->blowup_factor <= 0 || (opt->blowup_factor > 1 && std::isfinite(opt->blowup_factor)))) {
+        g_init_error = "ccmc_init: blowup_factor must be <= 0 (off) or a finite factor above 1";
+        return CCMC_EINVAL;
+    }
     if (opt->n_ranks > kMaxRanks) {
         g_init_error = "ccmc_init: n_ranks above 512";
         return CCMC_EINVAL;
@@ -1619,6 +1662,7 @@ ccmc_status ccmc_init(const ccmc_system *sys, const ccmc_integrals *ints, int tr
         return rc;
     }
     st->n0 = opt->init_pop;
+    st->last_ntot = std::fabs(opt->init_pop);
     *out = st;
     return CCMC_OK;
 }
@@ -1672,7 +1716,7 @@ ccmc_status ccmc_run(ccmc_state *st, int n_steps, double tau, ccmc_shift_control
         return CCMC_EINVAL;
     }
     for (int i = 0; i < n_steps; ++i) {
-        ccmc_stats s;
+        ccmc_stats s{};
         const ccmc_status rc = ccmc_step(st, tau, ctl->shift, *n_attempts, &s);
         if (rc != CCMC_OK) return rc;
         if (out) out[i] = s;

@@ -573,7 +573,9 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
             // t_HF^(1-s) prod t_i with that sign (a sign flip is exact in either order)
             const int sigma = ((e & 1) ? -1 : 1) * excitor_sign<W>(S, d);
             const T Ac = (s == 0) ? (T)n0 : (sigma < 0 ? -prod : prod);
-            A = Ac / (T)p;
+            // p is formed in FP64 and can fall below the FP32 range at large populations
+            // (n_sel p_size s! prod q_i/Q): divide in FP64, then round to T
+            A = (T)((double)Ac / p);
             n = attempt_count<T>(A, a.thr_cluster, a.kmin, &sc->err);
             cnt = (uint64_t)n + 1;
             if (L <= S.l) death = -(T)a.tau * (diagonal<W, T>(S, d) - (T)a.shift) * A;

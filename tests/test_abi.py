@@ -50,3 +50,34 @@ def test_library_has_no_oracle_dependency():
                  "paper_1807_03749_amd/csrc/primitives.h"):
         txt = open(os.path.join(ROOT, path)).read()
         assert "oracle" not in txt.lower().replace("oracle_", ""), path
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes structures of the binding have the sizes and field offsets that a C compiler
+    gives the header's structures (a field added on one side only would shift the others)."""
+    import shutil
+    import subprocess
+
+    from paper_1807_03749_amd import ccmc
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"ccmc_system": ccmc.ccmc_system, "ccmc_integrals": ccmc.ccmc_integrals,
+               "ccmc_options": ccmc.ccmc_options, "ccmc_stats": ccmc.ccmc_stats,
+               "ccmc_shift_control": ccmc.ccmc_shift_control, "ccmc_kernel_time": ccmc.ccmc_kernel_time}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ccmc.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln.strip()}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)

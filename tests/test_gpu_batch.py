@@ -61,6 +61,11 @@ def _drive(states, starts, steps, batched):
     return [s_.ccmc_export() for s_ in states]
 
 
+def _no_time(stats: dict) -> dict:
+    """Step statistics without the wall time of the call (which differs run to run)."""
+    return {k: v for k, v in stats.items() if k != "ms"}
+
+
 def test_batch_equals_alone():
     starts = [0, 3, 5, 1, 8, 2, 6]
     alone = _drive([_make(c) for c in SOLVES], starts, 25, batched=False)
@@ -112,7 +117,7 @@ def test_alternating_alone_and_batched_steps():
             assert isinstance(rp, dict), rp
             npart = driver.selections(rp["n_total"])
         assert isinstance(rb, dict), rb
-        assert ra == rb, (t, how, ra, rb)
+        assert _no_time(ra) == _no_time(rb), (t, how, ra, rb)
         na, nb = driver.selections(rb["n_total"]), driver.selections(ra["n_total"])
     ka, aa, ra_, sa = a.ccmc_export()
     kb, ab, rb_, sb = b.ccmc_export()

@@ -49,6 +49,7 @@ def test_run_matches_python_loop(chunks):
         out, nsel = b.ccmc_run(k, TAU, c, nsel)
         got += [out[i].as_dict() for i in range(k)]
     for t, (x, y) in enumerate(zip(ref, got)):
+        x, y = ({k: v for k, v in z.items() if k != "ms"} for z in (x, y))  # the call's wall time differs
         assert x == y, (t, x, y)
     assert nsel == nsel_py and c.shift == py_ctl.shift and bool(c.varying)
     ka, aa, na, sa = a.ccmc_export()

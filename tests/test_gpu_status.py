@@ -1,0 +1,82 @@
+"""Step statistics carry the call's wall time and each state's own outcome; the growth bound
+(blow-up detector) rolls a step back and leaves the state exactly as it was; a batch reports
+every state's own failure."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1807_03749_amd import ccmc, driver
+
+pytestmark = pytest.mark.gpu
+
+TAU = 0.05  # a large time step: the population grows fast from the reference
+EBLOWUP, ENOMEM = -5, -2
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _state(**kw):
+    opts = dict(init_pop=50.0, seed=77)
+    opts.update(kw)
+    return ccmc.State("ueg", 14, 2, n2_max=2, rs=1.0, **opts)
+
+
+def test_stats_carry_time_and_status():
+    _say("[status] UEG 14e/38so CCSD, one step")
+    s = _state()
+    st = s.ccmc_step(TAU, 0.0, 50)
+    assert st["status"] == 0 and st["ms"] > 0.0
+    s.close()
+
+
+def test_growth_bound_rolls_back_and_matches_an_unbounded_run():
+    _say("[status] growth bound 1.3 against an unbounded twin")
+    free = _state()
+    bound = _state(blowup_factor=1.3)
+    nsel, prev = 50, 50.0
+    failed = False
+    for it in range(300):
+        ref = free.ccmc_step(TAU, 0.0, nsel)
+        before = bound.ccmc_export()
+        try:
+            got = bound.ccmc_step(TAU, 0.0, nsel)
+        except ccmc.CCMCError as e:
+            assert e.status == EBLOWUP, e
+            # the unbounded twin shows the growth that tripped the bound
+            assert ref["n_total"] > 1.3 * prev
+            after = bound.ccmc_export()
+            assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+            assert before[2] == after[2] and before[3] == after[3]
+            failed = True
+            break
+        for f in ("n_total", "n_ref", "n_excitors", "n_spawn_attempts", "eproj_num"):
+            assert got[f] == ref[f], (it, f)
+        assert ref["n_total"] <= 1.3 * prev
+        prev = ref["n_total"]
+        nsel = driver.selections(ref["n_total"])
+    assert failed, "the population never grew by 30% in one step"
+    free.close()
+    bound.close()
+
+
+def test_batch_reports_each_states_own_failure():
+    _say("[status] batch: blow-up, out of budget, success")
+    a = _state(blowup_factor=1.0001)  # any growth on the first step trips it
+    b = _state()
+    b.ccmc_set_budget(b.ccmc_memory() + 4096)  # no room for the step's buffers
+    c = _state()
+    ka = a.ccmc_export()
+    res = ccmc.ccmc_step_batch([a, b, c], [TAU] * 3, [0.0] * 3, [50] * 3)
+    assert isinstance(res[0], ccmc.CCMCError) and res[0].status == EBLOWUP, res[0]
+    assert isinstance(res[1], ccmc.CCMCError) and res[1].status == ENOMEM, res[1]
+    assert isinstance(res[2], dict) and res[2]["status"] == 0 and res[2]["step"] == 1
+    kb = a.ccmc_export()
+    assert kb[3] == ka[3] and len(kb[1]) == len(ka[1])
+    for s in (a, b, c):
+        s.close()
