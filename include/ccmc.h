@@ -168,6 +168,23 @@ ccmc_status ccmc_init(const ccmc_system *sys, const ccmc_integrals *ints, int tr
 ccmc_status ccmc_step(ccmc_state *st, double tau, double shift, uint64_t n_attempts,
                       ccmc_stats *out);
 
+/* The same step as ccmc_step, for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): it calls no hipMalloc, hipFree,
+ * hipHostMalloc or other allocating routine.  The step's zeroed area -- the step scalars,
+ * scan tickets, look-back status words, radix histograms, fold tile summaries and the first
+ * stage of the final reduction -- lives in a fixed device array of CCMC_NOALLOC_AREA_BYTES
+ * (16 MiB) per GPU, which each GPU holds until the process ends; every other buffer is the
+ * state's own, sized by earlier ccmc_step calls (or ccmc_import) and never grown here.
+ * Results are those of ccmc_step (same kernels, same Philox counters).
+ * Errors (state unchanged): CCMC_ENOMEM when the step needs a larger buffer than the state
+ * holds -- planned from its earlier steps, or found on the device when a count exceeds the
+ * planned capacity -- or a step area above the array's size (step once with ccmc_step to
+ * reserve, then retry), and the other errors of ccmc_step.  The array is shared by every call on its GPU and keeps the last
+ * call's contents (each call clears the part it uses): calls that overlap in time on one GPU,
+ * e.g. from two host threads, race.  Profiling (ccmc_profile) is ignored by this call. */
+#define CCMC_NOALLOC_AREA_BYTES (16u << 20)
+ccmc_status ccmc_step_noalloc(ccmc_state *st, double tau, double shift, uint64_t n_attempts, ccmc_stats *out);
+
 /* Population control of a run of steps (the log-growth shift update the paper's method is used
  * with; the paper cites it without a formula).  The shift stays fixed until N_tot first reaches
  * `target`; from then on, every `period` steps, S <- S - damping / (period tau) *

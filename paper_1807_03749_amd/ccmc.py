@@ -82,7 +82,7 @@ class ccmc_kernel_time(C.Structure):
                 ("items", C.c_double)]
 
 
-EXPORTED = ["ccmc_options_default", "ccmc_init", "ccmc_step", "ccmc_step_batch", "ccmc_energy", "ccmc_free",
+EXPORTED = ["ccmc_options_default", "ccmc_init", "ccmc_step", "ccmc_step_noalloc", "ccmc_step_batch", "ccmc_energy", "ccmc_free",
             "ccmc_last_error",
             "ccmc_export_size", "ccmc_export", "ccmc_import", "ccmc_spawns_size", "ccmc_export_spawns",
             "ccmc_profile", "ccmc_profile_read", "ccmc_dims", "ccmc_memory", "ccmc_set_budget",
@@ -106,6 +106,7 @@ def lib():
             "ccmc_init": (st, [C.POINTER(ccmc_system), C.POINTER(ccmc_integrals), C.c_int, C.POINTER(ccmc_options),
                                C.POINTER(vp)]),
             "ccmc_step": (st, [vp, C.c_double, C.c_double, C.c_uint64, C.POINTER(ccmc_stats)]),
+            "ccmc_step_noalloc": (st, [vp, C.c_double, C.c_double, C.c_uint64, C.POINTER(ccmc_stats)]),
             "ccmc_step_batch": (st, [C.POINTER(vp), C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.POINTER(C.c_uint64), C.POINTER(ccmc_stats)]),
             "ccmc_energy": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -205,6 +206,13 @@ class State:
         return out.as_dict()
 
     step = ccmc_step
+
+    def ccmc_step_noalloc(self, tau: float, shift: float, n_attempts: int) -> dict:
+        """ccmc_step without any allocation: the step area is the GPU's fixed array and the
+        state's buffers must already be large enough (CCMC_ENOMEM otherwise)."""
+        out = ccmc_stats()
+        self._check(lib().ccmc_step_noalloc(self._h, float(tau), float(shift), int(n_attempts), C.byref(out)))
+        return out.as_dict()
 
     def ccmc_run(self, n_steps: int, tau: float, ctl: ccmc_shift_control, n_attempts: int):
         """`n_steps` steps in the library's own loop under the population control `ctl`

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,9 +21,50 @@
 
 using namespace ccmc;
 
+// The step area of ccmc_step_noalloc: a fixed device array, one copy per GPU, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the host it is only a
+// stand-in for the symbol); it uses the device address hipGetSymbolAddress gives for each GPU.
+static __device__ __align__(256) uint64_t scratch[CCMC_NOALLOC_AREA_BYTES / sizeof(uint64_t)];
+
 namespace {
 
 thread_local std::string g_init_error;
+
+// Device address of the fixed step area (`scratch`, above) on each GPU.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint64_t *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on GPU dev, looked up once per GPU with that GPU current.
+ccmc_status noalloc_area(int dev, uint64_t **out, std::string &err)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= kMaxDevices) {
+        err = "ccmc_init: device index beyond the no-allocation area table";
+        return CCMC_EDEVICE;
+    }
+    if (!g_scratch_dev[dev]) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) {
+            err = "ccmc_init: hipGetDevice failed";
+            return CCMC_EDEVICE;
+        }
+        if (cur != dev && hipSetDevice(dev) != hipSuccess) {
+            err = "ccmc_init: hipSetDevice failed";
+            return CCMC_EDEVICE;
+        }
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) {
+            err = std::string("ccmc_init: hipGetSymbolAddress of the no-allocation area failed: ") + hipGetErrorString(e);
+            return CCMC_EDEVICE;
+        }
+        g_scratch_dev[dev] = static_cast<uint64_t *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return CCMC_OK;
+}
 
 // ------------------------------------------------------------------ device buffers
 struct DevBuf {
@@ -125,6 +167,11 @@ struct ccmc_state {
     uint64_t last_nrec = 0;
     int last_rec_buf = -1;
     size_t bytes_held = 0;
+    // ccmc_step_noalloc: the GPU of the state's stream, that GPU's copy of the fixed step area,
+    // and the flag that turns every buffer growth of the call into CCMC_ENOMEM
+    int device = 0;
+    uint64_t *noalloc_area = nullptr;
+    bool no_grow = false;
     std::string err;
     bool prof = false;
     std::string prof_names;  // "*" or ",name,name,": the launches timed
@@ -153,6 +200,11 @@ namespace {
 ccmc_status ensure(ccmc_state *st, DevBuf &b, size_t bytes)
 {
     if (bytes <= b.bytes) return CCMC_OK;
+    if (st->no_grow) {
+        st->err = "ccmc_step_noalloc: the step needs a buffer of " + std::to_string(bytes) + " bytes where the state holds " +
+                  std::to_string(b.bytes) + "; step once with ccmc_step to reserve it";
+        return CCMC_ENOMEM;
+    }
     size_t nb = std::max<size_t>(bytes, 256);
     nb = std::max(nb, b.bytes + b.bytes / 2);
     if (st->opt.hbm_budget_bytes && st->bytes_held - b.bytes + nb > st->opt.hbm_budget_bytes) {
@@ -604,8 +656,22 @@ ccmc_status plan_sizes(Plan<W, T> &p)
         a.gsh = sh;
     }
     p.slot_cap = std::max<uint64_t>(kGenSlots, (st->slot_hint + kGenSlots - 1) / kGenSlots * kGenSlots);
-    p.nblk_cap = p.slot_cap / kGenSlots;
     p.rec_cap = std::max<uint64_t>(1, std::min<uint64_t>(st->rec_hint, p.slot_cap));
+    if (st->no_grow) {
+        // ccmc_step_noalloc: the capacities are what the state's buffers hold (a count beyond
+        // them is found on the device and fails the call); nothing is planned beyond them
+        const uint64_t slots_held = st->rcap / kGenSlots * kGenSlots;
+        const uint64_t abs_held = st->abs_part.bytes / sizeof(double);
+        const uint64_t merged_held = std::min<uint64_t>(st->scap ? st->scap - 1 : 0,
+                                                        abs_held ? (abs_held - 1) * kMergeTile : 0);
+        p.slot_cap = std::min(p.slot_cap, slots_held);
+        p.rec_cap = std::min({p.rec_cap, p.slot_cap, st->dcap ? st->dcap - 1 : 0, merged_held > ne ? merged_held - ne : 0});
+        if (p.slot_cap < kGenSlots || p.rec_cap < 1) {
+            st->err = "ccmc_step_noalloc: the state holds no record buffers for this step; step once with ccmc_step to reserve them";
+            return CCMC_ENOMEM;
+        }
+    }
+    p.nblk_cap = p.slot_cap / kGenSlots;
     if (p.slot_cap + ne + 1 >= (1ull << 32)) {
         st->err = "more than 2^32 record slots in one step";
         return CCMC_EOVERFLOW;
@@ -685,6 +751,16 @@ ccmc_status plan_area(Plan<W, T> &p, int passes)
     p.o_pstat = p.o_pghist + kRadixBins / 2;
     p.o_fin = p.o_pstat + p.ptiles * kRadixBins;
     p.lb_words = p.o_fin + kMaxFinalParts * (sizeof(FinalPart) / 8);
+    if (st->no_grow) {  // ccmc_step_noalloc: the GPU's fixed area, cleared by the step's first kernel
+        if (p.lb_words * sizeof(uint64_t) > CCMC_NOALLOC_AREA_BYTES) {
+            st->err = "ccmc_step_noalloc: the step area needs " + std::to_string(p.lb_words * sizeof(uint64_t)) +
+                      " bytes, above the fixed " + std::to_string((unsigned long long)CCMC_NOALLOC_AREA_BYTES);
+            return CCMC_ENOMEM;
+        }
+        p.lb = st->noalloc_area;
+        p.sc = reinterpret_cast<Scratch *>(p.lb);
+        return CCMC_OK;
+    }
     const void *lb_was = st->lb.p;
     TRY(ensure(st, st->lb, p.lb_words * sizeof(uint64_t)));
     if (st->lb.p != lb_was) st->lb_clean_bytes = 0;  // a new area holds no known contents
@@ -768,6 +844,28 @@ ccmc_status launch_tables(ccmc_state *st, const ArgArena &ar, std::vector<Launch
     return CCMC_OK;
 }
 
+// Pinned, coherent host memory for the step scalars of n states, which k_final_part writes.
+ccmc_status host_scalars(ccmc_state *lead, size_t n)
+{
+    if (lead->batch_hcap >= n) return CCMC_OK;
+    if (lead->no_grow) {
+        lead->err = "ccmc_step_noalloc: no pinned memory for the step scalars";
+        return CCMC_ENOMEM;
+    }
+    if (lead->batch_hscr) (void)hipHostFree(lead->batch_hscr);
+    lead->batch_hscr = lead->batch_hdev = nullptr;
+    lead->batch_hcap = 0;
+    if (hipHostMalloc((void **)&lead->batch_hscr, n * sizeof(Scratch), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void **)&lead->batch_hdev, lead->batch_hscr, 0) != hipSuccess) {
+        lead->err = "hipHostMalloc failed";
+        return CCMC_EDEVICE;
+    }
+    std::memset(lead->batch_hscr, 0, n * sizeof(Scratch));
+    lead->batch_hcap = n;
+    return CCMC_OK;
+}
+
 // One attempt at a step of every state in `ps` (same words and precision), in shared
 // launches.  Sizes produced on the device (record slots, records, new determinants,
 // survivors) are never read back in the middle: kernels read them from device memory, and
@@ -804,19 +902,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
             return CCMC_OK;
         }
     }
-    if (lead->batch_hcap < n) {
-        if (lead->batch_hscr) (void)hipHostFree(lead->batch_hscr);
-        lead->batch_hscr = lead->batch_hdev = nullptr;
-        lead->batch_hcap = 0;
-        if (hipHostMalloc((void **)&lead->batch_hscr, n * sizeof(Scratch), hipHostMallocMapped | hipHostMallocCoherent) !=
-                hipSuccess ||
-            hipHostGetDevicePointer((void **)&lead->batch_hdev, lead->batch_hscr, 0) != hipSuccess) {
-            lead->err = "hipHostMalloc failed";
-            return CCMC_EDEVICE;
-        }
-        std::memset(lead->batch_hscr, 0, n * sizeof(Scratch));
-        lead->batch_hcap = n;
-    }
+    TRY(host_scalars(lead, n));
     Scratch *scr_copy = lead->batch_hdev;
     const uint64_t seq = ++lead->batch_seq;
     const double kb = (double)(W * 8);  // bytes of one bitstring
@@ -836,7 +922,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
     {
         std::vector<ClearArgs> args;
         for (size_t i = 0; i < n; ++i) {
-            const bool clean = n == 1 && ps[i].st->lb_clean_bytes >= ps[i].lb_words * sizeof(uint64_t);
+            const bool clean = n == 1 && !ps[i].st->no_grow && ps[i].st->lb_clean_bytes >= ps[i].lb_words * sizeof(uint64_t);
             args.push_back(ClearArgs{ps[i].lb, ps[i].lb_words, ptr<double>(ps[i].st->delta), ps[i].ne});
             blk[i] = clean ? 0 : grid_for(ps[i].lb_words + ps[i].ne);
             ps[i].st->lb_clean_bytes = 0;
@@ -1131,7 +1217,7 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
     }
     // ---- a single state clears its whole area and fold sums for the next step now, while the
     // host reads this step's scalars and plans the next one (the scalars went to host memory)
-    if (n == 1) {
+    if (n == 1 && !ps[0].st->no_grow) {
         ccmc_state *const one = ps[0].st;
         const uint64_t words = one->lb.bytes / sizeof(uint64_t);
         const std::vector<ClearArgs> args{ClearArgs{ps[0].lb, words, ptr<double>(one->delta), one->scap}};
@@ -1273,8 +1359,16 @@ ccmc_status step_impl(ccmc_state *const *sts, size_t n, const double *tau, const
             break;
         }
         std::vector<Plan<W, T> *> again;
-        for (auto *p : live)
-            if (p->rc == CCMC_OK && p->replay) again.push_back(p);
+        for (auto *p : live) {
+            if (p->rc != CCMC_OK || !p->replay) continue;
+            if (p->st->no_grow) {  // ccmc_step_noalloc cannot grow the buffers a replay needs
+                p->st->err = "ccmc_step_noalloc: a count of the step exceeded the buffers the state holds; step once with "
+                             "ccmc_step to grow them";
+                p->rc = CCMC_ENOMEM;
+                continue;
+            }
+            again.push_back(p);
+        }
         live.swap(again);
     }
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1653,7 +1747,21 @@ ccmc_status ccmc_init(const ccmc_system *sys, const ccmc_integrals *ints, int tr
         }
         st->own_stream = true;
     }
-    ccmc_status rc = CCMC_OK;
+    {
+        int dev = 0;
+        if (hipStreamGetDevice(st->stream, &dev) != hipSuccess) {
+            (void)hipGetLastError();
+            if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        }
+        st->device = dev;
+        std::string e;
+        if (noalloc_area(dev, &st->noalloc_area, e) != CCMC_OK) {
+            g_init_error = e;
+            destroy(st);
+            return CCMC_EDEVICE;
+        }
+    }
+    ccmc_status rc = host_scalars(st, 1);
     if (rc == CCMC_OK) rc = dispatch<SystemF>(st, st, ints);
     if (rc == CCMC_OK) rc = dispatch<StoreF>(st, st, (uint64_t)1024);
     if (rc != CCMC_OK) {
@@ -1682,6 +1790,29 @@ ccmc_status ccmc_step(ccmc_state *st, double tau, double shift, uint64_t n_attem
     ccmc_state *const sts[1] = {st};
     ccmc_stats *const outs[1] = {out};
     return dispatch<StepF>(st, sts, (size_t)1, &tau, &shift, &n_attempts, outs);
+}
+
+ccmc_status ccmc_step_noalloc(ccmc_state *st, double tau, double shift, uint64_t n_attempts, ccmc_stats *out)
+{
+    if (!st) return CCMC_EINVAL;
+    if (!st->noalloc_area || st->batch_hcap < 1) {
+        st->err = "ccmc_step_noalloc: the state has no fixed step area";
+        return CCMC_EDEVICE;
+    }
+    // every buffer growth of this call fails instead of allocating; profiling (which takes
+    // events) is off for the call
+    struct Restore {
+        ccmc_state *s;
+        bool prof;
+        ~Restore()
+        {
+            s->no_grow = false;
+            s->prof = prof;
+        }
+    } restore{st, st->prof};
+    st->no_grow = true;
+    st->prof = false;
+    return ccmc_step(st, tau, shift, n_attempts, out);
 }
 
 ccmc_status ccmc_shift_update(ccmc_shift_control *ctl, double n_total, double tau)
