@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -872,8 +873,17 @@ ccmc_status host_scalars(ccmc_state *lead, size_t n)
 // grids cover capacities planned from each state's previous step.  If a count exceeds its
 // capacity, the overflow bit turns that state's final compaction into a no-op; the host
 // then grows its buffers and replays its step with the same Philox counters (replay[i]).
+// A batch whose launches are queued and whose scalars are still to be collected.
 template <int W, typename T>
-ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
+struct Launched {
+    std::vector<Plan<W, T>> ps;
+    std::vector<Plan<W, T> *> src;
+    ccmc_state *lead = nullptr;
+    uint64_t seq = 0;
+};
+
+template <int W, typename T>
+ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
 {
     // plan every state; a state that cannot be planned (no memory, too many slots) drops out
     // of the batch unchanged
@@ -1230,6 +1240,25 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
     // ---- a batch: the argument tables in one copy, then the launches (a single state has
     // launched each kernel as it was staged)
     if (n > 1) TRY(launch_tables(lead, ar, recs, s));
+    L.ps = std::move(ps);
+    L.src = std::move(src);
+    L.lead = lead;
+    L.seq = seq;
+    return CCMC_OK;
+}
+
+// Collect a launched batch: wait for its scalars, then commit (or roll back) each state.
+template <int W, typename T>
+ccmc_status batch_finish(Launched<W, T> &L)
+{
+    if (L.ps.empty()) return CCMC_OK;
+    auto &ps = L.ps;
+    auto &src = L.src;
+    const size_t n = ps.size();
+    ccmc_state *lead = L.lead;
+    ccmc_state *const st = lead;  // errors of the batch's HIP calls are reported on its first state
+    hipStream_t s = lead->stream;
+    const uint64_t seq = L.seq;
 
     // ---- (a14) the one synchronisation of the step: k_final_part writes each state's scalars into
     // pinned host memory and then the batch's sequence number; the host polls for it (and,
@@ -1323,65 +1352,104 @@ ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
     return CCMC_OK;
 }
 
-// Steps of several states (same words and precision) in shared launches; a state whose
-// capacities overflowed steps again, with the others that did, after growing.  A state whose
-// step fails is left unchanged with its error text set; the others complete their step.  The
-// first failure's status is returned.
+template <int W, typename T>
+ccmc_status step_batch_once(std::vector<Plan<W, T> *> &all)
+{
+    Launched<W, T> L;
+    TRY(batch_launch<W, T>(all, L));
+    return batch_finish<W, T>(L);
+}
+
+// Steps of several states (same words and precision) in shared launches, in two halves so
+// that the groups of one ccmc_step_batch call (one per words and precision) are all queued
+// before the host waits for any: launch() plans and queues the first attempt; complete()
+// collects it, then steps again, alone, the states whose capacities overflowed (after
+// growing).  A state whose step fails is left unchanged with its error text set; the others
+// complete their step.  complete() returns the first failure's status.
+struct GroupStep {
+    virtual ~GroupStep() = default;
+    virtual void launch() = 0;
+    virtual ccmc_status complete() = 0;
+};
+
+template <int W, typename T>
+struct GroupStepT final : GroupStep {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    std::vector<Plan<W, T>> ps;
+    std::vector<Plan<W, T> *> live;
+    Launched<W, T> L;
+    ccmc_status launch_rc = CCMC_OK;
+
+    GroupStepT(ccmc_state *const *sts, size_t n, const double *tau, const double *shift, const uint64_t *n_sel,
+               ccmc_stats *const *outs)
+        : ps(n)
+    {
+        for (size_t i = 0; i < n; ++i) {
+            ps[i].st = sts[i];
+            ps[i].tau = tau[i];
+            ps[i].shift = shift[i];
+            ps[i].n_sel = n_sel[i];
+            ps[i].out = outs ? outs[i] : nullptr;
+            live.push_back(&ps[i]);
+        }
+    }
+
+    void launch() override { launch_rc = batch_launch<W, T>(live, L); }
+
+    ccmc_status complete() override
+    {
+        ccmc_status rb = launch_rc == CCMC_OK ? batch_finish<W, T>(L) : launch_rc;
+        for (int attempt = 1;; ++attempt) {
+            if (rb != CCMC_OK) {  // a HIP failure of the shared launches: every state still in the batch fails
+                for (auto *p : live) {
+                    if (p->st != live[0]->st) p->st->err = live[0]->st->err;
+                    p->rc = rb;
+                }
+                break;
+            }
+            std::vector<Plan<W, T> *> again;
+            for (auto *p : live) {
+                if (p->rc != CCMC_OK || !p->replay) continue;
+                if (p->st->no_grow) {  // ccmc_step_noalloc cannot grow the buffers a replay needs
+                    p->st->err = "ccmc_step_noalloc: a count of the step exceeded the buffers the state holds; step once "
+                                 "with ccmc_step to grow them";
+                    p->rc = CCMC_ENOMEM;
+                    continue;
+                }
+                again.push_back(p);
+            }
+            live.swap(again);
+            if (live.empty()) break;
+            if (attempt == 8) {
+                for (auto *p : live) {
+                    p->st->err = "step capacity did not converge";
+                    p->rc = CCMC_ENOMEM;
+                }
+                break;
+            }
+            rb = step_batch_once<W, T>(live);
+        }
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        ccmc_status first = CCMC_OK;
+        for (auto &p : ps) {
+            if (p.out) {
+                if (p.rc != CCMC_OK) *p.out = ccmc_stats{};
+                p.out->ms = ms;
+                p.out->status = p.rc;
+            }
+            if (p.rc != CCMC_OK && first == CCMC_OK) first = p.rc;
+        }
+        return first;
+    }
+};
+
 template <int W, typename T>
 ccmc_status step_impl(ccmc_state *const *sts, size_t n, const double *tau, const double *shift, const uint64_t *n_sel,
                       ccmc_stats *const *outs)
 {
-    const auto t0 = std::chrono::steady_clock::now();
-    std::vector<Plan<W, T>> ps(n);
-    std::vector<Plan<W, T> *> live;
-    for (size_t i = 0; i < n; ++i) {
-        ps[i].st = sts[i];
-        ps[i].tau = tau[i];
-        ps[i].shift = shift[i];
-        ps[i].n_sel = n_sel[i];
-        ps[i].out = outs ? outs[i] : nullptr;
-        live.push_back(&ps[i]);
-    }
-    for (int attempt = 0; !live.empty(); ++attempt) {
-        if (attempt == 8) {
-            for (auto *p : live) {
-                p->st->err = "step capacity did not converge";
-                p->rc = CCMC_ENOMEM;
-            }
-            break;
-        }
-        const ccmc_status rb = step_batch_once<W, T>(live);
-        if (rb != CCMC_OK) {  // a HIP failure of the shared launches: every state still in the batch fails
-            for (auto *p : live) {
-                if (p->st != live[0]->st) p->st->err = live[0]->st->err;
-                p->rc = rb;
-            }
-            break;
-        }
-        std::vector<Plan<W, T> *> again;
-        for (auto *p : live) {
-            if (p->rc != CCMC_OK || !p->replay) continue;
-            if (p->st->no_grow) {  // ccmc_step_noalloc cannot grow the buffers a replay needs
-                p->st->err = "ccmc_step_noalloc: a count of the step exceeded the buffers the state holds; step once with "
-                             "ccmc_step to grow them";
-                p->rc = CCMC_ENOMEM;
-                continue;
-            }
-            again.push_back(p);
-        }
-        live.swap(again);
-    }
-    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    ccmc_status first = CCMC_OK;
-    for (auto &p : ps) {
-        if (p.out) {
-            if (p.rc != CCMC_OK) *p.out = ccmc_stats{};
-            p.out->ms = ms;
-            p.out->status = p.rc;
-        }
-        if (p.rc != CCMC_OK && first == CCMC_OK) first = p.rc;
-    }
-    return first;
+    GroupStepT<W, T> g(sts, n, tau, shift, n_sel, outs);
+    g.launch();
+    return g.complete();
 }
 
 template <int W, typename T>
@@ -1526,6 +1594,15 @@ struct StepF {
                            ccmc_stats *const *outs)
     {
         return step_impl<W, T>(sts, n, tau, shift, n_sel, outs);
+    }
+};
+template <int W, typename T>
+struct GroupF {
+    static ccmc_status run(std::unique_ptr<GroupStep> *out, ccmc_state *const *sts, size_t n, const double *tau,
+                           const double *shift, const uint64_t *n_sel, ccmc_stats *const *outs)
+    {
+        out->reset(new GroupStepT<W, T>(sts, n, tau, shift, n_sel, outs));
+        return CCMC_OK;
     }
 };
 template <int W, typename T>
@@ -1889,8 +1966,11 @@ ccmc_status ccmc_step_batch(ccmc_state *const *states, int n, const double *tau,
         }
     }
     // one batch per (words, precision); each runs on the stream of its first state, after the
-    // work already queued on the others' streams
+    // work already queued on the others' streams.  Every group is queued before the host
+    // waits for any, so groups on different streams run on the device together.
+    const auto t0 = std::chrono::steady_clock::now();
     std::vector<char> done(n, 0);
+    std::vector<std::unique_ptr<GroupStep>> groups;
     ccmc_status rc = CCMC_OK;
     for (int i = 0; i < n; ++i) {
         if (done[i]) continue;
@@ -1907,16 +1987,36 @@ ccmc_status ccmc_step_batch(ccmc_state *const *states, int n, const double *tau,
             ga.push_back(n_attempts[j]);
             go.push_back(out ? out + j : nullptr);
         }
-        for (size_t k = 1; k < g.size(); ++k) {
+        bool waits = true;
+        for (size_t k = 1; k < g.size() && waits; ++k) {
             if (g[k]->stream == g[0]->stream) continue;
             hipEvent_t ev;
-            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return CCMC_EDEVICE;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                waits = false;
+                break;
+            }
             (void)hipEventRecord(ev, g[k]->stream);
             (void)hipStreamWaitEvent(g[0]->stream, ev, 0);
             (void)hipEventDestroy(ev);
         }
-        const ccmc_status r = dispatch<StepF>(g[0], g.data(), g.size(), gt.data(), gs.data(), ga.data(), go.data());
+        std::unique_ptr<GroupStep> gp;
+        const ccmc_status r =
+            waits ? dispatch<GroupF>(g[0], &gp, g.data(), g.size(), gt.data(), gs.data(), ga.data(), go.data()) : CCMC_EDEVICE;
+        if (r != CCMC_OK || !gp) {  // this group and the ones after it do not step; the queued ones finish
+            rc = r != CCMC_OK ? r : CCMC_EINVAL;
+            for (ccmc_state *x : g) x->err = "ccmc_step_batch: the group of this state could not be queued";
+            break;
+        }
+        gp->launch();
+        groups.push_back(std::move(gp));
+    }
+    for (auto &gp : groups) {
+        const ccmc_status r = gp->complete();
         if (r != CCMC_OK && rc == CCMC_OK) rc = r;
+    }
+    if (out) {  // every state's statistics carry the wall time of the whole batch
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        for (int i = 0; i < n; ++i) out[i].ms = ms;
     }
     return rc;
 }

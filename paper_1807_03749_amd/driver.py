@@ -7,6 +7,7 @@ Computational Methods section (reblocking analysis of the stochastic error).
 """
 from __future__ import annotations
 
+import json
 import math
 from dataclasses import dataclass, field
 
@@ -36,6 +37,43 @@ class ShiftControl:
             prev = self.history[-1 - self.period]
             self.shift -= self.damping / (self.period * self.tau) * math.log(n_total / prev)
         return self.shift
+
+
+    def to_dict(self) -> dict:
+        d = dict(target=self.target, tau=self.tau, damping=self.damping, period=self.period, shift=self.shift,
+                 varying=self.varying, history=list(self.history))
+        if self.varying:
+            d["anchor"] = self._anchor
+        return d
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "ShiftControl":
+        c = cls(target=d["target"], tau=d["tau"], damping=d["damping"], period=d["period"], shift=d["shift"],
+                varying=d["varying"], history=list(d["history"]))
+        if c.varying:
+            c._anchor = d["anchor"]
+        return c
+
+
+@dataclass
+class Shoulder:
+    """The shoulder statistic of Sec. IV.A: the largest N_tot / N_0 of a run and the total
+    population where it occurred.  A run that has passed its shoulder shows a maximum that
+    stays put while N_tot grows; a run still below it (whose population control is unstable)
+    shows a ratio that keeps rising."""
+    ratio: float = 0.0
+    at: float = 0.0
+    last: float = 0.0
+
+    def update(self, n_total: float, n_ref: float) -> None:
+        if n_ref != 0.0:
+            self.last = n_total / abs(n_ref)
+            if self.last > self.ratio:
+                self.ratio, self.at = self.last, n_total
+
+    def as_dict(self) -> dict:
+        return dict(max_ntot_over_n0=self.ratio, at_ntot=self.at, last_ntot_over_n0=self.last,
+                    passed=bool(self.last < 0.9 * self.ratio))
 
 
 def selections(n_total: float) -> int:
@@ -116,6 +154,54 @@ def reweight(num: np.ndarray, den: np.ndarray, shift: np.ndarray, tau: float, me
     return out
 
 
+# ------------------------------------------------------------------ checkpoint / resume
+
+def _ctl_to_dict(ctl) -> dict:
+    if isinstance(ctl, ShiftControl):
+        return dict(kind="python", **ctl.to_dict())
+    # the library's native control (ccmc.ccmc_shift_control): its fields, ring included
+    return dict(kind="native", target=ctl.target, damping=ctl.damping, period=ctl.period, varying=ctl.varying,
+                shift=ctl.shift, since=ctl.since, n_hist=[float(x) for x in ctl.n_hist])
+
+
+def _ctl_from_dict(d: dict):
+    if d["kind"] == "python":
+        return ShiftControl.from_dict({k: v for k, v in d.items() if k != "kind"})
+    from . import ccmc
+    c = ccmc.ccmc_shift_control(target=d["target"], damping=d["damping"], period=d["period"], varying=d["varying"],
+                                shift=d["shift"], since=d["since"])
+    for i, x in enumerate(d["n_hist"]):
+        c.n_hist[i] = x
+    return c
+
+
+def save_checkpoint(path: str, state, ctl, nsel: int, series: dict | None = None) -> None:
+    """Everything a run needs to continue exactly (the paper restarts runs from checkpoints,
+    Sec. III.A): the excitor store (keys and amplitudes as FP64), N_0, the step index (which
+    keys every Philox counter of the next step), the population control's whole state, the
+    next step's selection count and the energy series recorded so far.  `state` is anything
+    with export_state() -> (keys, amps, n_ref, step)."""
+    keys, amps, n_ref, step = state.export_state()
+    arrays = {f"series_{k}": np.asarray(v) for k, v in (series or {}).items()}
+    np.savez(path, keys=keys, amps=amps, n_ref=np.float64(n_ref), step=np.uint64(step), nsel=np.uint64(nsel),
+             ctl=np.array(json.dumps(_ctl_to_dict(ctl))), **arrays)
+
+
+def load_checkpoint(path: str) -> dict:
+    with np.load(path, allow_pickle=False) as z:
+        out = dict(keys=z["keys"], amps=z["amps"], n_ref=float(z["n_ref"]), step=int(z["step"]), nsel=int(z["nsel"]),
+                   ctl=_ctl_from_dict(json.loads(str(z["ctl"]))),
+                   series={k[len("series_"):]: z[k] for k in z.files if k.startswith("series_")})
+    return out
+
+
+def resume(state, ckpt: dict):
+    """Load a checkpoint into `state` (import_state); returns (control, next selections,
+    series)."""
+    state.import_state(ckpt["keys"], ckpt["amps"], ckpt["n_ref"], ckpt["step"])
+    return ckpt["ctl"], ckpt["nsel"], {k: list(v) for k, v in ckpt["series"].items()}
+
+
 # -------------------------------------------------------------------------- run loop
 
 @dataclass
@@ -133,9 +219,11 @@ class RunResult:
 
 
 def run(state, tau: float, steps: int, target: float, equilibrate: int = 0, shift: ShiftControl | None = None,
-        first_selections: int | None = None, callback=None) -> RunResult:
+        first_selections: int | None = None, callback=None, jsonl=None) -> RunResult:
     """Propagate `state` (a ccmc.State) for `steps` steps with population control; the
-    projected-energy terms after `equilibrate` steps enter the reblocked estimate."""
+    projected-energy terms after `equilibrate` steps enter the reblocked estimate.  With
+    `jsonl` (a writable text file), every step's statistics and shift go to it as one JSON
+    line."""
     import time
 
     ctl = shift or ShiftControl(target=target, tau=tau)
@@ -152,6 +240,8 @@ def run(state, tau: float, steps: int, target: float, equilibrate: int = 0, shif
             res.den.append(st["eproj_den"])
         ctl.update(st["n_total"])
         nsel = selections(st["n_total"])
+        if jsonl is not None:
+            jsonl.write(json.dumps(dict(st, shift=ctl.shift)) + "\n")
         if callback:
             callback(it, st, ctl)
     res.seconds = time.perf_counter() - t0

@@ -16,6 +16,12 @@ whose population runs away beyond what one step can select (2^32 selections).
 Finished solves free their memory at once, so waiting requests join the running batch
 between two steps -- continuous batching, not a queue of whole runs.
 
+A solve whose population keeps growing after the shift has started to vary, to `runaway`
+times its target, is ended as diverged: its target lies below the population at which the
+walk stabilises (the shoulder of Sec. IV.A, whose height the solve's largest N_tot / N_0
+tracks), and stepping it further would only hold memory.  Results are reported as converged
+(time to energy), capped (the step cap reached first: a right-censored time) or failed.
+
 Each solve's result does not depend on what else is in the batch: its steps use its own
 store and its own Philox key, and the shift and selection count come from its own
 statistics, so a solve served in a mix returns exactly the energy it returns alone.
@@ -56,6 +62,8 @@ class Solve:
     num: list = field(default_factory=list)
     den: list = field(default_factory=list)
     attempts: int = 0
+    shoulder: float = 0.0   # largest N_tot / N_0 so far (Sec. IV.A)
+    shoulder_at: float = 0.0  # the N_tot where it was seen
 
 
 @dataclass
@@ -71,10 +79,16 @@ class Result:
     attempts: int
     failed: str = ""
     grown: int = 0          # times the solve's memory reservation was doubled
+    shoulder: float = 0.0   # largest N_tot / N_0 of the solve, and the N_tot where it was seen
+    shoulder_at: float = 0.0
 
     @property
     def time_to_energy(self) -> float:
         return self.finished - self.arrival
+
+    @property
+    def outcome(self) -> str:
+        return "converged" if self.converged else ("failed" if self.failed else "capped")
 
 
 def estimate_bytes(req: Request) -> int:
@@ -88,7 +102,7 @@ def estimate_bytes(req: Request) -> int:
 class Server:
     def __init__(self, hbm_budget: float = 64e9, max_active: int = 32, tol: float = 1e-4, equil: int = 500,
                  min_samples: int = 512, check_every: int = 256, max_steps: int = 20000, safety: float = 4.0,
-                 max_grow: int = 3, clock=time.perf_counter, sleep=time.sleep, log=None):
+                 max_grow: int = 3, runaway: float = 20.0, clock=time.perf_counter, sleep=time.sleep, log=None):
         self.hbm_budget = hbm_budget
         self.max_active = max_active
         self.tol = tol
@@ -98,6 +112,7 @@ class Server:
         self.max_steps = max_steps
         self.safety = safety
         self.max_grow = max_grow
+        self.runaway = runaway
         self.clock = clock
         self.sleep = sleep
         self.log = log or (lambda m: None)
@@ -119,6 +134,10 @@ class Server:
         """Book one step's statistics; True when the solve is finished."""
         s.steps += 1
         s.attempts += stats["n_spawn_attempts"]
+        if stats["n_ref"] != 0.0:
+            r = stats["n_total"] / abs(stats["n_ref"])
+            if r > s.shoulder:
+                s.shoulder, s.shoulder_at = r, stats["n_total"]
         was = s.ctl.varying
         s.ctl.update(stats["n_total"])
         if s.ctl.varying and not was:
@@ -133,13 +152,17 @@ class Server:
                     return True
         return s.steps >= self.max_steps
 
+    def _runaway(self, s: Solve, stats: dict) -> bool:
+        """The population grew to `runaway` times its target after the shift started to vary."""
+        return s.varying_since >= 0 and self.runaway > 0 and stats["n_total"] > self.runaway * s.req.target
+
     def _finish(self, s: Solve, now: float, failed: str = "") -> Result:
         e = err = float("nan")
         if len(s.num) >= 16:
             e, err, _ = driver.reblock_ratio(np.array(s.num), np.array(s.den))
         s.state.close()
         return Result(s.req.request_id, s.req.arrival, s.admitted, now, s.steps, e, err,
-                      bool(err < self.tol) and not failed, s.attempts, failed, s.grown)
+                      bool(err < self.tol) and not failed, s.attempts, failed, s.grown, s.shoulder, s.shoulder_at)
 
     # ------------------------------------------------------------------------ the loop
     def run(self, requests: list[Request]) -> list[Result]:
@@ -198,6 +221,13 @@ class Server:
                     results.append(self._finish(s, now))
                     used -= s.est_bytes
                     self.log(f"done {s.req.request_id} at {now:.2f}s after {s.steps} steps")
+                elif self._runaway(s, r):
+                    results.append(self._finish(
+                        s, now, failed=f"diverged: N_tot {r['n_total']:.3g} is {r['n_total'] / s.req.target:.0f}x the "
+                                       f"target under shift control, N_tot/N_0 up to {s.shoulder:.0f} (target below "
+                                       f"the shoulder)"))
+                    used -= s.est_bytes
+                    self.log(f"diverged {s.req.request_id} at {now:.2f}s after {s.steps} steps")
                 else:
                     keep.append(s)
             active = keep
@@ -215,11 +245,21 @@ def requests_from_stream(stream: list[dict], precision: str = "fp32") -> list[Re
 
 
 def summary(results: list[Result], wall: float) -> dict:
-    tte = np.array([r.time_to_energy for r in results])
-    conv = [r for r in results if r.converged]
-    return dict(requests=len(results), converged=len(conv), failed=sum(1 for r in results if r.failed),
-                reservations_grown=sum(r.grown for r in results),
+    """Time-to-energy percentiles over the converged solves only; capped solves (the step cap
+    reached before the error fell below the tolerance) are right-censored times, listed apart;
+    failed solves are counted by kind."""
+    conv = [r for r in results if r.outcome == "converged"]
+    capped = [r for r in results if r.outcome == "capped"]
+    failed = [r for r in results if r.outcome == "failed"]
+    tte = np.array([r.time_to_energy for r in conv])
+    kinds: dict = {}
+    for r in failed:
+        k = r.failed.split(":")[0].strip()[:60]
+        kinds[k] = kinds.get(k, 0) + 1
+    return dict(requests=len(results), converged=len(conv), capped=len(capped), failed=len(failed),
+                failures=kinds, reservations_grown=sum(r.grown for r in results),
                 p50_time_to_energy_s=float(np.percentile(tte, 50)) if len(tte) else None,
                 p99_time_to_energy_s=float(np.percentile(tte, 99)) if len(tte) else None,
+                capped_after_s=sorted(round(r.time_to_energy, 2) for r in capped),
                 attempts_per_s=sum(r.attempts for r in results) / wall if wall > 0 else None,
                 wall_s=wall, mean_steps=float(np.mean([r.steps for r in results])) if results else None)

@@ -31,7 +31,9 @@ def _requests():
     return [serve.Request(0, 0.0, ueg(2, 2, 1.0), 1e3, 0.005, 101, "fp32"),
             serve.Request(1, 0.02, ueg(2, 2, 0.5), 1.5e3, 0.005, 102, "fp64"),
             serve.Request(2, 0.05, ueg(3, 4, 1.0), 2e3, 0.005, 103, "fp32"),
-            serve.Request(3, 0.08, ueg(2, 4, 0.5), 1e3, 0.005, 104, "fp32")]
+            serve.Request(3, 0.08, ueg(2, 4, 0.5), 1e3, 0.005, 104, "fp32"),
+            # two-word determinants: a group of their own, queued beside the one-word groups
+            serve.Request(4, 0.09, ueg(2, 5, 1.0), 1e3, 0.005, 105, "fp32")]
 
 
 def _server(clock):
@@ -42,7 +44,7 @@ def _server(clock):
 def test_results_same_alone_and_in_the_mix():
     c = FakeClock()
     mixed = _server(c).run(_requests())
-    assert [r.request_id for r in mixed] == [0, 1, 2, 3]
+    assert [r.request_id for r in mixed] == [0, 1, 2, 3, 4]
     # with three slots, request 3 waits for a free one: admitted after it arrived
     assert mixed[3].admitted > mixed[3].arrival
     for req in _requests():

@@ -88,6 +88,30 @@ def test_growth_needs_room_in_the_server_budget(fakes):
 
 def test_runaway_population_ends_alone(fakes):
     FakeState.script = {1: (1.0, 0.0), 2: (4.0, 0.0)}  # solve 2 quadruples every step
-    res = _run([_req(0, 1), _req(1, 2)])
+    res = _run([_req(0, 1), _req(1, 2)], runaway=0)  # no divergence rule: the 2^32 guard ends it
     assert not res[0].failed and res[0].steps == 60
     assert res[1].failed == "population beyond 2^32 selections per step" and res[1].steps < 60
+
+
+def test_population_runaway_under_shift_control_is_diverged(fakes):
+    """A solve that passes 20 times its target after the shift started to vary ends as
+    diverged, early, with its N_tot / N_0 record; the other solve runs on."""
+    FakeState.script = {1: (1.0, 0.0), 2: (4.0, 0.0)}
+    res = _run([_req(0, 1), _req(1, 2)])
+    assert not res[0].failed and res[0].steps == 60
+    assert res[1].failed.startswith("diverged") and res[1].steps == 4 and res[1].shoulder == pytest.approx(10.0)
+
+
+def _result(i, arrival, finished, converged, failed=""):
+    return serve.Result(i, arrival, arrival, finished, 100, -0.1, 1e-5, converged, 1000, failed)
+
+
+def test_summary_percentiles_over_converged_only():
+    res = [_result(0, 0.0, 10.0, True), _result(1, 1.0, 21.0, True), _result(2, 2.0, 92.0, False),
+           _result(3, 3.0, 5.0, False, failed="CCMC_ENOMEM: budget"), _result(4, 4.0, 7.0, False, failed="diverged: x")]
+    s = serve.summary(res, wall=100.0)
+    assert (s["requests"], s["converged"], s["capped"], s["failed"]) == (5, 2, 1, 2)
+    assert s["p50_time_to_energy_s"] == pytest.approx(15.0) and s["p99_time_to_energy_s"] == pytest.approx(19.9)
+    assert s["capped_after_s"] == [90.0]
+    assert s["failures"] == {"CCMC_ENOMEM": 1, "diverged": 1}
+    assert s["attempts_per_s"] == pytest.approx(50.0)
