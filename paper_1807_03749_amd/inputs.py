@@ -77,7 +77,8 @@ class Workload:
 WORKLOADS = {
     "ueg14_38_ccsd_fp64": Workload(
         name="ueg14_38_ccsd_fp64", system="ueg", n_electrons=14, n2_max=2, rs=1.0, truncation=2,
-        tau=0.005, target_population=5e4, steps=1000),
+        tau=0.005, target_population=5e4, steps=1000,
+        extra=dict(shift_from_growth=True, bench_steps=400, bench_warmup=100)),
     "ueg14_114_ccsdt_fnc": Workload(
         name="ueg14_114_ccsdt_fnc", system="ueg", n_electrons=14, n2_max=5, rs=1.0, truncation=3,
         tau=0.002, target_population=1e6, full_noncomposite=True, min_spawn_attempts=4,
@@ -85,11 +86,15 @@ WORKLOADS = {
     "mol16_92_ccsdtq_fp32": Workload(
         name="mol16_92_ccsdtq_fp32", system="mol", n_electrons=16, n_spatial=46, n_chol=138,
         truncation=4, tau=5e-4, target_population=5e6, full_noncomposite=True, min_spawn_attempts=8,
-        multispawn_threshold=1.0, noncomposite_threshold=1.0, precision="fp32", steps=2000),
+        multispawn_threshold=1.0, noncomposite_threshold=1.0, precision="fp32", steps=2000,
+        # below its shoulder at this target: grown at tau itself, the shift started from the
+        # growth rate and held with a strong damping (see the benchmark's population control)
+        extra=dict(grow_factor=1.0, shift_from_growth=True, control_damping=0.5, bench_steps=30, bench_warmup=10)),
     "ueg54_246_ccsd_fp32": Workload(
         name="ueg54_246_ccsd_fp32", system="ueg", n_electrons=54, n2_max=9, rs=1.0, truncation=2,
         tau=0.001, target_population=1e8, full_noncomposite=True, min_spawn_attempts=8,
-        multispawn_threshold=1.0, noncomposite_threshold=1.0, precision="fp32", steps=200),
+        multispawn_threshold=1.0, noncomposite_threshold=1.0, precision="fp32", steps=200,
+        extra=dict(bench_steps=10, bench_warmup=5)),
 }
 
 
