@@ -139,6 +139,7 @@ struct ccmc_state {
     double last_num = 0, last_den = 0;
     // per-step buffers
     DevBuf P, guide, delta, rtab;
+    DevBuf drec;  // draw records: prefix, amplitude and bitstring of each excitor, (2 + W) words
     DevBuf vkey[2], perm, seg;  // virtual processors: placement keys, the partition, its segments
     uint64_t rt_n = 0;   // rank-table buckets
     uint32_t rsh = 0;    // rank-table shift
@@ -149,7 +150,7 @@ struct ccmc_state {
     DevBuf block_item, gcount, gspawn, gdeath, boff;
     DevBuf rkey, ramp, rid;  // per-block record regions
     uint64_t rcap = 0;              // region slots
-    DevBuf drank, dkey, damp, did, sr[2], sidx[2], tile_region;
+    DevBuf drank, dkey, damp, did, sr[2], sval[2], tile_region;
     DevBuf ins, seg_sum, nkey, nrank, nins, nsum;
     uint64_t dcap = 0;  // dense record capacity
     uint64_t slot_hint = 1 << 16, rec_hint = 1 << 14;  // capacities planned for the next step
@@ -569,6 +570,7 @@ ccmc_status ensure_store(ccmc_state *st, uint64_t n)
     TRY(ensure(st, st->sK[1 - c], nc * sizeof(T)));
     TRY(ensure(st, st->srank[1 - c], nc * sizeof(uint64_t)));
     TRY(ensure(st, st->P, nc * sizeof(uint64_t)));
+    TRY(ensure(st, st->drec, nc * (2 + W) * sizeof(uint64_t)));
     TRY(ensure(st, st->guide, guide_cap(nc) * sizeof(uint32_t)));
     if (st->opt.n_ranks > 1) {
         for (DevBuf *b : {&st->vkey[0], &st->vkey[1]}) TRY(ensure(st, *b, nc * sizeof(uint64_t)));
@@ -609,6 +611,7 @@ struct Plan {
     unsigned nb_fnc = 0, nb_sel = 0, nb_rt = 0, nb_abs = 0;
     uint64_t o_tick = 0, o_weights = 0, o_off = 0, o_boff = 0, o_merge = 0, o_ghist = 0, o_rstat = 0;
     uint64_t o_fold = 0, o_fin = 0;
+    bool packed = false;     // sort keys carry the rank in their high half and the record's position below
     bool ranked = false;     // virtual processors: the store is partitioned by processor
     uint64_t ptiles = 0;     // radix tiles of the partition
     uint64_t o_pghist = 0, o_pstat = 0;
@@ -645,6 +648,7 @@ ccmc_status plan_sizes(Plan<W, T> &p)
     a.key1 = (uint32_t)(st->opt.seed >> 32);
     a.n_sel = p.n_sel;
     a.fnc = p.fnc ? 1 : 0;
+    p.packed = st->rank_bits <= 32;
     p.ranked = st->opt.n_ranks > 1;
     a.n_ranks = p.ranked ? st->opt.n_ranks : 1;
     p.ptiles = p.ranked ? (ne + kSortTile - 1) / kSortTile : 0;
@@ -703,7 +707,7 @@ ccmc_status plan_sizes(Plan<W, T> &p)
         TRY(ensure(st, st->damp, nc * sizeof(T)));
         for (DevBuf *b : {&st->drank, &st->sr[0], &st->sr[1], &st->ins, &st->nins, &st->nrank})
             TRY(ensure(st, *b, nc * sizeof(uint64_t)));
-        for (DevBuf *b : {&st->sidx[0], &st->sidx[1]}) TRY(ensure(st, *b, nc * sizeof(uint32_t)));
+        for (DevBuf *b : {&st->sval[0], &st->sval[1]}) TRY(ensure(st, *b, nc * sizeof(T)));
         for (DevBuf *b : {&st->seg_sum, &st->nsum}) TRY(ensure(st, *b, nc * sizeof(double)));
         TRY(ensure(st, st->tile_region, (nc / kGatherTile + 2) * sizeof(uint32_t)));
         st->dcap = nc;
@@ -958,7 +962,7 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
         std::vector<RadixGhistArgs> args;
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
-            args.push_back(RadixGhistArgs{ptr<uint64_t>(p.st->vkey[0]), &p.sc->n_place, 1,
+            args.push_back(RadixGhistArgs{ptr<uint64_t>(p.st->vkey[0]), &p.sc->n_place, 1, 0,
                                           reinterpret_cast<uint32_t *>(p.lb + p.o_pghist)});
             blk[i] = (uint32_t)p.ptiles;
         }
@@ -966,18 +970,18 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
               [s](const auto &a, unsigned g, auto... bm) { k_radix_ghist<<<g, kThreads, 0, s>>>(a, bm...); });
     }
     {
-        std::vector<RadixOnesweepArgs> args;
+        std::vector<RadixOnesweepArgs<uint32_t>> args;
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
             ccmc_state *st = p.st;
-            args.push_back(RadixOnesweepArgs{ptr<uint64_t>(st->vkey[0]), nullptr, ptr<uint64_t>(st->vkey[1]),
+            args.push_back(RadixOnesweepArgs<uint32_t>{ptr<uint64_t>(st->vkey[0]), nullptr, ptr<uint64_t>(st->vkey[1]),
                                              ptr<uint32_t>(st->perm), &p.sc->n_place, 0,
                                              reinterpret_cast<const uint32_t *>(p.lb + p.o_pghist), p.lb + p.o_pstat,
                                              p.lb + p.o_tick + kTkPlace});
             blk[i] = (uint32_t)p.ptiles;
         }
         stage(ar, recs, "place_sweep", args, blk, works([&](auto &p) { return Work{20.0, nullptr, p.ranked ? p.ne : 0}; }),
-              [s](const auto &a, unsigned g, auto... bm) { k_radix_onesweep<<<g, kThreads, 0, s>>>(a, bm...); });
+              [s](const auto &a, unsigned g, auto... bm) { k_radix_onesweep<uint32_t><<<g, kThreads, 0, s>>>(a, bm...); });
     }
     // ---- (a1) selection weights, formed inside the scan of their prefix; the draw guide
     {
@@ -1004,11 +1008,15 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
             ccmc_state *st = p.st;
             args.push_back(GuideArgs{ptr<uint64_t>(st->P), ptr<uint32_t>(st->guide), p.a.gcap, p.a.gsh, p.ne,
                                      p.ranked ? ptr<uint64_t>(st->vkey[1]) : nullptr,
-                                     p.ranked ? ptr<uint32_t>(st->seg) : nullptr, p.a.n_ranks});
+                                     p.ranked ? ptr<uint32_t>(st->seg) : nullptr, p.a.n_ranks, st->samp[p.c].p,
+                                     sizeof(T) == 8 ? 1 : 0, ptr<uint64_t>(st->skey[p.c]), st->scap, W,
+                                     p.ranked ? ptr<uint32_t>(st->perm) : nullptr,
+                                     DrawRecs{ptr<uint64_t>(st->drec), (uint32_t)(2 + W)}});
             blk[i] = p.n_sel && p.ne ? grid_for(p.ne) : 0;
         }
-        // bytes: prefix read, about one guide entry per two excitors
-        stage(ar, recs, "guide", args, blk, works([&](auto &p) { return Work{10.0, nullptr, p.ne}; }),
+        // bytes: prefix, amplitude and bitstring read, the draw record written, about one guide
+        // entry per two excitors
+        stage(ar, recs, "guide", args, blk, works([&](auto &p) { return Work{10.0 + 8.0 + tb + kb + 8.0 * (2 + W), nullptr, p.ne}; }),
               [s](const auto &a, unsigned g, auto... bm) { k_guide<<<g, kThreads, 0, s>>>(a, bm...); });
     }
     // ---- (a2-a5, a9, a10) items: non-composite (FNC) then sampled clusters; then the rank table
@@ -1035,7 +1043,7 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
             const uint64_t *srank = ptr<uint64_t>(st->srank[p.c]);
             const RankTable rt{srank, p.ne, ptr<uint32_t>(st->rtab), st->rt_n, st->rsh};
             args.push_back(A{st->sd, ptr<uint64_t>(st->skey[p.c]), ptr<T>(st->samp[p.c]), ptr<T>(st->sK[p.c]), st->scap,
-                             p.ne, ptr<uint64_t>(st->P), ptr<uint32_t>(st->guide),
+                             p.ne, ptr<uint64_t>(st->P), ptr<uint64_t>(st->drec), ptr<uint32_t>(st->guide),
                              Ranks{p.ranked ? ptr<uint32_t>(st->perm) : nullptr, p.ranked ? ptr<uint32_t>(st->seg) : nullptr},
                              st->n0, p.a, items_of(p), p.nb_fnc,
                              p.n_fnc, p.nb_fnc + p.nb_sel, rt, parts_of(p), p.sc});
@@ -1112,21 +1120,23 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
             auto &p = ps[i];
             ccmc_state *st = p.st;
             args.push_back(A{st->sd, regions_of(p), ptr<uint32_t>(st->boff), ptr<uint32_t>(st->tile_region), p.nblk_cap,
-                             p.rec_cap, dense_of(p), p.ids ? 1 : 0, p.sc});
+                             p.rec_cap, dense_of(p), p.ids ? 1 : 0, p.packed ? 1 : 0, p.sc});
             blk[i] = grid_for(p.rec_cap, kGatherTile);
         }
+        // bytes: each record's region key and amplitude read, its sort key, amplitude and
+        // bitstring written (with spawn ids kept: also its id read and written)
         stage(ar, recs, "gather", args, blk, works([&](auto &p) {
-                  return Work{2.0 * (kb + tb + (p.ids ? 8.0 : 0.0)) + 8.0, &p.st->cnt_rec, 0};
+                  return Work{2.0 * (kb + tb) + 8.0 + (p.ids ? 16.0 : 0.0), &p.st->cnt_rec, 0};
               }),
               [s](const auto &a, unsigned g, auto... bm) { k_gather<W, T><<<g, kThreads, 0, s>>>(a, bm...); });
     }
-    // ---- (a11) stable LSD radix sort of (rank, record index): one histogram launch for all
+    // ---- (a11) stable LSD radix sort of (rank, amplitude): one histogram launch for all
     // passes, then one single-sweep launch per digit
     {
         std::vector<RadixGhistArgs> args;
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
-            args.push_back(RadixGhistArgs{ptr<uint64_t>(p.st->drank), &p.sc->n_live, passes,
+            args.push_back(RadixGhistArgs{ptr<uint64_t>(p.st->drank), &p.sc->n_live, passes, p.packed ? 32 : 0,
                                           reinterpret_cast<uint32_t *>(p.lb + p.o_ghist)});
             blk[i] = (uint32_t)p.tiles;
         }
@@ -1134,23 +1144,23 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
               [s](const auto &a, unsigned g, auto... bm) { k_radix_ghist<<<g, kThreads, 0, s>>>(a, bm...); });
     }
     for (int pass = 0; pass < passes; ++pass) {
-        std::vector<RadixOnesweepArgs> args;
+        std::vector<RadixOnesweepArgs<T>> args;
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
             ccmc_state *st = p.st;
             const int ob = pass & 1;
             const uint64_t *kin = pass == 0 ? ptr<uint64_t>(st->drank) : ptr<uint64_t>(st->sr[ob ^ 1]);
-            const uint32_t *iin = pass == 0 ? nullptr : ptr<uint32_t>(st->sidx[ob ^ 1]);
-            args.push_back(RadixOnesweepArgs{kin, iin, ptr<uint64_t>(st->sr[ob]), ptr<uint32_t>(st->sidx[ob]), &p.sc->n_live,
-                                             kRadixBits * pass,
+            const T *vin = pass == 0 ? ptr<T>(st->damp) : ptr<T>(st->sval[ob ^ 1]);
+            args.push_back(RadixOnesweepArgs<T>{kin, vin, ptr<uint64_t>(st->sr[ob]), ptr<T>(st->sval[ob]), &p.sc->n_live,
+                                             (p.packed ? 32 : 0) + kRadixBits * pass,
                                              reinterpret_cast<const uint32_t *>(p.lb + p.o_ghist) + kRadixBins * pass,
                                              p.lb + p.o_rstat + (uint64_t)pass * p.tiles * kRadixBins,
                                              p.lb + p.o_tick + kTkRadix + pass});
             blk[i] = (uint32_t)p.tiles;
         }
-        stage(ar, recs, "radix_onesweep", args, blk,
-              works([&](auto &p) { return Work{2 * 8.0 + (pass ? 8.0 : 4.0), &p.st->cnt_rec, 0}; }),
-              [s](const auto &a, unsigned g, auto... bm) { k_radix_onesweep<<<g, kThreads, 0, s>>>(a, bm...); });
+        // bytes: each (rank, amplitude) pair read and written
+        stage(ar, recs, "radix_onesweep", args, blk, works([&](auto &p) { return Work{2.0 * (8.0 + tb), &p.st->cnt_rec, 0}; }),
+              [s](const auto &a, unsigned g, auto... bm) { k_radix_onesweep<T><<<g, kThreads, 0, s>>>(a, bm...); });
     }
     const int sorted = (passes - 1) & 1;  // buffer of the last pass
     // ---- (a12) runs of equal determinants: fold in record order, store lookup by rank
@@ -1168,13 +1178,13 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
             ccmc_state *st = p.st;
             const NewDets nd{ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), ptr<uint64_t>(st->nins), ptr<double>(st->nsum),
                              st->dcap, ptr<uint64_t>(st->dkey), st->dcap};
-            args.push_back(A{ptr<uint64_t>(st->sr[sorted]), ptr<uint32_t>(st->sidx[sorted]), ptr<T>(st->damp), p.rec_cap,
+            args.push_back(A{st->sd, ptr<uint64_t>(st->sr[sorted]), ptr<T>(st->sval[sorted]), p.packed ? 1 : 0, p.rec_cap,
                              ptr<uint64_t>(st->srank[p.c]), p.ne, ptr<double>(st->delta), ptr<uint64_t>(st->ins),
                              ptr<double>(st->seg_sum), ptr<uint32_t>(st->rtab), st->rt_n, st->rsh, fold_of(p), nd, p.sc});
             blk[i] = (uint32_t)p.fold_tiles;
         }
-        // bytes: rank, index, gathered amount and (per head) the new-determinant entry
-        stage(ar, recs, "seg_fold", args, blk, works([&](auto &p) { return Work{8.0 + 4.0 + tb, &p.st->cnt_rec, 0, nullptr, kb + 24.0, &p.st->cnt_new}; }),
+        // bytes: each sorted (rank, amplitude) pair and (per head) the new-determinant entry
+        stage(ar, recs, "seg_fold", args, blk, works([&](auto &p) { return Work{8.0 + tb, &p.st->cnt_rec, 0, nullptr, kb + 24.0, &p.st->cnt_new}; }),
               [s](const auto &a, unsigned g, auto... bm) { k_seg_fold<W, T><<<g, kThreads, 0, s>>>(a, bm...); });
     }
     {
@@ -1182,7 +1192,7 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
             ccmc_state *st = p.st;
-            args.push_back(SegCloseArgs{ptr<uint64_t>(st->sr[sorted]), p.fold_tiles, ptr<uint64_t>(st->srank[p.c]), p.ne,
+            args.push_back(SegCloseArgs{ptr<uint64_t>(st->sr[sorted]), p.packed ? 1 : 0, p.fold_tiles, ptr<uint64_t>(st->srank[p.c]), p.ne,
                                         ptr<double>(st->delta), ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum),
                                         ptr<double>(st->nsum), fold_of(p), p.sc});
             blk[i] = grid_for(p.fold_tiles);
@@ -1638,10 +1648,10 @@ void destroy(ccmc_state *st)
     if (st->stream) (void)hipStreamSynchronize(st->stream);
     DevBuf *bufs[] = {&st->t_grid, &st->t_nvec, &st->t_vq, &st->t_h, &st->t_eri, &st->t_fock, &st->t_vpair,
                       &st->t_binv, &st->t_bino, &st->skey[0], &st->skey[1], &st->samp[0], &st->samp[1], &st->sK[0],
-                      &st->sK[1], &st->srank[0], &st->srank[1], &st->P, &st->guide, &st->delta, &st->rtab, &st->ikey,
+                      &st->sK[1], &st->srank[0], &st->srank[1], &st->P, &st->drec, &st->guide, &st->delta, &st->rtab, &st->ikey,
                       &st->iA, &st->ideath, &st->in, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,
                       &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->boff, &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
-                      &st->sidx[0], &st->sidx[1], &st->tile_region,
+                      &st->sval[0], &st->sval[1], &st->tile_region,
                       &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->lb, &st->arg_dev,
                       &st->vkey[0], &st->vkey[1], &st->perm, &st->seg};
     for (DevBuf *b : bufs) release(st, *b);

@@ -442,6 +442,36 @@ __device__ __forceinline__ uint64_t space_rank(const SysDev &S, const uint64_t *
     return r;
 }
 
+// The determinant of rank r (the inverse of space_rank): orbitals are decided from the top.
+// With the bits above p fixed (a electrons placed, v of them virtual), the determinants that
+// leave p empty number S(p) = sum_j C(virtual orbitals below p, j) C(reference orbitals below
+// p, k - j) over j <= l - v (k = N - a electrons still to place), and they all come before the
+// ones that fill p: p is filled iff r >= S(p), and then r drops by S(p).
+template <int W>
+__device__ __forceinline__ void space_unrank(const SysDev &S, uint64_t r, uint64_t *d)
+{
+    const int N = S.nel, l = S.l;
+#pragma unroll
+    for (int w = 0; w < W; ++w) d[w] = 0;
+    int a = 0, v = 0;
+    for (int p = S.M - 1; p >= 0 && a < N; --p) {
+        const int k = N - a;
+        const int nv = p > N ? p - N : 0, no = p < N ? p : N;
+        const int jmax = (l - v) < k ? (l - v) : k;
+        uint64_t empty = 0;
+        for (int j = 0; j <= jmax; ++j) {
+            if (k - j > no) continue;
+            empty += S.binom_v[nv * 9 + j] * S.binom_o[no * (N + 1) + (k - j)];
+        }
+        if (r >= empty) {
+            r -= empty;
+            d[p >> 6] |= 1ull << (p & 63);
+            ++a;
+            v += (p >= N) ? 1 : 0;
+        }
+    }
+}
+
 // Cluster-size distribution: p(s) = 2^-(s-lo+1) for lo <= s < hi, the remainder at hi.
 __device__ __forceinline__ int draw_size(double u, int lo, int hi)
 {

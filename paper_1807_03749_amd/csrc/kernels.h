@@ -10,7 +10,7 @@
 //   k_generate       one lane per record slot: death or spawning attempt        (a6, a7, a8)
 //   region scan      records per generation block
 //   k_gather         dense records and their truncated-space rank               (a8)
-//   radix sort       stable LSD sort of (rank, record index)                    (a11)
+//   radix sort       stable LSD sort of (rank | position, amplitude)            (a11)
 //   k_seg_fold       sum of each run in record order, store lookup, new         (a12)
 //                    determinants numbered by look-back; k_seg_close for runs across tiles
 //   k_merge          merge, occupation rounding and compaction into the other    (a12, a13)
@@ -128,19 +128,22 @@ __device__ __forceinline__ uint32_t attempt_count(T A, double thr, uint32_t kmin
 // q_i = max(1, rint(|N_i| 2^24)), formed while the inclusive prefix P is scanned: the prefix
 // is exact, so the excitor drawn for a given random number does not depend on the
 // summation order (Sec. II: probability |t_i| / (N_tot - t_HF)).
+constexpr uint64_t kWeightCap = 1ull << 52;  // |N_i| >= 2^28 (or NaN) is a blow-up
+
+__device__ __forceinline__ uint64_t weight_of(double amp)
+{
+    double w = rint(fabs(amp) * 16777216.0);
+    w = w < 1.0 ? 1.0 : w;
+    return (uint64_t)fmin(w, (double)kWeightCap);  // NaN -> kWeightCap
+}
+
 template <typename T>
 struct WeightSrc {
     const T *amp;
     Scratch *sc;
     const uint32_t *perm;  // weights in the order of the processor partition, or store order
-    static constexpr uint64_t kCap = 1ull << 52;  // |N_i| >= 2^28 (or NaN) is a blow-up
-    __device__ __forceinline__ uint64_t operator()(uint64_t i) const
-    {
-        const double a = fabs((double)amp[perm ? perm[i] : i]);
-        double w = rint(a * 16777216.0);
-        w = w < 1.0 ? 1.0 : w;
-        return (uint64_t)fmin(w, (double)kCap);  // NaN -> kCap
-    }
+    static constexpr uint64_t kCap = kWeightCap;
+    __device__ __forceinline__ uint64_t operator()(uint64_t i) const { return weight_of((double)amp[perm ? perm[i] : i]); }
     __device__ __forceinline__ void check(uint64_t q) const
     {
         if (q >= kCap) atomicOr((unsigned long long *)&sc->err, (unsigned long long)kErrBlowup);
@@ -155,6 +158,27 @@ struct WeightSrc {
 // them together); the last one also owns the two closing buckets.  The shift comes from the
 // host (from the previous step's Q), so buckets past the capacity gcap may exist: draws there
 // search from guide[gcap - 1] to the end.
+//
+// The same lanes write each excitor's draw record: everything a draw of it reads, in one
+// place -- its inclusive prefix, its amplitude (the bits of T in the low bytes of a 64-bit
+// word) and its bitstring (W words) -- so that a draw, after the guide, touches one or two
+// lines instead of one per array.  Records follow the order of the prefix (the processor
+// partition's, or the store's).
+struct DrawRecs {
+    uint64_t *rec;
+    uint32_t stride;  // 64-bit words per record: 2 + W
+};
+
+template <typename T>
+__device__ __forceinline__ T rec_amp(uint64_t bits)
+{
+    if constexpr (sizeof(T) == 8) {
+        return __longlong_as_double((long long)bits);
+    } else {
+        return __int_as_float((int)(uint32_t)bits);
+    }
+}
+
 struct GuideArgs {
     const uint64_t *P;
     uint32_t *guide;
@@ -166,12 +190,27 @@ struct GuideArgs {
     const uint64_t *vsorted;
     uint32_t *seg;
     uint32_t n_ranks;
+    // the draw records: store columns to copy (through perm in partition order)
+    const void *amp;
+    int amp8;  // amplitudes of 8 bytes (else 4)
+    const uint64_t *skey;
+    uint64_t sstride;
+    int words;
+    const uint32_t *perm;
+    DrawRecs dr;
 };
 
 __device__ __forceinline__ void k_guide_entry(const GuideArgs &A, uint32_t blk, uint32_t nblk)
 {
     const uint64_t g = (uint64_t)blk * kThreads + threadIdx.x;
     uint64_t b0 = 0, b1 = 0;
+    if (g < A.n) {
+        const uint64_t src = A.perm ? A.perm[g] : g;
+        uint64_t *r = A.dr.rec + g * A.dr.stride;
+        r[0] = A.P[g];
+        r[1] = A.amp8 ? static_cast<const uint64_t *>(A.amp)[src] : (uint64_t) static_cast<const uint32_t *>(A.amp)[src];
+        for (int w = 0; w < A.words; ++w) r[2 + w] = A.skey[(uint64_t)w * A.sstride + src];
+    }
     if (g < A.n) {
         const uint64_t unit = 1ull << A.gsh, lo = g ? A.P[g - 1] : 0, hi = A.P[g];
         b0 = (lo + unit - 1) >> A.gsh;
@@ -429,11 +468,12 @@ __device__ __forceinline__ void noncomposite_block(unsigned blk, const SysDev &S
 // discarded (Sec. II).  The product of the excitors is collapsed by applying them to the
 // reference one operator at a time; a repeated hole or particle makes it vanish.
 template <int W, typename T>
-__device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
-                                                     uint64_t sstride, uint64_t ne, const uint64_t *__restrict__ P,
+__device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, const uint64_t *__restrict__ drec,
+                                                     uint64_t ne, const uint64_t *__restrict__ P,
                                                      const uint32_t *__restrict__ guide, Ranks rk, double n0, StepArgs a,
                                                      Items<T> it, uint64_t item_base, ItemPartials part, Scratch *sc)
 {
+    constexpr uint32_t kRec = 2 + W;  // words of a draw record: prefix, amplitude, bitstring
     const uint64_t k = (uint64_t)blk * kThreads + threadIdx.x;
     double num = 0.0;
     uint64_t att = 0, disc = 0, mx = 0;
@@ -477,14 +517,15 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
                 }
             }
         }
-        // lock-step binary searches: first i in [l0, h0) with P[i] > x
+        // lock-step binary searches: first i in [l0, h0) with P[i] > x (the prefix of the
+        // draw records)
         for (bool more = ok && s > 0; more;) {
             more = false;
 #pragma unroll
             for (int c = 0; c < kMaxClusterSize; ++c) {
                 if (c < s && l0[c] < h0[c]) {
                     const uint32_t mid = (l0[c] + h0[c]) >> 1;
-                    if (P[mid] > xs[c])
+                    if (drec[(uint64_t)mid * kRec] > xs[c])
                         h0[c] = mid;
                     else
                         l0[c] = mid + 1;
@@ -498,8 +539,8 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
 #pragma unroll
             for (int b = 0; b < c; ++b)
                 if (c < s) ok &= (l0[b] != l0[c]);
-        // selection probability and product of amplitudes, in draw order; l0 becomes the
-        // store index of each draw
+        // selection probability and product of amplitudes, in draw order; each draw's weight
+        // is its amplitude's (the prefix step P[i] - P[i-1] exactly)
         double fact = 1.0;
         for (int c = 2; c <= s; ++c) fact *= (double)c;
         double p = (double)count * size_prob(s, lo, hi) * fact;
@@ -507,10 +548,8 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
 #pragma unroll
         for (int c = 0; c < kMaxClusterSize; ++c) {
             if (c < s && ok) {
-                const uint32_t i = l0[c];
-                const uint64_t qi = P[i] - (i ? P[i - 1] : 0);
-                if (a.n_ranks > 1) l0[c] = rk.perm[i];
-                const T ni = samp[l0[c]];
+                const T ni = rec_amp<T>(drec[(uint64_t)l0[c] * kRec + 1]);
+                const uint64_t qi = weight_of((double)ni);
                 p *= (double)qi / (double)Q;
                 if (c == 0)
                     prod = ni;
@@ -539,7 +578,7 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
             if (c < 0 || !ok) continue;
             uint64_t x[W];
 #pragma unroll
-            for (int w = 0; w < W; ++w) x[w] = skey[(uint64_t)w * sstride + l0[c]];
+            for (int w = 0; w < W; ++w) x[w] = drec[(uint64_t)l0[c] * kRec + 2 + w];
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 uint64_t h = S.hf[w] & ~x[w];
@@ -614,7 +653,8 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
 template <int W, typename T>
 __device__ __forceinline__ void items_body(uint32_t blk, uint32_t nblk, SysDev S, const uint64_t *__restrict__ skey, const T *__restrict__ samp,
                                                     const T *__restrict__ sK, uint64_t sstride, uint64_t ne,
-                                                    const uint64_t *__restrict__ P, const uint32_t *__restrict__ guide,
+                                                    const uint64_t *__restrict__ P, const uint64_t *__restrict__ drec,
+                                                    const uint32_t *__restrict__ guide,
                                                     Ranks rk, double n0, StepArgs a, Items<T> it, unsigned nb_fnc, uint64_t n_fnc,
                                                     unsigned nb_items, RankTable rt, ItemPartials part, Scratch *sc)
 {
@@ -630,7 +670,7 @@ __device__ __forceinline__ void items_body(uint32_t blk, uint32_t nblk, SysDev S
     } else {
         const unsigned b = blk - nb_fnc;
         ItemPartials ps{part.num + nb_fnc, part.att + nb_fnc, part.disc + nb_fnc, part.maxn + nb_fnc};
-        select_block<W, T>(b, S, skey, samp, sstride, ne, P, guide, rk, n0, a, it, n_fnc, ps, sc);
+        select_block<W, T>(b, S, drec, ne, P, guide, rk, n0, a, it, n_fnc, ps, sc);
     }
 }
 
@@ -643,6 +683,7 @@ struct ItemsArgs {
     uint64_t sstride;
     uint64_t ne;
     const uint64_t *P;
+    const uint64_t *drec;
     const uint32_t *guide;
     Ranks rk;
     double n0;
@@ -659,7 +700,7 @@ struct ItemsArgs {
 template <int W, typename T>
 __device__ __forceinline__ void k_items_entry(const ItemsArgs<W, T> &A, uint32_t blk, uint32_t nblk)
 {
-    items_body<W, T>(blk, nblk, A.S, A.skey, A.samp, A.sK, A.sstride, A.ne, A.P, A.guide, A.rk, A.n0, A.a, A.it, A.nb_fnc, A.n_fnc, A.nb_items, A.rt, A.part, A.sc);
+    items_body<W, T>(blk, nblk, A.S, A.skey, A.samp, A.sK, A.sstride, A.ne, A.P, A.drec, A.guide, A.rk, A.n0, A.a, A.it, A.nb_fnc, A.n_fnc, A.nb_items, A.rt, A.part, A.sc);
 }
 
 template <int W, typename T>
@@ -1087,10 +1128,13 @@ struct RegionOut {
     }
 };
 
+// The sort key of a record: its rank, or with `packed` (ranks of at most 32 bits) the rank in the
+// high half and the record's dense position in the low half, so that the sorted list also
+// tells where each record's bitstring is.
 template <int W, typename T>
 __device__ __forceinline__ void gather_body(uint32_t blk, uint32_t nblk, const SysDev S, Records reg, const uint32_t *__restrict__ boff,
                                             const uint32_t *__restrict__ tile_region, uint64_t n_blocks, uint64_t rec_cap,
-                                            Records out, int keep_ids, Scratch *sc)
+                                            Records out, int keep_ids, int packed, Scratch *sc)
 {
     __shared__ uint32_t s_b[kGatherLds + 1];
     // records the annihilation works on: all of them, or none after a capacity overflow
@@ -1141,9 +1185,10 @@ __device__ __forceinline__ void gather_body(uint32_t blk, uint32_t nblk, const S
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             d[w] = reg.key[(uint64_t)w * reg.stride + src];
-            out.key[(uint64_t)w * out.stride + r] = d[w];
+            if (packed || keep_ids) out.key[(uint64_t)w * out.stride + r] = d[w];
         }
-        out.rank[r] = space_rank<W>(S, d);
+        const uint64_t rk = space_rank<W>(S, d);
+        out.rank[r] = packed ? (rk << 32 | r) : rk;
         static_cast<T *>(out.amp)[r] = static_cast<const T *>(reg.amp)[src];
         if (keep_ids) out.id[r] = reg.id[src];
     }
@@ -1159,13 +1204,14 @@ struct GatherArgs {
     uint64_t rec_cap;
     Records out;
     int keep_ids;
+    int packed;
     Scratch *sc;
 };
 
 template <int W, typename T>
 __device__ __forceinline__ void k_gather_entry(const GatherArgs<W, T> &A, uint32_t blk, uint32_t nblk)
 {
-    gather_body<W, T>(blk, nblk, A.S, A.reg, A.boff, A.tile_region, A.n_blocks, A.rec_cap, A.out, A.keep_ids, A.sc);
+    gather_body<W, T>(blk, nblk, A.S, A.reg, A.boff, A.tile_region, A.n_blocks, A.rec_cap, A.out, A.keep_ids, A.packed, A.sc);
 }
 
 template <int W, typename T>
@@ -1204,21 +1250,27 @@ struct FoldTiles {
     uint64_t *ticket;
 };
 
-// The determinants that are not in the store, in rank order: bitstring, rank, insertion
-// point in the store and summed amount.
+// The determinants that are not in the store, in rank order: bitstring, rank, insertion point
+// in the store and summed amount.
 struct NewDets {
     uint64_t *key;
     uint64_t *rank;
     uint64_t *ins;
     double *sum;
     uint64_t stride;
-    const uint64_t *rkey;  // dense record bitstrings (stride rstride)
+    const uint64_t *rkey;  // dense record bitstrings (stride rstride), read with packed sort keys
     uint64_t rstride;
 };
 
+// Rank of a sorted record key (see gather_body).
+__device__ __forceinline__ uint64_t key_rank(uint64_t k, int packed) { return packed ? k >> 32 : k; }
+
+// The records arrive sorted as (key, amplitude) pairs: the amplitudes are read in order.  A new
+// determinant's bitstring is read from the dense records at the position the packed key
+// carries, or (ranks above 32 bits) recovered from its rank.
 template <int W, typename T>
-__device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ rank, const uint32_t *__restrict__ idx,
-                                                       const T *__restrict__ ramp, uint64_t cap,
+__device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const SysDev &S, const uint64_t *__restrict__ rank,
+                                                       const T *__restrict__ val, int packed, uint64_t cap,
                                                        const uint64_t *__restrict__ srank, uint64_t ne,
                                                        double *__restrict__ delta, uint64_t *__restrict__ ins,
                                                        double *__restrict__ seg_sum,
@@ -1247,19 +1299,18 @@ __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const
     if (threadIdx.x == 0) s_open = kNoOpen;
     // this thread's records, the one before and the one after (clamped: unconditional loads)
     uint64_t rr[kFoldItems + 1];
-    uint32_t ii[kFoldItems];
+    uint32_t pos_of[kFoldItems];  // dense position of each record (packed keys)
 #pragma unroll
     for (int i = 0; i <= kFoldItems; ++i) {
         const uint64_t r = r0 + i;
-        rr[i] = rank[r < n ? r : n - 1];
-        rr[i] = r < n ? rr[i] : ~0ull;
+        const uint64_t k = rank[r < n ? r : n - 1];
+        if (i < kFoldItems) pos_of[i] = (uint32_t)k;
+        rr[i] = r < n ? key_rank(k, packed) : ~0ull;
     }
-    const uint64_t rprev = r0 ? rank[r0 - 1 < n ? r0 - 1 : n - 1] : ~0ull;
-#pragma unroll
-    for (int i = 0; i < kFoldItems; ++i) ii[i] = idx[r0 + i < n ? r0 + i : n - 1];
+    const uint64_t rprev = r0 ? key_rank(rank[r0 - 1 < n ? r0 - 1 : n - 1], packed) : ~0ull;
     double v[kFoldItems];
 #pragma unroll
-    for (int i = 0; i < kFoldItems; ++i) v[i] = (double)ramp[ii[i]];
+    for (int i = 0; i < kFoldItems; ++i) v[i] = (double)val[r0 + i < n ? r0 + i : n - 1];
     bool head[kFoldItems];
     uint32_t any = 0;
 #pragma unroll
@@ -1309,7 +1360,7 @@ __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const
                 if (s_head[k]) break;
             }
             // past the tile end: continues if the next tile starts with the same rank
-            open[i] = k == kThreads && base + kFoldTile < n && rank[base + kFoldTile] == rk;
+            open[i] = k == kThreads && base + kFoldTile < n && key_rank(rank[base + kFoldTile], packed) == rk;
         }
         acc[i] = sum;
     }
@@ -1373,8 +1424,15 @@ __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const
         seg_sum[r] = acc[i];
         if (fresh[i]) {
             const uint64_t jj = jbase + j++;
+            uint64_t d[W];
+            if (packed) {
 #pragma unroll
-            for (int w = 0; w < W; ++w) nd.key[(uint64_t)w * nd.stride + jj] = nd.rkey[(uint64_t)w * nd.rstride + ii[i]];
+                for (int w = 0; w < W; ++w) d[w] = nd.rkey[(uint64_t)w * nd.rstride + pos_of[i]];
+            } else {
+                space_unrank<W>(S, rk, d);
+            }
+#pragma unroll
+            for (int w = 0; w < W; ++w) nd.key[(uint64_t)w * nd.stride + jj] = d[w];
             nd.rank[jj] = rk;
             nd.ins[jj] = pos;
             nd.sum[jj] = acc[i];
@@ -1409,9 +1467,10 @@ __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const
 
 template <int W, typename T>
 struct SegFoldArgs {
+    SysDev S;
     const uint64_t *rank;
-    const uint32_t *idx;
-    const T *ramp;
+    const T *val;
+    int packed;
     uint64_t cap;
     const uint64_t *srank;
     uint64_t ne;
@@ -1429,7 +1488,7 @@ struct SegFoldArgs {
 template <int W, typename T>
 __device__ __forceinline__ void k_seg_fold_entry(const SegFoldArgs<W, T> &A, uint32_t blk, uint32_t nblk)
 {
-    seg_fold_body<W, T>(blk, nblk, A.rank, A.idx, A.ramp, A.cap, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.rtab, A.rt_n,
+    seg_fold_body<W, T>(blk, nblk, A.S, A.rank, A.val, A.packed, A.cap, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.rtab, A.rt_n,
                         A.rsh, A.ft, A.nd, A.sc);
 }
 
@@ -1448,7 +1507,7 @@ __global__ void __launch_bounds__(kThreads) k_seg_fold(const SegFoldArgs<W, T> A
 
 // Finish the open runs: add the leading pieces of the following tiles until one holds a head.
 // One lane per tile.
-__device__ __forceinline__ void seg_close_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ rank, uint64_t n_tiles,
+__device__ __forceinline__ void seg_close_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ rank, int packed, uint64_t n_tiles,
                                                         const uint64_t *__restrict__ srank, uint64_t ne,
                                                         double *__restrict__ delta, const uint64_t *__restrict__ ins,
                                                         double *__restrict__ seg_sum, double *__restrict__ nsum, FoldTiles ft,
@@ -1464,7 +1523,7 @@ __device__ __forceinline__ void seg_close_body(uint32_t blk, uint32_t nblk, cons
         if (ft.has_head[k]) break;
     }
     seg_sum[r] = acc;
-    const uint64_t rk = rank[r];
+    const uint64_t rk = key_rank(rank[r], packed);
     if (rk == 0) {
         sc->hf_sum = acc;
         sc->hf_hit = 1;
@@ -1479,6 +1538,7 @@ __device__ __forceinline__ void seg_close_body(uint32_t blk, uint32_t nblk, cons
 
 struct SegCloseArgs {
     const uint64_t *rank;
+    int packed;
     uint64_t n_tiles;
     const uint64_t *srank;
     uint64_t ne;
@@ -1492,7 +1552,7 @@ struct SegCloseArgs {
 
 __device__ __forceinline__ void k_seg_close_entry(const SegCloseArgs &A, uint32_t blk, uint32_t nblk)
 {
-    seg_close_body(blk, nblk, A.rank, A.n_tiles, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.nsum, A.ft, A.sc);
+    seg_close_body(blk, nblk, A.rank, A.packed, A.n_tiles, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.nsum, A.ft, A.sc);
 }
 
 __global__ void __launch_bounds__(kThreads) k_seg_close(const SegCloseArgs *__restrict__ args, BatchMap bm)

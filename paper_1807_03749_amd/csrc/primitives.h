@@ -308,13 +308,14 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active)
 }
 
 // ------------------------------------------------------------ onesweep radix passes
-// Keys are 64-bit, sorted by kRadixBits-bit digits from the least significant up.
+// Keys are 64-bit, sorted by kRadixBits-bit digits from bit shift0 up (bits below shift0 are
+// carried, not sorted on: the sort stays stable in the input order for equal sorted bits).
 // Digit histograms of every pass in one read of the keys (they do not depend on the order),
 // aggregated per wavefront and per block before one global atomic per bin.
 constexpr int kRadixMaxPasses = (64 + kRadixBits - 1) / kRadixBits;
 
 __device__ __forceinline__ void radix_ghist_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ key, const uint64_t *__restrict__ n_live,
-                                                          int passes, uint32_t *__restrict__ ghist)
+                                                          int passes, int shift0, uint32_t *__restrict__ ghist)
 {
     const uint64_t n = *n_live;
     __shared__ uint32_t h[kRadixMaxPasses][kRadixBins];
@@ -335,7 +336,8 @@ __device__ __forceinline__ void radix_ghist_body(uint32_t blk, uint32_t nblk, co
             const bool valid = g < n;
             const uint64_t active = __ballot(valid);
             for (int p = 0; p < passes; ++p) {
-                const uint32_t d = (uint32_t)((k[r] >> (kRadixBits * p)) & (kRadixBins - 1));
+                const int sh = shift0 + kRadixBits * p;  // a batch's extra passes may lie past bit 63
+                const uint32_t d = sh < 64 ? (uint32_t)((k[r] >> sh) & (kRadixBins - 1)) : 0u;
                 if (valid) {
                     const uint64_t peers = match_digit(d, active);
                     if (lanes_below(peers) == 0) atomicAdd(&h[p][d], (uint32_t)__popcll(peers));
@@ -353,12 +355,13 @@ struct RadixGhistArgs {
     const uint64_t *key;
     const uint64_t *n_live;
     int passes;
+    int shift0;  // bit of the first digit (the sort key's low bits may carry other data)
     uint32_t *ghist;
 };
 
 __device__ __forceinline__ void k_radix_ghist_entry(const RadixGhistArgs &A, uint32_t blk, uint32_t nblk)
 {
-    radix_ghist_body(blk, nblk, A.key, A.n_live, A.passes, A.ghist);
+    radix_ghist_body(blk, nblk, A.key, A.n_live, A.passes, A.shift0, A.ghist);
 }
 
 __global__ void __launch_bounds__(kThreads) k_radix_ghist(const RadixGhistArgs *__restrict__ args, BatchMap bm)
@@ -372,7 +375,9 @@ __global__ void __launch_bounds__(kThreads) k_radix_ghist(const RadixGhistArgs A
     k_radix_ghist_entry(A, blockIdx.x, gridDim.x);
 }
 
-// One stable pass by the digit at `shift`.  Wavefront w of a tile owns the tile's keys
+// One stable pass by the digit at `shift`, carrying one value of type V per key (the record's
+// amplitude in the annihilation sort; an index generated from the input position when
+// val_in is null, for the processor partition).  Wavefront w of a tile owns the tile's keys
 // [w * 64 * kSortItems, (w + 1) * 64 * kSortItems), 64 per round, and ranks them against its
 // own LDS digit counters (no block barrier between rounds: a wavefront's LDS accesses are in
 // order).  The tile then combines its wavefronts' counts, publishes its per-digit counts,
@@ -382,8 +387,9 @@ __global__ void __launch_bounds__(kThreads) k_radix_ghist(const RadixGhistArgs A
 // digits x + j * kThreads of the per-digit work.
 constexpr int kDigitsPerThread = kRadixBins / kThreads;
 
-__device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ key_in, const uint32_t *__restrict__ idx_in,
-                                                             uint64_t *__restrict__ key_out, uint32_t *__restrict__ idx_out,
+template <typename V>
+__device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ key_in, const V *__restrict__ idx_in,
+                                                             uint64_t *__restrict__ key_out, V *__restrict__ idx_out,
                                                              const uint64_t *__restrict__ n_live, int shift,
                                                              const uint32_t *__restrict__ ghist, uint64_t *__restrict__ status,
                                                              uint64_t *__restrict__ ticket)
@@ -402,21 +408,21 @@ __device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk,
     if (base >= n) return;  // tiles beyond the live count: nobody waits on them
     const uint64_t wbase = base + (uint64_t)w * 64 * kSortItems;
     uint64_t k[kSortItems];
-    uint32_t ix[kSortItems];
+    V ix[kSortItems];
     uint16_t rk[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {  // all loads in flight before the ranking rounds
         const uint64_t g = wbase + (uint64_t)r * 64 + lane;
         const uint64_t gc = g < n ? g : n - 1;  // clamped: unconditional loads
         k[r] = key_in[gc];
-        ix[r] = idx_in ? idx_in[gc] : (uint32_t)g;
+        ix[r] = idx_in ? idx_in[gc] : (V)g;
     }
     uint32_t *cnt = wave_cnt[w];
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const uint64_t g = wbase + (uint64_t)r * 64 + lane;
         const bool valid = g < n;
-        const uint32_t d = (uint32_t)((k[r] >> shift) & (kRadixBins - 1));
+        const uint32_t d = shift < 64 ? (uint32_t)((k[r] >> shift) & (kRadixBins - 1)) : 0u;
         const uint64_t active = __ballot(valid);
         uint32_t rank = 0;
         if (valid) {
@@ -494,7 +500,7 @@ __device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk,
     for (int r = 0; r < kSortItems; ++r) {
         const uint64_t g = wbase + (uint64_t)r * 64 + lane;
         if (g < n) {
-            const uint32_t d = (uint32_t)((k[r] >> shift) & (kRadixBins - 1));
+            const uint32_t d = shift < 64 ? (uint32_t)((k[r] >> shift) & (kRadixBins - 1)) : 0u;
             const uint32_t dst = dig_base[d] + wave_cnt[w][d] + rk[r];
             key_out[dst] = k[r];
             idx_out[dst] = ix[r];
@@ -502,11 +508,12 @@ __device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk,
     }
 }
 
+template <typename V>
 struct RadixOnesweepArgs {
     const uint64_t *key_in;
-    const uint32_t *idx_in;
+    const V *idx_in;
     uint64_t *key_out;
-    uint32_t *idx_out;
+    V *idx_out;
     const uint64_t *n_live;
     int shift;
     const uint32_t *ghist;
@@ -514,20 +521,23 @@ struct RadixOnesweepArgs {
     uint64_t *ticket;
 };
 
-__device__ __forceinline__ void k_radix_onesweep_entry(const RadixOnesweepArgs &A, uint32_t blk, uint32_t nblk)
+template <typename V>
+__device__ __forceinline__ void k_radix_onesweep_entry(const RadixOnesweepArgs<V> &A, uint32_t blk, uint32_t nblk)
 {
-    radix_onesweep_body(blk, nblk, A.key_in, A.idx_in, A.key_out, A.idx_out, A.n_live, A.shift, A.ghist, A.status, A.ticket);
+    radix_onesweep_body<V>(blk, nblk, A.key_in, A.idx_in, A.key_out, A.idx_out, A.n_live, A.shift, A.ghist, A.status, A.ticket);
 }
 
-__global__ void __launch_bounds__(kThreads) k_radix_onesweep(const RadixOnesweepArgs *__restrict__ args, BatchMap bm)
+template <typename V>
+__global__ void __launch_bounds__(kThreads) k_radix_onesweep(const RadixOnesweepArgs<V> *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
-    k_radix_onesweep_entry(args[batch_state(bm, blk, nblk)], blk, nblk);
+    k_radix_onesweep_entry<V>(args[batch_state(bm, blk, nblk)], blk, nblk);
 }
 
-__global__ void __launch_bounds__(kThreads) k_radix_onesweep(const RadixOnesweepArgs A)
+template <typename V>
+__global__ void __launch_bounds__(kThreads) k_radix_onesweep(const RadixOnesweepArgs<V> A)
 {
-    k_radix_onesweep_entry(A, blockIdx.x, gridDim.x);
+    k_radix_onesweep_entry<V>(A, blockIdx.x, gridDim.x);
 }
 
 }  // namespace ccmc

@@ -5,10 +5,13 @@
 
   python -m paper_1807_03749_amd.profile_summary traffic --kernel k_generate --name generate
       --workload W --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv
-      --copy-bytes N --command "..." --out FILE
+      --copy-bytes N --command "..." --out FILE [--last K]
       HBM bytes per dispatch of one kernel: FETCH_SIZE and WRITE_SIZE (KiB per dispatch,
-      averaged over its dispatches), each scaled by expected / measured of the same counter
-      on device copies of N bytes (a read of N and a write of N bytes per copy).
+      averaged over its dispatches, or over its last K dispatches: the steps at the workload's
+      population, after the growth phase), each scaled by expected / measured of the same
+      counter on device copies of N bytes (a read of N and a write of N bytes per copy).  With
+      a comma-separated --kernel list the figure is per step: the listed kernels' bytes summed
+      over their dispatches of the last K steps (one step = one dispatch of the first kernel).
 
   python -m paper_1807_03749_amd.profile_summary valu --pmc P.csv --kernels k_items,k_generate
       --simds 1024 --xcds 8 --workload W --command "..." --out FILE
@@ -77,33 +80,53 @@ def _per_dispatch(path, counter, match):
         if r["Counter_Name"] != counter or not match(r["Kernel_Name"]):
             continue
         vals[r["Dispatch_Id"]] = vals.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
-    return list(vals.values())
+    return [vals[k] for k in sorted(vals, key=int)]  # in dispatch order
 
 
 def traffic(args):
-    kern = lambda n: args.kernel in n
+    names = [k for k in args.kernel.split(",") if k]
     copy = lambda n: "copy" in n.lower()
-    f = _per_dispatch(args.fetch, "FETCH_SIZE", kern)
-    w = _per_dispatch(args.write, "WRITE_SIZE", kern)
     cf = _per_dispatch(args.copy_fetch, "FETCH_SIZE", copy)
     cw = _per_dispatch(args.copy_write, "WRITE_SIZE", copy)
-    if not (f and w and cf and cw):
-        raise SystemExit("traffic: a counter file holds no matching dispatch")
     exp_kib = args.copy_bytes * args.copy_reps / 1024.0
+    if not (cf and cw):
+        raise SystemExit("traffic: a copy counter file holds no copy dispatch")
     sf, sw = exp_kib / sum(cf), exp_kib / sum(cw)
-    fk, wk = sum(f) / len(f), sum(w) / len(w)
+    f, w = [], []
+    steps = None
+    for i, k in enumerate(names):
+        fk = _per_dispatch(args.fetch, "FETCH_SIZE", lambda n, k=k: k in n)
+        wk = _per_dispatch(args.write, "WRITE_SIZE", lambda n, k=k: k in n)
+        if not (fk and wk):
+            raise SystemExit(f"traffic: no dispatch of {k}")
+        if len(names) > 1:  # per step: the last K steps' dispatches of each kernel
+            if i == 0:
+                steps = min(args.last or len(fk), len(fk))
+            per = max(1, round(len(fk) / len(_per_dispatch(args.fetch, "FETCH_SIZE", lambda n: names[0] in n))))
+            fk, wk = fk[-steps * per:], wk[-steps * per:]
+        elif args.last:
+            fk, wk = fk[-args.last:], wk[-args.last:]
+        f.append(fk)
+        w.append(wk)
+    if len(names) > 1:
+        fk = sum(sum(x) for x in f) / steps
+        wk = sum(sum(x) for x in w) / steps
+        f, w = [None] * steps, [None] * steps
+    else:
+        f, w = f[0], w[0]
+        fk, wk = sum(f) / len(f), sum(w) / len(w)
     hbm = (fk * sf + wk * sw) * 1024.0
     lines = [f"# HBM traffic of {args.kernel} ({args.name}) on {args.workload}  ({datetime.date.today().isoformat()})",
              f"# command: {args.command}",
              f"source_hash = {_source_hash()}",
-             f"dispatches_fetch = {len(f)}",
-             f"dispatches_write = {len(w)}",
-             f"fetch_kib_per_dispatch = {fk:.1f}",
-             f"write_kib_per_dispatch = {wk:.1f}",
+             f"{'steps' if len(names) > 1 else 'dispatches'}_fetch = {len(f)}",
+             f"{'steps' if len(names) > 1 else 'dispatches'}_write = {len(w)}",
+             f"fetch_kib_per_{'step' if len(names) > 1 else 'dispatch'} = {fk:.1f}",
+             f"write_kib_per_{'step' if len(names) > 1 else 'dispatch'} = {wk:.1f}",
              f"copy_bytes = {args.copy_bytes} x {args.copy_reps} copies",
              f"copy_fetch_kib_measured = {sum(cf):.1f}  (expected {exp_kib:.1f}, scale {sf:.4f})",
              f"copy_write_kib_measured = {sum(cw):.1f}  (expected {exp_kib:.1f}, scale {sw:.4f})",
-             f"hbm_bytes_per_launch = {hbm:.0f}"]
+             f"hbm_bytes_per_{'step' if len(names) > 1 else 'launch'} = {hbm:.0f}"]
     _write(args.out, lines)
 
 
@@ -148,6 +171,7 @@ def main():
         t.add_argument(a, required=True)
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--copy-reps", type=int, default=5)
+    t.add_argument("--last", type=int, default=0)
     t.add_argument("--out")
     v = sub.add_parser("valu")
     for a in ("--pmc", "--kernels", "--workload", "--command"):

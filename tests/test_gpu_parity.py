@@ -39,6 +39,11 @@ CASES = [
     ("ueg54_246_ccsd_fnc_ms8", dict(system="ueg", n_el=54, n2_max=9), 2,
      dict(full_noncomposite=True, min_spawn_attempts=8, multispawn_threshold=1.0, init_pop=300.0, seed=11),
      0.001, 12, 300),
+    # a truncated space of 2.9e10 determinants: 35-bit ranks, sorted without the record position
+    # beside them (a new determinant's bitstring is recovered from its rank)
+    ("ueg54_246_ccsdt_fnc_wide_ranks", dict(system="ueg", n_el=54, n2_max=9), 3,
+     dict(full_noncomposite=True, min_spawn_attempts=4, multispawn_threshold=1.0, init_pop=300.0, seed=23),
+     0.001, 10, 300),
     ("ueg14_186_ccsd_fnc_w3", dict(system="ueg", n_el=14, n2_max=8), 2,
      dict(full_noncomposite=True, min_spawn_attempts=2, multispawn_threshold=1.0, init_pop=300.0, seed=31), 0.002,
      15, 300),
