@@ -2,15 +2,19 @@
 
 Tolerances (FP64 mode): keys, record ids and every count bit-exact; spawn amplitudes to
 1e-12 relative; death amounts -tau (K - S) A to 1e-12 relative plus the rounding of
-K = H_DD - E_HF itself, |d| eps_K / |K - S| with eps_K = 1e-12 (1 + |E_HF|) (the GPU forms K
-from the holes and particles, the oracle from the full Slater-Condon diagonal, and the two
-differ in their last bits; where K - S nearly cancels that dominates); annihilated
+K = H_DD - E_HF itself, |d| eps_K / |K - S| (the GPU forms K from the holes and particles
+with a few table terms, the oracle from the full Slater-Condon diagonal minus E_HF, which
+cancels terms as large as the diagonal's; where K - S nearly cancels that dominates).  eps_K
+is eight times the random-walk rounding of the oracle's sums: 2^-53 sqrt(n) (A + A_HF) with
+n = N + N^2 terms and A, A_HF bounds on the sums of their magnitudes (N max|h_pp| +
+N^2/2 max|<pq||pq>|, and the same sum over the reference); annihilated
 amplitudes to 1e-12 of the magnitude of what was summed (|N_old| + sum of each record's
 magnitude and error bound), which bounds a sum whatever its cancellation; the
 projected-energy numerator to 1e-11 relative (a tree reduction against a serial one).
 """
 from __future__ import annotations
 
+import math
 from collections import defaultdict
 
 import numpy as np
@@ -41,6 +45,22 @@ def evolve_oracle(R: orc.Run, steps: int, tau: float, first_nsel: int):
     return st
 
 
+_EPS_K = {}
+
+
+def diagonal_rounding(S: orc.System) -> float:
+    """eps_K of the module docstring, once per system."""
+    if id(S) not in _EPS_K:
+        N, M = S.n_el, S.M
+        hmax = max(abs(S.h1(p, p)) for p in range(M))
+        vmax = max(abs(S.u2(p, q, p, q) - S.u2(p, q, q, p)) for p in range(M) for q in range(M) if p != q)
+        a_hf = sum(abs(S.h1(p, p)) for p in range(N)) + 0.5 * sum(
+            abs(S.u2(p, q, p, q) - S.u2(p, q, q, p)) for p in range(N) for q in range(N) if p != q)
+        a_max = N * hmax + 0.5 * N * N * vmax
+        _EPS_K[id(S)] = 8.0 * 2.0 ** -53 * math.sqrt(N + N * N) * (a_max + a_hf)
+    return _EPS_K[id(S)]
+
+
 def key_tuple(k):
     return tuple(int(x) for x in k)
 
@@ -64,12 +84,16 @@ def compare_step(S: orc.System, R: orc.Run, g: ccmc.State, tau: float, shift: fl
     assert np.array_equal(gi, oi), "record ids differ"
     assert np.array_equal(gk, ok_), "record keys differ"
     ehf = S.ehf()
-    eps_k = 1e-12 * (1.0 + abs(ehf))
+    eps_k = diagonal_rounding(S)
     death = (oi & np.uint64((1 << 30) - 1)) == 0
     bound = amp_rtol * np.abs(oa)
+    dk_max = 0.0  # the largest difference of K the death amounts imply
     for r in np.nonzero(death)[0]:
         K = S.hamiltonian(ok_[r], ok_[r]) - ehf
         bound[r] += abs(oa[r]) * eps_k / max(abs(K - shift), 1e-300)
+        if oa[r] != 0.0:
+            dk_max = max(dk_max, abs(ga[r] - oa[r]) * abs(K - shift) / abs(oa[r]))
+    print(f"[parity] death records: implied |dK| up to {dk_max:.2e}, allowance eps_K {eps_k:.2e}", flush=True)
     bad = np.abs(ga - oa) > bound
     assert not bad.any(), (int(bad.sum()), float(np.max(np.abs(ga - oa) - bound)))
     assert np.all(np.abs(ga[~death] - oa[~death]) <= amp_rtol * np.abs(oa[~death]))
