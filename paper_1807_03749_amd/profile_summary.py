@@ -3,6 +3,11 @@
   python -m paper_1807_03749_amd.profile_summary stats <run>_kernel_stats.csv --command "..." --out FILE
       per-kernel dispatch statistics (calls, total / average / min / max duration, share)
 
+  python -m paper_1807_03749_amd.profile_summary trace <run>_kernel_trace.csv --steps K --command "..." --out FILE
+      the same statistics from a per-dispatch kernel trace, over the last K steps only (a step
+      ends with its k_final_part dispatch), so that the growth of the population before the
+      timed steps does not enter them
+
   python -m paper_1807_03749_amd.profile_summary traffic --kernel k_generate --name generate
       --workload W --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv
       --copy-bytes N --command "..." --out FILE [--last K]
@@ -71,6 +76,37 @@ def stats(args):
         lines.append(f"  {_short(r['Name'])[:58]:58s} {int(r['Calls']):7d} {t / 1e6:10.3f} "
                      f"{float(r['AverageNs']) / 1e3:9.2f} {float(r['MinNs']) / 1e3:9.2f} "
                      f"{float(r['MaxNs']) / 1e3:9.2f} {100 * t / tot:5.1f}%")
+    _write(args.out, lines)
+
+
+def trace(args):
+    rows = _rows(args.csv)
+    for r in rows:
+        r["_s"], r["_e"] = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+    rows.sort(key=lambda r: r["_s"])
+    ends = [r["_e"] for r in rows if "k_final_part" in r["Kernel_Name"]]
+    if len(ends) < args.steps + 1:
+        raise SystemExit(f"trace: {len(ends)} steps in the trace, fewer than {args.steps} + 1")
+    t0 = ends[-args.steps - 1]
+    agg = {}
+    for r in rows:
+        if r["_s"] < t0:
+            continue
+        d = r["_e"] - r["_s"]
+        a = agg.setdefault(_short(r["Kernel_Name"]), [0, 0, 1 << 62, 0])
+        a[0] += 1
+        a[1] += d
+        a[2] = min(a[2], d)
+        a[3] = max(a[3], d)
+    tot = sum(a[1] for a in agg.values())
+    lines = [f"# rocprofv3 kernel statistics over the last {args.steps} steps  ({datetime.date.today().isoformat()})",
+             f"# command: {args.command}",
+             f"# source_hash = {_source_hash()}",
+             f"# {'kernel':58s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} {'share':>6s}",]
+    for k, a in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"  {k[:58]:58s} {a[0]:7d} {a[1] / 1e6:10.3f} {a[1] / a[0] / 1e3:9.2f} {a[2] / 1e3:9.2f} "
+                     f"{a[3] / 1e3:9.2f} {100 * a[1] / tot:5.1f}%")
+    lines.append(f"# per step: {tot / 1e3 / args.steps:.1f} us of kernel time")
     _write(args.out, lines)
 
 
@@ -173,6 +209,11 @@ def main():
     t.add_argument("--copy-reps", type=int, default=5)
     t.add_argument("--last", type=int, default=0)
     t.add_argument("--out")
+    r = sub.add_parser("trace")
+    r.add_argument("csv")
+    r.add_argument("--steps", type=int, required=True)
+    r.add_argument("--command", required=True)
+    r.add_argument("--out")
     v = sub.add_parser("valu")
     for a in ("--pmc", "--kernels", "--workload", "--command"):
         v.add_argument(a, required=True)
@@ -180,7 +221,7 @@ def main():
     v.add_argument("--xcds", type=int, default=8)
     v.add_argument("--out")
     args = ap.parse_args()
-    {"stats": stats, "traffic": traffic, "valu": valu}[args.cmd](args)
+    {"stats": stats, "trace": trace, "traffic": traffic, "valu": valu}[args.cmd](args)
 
 
 if __name__ == "__main__":
