@@ -229,7 +229,7 @@ def leg_record(w: inputs.Workload, precision: str, res: dict, steps: int, warmup
                         within_20pct_of_target=bool(abs(res["n_total"] / w.target_population - 1) <= 0.2),
                         shoulder=res["shoulder"]),
         attempts_per_step=res["attempts"] / steps, records_per_step=prof.get("gather", {}).get("items", 0) / nb,
-        roofline=roofline(res["timed"], w), annihilation_roofline=annihilation_roofline(prof),
+        roofline=roofline(res["timed"], w), annihilation_roofline=annihilation_roofline(prof, w),
         kernels={k: dict(avg_ms=p["ms"] / max(p["launches"], 1), launches=p["launches"],
                          items_per_launch=p["items"] / max(p["launches"], 1),
                          bytes_per_launch=p["bytes"] / max(p["launches"], 1)) for k, p in prof.items()},
@@ -250,8 +250,9 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary
+def measured_traffic(kernel: str, workload: str, key: str = "hbm_bytes_per_launch"):
+    """HBM bytes per launch of `kernel` (or per step of a kernel group such as
+    "annihilation", key hbm_bytes_per_step) from the committed counter summary
     (profiles/<kernel>_<workload>_traffic.txt: FETCH_SIZE and WRITE_SIZE per dispatch,
     scaled by the same counters on a copy of known size), or None when the summary is
     missing or was taken on other sources."""
@@ -267,7 +268,7 @@ def measured_traffic(kernel: str, workload: str):
     if kv.get("source_hash") != source_hash():
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
 
@@ -300,16 +301,25 @@ def roofline(timed: dict, w: inputs.Workload):
 ANNIHILATION = ("gather", "radix_ghist", "radix_onesweep", "seg_fold", "seg_close", "merge")
 
 
-def annihilation_roofline(prof: dict):
+def annihilation_roofline(prof: dict, w: inputs.Workload | None = None):
     """Algorithmic HBM bandwidth of the annihilation kernels (sort, fold, merge, rounding,
-    compaction) taken together, from the per-kernel breakdown."""
+    compaction) taken together, from the per-kernel breakdown; with the committed counter
+    summary of the workload (profiles/annihilation_<workload>_traffic.txt, per step), also
+    the measured HBM bytes per step and the bandwidth they give over the same kernel time."""
     names = [n for n in ANNIHILATION if n in prof]
     ms = sum(prof[n]["ms"] for n in names)
     by = sum(prof[n]["bytes"] for n in names)
     if ms <= 0:
         return None
-    return dict(kernels=names, ms=ms, bytes=by, achieved=by / (ms / 1e3) / 1e9, peak=HBM_PEAK_GBS,
-                unit="GB/s", frac=by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS)
+    steps = max(1, prof.get("gather", {}).get("launches", 1))
+    out = dict(kernels=names, ms_per_step=ms / steps, bytes_per_step=by / steps, achieved=by / (ms / 1e3) / 1e9,
+               peak=HBM_PEAK_GBS, unit="GB/s", frac=by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS)
+    t = measured_traffic("annihilation", w.name, "hbm_bytes_per_step") if w is not None else None
+    out["traffic_per_step"] = t
+    if t is not None:
+        gbs = t / (ms / steps / 1e3) / 1e9
+        out.update(measured_gbs=gbs, measured_frac=gbs / HBM_PEAK_GBS)
+    return out
 
 
 def replica_runs(w: inputs.Workload, precision: str, replicas: int, steps: int, equil: int, log):
