@@ -84,7 +84,7 @@ def test_oracle_long_run_matches_deterministic_ccsd():
     rows, mean, sem, stored_ccsd = _stored_long_run()
     es = np.array([e for _, e, _ in rows])
     assert len(rows) >= 4 and mean == pytest.approx(es.mean(), abs=1e-9)
-    assert sem == pytest.approx(es.std(ddof=1) / math.sqrt(len(es)), rel=1e-6)
+    assert sem == pytest.approx(es.std(ddof=1) / math.sqrt(len(es)), rel=1e-4)  # energies stored to 10 digits
     S = ob.System.ueg(14, 2, 1.0)
     ec, _, _ = ccsd.ccsd_doubles(S)
     assert stored_ccsd == pytest.approx(ec, abs=1e-11)  # the stored value is the solver's
