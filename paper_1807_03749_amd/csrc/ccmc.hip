@@ -138,11 +138,9 @@ struct ccmc_state {
     uint64_t step = 0;
     double last_num = 0, last_den = 0;
     // per-step buffers
-    DevBuf P, guide, delta, rtab;
+    DevBuf P, guide, delta, fence, rtab;
     DevBuf drec;  // draw records: prefix, amplitude and bitstring of each excitor, (2 + W) words
     DevBuf vkey[2], perm, seg;  // virtual processors: placement keys, the partition, its segments
-    uint64_t rt_n = 0;   // rank-table buckets
-    uint32_t rsh = 0;    // rank-table shift
     uint64_t last_q = 0; // Q of the last step (sizes the next selection guide)
     DevBuf ikey, iA, ideath, in, icnt, ioff;
     uint64_t icap = 0;
@@ -580,13 +578,10 @@ ccmc_status ensure_store(ccmc_state *st, uint64_t n)
     // the per-entry sums start at zero (a grown buffer holds no contents)
     TRY(ensure(st, st->delta, nc * sizeof(double)));
     k_fill<double><<<grid_for(nc), kThreads, 0, st->stream>>>(ptr<double>(st->delta), nc, 0.0);
-    // rank table: about one bucket per store entry, at most one per rank
-    int rt_bits = 1;
-    while (rt_bits < 40 && (1ull << rt_bits) < nc) ++rt_bits;
-    rt_bits = std::min(rt_bits, std::max(st->rank_bits, 1));
-    st->rt_n = 1ull << rt_bits;
-    st->rsh = (uint32_t)std::max(0, st->rank_bits - rt_bits);
-    TRY(ensure(st, st->rtab, (st->rt_n + 1) * sizeof(uint32_t)));
+    // the lookup index: every kFence-th rank (for a store too large for the cache), and the
+    // rank table, at most one bucket per fence entry rounded up to a power of two (planned per step)
+    TRY(ensure(st, st->fence, (nc / kFence + 2) * sizeof(uint64_t)));
+    TRY(ensure(st, st->rtab, (8 * std::min<uint64_t>(nc, kFenceDirect) + 2 * (nc / kFence) + 2) * sizeof(uint32_t)));
     st->scap = nc;
     return CCMC_OK;
 }
@@ -612,6 +607,8 @@ struct Plan {
     uint64_t o_tick = 0, o_weights = 0, o_off = 0, o_boff = 0, o_merge = 0, o_ghist = 0, o_rstat = 0;
     uint64_t o_fold = 0, o_fin = 0;
     bool packed = false;     // sort keys carry the rank in their high half and the record's position below
+    uint64_t rt_n = 1;       // rank-table buckets of the store lookups, and their shift in rank space
+    uint32_t rsh = 0;
     bool ranked = false;     // virtual processors: the store is partitioned by processor
     uint64_t ptiles = 0;     // radix tiles of the partition
     uint64_t o_pghist = 0, o_pstat = 0;
@@ -721,7 +718,15 @@ ccmc_status plan_sizes(Plan<W, T> &p)
     p.passes = std::max(1, (st->rank_bits + kRadixBits - 1) / kRadixBits);
     p.nb_fnc = p.fnc ? grid_for(p.n_fnc) : 0;
     p.nb_sel = p.n_sel ? grid_for(p.n_sel) : 0;
-    p.nb_rt = ne ? grid_for(st->rt_n) : 0;
+    {  // about one rank-space bucket per fence entry; four per entry for a store in the cache
+        const uint64_t want = fence_stride(ne) > 1 ? fence_count(ne) : 4 * ne;
+        int rt_bits = 1;
+        while (rt_bits < 40 && (1ull << rt_bits) < want) ++rt_bits;
+        rt_bits = std::min(rt_bits, std::max(st->rank_bits, 1));
+        p.rt_n = 1ull << rt_bits;
+        p.rsh = (uint32_t)std::max(0, st->rank_bits - rt_bits);
+    }
+    p.nb_rt = ne ? (fence_stride(ne) > 1 ? grid_for(fence_count(ne)) : 0) + grid_for(p.rt_n) : 0;
     p.n_parts = p.nb_fnc + p.nb_sel;
     const size_t nparts = (size_t)(p.n_parts + 1);
     TRY(ensure(st, st->num_part, nparts * sizeof(double)));
@@ -1041,7 +1046,8 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
             auto &p = ps[i];
             ccmc_state *st = p.st;
             const uint64_t *srank = ptr<uint64_t>(st->srank[p.c]);
-            const RankTable rt{srank, p.ne, ptr<uint32_t>(st->rtab), st->rt_n, st->rsh};
+            const Fence rt{srank, p.ne, ptr<uint64_t>(st->fence), ptr<uint32_t>(st->rtab), p.rt_n, p.rsh};
+            // with fs = 1 the fence is the store's ranks themselves
             args.push_back(A{st->sd, ptr<uint64_t>(st->skey[p.c]), ptr<T>(st->samp[p.c]), ptr<T>(st->sK[p.c]), st->scap,
                              p.ne, ptr<uint64_t>(st->P), ptr<uint64_t>(st->drec), ptr<uint32_t>(st->guide),
                              Ranks{p.ranked ? ptr<uint32_t>(st->perm) : nullptr, p.ranked ? ptr<uint32_t>(st->seg) : nullptr},
@@ -1180,7 +1186,8 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
                              st->dcap, ptr<uint64_t>(st->dkey), st->dcap};
             args.push_back(A{st->sd, ptr<uint64_t>(st->sr[sorted]), ptr<T>(st->sval[sorted]), p.packed ? 1 : 0, p.rec_cap,
                              ptr<uint64_t>(st->srank[p.c]), p.ne, ptr<double>(st->delta), ptr<uint64_t>(st->ins),
-                             ptr<double>(st->seg_sum), ptr<uint32_t>(st->rtab), st->rt_n, st->rsh, fold_of(p), nd, p.sc});
+                             ptr<double>(st->seg_sum), fence_stride(p.ne) > 1 ? ptr<uint64_t>(st->fence) : ptr<uint64_t>(st->srank[p.c]),
+                             ptr<uint32_t>(st->rtab), p.rt_n, p.rsh, fold_of(p), nd, p.sc});
             blk[i] = (uint32_t)p.fold_tiles;
         }
         // bytes: each sorted (rank, amplitude) pair and (per head) the new-determinant entry
@@ -1648,7 +1655,7 @@ void destroy(ccmc_state *st)
     if (st->stream) (void)hipStreamSynchronize(st->stream);
     DevBuf *bufs[] = {&st->t_grid, &st->t_nvec, &st->t_vq, &st->t_h, &st->t_eri, &st->t_fock, &st->t_vpair,
                       &st->t_binv, &st->t_bino, &st->skey[0], &st->skey[1], &st->samp[0], &st->samp[1], &st->sK[0],
-                      &st->sK[1], &st->srank[0], &st->srank[1], &st->P, &st->drec, &st->guide, &st->delta, &st->rtab, &st->ikey,
+                      &st->sK[1], &st->srank[0], &st->srank[1], &st->P, &st->drec, &st->guide, &st->delta, &st->fence, &st->rtab, &st->ikey,
                       &st->iA, &st->ideath, &st->in, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,
                       &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->boff, &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
                       &st->sval[0], &st->sval[1], &st->tile_region,

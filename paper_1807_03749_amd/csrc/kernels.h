@@ -284,31 +284,54 @@ __global__ void __launch_bounds__(kThreads) k_place(const PlaceArgs<W> A)
     k_place_entry<W>(A, blockIdx.x, gridDim.x);
 }
 
-// The rank table of the store lookups: rtab[c] is the first store entry whose rank is at
-// least c << rsh, so a rank r lies in [rtab[r >> rsh], rtab[(r >> rsh) + 1]].  One lane per
-// bucket (binary search); these lanes ride along in the items launch, which waits on memory.
-struct RankTable {
+// The index of the store lookups, in two levels.  The fence holds every fs-th rank of the
+// sorted store, fence[k] = rank[k fs] (k < nf): with fs = kFence a run of fs consecutive ranks
+// is one 128-byte line; a store small enough to stay in the cache takes fs = 1 (the fence is the
+// ranks themselves, and the lookup skips its second level).  The rank table
+// rtab[c] = first k with fence[k] >= c << rsh (c < rt_n) narrows the fence search for a rank r
+// to k in [rtab[r >> rsh], rtab[(r >> rsh) + 1]].  Both ride
+// along in the items launch, which waits on memory: a lane per fence entry copies its rank, a
+// lane per bucket searches the ranks at fence positions.  (Buckets that point into the whole
+// store needed a binary search per bucket with a dependent line fetch per probe, about 10 GB
+// per step at 5x10^6 excitors; lanes per store entry that fill the buckets above their rank
+// make fills as long and uneven as the gaps between ranks in a space of 7x10^8 determinants.)
+constexpr uint64_t kFence = 16;
+constexpr uint64_t kFenceDirect = 1ull << 17;  // stores up to this many entries (1 MB of ranks) take fs = 1
+
+__host__ __device__ __forceinline__ uint64_t fence_stride(uint64_t ne) { return ne <= kFenceDirect ? 1 : kFence; }
+__host__ __device__ __forceinline__ uint64_t fence_count(uint64_t ne) { return (ne + fence_stride(ne) - 1) / fence_stride(ne); }
+
+struct Fence {
     const uint64_t *srank;
     uint64_t ne;
+    uint64_t *fence;
     uint32_t *rtab;
     uint64_t rt_n;
     uint32_t rsh;
 };
 
-__device__ __forceinline__ void rank_table_block(unsigned blk, const RankTable &rt)
+// blocks [0, fence blocks): the fence (none with fs = 1); the blocks after them: the rank table
+__device__ __forceinline__ void fence_block(unsigned blk, const Fence &f)
 {
-    const uint64_t c = (uint64_t)blk * kThreads + threadIdx.x;
-    if (c >= rt.rt_n) return;
-    const uint64_t key = c << rt.rsh;
-    uint64_t l0 = 0, h0 = rt.ne;
+    const uint64_t fs = fence_stride(f.ne), nf = fence_count(f.ne);
+    const unsigned nbf = fs > 1 ? (unsigned)((nf + kThreads - 1) / kThreads) : 0u;
+    if (blk < nbf) {
+        const uint64_t k = (uint64_t)blk * kThreads + threadIdx.x;
+        if (k < nf) f.fence[k] = f.srank[k * fs];
+        return;
+    }
+    const uint64_t c = (uint64_t)(blk - nbf) * kThreads + threadIdx.x;
+    if (c >= f.rt_n) return;
+    const uint64_t key = c << f.rsh;
+    uint64_t l0 = 0, h0 = nf;
     while (l0 < h0) {
         const uint64_t mid = (l0 + h0) >> 1;
-        if (rt.srank[mid] < key)
+        if (f.srank[mid * fs] < key)
             l0 = mid + 1;
         else
             h0 = mid;
     }
-    rt.rtab[c] = (uint32_t)l0;
+    f.rtab[c] = (uint32_t)l0;
 }
 
 // ------------------------------------- co-location of excitors over iterations (Sec. III.B)
@@ -656,10 +679,10 @@ __device__ __forceinline__ void items_body(uint32_t blk, uint32_t nblk, SysDev S
                                                     const uint64_t *__restrict__ P, const uint64_t *__restrict__ drec,
                                                     const uint32_t *__restrict__ guide,
                                                     Ranks rk, double n0, StepArgs a, Items<T> it, unsigned nb_fnc, uint64_t n_fnc,
-                                                    unsigned nb_items, RankTable rt, ItemPartials part, Scratch *sc)
+                                                    unsigned nb_items, Fence rt, ItemPartials part, Scratch *sc)
 {
-    if (blk >= nb_items) {  // trailing blocks: the rank table for the annihilation
-        rank_table_block(blk - nb_items, rt);
+    if (blk >= nb_items) {  // trailing blocks: the fence of the store lookups
+        fence_block(blk - nb_items, rt);
         return;
     }
     // a prefix beyond 2^53 makes the selection probabilities inexact: refuse the step
@@ -692,7 +715,7 @@ struct ItemsArgs {
     unsigned nb_fnc;
     uint64_t n_fnc;
     unsigned nb_items;
-    RankTable rt;
+    Fence rt;
     ItemPartials part;
     Scratch *sc;
 };
@@ -1274,7 +1297,8 @@ __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const
                                                        const uint64_t *__restrict__ srank, uint64_t ne,
                                                        double *__restrict__ delta, uint64_t *__restrict__ ins,
                                                        double *__restrict__ seg_sum,
-                                                       const uint32_t *__restrict__ rtab, uint64_t rt_n, uint32_t rsh,
+                                                       const uint64_t *__restrict__ fence, const uint32_t *__restrict__ rtab,
+                                                       uint64_t rt_n, uint32_t rsh,
                                                        FoldTiles ft, NewDets nd, Scratch *sc)
 {
     __shared__ double s_lead[kThreads];
@@ -1364,18 +1388,48 @@ __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const
         }
         acc[i] = sum;
     }
-    // store lookups of all heads of this thread in lock step: first entry with rank >= rk,
-    // within the range the rank table gives
+    // store lookups of all heads of this thread in lock step: first entry with rank >= rk.
+    // The fence first: the first chunk whose leading rank exceeds rk (f in [0, nf]); the entry
+    // then lies in [(f-1) kFence, min(f kFence, ne)] (0 when f = 0).
+    const uint32_t nf = (uint32_t)fence_count(ne), fs = (uint32_t)fence_stride(ne);
     uint32_t lo[kFoldItems], hi[kFoldItems];
 #pragma unroll
     for (int i = 0; i < kFoldItems; ++i) {
         lo[i] = hi[i] = 0;
-        if (head[i] && rr[i] != 0 && ne) {
+        if (head[i] && rr[i] != 0 && ne) {  // the fence range of the rank's bucket
             const uint64_t c = rr[i] >> rsh;
             lo[i] = rtab[c];
-            hi[i] = c + 1 < rt_n ? rtab[c + 1] : (uint32_t)ne;
+            hi[i] = c + 1 < rt_n ? rtab[c + 1] : nf;
         }
     }
+    if (fs > 1) {
+        // the first fence entry of the range with fence[k] > rk, else the range's end
+        for (bool busy = true; busy;) {
+            busy = false;
+#pragma unroll
+            for (int i = 0; i < kFoldItems; ++i) {
+                if (lo[i] < hi[i]) {
+                    const uint32_t mid = (lo[i] + hi[i]) >> 1;
+                    if (fence[mid] > rr[i])
+                        hi[i] = mid;
+                    else
+                        lo[i] = mid + 1;
+                    busy |= lo[i] < hi[i];
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kFoldItems; ++i) {
+            const uint32_t f = lo[i];
+            if (head[i] && rr[i] != 0 && ne && f > 0) {
+                lo[i] = (f - 1) * fs;
+                hi[i] = f * fs < ne ? f * fs : (uint32_t)ne;
+            } else {
+                lo[i] = hi[i] = 0;
+            }
+        }
+    }
+    // with fs = 1 the bucket's range is already the range of store entries to search
     for (bool busy = true; busy;) {
         busy = false;
 #pragma unroll
@@ -1477,6 +1531,7 @@ struct SegFoldArgs {
     double *delta;
     uint64_t *ins;
     double *seg_sum;
+    const uint64_t *fence;
     const uint32_t *rtab;
     uint64_t rt_n;
     uint32_t rsh;
@@ -1488,8 +1543,8 @@ struct SegFoldArgs {
 template <int W, typename T>
 __device__ __forceinline__ void k_seg_fold_entry(const SegFoldArgs<W, T> &A, uint32_t blk, uint32_t nblk)
 {
-    seg_fold_body<W, T>(blk, nblk, A.S, A.rank, A.val, A.packed, A.cap, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.rtab, A.rt_n,
-                        A.rsh, A.ft, A.nd, A.sc);
+    seg_fold_body<W, T>(blk, nblk, A.S, A.rank, A.val, A.packed, A.cap, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.fence,
+                        A.rtab, A.rt_n, A.rsh, A.ft, A.nd, A.sc);
 }
 
 template <int W, typename T>
