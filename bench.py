@@ -479,11 +479,16 @@ def serving_benchmark(n_requests: int, max_steps: int, tol: float, budget: float
     res = srv.run(reqs)
     wall = time.perf_counter() - t0
     out = serve.summary(res, wall)
+    est = sorted(r.steps * (r.error / tol) ** 2 for r in res if r.outcome == "capped" and r.error == r.error)
+    out["capped_steps_to_tol_median"] = float(np.median(est)) if est else None
     out.update(batch_steps=srv.batch_steps, state_steps=srv.state_steps, max_steps=max_steps, tol=tol,
                hbm_budget=budget, slots=slots,
                per_request=[dict(id=r.request_id, arrival=round(r.arrival, 3), tte=round(r.time_to_energy, 3),
                                  steps=r.steps, e=r.energy, err=r.error, outcome=r.outcome,
                                  shoulder=round(r.shoulder, 2),
+                                 # a capped solve's error falls as 1/sqrt(steps): the steps it would need
+                                 **({"steps_to_tol_estimate": round(r.steps * (r.error / tol) ** 2)}
+                                    if r.outcome == "capped" and r.error == r.error else {}),
                                  **({"failed": r.failed} if r.failed else {}),
                                  **({"grown": r.grown} if r.grown else {})) for r in res])
     return out

@@ -126,7 +126,7 @@ struct ccmc_state {
     HostSys hs;
     SysDev sd{};
     std::vector<DevBuf *> all;
-    DevBuf t_grid, t_nvec, t_vq, t_h, t_eri, t_fock, t_vpair, t_binv, t_bino;
+    DevBuf t_grid, t_nvec, t_vq, t_h, t_eri, t_fock, t_vpair, t_binv, t_bino, t_pairs, t_kpack;
     int rank_bits = 0;  // bits of the largest truncated-space rank
     // the store: current buffer cur, merge target 1 - cur
     DevBuf skey[2], samp[2], sK[2], srank[2];
@@ -496,7 +496,26 @@ ccmc_status upload_system(ccmc_state *st, const ccmc_integrals *ints)
     TRY(upload_table<T>(st, st->t_vpair, hs.vpair));
     S.fock = st->t_fock.p;
     S.vpair = st->t_vpair.p;
+    {  // occupied pairs (x < y) in lexicographic rank order, for the generators' pair draws
+        std::vector<uint32_t> pr;
+        for (int x = 0; x < hs.nel; ++x)
+            for (int y = x + 1; y < hs.nel; ++y) pr.push_back((uint32_t)x | ((uint32_t)y << 16));
+        pr.push_back(0);
+        TRY(ensure(st, st->t_pairs, pr.size() * sizeof(uint32_t)));
+        HIP_TRY(hipMemcpy(st->t_pairs.p, pr.data(), pr.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        S.pairs = ptr<uint32_t>(st->t_pairs);
+    }
     if (hs.kind == CCMC_UEG) {
+        if (hs.G > 127) {
+            st->err = "UEG basis too wide for the packed wavevectors (|n_i| > 127)";
+            return CCMC_EINVAL;
+        }
+        std::vector<uint32_t> kp((size_t)hs.nsp + 1, 0);
+        for (int p = 0; p < hs.nsp; ++p)
+            for (int c = 0; c < 3; ++c) kp[p] |= (uint32_t)(hs.nvec[3 * p + c] + hs.G + 256) << (10 * c);
+        TRY(ensure(st, st->t_kpack, kp.size() * sizeof(uint32_t)));
+        HIP_TRY(hipMemcpy(st->t_kpack.p, kp.data(), kp.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        S.kpack = ptr<uint32_t>(st->t_kpack);
         S.G = hs.G;
         TRY(ensure(st, st->t_grid, hs.grid.size() * sizeof(int)));
         HIP_TRY(hipMemcpy(st->t_grid.p, hs.grid.data(), hs.grid.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -1653,7 +1672,7 @@ void destroy(ccmc_state *st)
 {
     if (!st) return;
     if (st->stream) (void)hipStreamSynchronize(st->stream);
-    DevBuf *bufs[] = {&st->t_grid, &st->t_nvec, &st->t_vq, &st->t_h, &st->t_eri, &st->t_fock, &st->t_vpair,
+    DevBuf *bufs[] = {&st->t_pairs, &st->t_kpack, &st->t_grid, &st->t_nvec, &st->t_vq, &st->t_h, &st->t_eri, &st->t_fock, &st->t_vpair,
                       &st->t_binv, &st->t_bino, &st->skey[0], &st->skey[1], &st->samp[0], &st->samp[1], &st->sK[0],
                       &st->sK[1], &st->srank[0], &st->srank[1], &st->P, &st->drec, &st->guide, &st->delta, &st->fence, &st->rtab, &st->ikey,
                       &st->iA, &st->ideath, &st->in, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,

@@ -38,6 +38,9 @@ struct SysDev {
     // ranks in the truncated space (see space_rank)
     const uint64_t *binom_v;  // [(M+1) * 9]: C(n, j), j <= 8
     const uint64_t *binom_o;  // [(N+1) * (N+1)]: C(n, k), saturating
+    // excitation generators
+    const uint32_t *pairs;    // [N (N-1) / 2]: the pair (x < y) of each rank, x | y << 16 (lexicographic)
+    const uint32_t *kpack;    // UEG [nsp]: wavevector components + G + 256 in 10-bit fields (x, y, z)
 };
 
 // ------------------------------------------------------------------ Philox4x32-10
@@ -485,21 +488,6 @@ __device__ __forceinline__ int draw_size(double u, int lo, int hi)
 __device__ __forceinline__ double size_prob(int s, int lo, int hi)
 {
     return (s < hi) ? ldexp(1.0, -(s - lo + 1)) : ldexp(1.0, -(hi - lo));
-}
-
-// Pair (x < y) of rank r in lexicographic order over n items.  Row x starts at
-// S(x) = x (2n - x - 1) / 2; x is the root of S(x) = r rounded down, then corrected by one
-// step either way against rounding of the square root.
-__device__ __forceinline__ void unrank_pair(int n, uint32_t r, int &x, int &y)
-{
-    const double b = 2.0 * n - 1.0;
-    int t = (int)floor(0.5 * (b - sqrt(b * b - 8.0 * (double)r)));
-    t = t < 0 ? 0 : (t > n - 2 ? n - 2 : t);
-    auto start = [n](int v) { return (uint32_t)(v * (2 * n - v - 1) / 2); };
-    if (start(t) > r) --t;
-    else if (t + 1 <= n - 2 && start(t + 1) <= r) ++t;
-    x = t;
-    y = x + 1 + (int)(r - start(t));
 }
 
 }  // namespace ccmc

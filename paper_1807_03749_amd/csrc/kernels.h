@@ -769,15 +769,16 @@ __device__ __forceinline__ bool gen_excitation(const SysDev &S, const uint64_t *
     if (S.kind == kSystemUEG) {
         const uint32_t pr = (uint32_t)below(r.get(0), S.npairs);
         const int alpha = (int)below(r.get(1), S.half);
-        int xa, ya;
-        unrank_pair(N, pr, xa, ya);
-        i = select_bit<W>(d, xa);
-        j = select_bit<W>(d, ya);
+        const uint32_t xy = S.pairs[pr];  // the pair (x < y) of lexicographic rank pr, tabulated
+        i = select_bit<W>(d, (int)(xy & 0xFFFFu));
+        j = select_bit<W>(d, (int)(xy >> 16));
         ta = 2 * alpha + (i & 1);
         if (bit_test<W>(d, ta)) return false;
-        const int *ni = S.nvec + 3 * (i >> 1), *nj = S.nvec + 3 * (j >> 1), *na = S.nvec + 3 * (ta >> 1);
-        const int bx = ni[0] + nj[0] - na[0], by = ni[1] + nj[1] - na[1], bz = ni[2] + nj[2] - na[2];
+        // k_b = k_i + k_j - k_a, all three components in one integer sum of the packed fields
+        // (each field stays inside its 10 bits: no carry or borrow crosses between them)
         const int G = S.G, D = 2 * G + 1;
+        const int s3 = (int)S.kpack[i >> 1] + (int)S.kpack[j >> 1] - (int)S.kpack[ta >> 1];
+        const int bx = (s3 & 1023) - 256 - G, by = ((s3 >> 10) & 1023) - 256 - G, bz = ((s3 >> 20) & 1023) - 256 - G;
         if (bx < -G || bx > G || by < -G || by > G || bz < -G || bz > G) return false;
         const int beta = S.grid[((bx + G) * D + (by + G)) * D + (bz + G)];
         if (beta < 0) return false;
@@ -791,10 +792,9 @@ __device__ __forceinline__ bool gen_excitation(const SysDev &S, const uint64_t *
             ta = 2 * (int)below(r.get(2), S.half) + (i & 1);
             if (bit_test<W>(d, ta)) return false;
         } else {
-            int xa, ya;
-            unrank_pair(N, (uint32_t)below(r.get(1), S.npairs), xa, ya);
-            i = select_bit<W>(d, xa);
-            j = select_bit<W>(d, ya);
+            const uint32_t xy = S.pairs[(uint32_t)below(r.get(1), S.npairs)];
+            i = select_bit<W>(d, (int)(xy & 0xFFFFu));
+            j = select_bit<W>(d, (int)(xy >> 16));
             ta = 2 * (int)below(r.get(2), S.half) + (i & 1);
             tb = 2 * (int)below(r.get(3), S.half) + (j & 1);
             if (ta == tb || bit_test<W>(d, ta) || bit_test<W>(d, tb)) return false;
@@ -1253,10 +1253,12 @@ __global__ void __launch_bounds__(kThreads) k_gather(const GatherArgs<W, T> A)
 // ---------------------------------------------------------------- annihilation
 // Records are sorted by rank (equal ranks = equal determinants, ascending rank = ascending
 // key) and, within a determinant, by record id (the sort is stable).  The contributions to a
-// determinant are summed in record order in two levels: each thread left-folds the pieces of
-// runs among its kFoldItems consecutive records, and a run's head then adds the pieces of the
-// following threads and tiles in order.  The grouping is fixed by the tiling, so the sums are
-// reproducible and equal the plain left fold up to rounding order.  The head of each run looks
+// determinant are summed in three levels: each thread left-folds the pieces of runs among its
+// kFoldItems consecutive records; a segmented suffix scan over the threads of a tile sums the
+// following threads' pieces of a run (a tree of log2(kThreads) rounds, so a run as long as the
+// tile costs no serial walk); a run's head adds that sum, then the pieces of the following
+// tiles in order.  The grouping is fixed by the tiling, so the sums are reproducible and equal
+// the plain left fold up to rounding order.  The head of each run looks
 // its rank up in the store: a hit adds to that entry, the reference (rank 0) adds to N_0, a
 // miss becomes a new excitor at insertion point ins.  A run that continues past its tile is
 // left "open": its head is finished by k_seg_close once every tile's leading piece is known.
@@ -1356,6 +1358,28 @@ __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const
     s_lead[threadIdx.x] = lead;
     s_head[threadIdx.x] = any;
     __syncthreads();
+    // segmented suffix sums over the threads (Hillis-Steele, log2(kThreads) rounds): afterwards
+    // s_lead[t] is the sum of the leading pieces of threads t .. e, e the first thread >= t
+    // holding a head (or the last thread), and s_head[t] tells whether there is such a head
+    {
+        const uint32_t t = threadIdx.x;
+        double rv = lead;
+        uint32_t rf = any;
+#pragma unroll
+        for (uint32_t off = 1; off < (uint32_t)kThreads; off <<= 1) {
+            const bool in = t + off < (uint32_t)kThreads;
+            const double ov = in ? s_lead[t + off] : 0.0;
+            const uint32_t of = in ? s_head[t + off] : 0u;
+            __syncthreads();
+            if (!rf && in) {
+                rv += ov;
+                rf = of;
+            }
+            s_lead[t] = rv;
+            s_head[t] = rf;
+            __syncthreads();
+        }
+    }
     // runs that start here: fold the rest of this thread's piece, then the following pieces
     double acc[kFoldItems];
     bool open[kFoldItems];
@@ -1378,13 +1402,13 @@ __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const
             }
         }
         if (m == kFoldItems && rr[kFoldItems] == rk) {  // the run continues into the next thread
-            int k = threadIdx.x + 1;
-            for (; k < kThreads; ++k) {
-                sum += s_lead[k];
-                if (s_head[k]) break;
+            bool to_end = true;  // no head after this thread: the run reaches the tile's end
+            if (threadIdx.x + 1 < kThreads) {
+                sum += s_lead[threadIdx.x + 1];
+                to_end = !s_head[threadIdx.x + 1];
             }
             // past the tile end: continues if the next tile starts with the same rank
-            open[i] = k == kThreads && base + kFoldTile < n && key_rank(rank[base + kFoldTile], packed) == rk;
+            open[i] = to_end && base + kFoldTile < n && key_rank(rank[base + kFoldTile], packed) == rk;
         }
         acc[i] = sum;
     }
@@ -1503,17 +1527,8 @@ __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double tl = 0.0;  // the tile's leading piece, in record order
-        uint32_t hh = 0;
-        for (int k = 0; k < kThreads; ++k) {
-            tl += s_lead[k];
-            if (s_head[k]) {
-                hh = 1;
-                break;
-            }
-        }
-        ft.lead[tile] = tl;
-        ft.has_head[tile] = hh;
+        ft.lead[tile] = s_lead[0];  // the tile's leading piece
+        ft.has_head[tile] = s_head[0];
         ft.open[tile] = s_open;
         ft.open_new[tile] = s_open_new;
     }
