@@ -149,7 +149,7 @@ struct ccmc_state {
     DevBuf rkey, ramp, rid;  // per-block record regions
     uint64_t rcap = 0;              // region slots
     DevBuf drank, dkey, damp, did, sr[2], sval[2], tile_region;
-    DevBuf ins, seg_sum, nkey, nrank, nins, nsum;
+    DevBuf nkey, nrank, nins, nsum;
     uint64_t dcap = 0;  // dense record capacity
     uint64_t slot_hint = 1 << 16, rec_hint = 1 << 14;  // capacities planned for the next step
     uint64_t cnt_slots = 0, cnt_rec = 0, cnt_merged = 0, cnt_new = 0, cnt_att = 0, cnt_live_items = 0;  // live counts of the last step
@@ -606,7 +606,7 @@ ccmc_status ensure_store(ccmc_state *st, uint64_t n)
 }
 
 // ---------------------------------------------------------------------- the step
-constexpr uint64_t kMaxFinalParts = 512;  // blocks of the first stage of the final reduction
+constexpr uint64_t kMaxFinalParts = kThreads * kFinalPerThread;  // blocks of the first stage of the final reduction
 
 // Per-state plan of one batched step: sizes, capacities, the layout of the step area and
 // every pointer the kernels need.  Planning allocates; nothing is launched before every state
@@ -721,10 +721,10 @@ ccmc_status plan_sizes(Plan<W, T> &p)
         const uint64_t nc = p.rec_cap + 1;
         for (DevBuf *b : {&st->dkey, &st->nkey}) TRY(ensure(st, *b, nc * W * sizeof(uint64_t)));
         TRY(ensure(st, st->damp, nc * sizeof(T)));
-        for (DevBuf *b : {&st->drank, &st->sr[0], &st->sr[1], &st->ins, &st->nins, &st->nrank})
+        for (DevBuf *b : {&st->drank, &st->sr[0], &st->sr[1], &st->nins, &st->nrank})
             TRY(ensure(st, *b, nc * sizeof(uint64_t)));
         for (DevBuf *b : {&st->sval[0], &st->sval[1]}) TRY(ensure(st, *b, nc * sizeof(T)));
-        for (DevBuf *b : {&st->seg_sum, &st->nsum}) TRY(ensure(st, *b, nc * sizeof(double)));
+        TRY(ensure(st, st->nsum, nc * sizeof(double)));
         TRY(ensure(st, st->tile_region, (nc / kGatherTile + 2) * sizeof(uint32_t)));
         st->dcap = nc;
     }
@@ -776,7 +776,7 @@ ccmc_status plan_area(Plan<W, T> &p, int passes)
     p.o_ghist = p.o_merge + grid_for(p.mcap, kMergeTile);
     p.o_rstat = p.o_ghist + (uint64_t)passes * kRadixBins / 2;
     p.o_fold = p.o_rstat + (uint64_t)passes * p.tiles * kRadixBins;
-    p.o_pghist = p.o_fold + 5 * p.fold_tiles;  // lead, has_head, open, open_new, look-back status
+    p.o_pghist = p.o_fold + 8 * p.fold_tiles;  // lead, has_head, open, open_new, look-back status, open run
     p.o_pstat = p.o_pghist + kRadixBins / 2;
     p.o_fin = p.o_pstat + p.ptiles * kRadixBins;
     p.lb_words = p.o_fin + kMaxFinalParts * (sizeof(FinalPart) / 8);
@@ -1193,7 +1193,8 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
         uint64_t *f = p.lb + p.o_fold;
         const uint64_t nt = p.fold_tiles;
         return FoldTiles{reinterpret_cast<double *>(f), reinterpret_cast<uint32_t *>(f + nt), f + 2 * nt, f + 3 * nt,
-                         f + 4 * nt, p.lb + p.o_tick + kTkFold};
+                         f + 4 * nt, reinterpret_cast<double *>(f + 5 * nt), f + 6 * nt, f + 7 * nt,
+                         p.lb + p.o_tick + kTkFold};
     };
     {
         using A = SegFoldArgs<W, T>;
@@ -1204,8 +1205,8 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
             const NewDets nd{ptr<uint64_t>(st->nkey), ptr<uint64_t>(st->nrank), ptr<uint64_t>(st->nins), ptr<double>(st->nsum),
                              st->dcap, ptr<uint64_t>(st->dkey), st->dcap};
             args.push_back(A{st->sd, ptr<uint64_t>(st->sr[sorted]), ptr<T>(st->sval[sorted]), p.packed ? 1 : 0, p.rec_cap,
-                             ptr<uint64_t>(st->srank[p.c]), p.ne, ptr<double>(st->delta), ptr<uint64_t>(st->ins),
-                             ptr<double>(st->seg_sum), fence_stride(p.ne) > 1 ? ptr<uint64_t>(st->fence) : ptr<uint64_t>(st->srank[p.c]),
+                             ptr<uint64_t>(st->srank[p.c]), p.ne, ptr<double>(st->delta),
+                             fence_stride(p.ne) > 1 ? ptr<uint64_t>(st->fence) : ptr<uint64_t>(st->srank[p.c]),
                              ptr<uint32_t>(st->rtab), p.rt_n, p.rsh, fold_of(p), nd, p.sc});
             blk[i] = (uint32_t)p.fold_tiles;
         }
@@ -1218,12 +1219,11 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
             ccmc_state *st = p.st;
-            args.push_back(SegCloseArgs{ptr<uint64_t>(st->sr[sorted]), p.packed ? 1 : 0, p.fold_tiles, ptr<uint64_t>(st->srank[p.c]), p.ne,
-                                        ptr<double>(st->delta), ptr<uint64_t>(st->ins), ptr<double>(st->seg_sum),
+            args.push_back(SegCloseArgs{p.fold_tiles, ptr<uint64_t>(st->srank[p.c]), p.ne, ptr<double>(st->delta),
                                         ptr<double>(st->nsum), fold_of(p), p.sc});
             blk[i] = grid_for(p.fold_tiles);
         }
-        stage(ar, recs, "seg_close", args, blk, works([&](auto &p) { return Work{24.0, nullptr, p.fold_tiles}; }),
+        stage(ar, recs, "seg_close", args, blk, works([&](auto &p) { return Work{48.0, nullptr, p.fold_tiles}; }),
               [s](const auto &a, unsigned g, auto... bm) { k_seg_close<<<g, kThreads, 0, s>>>(a, bm...); });
     }
     // ---- (a12, a13) merge, round and compact into the other store buffer
@@ -1678,7 +1678,7 @@ void destroy(ccmc_state *st)
                       &st->iA, &st->ideath, &st->in, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,
                       &st->block_item, &st->gcount, &st->gspawn, &st->gdeath, &st->boff, &st->rkey, &st->ramp, &st->rid, &st->drank, &st->dkey, &st->damp, &st->did, &st->sr[0], &st->sr[1],
                       &st->sval[0], &st->sval[1], &st->tile_region,
-                      &st->ins, &st->seg_sum, &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->lb, &st->arg_dev,
+                      &st->nkey, &st->nrank, &st->nins, &st->nsum, &st->lb, &st->arg_dev,
                       &st->vkey[0], &st->vkey[1], &st->perm, &st->seg};
     for (DevBuf *b : bufs) release(st, *b);
     for (auto &p : st->pending) {

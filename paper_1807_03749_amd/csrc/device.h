@@ -114,31 +114,41 @@ __device__ __forceinline__ int count_below(const uint64_t *d, int p)
 // position of the n-th set bit (0-based) of a 64-bit word
 __device__ __forceinline__ int select64(uint64_t x, int n)
 {
-    int pos = 0;
+    // the half first, then five halving rounds on 32-bit words
+    const uint32_t lo = (uint32_t)x;
+    const int c0 = __popc(lo);
+    const bool up = n >= c0;
+    uint32_t v = up ? (uint32_t)(x >> 32) : lo;
+    n = up ? n - c0 : n;
+    int pos = up ? 32 : 0;
 #pragma unroll
-    for (int s = 32; s > 0; s >>= 1) {
-        const int c = __popcll(x & ((1ull << s) - 1ull));
-        if (n >= c) {
-            n -= c;
-            x >>= s;
-            pos += s;
-        }
+    for (int s = 16; s > 0; s >>= 1) {
+        const int c = __popc(v & ((1u << s) - 1u));
+        const bool g = n >= c;
+        n = g ? n - c : n;
+        v = g ? v >> s : v;
+        pos += g ? s : 0;
     }
     return pos;
 }
-// orbital of the n-th occupied spin orbital of d
+// orbital of the n-th occupied spin orbital of d (-1 if d has at most n): the word is chosen
+// by running popcounts, then one select within it
 template <int W>
 __device__ __forceinline__ int select_bit(const uint64_t *d, int n)
 {
+    uint64_t x = d[0];
     int base = 0;
+    bool found = false;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         const int c = __popcll(d[w]);
-        if (n < c) return base + select64(d[w], n);
-        n -= c;
-        base += 64;
+        const bool here = !found && n < c;
+        x = here ? d[w] : x;
+        base = here ? 64 * w : base;
+        n = (found || here) ? n : n - c;
+        found = found || here;
     }
-    return -1;
+    return found ? base + select64(x, n) : -1;
 }
 template <int W>
 __device__ __forceinline__ int popcount(const uint64_t *d)

@@ -874,10 +874,11 @@ struct SlotOut {
     }
 };
 
-// Items of a generation block whose offsets are searched in LDS (more: searched in HBM).
-// With 1536 the block's LDS is 22.6 KB, so 7 blocks fit in a CU's 160 KB; with the register
-// budget of 7 waves per SIMD below, the kernel runs at 7 waves per SIMD instead of 6.
-constexpr int kGenLdsItems = 1536;
+// Items of a generation block whose offsets are staged in LDS (more: searched in HBM).  With
+// 1024 the block's LDS is 22.5 KB, so 7 blocks fit in a CU's 160 KB; with the register budget
+// of 7 waves per SIMD below, the kernel runs at 7 waves per SIMD instead of 6.
+constexpr int kGenLdsItems = 1024;
+constexpr int kGenWaveSlots = 64 * kGenRounds;  // consecutive slots of one wavefront
 
 // Per-block statistics of the generation kernel (no single-address atomics).
 struct GenStats {
@@ -886,12 +887,14 @@ struct GenStats {
     uint32_t *deaths;
 };
 
-// One block covers kGenSlots consecutive record slots.  Pass 1, one lane per slot: find the
-// slot's item, and keep the slot as a candidate if it is a non-zero death or an attempt whose
-// excitation is valid (compacted into LDS in slot order).  Pass 2, one lane per candidate:
-// evaluate the element and the spawned amount, and write the records in slot order into the
-// block's region.  Splitting the two halves keeps every lane of pass 2 busy: only a small
-// fraction of the attempts survive pass 1.
+// One block covers kGenSlots consecutive record slots, wavefront w the kGenWaveSlots slots
+// from w * kGenWaveSlots.  The item of each slot comes from a slot map in LDS: every item with
+// a slot marks its first slot in the block, and a running maximum over the slots fills the
+// rest.  Pass 1, one lane per slot: keep the slot as a candidate if it is a non-zero death or an
+// attempt whose excitation is valid, compacted per wavefront in slot order.  Pass 2, one lane
+// per candidate: evaluate the element and the spawned amount, and write the records in slot
+// order into the block's region.  Splitting the two halves keeps every lane of pass 2 busy:
+// only a small fraction of the attempts survive pass 1.
 constexpr uint32_t kCandDeath = 1u << 31;
 
 template <int W, typename T>
@@ -901,7 +904,9 @@ __device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDe
                                                        int keep_ids, GenStats gs, Scratch *sc)
 {
     __shared__ uint32_t s_off[kGenLdsItems + 1];  // item offsets relative to the first item's
+    __shared__ uint16_t s_map[kGenSlots];         // item of each slot, relative to the first item
     __shared__ uint32_t wave_tot[kWaves];
+    __shared__ uint32_t s_wpre[kWaves + 1];       // candidates of the wavefronts before each
     __shared__ uint32_t c_item[kGenSlots];  // candidate: item
     __shared__ uint32_t c_slot[kGenSlots];  // candidate: slot in its item (kCandDeath: the death)
     __shared__ uint64_t c_orb[kGenSlots];   // candidate: i, j, a, b (16 bits each)
@@ -923,33 +928,62 @@ __device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDe
     const uint64_t hi = g0 + kGenSlots < n_slots ? block_item[blk + 1] : n_items - 1;
     const bool lds = hi - lo + 1 <= (uint64_t)kGenLdsItems;
     const uint64_t obase = off[lo];  // <= g0; every slot of the block is below obase + 2^31
-    if (lds)
+    const int wv = wave_id(), lane = lane_id();
+    if (lds) {
         for (uint64_t t = threadIdx.x; t <= hi - lo + 1; t += kThreads) {
             const uint64_t r = off[lo + t] - obase;
             s_off[t] = r < 0xFFFFFFFFull ? (uint32_t)r : 0xFFFFFFFFu;
         }
-    __syncthreads();
-    // ---- pass 1: candidates
-    uint32_t nc_total = 0;
+        for (int t = threadIdx.x; t < kGenSlots; t += kThreads) s_map[t] = 0;  // slot 0 is item lo's
+        __syncthreads();
+        const uint32_t g0r = (uint32_t)(g0 - obase);
+        for (uint32_t r = 1 + threadIdx.x; r <= (uint32_t)(hi - lo); r += kThreads) {
+            const uint32_t s0 = s_off[r];
+            if (s_off[r + 1] > s0 && s0 - g0r < (uint32_t)kGenSlots) s_map[s0 - g0r] = (uint16_t)r;  // s0 > g0r
+        }
+        __syncthreads();
+        // running maximum: kPer consecutive slots per thread, then over the threads
+        constexpr int kPer = kGenSlots / kThreads;
+        uint32_t m[kPer], run = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const uint32_t x = s_map[threadIdx.x * kPer + j];
+            run = x > run ? x : run;
+            m[j] = run;
+        }
+        uint32_t inc = run;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc = t > inc ? t : inc;
+        }
+        if (lane == 63) wave_tot[wv] = inc;
+        uint32_t before = __shfl_up(inc, 1, 64);
+        before = lane ? before : 0u;
+        __syncthreads();
+#pragma unroll
+        for (int ww = 0; ww < kWaves; ++ww)
+            if (ww < wv) before = wave_tot[ww] > before ? wave_tot[ww] : before;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) s_map[threadIdx.x * kPer + j] = (uint16_t)(m[j] > before ? m[j] : before);
+        __syncthreads();
+    }
+    // ---- pass 1: candidates, compacted into this wavefront's segment of the candidate lists
+    uint32_t wcount = 0;
+    const uint32_t wseg = (uint32_t)wv * kGenWaveSlots;
     for (int rd = 0; rd < kGenRounds; ++rd) {
-        const uint64_t g = g0 + (uint64_t)rd * kThreads + threadIdx.x;
+        const uint32_t t = wseg + (uint32_t)rd * 64 + (uint32_t)lane;
+        const uint64_t g = g0 + t;
         bool keep = false;
         uint32_t item32 = 0, slot = 0;
         uint64_t orb = 0;
         if (g < n_slots) {
             uint64_t item;
-            if (lds) {  // last item in [lo, hi] whose offset is <= g, searched in LDS
-                const uint32_t gr = (uint32_t)(g - obase);
-                uint32_t l0 = 0, h0 = (uint32_t)(hi - lo + 1);
-                while (l0 < h0) {
-                    const uint32_t mid = (l0 + h0) >> 1;
-                    if (s_off[mid] > gr)
-                        h0 = mid;
-                    else
-                        l0 = mid + 1;
-                }
-                item = lo + l0 - 1;
-            } else {
+            if (lds) {
+                const uint32_t rel = s_map[t];
+                item = lo + rel;
+                slot = (uint32_t)(g - obase) - s_off[rel];
+            } else {  // last item in [lo, hi] whose offset is <= g, searched in HBM
                 uint64_t l0 = lo, h0 = hi + 1;
                 while (l0 < h0) {
                     const uint64_t mid = (l0 + h0) >> 1;
@@ -959,9 +993,9 @@ __device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDe
                         l0 = mid + 1;
                 }
                 item = l0 - 1;
+                slot = (uint32_t)(g - off[item]);
             }
             item32 = (uint32_t)item;
-            slot = (uint32_t)(g - off[item]);
             if (slot == 0) {
                 keep = it.death[item] != T(0);
                 slot = kCandDeath;
@@ -970,32 +1004,35 @@ __device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDe
                 const uint32_t k = (uint32_t)(nc ? item : item - n_fnc);
                 uint64_t d[W], tgt[W];
 #pragma unroll
-                for (int w = 0; w < W; ++w) d[w] = it.key[(uint64_t)w * it.stride + item];
+                for (int ww = 0; ww < W; ++ww) d[ww] = it.key[(uint64_t)ww * it.stride + item];
                 int i, j, ta, tb;
                 keep = gen_excitation<W>(S, d, nc ? kSpawnNonComposite : kSpawnSampled, k, slot - 1, a, tgt, i, j, ta, tb);
                 orb = (uint64_t)(uint16_t)i | ((uint64_t)(uint16_t)j << 16) | ((uint64_t)(uint16_t)ta << 32) |
                       ((uint64_t)(uint16_t)tb << 48);
             }
         }
-        // compaction in slot order
         const uint64_t mk = __ballot(keep);
-        if (lane_id() == 0) wave_tot[wave_id()] = (uint32_t)__popcll(mk);
-        __syncthreads();
-        uint32_t before = 0, total = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-            if (w < wave_id()) before += wave_tot[w];
-            total += wave_tot[w];
-        }
         if (keep) {
-            const uint32_t q = nc_total + before + (uint32_t)lanes_below(mk);
+            const uint32_t q = wseg + wcount + (uint32_t)lanes_below(mk);
             c_item[q] = item32;
             c_slot[q] = slot;
             c_orb[q] = orb;
         }
-        nc_total += total;
-        __syncthreads();
+        wcount += (uint32_t)__popcll(mk);
     }
+    if (lane == 0) wave_tot[wv] = wcount;
+    __syncthreads();
+    if (threadIdx.x == 0) {  // candidates of the wavefronts before each
+        uint32_t acc = 0;
+#pragma unroll
+        for (int ww = 0; ww < kWaves; ++ww) {
+            s_wpre[ww] = acc;
+            acc += wave_tot[ww];
+        }
+        s_wpre[kWaves] = acc;
+    }
+    __syncthreads();
+    const uint32_t nc_total = s_wpre[kWaves];
     // ---- pass 2: amounts of the candidates, records in slot order
     uint32_t base = 0, spawns = 0, deaths = 0;
     for (uint32_t e0 = 0; e0 < nc_total; e0 += kThreads) {
@@ -1005,8 +1042,14 @@ __device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDe
         T x = T(0);
         uint64_t id = 0;
         if (e < nc_total) {
-            const uint64_t item = c_item[e];
-            const uint32_t cs = c_slot[e];
+            uint32_t q = e;  // position of candidate e: its wavefront's segment, then its rank there
+#pragma unroll
+            for (int ww = 0; ww < kWaves; ++ww) {
+                const uint32_t p0 = s_wpre[ww];
+                if (e >= p0) q = (uint32_t)ww * kGenWaveSlots + (e - p0);
+            }
+            const uint64_t item = c_item[q];
+            const uint32_t cs = c_slot[q];
             const bool nc = item < n_fnc;
             const uint32_t k = (uint32_t)(nc ? item : item - n_fnc);
             uint64_t d[W];
@@ -1020,7 +1063,7 @@ __device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDe
                 ++deaths;
                 id = ((nc ? 0ull : 1ull) << 62) | ((uint64_t)k << 30);
             } else {
-                const uint64_t orb = c_orb[e];
+                const uint64_t orb = c_orb[q];
                 const int i = (int16_t)(orb & 0xFFFF), j = (int16_t)((orb >> 16) & 0xFFFF);
                 const int ta = (int16_t)((orb >> 32) & 0xFFFF), tb = (int16_t)((orb >> 48) & 0xFFFF);
 #pragma unroll
@@ -1261,17 +1304,21 @@ __global__ void __launch_bounds__(kThreads) k_gather(const GatherArgs<W, T> A)
 // the plain left fold up to rounding order.  The head of each run looks
 // its rank up in the store: a hit adds to that entry, the reference (rank 0) adds to N_0, a
 // miss becomes a new excitor at insertion point ins.  A run that continues past its tile is
-// left "open": its head is finished by k_seg_close once every tile's leading piece is known.
+// left "open" (its sum within the tile, rank and insertion point go to the tile's summary):
+// k_seg_close finishes it once every tile's leading piece is known.
 constexpr int kFoldItems = 8;
 constexpr int kFoldTile = kThreads * kFoldItems;
 constexpr uint64_t kNoOpen = ~0ull;
 
 struct FoldTiles {
-    double *lead;       // per tile: left fold of its records before its first run head
-    uint32_t *has_head; // per tile: any run head in the tile
-    uint64_t *open;     // per tile: record index of its open head, or kNoOpen
-    uint64_t *open_new; // per tile: new-determinant index of its open head (if new)
-    uint64_t *status;   // per tile: look-back status of the count of new determinants
+    double *lead;        // per tile: left fold of its records before its first run head
+    uint32_t *has_head;  // per tile: any run head in the tile
+    uint64_t *open;      // per tile: record index of its open head, or kNoOpen
+    uint64_t *open_new;  // per tile: new-determinant index of its open head (if new)
+    uint64_t *status;    // per tile: look-back status of the count of new determinants
+    double *open_sum;    // per tile: the open run's sum within the tile
+    uint64_t *open_pos;  // per tile: the open run's store insertion point
+    uint64_t *open_rank; // per tile: the open run's rank
     uint64_t *ticket;
 };
 
@@ -1297,15 +1344,15 @@ template <int W, typename T>
 __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const SysDev &S, const uint64_t *__restrict__ rank,
                                                        const T *__restrict__ val, int packed, uint64_t cap,
                                                        const uint64_t *__restrict__ srank, uint64_t ne,
-                                                       double *__restrict__ delta, uint64_t *__restrict__ ins,
-                                                       double *__restrict__ seg_sum,
+                                                       double *__restrict__ delta,
                                                        const uint64_t *__restrict__ fence, const uint32_t *__restrict__ rtab,
                                                        uint64_t rt_n, uint32_t rsh,
                                                        FoldTiles ft, NewDets nd, Scratch *sc)
 {
     __shared__ double s_lead[kThreads];
     __shared__ uint32_t s_head[kThreads];
-    __shared__ uint64_t s_open, s_open_new, s_tile, s_prefix;
+    __shared__ uint64_t s_open, s_open_new, s_open_pos, s_open_rank, s_tile, s_prefix;
+    __shared__ double s_open_sum;
     const uint64_t n = sc->n_live;
     // tiles in ticket order: the look-back over the counts of new determinants only waits
     // for tiles that are already running
@@ -1498,8 +1545,6 @@ __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const
         const uint64_t rk = rr[i];
         const uint64_t r = r0 + i;
         const uint64_t pos = lo[i];
-        ins[r] = pos;
-        seg_sum[r] = acc[i];
         if (fresh[i]) {
             const uint64_t jj = jbase + j++;
             uint64_t d[W];
@@ -1513,11 +1558,14 @@ __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const
             for (int w = 0; w < W; ++w) nd.key[(uint64_t)w * nd.stride + jj] = d[w];
             nd.rank[jj] = rk;
             nd.ins[jj] = pos;
-            nd.sum[jj] = acc[i];
+            if (!open[i]) nd.sum[jj] = acc[i];  // an open run's sum is written when it is closed
             if (open[i]) s_open_new = jj;
         }
-        if (open[i]) {
-            s_open = r;  // at most one per tile: the run of the tile's last record
+        if (open[i]) {  // at most one per tile: the run of the tile's last record
+            s_open = r;
+            s_open_sum = acc[i];
+            s_open_pos = pos;
+            s_open_rank = rk;
         } else if (rk == 0) {
             sc->hf_sum = acc[i];
             sc->hf_hit = 1;
@@ -1531,6 +1579,9 @@ __device__ __forceinline__ void seg_fold_body(uint32_t blk, uint32_t nblk, const
         ft.has_head[tile] = s_head[0];
         ft.open[tile] = s_open;
         ft.open_new[tile] = s_open_new;
+        ft.open_sum[tile] = s_open_sum;
+        ft.open_pos[tile] = s_open_pos;
+        ft.open_rank[tile] = s_open_rank;
     }
 }
 
@@ -1544,8 +1595,6 @@ struct SegFoldArgs {
     const uint64_t *srank;
     uint64_t ne;
     double *delta;
-    uint64_t *ins;
-    double *seg_sum;
     const uint64_t *fence;
     const uint32_t *rtab;
     uint64_t rt_n;
@@ -1558,7 +1607,7 @@ struct SegFoldArgs {
 template <int W, typename T>
 __device__ __forceinline__ void k_seg_fold_entry(const SegFoldArgs<W, T> &A, uint32_t blk, uint32_t nblk)
 {
-    seg_fold_body<W, T>(blk, nblk, A.S, A.rank, A.val, A.packed, A.cap, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.fence,
+    seg_fold_body<W, T>(blk, nblk, A.S, A.rank, A.val, A.packed, A.cap, A.srank, A.ne, A.delta, A.fence,
                         A.rtab, A.rt_n, A.rsh, A.ft, A.nd, A.sc);
 }
 
@@ -1575,30 +1624,25 @@ __global__ void __launch_bounds__(kThreads) k_seg_fold(const SegFoldArgs<W, T> A
     k_seg_fold_entry<W, T>(A, blockIdx.x, gridDim.x);
 }
 
-// Finish the open runs: add the leading pieces of the following tiles until one holds a head.
-// One lane per tile.
-__device__ __forceinline__ void seg_close_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ rank, int packed, uint64_t n_tiles,
-                                                        const uint64_t *__restrict__ srank, uint64_t ne,
-                                                        double *__restrict__ delta, const uint64_t *__restrict__ ins,
-                                                        double *__restrict__ seg_sum, double *__restrict__ nsum, FoldTiles ft,
-                                                        Scratch *sc)
+// Finish the open runs: add the leading pieces of the following tiles until one holds a head,
+// then land on N_0, the store entry or the new determinant.  One lane per tile.
+__device__ __forceinline__ void seg_close_body(uint32_t blk, uint32_t nblk, uint64_t n_tiles, const uint64_t *__restrict__ srank,
+                                               uint64_t ne, double *__restrict__ delta, double *__restrict__ nsum,
+                                               FoldTiles ft, Scratch *sc)
 {
     const uint64_t t = (uint64_t)blk * kThreads + threadIdx.x;
-    if (t >= n_tiles) return;
-    const uint64_t r = ft.open[t];
-    if (r == kNoOpen) return;
-    double acc = seg_sum[r];
+    if (t >= n_tiles || ft.open[t] == kNoOpen) return;
+    double acc = ft.open_sum[t];
     for (uint64_t k = t + 1; k < n_tiles; ++k) {
         acc += ft.lead[k];
         if (ft.has_head[k]) break;
     }
-    seg_sum[r] = acc;
-    const uint64_t rk = key_rank(rank[r], packed);
+    const uint64_t rk = ft.open_rank[t];
     if (rk == 0) {
         sc->hf_sum = acc;
         sc->hf_hit = 1;
     } else {
-        const uint64_t pos = ins[r];
+        const uint64_t pos = ft.open_pos[t];
         if (pos < ne && srank[pos] == rk)
             delta[pos] = acc;
         else
@@ -1607,14 +1651,10 @@ __device__ __forceinline__ void seg_close_body(uint32_t blk, uint32_t nblk, cons
 }
 
 struct SegCloseArgs {
-    const uint64_t *rank;
-    int packed;
     uint64_t n_tiles;
     const uint64_t *srank;
     uint64_t ne;
     double *delta;
-    const uint64_t *ins;
-    double *seg_sum;
     double *nsum;
     FoldTiles ft;
     Scratch *sc;
@@ -1622,7 +1662,7 @@ struct SegCloseArgs {
 
 __device__ __forceinline__ void k_seg_close_entry(const SegCloseArgs &A, uint32_t blk, uint32_t nblk)
 {
-    seg_close_body(blk, nblk, A.rank, A.packed, A.n_tiles, A.srank, A.ne, A.delta, A.ins, A.seg_sum, A.nsum, A.ft, A.sc);
+    seg_close_body(blk, nblk, A.n_tiles, A.srank, A.ne, A.delta, A.nsum, A.ft, A.sc);
 }
 
 __global__ void __launch_bounds__(kThreads) k_seg_close(const SegCloseArgs *__restrict__ args, BatchMap bm)
@@ -1876,6 +1916,41 @@ struct FinalPart {
     uint64_t att, disc, mx, sp, de, pad;
 };
 
+// Every field of a FinalPart over the block, in one exchange: a shuffle tree within each
+// wavefront, then thread 0 adds the wavefronts in order (the result is valid in thread 0).
+__device__ __forceinline__ FinalPart block_reduce_part(FinalPart a)
+{
+    __shared__ FinalPart s_w[kWaves];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a.num += __shfl_down(a.num, o, 64);
+        a.tot += __shfl_down(a.tot, o, 64);
+        a.att += __shfl_down(a.att, o, 64);
+        a.disc += __shfl_down(a.disc, o, 64);
+        a.sp += __shfl_down(a.sp, o, 64);
+        a.de += __shfl_down(a.de, o, 64);
+        const uint64_t m = __shfl_down(a.mx, o, 64);
+        a.mx = m > a.mx ? m : a.mx;
+    }
+    if (lane_id() == 0) s_w[wave_id()] = a;
+    __syncthreads();
+    FinalPart r{};
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const FinalPart b = s_w[w];
+            r.num += b.num;
+            r.tot += b.tot;
+            r.att += b.att;
+            r.disc += b.disc;
+            r.sp += b.sp;
+            r.de += b.de;
+            r.mx = b.mx > r.mx ? b.mx : r.mx;
+        }
+    }
+    return r;
+}
+
 __device__ __forceinline__ void chunk_of(uint64_t n, uint64_t g, uint64_t nb, uint64_t &lo, uint64_t &hi)
 {
     const uint64_t c = (n + nb - 1) / nb;
@@ -1951,33 +2026,46 @@ __device__ __forceinline__ void final_part_body(uint32_t blk, uint32_t nblk, Ite
 #pragma unroll
         for (int u = 0; u < 2 * U; ++u) tot += x[u];
     }
-    FinalPart r;
-    r.num = block_reduce_sum(num);
-    r.tot = block_reduce_sum(tot);
-    r.att = block_reduce_sum(att);
-    r.disc = block_reduce_sum(disc);
-    r.sp = block_reduce_sum(sp);
-    r.de = block_reduce_sum(de);
-    r.mx = block_reduce_max(mx);
-    r.pad = 0;
+    FinalPart r{};
+    r.num = num;
+    r.tot = tot;
+    r.att = att;
+    r.disc = disc;
+    r.sp = sp;
+    r.de = de;
+    r.mx = mx;
+    r = block_reduce_part(r);
     if (threadIdx.x == 0) out[blk] = r;
 }
+
+// The second stage, by the whole last block: thread t sums parts t, t + kThreads, ... (in that
+// order), then the block reduces in its fixed tree order.  All loads of a thread are issued
+// before its first add.
+constexpr int kFinalPerThread = 2;  // parts per thread: n <= kThreads * kFinalPerThread
 
 __device__ __forceinline__ void final_body(uint32_t blk, uint32_t nblk, const FinalPart *__restrict__ in, uint64_t n, Scratch *sc,
                                            Scratch *copy, uint64_t seq)
 {
-    if (threadIdx.x != 0) return;
-    FinalPart a{};
-    for (uint64_t i = 0; i < n; ++i) {
-        const FinalPart b = in[i];
-        a.num += b.num;
-        a.tot += b.tot;
-        a.att += b.att;
-        a.disc += b.disc;
-        a.sp += b.sp;
-        a.de += b.de;
-        a.mx = b.mx > a.mx ? b.mx : a.mx;
+    FinalPart b[kFinalPerThread];
+#pragma unroll
+    for (int u = 0; u < kFinalPerThread; ++u) {
+        const uint64_t i = (uint64_t)u * kThreads + threadIdx.x;
+        b[u] = in[i < n ? i : 0];
+        if (i >= n) b[u] = FinalPart{};
     }
+    FinalPart a{};
+#pragma unroll
+    for (int u = 0; u < kFinalPerThread; ++u) {
+        a.num += b[u].num;
+        a.tot += b[u].tot;
+        a.att += b[u].att;
+        a.disc += b[u].disc;
+        a.sp += b[u].sp;
+        a.de += b[u].de;
+        a.mx = b[u].mx > a.mx ? b[u].mx : a.mx;
+    }
+    a = block_reduce_part(a);
+    if (threadIdx.x != 0) return;
     sc->num = a.num;
     sc->n_total = a.tot;
     sc->n_attempts = a.att;
@@ -2009,18 +2097,20 @@ struct FinalPartArgs {
 };
 
 // Both stages of the reduction in one launch: each block publishes its part and counts
-// itself done (an acquire-release atomic); the block that finishes last sums the parts in
+// itself done (a release atomic); the block that finishes last acquires, sums the parts in
 // block order and hands the scalars to the host.
 __device__ __forceinline__ void k_final_part_entry(const FinalPartArgs &A, uint32_t blk, uint32_t nblk)
 {
     final_part_body(blk, nblk, A.part, A.n_parts, A.gs, A.n_gen, A.abs_part, A.n_abs, A.sc, A.ne, A.out);
     __shared__ bool s_last;
     if (threadIdx.x == 0) {
-        const uint64_t before = __hip_atomic_fetch_add(A.done, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t before = __hip_atomic_fetch_add(A.done, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         s_last = before + 1 == nblk;
     }
     __syncthreads();
-    if (s_last) final_body(blk, nblk, A.out, nblk, A.sc, A.copy, A.seq);
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // only the last block reads the others' parts
+    final_body(blk, nblk, A.out, nblk, A.sc, A.copy, A.seq);
 }
 
 __global__ void __launch_bounds__(kThreads) k_final_part(const FinalPartArgs *__restrict__ args, BatchMap bm)
