@@ -988,7 +988,7 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
             auto &p = ps[i];
             args.push_back(RadixGhistArgs{ptr<uint64_t>(p.st->vkey[0]), &p.sc->n_place, 1, 0,
                                           reinterpret_cast<uint32_t *>(p.lb + p.o_pghist)});
-            blk[i] = (uint32_t)p.ptiles;
+            blk[i] = (uint32_t)std::min<uint64_t>(p.ptiles, kGhistBlocks);
         }
         stage(ar, recs, "place_ghist", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.ranked ? p.ne : 0}; }),
               [s](const auto &a, unsigned g, auto... bm) { k_radix_ghist<<<g, kThreads, 0, s>>>(a, bm...); });
@@ -1163,7 +1163,7 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
             auto &p = ps[i];
             args.push_back(RadixGhistArgs{ptr<uint64_t>(p.st->drank), &p.sc->n_live, passes, p.packed ? 32 : 0,
                                           reinterpret_cast<uint32_t *>(p.lb + p.o_ghist)});
-            blk[i] = (uint32_t)p.tiles;
+            blk[i] = (uint32_t)std::min<uint64_t>(p.tiles, kGhistBlocks);
         }
         stage(ar, recs, "radix_ghist", args, blk, works([&](auto &p) { return Work{8.0, &p.st->cnt_rec, 0}; }),
               [s](const auto &a, unsigned g, auto... bm) { k_radix_ghist<<<g, kThreads, 0, s>>>(a, bm...); });

@@ -310,9 +310,11 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active)
 // ------------------------------------------------------------ onesweep radix passes
 // Keys are 64-bit, sorted by kRadixBits-bit digits from bit shift0 up (bits below shift0 are
 // carried, not sorted on: the sort stays stable in the input order for equal sorted bits).
-// Digit histograms of every pass in one read of the keys (they do not depend on the order),
-// aggregated per wavefront and per block before one global atomic per bin.
+// Digit histograms of every pass in one read of the keys (they do not depend on the order):
+// per-lane LDS atomics, except where a wavefront's digits are all equal (the top digits of
+// narrow key ranges), which add once; then one global atomic per non-empty bin and block.
 constexpr int kRadixMaxPasses = (64 + kRadixBits - 1) / kRadixBits;
+constexpr uint64_t kGhistBlocks = 1024;  // blocks of the histogram launch at most (four per CU)
 
 __device__ __forceinline__ void radix_ghist_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ key, const uint64_t *__restrict__ n_live,
                                                           int passes, int shift0, uint32_t *__restrict__ ghist)
@@ -322,8 +324,8 @@ __device__ __forceinline__ void radix_ghist_body(uint32_t blk, uint32_t nblk, co
     for (int p = 0; p < passes; ++p)
         for (int d = threadIdx.x; d < kRadixBins; d += kThreads) h[p][d] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blk * kSortTile;
-    if (base < n) {
+    // tiles blk, blk + nblk, ...: few blocks, so that few atomics meet on each global bin
+    for (uint64_t base = (uint64_t)blk * kSortTile; base < n; base += (uint64_t)nblk * kSortTile) {
         uint64_t k[kSortItems];
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
@@ -335,12 +337,16 @@ __device__ __forceinline__ void radix_ghist_body(uint32_t blk, uint32_t nblk, co
             const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
             const bool valid = g < n;
             const uint64_t active = __ballot(valid);
+            const int leader = active ? __ffsll((long long)active) - 1 : 0;
             for (int p = 0; p < passes; ++p) {
                 const int sh = shift0 + kRadixBits * p;  // a batch's extra passes may lie past bit 63
                 const uint32_t d = sh < 64 ? (uint32_t)((k[r] >> sh) & (kRadixBins - 1)) : 0u;
-                if (valid) {
-                    const uint64_t peers = match_digit(d, active);
-                    if (lanes_below(peers) == 0) atomicAdd(&h[p][d], (uint32_t)__popcll(peers));
+                const uint32_t d0 = (uint32_t)__shfl((int)d, leader, 64);
+                const bool same = __ballot(valid && d != d0) == 0;  // every active lane holds d0
+                if (same) {
+                    if (lane_id() == leader && active) atomicAdd(&h[p][d0], (uint32_t)__popcll(active));
+                } else if (valid) {
+                    atomicAdd(&h[p][d], 1u);
                 }
             }
         }
@@ -381,10 +387,12 @@ __global__ void __launch_bounds__(kThreads) k_radix_ghist(const RadixGhistArgs A
 // [w * 64 * kSortItems, (w + 1) * 64 * kSortItems), 64 per round, and ranks them against its
 // own LDS digit counters (no block barrier between rounds: a wavefront's LDS accesses are in
 // order).  The tile then combines its wavefronts' counts, publishes its per-digit counts,
-// looks back over the earlier tiles digit by digit, and scatters each key to
-// digit base + earlier tiles + earlier wavefronts + rank in its wavefront.  status holds
-// kRadixBins words per tile and must be zero before the launch.  Thread x also owns the
-// digits x + j * kThreads of the per-digit work.
+// looks back over the earlier tiles digit by digit, and places each key at
+// digit base + earlier tiles + earlier wavefronts + rank in its wavefront.  The tile is
+// staged in LDS in its sorted order first (keys, then values), so that consecutive lanes
+// write consecutive addresses of a digit's run.  status holds kRadixBins words per tile and
+// must be zero before the launch.  Thread x also owns the digits x + j * kThreads of the
+// per-digit work.
 constexpr int kDigitsPerThread = kRadixBins / kThreads;
 
 template <typename V>
@@ -395,7 +403,9 @@ __device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk,
                                                              uint64_t *__restrict__ ticket)
 {
     __shared__ uint32_t wave_cnt[kWaves][kRadixBins];  // per wavefront: digit counts, then offsets
-    __shared__ uint32_t dig_base[kRadixBins];
+    __shared__ uint32_t dig_base[kRadixBins];          // output position of the digit's run, less its tile start
+    __shared__ uint32_t t_start[kRadixBins];           // the digit's start in the tile's sorted order
+    __shared__ uint64_t s_stage[kSortTile];            // the tile in sorted order: keys, then values
     __shared__ uint64_t s_tile;
     const uint64_t n = *n_live;
     if (threadIdx.x == 0) s_tile = atomicAdd((unsigned long long *)ticket, 1ull);
@@ -449,15 +459,18 @@ __device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk,
         }
         tile_cnt[j] = acc;
     }
-    // global base of each digit: exclusive prefix of the pass histogram over the digits
-    uint32_t gbase[kDigitsPerThread];
+    // global base of each digit: exclusive prefix of the pass histogram over the digits; and
+    // the digit's start in the tile: exclusive prefix of the tile's counts
+    uint32_t gbase[kDigitsPerThread], tbase[kDigitsPerThread];
     {
-        uint32_t carry = 0;
+        uint32_t carry = 0, tcarry = 0;
 #pragma unroll
         for (int j = 0; j < kDigitsPerThread; ++j) {
-            uint32_t tot;
+            uint32_t tot, ttot;
             gbase[j] = carry + block_exclusive_scan(ghist[threadIdx.x + j * kThreads], &tot);
             carry += tot;
+            tbase[j] = tcarry + block_exclusive_scan(tile_cnt[j], &ttot);
+            tcarry += ttot;
         }
     }
     // publish this tile's counts, then sum the earlier tiles' counts (the digit chains of a
@@ -493,18 +506,45 @@ __device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk,
     for (int j = 0; j < kDigitsPerThread; ++j) {
         const int d = threadIdx.x + j * kThreads;
         if (t > 0) lb_publish(&st[d], kLbInclusive, excl[j] + tile_cnt[j]);
-        dig_base[d] = gbase[j] + (uint32_t)excl[j];
+        dig_base[d] = gbase[j] + (uint32_t)excl[j] - tbase[j];
+        t_start[d] = tbase[j];
     }
     __syncthreads();
+    // position of each key in the tile's sorted order; the keys staged there
+    uint32_t lp[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const uint64_t g = wbase + (uint64_t)r * 64 + lane;
-        if (g < n) {
-            const uint32_t d = shift < 64 ? (uint32_t)((k[r] >> shift) & (kRadixBins - 1)) : 0u;
-            const uint32_t dst = dig_base[d] + wave_cnt[w][d] + rk[r];
-            key_out[dst] = k[r];
-            idx_out[dst] = ix[r];
+        const uint32_t d = shift < 64 ? (uint32_t)((k[r] >> shift) & (kRadixBins - 1)) : 0u;
+        lp[r] = t_start[d] + wave_cnt[w][d] + rk[r];
+        if (g < n) s_stage[lp[r]] = k[r];
+    }
+    __syncthreads();
+    const uint32_t tn = n - base < (uint64_t)kSortTile ? (uint32_t)(n - base) : (uint32_t)kSortTile;
+    uint32_t dst[kSortItems];  // output position of sorted slot threadIdx.x + m * kThreads
+#pragma unroll
+    for (int m = 0; m < kSortItems; ++m) {
+        const uint32_t i = threadIdx.x + (uint32_t)m * kThreads;
+        dst[m] = 0;
+        if (i < tn) {
+            const uint64_t key = s_stage[i];
+            const uint32_t d = shift < 64 ? (uint32_t)((key >> shift) & (kRadixBins - 1)) : 0u;
+            dst[m] = dig_base[d] + i;
+            key_out[dst[m]] = key;
         }
+    }
+    __syncthreads();  // the keys are read: the stage takes the values
+    V *sv = reinterpret_cast<V *>(s_stage);
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint64_t g = wbase + (uint64_t)r * 64 + lane;
+        if (g < n) sv[lp[r]] = ix[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kSortItems; ++m) {
+        const uint32_t i = threadIdx.x + (uint32_t)m * kThreads;
+        if (i < tn) idx_out[dst[m]] = sv[i];
     }
 }
 
