@@ -984,14 +984,23 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
     }
     {
         std::vector<RadixGhistArgs> args;
+        uint64_t most = 0;
+        for (auto &p : ps) most = std::max(most, p.ptiles);
+        const bool fat = most >= kGhistFatFrom;
+        const int nt = fat ? kGhistFat : kThreads;
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
             args.push_back(RadixGhistArgs{ptr<uint64_t>(p.st->vkey[0]), &p.sc->n_place, 1, 0,
                                           reinterpret_cast<uint32_t *>(p.lb + p.o_pghist)});
-            blk[i] = (uint32_t)std::min<uint64_t>(p.ptiles, kGhistBlocks);
+            blk[i] = p.ptiles ? (uint32_t)ghist_grid(p.ptiles * kSortTile, nt) : 0u;
         }
         stage(ar, recs, "place_ghist", args, blk, works([&](auto &p) { return Work{8.0, nullptr, p.ranked ? p.ne : 0}; }),
-              [s](const auto &a, unsigned g, auto... bm) { k_radix_ghist<<<g, kThreads, 0, s>>>(a, bm...); });
+              [s, fat](const auto &a, unsigned g, auto... bm) {
+                  if (fat)
+                      k_radix_ghist<kGhistFat><<<g, kGhistFat, 0, s>>>(a, bm...);
+                  else
+                      k_radix_ghist<kThreads><<<g, kThreads, 0, s>>>(a, bm...);
+              });
     }
     {
         std::vector<RadixOnesweepArgs<uint32_t>> args;
@@ -1159,14 +1168,23 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
     // passes, then one single-sweep launch per digit
     {
         std::vector<RadixGhistArgs> args;
+        uint64_t most = 0;
+        for (auto &p : ps) most = std::max(most, p.tiles);
+        const bool fat = most >= kGhistFatFrom;
+        const int nt = fat ? kGhistFat : kThreads;
         for (size_t i = 0; i < n; ++i) {
             auto &p = ps[i];
             args.push_back(RadixGhistArgs{ptr<uint64_t>(p.st->drank), &p.sc->n_live, passes, p.packed ? 32 : 0,
                                           reinterpret_cast<uint32_t *>(p.lb + p.o_ghist)});
-            blk[i] = (uint32_t)std::min<uint64_t>(p.tiles, kGhistBlocks);
+            blk[i] = p.tiles ? (uint32_t)ghist_grid(p.tiles * kSortTile, nt) : 0u;
         }
         stage(ar, recs, "radix_ghist", args, blk, works([&](auto &p) { return Work{8.0, &p.st->cnt_rec, 0}; }),
-              [s](const auto &a, unsigned g, auto... bm) { k_radix_ghist<<<g, kThreads, 0, s>>>(a, bm...); });
+              [s, fat](const auto &a, unsigned g, auto... bm) {
+                  if (fat)
+                      k_radix_ghist<kGhistFat><<<g, kGhistFat, 0, s>>>(a, bm...);
+                  else
+                      k_radix_ghist<kThreads><<<g, kThreads, 0, s>>>(a, bm...);
+              });
     }
     for (int pass = 0; pass < passes; ++pass) {
         std::vector<RadixOnesweepArgs<T>> args;

@@ -314,27 +314,40 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active)
 // per-lane LDS atomics, except where a wavefront's digits are all equal (the top digits of
 // narrow key ranges), which add once; then one global atomic per non-empty bin and block.
 constexpr int kRadixMaxPasses = (64 + kRadixBits - 1) / kRadixBits;
-constexpr uint64_t kGhistBlocks = 1024;  // blocks of the histogram launch at most (four per CU)
+// The histogram launch: each block adds its bins to the global histogram once, and on a large
+// input those atomics are what the grid waits on, so large inputs take few fat blocks (NT =
+// 1024 threads, at most one per CU); small ones take one 256-thread block per tile, to spread
+// over more CUs.
+constexpr int kGhistFat = 1024;
+constexpr uint64_t kGhistFatFrom = 256;  // radix tiles from which the fat blocks are used
+constexpr uint64_t kGhistBlocks = 1024;  // blocks of either kind at most
+__host__ __device__ __forceinline__ uint64_t ghist_grid(uint64_t n, int nt)
+{
+    const uint64_t tile = (uint64_t)nt * kSortItems, t = (n + tile - 1) / tile;
+    const uint64_t cap = nt == kGhistFat ? kGhistBlocks / 4 : kGhistBlocks;
+    return t < cap ? (t ? t : 1) : cap;
+}
 
+template <int NT>
 __device__ __forceinline__ void radix_ghist_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ key, const uint64_t *__restrict__ n_live,
                                                           int passes, int shift0, uint32_t *__restrict__ ghist)
 {
     const uint64_t n = *n_live;
     __shared__ uint32_t h[kRadixMaxPasses][kRadixBins];
     for (int p = 0; p < passes; ++p)
-        for (int d = threadIdx.x; d < kRadixBins; d += kThreads) h[p][d] = 0;
+        for (int d = threadIdx.x; d < kRadixBins; d += NT) h[p][d] = 0;
     __syncthreads();
     // tiles blk, blk + nblk, ...: few blocks, so that few atomics meet on each global bin
-    for (uint64_t base = (uint64_t)blk * kSortTile; base < n; base += (uint64_t)nblk * kSortTile) {
+    for (uint64_t base = (uint64_t)blk * ((uint64_t)NT * kSortItems); base < n; base += (uint64_t)nblk * ((uint64_t)NT * kSortItems)) {
         uint64_t k[kSortItems];
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
-            const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
+            const uint64_t g = base + (uint64_t)r * NT + threadIdx.x;
             k[r] = key[g < n ? g : n - 1];  // clamped: unconditional loads
         }
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
-            const uint64_t g = base + (uint64_t)r * kThreads + threadIdx.x;
+            const uint64_t g = base + (uint64_t)r * NT + threadIdx.x;
             const bool valid = g < n;
             const uint64_t active = __ballot(valid);
             const int leader = active ? __ffsll((long long)active) - 1 : 0;
@@ -353,7 +366,7 @@ __device__ __forceinline__ void radix_ghist_body(uint32_t blk, uint32_t nblk, co
     }
     __syncthreads();
     for (int p = 0; p < passes; ++p)
-        for (int d = threadIdx.x; d < kRadixBins; d += kThreads)
+        for (int d = threadIdx.x; d < kRadixBins; d += NT)
             if (h[p][d]) atomicAdd(&ghist[p * kRadixBins + d], h[p][d]);
 }
 
@@ -365,20 +378,23 @@ struct RadixGhistArgs {
     uint32_t *ghist;
 };
 
+template <int NT>
 __device__ __forceinline__ void k_radix_ghist_entry(const RadixGhistArgs &A, uint32_t blk, uint32_t nblk)
 {
-    radix_ghist_body(blk, nblk, A.key, A.n_live, A.passes, A.shift0, A.ghist);
+    radix_ghist_body<NT>(blk, nblk, A.key, A.n_live, A.passes, A.shift0, A.ghist);
 }
 
-__global__ void __launch_bounds__(kThreads) k_radix_ghist(const RadixGhistArgs *__restrict__ args, BatchMap bm)
+template <int NT>
+__global__ void __launch_bounds__(NT) k_radix_ghist(const RadixGhistArgs *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
-    k_radix_ghist_entry(args[batch_state(bm, blk, nblk)], blk, nblk);
+    k_radix_ghist_entry<NT>(args[batch_state(bm, blk, nblk)], blk, nblk);
 }
 
-__global__ void __launch_bounds__(kThreads) k_radix_ghist(const RadixGhistArgs A)
+template <int NT>
+__global__ void __launch_bounds__(NT) k_radix_ghist(const RadixGhistArgs A)
 {
-    k_radix_ghist_entry(A, blockIdx.x, gridDim.x);
+    k_radix_ghist_entry<NT>(A, blockIdx.x, gridDim.x);
 }
 
 // One stable pass by the digit at `shift`, carrying one value of type V per key (the record's
