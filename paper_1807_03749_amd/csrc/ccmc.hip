@@ -126,7 +126,7 @@ struct ccmc_state {
     HostSys hs;
     SysDev sd{};
     std::vector<DevBuf *> all;
-    DevBuf t_grid, t_nvec, t_vq, t_h, t_eri, t_fock, t_vpair, t_binv, t_bino, t_pairs, t_kpack;
+    DevBuf t_grid, t_nvec, t_vq, t_h, t_eri, t_fock, t_vpair, t_binv, t_bino, t_rankv, t_pairs, t_kpack;
     int rank_bits = 0;  // bits of the largest truncated-space rank
     // the store: current buffer cur, merge target 1 - cur
     DevBuf skey[2], samp[2], sK[2], srank[2];
@@ -491,6 +491,19 @@ ccmc_status upload_system(ccmc_state *st, const ccmc_integrals *ints)
         HIP_TRY(hipMemcpy(st->t_bino.p, bo.data(), bo.size() * 8, hipMemcpyHostToDevice));
         S.binom_v = ptr<uint64_t>(st->t_binv);
         S.binom_o = ptr<uint64_t>(st->t_bino);
+        // the rank's term of a virtual orbital p with v virtual electrons above it (all the
+        // electrons above p are then virtual): sum_j C(p - N, j) C(N, N - v - j), j <= l - v
+        const int L = st->l;
+        std::vector<uint64_t> rv((size_t)(M - N + 1) * (L + 1), 0);
+        for (int nv = 0; nv <= M - N; ++nv)
+            for (int v = 0; v <= L && v <= N; ++v) {
+                uint64_t t = 0;
+                for (int j = 0; j <= L - v && j <= N - v; ++j) t += bv[(size_t)nv * 9 + j] * bo[(size_t)N * (N + 1) + (N - v - j)];
+                rv[(size_t)nv * (L + 1) + v] = t;
+            }
+        TRY(ensure(st, st->t_rankv, rv.size() * 8));
+        HIP_TRY(hipMemcpy(st->t_rankv.p, rv.data(), rv.size() * 8, hipMemcpyHostToDevice));
+        S.rank_v = ptr<uint64_t>(st->t_rankv);
     }
     TRY(upload_table<T>(st, st->t_fock, hs.fock));
     TRY(upload_table<T>(st, st->t_vpair, hs.vpair));
@@ -1690,7 +1703,7 @@ void destroy(ccmc_state *st)
 {
     if (!st) return;
     if (st->stream) (void)hipStreamSynchronize(st->stream);
-    DevBuf *bufs[] = {&st->t_pairs, &st->t_kpack, &st->t_grid, &st->t_nvec, &st->t_vq, &st->t_h, &st->t_eri, &st->t_fock, &st->t_vpair,
+    DevBuf *bufs[] = {&st->t_rankv, &st->t_pairs, &st->t_kpack, &st->t_grid, &st->t_nvec, &st->t_vq, &st->t_h, &st->t_eri, &st->t_fock, &st->t_vpair,
                       &st->t_binv, &st->t_bino, &st->skey[0], &st->skey[1], &st->samp[0], &st->samp[1], &st->sK[0],
                       &st->sK[1], &st->srank[0], &st->srank[1], &st->P, &st->drec, &st->guide, &st->delta, &st->fence, &st->rtab, &st->ikey,
                       &st->iA, &st->ideath, &st->in, &st->icnt, &st->ioff, &st->num_part, &st->att_part, &st->disc_part, &st->max_part, &st->abs_part,

@@ -38,6 +38,7 @@ struct SysDev {
     // ranks in the truncated space (see space_rank)
     const uint64_t *binom_v;  // [(M+1) * 9]: C(n, j), j <= 8
     const uint64_t *binom_o;  // [(N+1) * (N+1)]: C(n, k), saturating
+    const uint64_t *rank_v;   // [(M-N+1) * (l+1)]: rank term of a virtual orbital (see space_rank)
     // excitation generators
     const uint32_t *pairs;    // [N (N-1) / 2]: the pair (x < y) of each rank, x | y << 16 (lexicographic)
     const uint32_t *kpack;    // UEG [nsp]: wavevector components + G + 256 in 10-bit fields (x, y, z)
@@ -432,24 +433,31 @@ __device__ __forceinline__ T diagonal(const SysDev &S, const uint64_t *d)
 template <int W>
 __device__ __forceinline__ uint64_t space_rank(const SysDev &S, const uint64_t *d)
 {
+    // Above the reference orbitals every electron placed so far is virtual (a = v, k = N - v),
+    // and the sum over j is tabulated per (p - N, v) in rank_v.  Below them D' has no
+    // virtual electron left to place below p (nv = 0): only j = 0 counts, C(p, k).
     const int N = S.nel, l = S.l;
     uint64_t r = 0;
-    int a = 0, v = 0;
+    int a = 0;
 #pragma unroll
     for (int w = W - 1; w >= 0; --w) {
-        uint64_t m = d[w];
+        uint64_t m = d[w] & ~S.hf[w];
+        while (m) {
+            const int p = 64 * w + 63 - __clzll((long long)m);
+            m &= ~(1ull << (p & 63));
+            if (a <= l) r += S.rank_v[(p - N) * (l + 1) + a];
+            ++a;
+        }
+    }
+#pragma unroll
+    for (int w = W - 1; w >= 0; --w) {
+        uint64_t m = d[w] & S.hf[w];
         while (m) {
             const int p = 64 * w + 63 - __clzll((long long)m);
             m &= ~(1ull << (p & 63));
             const int k = N - a;
-            const int nv = p > N ? p - N : 0, no = p < N ? p : N;
-            const int jmax = (l - v) < k ? (l - v) : k;
-            for (int j = 0; j <= jmax; ++j) {
-                if (k - j > no) continue;
-                r += S.binom_v[nv * 9 + j] * S.binom_o[no * (N + 1) + (k - j)];
-            }
+            if (k <= p) r += S.binom_o[p * (N + 1) + k];
             ++a;
-            v += (p >= N) ? 1 : 0;
         }
     }
     return r;
@@ -459,28 +467,30 @@ __device__ __forceinline__ uint64_t space_rank(const SysDev &S, const uint64_t *
 // With the bits above p fixed (a electrons placed, v of them virtual), the determinants that
 // leave p empty number S(p) = sum_j C(virtual orbitals below p, j) C(reference orbitals below
 // p, k - j) over j <= l - v (k = N - a electrons still to place), and they all come before the
-// ones that fill p: p is filled iff r >= S(p), and then r drops by S(p).
+// ones that fill p: p is filled iff r >= S(p), and then r drops by S(p).  As in space_rank,
+// S(p) is rank_v[p - N][v] above the reference orbitals and C(p, k) below them.
 template <int W>
 __device__ __forceinline__ void space_unrank(const SysDev &S, uint64_t r, uint64_t *d)
 {
     const int N = S.nel, l = S.l;
 #pragma unroll
     for (int w = 0; w < W; ++w) d[w] = 0;
-    int a = 0, v = 0;
-    for (int p = S.M - 1; p >= 0 && a < N; --p) {
-        const int k = N - a;
-        const int nv = p > N ? p - N : 0, no = p < N ? p : N;
-        const int jmax = (l - v) < k ? (l - v) : k;
-        uint64_t empty = 0;
-        for (int j = 0; j <= jmax; ++j) {
-            if (k - j > no) continue;
-            empty += S.binom_v[nv * 9 + j] * S.binom_o[no * (N + 1) + (k - j)];
-        }
+    int a = 0;
+    for (int p = S.M - 1; p >= N && a < N; --p) {
+        const uint64_t empty = a <= l ? S.rank_v[(p - N) * (l + 1) + a] : 0;
         if (r >= empty) {
             r -= empty;
             d[p >> 6] |= 1ull << (p & 63);
             ++a;
-            v += (p >= N) ? 1 : 0;
+        }
+    }
+    for (int p = (N < S.M ? N : S.M) - 1; p >= 0 && a < N; --p) {
+        const int k = N - a;
+        const uint64_t empty = k <= p ? S.binom_o[p * (N + 1) + k] : 0;
+        if (r >= empty) {
+            r -= empty;
+            d[p >> 6] |= 1ull << (p & 63);
+            ++a;
         }
     }
 }
