@@ -273,6 +273,27 @@ def measured_traffic(kernel: str, workload: str, key: str = "hbm_bytes_per_launc
         return None
 
 
+def measured_valu(kernel: str, workload: str):
+    """Vector-ALU counters of `kernel` on `workload` from the committed summary
+    (profiles/valu_<workload>.txt: SQ_WAVES and SQ_INSTS_VALU per dispatch over the timed
+    steps), or None when the summary is missing or was taken on other sources."""
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    rows, src = {}, None
+    with open(path) as f:
+        for ln in f:
+            if ln.startswith("source_hash"):
+                src = ln.split("=", 1)[1].strip()
+            elif ln.startswith("  k_"):
+                parts = ln.split()
+                rows[parts[0].rstrip("<")] = dict(waves=float(parts[2]), insts=float(parts[3]),
+                                                  busy=float(parts[4].rstrip("%")) / 100.0)
+    if src != source_hash():
+        return None
+    return rows.get(f"k_{kernel}")
+
+
 def roofline(timed: dict, w: inputs.Workload):
     """Roofline entry for the dominant kernel, from its HIP-event durations in the timed
     region.  generate and items are bound by the vector ALUs: their algorithmic work is the
@@ -289,6 +310,12 @@ def roofline(timed: dict, w: inputs.Workload):
         achieved = p["items"] / p["launches"] * ops / avg_s / 1e9
         r = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_GOPS, "unit": "Gop/s",
              f"ops_per_{unit}": ops, f"{unit}s_per_launch": p["items"] / p["launches"]}
+        m = measured_valu(name, w.name)
+        if m:  # the executed VALU instructions (64 lane operations each) over the same duration
+            lane_ops = m["waves"] * m["insts"] * 64.0
+            r["measured_valu"] = dict(waves_per_launch=m["waves"], valu_insts_per_wave=m["insts"],
+                                      lane_ops_per_launch=lane_ops, achieved=lane_ops / avg_s / 1e9,
+                                      frac=lane_ops / avg_s / 1e9 / ALU_PEAK_GOPS, valu_busy=m["busy"])
     else:
         achieved = p["bytes"] / p["launches"] / avg_s / 1e9
         r = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s")

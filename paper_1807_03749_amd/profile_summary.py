@@ -170,7 +170,8 @@ def valu(args):
     names = [k for k in args.kernels.split(",") if k]
     counters = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES", "SQ_WAIT_INST_ANY",
                 "GRBM_GUI_ACTIVE")
-    lines = [f"# vector-ALU use on {args.workload}  ({datetime.date.today().isoformat()})",
+    lines = [f"# vector-ALU use on {args.workload}  ({datetime.date.today().isoformat()})"
+             + (f", last {args.last} dispatches of each kernel" if args.last else ""),
              f"# command: {args.command}",
              f"source_hash = {_source_hash()}",
              f"simds = {args.simds}, xcds = {args.xcds} (GRBM_GUI_ACTIVE is divided by the XCDs)",
@@ -179,6 +180,8 @@ def valu(args):
         per = {c: _per_dispatch(args.pmc, c, lambda n, k=k: k in n) for c in counters}
         if not per["SQ_WAVES"]:
             raise SystemExit(f"valu: no dispatch of {k}")
+        if args.last:  # the last K dispatches of the kernel (the timed steps)
+            per = {c: v[-args.last:] for c, v in per.items()}
         av = {c: sum(v) / len(v) for c, v in per.items() if v}
         busy = 4.0 * av["SQ_ACTIVE_INST_VALU"] / (args.simds * av["GRBM_GUI_ACTIVE"] / args.xcds)
         lines.append(f"  {k:12s} {len(per['SQ_WAVES']):10d} {av['SQ_WAVES']:9.0f} "
@@ -219,6 +222,7 @@ def main():
         v.add_argument(a, required=True)
     v.add_argument("--simds", type=int, default=1024)
     v.add_argument("--xcds", type=int, default=8)
+    v.add_argument("--last", type=int, default=0)
     v.add_argument("--out")
     args = ap.parse_args()
     {"stats": stats, "trace": trace, "traffic": traffic, "valu": valu}[args.cmd](args)
