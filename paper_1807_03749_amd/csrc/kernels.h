@@ -530,18 +530,21 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
 #pragma unroll
         for (int c = 0; c < kMaxClusterSize; ++c) {
             if (c < s && ok) {
+                // the drawn excitor lies in [guide[gb], guide[gb + 1]] (past the table: in
+                // [guide[gcap - 1], ne - 1]); the last candidate's prefix exceeds x, so only the
+                // others are probed, and a bucket inside one excitor's weight needs no probe
                 const uint64_t gb = xs[c] >> gsh;
                 if (gb + 1 < a.gcap) {
                     l0[c] = guide[gb];
-                    h0[c] = guide[gb + 1] + 1u;
-                } else {  // past the table: search to the end
+                    h0[c] = guide[gb + 1];
+                } else {
                     l0[c] = guide[a.gcap - 1];
-                    h0[c] = (uint32_t)ne;
+                    h0[c] = (uint32_t)ne - 1u;
                 }
             }
         }
         // lock-step binary searches: first i in [l0, h0) with P[i] > x (the prefix of the
-        // draw records)
+        // draw records), else h0
         for (bool more = ok && s > 0; more;) {
             more = false;
 #pragma unroll
@@ -564,6 +567,21 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
                 if (c < s) ok &= (l0[b] != l0[c]);
         // selection probability and product of amplitudes, in draw order; each draw's weight
         // is its amplitude's (the prefix step P[i] - P[i-1] exactly)
+        // The drawn records' amplitudes and bitstrings: for one- and two-word determinants every
+        // load is issued before the first use (one latency instead of two); wider ones would
+        // hold too many registers, and load each field where it is used.
+        constexpr bool kPreload = W <= 2;
+        uint64_t ab[kMaxClusterSize], kx[kMaxClusterSize][kPreload ? W : 1];
+#pragma unroll
+        for (int c = 0; c < kMaxClusterSize; ++c) {
+            const uint64_t *rc = drec + (uint64_t)l0[c] * kRec;
+            const bool use = c < s && ok;
+            ab[c] = use ? rc[1] : 0ull;
+            if constexpr (kPreload) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) kx[c][w] = use ? rc[2 + w] : 0ull;
+            }
+        }
         double fact = 1.0;
         for (int c = 2; c <= s; ++c) fact *= (double)c;
         double p = (double)count * size_prob(s, lo, hi) * fact;
@@ -571,7 +589,7 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
 #pragma unroll
         for (int c = 0; c < kMaxClusterSize; ++c) {
             if (c < s && ok) {
-                const T ni = rec_amp<T>(drec[(uint64_t)l0[c] * kRec + 1]);
+                const T ni = rec_amp<T>(ab[c]);
                 const uint64_t qi = weight_of((double)ni);
                 p *= (double)qi / (double)Q;
                 if (c == 0)
@@ -596,12 +614,16 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
         int e = 0;
         // apply c_{X_s} first: annihilate holes ascending, then create particles descending
 #pragma unroll
-        for (int cc = 0; cc < kMaxClusterSize; ++cc) {
-            const int c = s - 1 - cc;
-            if (c < 0 || !ok) continue;
+        for (int c = kMaxClusterSize - 1; c >= 0; --c) {
+            if (c >= s || !ok) continue;
             uint64_t x[W];
 #pragma unroll
-            for (int w = 0; w < W; ++w) x[w] = drec[(uint64_t)l0[c] * kRec + 2 + w];
+            for (int w = 0; w < W; ++w) {
+                if constexpr (kPreload)
+                    x[w] = kx[c][w];
+                else
+                    x[w] = drec[(uint64_t)l0[c] * kRec + 2 + w];
+            }
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 uint64_t h = S.hf[w] & ~x[w];
