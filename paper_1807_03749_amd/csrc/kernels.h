@@ -79,6 +79,46 @@ struct ItemPartials {
     uint64_t *maxn;    // largest attempt count
 };
 
+// A block's four partials in one exchange: the shuffle tree of block_reduce_sum within each
+// wavefront (the same order, so the same sums), then thread 0 adds the wavefronts in order and
+// writes the block's entry.
+__device__ __forceinline__ void store_item_partials(double num, uint64_t att, uint64_t disc, uint64_t mx, ItemPartials part,
+                                                    uint32_t blk)
+{
+    __shared__ double s_num[kWaves];
+    __shared__ uint64_t s_att[kWaves], s_disc[kWaves], s_mx[kWaves];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        num += __shfl_down(num, o, 64);
+        att += __shfl_down(att, o, 64);
+        disc += __shfl_down(disc, o, 64);
+        const uint64_t m = __shfl_down(mx, o, 64);
+        mx = m > mx ? m : mx;
+    }
+    if (lane_id() == 0) {
+        s_num[wave_id()] = num;
+        s_att[wave_id()] = att;
+        s_disc[wave_id()] = disc;
+        s_mx[wave_id()] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double n = 0.0;
+        uint64_t a = 0, d = 0, m = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            n += s_num[w];
+            a += s_att[w];
+            d += s_disc[w];
+            m = s_mx[w] > m ? s_mx[w] : m;
+        }
+        part.num[blk] = n;
+        part.att[blk] = a;
+        part.disc[blk] = d;
+        part.maxn[blk] = m;
+    }
+}
+
 template <typename V, int NW = kWaves>
 __device__ __forceinline__ V block_reduce_max(V v)
 {
@@ -474,15 +514,7 @@ __device__ __forceinline__ void noncomposite_block(unsigned blk, const SysDev &S
         att = n;
         mx = n;
     }
-    const double bnum = block_reduce_sum(num);
-    const uint64_t batt = block_reduce_sum(att);
-    const uint64_t bmax = block_reduce_max(mx);
-    if (threadIdx.x == 0) {
-        part.num[blk] = bnum;
-        part.att[blk] = batt;
-        part.disc[blk] = 0;
-        part.maxn[blk] = bmax;
-    }
+    store_item_partials(num, att, 0, mx, part, blk);
 }
 
 // --------------------------------------------------------------- sampled clusters
@@ -679,16 +711,7 @@ __device__ __forceinline__ void select_block(unsigned blk, const SysDev &S, cons
         }
         it.cnt[j] = cnt;
     }
-    const double bnum = block_reduce_sum(num);
-    const uint64_t batt = block_reduce_sum(att);
-    const uint64_t bdisc = block_reduce_sum(disc);
-    const uint64_t bmax = block_reduce_max(mx);
-    if (threadIdx.x == 0) {
-        part.num[blk] = bnum;
-        part.att[blk] = batt;
-        part.disc[blk] = bdisc;
-        part.maxn[blk] = bmax;
-    }
+    store_item_partials(num, att, disc, mx, part, blk);
     if (k == 0) it.cnt[item_base + a.n_sel] = 0;  // closing entry of the slot-count scan
 }
 
