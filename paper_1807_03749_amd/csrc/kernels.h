@@ -1144,9 +1144,19 @@ __device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDe
         base += total;
         __syncthreads();
     }
-    const uint32_t bs = block_reduce_sum(spawns);
-    const uint32_t bd = block_reduce_sum(deaths);
+    // spawns and deaths of the block in one exchange (16 bits each per wavefront suffice)
+    uint32_t sd = spawns | deaths << 16;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sd += __shfl_down(sd, o, 64);
+    if (lane_id() == 0) wave_tot[wave_id()] = sd;
+    __syncthreads();
     if (threadIdx.x == 0) {
+        uint32_t bs = 0, bd = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            bs += wave_tot[w] & 0xFFFFu;
+            bd += wave_tot[w] >> 16;
+        }
         gs.count[blk] = base;
         gs.spawns[blk] = bs;
         gs.deaths[blk] = bd;
