@@ -819,6 +819,10 @@ __device__ __forceinline__ bool gen_excitation(const SysDev &S, const uint64_t *
         j = select_bit<W>(d, (int)(xy >> 16));
         ta = 2 * alpha + (i & 1);
         if (bit_test<W>(d, ta)) return false;
+        // the target's level is L(d) - [i virtual] - [j virtual] + [a virtual] + [b virtual]:
+        // when it exceeds the truncation whatever b is, the attempt ends here (the same
+        // outcome as the level test below, before the momentum arithmetic)
+        if (level_of<W>(S, d) - (i >= N) - (j >= N) + (ta >= N) > S.l) return false;
         // k_b = k_i + k_j - k_a, all three components in one integer sum of the packed fields
         // (each field stays inside its 10 bits: no carry or borrow crosses between them)
         const int G = S.G, D = 2 * G + 1;
