@@ -810,19 +810,25 @@ __device__ __forceinline__ bool gen_excitation(const SysDev &S, const uint64_t *
 {
     Draws r(a.key0, a.key1, purpose, k, m, a.step);
     const int N = S.nel;
-    j = tb = -1;
+    i = j = ta = tb = -1;
     if (S.kind == kSystemUEG) {
         const uint32_t pr = (uint32_t)below(r.get(0), S.npairs);
         const int alpha = (int)below(r.get(1), S.half);
         const uint32_t xy = S.pairs[pr];  // the pair (x < y) of lexicographic rank pr, tabulated
-        i = select_bit<W>(d, (int)(xy & 0xFFFFu));
-        j = select_bit<W>(d, (int)(xy >> 16));
+        const int x = (int)(xy & 0xFFFFu), y = (int)(xy >> 16);
+        // The target's level is L(d) - [i virtual] - [j virtual] + [a virtual] + [b virtual].
+        // When it exceeds the truncation whatever b is, the attempt ends early: the same
+        // outcome as the level test below.  d's occupied orbitals in index order are its
+        // N - L(d) reference ones, then its virtual ones, so i (the x-th) is virtual iff
+        // x >= N - L(d); with N even, a = 2 alpha + spin is virtual iff alpha >= N / 2.  So
+        // the test can run before the orbitals are selected.
+        const int Ld = level_of<W>(S, d);
+        if ((N & 1) == 0 && Ld - (x >= N - Ld) - (y >= N - Ld) + (alpha >= N / 2) > S.l) return false;
+        i = select_bit<W>(d, x);
+        j = select_bit<W>(d, y);
         ta = 2 * alpha + (i & 1);
         if (bit_test<W>(d, ta)) return false;
-        // the target's level is L(d) - [i virtual] - [j virtual] + [a virtual] + [b virtual]:
-        // when it exceeds the truncation whatever b is, the attempt ends here (the same
-        // outcome as the level test below, before the momentum arithmetic)
-        if (level_of<W>(S, d) - (i >= N) - (j >= N) + (ta >= N) > S.l) return false;
+        if (Ld - (i >= N) - (j >= N) + (ta >= N) > S.l) return false;  // (odd N)
         // k_b = k_i + k_j - k_a, all three components in one integer sum of the packed fields
         // (each field stays inside its 10 bits: no carry or borrow crosses between them)
         const int G = S.G, D = 2 * G + 1;
