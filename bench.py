@@ -39,8 +39,11 @@ from paper_1807_03749_amd import ccmc, driver, inputs  # noqa: E402
 
 METRIC = "cluster spawn attempts/s on 1 MI355X; FP32 vs FP64 at equal E_proj error"
 HBM_PEAK_GBS = 8000.0
-# Plain 32-bit vector ALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
-ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+# 32-bit vector ALU lane operations: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6 T lane-ops/s,
+# the published FP32 vector rate (157.3 TFLOP/s) with an FMA counted as one operation.  The
+# counters show the kernels here issuing more than 16 lane operations per SIMD and cycle (the
+# molecule-like generator: 41.6 T lane-ops/s executed), so a 16-lane peak would be exceeded.
+ALU_PEAK_GOPS = 256 * 4 * 32 * 2.4
 # Algorithmic lane operations of one spawning attempt: Philox4x32-10 blocks (10 rounds of two
 # 32x32 multiplies (4 ops), 4 xors and 2 key adds = 100 ops per block) -- 2 blocks for the UEG
 # generator's three 64-bit draws, 3 for the molecular generator's five -- plus about 100
