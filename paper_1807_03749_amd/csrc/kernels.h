@@ -1209,26 +1209,29 @@ __global__ void __launch_bounds__(kThreads) k_generate(const GenerateArgs<W, T> 
 }
 
 // Determinants of one or two words fit the register budget of 7 waves per SIMD without
-// spilling (at most 72 VGPRs); wider ones keep the compiler's own budget.
-#define CCMC_GENERATE_7_WAVES(W_, T_)                                                                                  \
+// spilling (at most 72 VGPRs), four words that of 6 (at most 80); wider ones keep the
+// compiler's own budget.
+#define CCMC_GENERATE_WAVES(W_, T_, N_)                                                                                \
     template <>                                                                                                        \
-    __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7, 7)))                            \
+    __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N_, N_)))                          \
     k_generate<W_, T_>(const GenerateArgs<W_, T_> *__restrict__ args, BatchMap bm)                                     \
     {                                                                                                                  \
         uint32_t blk, nblk;                                                                                            \
         k_generate_entry<W_, T_>(args[batch_state(bm, blk, nblk)], blk, nblk);                                         \
     }                                                                                                                  \
     template <>                                                                                                        \
-    __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7, 7)))                            \
+    __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N_, N_)))                          \
     k_generate<W_, T_>(const GenerateArgs<W_, T_> A)                                                                   \
     {                                                                                                                  \
         k_generate_entry<W_, T_>(A, blockIdx.x, gridDim.x);                                                            \
     }
-CCMC_GENERATE_7_WAVES(1, float)
-CCMC_GENERATE_7_WAVES(1, double)
-CCMC_GENERATE_7_WAVES(2, float)
-CCMC_GENERATE_7_WAVES(2, double)
-#undef CCMC_GENERATE_7_WAVES
+CCMC_GENERATE_WAVES(1, float, 7)
+CCMC_GENERATE_WAVES(1, double, 7)
+CCMC_GENERATE_WAVES(2, float, 7)
+CCMC_GENERATE_WAVES(2, double, 7)
+CCMC_GENERATE_WAVES(4, float, 6)
+CCMC_GENERATE_WAVES(4, double, 6)
+#undef CCMC_GENERATE_WAVES
 
 // Dense layout of the records.  Output position r belongs to the region q (generation block
 // q) with boff[q] <= r < boff[q+1], at slot position r - boff[q] of that region.  Block b
