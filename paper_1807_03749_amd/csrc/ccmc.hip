@@ -563,7 +563,7 @@ ccmc_status upload_system(ccmc_state *st, const ccmc_integrals *ints)
 // ------------------------------------------------------------------------ the store
 // Entries of the selection guide for a store capacity: several times the buckets the shift
 // aims at, so that Q may grow between steps before draws fall past the table.
-uint64_t guide_cap(uint64_t scap) { return 4 * scap + 8; }
+uint64_t guide_cap(uint64_t scap) { return 16 * scap + 8; }
 
 // Grow the store (both buffers) to hold n entries, keeping the current contents.
 template <int W, typename T>
@@ -682,11 +682,15 @@ ccmc_status plan_sizes(Plan<W, T> &p)
     a.n_ranks = p.ranked ? st->opt.n_ranks : 1;
     p.ptiles = p.ranked ? (ne + kSortTile - 1) / kSortTile : 0;
     {
-        // guide shift from the last step's Q (any shift gives the same draws; this one keeps
-        // about two buckets per excitor)
+        // guide shift from the last step's Q (any shift gives the same draws).  A store beyond
+        // about 10^6 excitors takes about eight buckets per excitor, so that most draws land in
+        // a bucket inside one excitor's weight and need no prefix probe in HBM (16e/92so items
+        // 947 -> 779 us, guide 100 -> 139 us); a smaller one, whose probes hit the cache, two,
+        // because there the fill of the finer guide costs more than the probes it saves.
+        const uint64_t per = ne > (1ull << 20) ? 8 : 2;
         const uint64_t q_est = st->last_q ? st->last_q : (ne << 24);
         uint32_t sh = 0;
-        while (sh < 63 && (q_est >> sh) + 2 > 2 * ne + 2) ++sh;
+        while (sh < 63 && (q_est >> sh) + 2 > per * ne + 2) ++sh;
         a.gsh = sh;
     }
     p.slot_cap = std::max<uint64_t>(kGenSlots, (st->slot_hint + kGenSlots - 1) / kGenSlots * kGenSlots);
