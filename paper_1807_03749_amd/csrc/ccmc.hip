@@ -1141,7 +1141,12 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
                   return Work{kb + tb + (p.ids ? 8.0 : 0.0), &p.st->cnt_rec, 0, &p.st->cnt_att, kb + 2 * tb + 12.0,
                               &p.st->cnt_live_items};
               }),
-              [s](const auto &a, unsigned g, auto... bm) { k_generate<W, T><<<g, kThreads, 0, s>>>(a, bm...); });
+              [s, ueg = ps[0].st->hs.kind == CCMC_UEG](const auto &a, unsigned g, auto... bm) {
+                  if (ueg)
+                      k_generate<W, T, kSystemUEG><<<g, kThreads, 0, s>>>(a, bm...);
+                  else
+                      k_generate<W, T, kSystemMol><<<g, kThreads, 0, s>>>(a, bm...);
+              });
     }
     {
         using A = ScanLbArgs<uint32_t, CountSrc<uint32_t>, RegionOut>;
@@ -2036,7 +2041,7 @@ ccmc_status ccmc_step_batch(ccmc_state *const *states, int n, const double *tau,
             return CCMC_EOVERFLOW;
         }
     }
-    // one batch per (words, precision); each runs on the stream of its first state, after the
+    // one batch per (words, precision, kind of system); each runs on the stream of its first state, after the
     // work already queued on the others' streams.  Every group is queued before the host
     // waits for any, so groups on different streams run on the device together.
     const auto t0 = std::chrono::steady_clock::now();
@@ -2050,7 +2055,9 @@ ccmc_status ccmc_step_batch(ccmc_state *const *states, int n, const double *tau,
         std::vector<uint64_t> ga;
         std::vector<ccmc_stats *> go;
         for (int j = i; j < n; ++j) {
-            if (done[j] || states[j]->WP != states[i]->WP || states[j]->fp32 != states[i]->fp32) continue;
+            if (done[j] || states[j]->WP != states[i]->WP || states[j]->fp32 != states[i]->fp32 ||
+                states[j]->hs.kind != states[i]->hs.kind)
+                continue;
             done[j] = 1;
             g.push_back(states[j]);
             gt.push_back(tau[j]);

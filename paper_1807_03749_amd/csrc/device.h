@@ -44,6 +44,14 @@ struct SysDev {
     const uint32_t *kpack;    // UEG [nsp]: wavevector components + G + 256 in 10-bit fields (x, y, z)
 };
 
+// Kernels specialised for one kind of system pass K = kSystemUEG or kSystemMol (the other
+// kind's code is then dropped at compile time); K = 0 decides at run time.
+template <int K>
+__device__ __forceinline__ bool is_ueg(const SysDev &S)
+{
+    return K == kSystemUEG || (K == 0 && S.kind == kSystemUEG);
+}
+
 // ------------------------------------------------------------------ Philox4x32-10
 // Salmon, Moraes, Dror & Shaw (SC'11): ten rounds, two 32x32->64 products per round,
 // Weyl key schedule.
@@ -207,12 +215,12 @@ __device__ __forceinline__ int excitor_sign(const SysDev &S, const uint64_t *d)
 
 // ------------------------------------------------------------------- integrals
 // <pq|rs> with spin deltas; momentum conservation is guaranteed by the callers (UEG).
-template <typename T>
+template <typename T, int K = 0>
 __device__ __forceinline__ T u2(const SysDev &S, int p, int q, int r, int s)
 {
     if (((p ^ r) & 1) | ((q ^ s) & 1)) return T(0);
     const int P = p >> 1, Q = q >> 1, R = r >> 1, X = s >> 1;
-    if (S.kind == kSystemUEG) {
+    if (is_ueg<K>(S)) {
         const int *np = S.nvec + 3 * P, *nr = S.nvec + 3 * R;
         const int dx = np[0] - nr[0], dy = np[1] - nr[1], dz = np[2] - nr[2];
         const int d2 = dx * dx + dy * dy + dz * dz;
@@ -222,22 +230,22 @@ __device__ __forceinline__ T u2(const SysDev &S, int p, int q, int r, int s)
     const size_t n = (size_t)S.nsp;
     return static_cast<const T *>(S.eri)[((P * n + R) * n + Q) * n + X];
 }
-template <typename T>
+template <typename T, int K = 0>
 __device__ __forceinline__ T anti(const SysDev &S, int p, int q, int r, int s)
 {
-    return u2<T>(S, p, q, r, s) - u2<T>(S, p, q, s, r);
+    return u2<T, K>(S, p, q, r, s) - u2<T, K>(S, p, q, s, r);
 }
-template <typename T>
+template <typename T, int K = 0>
 __device__ __forceinline__ T h1(const SysDev &S, int p, int q)
 {
     if ((p ^ q) & 1) return T(0);
-    if (S.kind == kSystemUEG) return T(0);  // only used off-diagonal (singles)
+    if (is_ueg<K>(S)) return T(0);  // only used off-diagonal (singles)
     return static_cast<const T *>(S.h)[(size_t)(p >> 1) * S.nsp + (q >> 1)];
 }
 
 // <D'| H |D> for D' = D with f1 < f2 replaced by t1 < t2 (a double excitation):
 // gamma <t1 t2 || f1 f2> with gamma = <D'| c+_t1 c+_t2 c_f2 c_f1 |D> from popcounts.
-template <int W, typename T>
+template <int W, typename T, int K = 0>
 __device__ __forceinline__ T double_element(const SysDev &S, const uint64_t *d, int f1, int f2, int t1, int t2)
 {
     uint64_t x[W];
@@ -250,13 +258,13 @@ __device__ __forceinline__ T double_element(const SysDev &S, const uint64_t *d, 
     e += count_below<W>(x, t2);
     bit_flip<W>(x, t2);
     e += count_below<W>(x, t1);
-    const T v = anti<T>(S, t1, t2, f1, f2);
+    const T v = anti<T, K>(S, t1, t2, f1, f2);
     return (e & 1) ? -v : v;
 }
 
 // <D'| H |D> for D' = D with f replaced by t (a single excitation):
 // gamma (h_tf + sum_{k in D} <tk||fk>) with gamma = <D'| c+_t c_f |D>.
-template <int W, typename T>
+template <int W, typename T, int K = 0>
 __device__ __forceinline__ T single_element(const SysDev &S, const uint64_t *d, int f, int t)
 {
     uint64_t x[W];
@@ -265,14 +273,14 @@ __device__ __forceinline__ T single_element(const SysDev &S, const uint64_t *d, 
     int e = count_below<W>(x, f);
     bit_flip<W>(x, f);
     e += count_below<W>(x, t);
-    T v = h1<T>(S, t, f);
+    T v = h1<T, K>(S, t, f);
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         uint64_t m = d[w];
         while (m) {
             const int k = 64 * w + __ffsll((long long)m) - 1;
             m &= m - 1;
-            v += anti<T>(S, t, k, f, k);
+            v += anti<T, K>(S, t, k, f, k);
         }
     }
     return (e & 1) ? -v : v;

@@ -803,7 +803,7 @@ struct Records {
 // a single).  spawn_amount then evaluates the Slater-Condon element and the spawned amount
 // -dtau H_tc s_D(c) s_D(t) A / (n p_gen) (Sec. II sign rule, Sec. IV.C), with the stochastic
 // rounding of amounts below the spawn cutoff; false when nothing is spawned.
-template <int W>
+template <int W, int K>
 __device__ __forceinline__ bool gen_excitation(const SysDev &S, const uint64_t *d, uint32_t purpose, uint32_t k,
                                                uint32_t m, const StepArgs &a, uint64_t *tgt, int &i, int &j, int &ta,
                                                int &tb)
@@ -811,7 +811,7 @@ __device__ __forceinline__ bool gen_excitation(const SysDev &S, const uint64_t *
     Draws r(a.key0, a.key1, purpose, k, m, a.step);
     const int N = S.nel;
     i = j = ta = tb = -1;
-    if (S.kind == kSystemUEG) {
+    if (is_ueg<K>(S)) {
         const uint32_t pr = (uint32_t)below(r.get(0), S.npairs);
         const int alpha = (int)below(r.get(1), S.half);
         const uint32_t xy = S.pairs[pr];  // the pair (x < y) of lexicographic rank pr, tabulated
@@ -840,18 +840,26 @@ __device__ __forceinline__ bool gen_excitation(const SysDev &S, const uint64_t *
         tb = 2 * beta + (j & 1);
         if (tb == ta || bit_test<W>(d, tb)) return false;
     } else {
+        // the truncation test first, from the draws alone (as in the UEG generator: with N
+        // even the target's level follows from the occupied ranks and the alphas)
         const bool single = uniform53(r.get(0)) < S.p_single;
+        const int Ld = level_of<W>(S, d);
         if (single) {
             const int xa = (int)below(r.get(1), (uint64_t)N);
+            const int aa = (int)below(r.get(2), S.half);
+            if ((N & 1) == 0 && Ld - (xa >= N - Ld) + (aa >= N / 2) > S.l) return false;
             i = select_bit<W>(d, xa);
-            ta = 2 * (int)below(r.get(2), S.half) + (i & 1);
+            ta = 2 * aa + (i & 1);
             if (bit_test<W>(d, ta)) return false;
         } else {
             const uint32_t xy = S.pairs[(uint32_t)below(r.get(1), S.npairs)];
-            i = select_bit<W>(d, (int)(xy & 0xFFFFu));
-            j = select_bit<W>(d, (int)(xy >> 16));
-            ta = 2 * (int)below(r.get(2), S.half) + (i & 1);
-            tb = 2 * (int)below(r.get(3), S.half) + (j & 1);
+            const int x = (int)(xy & 0xFFFFu), y = (int)(xy >> 16);
+            const int aa = (int)below(r.get(2), S.half), ab = (int)below(r.get(3), S.half);
+            if ((N & 1) == 0 && Ld - (x >= N - Ld) - (y >= N - Ld) + (aa >= N / 2) + (ab >= N / 2) > S.l) return false;
+            i = select_bit<W>(d, x);
+            j = select_bit<W>(d, y);
+            ta = 2 * aa + (i & 1);
+            tb = 2 * ab + (j & 1);
             if (ta == tb || bit_test<W>(d, ta) || bit_test<W>(d, tb)) return false;
         }
     }
@@ -867,14 +875,14 @@ __device__ __forceinline__ bool gen_excitation(const SysDev &S, const uint64_t *
     return level_of<W>(S, tgt) <= S.l;
 }
 
-template <int W, typename T>
+template <int W, typename T, int K>
 __device__ __forceinline__ bool spawn_amount(const SysDev &S, const uint64_t *d, const uint64_t *tgt, int i, int j, int ta,
                                              int tb, T A, uint32_t n, uint32_t purpose, uint32_t k, uint32_t m,
                                              const StepArgs &a, T &x)
 {
     double pgen;
     int ridx;
-    if (S.kind == kSystemUEG) {
+    if (is_ueg<K>(S)) {
         pgen = (((i & 1) == (j & 1)) ? 2.0 : 1.0) / ((double)S.npairs * (double)S.half);
         ridx = 2;
     } else if (j < 0) {
@@ -887,10 +895,10 @@ __device__ __forceinline__ bool spawn_amount(const SysDev &S, const uint64_t *d,
     }
     T H;
     if (j < 0) {
-        H = single_element<W, T>(S, d, i, ta);
+        H = single_element<W, T, K>(S, d, i, ta);
     } else {
         const int t1 = ta < tb ? ta : tb, t2 = ta < tb ? tb : ta;
-        H = double_element<W, T>(S, d, i, j, t1, t2);
+        H = double_element<W, T, K>(S, d, i, j, t1, t2);
     }
     const int sc = excitor_sign<W>(S, d), st = excitor_sign<W>(S, tgt);
     // -dtau H_ij s_D(i) s_D(j) A / (n p_gen)  (Sec. II spawning sign, Sec. IV.C eq. 10)
@@ -952,7 +960,7 @@ struct GenStats {
 // only a small fraction of the attempts survive pass 1.
 constexpr uint32_t kCandDeath = 1u << 31;
 
-template <int W, typename T>
+template <int W, typename T, int K>
 __device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDev S, Items<T> it, const uint64_t *__restrict__ off,
                                                        const uint64_t *__restrict__ block_item, uint64_t n_fnc,
                                                        uint64_t n_items, uint64_t slot_cap, StepArgs a, Records rec,
@@ -1061,7 +1069,7 @@ __device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDe
 #pragma unroll
                 for (int ww = 0; ww < W; ++ww) d[ww] = it.key[(uint64_t)ww * it.stride + item];
                 int i, j, ta, tb;
-                keep = gen_excitation<W>(S, d, nc ? kSpawnNonComposite : kSpawnSampled, k, slot - 1, a, tgt, i, j, ta, tb);
+                keep = gen_excitation<W, K>(S, d, nc ? kSpawnNonComposite : kSpawnSampled, k, slot - 1, a, tgt, i, j, ta, tb);
                 orb = (uint64_t)(uint16_t)i | ((uint64_t)(uint16_t)j << 16) | ((uint64_t)(uint16_t)ta << 32) |
                       ((uint64_t)(uint16_t)tb << 48);
             }
@@ -1129,7 +1137,7 @@ __device__ __forceinline__ void generate_body(uint32_t blk, uint32_t nblk, SysDe
                     bit_flip<W>(tgt, j);
                     bit_flip<W>(tgt, tb);
                 }
-                emit = spawn_amount<W, T>(S, d, tgt, i, j, ta, tb, it.A[item], it.n[item],
+                emit = spawn_amount<W, T, K>(S, d, tgt, i, j, ta, tb, it.A[item], it.n[item],
                                           nc ? kSpawnNonComposite : kSpawnSampled, k, cs - 1, a, x);
                 spawns += emit ? 1u : 0u;
                 id = ((nc ? 0ull : 1ull) << 62) | ((uint64_t)k << 30) | (uint64_t)cs;
@@ -1189,48 +1197,54 @@ struct GenerateArgs {
     Scratch *sc;
 };
 
-template <int W, typename T>
+template <int W, typename T, int K>
 __device__ __forceinline__ void k_generate_entry(const GenerateArgs<W, T> &A, uint32_t blk, uint32_t nblk)
 {
-    generate_body<W, T>(blk, nblk, A.S, A.it, A.off, A.block_item, A.n_fnc, A.n_items, A.slot_cap, A.a, A.rec, A.keep_ids, A.gs, A.sc);
+    generate_body<W, T, K>(blk, nblk, A.S, A.it, A.off, A.block_item, A.n_fnc, A.n_items, A.slot_cap, A.a, A.rec, A.keep_ids, A.gs, A.sc);
 }
 
-template <int W, typename T>
+// One kernel per kind of system (K = kSystemUEG or kSystemMol): the other generator's code and
+// registers are left out.
+template <int W, typename T, int K>
 __global__ void __launch_bounds__(kThreads) k_generate(const GenerateArgs<W, T> *__restrict__ args, BatchMap bm)
 {
     uint32_t blk, nblk;
-    k_generate_entry<W, T>(args[batch_state(bm, blk, nblk)], blk, nblk);
+    k_generate_entry<W, T, K>(args[batch_state(bm, blk, nblk)], blk, nblk);
 }
 
-template <int W, typename T>
+template <int W, typename T, int K>
 __global__ void __launch_bounds__(kThreads) k_generate(const GenerateArgs<W, T> A)
 {
-    k_generate_entry<W, T>(A, blockIdx.x, gridDim.x);
+    k_generate_entry<W, T, K>(A, blockIdx.x, gridDim.x);
 }
 
 // Determinants of one or two words fit the register budget of 7 waves per SIMD without
 // spilling (at most 72 VGPRs), four words that of 6 (at most 80); wider ones keep the
 // compiler's own budget.
-#define CCMC_GENERATE_WAVES(W_, T_, N_)                                                                                \
+#define CCMC_GENERATE_WAVES(W_, T_, K_, N_)                                                                            \
     template <>                                                                                                        \
     __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N_, N_)))                          \
-    k_generate<W_, T_>(const GenerateArgs<W_, T_> *__restrict__ args, BatchMap bm)                                     \
+    k_generate<W_, T_, K_>(const GenerateArgs<W_, T_> *__restrict__ args, BatchMap bm)                                 \
     {                                                                                                                  \
         uint32_t blk, nblk;                                                                                            \
-        k_generate_entry<W_, T_>(args[batch_state(bm, blk, nblk)], blk, nblk);                                         \
+        k_generate_entry<W_, T_, K_>(args[batch_state(bm, blk, nblk)], blk, nblk);                                     \
     }                                                                                                                  \
     template <>                                                                                                        \
     __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N_, N_)))                          \
-    k_generate<W_, T_>(const GenerateArgs<W_, T_> A)                                                                   \
+    k_generate<W_, T_, K_>(const GenerateArgs<W_, T_> A)                                                               \
     {                                                                                                                  \
-        k_generate_entry<W_, T_>(A, blockIdx.x, gridDim.x);                                                            \
+        k_generate_entry<W_, T_, K_>(A, blockIdx.x, gridDim.x);                                                        \
     }
-CCMC_GENERATE_WAVES(1, float, 7)
-CCMC_GENERATE_WAVES(1, double, 7)
-CCMC_GENERATE_WAVES(2, float, 7)
-CCMC_GENERATE_WAVES(2, double, 7)
-CCMC_GENERATE_WAVES(4, float, 6)
-CCMC_GENERATE_WAVES(4, double, 6)
+#define CCMC_GENERATE_WAVES_BOTH(W_, T_, N_)                                                                           \
+    CCMC_GENERATE_WAVES(W_, T_, kSystemUEG, N_)                                                                        \
+    CCMC_GENERATE_WAVES(W_, T_, kSystemMol, N_)
+CCMC_GENERATE_WAVES_BOTH(1, float, 7)
+CCMC_GENERATE_WAVES_BOTH(1, double, 7)
+CCMC_GENERATE_WAVES_BOTH(2, float, 7)
+CCMC_GENERATE_WAVES_BOTH(2, double, 7)
+CCMC_GENERATE_WAVES_BOTH(4, float, 6)
+CCMC_GENERATE_WAVES_BOTH(4, double, 6)
+#undef CCMC_GENERATE_WAVES_BOTH
 #undef CCMC_GENERATE_WAVES
 
 // Dense layout of the records.  Output position r belongs to the region q (generation block
