@@ -565,40 +565,17 @@ ccmc_status upload_system(ccmc_state *st, const ccmc_integrals *ints)
 // aims at, so that Q may grow between steps before draws fall past the table.
 uint64_t guide_cap(uint64_t scap) { return 16 * scap + 8; }
 
-// Grow the store (both buffers) to hold n entries, keeping the current contents.
+// The buffers sized by the store capacity whose contents do not outlive a step: the merge's
+// output store, the draw and guide arrays, the per-entry sums and the lookup index.  Ensured on
+// every call, so that a call that failed for memory after the store itself grew finds them again.
 template <int W, typename T>
-ccmc_status ensure_store(ccmc_state *st, uint64_t n)
+ccmc_status ensure_store_companions(ccmc_state *st, uint64_t nc)
 {
-    if (n <= st->scap) return CCMC_OK;
-    uint64_t nc = std::max<uint64_t>(n, std::max<uint64_t>(1024, st->scap + st->scap / 2));
-    DevBuf k, a, K, r;
-    TRY(ensure(st, k, nc * W * sizeof(uint64_t)));
-    TRY(ensure(st, a, nc * sizeof(T)));
-    TRY(ensure(st, K, nc * sizeof(T)));
-    TRY(ensure(st, r, nc * sizeof(uint64_t)));
-    const int c = st->cur;
-    if (st->ne) {
-        HIP_TRY(hipMemcpy2DAsync(k.p, nc * sizeof(uint64_t), st->skey[c].p, st->scap * sizeof(uint64_t),
-                                 st->ne * sizeof(uint64_t), W, hipMemcpyDeviceToDevice, st->stream));
-        HIP_TRY(hipMemcpyAsync(a.p, st->samp[c].p, st->ne * sizeof(T), hipMemcpyDeviceToDevice, st->stream));
-        HIP_TRY(hipMemcpyAsync(K.p, st->sK[c].p, st->ne * sizeof(T), hipMemcpyDeviceToDevice, st->stream));
-        HIP_TRY(hipMemcpyAsync(r.p, st->srank[c].p, st->ne * sizeof(uint64_t), hipMemcpyDeviceToDevice, st->stream));
-        HIP_TRY(hipStreamSynchronize(st->stream));
-    }
-    for (int b = 0; b < 2; ++b) {
-        release(st, st->skey[b]);
-        release(st, st->samp[b]);
-        release(st, st->sK[b]);
-        release(st, st->srank[b]);
-    }
-    st->skey[c] = k;
-    st->samp[c] = a;
-    st->sK[c] = K;
-    st->srank[c] = r;
-    TRY(ensure(st, st->skey[1 - c], nc * W * sizeof(uint64_t)));
-    TRY(ensure(st, st->samp[1 - c], nc * sizeof(T)));
-    TRY(ensure(st, st->sK[1 - c], nc * sizeof(T)));
-    TRY(ensure(st, st->srank[1 - c], nc * sizeof(uint64_t)));
+    const int m = 1 - st->cur;
+    TRY(ensure(st, st->skey[m], nc * W * sizeof(uint64_t)));
+    TRY(ensure(st, st->samp[m], nc * sizeof(T)));
+    TRY(ensure(st, st->sK[m], nc * sizeof(T)));
+    TRY(ensure(st, st->srank[m], nc * sizeof(uint64_t)));
     TRY(ensure(st, st->P, nc * sizeof(uint64_t)));
     TRY(ensure(st, st->drec, nc * (2 + W) * sizeof(uint64_t)));
     TRY(ensure(st, st->guide, guide_cap(nc) * sizeof(uint32_t)));
@@ -607,15 +584,58 @@ ccmc_status ensure_store(ccmc_state *st, uint64_t n)
         TRY(ensure(st, st->perm, nc * sizeof(uint32_t)));
         TRY(ensure(st, st->seg, (kMaxRanks + 2) * sizeof(uint32_t)));
     }
-    // the per-entry sums start at zero (a grown buffer holds no contents)
+    // the per-entry sums start at zero: a reallocated buffer holds no contents
+    const void *held = st->delta.p;
     TRY(ensure(st, st->delta, nc * sizeof(double)));
-    k_fill<double><<<grid_for(nc), kThreads, 0, st->stream>>>(ptr<double>(st->delta), nc, 0.0);
+    if (st->delta.p != held)
+        k_fill<double><<<grid_for(st->delta.bytes / sizeof(double)), kThreads, 0, st->stream>>>(
+            ptr<double>(st->delta), st->delta.bytes / sizeof(double), 0.0);
     // the lookup index: every kFence-th rank (for a store too large for the cache), and the
     // rank table, at most one bucket per fence entry rounded up to a power of two (planned per step)
     TRY(ensure(st, st->fence, (nc / kFence + 2) * sizeof(uint64_t)));
     TRY(ensure(st, st->rtab, (8 * std::min<uint64_t>(nc, kFenceDirect) + 2 * (nc / kFence) + 2) * sizeof(uint32_t)));
-    st->scap = nc;
     return CCMC_OK;
+}
+
+// Grow the store to hold n entries, keeping the current contents.  The key words are stored
+// one row per word with the capacity as the row pitch, so the capacity changes together with
+// the current buffers or not at all: a call that fails for memory leaves the store as it was.
+template <int W, typename T>
+ccmc_status ensure_store(ccmc_state *st, uint64_t n)
+{
+    if (n > st->scap) {
+        const uint64_t nc = std::max<uint64_t>(n, std::max<uint64_t>(1024, st->scap + st->scap / 2));
+        DevBuf nb[4];
+        const size_t bytes[4] = {nc * W * sizeof(uint64_t), nc * sizeof(T), nc * sizeof(T), nc * sizeof(uint64_t)};
+        for (int b = 0; b < 4; ++b) {
+            const ccmc_status rc = ensure(st, nb[b], bytes[b]);
+            if (rc != CCMC_OK) {
+                for (DevBuf &x : nb) release(st, x);
+                return rc;
+            }
+        }
+        const int c = st->cur;
+        if (st->ne) {
+            HIP_TRY(hipMemcpy2DAsync(nb[0].p, nc * sizeof(uint64_t), st->skey[c].p, st->scap * sizeof(uint64_t),
+                                     st->ne * sizeof(uint64_t), W, hipMemcpyDeviceToDevice, st->stream));
+            HIP_TRY(hipMemcpyAsync(nb[1].p, st->samp[c].p, st->ne * sizeof(T), hipMemcpyDeviceToDevice, st->stream));
+            HIP_TRY(hipMemcpyAsync(nb[2].p, st->sK[c].p, st->ne * sizeof(T), hipMemcpyDeviceToDevice, st->stream));
+            HIP_TRY(hipMemcpyAsync(nb[3].p, st->srank[c].p, st->ne * sizeof(uint64_t), hipMemcpyDeviceToDevice, st->stream));
+            HIP_TRY(hipStreamSynchronize(st->stream));
+        }
+        for (int b = 0; b < 2; ++b) {
+            release(st, st->skey[b]);
+            release(st, st->samp[b]);
+            release(st, st->sK[b]);
+            release(st, st->srank[b]);
+        }
+        st->skey[c] = nb[0];
+        st->samp[c] = nb[1];
+        st->sK[c] = nb[2];
+        st->srank[c] = nb[3];
+        st->scap = nc;
+    }
+    return ensure_store_companions<W, T>(st, st->scap);
 }
 
 // ---------------------------------------------------------------------- the step

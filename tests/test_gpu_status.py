@@ -1,6 +1,7 @@
 """Step statistics carry the call's wall time and each state's own outcome; the growth bound
-(blow-up detector) rolls a step back and leaves the state exactly as it was; a batch reports
-every state's own failure."""
+(blow-up detector) rolls a step back and leaves the state exactly as it was; so does a step
+refused for memory, wherever its planning ran out of budget; a batch reports every state's own
+failure."""
 from __future__ import annotations
 
 import sys
@@ -80,3 +81,44 @@ def test_batch_reports_each_states_own_failure():
     assert kb[3] == ka[3] and len(kb[1]) == len(ka[1])
     for s in (a, b, c):
         s.close()
+
+
+def test_budget_starved_twin_matches_after_every_retry():
+    """A step refused for memory leaves the state unchanged, wherever in its planning the budget
+    ran out: a twin whose budget is raised a little after each refusal (so that refusals fall
+    between the growth of the store and of the arrays sized by it) takes the same steps as an
+    unconstrained run.  Two key words per determinant (114 spin orbitals), so that a store laid
+    out with a stale row pitch would show."""
+    _say("[status] UEG 14e/114so CCSDT FP32: budget-starved twin against a free run")
+    mk = lambda: ccmc.State("ueg", 14, 3, n2_max=5, rs=1.0, precision="fp32", init_pop=20.0, seed=4242,
+                            full_noncomposite=1, min_spawn_attempts=4)
+    free, starved = mk(), mk()
+    assert free.n_words == 2
+    budget = starved.ccmc_memory() + 4096
+    starved.ccmc_set_budget(budget)
+    nsel, refused = 20, 0
+    for it in range(80):
+        ref = free.ccmc_step(0.01, 0.0, nsel)
+        # raise the twin's budget in steps of a sixth of the way to a little above what the free
+        # run holds, so that refusals fall at several points of the twin's planning
+        target = int(free.ccmc_memory() * 1.25) + (1 << 20)
+        for _ in range(2000):
+            try:
+                got = starved.ccmc_step(0.01, 0.0, nsel)
+                break
+            except ccmc.CCMCError as e:
+                assert e.status == ENOMEM, e
+                refused += 1
+                budget += max(65536, (target - budget) // 6)
+                starved.ccmc_set_budget(budget)
+        else:
+            raise AssertionError("the budget never sufficed")
+        for f in ("n_total", "n_ref", "n_excitors", "n_spawn_attempts", "eproj_num"):
+            assert got[f] == ref[f], (it, f, got[f], ref[f])
+        nsel = driver.selections(ref["n_total"])
+    a, b = free.ccmc_export(), starved.ccmc_export()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+    _say(f"[status] {refused} refusals, {len(a[1])} excitors, N_tot {ref['n_total']:.4g}")
+    assert refused >= 10
+    free.close()
+    starved.close()
