@@ -655,6 +655,7 @@ struct Plan {
     int c = 0, passes = 1;
     uint64_t ne = 0, n_fnc = 0, n_items = 0, slot_cap = 0, nblk_cap = 0, rec_cap = 0, mcap = 0, tiles = 0;
     uint64_t fold_tiles = 0, fin_blocks = 1, n_parts = 0, lb_words = 0;
+    uint64_t gentries = 0;   // selection-guide buckets the step fills (from the last step's Q)
     unsigned nb_fnc = 0, nb_sel = 0, nb_rt = 0, nb_abs = 0;
     uint64_t o_tick = 0, o_weights = 0, o_off = 0, o_boff = 0, o_merge = 0, o_ghist = 0, o_rstat = 0;
     uint64_t o_fold = 0, o_fin = 0;
@@ -712,6 +713,7 @@ ccmc_status plan_sizes(Plan<W, T> &p)
         uint32_t sh = 0;
         while (sh < 63 && (q_est >> sh) + 2 > per * ne + 2) ++sh;
         a.gsh = sh;
+        p.gentries = (q_est >> sh) + 2;
     }
     p.slot_cap = std::max<uint64_t>(kGenSlots, (st->slot_hint + kGenSlots - 1) / kGenSlots * kGenSlots);
     p.rec_cap = std::max<uint64_t>(1, std::min<uint64_t>(st->rec_hint, p.slot_cap));
@@ -1084,9 +1086,12 @@ ccmc_status batch_launch(std::vector<Plan<W, T> *> &all, Launched<W, T> &L)
                                      DrawRecs{ptr<uint64_t>(st->drec), (uint32_t)(2 + W)}});
             blk[i] = p.n_sel && p.ne ? grid_for(p.ne) : 0;
         }
-        // bytes: prefix, amplitude and bitstring read, the draw record written, about one guide
-        // entry per two excitors
-        stage(ar, recs, "guide", args, blk, works([&](auto &p) { return Work{10.0 + 8.0 + tb + kb + 8.0 * (2 + W), nullptr, p.ne}; }),
+        // bytes: prefix, amplitude and bitstring read, the draw record written, and the guide's
+        // buckets (one to two per excitor, four to eight beyond 2^20 excitors)
+        stage(ar, recs, "guide", args, blk, works([&](auto &p) {
+                  const double guide = p.ne ? 4.0 * (double)p.gentries / (double)p.ne : 0.0;
+                  return Work{guide + 8.0 + tb + kb + 8.0 * (2 + W), nullptr, p.ne};
+              }),
               [s](const auto &a, unsigned g, auto... bm) { k_guide<<<g, kThreads, 0, s>>>(a, bm...); });
     }
     // ---- (a2-a5, a9, a10) items: non-composite (FNC) then sampled clusters; then the rank table
