@@ -267,7 +267,8 @@ ccmc_status ccmc_export(const ccmc_state *st, uint64_t *keys, double *amps, uint
 
 /* Replace the store: keys strictly ascending, each with N electrons, excitation level in
  * [1, l], no bits at or above M, amplitudes finite and non-zero; N_0 finite; the next step
- * uses Philox counters of step index `step`.  EINVAL on any violation (state unchanged). */
+ * uses Philox counters of step index `step`.  EINVAL on any violation, ENOMEM when the store
+ * cannot grow to n entries within the budget (the state unchanged in both cases). */
 ccmc_status ccmc_import(ccmc_state *st, const uint64_t *keys, const double *amps, uint64_t n,
                         double n_ref, uint64_t step);
 

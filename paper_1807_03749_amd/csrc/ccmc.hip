@@ -1597,7 +1597,8 @@ ccmc_status import_impl(ccmc_state *st, const uint64_t *keys, const double *amps
         st->err = "import: N_0 not finite";
         return CCMC_EINVAL;
     }
-    st->ne = 0;
+    // a grown store keeps the old contents, so that a growth refused part way (the store's own
+    // buffers grown, the arrays sized by it not) leaves the state as it was
     TRY(ensure_store<W, T>(st, n + 1));
     const int c = st->cur;
     const uint64_t cap = st->scap;

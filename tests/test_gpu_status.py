@@ -122,3 +122,44 @@ def test_budget_starved_twin_matches_after_every_retry():
     assert refused >= 10
     free.close()
     starved.close()
+
+
+def test_import_refused_for_memory_leaves_the_store():
+    """ccmc_import under a budget that is raised a little after each refusal: every refusal leaves
+    the store, N_0 and the step index as they were (two key words, so that a stale row pitch
+    would show), and the import that succeeds holds exactly the imported store."""
+    _say("[status] UEG 14e/114so CCSDT FP64: import refused for memory")
+    mk = lambda seed, pop: ccmc.State("ueg", 14, 3, n2_max=5, rs=1.0, init_pop=pop, seed=seed)
+    big, small = mk(5, 2e4), mk(6, 20.0)
+    nb, ns = 20000, 20
+    for _ in range(40):
+        ns = driver.selections(small.ccmc_step(0.01, 0.0, ns)["n_total"])
+    for _ in range(60):
+        nb = driver.selections(big.ccmc_step(0.01, 0.0, nb)["n_total"])
+    kb, ab, n0b, stepb = big.ccmc_export()
+    before = small.ccmc_export()
+    # beyond the small state's store capacity (its excitors plus a step's records, >= 4096)
+    assert len(ab) > 20000, (len(ab), len(before[1]))
+    budget = small.ccmc_memory() + 4096
+    small.ccmc_set_budget(budget)
+    refused = 0
+    for _ in range(2000):  # steps of 256 KiB: the import needs a few MB for ~3x10^4 excitors
+        try:
+            small.ccmc_import(kb, ab, n0b, stepb)
+            break
+        except ccmc.CCMCError as e:
+            assert e.status == ENOMEM, e
+            refused += 1
+            now = small.ccmc_export()
+            assert np.array_equal(now[0], before[0]) and np.array_equal(now[1], before[1])
+            assert now[2] == before[2] and now[3] == before[3]
+            budget += 1 << 18
+            small.ccmc_set_budget(budget)
+    else:
+        raise AssertionError("the budget never sufficed")
+    after = small.ccmc_export()
+    assert np.array_equal(after[0], kb) and np.array_equal(after[1], ab) and after[2] == n0b and after[3] == stepb
+    _say(f"[status] {refused} refusals before the import of {len(ab)} excitors")
+    assert refused >= 5
+    big.close()
+    small.close()
