@@ -410,6 +410,7 @@ __global__ void __launch_bounds__(NT) k_radix_ghist(const RadixGhistArgs A)
 // must be zero before the launch.  Thread x also owns the digits x + j * kThreads of the
 // per-digit work.
 constexpr int kDigitsPerThread = kRadixBins / kThreads;
+constexpr int kRadixLbDepth = 4;  // predecessor tiles read per digit and look-back round
 
 template <typename V>
 __device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk, const uint64_t *__restrict__ key_in, const V *__restrict__ idx_in,
@@ -505,15 +506,34 @@ __device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk,
 #pragma unroll
         for (int j = 0; j < kDigitsPerThread; ++j) {
             if (pp[j] < 0) continue;
-            const uint64_t sw = __hip_atomic_load(&status[(uint64_t)pp[j] * kRadixBins + threadIdx.x + j * kThreads],
-                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t flag = sw & ~kLbValue;
-            if (flag == 0) {
-                busy = true;  // not published yet: poll again
-                continue;
+            // kRadixLbDepth predecessors per round, all loads in flight together; consumed
+            // nearest first up to the first inclusive word, or up to an unpublished one, from
+            // which the next round polls again
+            uint64_t sw[kRadixLbDepth];
+#pragma unroll
+            for (int q = 0; q < kRadixLbDepth; ++q) {
+                const int64_t p = pp[j] - q;
+                sw[q] = p >= 0 ? __hip_atomic_load(&status[(uint64_t)p * kRadixBins + threadIdx.x + j * kThreads],
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                               : kLbInclusive;
             }
-            excl[j] += sw & kLbValue;
-            pp[j] = flag == kLbInclusive ? -1 : pp[j] - 1;
+            bool stop = false;
+#pragma unroll
+            for (int q = 0; q < kRadixLbDepth; ++q) {
+                if (stop) continue;
+                const uint64_t flag = sw[q] & ~kLbValue;
+                if (flag == 0) {
+                    stop = true;  // not published yet: poll again from this tile
+                    continue;
+                }
+                excl[j] += sw[q] & kLbValue;
+                if (flag == kLbInclusive) {
+                    pp[j] = -1;
+                    stop = true;
+                } else {
+                    pp[j] -= 1;
+                }
+            }
             busy |= pp[j] >= 0;
         }
         if (!busy) break;
