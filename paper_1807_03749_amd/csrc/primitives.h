@@ -476,6 +476,11 @@ __device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk,
         }
         tile_cnt[j] = acc;
     }
+    // publish this tile's counts first, so that later tiles' look-backs find them sooner
+    uint64_t *st = status + t * kRadixBins;
+#pragma unroll
+    for (int j = 0; j < kDigitsPerThread; ++j)
+        lb_publish(&st[threadIdx.x + j * kThreads], t == 0 ? kLbInclusive : kLbAggregate, tile_cnt[j]);
     // global base of each digit: exclusive prefix of the pass histogram over the digits; and
     // the digit's start in the tile: exclusive prefix of the tile's counts
     uint32_t gbase[kDigitsPerThread], tbase[kDigitsPerThread];
@@ -490,14 +495,11 @@ __device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk,
             tcarry += ttot;
         }
     }
-    // publish this tile's counts, then sum the earlier tiles' counts (the digit chains of a
-    // thread advance together)
-    uint64_t *st = status + t * kRadixBins;
+    // sum the earlier tiles' counts (the digit chains of a thread advance together)
     uint64_t excl[kDigitsPerThread];
     int64_t pp[kDigitsPerThread];
 #pragma unroll
     for (int j = 0; j < kDigitsPerThread; ++j) {
-        lb_publish(&st[threadIdx.x + j * kThreads], t == 0 ? kLbInclusive : kLbAggregate, tile_cnt[j]);
         excl[j] = 0;
         pp[j] = (int64_t)t - 1;
     }
