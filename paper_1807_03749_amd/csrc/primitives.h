@@ -444,6 +444,9 @@ __device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk,
         k[r] = key_in[gc];
         ix[r] = idx_in ? idx_in[gc] : (V)g;
     }
+    uint32_t gh[kDigitsPerThread];  // this thread's digits of the pass histogram
+#pragma unroll
+    for (int j = 0; j < kDigitsPerThread; ++j) gh[j] = ghist[threadIdx.x + j * kThreads];
     uint32_t *cnt = wave_cnt[w];
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
@@ -483,16 +486,19 @@ __device__ __forceinline__ void radix_onesweep_body(uint32_t blk, uint32_t nblk,
         lb_publish(&st[threadIdx.x + j * kThreads], t == 0 ? kLbInclusive : kLbAggregate, tile_cnt[j]);
     // global base of each digit: exclusive prefix of the pass histogram over the digits; and
     // the digit's start in the tile: exclusive prefix of the tile's counts
+    // (both in one scan: the histogram in the high half, the tile's counts in the low half,
+    // which holds at most kSortTile and never carries; the histogram sums to the live count,
+    // below 2^32)
     uint32_t gbase[kDigitsPerThread], tbase[kDigitsPerThread];
     {
-        uint32_t carry = 0, tcarry = 0;
+        uint64_t carry = 0;
 #pragma unroll
         for (int j = 0; j < kDigitsPerThread; ++j) {
-            uint32_t tot, ttot;
-            gbase[j] = carry + block_exclusive_scan(ghist[threadIdx.x + j * kThreads], &tot);
+            uint64_t tot;
+            const uint64_t ex = carry + block_exclusive_scan(((uint64_t)gh[j] << 32) | tile_cnt[j], &tot);
             carry += tot;
-            tbase[j] = tcarry + block_exclusive_scan(tile_cnt[j], &ttot);
-            tcarry += ttot;
+            gbase[j] = (uint32_t)(ex >> 32);
+            tbase[j] = (uint32_t)ex;
         }
     }
     // sum the earlier tiles' counts (the digit chains of a thread advance together)
