@@ -2040,9 +2040,10 @@ __device__ __forceinline__ void chunk_of(uint64_t n, uint64_t g, uint64_t nb, ui
     hi = lo + c < n ? lo + c : n;
 }
 
-__device__ __forceinline__ void final_part_body(uint32_t blk, uint32_t nblk, ItemPartials part, uint64_t n_parts, GenStats gs, uint64_t n_gen,
-                                                         const double *__restrict__ abs_part, uint64_t n_abs,
-                                                         const Scratch *sc, uint64_t ne, FinalPart *__restrict__ out)
+// The block's part of the first stage (valid in thread 0).
+__device__ __forceinline__ FinalPart final_part_body(uint32_t blk, uint32_t nblk, ItemPartials part, uint64_t n_parts, GenStats gs,
+                                                     uint64_t n_gen, const double *__restrict__ abs_part, uint64_t n_abs,
+                                                     const Scratch *sc, uint64_t ne)
 {
     {  // the merge wrote the absolute sums of the tiles covering the merged store only
         const uint64_t live = (ne + sc->n_new + kMergeTile - 1) / kMergeTile;
@@ -2116,8 +2117,25 @@ __device__ __forceinline__ void final_part_body(uint32_t blk, uint32_t nblk, Ite
     r.sp = sp;
     r.de = de;
     r.mx = mx;
-    r = block_reduce_part(r);
-    if (threadIdx.x == 0) out[blk] = r;
+    return block_reduce_part(r);
+}
+
+// The step's scalars from the reduced statistics, by one thread.
+__device__ __forceinline__ void final_write(const FinalPart &a, Scratch *sc, Scratch *copy, uint64_t seq)
+{
+    sc->num = a.num;
+    sc->n_total = a.tot;
+    sc->n_attempts = a.att;
+    sc->n_discarded = a.disc;
+    sc->max_n = a.mx;
+    sc->n_spawns = a.sp;
+    sc->n_deaths = a.de;
+    // The step's scalars go straight to the host's pinned copy; the batch's sequence number is
+    // stored last, behind a system-scope release, so the host that sees it sees the rest.
+    Scratch c = *sc;
+    c.seq = 0;  // no batch has number 0: the host waits for the release below
+    *copy = c;
+    __hip_atomic_store(&copy->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // The second stage, by the whole last block: thread t sums parts t, t + kThreads, ... (in that
@@ -2147,20 +2165,7 @@ __device__ __forceinline__ void final_body(uint32_t blk, uint32_t nblk, const Fi
         a.mx = b[u].mx > a.mx ? b[u].mx : a.mx;
     }
     a = block_reduce_part(a);
-    if (threadIdx.x != 0) return;
-    sc->num = a.num;
-    sc->n_total = a.tot;
-    sc->n_attempts = a.att;
-    sc->n_discarded = a.disc;
-    sc->max_n = a.mx;
-    sc->n_spawns = a.sp;
-    sc->n_deaths = a.de;
-    // The step's scalars go straight to the host's pinned copy; the batch's sequence number is
-    // stored last, behind a system-scope release, so the host that sees it sees the rest.
-    Scratch c = *sc;
-    c.seq = 0;  // no batch has number 0: the host waits for the release below
-    *copy = c;
-    __hip_atomic_store(&copy->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (threadIdx.x == 0) final_write(a, sc, copy, seq);
 }
 
 struct FinalPartArgs {
@@ -2180,10 +2185,16 @@ struct FinalPartArgs {
 
 // Both stages of the reduction in one launch: each block publishes its part and counts
 // itself done (a release atomic); the block that finishes last acquires, sums the parts in
-// block order and hands the scalars to the host.
+// block order and hands the scalars to the host.  A state with one block hands its sum over
+// directly.
 __device__ __forceinline__ void k_final_part_entry(const FinalPartArgs &A, uint32_t blk, uint32_t nblk)
 {
-    final_part_body(blk, nblk, A.part, A.n_parts, A.gs, A.n_gen, A.abs_part, A.n_abs, A.sc, A.ne, A.out);
+    const FinalPart r = final_part_body(blk, nblk, A.part, A.n_parts, A.gs, A.n_gen, A.abs_part, A.n_abs, A.sc, A.ne);
+    if (nblk == 1) {  // the only block holds the whole sum: no hand-over between blocks
+        if (threadIdx.x == 0) final_write(r, A.sc, A.copy, A.seq);
+        return;
+    }
+    if (threadIdx.x == 0) A.out[blk] = r;
     __shared__ bool s_last;
     if (threadIdx.x == 0) {
         const uint64_t before = __hip_atomic_fetch_add(A.done, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
