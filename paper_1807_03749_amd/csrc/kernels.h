@@ -1894,14 +1894,16 @@ __device__ __forceinline__ void merge_body(uint32_t blk, uint32_t nblk, const Sy
             const uint64_t m = __ballot(v[u] != T(0));
             if (lane == 0) s_cnt[u][w] = (uint32_t)__popcll(m);
         }
-        const double tile_abs = block_reduce_sum(abs_sum);  // its barriers also publish s_cnt
+        __syncthreads();  // the survivor counts are published
         uint64_t tile_keep = 0;
 #pragma unroll
         for (int u = 0; u < kMergeItems; ++u)
 #pragma unroll
             for (int x = 0; x < kWaves; ++x) tile_keep += s_cnt[u][x];
+        // the tile's count goes out before the |N| sum, so that later tiles' look-backs find it sooner
+        if (threadIdx.x == 0) lb_publish(&status[tile], tile == 0 ? kLbInclusive : kLbAggregate, tile_keep);
+        const double tile_abs = block_reduce_sum(abs_sum);
         if (w == 0) {
-            if (lane == 0) lb_publish(&status[tile], tile == 0 ? kLbInclusive : kLbAggregate, tile_keep);
             const uint64_t prefix = tile == 0 ? 0 : lb_wave_lookback(status, tile);
             if (lane == 0) {
                 if (tile > 0) lb_publish(&status[tile], kLbInclusive, prefix + tile_keep);
