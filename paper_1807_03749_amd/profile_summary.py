@@ -27,6 +27,13 @@
       16-lane SIMD; GRBM_GUI_ACTIVE arrives summed over the XCDs), and the fraction of wave
       time spent waiting.
 
+  python -m paper_1807_03749_amd.profile_summary gaps <run>_kernel_trace.csv --steps K
+      [--api <run>_hip_api_trace.csv] --command "..." --out FILE
+      the idle time of the GPU between consecutive kernels over the last K steps (median per
+      pair of kernels, and the sum per step), and with an API trace the host's time per
+      hipLaunchKernel call: where the host issues launches more slowly than the kernels run,
+      the GPU waits between them
+
 The summaries record the hash of the HIP sources they were taken on; bench.py uses a
 traffic figure only while that hash still matches.
 """
@@ -107,6 +114,42 @@ def trace(args):
         lines.append(f"  {k[:58]:58s} {a[0]:7d} {a[1] / 1e6:10.3f} {a[1] / a[0] / 1e3:9.2f} {a[2] / 1e3:9.2f} "
                      f"{a[3] / 1e3:9.2f} {100 * a[1] / tot:5.1f}%")
     lines.append(f"# per step: {tot / 1e3 / args.steps:.1f} us of kernel time")
+    _write(args.out, lines)
+
+
+def gaps(args):
+    rows = _rows(args.csv)
+    for r in rows:
+        r["_s"], r["_e"] = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+    rows.sort(key=lambda r: r["_s"])
+    ends = [r["_e"] for r in rows if "k_final_part" in r["Kernel_Name"]]
+    if len(ends) < args.steps + 1:
+        raise SystemExit(f"gaps: {len(ends)} steps in the trace, fewer than {args.steps} + 1")
+    t0 = ends[-args.steps - 1]
+    rows = [r for r in rows if r["_s"] >= t0 and not r["Kernel_Name"].startswith("__amd")]
+    pairs, idle = {}, 0
+    for a, b in zip(rows, rows[1:]):
+        g = max(0, b["_s"] - a["_e"])
+        idle += g
+        key = (_short(a["Kernel_Name"]).split("<")[0], _short(b["Kernel_Name"]).split("<")[0])
+        pairs.setdefault(key, []).append(g)
+    lines = [f"# idle GPU time between kernels over the last {args.steps} steps  ({datetime.date.today().isoformat()})",
+             f"# command: {args.command}",
+             f"# source_hash = {_source_hash()}",
+             f"# {'kernel':>20s} -> {'next kernel':20s} {'count':>6s} {'median_gap_us':>14s}"]
+    for (x, y), v in sorted(pairs.items(), key=lambda kv: -sorted(kv[1])[len(kv[1]) // 2]):
+        v = sorted(v)
+        lines.append(f"  {x:>20s} -> {y:20s} {len(v):6d} {v[len(v) // 2] / 1e3:14.2f}")
+    lines.append(f"# per step: {idle / 1e3 / args.steps:.1f} us idle between kernels")
+    if args.api:
+        launch = {}
+        for r in _rows(args.api):
+            if r["Function"] == "hipLaunchKernel" and int(r["Start_Timestamp"]) >= t0 - 10**9:
+                launch[r["Correlation_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        d = sorted(launch[r["Correlation_Id"]] for r in rows if r.get("Correlation_Id") in launch)
+        if d:
+            lines.append(f"# hipLaunchKernel host time per launch (under the API tracer): median {d[len(d) // 2] / 1e3:.2f} us "
+                         f"over {len(d)} launches")
     _write(args.out, lines)
 
 
@@ -217,6 +260,12 @@ def main():
     r.add_argument("--steps", type=int, required=True)
     r.add_argument("--command", required=True)
     r.add_argument("--out")
+    g = sub.add_parser("gaps")
+    g.add_argument("csv")
+    g.add_argument("--steps", type=int, required=True)
+    g.add_argument("--api")
+    g.add_argument("--command", required=True)
+    g.add_argument("--out")
     v = sub.add_parser("valu")
     for a in ("--pmc", "--kernels", "--workload", "--command"):
         v.add_argument(a, required=True)
@@ -225,7 +274,7 @@ def main():
     v.add_argument("--last", type=int, default=0)
     v.add_argument("--out")
     args = ap.parse_args()
-    {"stats": stats, "trace": trace, "traffic": traffic, "valu": valu}[args.cmd](args)
+    {"stats": stats, "trace": trace, "traffic": traffic, "valu": valu, "gaps": gaps}[args.cmd](args)
 
 
 if __name__ == "__main__":

@@ -47,3 +47,25 @@ def test_valu_busy_divides_the_xcd_sum(tmp_path):
     out = _run("valu", "--pmc", str(tmp_path / "v.csv"), "--kernels", "k_generate<", "--workload", "w", "--command", "t")
     row = [ln for ln in out.splitlines() if ln.strip().startswith("k_generate<")][0].split()
     assert row[1] == "1" and float(row[3]) == 50.0 and row[4] == "50.0%" and row[5] == "25.0%"
+
+
+def test_gaps_sum_the_idle_time_between_kernels(tmp_path):
+    # two steps of three kernels; in the last step the GPU waits 4 us before k_items and 1 us
+    # before k_final_part; hipLaunchKernel takes 7 us per call
+    seq = [("k_guide", 0, 10), ("k_items", 10, 20), ("k_final_part", 20, 25),
+           ("k_guide", 30, 40), ("k_items", 44, 60), ("k_final_part", 61, 65)]
+    with open(tmp_path / "k.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Correlation_Id", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for i, (n, s, e) in enumerate(seq):
+            w.writerow({"Kernel_Name": f"void ccmc::{n}(args)", "Correlation_Id": i, "Start_Timestamp": s * 1000,
+                        "End_Timestamp": e * 1000})
+    with open(tmp_path / "a.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Function", "Correlation_Id", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for i in range(len(seq)):
+            w.writerow({"Function": "hipLaunchKernel", "Correlation_Id": i, "Start_Timestamp": 0, "End_Timestamp": 7000})
+    out = _run("gaps", str(tmp_path / "k.csv"), "--steps", "1", "--api", str(tmp_path / "a.csv"), "--command", "t")
+    rows = {tuple(ln.split()[:3:2]): float(ln.split()[-1]) for ln in out.splitlines() if "->" in ln and not ln.startswith("#")}
+    assert rows[("k_guide", "k_items")] == 4.0 and rows[("k_items", "k_final_part")] == 1.0
+    assert "per step: 5.0 us idle" in out and "median 7.00 us" in out
